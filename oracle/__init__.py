@@ -1,0 +1,297 @@
+"""The oracle: TEST INFRASTRUCTURE ONLY.
+
+A plain, slow, single-threaded CPU implementation (``oracle.c``) of succinct
+colour coding: the build-up dynamic program of Eq. (1), totals, the uniform and
+shape-restricted colourful-treelet sampler, graphlet classification, spanning
+tree numbers and AGS. Only ``tests/``, the smoke check and the benchmark's
+CPU-baseline leg may import this package. It shares no code with the GPU
+library and neither imports the other.
+
+Counts are exact unsigned 128-bit integers; they cross into Python as
+(lo, hi) uint64 pairs and are returned as Python ints or object arrays where a
+plain view is needed.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+ROOT_ZERO = 0
+ROOT_ALL = 1
+
+OK, EINVAL, ENOMEM, EOVERFLOW, EEMPTY = 0, -1, -2, -3, -5
+
+
+class OracleError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"oracle status {status}: {msg}")
+        self.status = status
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain -O2, no fast-math, no contraction)."""
+    if force or not os.path.exists(_LIB):
+        subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-shared", "-fPIC",
+                               "-ffp-contract=off", _SRC, "-o", _LIB + ".tmp"])
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        L = C.CDLL(_LIB)
+        P = C.c_void_p
+        i64, i32, u64, u32 = C.c_int64, C.c_int32, C.c_uint64, C.c_uint32
+        sig = {
+            "orc_last_error": (C.c_char_p, []),
+            "orc_num_shapes": (C.c_int, [C.c_int]),
+            "orc_shape_string": (C.c_int, [C.c_int, C.c_int, C.c_char_p, C.c_int]),
+            "orc_shape_decomp": (C.c_int, [C.c_int, C.c_int, P, P, P, P]),
+            "orc_num_unrooted": (C.c_int, [C.c_int]),
+            "orc_shape_unrooted": (C.c_int, [C.c_int, C.c_int]),
+            "orc_key": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_uint]),
+            "orc_num_keys": (C.c_int, [C.c_int]),
+            "orc_check_csr": (C.c_int, [i64, P, P]),
+            "orc_build": (C.c_int, [i64, P, P, P, C.c_int, C.c_int, C.POINTER(P)]),
+            "orc_table_free": (None, [P]),
+            "orc_level_nnz": (i64, [P, C.c_int]),
+            "orc_export_level": (C.c_int, [P, C.c_int, P, P, P, P]),
+            "orc_totals": (None, [P, P, P]),
+            "orc_eta": (None, [P, P]),
+            "orc_occ": (C.c_int, [P, i64, C.c_int, P]),
+            "orc_philox4x64": (None, [P, P, P]),
+            "orc_uniform_below": (C.c_int, [u64, u64, u64, u64, u64, u32, P]),
+            "orc_sample": (C.c_int, [P, C.c_int, i64, u64, u64, u64, P, P]),
+            "orc_canonical_code": (u32, [u32, C.c_int]),
+            "orc_num_classes": (C.c_int, [C.c_int]),
+            "orc_catalog_codes": (C.c_int, [C.c_int, P]),
+            "orc_classify": (C.c_int, [i64, P, P, C.c_int, P, i64, P, P]),
+            "orc_spanning_trees": (i64, [u32, C.c_int]),
+            "orc_spanning_trees_by_shape": (C.c_int, [u32, C.c_int, P]),
+            "orc_ags": (C.c_int, [P, i64, i64, i64, u64, u64, P, P, P, P, P]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _check(st: int):
+    if st != OK:
+        raise OracleError(st, lib().orc_last_error().decode())
+
+
+def _u128(lo, hi) -> int:
+    return int(lo) | (int(hi) << 64)
+
+
+# --------------------------------------------------------------------------
+# Treelet algebra
+# --------------------------------------------------------------------------
+
+def num_shapes(h: int) -> int:
+    """Number r_h of rooted treelet shapes on h nodes."""
+    return lib().orc_num_shapes(h)
+
+
+def shape_string(h: int, r: int) -> str:
+    """Canonical DFS bitstring of the rank-r rooted shape on h nodes."""
+    buf = C.create_string_buffer(64)
+    _check(lib().orc_shape_string(h, r, buf, 64))
+    return buf.value.decode()
+
+
+def shape_decomp(h: int, r: int):
+    """(|T'|, rank T', rank T'', beta_T) of the canonical decomposition."""
+    v = [C.c_int() for _ in range(4)]
+    _check(lib().orc_shape_decomp(h, r, *[C.byref(x) for x in v]))
+    return tuple(x.value for x in v)
+
+
+def num_unrooted(h: int) -> int:
+    return lib().orc_num_unrooted(h)
+
+
+def shape_unrooted(h: int, r: int) -> int:
+    return lib().orc_shape_unrooted(h, r)
+
+
+def key(k: int, h: int, rank: int, mask: int) -> int:
+    return lib().orc_key(k, h, rank, mask)
+
+
+def num_keys(k: int) -> int:
+    return lib().orc_num_keys(k)
+
+
+# --------------------------------------------------------------------------
+# Table
+# --------------------------------------------------------------------------
+
+class Table:
+    """The oracle's count table for one graph and colouring."""
+
+    def __init__(self, g, colors: np.ndarray, k: int, rooting: int = ROOT_ZERO):
+        self.g = g
+        self.k = k
+        self.rooting = rooting
+        self.colors = np.ascontiguousarray(colors, dtype=np.uint8)
+        self._h = C.c_void_p()
+        _check(lib().orc_build(g.n, _p(g.row_ptr), _p(g.col_idx), _p(self.colors), k, rooting,
+                               C.byref(self._h)))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().orc_table_free(h)
+            self._h = None
+
+    def level_nnz(self, h: int) -> int:
+        return int(lib().orc_level_nnz(self._h, h))
+
+    def export_level(self, h: int):
+        """(off int64[n+1], key uint16[nnz], lo uint64[nnz], hi uint64[nnz])."""
+        nnz = self.level_nnz(h)
+        off = np.zeros(self.g.n + 1, np.int64)
+        key = np.zeros(max(nnz, 1), np.uint16)
+        lo = np.zeros(max(nnz, 1), np.uint64)
+        hi = np.zeros(max(nnz, 1), np.uint64)
+        _check(lib().orc_export_level(self._h, h, _p(off), _p(key), _p(lo), _p(hi)))
+        return off, key[:nnz], lo[:nnz], hi[:nnz]
+
+    def level_dict(self, h: int) -> dict:
+        """{(v, key): count} of level h, counts as Python ints."""
+        off, key, lo, hi = self.export_level(h)
+        out = {}
+        for v in range(self.g.n):
+            for q in range(off[v], off[v + 1]):
+                out[(v, int(key[q]))] = _u128(lo[q], hi[q])
+        return out
+
+    def totals(self):
+        """(t, [t_j]) as Python ints."""
+        nu = num_unrooted(self.k)
+        t = np.zeros(2, np.uint64)
+        tj = np.zeros(2 * max(nu, 1), np.uint64)
+        lib().orc_totals(self._h, _p(t), _p(tj))
+        return _u128(t[0], t[1]), [_u128(tj[2 * j], tj[2 * j + 1]) for j in range(nu)]
+
+    def eta(self) -> list:
+        out = np.zeros(2 * max(self.g.n, 1), np.uint64)
+        lib().orc_eta(self._h, _p(out))
+        return [_u128(out[2 * v], out[2 * v + 1]) for v in range(self.g.n)]
+
+    def occ(self, v: int, key: int = -1) -> int:
+        out = np.zeros(2, np.uint64)
+        _check(lib().orc_occ(self._h, v, key, _p(out)))
+        return _u128(out[0], out[1])
+
+    def sample(self, n: int, seed: int, stream: int = 0, shape: int = -1, first_index: int = 0):
+        """(verts int32[n, k], parent int8[n, k])."""
+        verts = np.zeros((max(n, 1), self.k), np.int32)
+        par = np.zeros((max(n, 1), self.k), np.int8)
+        _check(lib().orc_sample(self._h, shape, n, seed, stream, first_index, _p(verts), _p(par)))
+        return verts[:n], par[:n]
+
+    def ags(self, cbar: int, round_size: int, budget: int, seed: int, stream: int = 0):
+        """AGS rounds; returns dict with hits, w, n_j, round shapes."""
+        s = num_classes(self.k)
+        ns = num_unrooted(self.k)
+        hits = np.zeros(s, np.int64)
+        w = np.zeros(s, np.float64)
+        nj = np.zeros(ns, np.int64)
+        shapes = np.zeros(max(budget // max(round_size, 1), 1), np.int32)
+        nr = C.c_int64()
+        _check(lib().orc_ags(self._h, cbar, round_size, budget, seed, stream,
+                             _p(hits), _p(w), _p(nj), _p(shapes), C.byref(nr)))
+        return {"hits": hits, "w": w, "n_j": nj, "round_shapes": shapes[:nr.value]}
+
+
+def check_csr(g) -> int:
+    return lib().orc_check_csr(g.n, _p(g.row_ptr), _p(g.col_idx))
+
+
+# --------------------------------------------------------------------------
+# Random numbers
+# --------------------------------------------------------------------------
+
+def philox4x64(ctr, key) -> list:
+    c = np.array(ctr, np.uint64)
+    kk = np.array(key, np.uint64)
+    out = np.zeros(4, np.uint64)
+    lib().orc_philox4x64(_p(c), _p(kk), _p(out))
+    return [int(x) for x in out]
+
+
+def uniform_below(N: int, seed: int, stream: int, idx: int, draw: int) -> int:
+    out = np.zeros(2, np.uint64)
+    _check(lib().orc_uniform_below(N & (2**64 - 1), N >> 64, seed, stream, idx, draw, _p(out)))
+    return _u128(out[0], out[1])
+
+
+# --------------------------------------------------------------------------
+# Graphlets
+# --------------------------------------------------------------------------
+
+def canonical_code(code: int, k: int) -> int:
+    return int(lib().orc_canonical_code(code, k))
+
+
+def num_classes(k: int) -> int:
+    return int(lib().orc_num_classes(k))
+
+
+def catalog_codes(k: int) -> np.ndarray:
+    out = np.zeros(num_classes(k), np.uint32)
+    _check(lib().orc_catalog_codes(k, _p(out)))
+    return out
+
+
+def classify(g, k: int, verts: np.ndarray):
+    """(code uint32[n], class int32[n]) of each sample's induced k-graphlet."""
+    verts = np.ascontiguousarray(verts, dtype=np.int32).reshape(-1, k)
+    n = verts.shape[0]
+    code = np.zeros(max(n, 1), np.uint32)
+    cls = np.zeros(max(n, 1), np.int32)
+    _check(lib().orc_classify(g.n, _p(g.row_ptr), _p(g.col_idx), k, _p(verts), n, _p(code), _p(cls)))
+    return code[:n], cls[:n]
+
+
+def spanning_trees(code: int, k: int) -> int:
+    return int(lib().orc_spanning_trees(code, k))
+
+
+def spanning_trees_by_shape(code: int, k: int) -> np.ndarray:
+    out = np.zeros(max(num_unrooted(k), 1), np.int64)
+    _check(lib().orc_spanning_trees_by_shape(code, k, _p(out)))
+    return out[:num_unrooted(k)]
+
+
+def pair_index(k: int):
+    """Row-major numbering of the pairs i < j used by the adjacency code."""
+    idx = {}
+    q = 0
+    for i in range(k):
+        for j in range(i + 1, k):
+            idx[(i, j)] = q
+            q += 1
+    return idx
