@@ -1,0 +1,243 @@
+/*
+ * scc.h -- succinct colour coding on one AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of libscc.so: the build-up phase (the count table of colourful rooted
+ * treelets), the colourful-treelet sampler, induced-graphlet classification
+ * and adaptive graphlet sampling of Bressan, Leucci and Panconesi, "Faster
+ * motif counting via succinct color coding and adaptive sampling".
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Every call returns scc_status; 0 (SCC_OK) is success. On any other value
+ *   scc_last_error() returns a message for the calling thread. Output buffers
+ *   are not modified on error unless stated.
+ * - "device pointer" means memory on the GPU the library runs on (for example a
+ *   PyTorch CUDA tensor's data_ptr()); "host pointer" means ordinary memory.
+ * - `stream` is a hipStream_t passed as void*; NULL means the default stream.
+ *   Work is enqueued on that stream; calls that return host values
+ *   synchronise it.
+ * - The graph is a simple undirected graph in CSR form (Sec. 1.3): row_ptr
+ *   int64[n+1], col_idx int32[2m]; every row strictly increasing, symmetric,
+ *   without self-loops. Colours are uint8[n] with values in [0, k) (Sec. 2).
+ * - Colour sets are k-bit masks (bit j = colour j). A coloured rooted treelet
+ *   (T, C), |T| = |C| = h, has the key
+ *       key = off_h + rank_h(T) * binom(k, h) + colex(C),
+ *   where rank_h orders the rooted shapes on h nodes by their DFS bitstring
+ *   (Sec. 3.2: '1' away from the root, '0' back, children in descending
+ *   lexicographic order), colex(C) is the number of h-subsets of [k] with a
+ *   smaller bitmask, and off_h = sum_{h'<h} r_{h'} binom(k, h'). For k = 8
+ *   there are 1991 keys, which fit in 11 bits (Sec. 3.3).
+ * - Counts are exact unsigned integers up to 128 bits, passed as (lo, hi)
+ *   uint64 pairs.
+ */
+#ifndef SCC_H
+#define SCC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SCC_OK = 0,
+    SCC_EINVAL = -1,       /* bad argument: k not in [2, 8], colour >= k, non-simple,
+                              unsorted or asymmetric CSR, n >= 2^31, bad shape id ... */
+    SCC_ENOMEM = -2,       /* device allocation failed */
+    SCC_EOVERFLOW = -3,    /* a count would need more bits than allowed (max_bits) */
+    SCC_EDEVICE = -4,      /* a HIP runtime error */
+    SCC_EEMPTY = -5,       /* nothing to sample: the requested total is 0 */
+    SCC_EBUSY = -6,        /* server full: request not admitted */
+    SCC_EUNSUPPORTED = -7  /* valid request this build does not support */
+} scc_status;
+
+enum { SCC_ROOT_ZERO = 0, SCC_ROOT_ALL = 1 };
+
+typedef struct scc_table scc_table;
+
+/* Device allocator hooks. alloc returns device memory of at least `bytes`
+   bytes (or NULL); free releases it. Both are called on the caller's thread
+   with the build's stream in `stream`. */
+typedef struct {
+    void *(*alloc)(size_t bytes, void *stream, void *ctx);
+    void (*free)(void *ptr, void *stream, void *ctx);
+    void *ctx;
+} scc_allocator;
+
+typedef struct {
+    int64_t n;                 /* number of vertices, < 2^31 */
+    int64_t nnz;               /* 2m, length of col_idx */
+    const int64_t *row_ptr;    /* device pointer, n + 1 entries */
+    const int32_t *col_idx;    /* device pointer, nnz entries */
+} scc_csr;
+
+typedef struct {
+    int rooting;               /* SCC_ROOT_ZERO (default): level k kept at colour-0
+                                  vertices only (zero-rooting, Sec. 3.4);
+                                  SCC_ROOT_ALL: at every vertex (Eq. (1) as is) */
+    int max_bits;              /* 64 or 128 (0 = 128): widest count allowed */
+    void *stream;              /* hipStream_t for all work of the build */
+    const scc_allocator *alloc;/* NULL: hipMalloc / hipFree */
+    int hub_degree;            /* gather rows of at least this degree are split over
+                                  many workgroups; 0 = library default */
+    int validate;              /* nonzero: check the CSR and colours on the device first */
+} scc_build_opts;
+
+/*
+ * scc_build_table -- the build-up phase (Sec. 2.1, Eq. (1)).
+ *
+ * Computes c(T_C, v) for every colourful rooted treelet (T, C) on h <= k nodes
+ * and every vertex v: level 1 is c((., {c_v}), v) = 1 and level h >= 2 is
+ *   c(T_C, v) = (1/beta_T) sum_{u ~ v} sum_{C' subset C, |C'| = |T'|}
+ *               c(T'_{C'}, v) c(T''_{C \ C'}, u),
+ * with (T', T'') the canonical decomposition of T (T'' = the first child
+ * subtree of the root, T' = the rest) and beta_T the number of root children
+ * whose subtree equals T''. Only non-zero counts are stored (Sec. 3.2, "Count
+ * tables"); level k is stored at colour-0 vertices (SCC_ROOT_ZERO) or at all
+ * vertices (SCC_ROOT_ALL). Then computes the per-vertex level-k totals eta_v,
+ * their running sum over vertices, the total t and per-unrooted-shape totals t_j.
+ *
+ * g, colors: device pointers, borrowed for the lifetime of the table (the
+ * sampler and classifier read them); the caller keeps them alive and unchanged.
+ * colors: uint8[n]. k in [2, 8]. opt may be NULL (defaults).
+ * *out receives a library-owned, immutable table; free it with
+ * scc_table_destroy. Errors: SCC_EINVAL (k, colours or CSR; the CSR is checked
+ * only when opt->validate is set), SCC_EOVERFLOW (a count needs more than
+ * max_bits bits; detected from a per-vertex bound before anything wraps),
+ * SCC_ENOMEM, SCC_EDEVICE. On error *out is NULL.
+ */
+scc_status scc_build_table(const scc_csr *g, const uint8_t *colors, int k,
+                           const scc_build_opts *opt, scc_table **out);
+
+/* Frees the table and its device memory. NULL is allowed. */
+void scc_table_destroy(scc_table *t);
+
+typedef struct {
+    int64_t n;
+    int k;
+    int rooting;
+    int num_unrooted;          /* unrooted k-treelet shapes (1,1,1,2,3,6,11,23 for k=1..8) */
+    int64_t nnz[9];            /* stored non-zero counts per level h = 1..k (nnz[0] unused) */
+    int64_t wide_vertices[9];  /* vertices whose level-h counts are stored with 128 bits */
+    int64_t bytes;             /* device bytes held by the table */
+    uint64_t t[2];             /* total colourful k-treelet copies (lo, hi) */
+    uint64_t tj[32][2];        /* per unrooted shape j */
+    double level_ms[9];        /* device time of level h (bound, gather, combine, pack) */
+    double gather_ms[9];       /* device time of the neighbour-sum gather of level h */
+    double gather_bytes[9];    /* its algorithmic bytes: 4 d_v + neighbours' records
+                                  (10 B per 64-bit entry, 18 B per 128-bit entry)
+                                  + the dense neighbour sums written, over gathered rows */
+} scc_table_info;
+
+/* Table summary (host struct). Synchronises the table's stream once. */
+scc_status scc_table_info_get(const scc_table *t, scc_table_info *out);
+
+/*
+ * scc_occ -- database queries of Sec. 3: occ(T_C, v) (key >= 0: the count of
+ * the coloured rooted treelet with that key at v) or occ(v) (key = -1: eta_v,
+ * the number of colourful k-treelet copies stored at v). out: host uint64[2]
+ * (lo, hi). Errors: SCC_EINVAL for v or key out of range.
+ */
+scc_status scc_occ(const scc_table *t, int64_t v, int32_t key, uint64_t out[2]);
+
+/*
+ * scc_export_level -- the stored level-h records in vertex order.
+ * With off == NULL only *nnz_out is set (the number of stored counts).
+ * Otherwise off: device int64[n+1] (record of v is [off[v], off[v+1])),
+ * key: device uint16[nnz] (ascending within a record), lo/hi: device
+ * uint64[nnz] (the count's low and high 64 bits). All caller-owned.
+ */
+scc_status scc_export_level(const scc_table *t, int h, int64_t *nnz_out,
+                            int64_t *off, uint16_t *key, uint64_t *lo, uint64_t *hi, void *stream);
+
+/*
+ * scc_sample -- colourful k-treelet copies (Sec. 2.2; sample(T) of Sec. 4.1).
+ *
+ * shape = -1: each colourful k-treelet copy of the graph with probability 1/t;
+ * shape = j:  each copy whose unrooted shape is j with probability 1/t_j.
+ * Procedure (it fixes the stream, so equal arguments give equal samples):
+ * draw X in [0, T) over the admissible level-k counts (vertices ascending, then
+ * keys ascending) and take the first (T_C, v) whose running sum exceeds X;
+ * then repeatedly decompose (T, C) at x into (T', T''): draw C'' (subsets of
+ * C \ {c_x} of size |T''| by ascending bitmask, weight c(T'_{C\C''}, x) *
+ * sum_{u~x} c(T''_{C''}, u)), then u ~ x (CSR order, weight c(T''_{C''}, u)),
+ * and continue with (T', C \ C'', x) before (T'', C'', u). Uniform integers in
+ * [0, N) come from Philox4x64-10 with key (seed, stream_id) and counter
+ * (sample index, draw << 32 | attempt, 0, 0), masked to the bit length of N-1
+ * and rejected when >= N; draw 0 is the root, draws 1 + 2i and 2 + 2i belong
+ * to the i-th decomposition. Sample s uses index first_index + s.
+ *
+ * out_verts: device int32[n * k], vertex ids in discovery order, root first.
+ * out_parent: device int8[n * k], position of each vertex's parent (-1 for the
+ * root). Errors: SCC_EINVAL (shape id), SCC_EEMPTY (total 0).
+ */
+scc_status scc_sample(const scc_table *t, int32_t shape, int64_t n, uint64_t seed,
+                      uint64_t stream_id, uint64_t first_index,
+                      int32_t *out_verts, int8_t *out_parent, void *stream);
+
+/*
+ * scc_classify -- graphlet classification of samples (Sec. 4.4).
+ * For each sample (k vertices of the table's graph), the induced adjacency
+ * code  sum_{i<j} [v_i ~ v_j] 2^{idx(i,j)}  (pairs numbered row by row) and the
+ * class id of its graphlet: the rank of its canonical code (the minimum code
+ * over all k! vertex orders) among the canonical codes of all connected graphs
+ * on k vertices (N_k = 1,1,2,6,21,112,853,11117 for k = 1..8).
+ * verts: device int32[n * k]. out_code: device uint32[n] or NULL.
+ * out_class: device uint32[n]. The first call for a k builds a per-k lookup
+ * table on the device (2^(k(k-1)/2) entries; 512 MiB for k = 8) that is kept
+ * until scc_release_caches().
+ */
+scc_status scc_classify(const scc_table *t, const int32_t *verts, int64_t n,
+                        uint32_t *out_code, uint32_t *out_class, void *stream);
+
+/*
+ * scc_catalog -- the graphlet classes for k (Sec. 4.4 and Sec. 4.1).
+ * num_classes receives N_k. If codes != NULL: host uint32[N_k], canonical code
+ * of each class (ascending). If sigma != NULL: host int64[N_k], the number of
+ * spanning trees sigma_i (Kirchhoff's matrix-tree theorem). If sigma_ij !=
+ * NULL: host int64[N_k * num_unrooted], the spanning trees of H_i of unrooted
+ * shape j (row-major by class). Computing sigma_ij for k = 8 takes seconds.
+ */
+scc_status scc_catalog(int k, int64_t *num_classes, uint32_t *codes, int64_t *sigma,
+                       int64_t *sigma_ij, void *stream);
+
+/*
+ * scc_ags -- adaptive graphlet sampling (Sec. 4.1, Algorithm AGS), in rounds.
+ * Round r draws `round_size` samples of one unrooted shape j with sample
+ * indices [drawn, drawn + round_size) of (seed, stream_id), classifies them and
+ * adds the hits to c_i and round_size to n_j. Start: the shape with the largest
+ * t_j (ties: smaller j). After a round in which some class first reaches
+ * c_i >= cbar it becomes covered, and the next shape is
+ *   j* = argmin_{j: t_j > 0} (1/t_j) sum_{i covered} sigma_ij c_i / w_i,
+ *   w_i = sum_j n_j sigma_ij / t_j  (double precision, j and i ascending; ties
+ * to the smaller j). Stops when every class is covered or the next round would
+ * exceed `budget` samples. round_size = 1 is the algorithm as printed.
+ * Outputs (host): hits int64[N_k]; w double[N_k] (0 for classes never hit;
+ * c_i / w_i estimates the colourful count of class i, divide by k!/k^k for the
+ * count in the graph); n_j int64[num_unrooted]; round_shapes int32[budget /
+ * round_size] or NULL; *n_rounds.
+ */
+scc_status scc_ags(const scc_table *t, int64_t cbar, int64_t round_size, int64_t budget,
+                   uint64_t seed, uint64_t stream_id, int64_t *hits, double *w, int64_t *n_j,
+                   int32_t *round_shapes, int64_t *n_rounds, void *stream);
+
+/* Number of unrooted k-treelet shapes (free trees on k nodes), -1 if k is
+   outside [1, 8]. Shape ids j in [0, this) order the shapes by the smallest
+   DFS bitstring among their rootings. */
+int scc_num_unrooted(int k);
+
+/* Frees per-k device lookup tables kept by scc_classify. */
+void scc_release_caches(void);
+
+/* Thread-local message for the last non-OK status of this thread. */
+const char *scc_last_error(void);
+
+/* Library version string. */
+const char *scc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SCC_H */

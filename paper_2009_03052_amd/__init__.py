@@ -1,0 +1,261 @@
+"""Python binding of libscc (succinct colour coding on one MI355X).
+
+Argument marshalling only: every step runs in the HIP library ``libscc.so``
+(built in-tree by ``build.py``). PyTorch provides device memory (through its
+caching allocator, handed to the library as allocator hooks) and streams.
+Importing this package fails loudly when the library is missing.
+
+The names follow the C ABI in ``include/scc.h``: :class:`Table` wraps
+``scc_build_table`` and the queries on a table (``occ``, ``export_level``,
+``sample``, ``classify``, ``ags``); :func:`catalog` wraps ``scc_catalog``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libscc.so")
+
+OK, EINVAL, ENOMEM, EOVERFLOW, EDEVICE, EEMPTY, EBUSY, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
+ROOT_ZERO, ROOT_ALL = 0, 1
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with paper_2009_03052_amd/build.py "
+                      "(there is no fallback path)")
+
+_lib = C.CDLL(LIB_PATH)
+
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
+class _Allocator(C.Structure):
+    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("ctx", C.c_void_p)]
+
+
+class _Csr(C.Structure):
+    _fields_ = [("n", C.c_int64), ("nnz", C.c_int64), ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p)]
+
+
+class _BuildOpts(C.Structure):
+    _fields_ = [("rooting", C.c_int), ("max_bits", C.c_int), ("stream", C.c_void_p),
+                ("alloc", C.POINTER(_Allocator)), ("hub_degree", C.c_int), ("validate", C.c_int)]
+
+
+class TableInfo(C.Structure):
+    _fields_ = [("n", C.c_int64), ("k", C.c_int), ("rooting", C.c_int), ("num_unrooted", C.c_int),
+                ("nnz", C.c_int64 * 9), ("wide_vertices", C.c_int64 * 9), ("bytes", C.c_int64),
+                ("t", C.c_uint64 * 2), ("tj", (C.c_uint64 * 2) * 32), ("level_ms", C.c_double * 9),
+                ("gather_ms", C.c_double * 9), ("gather_bytes", C.c_double * 9)]
+
+
+_P = C.c_void_p
+_i64, _u64, _i32 = C.c_int64, C.c_uint64, C.c_int32
+_SIGS = {
+    "scc_build_table": (C.c_int, [C.POINTER(_Csr), _P, C.c_int, C.POINTER(_BuildOpts), C.POINTER(_P)]),
+    "scc_table_destroy": (None, [_P]),
+    "scc_table_info_get": (C.c_int, [_P, C.POINTER(TableInfo)]),
+    "scc_occ": (C.c_int, [_P, _i64, _i32, _P]),
+    "scc_export_level": (C.c_int, [_P, C.c_int, C.POINTER(_i64), _P, _P, _P, _P, _P]),
+    "scc_sample": (C.c_int, [_P, _i32, _i64, _u64, _u64, _u64, _P, _P, _P]),
+    "scc_classify": (C.c_int, [_P, _P, _i64, _P, _P, _P]),
+    "scc_catalog": (C.c_int, [C.c_int, C.POINTER(_i64), _P, _P, _P, _P]),
+    "scc_ags": (C.c_int, [_P, _i64, _i64, _i64, _u64, _u64, _P, _P, _P, _P, C.POINTER(_i64), _P]),
+    "scc_release_caches": (None, []),
+    "scc_num_unrooted": (C.c_int, [C.c_int]),
+    "scc_last_error": (C.c_char_p, []),
+    "scc_version": (C.c_char_p, []),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+class SccError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"scc status {status}: {msg}")
+        self.status = status
+
+
+def _check(st: int):
+    if st != OK:
+        raise SccError(st, _lib.scc_last_error().decode(errors="replace"))
+
+
+def exported_symbols() -> list:
+    return sorted(_SIGS)
+
+
+def version() -> str:
+    return _lib.scc_version().decode()
+
+
+# PyTorch's caching allocator behind the library's allocator hooks
+def _torch_alloc(nbytes, stream, ctx):
+    try:
+        return torch.cuda.caching_allocator_alloc(int(nbytes), torch.cuda.current_device(),
+                                                  int(stream) if stream else None)
+    except Exception:
+        return None
+
+
+def _torch_free(ptr, stream, ctx):
+    torch.cuda.caching_allocator_delete(ptr)
+
+
+_alloc_cb = _ALLOC_FN(_torch_alloc)
+_free_cb = _FREE_FN(_torch_free)
+TORCH_ALLOCATOR = _Allocator(_alloc_cb, _free_cb, None)
+
+
+def _stream_ptr(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t: torch.Tensor | None):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+def _u128(lo, hi) -> int:
+    return int(lo) | (int(hi) << 64)
+
+
+class DeviceGraph:
+    """A CSR graph resident on the GPU (int64 row_ptr, int32 col_idx)."""
+
+    def __init__(self, row_ptr, col_idx, device="cuda"):
+        self.row_ptr = torch.as_tensor(np.asarray(row_ptr), dtype=torch.int64).to(device).contiguous()
+        self.col_idx = torch.as_tensor(np.asarray(col_idx), dtype=torch.int32).to(device).contiguous()
+        self.n = int(self.row_ptr.numel() - 1)
+        self.nnz = int(self.col_idx.numel())
+
+    @classmethod
+    def from_graph(cls, g, device="cuda"):
+        return cls(g.row_ptr, g.col_idx, device)
+
+
+class Table:
+    """The count table of one graph and colouring (``scc_build_table``)."""
+
+    def __init__(self, graph: DeviceGraph, colors, k: int, rooting: int = ROOT_ZERO, max_bits: int = 128,
+                 validate: bool = False, stream=None, use_torch_allocator: bool = True):
+        self.graph = graph
+        self.colors = torch.as_tensor(np.asarray(colors) if not torch.is_tensor(colors) else colors,
+                                      dtype=torch.uint8).to(graph.row_ptr.device).contiguous()
+        self.k = k
+        self._stream = stream
+        csr = _Csr(graph.n, graph.nnz, graph.row_ptr.data_ptr(), graph.col_idx.data_ptr())
+        opts = _BuildOpts(rooting, max_bits, _stream_ptr(stream),
+                          C.pointer(TORCH_ALLOCATOR) if use_torch_allocator else None, 0, 1 if validate else 0)
+        self._h = _P()
+        _check(_lib.scc_build_table(C.byref(csr), _ptr(self.colors), k, C.byref(opts), C.byref(self._h)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.scc_table_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> TableInfo:
+        out = TableInfo()
+        _check(_lib.scc_table_info_get(self._h, C.byref(out)))
+        return out
+
+    def totals(self):
+        """(t, [t_j]) as Python ints."""
+        i = self.info()
+        return _u128(i.t[0], i.t[1]), [_u128(i.tj[j][0], i.tj[j][1]) for j in range(i.num_unrooted)]
+
+    def occ(self, v: int, key: int = -1) -> int:
+        out = (C.c_uint64 * 2)()
+        _check(_lib.scc_occ(self._h, v, key, out))
+        return _u128(out[0], out[1])
+
+    def export_level(self, h: int, stream=None):
+        """(off int64[n+1], key uint16 as int32[nnz], lo uint64[nnz], hi uint64[nnz]) as numpy arrays."""
+        nnz = _i64()
+        _check(_lib.scc_export_level(self._h, h, C.byref(nnz), None, None, None, None, None))
+        dev = self.graph.row_ptr.device
+        off = torch.empty(self.graph.n + 1, dtype=torch.int64, device=dev)
+        key = torch.empty(max(nnz.value, 1), dtype=torch.int16, device=dev)
+        lo = torch.empty(max(nnz.value, 1), dtype=torch.int64, device=dev)
+        hi = torch.empty(max(nnz.value, 1), dtype=torch.int64, device=dev)
+        _check(_lib.scc_export_level(self._h, h, C.byref(nnz), _ptr(off), _ptr(key), _ptr(lo), _ptr(hi),
+                                     _stream_ptr(stream)))
+        n = nnz.value
+        return (off.cpu().numpy(), key[:n].cpu().numpy().view(np.uint16), lo[:n].cpu().numpy().view(np.uint64),
+                hi[:n].cpu().numpy().view(np.uint64))
+
+    def sample(self, n: int, seed: int, stream_id: int = 0, shape: int = -1, first_index: int = 0, stream=None,
+               out=None):
+        """(verts int32[n, k], parent int8[n, k]) device tensors."""
+        dev = self.graph.row_ptr.device
+        if out is None:
+            verts = torch.empty((max(n, 1), self.k), dtype=torch.int32, device=dev)
+            par = torch.empty((max(n, 1), self.k), dtype=torch.int8, device=dev)
+        else:
+            verts, par = out
+        _check(_lib.scc_sample(self._h, shape, n, seed, stream_id, first_index, _ptr(verts), _ptr(par),
+                               _stream_ptr(stream)))
+        return verts[:n], par[:n]
+
+    def classify(self, verts: torch.Tensor, stream=None, want_code: bool = True, out=None):
+        """(code uint32 as int32[n] or None, class uint32 as int32[n]) device tensors."""
+        verts = verts.contiguous()
+        n = verts.shape[0]
+        dev = verts.device
+        if out is None:
+            cls = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+            code = torch.empty(max(n, 1), dtype=torch.int32, device=dev) if want_code else None
+        else:
+            code, cls = out
+        _check(_lib.scc_classify(self._h, _ptr(verts), n, _ptr(code), _ptr(cls), _stream_ptr(stream)))
+        return (code[:n] if code is not None else None), cls[:n]
+
+    def ags(self, cbar: int, round_size: int, budget: int, seed: int, stream_id: int = 0, stream=None):
+        s = num_classes(self.k)
+        nu = self.info().num_unrooted
+        hits = np.zeros(s, np.int64)
+        w = np.zeros(s, np.float64)
+        nj = np.zeros(nu, np.int64)
+        shapes = np.zeros(max(budget // max(round_size, 1), 1), np.int32)
+        nr = _i64()
+        _check(_lib.scc_ags(self._h, cbar, round_size, budget, seed, stream_id,
+                            hits.ctypes.data_as(_P), w.ctypes.data_as(_P), nj.ctypes.data_as(_P),
+                            shapes.ctypes.data_as(_P), C.byref(nr), _stream_ptr(stream)))
+        return {"hits": hits, "w": w, "n_j": nj, "round_shapes": shapes[:nr.value]}
+
+
+def num_classes(k: int) -> int:
+    n = _i64()
+    _check(_lib.scc_catalog(k, C.byref(n), None, None, None, _stream_ptr()))
+    return n.value
+
+
+def catalog(k: int, with_sigma: bool = True, with_sigma_ij: bool = False):
+    """dict with class codes, sigma_i and (optionally) sigma_ij."""
+    s = num_classes(k)
+    codes = np.zeros(s, np.uint32)
+    sigma = np.zeros(s, np.int64) if with_sigma else None
+    nu = _lib.scc_num_unrooted(k)
+    sij = np.zeros(s * nu, np.int64) if with_sigma_ij else None
+    n = _i64()
+    _check(_lib.scc_catalog(k, C.byref(n), codes.ctypes.data_as(_P),
+                            sigma.ctypes.data_as(_P) if sigma is not None else None,
+                            sij.ctypes.data_as(_P) if sij is not None else None, _stream_ptr()))
+    return {"codes": codes, "sigma": sigma, "sigma_ij": sij.reshape(s, nu) if sij is not None else None}
+
+
+def release_caches():
+    _lib.scc_release_caches()

@@ -1,0 +1,464 @@
+// Graphlet classification (Sec. 4.4) and adaptive graphlet sampling (Sec. 4.1).
+//
+// The adjacency code of k ordered vertices is sum_{i<j} [v_i ~ v_j] 2^idx(i,j)
+// with pairs numbered row by row; a graphlet's canonical code is the minimum
+// code over all k! orders, and its class id is the rank of that code among the
+// canonical codes of all connected k-vertex graphs.
+//
+// A per-k lookup table maps every code to its class. It is built on the GPU:
+// each thread canonicalises one code by a branch-and-bound search over vertex
+// orders (positions filled from the most significant row down; only vertices
+// giving the smallest row survive, and of two interchangeable "twin" vertices
+// only one is tried), flags the codes that are their own canonical form, and a
+// scan of the flags ranks them.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <unordered_map>
+
+#include "table.hpp"
+
+namespace {
+
+__host__ __device__ inline int row_start(int p, int k) { return p * k - p * (p + 1) / 2; }
+__host__ __device__ inline int pair_id(int i, int j, int k) { return row_start(i, k) + (j - i - 1); }
+
+__host__ __device__ inline void code_to_adj(uint32_t code, int k, uint32_t *adj)
+{
+    for (int i = 0; i < k; i++) adj[i] = 0;
+    for (int i = 0; i < k; i++)
+        for (int j = i + 1; j < k; j++)
+            if (code >> pair_id(i, j, k) & 1u) { adj[i] |= 1u << j; adj[j] |= 1u << i; }
+}
+
+__host__ __device__ inline bool adj_connected(const uint32_t *adj, int k)
+{
+    uint32_t seen = 1u, front = 1u;
+    while (front) {
+        uint32_t nf = 0;
+        for (uint32_t f = front; f; f &= f - 1) nf |= adj[__builtin_ctz(f)];
+        nf &= ~seen;
+        seen |= nf;
+        front = nf;
+    }
+    return seen == (1u << k) - 1u;
+}
+
+constexpr uint32_t NONE = 0xffffffffu;
+
+// minimum adjacency code over all vertex orders (see file comment)
+__host__ __device__ uint32_t canonical_min(uint32_t code, int k)
+{
+    uint32_t adj[SCC_KMAX];
+    code_to_adj(code, k, adj);
+    if (!adj_connected(adj, k)) return NONE;
+    if (k == 1) return 0;
+    uint32_t best = NONE;
+    uint32_t cand[SCC_KMAX];   // remaining candidates at each position
+    uint32_t at[SCC_KMAX];     // code with rows >= p fixed, per position
+    int pos[SCC_KMAX];         // vertex at each position
+    const uint32_t all = (1u << k) - 1u;
+    uint32_t placed = 0;
+    int p = k - 1;
+    uint32_t cur = 0;
+    bool enter = true;
+    for (;;) {
+        if (enter) {
+            // rows of the unplaced vertices against positions p+1 .. k-1
+            uint32_t m = 0xffffffffu, cset = 0;
+            for (uint32_t f = all & ~placed; f; f &= f - 1) {
+                const int x = __builtin_ctz(f);
+                uint32_t r = 0;
+                for (int q = p + 1; q < k; q++) r |= ((adj[x] >> pos[q]) & 1u) << (q - p - 1);
+                if (r < m) { m = r; cset = 1u << x; }
+                else if (r == m) cset |= 1u << x;
+            }
+            const int rs = row_start(p, k);
+            const uint32_t code_p = cur | (m << rs);
+            const int total = k * (k - 1) / 2;
+            bool prune = false;
+            if (best != NONE && rs < total) {
+                const uint32_t a = code_p >> rs, b = best >> rs;
+                prune = a > b;
+            }
+            if (!prune && p == 0) {
+                if (code_p < best) best = code_p;
+                prune = true;   // complete: go back up
+            }
+            if (!prune) {
+                // one representative per class of twins (swapping twins is an automorphism)
+                uint32_t keep = 0;
+                for (uint32_t f = cset; f; f &= f - 1) {
+                    const int x = __builtin_ctz(f);
+                    bool twin = false;
+                    for (uint32_t g = keep; g; g &= g - 1) {
+                        const int y = __builtin_ctz(g);
+                        if ((adj[x] & ~(1u << y)) == (adj[y] & ~(1u << x))) { twin = true; break; }
+                    }
+                    if (!twin) keep |= 1u << x;
+                }
+                cand[p] = keep;
+                at[p] = code_p;
+            } else {
+                // move up to the nearest position with candidates left
+                p++;
+                while (p < k) {
+                    placed &= ~(1u << pos[p]);
+                    if (cand[p]) break;
+                    p++;
+                }
+                if (p >= k) break;
+            }
+        }
+        // take the next candidate at position p and descend
+        const int x = __builtin_ctz(cand[p]);
+        cand[p] &= cand[p] - 1;
+        pos[p] = x;
+        placed |= 1u << x;
+        cur = at[p];
+        p--;
+        enter = true;
+    }
+    return best;
+}
+
+__global__ void k_canon(int k, uint64_t ncodes, uint32_t *canon, uint32_t *rep)
+{
+    const uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncodes) return;
+    const uint32_t m = canonical_min((uint32_t)c, k);
+    canon[c] = m;
+    rep[c] = (m == (uint32_t)c) ? 1u : 0u;
+}
+
+__global__ void k_class_lut(uint64_t ncodes, const uint32_t *canon, const uint32_t *rank_incl, uint16_t *lut,
+                            uint32_t *cat)
+{
+    const uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncodes) return;
+    const uint32_t m = canon[c];
+    lut[c] = m == NONE ? (uint16_t)0xffff : (uint16_t)(rank_incl[m] - 1u);
+    if (m == (uint32_t)c) cat[rank_incl[c] - 1u] = (uint32_t)c;
+}
+
+__device__ inline bool has_edge(const GraphView &g, int32_t a, int32_t b)
+{
+    int64_t lo = g.row_ptr[a], hi = g.row_ptr[a + 1];
+    const int64_t lo2 = g.row_ptr[b], hi2 = g.row_ptr[b + 1];
+    int32_t target = b;
+    if (hi2 - lo2 < hi - lo) { lo = lo2; hi = hi2; target = a; }
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        const int32_t w = g.col_idx[mid];
+        if (w == target) return true;
+        if (w < target) lo = mid + 1; else hi = mid;
+    }
+    return false;
+}
+
+__global__ void k_classify(GraphView g, int k, const int32_t *verts, int64_t n, const uint16_t *lut,
+                           uint32_t *out_code, uint32_t *out_class)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    int32_t vs[SCC_KMAX];
+    bool ok = true;
+    for (int i = 0; i < k; i++) {
+        vs[i] = verts[s * k + i];
+        ok = ok && vs[i] >= 0 && vs[i] < g.n;
+    }
+    if (!ok) {
+        if (out_code) out_code[s] = 0xffffffffu;
+        out_class[s] = 0xffffffffu;
+        return;
+    }
+    uint32_t code = 0;
+    int q = 0;
+    for (int i = 0; i < k; i++)
+        for (int j = i + 1; j < k; j++, q++)
+            if (has_edge(g, vs[i], vs[j])) code |= 1u << q;
+    if (out_code) out_code[s] = code;
+    const uint16_t c = lut[code];
+    out_class[s] = c == 0xffff ? 0xffffffffu : (uint32_t)c;
+}
+
+__global__ void k_hist(const uint32_t *cls, int64_t n, uint32_t nclass, unsigned long long *hist)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const uint32_t c = cls[s];
+    if (c < nclass) atomicAdd(&hist[c], 1ull);
+}
+
+// ---------------------------------------------------------------------------
+// per-k class data, kept for the life of the process
+// ---------------------------------------------------------------------------
+struct ClassData {
+    uint16_t *lut = nullptr;          // device, 2^(k(k-1)/2) entries
+    std::vector<uint32_t> codes;      // canonical code of each class
+    std::vector<int64_t> sigma;       // spanning trees
+    std::vector<std::vector<int64_t>> sigma_ij;   // per class, computed on demand
+};
+
+std::mutex g_cls_mu;
+ClassData *g_cls[SCC_KMAX + 1];
+
+scc_status ensure_classes(int k, hipStream_t st, ClassData **out)
+{
+    std::lock_guard<std::mutex> lk(g_cls_mu);
+    if (g_cls[k]) { *out = g_cls[k]; return SCC_OK; }
+    const int nb = k * (k - 1) / 2;
+    const uint64_t ncodes = 1ull << nb;
+    uint32_t *canon = nullptr, *rank = nullptr, *cat = nullptr;
+    uint16_t *lut = nullptr;
+    auto cleanup = [&]() { (void)hipFree(canon); (void)hipFree(rank); (void)hipFree(cat); };
+    if (hipMalloc(&canon, ncodes * 4) != hipSuccess || hipMalloc(&rank, ncodes * 4) != hipSuccess ||
+        hipMalloc(&lut, ncodes * 2) != hipSuccess || hipMalloc(&cat, 65536 * 4) != hipSuccess) {
+        cleanup();
+        (void)hipFree(lut);
+        return set_error(SCC_ENOMEM, "class lookup table for k = %d", k);
+    }
+    const unsigned blocks = (unsigned)((ncodes + 255) / 256);
+    hipLaunchKernelGGL(k_canon, dim3(blocks), dim3(256), 0, st, k, ncodes, canon, rank);
+    // inclusive scan of the representative flags, in place
+    scc_table tmp;
+    tmp.stream = st;
+    scc_status s = scan_u32(&tmp, rank, rank, (int64_t)ncodes);
+    if (s) { cleanup(); (void)hipFree(lut); return s; }
+    uint32_t nclass = 0;
+    if (hipMemcpy(&nclass, rank + (ncodes - 1), 4, hipMemcpyDeviceToHost) != hipSuccess) {
+        cleanup(); (void)hipFree(lut);
+        return set_error(SCC_EDEVICE, "class count");
+    }
+    hipLaunchKernelGGL(k_class_lut, dim3(blocks), dim3(256), 0, st, ncodes, canon, rank, lut, cat);
+    ClassData *cd = new ClassData();
+    cd->lut = lut;
+    cd->codes.resize(nclass);
+    hipError_t e = hipMemcpyAsync(cd->codes.data(), cat, nclass * 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    cleanup();
+    if (e != hipSuccess) { (void)hipFree(lut); delete cd; return set_error(SCC_EDEVICE, "class table: %s", hipGetErrorString(e)); }
+    cd->sigma_ij.resize(nclass);
+    g_cls[k] = cd;
+    *out = cd;
+    return SCC_OK;
+}
+
+// number of spanning trees: determinant of the reduced Laplacian modulo the
+// prime 2^61 - 1 (the true value is below 8^6, so the residue is the value)
+int64_t spanning_trees_host(uint32_t code, int k)
+{
+    if (k == 1) return 1;
+    const uint64_t P = (1ull << 61) - 1;
+    uint32_t adj[SCC_KMAX];
+    code_to_adj(code, k, adj);
+    const int m = k - 1;
+    uint64_t A[SCC_KMAX][SCC_KMAX];
+    for (int i = 0; i < m; i++)
+        for (int j = 0; j < m; j++) {
+            const int a = i + 1, b = j + 1;
+            if (a == b) A[i][j] = (uint64_t)__builtin_popcount(adj[a]);
+            else A[i][j] = (adj[a] >> b & 1u) ? P - 1 : 0;
+        }
+    auto mulm = [&](uint64_t x, uint64_t y) { return (uint64_t)(((u128)x * y) % P); };
+    auto powm = [&](uint64_t x, uint64_t e) { uint64_t r = 1; while (e) { if (e & 1) r = mulm(r, x); x = mulm(x, x); e >>= 1; } return r; };
+    uint64_t det = 1;
+    for (int c = 0; c < m; c++) {
+        int piv = -1;
+        for (int r = c; r < m; r++) if (A[r][c]) { piv = r; break; }
+        if (piv < 0) return 0;
+        if (piv != c) { for (int j = 0; j < m; j++) std::swap(A[piv][j], A[c][j]); det = (P - det) % P; }
+        det = mulm(det, A[c][c]);
+        const uint64_t inv = powm(A[c][c], P - 2);
+        for (int r = c + 1; r < m; r++) {
+            if (!A[r][c]) continue;
+            const uint64_t f = mulm(A[r][c], inv);
+            for (int j = c; j < m; j++) A[r][j] = (A[r][j] + P - mulm(f, A[c][j])) % P;
+        }
+    }
+    return (int64_t)det;
+}
+
+// spanning trees of a graphlet by unrooted shape: a depth-first choice of k-1
+// edges that never closes a cycle (every acyclic (k-1)-edge set on k vertices
+// is a spanning tree); each tree's shape is looked up through its edge code
+void spanning_trees_by_shape_host(uint32_t code, int k, int64_t *out)
+{
+    static std::mutex memo_mu;
+    static std::unordered_map<uint64_t, int> memo;   // (k, tree code) -> shape
+    const int nu = unrooted_count(k);
+    for (int j = 0; j < nu; j++) out[j] = 0;
+    if (k == 1) { out[0] = 1; return; }
+    int eu[32], ev[32], ne = 0;
+    for (int i = 0; i < k; i++)
+        for (int j = i + 1; j < k; j++)
+            if (code >> pair_id(i, j, k) & 1u) { eu[ne] = i; ev[ne] = j; ne++; }
+    int comp[SCC_KMAX];
+    for (int i = 0; i < k; i++) comp[i] = i;
+    // recursive lambda over edge index with the component labels
+    std::function<void(int, int, uint32_t)> rec = [&](int e, int chosen, uint32_t tcode) {
+        if (chosen == k - 1) {
+            const uint64_t key = ((uint64_t)k << 32) | tcode;
+            int sh;
+            {
+                std::lock_guard<std::mutex> g(memo_mu);
+                auto it = memo.find(key);
+                if (it != memo.end()) sh = it->second;
+                else {
+                    uint32_t adj[SCC_KMAX];
+                    code_to_adj(tcode, k, adj);
+                    sh = tree_unrooted_id(k, adj);
+                    memo.emplace(key, sh);
+                }
+            }
+            out[sh]++;
+            return;
+        }
+        if (ne - e < (k - 1) - chosen) return;
+        // take edge e if it joins two components
+        const int a = comp[eu[e]], b = comp[ev[e]];
+        if (a != b) {
+            int save[SCC_KMAX];
+            memcpy(save, comp, sizeof save);
+            for (int i = 0; i < k; i++) if (comp[i] == b) comp[i] = a;
+            rec(e + 1, chosen + 1, tcode | (1u << pair_id(eu[e], ev[e], k)));
+            memcpy(comp, save, sizeof save);
+        }
+        rec(e + 1, chosen, tcode);
+    };
+    rec(0, 0, 0);
+}
+
+}  // namespace
+
+extern "C" scc_status scc_classify(const scc_table *T, const int32_t *verts, int64_t n, uint32_t *out_code,
+                                   uint32_t *out_class, void *stream)
+{
+    if (!T) return set_error(SCC_EINVAL, "table NULL");
+    if (n < 0) return set_error(SCC_EINVAL, "n < 0");
+    if (n == 0) return SCC_OK;
+    if (!verts || !out_class) return set_error(SCC_EINVAL, "NULL buffer");
+    hipStream_t st = stream ? (hipStream_t)stream : T->stream;
+    ClassData *cd;
+    scc_status s = ensure_classes(T->k, st, &cd);
+    if (s) return s;
+    GraphView g{T->n, T->row_ptr, T->col_idx, T->colors};
+    hipLaunchKernelGGL(k_classify, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g, T->k, verts, n, cd->lut,
+                       out_code, out_class);
+    HIP_TRY(hipGetLastError());
+    return SCC_OK;
+}
+
+extern "C" scc_status scc_catalog(int k, int64_t *num_classes, uint32_t *codes, int64_t *sigma, int64_t *sigma_ij,
+                                  void *stream)
+{
+    if (k < 1 || k > SCC_KMAX) return set_error(SCC_EINVAL, "k out of range");
+    ClassData *cd;
+    scc_status s = ensure_classes(k, (hipStream_t)stream, &cd);
+    if (s) return s;
+    const int64_t nc = (int64_t)cd->codes.size();
+    if (num_classes) *num_classes = nc;
+    if (codes) memcpy(codes, cd->codes.data(), nc * 4);
+    if (sigma)
+        for (int64_t i = 0; i < nc; i++) sigma[i] = spanning_trees_host(cd->codes[i], k);
+    if (sigma_ij) {
+        const int nu = unrooted_count(k);
+        for (int64_t i = 0; i < nc; i++) spanning_trees_by_shape_host(cd->codes[i], k, sigma_ij + i * nu);
+    }
+    return SCC_OK;
+}
+
+extern "C" void scc_release_caches(void)
+{
+    std::lock_guard<std::mutex> lk(g_cls_mu);
+    for (int k = 0; k <= SCC_KMAX; k++) {
+        if (g_cls[k]) { (void)hipFree(g_cls[k]->lut); delete g_cls[k]; g_cls[k] = nullptr; }
+    }
+}
+
+extern "C" scc_status scc_ags(const scc_table *tc, int64_t cbar, int64_t round_size, int64_t budget, uint64_t seed,
+                              uint64_t stream_id, int64_t *hits, double *w_out, int64_t *n_j, int32_t *round_shapes,
+                              int64_t *n_rounds, void *stream)
+{
+    scc_table *T = const_cast<scc_table *>(tc);
+    if (!T || !hits || !w_out || !n_j || !n_rounds) return set_error(SCC_EINVAL, "NULL argument");
+    if (cbar < 1 || round_size < 1 || budget < 0) return set_error(SCC_EINVAL, "bad AGS parameters");
+    const int k = T->k;
+    hipStream_t st = stream ? (hipStream_t)stream : T->stream;
+    ClassData *cd;
+    scc_status s = ensure_classes(k, st, &cd);
+    if (s) return s;
+    const int S = (int)cd->codes.size(), NS = T->hlut.num_unr;
+    std::vector<int64_t> c(S, 0), nj(NS, 0);
+    std::vector<double> w(S, 0.0), tjd(NS);
+    std::vector<char> cov(S, 0), sig_ok(S, 0);
+    std::vector<int64_t> sig((size_t)S * NS, 0);
+    for (int q = 0; q < NS; q++) tjd[q] = (double)T->tj[q];
+    int j = -1;
+    for (int q = 0; q < NS; q++)
+        if (T->tj[q] > 0 && (j < 0 || T->tj[q] > T->tj[j])) j = q;
+    if (j < 0) return set_error(SCC_EEMPTY, "no colourful %d-treelet", k);
+    int32_t *dv = (int32_t *)T->mem.get((size_t)round_size * k * 4);
+    int8_t *dp = (int8_t *)T->mem.get((size_t)round_size * k);
+    uint32_t *dc = (uint32_t *)T->mem.get((size_t)round_size * 4);
+    unsigned long long *dh = (unsigned long long *)T->mem.get((size_t)S * 8);
+    std::vector<unsigned long long> hh(S);
+    auto done = [&](scc_status r) { T->mem.put(dv); T->mem.put(dp); T->mem.put(dc); T->mem.put(dh); return r; };
+    if (!dv || !dp || !dc || !dh) return done(set_error(SCC_ENOMEM, "AGS buffers"));
+    int64_t drawn = 0, nr = 0, ncov = 0;
+    while (ncov < S && drawn + round_size <= budget) {
+        s = scc_sample(T, j, round_size, seed, stream_id, (uint64_t)drawn, dv, dp, st);
+        if (s) return done(s);
+        s = scc_classify(T, dv, round_size, nullptr, dc, st);
+        if (s) return done(s);
+        if (hipMemsetAsync(dh, 0, (size_t)S * 8, st) != hipSuccess) return done(set_error(SCC_EDEVICE, "AGS memset"));
+        hipLaunchKernelGGL(k_hist, dim3((unsigned)((round_size + 255) / 256)), dim3(256), 0, st, dc, round_size, (uint32_t)S, dh);
+        if (hipMemcpyAsync(hh.data(), dh, (size_t)S * 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return done(set_error(SCC_EDEVICE, "AGS histogram"));
+        if (round_shapes) round_shapes[nr] = j;
+        nr++;
+        drawn += round_size;
+        nj[j] += round_size;
+        for (int i = 0; i < S; i++) {
+            if (!hh[i]) continue;
+            c[i] += (int64_t)hh[i];
+            if (!sig_ok[i]) { spanning_trees_by_shape_host(cd->codes[i], k, &sig[(size_t)i * NS]); sig_ok[i] = 1; }
+        }
+        bool newcov = false;
+        for (int i = 0; i < S; i++)
+            if (!cov[i] && c[i] >= cbar) { cov[i] = 1; ncov++; newcov = true; }
+        if (newcov && ncov < S) {
+            for (int i = 0; i < S; i++) {
+                if (!cov[i]) continue;
+                double acc = 0.0;
+                for (int q = 0; q < NS; q++)
+                    if (tjd[q] > 0) acc += (double)nj[q] * (double)sig[(size_t)i * NS + q] / tjd[q];
+                w[i] = acc;
+            }
+            int best = -1;
+            double bv = 0.0;
+            for (int q = 0; q < NS; q++) {
+                if (!(tjd[q] > 0)) continue;
+                double acc = 0.0;
+                for (int i = 0; i < S; i++)
+                    if (cov[i]) acc += (double)sig[(size_t)i * NS + q] * (double)c[i] / w[i];
+                acc /= tjd[q];
+                if (best < 0 || acc < bv) { best = q; bv = acc; }
+            }
+            j = best;
+        }
+    }
+    for (int i = 0; i < S; i++) {
+        double acc = 0.0;
+        if (sig_ok[i])
+            for (int q = 0; q < NS; q++)
+                if (tjd[q] > 0) acc += (double)nj[q] * (double)sig[(size_t)i * NS + q] / tjd[q];
+        hits[i] = c[i];
+        w_out[i] = acc;
+    }
+    for (int q = 0; q < NS; q++) n_j[q] = nj[q];
+    *n_rounds = nr;
+    return done(SCC_OK);
+}

@@ -1,0 +1,383 @@
+// The sampling phase on the GPU (Sec. 2.2) and the table's database queries
+// occ(v), occ(T_C, v) (Sec. 3), plus export of stored records.
+//
+// One wave draws one sample. Every draw is a scan over a short list in a fixed
+// order (vertices, record entries, colour sets, neighbours): the wave loads 64
+// items, forms their inclusive running sum with shuffles, and the first lane
+// whose running sum exceeds the drawn integer wins.
+#include <cstring>
+
+#include "table.hpp"
+
+namespace {
+
+struct SampleArgs {
+    GraphView g;
+    const DevLut *L;
+    int k, shape, zero;
+    LevelView lev[SCC_KMAX + 1];          // 2..k
+    const uint64_t *Slo[SCC_KMAX + 1];    // neighbour sums 1..k-1
+    const uint64_t *Shi[SCC_KMAX + 1];
+    const u128 *M[SCC_KMAX + 1];
+    const u128 *pre;                      // running sums of admissible level-k totals
+    u128 total;
+    uint64_t seed, stream, first;
+    int64_t nsamp;
+    int32_t *verts;
+    int8_t *par;
+    int *err;
+};
+
+__device__ inline int key_level(const DevLut &L, uint32_t key)
+{
+    int h = 1;
+    while (h < L.k && (int)key >= L.off[h + 1]) h++;
+    return h;
+}
+
+// first lane (in order) whose inclusive running sum exceeds `target`; -1 if none
+__device__ inline int first_exceeding(u128 incl, u128 target)
+{
+    uint64_t bal = __ballot(incl > target);
+    return bal ? __ffsll((long long)bal) - 1 : -1;
+}
+
+// count of (T, C) with the given key at x (level h), level 1 handled implicitly
+__device__ inline u128 own_count(const SampleArgs &A, int h, int64_t x, uint32_t key)
+{
+    if (h == 1) return (key == (uint32_t)A.g.colors[x]) ? 1 : 0;   // key of ({.}, {c}) is c
+    return record_lookup(A.lev[h], x, key);
+}
+
+__global__ void __launch_bounds__(WAVE) k_sample(SampleArgs A)
+{
+    __shared__ int32_t sv[SCC_KMAX];
+    __shared__ int8_t sp_par[SCC_KMAX];
+    __shared__ uint32_t st_key[2 * SCC_KMAX];
+    __shared__ int st_pos[2 * SCC_KMAX];
+    __shared__ u128 st_cnt[2 * SCC_KMAX];
+    const DevLut &L = *A.L;
+    const int lane = lane_id();
+    const int k = A.k;
+    for (int64_t s = blockIdx.x; s < A.nsamp; s += gridDim.x) {
+        const uint64_t idx = A.first + (uint64_t)s;
+        // (1) root: first vertex whose running sum exceeds X, then the entry of its record
+        const u128 X = draw_below(A.total, A.seed, A.stream, idx, 0);
+        int64_t lo = 0, hi = A.g.n - 1;
+        while (lo < hi) {
+            int64_t mid = (lo + hi) >> 1;
+            if (A.pre[mid] > X) hi = mid; else lo = mid + 1;
+        }
+        const int64_t v = lo;
+        const u128 res = X - (v > 0 ? A.pre[v - 1] : (u128)0);
+        const LevelView &Lk = A.lev[k];
+        const uint32_t mk = Lk.meta[v], lenk = META_LEN(mk), kwk = key_words(lenk);
+        const uint64_t *reck = Lk.pool + (lenk ? Lk.off[v] : 0);
+        u128 run = 0;
+        uint32_t rkey = 0xffffffffu;
+        u128 rcnt = 0;
+        for (uint32_t b0 = 0; b0 < lenk; b0 += WAVE) {
+            const uint32_t e = b0 + lane;
+            u128 c = 0;
+            uint32_t key = 0;
+            if (e < lenk) {
+                key = ((const uint16_t *)reck)[e];
+                const int t = (int)(key - L.off[k]) / L.bk[k];
+                if (A.shape < 0 || L.unr_of[t] == A.shape)
+                    c = mk128(reck[kwk + e], META_WIDE(mk) ? reck[kwk + lenk + e] : 0);
+            }
+            const u128 incl = run + wave_incl_scan128(c);
+            const int w = first_exceeding(incl, res);
+            if (w >= 0) {
+                rkey = __shfl(key, w, WAVE);
+                rcnt = shfl128(c, w);
+                break;
+            }
+            run = shfl128(incl, WAVE - 1);
+        }
+        if (rkey == 0xffffffffu) {
+            if (lane == 0) atomicOr(A.err, 1);
+            continue;
+        }
+        if (lane == 0) {
+            sv[0] = (int32_t)v; sp_par[0] = -1;
+            st_key[0] = rkey; st_pos[0] = 0; st_cnt[0] = rcnt;
+        }
+        __syncthreads();
+        int nv = 1, sp = 1, dec = 0;
+        bool fail = false;
+        // (2) decompose, LIFO: (T', C \ C'', x) is processed before (T'', C'', u)
+        while (sp > 0 && !fail) {
+            sp--;
+            const uint32_t key = st_key[sp];
+            const int pos = st_pos[sp];
+            const u128 cT = st_cnt[sp];
+            __syncthreads();
+            const int h = key_level(L, key);
+            if (h == 1) continue;
+            const int rel = (int)key - L.off[h];
+            const int t = rel / L.bk[h];
+            const uint32_t C = L.mask_k[h][rel - t * L.bk[h]];
+            const int64_t x = sv[pos];
+            const int cx = A.g.colors[x];
+            const int hp = L.dec_hp[h][t], hpp = h - hp, a = L.dec_a[h][t], b = L.dec_b[h][t];
+            const int beta = L.dec_beta[h][t];
+            const u128 Y = draw_below((u128)beta * cT, A.seed, A.stream, idx, 1 + 2 * dec);
+            // stage 1: C'' among the |T''|-subsets of C \ {c_x}, ascending bitmask
+            const uint32_t R = C & ~(1u << cx);
+            int ncand = 1;
+            for (int i = 1; i <= hpp; i++) ncand = ncand * (h - 1 - hpp + i) / i;
+            u128 w = 0, xprime = 0, sval = 0;
+            uint32_t cpp = 0;
+            if (lane < ncand) {
+                // deposit the lane-th hpp-subset of the low h-1 positions onto R's bits
+                uint32_t pm = L.mask_s[hpp][lane], dep = 0, rr = R;
+                for (int q = 0; rr; q++) {
+                    const uint32_t bit = rr & (~rr + 1u);
+                    if (pm >> q & 1u) dep |= bit;
+                    rr &= rr - 1u;
+                }
+                cpp = dep;
+                const uint32_t kprime = L.off[hp] + a * L.bk[hp] + L.colex_k[C ^ cpp];
+                xprime = own_count(A, hp, x, kprime);
+                const int ws = L.WS[hpp];
+                const int si = b * L.bk1[hpp] + L.colex_s[compress_out(cpp, cx)];
+                const uint64_t slo = A.Slo[hpp][(size_t)x * ws + si];
+                const uint64_t shi = hi64(A.M[hpp][x]) ? A.Shi[hpp][(size_t)x * ws + si] : 0;
+                sval = mk128(slo, shi);
+                w = xprime * sval;
+            }
+            const u128 incl1 = wave_incl_scan128(w);
+            const int w1 = first_exceeding(incl1, Y);
+            if (w1 < 0) { fail = true; break; }
+            const uint32_t Cpp = __shfl(cpp, w1, WAVE);
+            const u128 Xp = shfl128(xprime, w1);
+            const u128 Sv = shfl128(sval, w1);
+            // stage 2: neighbour u of x with weight c(T''_{C''}, u), CSR order
+            const u128 Z = draw_below(Sv, A.seed, A.stream, idx, 2 + 2 * dec);
+            const uint32_t kpp = L.off[hpp] + b * L.bk[hpp] + L.colex_k[Cpp];
+            const int64_t ra = A.g.row_ptr[x], rb = A.g.row_ptr[x + 1];
+            u128 run2 = 0;
+            int64_t u = -1;
+            u128 wu = 0;
+            for (int64_t base = ra; base < rb; base += WAVE) {
+                const int64_t e = base + lane;
+                u128 c = 0;
+                int32_t uu = -1;
+                if (e < rb) {
+                    uu = A.g.col_idx[e];
+                    c = own_count(A, hpp, uu, kpp);
+                }
+                const u128 incl = run2 + wave_incl_scan128(c);
+                const int w2 = first_exceeding(incl, Z);
+                if (w2 >= 0) {
+                    u = __shfl(uu, w2, WAVE);
+                    wu = shfl128(c, w2);
+                    break;
+                }
+                run2 = shfl128(incl, WAVE - 1);
+            }
+            if (u < 0) { fail = true; break; }
+            if (lane == 0) {
+                sv[nv] = (int32_t)u;
+                sp_par[nv] = (int8_t)pos;
+                st_key[sp] = kpp; st_pos[sp] = nv; st_cnt[sp] = wu;
+                st_key[sp + 1] = L.off[hp] + a * L.bk[hp] + L.colex_k[C ^ Cpp];
+                st_pos[sp + 1] = pos; st_cnt[sp + 1] = Xp;
+            }
+            __syncthreads();
+            nv++;
+            sp += 2;
+            dec++;
+        }
+        if (fail || nv != k) {
+            if (lane == 0) atomicOr(A.err, 2);
+            continue;
+        }
+        if (lane < k) {
+            A.verts[(size_t)s * k + lane] = sv[lane];
+            A.par[(size_t)s * k + lane] = sp_par[lane];
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_occ(GraphView g, const DevLut *Lp, LevelView lev_h, int h, int64_t v, int32_t key,
+                      const u128 *eta, u128 *out)
+{
+    if (threadIdx.x != 0) return;
+    if (key < 0) { *out = eta[v]; return; }
+    if (h == 1) { *out = ((uint32_t)key == g.colors[v]) ? 1 : 0; return; }
+    *out = record_lookup(lev_h, v, (uint32_t)key);
+}
+
+__global__ void k_len(int64_t n, const uint32_t *meta, int h1, const uint8_t *colors, uint64_t *len)
+{
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    len[v] = h1 ? 1 : META_LEN(meta[v]);
+}
+
+__global__ void __launch_bounds__(WAVE) k_export(int64_t n, LevelView Lv, int h1, const uint8_t *colors,
+                                                 const uint64_t *incl, int64_t *off, uint16_t *key,
+                                                 uint64_t *lo, uint64_t *hi)
+{
+    const int64_t v = blockIdx.x;
+    const int lane = threadIdx.x;
+    const uint64_t end = incl[v];
+    if (h1) {
+        if (lane == 0) {
+            off[v] = (int64_t)end - 1;
+            if (v == n - 1) off[n] = (int64_t)end;
+            key[end - 1] = colors[v];
+            lo[end - 1] = 1;
+            hi[end - 1] = 0;
+        }
+        return;
+    }
+    const uint32_t m = Lv.meta[v], len = META_LEN(m);
+    const uint64_t start = end - len;
+    if (lane == 0) {
+        off[v] = (int64_t)start;
+        if (v == n - 1) off[n] = (int64_t)end;
+    }
+    if (!len) return;
+    const uint64_t *rec = Lv.pool + Lv.off[v];
+    const uint32_t kw = key_words(len);
+    for (uint32_t e = lane; e < len; e += WAVE) {
+        key[start + e] = ((const uint16_t *)rec)[e];
+        lo[start + e] = rec[kw + e];
+        hi[start + e] = META_WIDE(m) ? rec[kw + len + e] : 0;
+    }
+}
+
+LevelView lview(const TableLevel &l) { return LevelView{l.pool, l.off, l.meta, l.N}; }
+
+}  // namespace
+
+scc_status table_prefix(scc_table *T, int shape, const u128 **pre, u128 *total)
+{
+    if (shape < 0) {
+        *pre = T->pre;
+        *total = T->root_total;
+        return SCC_OK;
+    }
+    std::lock_guard<std::mutex> g(T->mu);
+    auto it = T->pre_shape.find(shape);
+    if (it != T->pre_shape.end()) {
+        *pre = it->second;
+        *total = T->tot_shape[shape];
+        return SCC_OK;
+    }
+    const int64_t n = T->n;
+    u128 *eta = (u128 *)T->mem.get((size_t)n * 16 + 16);
+    u128 *p = (u128 *)T->alloc((size_t)n * 16 + 16);
+    if (!eta || !p) { T->mem.put(eta); return set_error(SCC_ENOMEM, "shape prefix"); }
+    launch_eta_shape(T, shape, eta);
+    scc_status s = scan_u128(T, eta, p, n);
+    T->mem.put(eta);
+    if (s) return s;
+    u128 tot = 0;
+    if (n) {
+        HIP_TRY(hipMemcpyAsync(&tot, p + (n - 1), 16, hipMemcpyDeviceToHost, T->stream));
+        HIP_TRY(hipStreamSynchronize(T->stream));
+    }
+    T->pre_shape[shape] = p;
+    T->tot_shape[shape] = tot;
+    *pre = p;
+    *total = tot;
+    return SCC_OK;
+}
+
+extern "C" scc_status scc_sample(const scc_table *tc, int32_t shape, int64_t n, uint64_t seed,
+                                 uint64_t stream_id, uint64_t first_index, int32_t *out_verts,
+                                 int8_t *out_parent, void *stream)
+{
+    scc_table *T = const_cast<scc_table *>(tc);
+    if (!T) return set_error(SCC_EINVAL, "table NULL");
+    if (n < 0) return set_error(SCC_EINVAL, "n < 0");
+    if (shape < -1 || shape >= T->hlut.num_unr) return set_error(SCC_EINVAL, "shape %d out of range", shape);
+    if (n == 0) return SCC_OK;
+    if (!out_verts || !out_parent) return set_error(SCC_EINVAL, "output NULL");
+    const u128 *pre;
+    u128 total;
+    scc_status s = table_prefix(T, shape, &pre, &total);
+    if (s) return s;
+    if (total == 0) return set_error(SCC_EEMPTY, "no colourful %d-treelet to sample", T->k);
+    hipStream_t st = stream ? (hipStream_t)stream : T->stream;
+    int *err = (int *)T->mem.get(16);
+    if (!err) return set_error(SCC_ENOMEM, "sample flags");
+    SampleArgs A{};
+    A.g = GraphView{T->n, T->row_ptr, T->col_idx, T->colors};
+    A.L = T->dlut; A.k = T->k; A.shape = shape; A.zero = T->rooting == SCC_ROOT_ZERO;
+    for (int h = 2; h <= T->k; h++) A.lev[h] = lview(T->lev[h]);
+    for (int h = 1; h < T->k; h++) { A.Slo[h] = T->S[h].lo; A.Shi[h] = T->S[h].hi; A.M[h] = T->S[h].M; }
+    A.pre = pre; A.total = total; A.seed = seed; A.stream = stream_id; A.first = first_index;
+    A.nsamp = n; A.verts = out_verts; A.par = out_parent; A.err = err;
+    hipError_t e = hipMemsetAsync(err, 0, 4, st);
+    const int64_t grid = std::min<int64_t>(n, (int64_t)1 << 20);
+    hipLaunchKernelGGL(k_sample, dim3((unsigned)grid), dim3(WAVE), 0, st, A);
+    int herr = 0;
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    T->mem.put(err);
+    if (e != hipSuccess) return set_error(SCC_EDEVICE, "sample: %s", hipGetErrorString(e));
+    if (herr) return set_error(SCC_EDEVICE, "internal: a sample draw fell off its list (%d)", herr);
+    return SCC_OK;
+}
+
+extern "C" scc_status scc_occ(const scc_table *T, int64_t v, int32_t key, uint64_t out[2])
+{
+    if (!T || !out) return set_error(SCC_EINVAL, "NULL argument");
+    if (v < 0 || v >= T->n) return set_error(SCC_EINVAL, "vertex out of range");
+    if (key >= T->hlut.nkeys || key < -1) return set_error(SCC_EINVAL, "key out of range");
+    int h = 1;
+    if (key >= 0)
+        while (h < T->k && key >= T->hlut.off[h + 1]) h++;
+    u128 *d = (u128 *)const_cast<scc_table *>(T)->mem.get(16);
+    if (!d) return set_error(SCC_ENOMEM, "occ");
+    GraphView g{T->n, T->row_ptr, T->col_idx, T->colors};
+    hipLaunchKernelGGL(k_occ, dim3(1), dim3(WAVE), 0, T->stream, g, T->dlut, lview(T->lev[h]), h, v, key, T->eta, d);
+    u128 r = 0;
+    hipError_t e = hipMemcpyAsync(&r, d, 16, hipMemcpyDeviceToHost, T->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(T->stream);
+    const_cast<scc_table *>(T)->mem.put(d);
+    if (e != hipSuccess) return set_error(SCC_EDEVICE, "occ: %s", hipGetErrorString(e));
+    out[0] = lo64(r);
+    out[1] = hi64(r);
+    return SCC_OK;
+}
+
+extern "C" scc_status scc_export_level(const scc_table *tc, int h, int64_t *nnz_out, int64_t *off,
+                                       uint16_t *key, uint64_t *lo, uint64_t *hi, void *stream)
+{
+    scc_table *T = const_cast<scc_table *>(tc);
+    if (!T) return set_error(SCC_EINVAL, "table NULL");
+    if (h < 1 || h > T->k) return set_error(SCC_EINVAL, "level %d out of range", h);
+    const int64_t nnz = T->lev[h].nnz;
+    if (nnz_out) *nnz_out = nnz;
+    if (!off) return SCC_OK;
+    const int64_t n = T->n;
+    hipStream_t st = stream ? (hipStream_t)stream : T->stream;
+    if (n == 0) {
+        int64_t z = 0;
+        HIP_TRY(hipMemcpyAsync(off, &z, 8, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        return SCC_OK;
+    }
+    uint64_t *len = (uint64_t *)T->mem.get((size_t)n * 8);
+    if (!len) return set_error(SCC_ENOMEM, "export scratch");
+    hipLaunchKernelGGL(k_len, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, T->lev[h].meta, h == 1, T->colors, len);
+    hipStream_t keep = T->stream;
+    T->stream = st;
+    scc_status s = scan_u64(T, len, len, n);
+    T->stream = keep;
+    if (s) { T->mem.put(len); return s; }
+    hipLaunchKernelGGL(k_export, dim3((unsigned)n), dim3(WAVE), 0, st, n, lview(T->lev[h]), h == 1, T->colors, len,
+                       off, key, lo, hi);
+    hipError_t e = hipStreamSynchronize(st);
+    T->mem.put(len);
+    if (e != hipSuccess) return set_error(SCC_EDEVICE, "export: %s", hipGetErrorString(e));
+    return SCC_OK;
+}

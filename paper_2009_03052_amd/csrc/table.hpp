@@ -1,0 +1,85 @@
+// The count table object behind the C ABI.
+#pragma once
+
+#include <map>
+#include <mutex>
+
+#include "device.hpp"
+
+struct TableLevel {
+    uint64_t *pool = nullptr;   // packed records
+    uint64_t pool_words = 0;
+    uint64_t *off = nullptr;    // [n] word offset of each record
+    uint32_t *meta = nullptr;   // [n] len | wide << 31
+    u128 *N = nullptr;          // [n] sum of the vertex's counts
+    int64_t nnz = 0;
+    int64_t wide = 0;
+};
+
+struct TableSums {
+    uint64_t *lo = nullptr;     // [n * WS_h]
+    uint64_t *hi = nullptr;     // [n * WS_h] when some vertex needs 128 bits
+    u128 *M = nullptr;          // [n] sum over neighbours of N_h
+};
+
+struct scc_table {
+    int k = 0, rooting = SCC_ROOT_ZERO, max_bits = 128;
+    int64_t n = 0, nnz_g = 0;
+    const int64_t *row_ptr = nullptr;
+    const int32_t *col_idx = nullptr;
+    const uint8_t *colors = nullptr;
+    hipStream_t stream = nullptr;
+    DevMem mem;
+    DevLut hlut;
+    DevLut *dlut = nullptr;          // device copy of hlut
+    int16_t *key_sidx = nullptr;     // [k * nkeys] neighbour-sum index of a key seen from colour c, or -1
+    int16_t *key_xidx = nullptr;     // [k * nkeys] own-count index of a key at a colour-c vertex, or -1
+    TableLevel lev[SCC_KMAX + 1];
+    TableSums S[SCC_KMAX + 1];
+    u128 *eta = nullptr;             // [n] admissible level-k total per vertex (all shapes)
+    u128 *pre = nullptr;             // [n] inclusive running sum of eta
+    u128 t = 0;                      // colourful k-treelet copies
+    u128 tj[32] = {0};
+    u128 root_total = 0;             // sum of eta (k * t under SCC_ROOT_ALL)
+    std::map<int, u128 *> pre_shape; // per unrooted shape: running sums, built on demand
+    std::map<int, u128> tot_shape;
+    std::mutex mu;
+    std::vector<void *> owned;       // every device allocation of the table
+    double level_ms[SCC_KMAX + 1] = {0};
+    double gather_ms[SCC_KMAX + 1] = {0};
+    double gather_bytes[SCC_KMAX + 1] = {0};
+    int64_t bytes = 0;
+
+    void *alloc(size_t bytes_)
+    {
+        void *p = mem.get(bytes_);
+        if (p) {
+            owned.push_back(p);
+            bytes += (int64_t)bytes_;
+        }
+        return p;
+    }
+    void release(void *p, size_t bytes_)
+    {
+        for (size_t i = 0; i < owned.size(); i++)
+            if (owned[i] == p) {
+                owned.erase(owned.begin() + i);
+                bytes -= (int64_t)bytes_;
+                mem.put(p);
+                return;
+            }
+    }
+    ~scc_table()
+    {
+        for (void *p : owned) mem.put(p);
+    }
+};
+
+// Running sums of admissible level-k totals for one unrooted shape (or all, shape < 0).
+scc_status table_prefix(scc_table *T, int shape, const u128 **pre, u128 *total);
+// Inclusive running sum of n u128 values on the stream (scratch from T's allocator).
+scc_status scan_u128(scc_table *T, const u128 *in, u128 *out, int64_t n);
+scc_status scan_u64(scc_table *T, const uint64_t *in, uint64_t *out, int64_t n);
+scc_status scan_u32(scc_table *T, const uint32_t *in, uint32_t *out, int64_t n);
+// admissible level-k totals of one unrooted shape per vertex (enqueued on T's stream)
+void launch_eta_shape(scc_table *T, int shape, u128 *eta);

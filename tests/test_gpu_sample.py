@@ -1,0 +1,120 @@
+"""GPU sampler, classifier, catalog and AGS vs the oracle (bit-exact samples and classes).
+
+The sampler's stream is fixed by (seed, stream id, sample index), so the GPU
+samples must equal the oracle's vertex for vertex and parent for parent.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle as O
+from gpu_util import assert_samples_equal, build_pair, random_graphs, scc
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("k", [2, 3, 4, 5, 6, 7, 8])
+@pytest.mark.parametrize("rooting", [O.ROOT_ZERO, O.ROOT_ALL])
+def test_uniform_samples_equal(k, rooting):
+    for name, g in random_graphs(k):
+        colors = gg.colors(g.n, k, seed=5 * k + rooting)
+        gt, ot = build_pair(g, colors, k, rooting=rooting)
+        if ot.totals()[0] == 0:
+            continue
+        assert_samples_equal(gt, ot, 300, seed=1000 + k, stream=rooting, label=name)
+
+
+@pytest.mark.parametrize("k", [4, 5, 6, 7, 8])
+def test_shape_restricted_samples_equal(k):
+    g = gg.chung_lu(600, 2400, 2.2, 60, seed=50 + k)
+    colors = gg.colors(g.n, k, seed=60 + k)
+    gt, ot = build_pair(g, colors, k)
+    t, tj = ot.totals()
+    assert gt.totals() == (t, tj)
+    for j, tot in enumerate(tj):
+        if tot == 0:
+            continue
+        assert_samples_equal(gt, ot, 120, seed=7, stream=j, shape=j, label=f"k{k} shape {j}")
+
+
+def test_sample_index_offsets_and_streams():
+    g = gg.chung_lu(2000, 9000, 2.1, 300, seed=3)
+    k = 6
+    gt, ot = build_pair(g, gg.colors(g.n, k, seed=4), k)
+    assert_samples_equal(gt, ot, 200, seed=99, stream=5, first=12345, label="offset")
+    a, _ = gt.sample(64, seed=99, stream_id=5)
+    b, _ = gt.sample(32, seed=99, stream_id=5, first_index=32)
+    assert np.array_equal(a[32:].cpu().numpy(), b.cpu().numpy())
+
+
+def test_samples_with_wide_counts():
+    leaves = 1 << 16
+    edges = [(0, i) for i in range(1, leaves + 1)] + [(i, i + 1) for i in range(1, 400)]
+    g = gg.csr_from_edges(leaves + 1, np.array(edges, np.int64))
+    colors = np.concatenate([[0], (np.arange(leaves) % 5) + 1]).astype(np.uint8)
+    gt, ot = build_pair(g, colors, 6)
+    assert_samples_equal(gt, ot, 200, seed=3, label="wide star")
+
+
+@pytest.mark.parametrize("k", [3, 4, 5, 6, 7, 8])
+def test_classify_equal(k):
+    g = gg.chung_lu(1500, 7000, 2.2, 120, seed=70 + k)
+    colors = gg.colors(g.n, k, seed=80 + k)
+    gt, ot = build_pair(g, colors, k)
+    if ot.totals()[0] == 0:
+        pytest.skip("no colourful treelet")
+    n = 400 if k < 8 else 60
+    gv = assert_samples_equal(gt, ot, n, seed=5, label=f"classify k{k}")
+    import torch
+    code, cls = gt.classify(torch.as_tensor(gv).cuda())
+    ocode, ocls = O.classify(g, k, gv)
+    assert np.array_equal(code.cpu().numpy().view(np.uint32), ocode)
+    assert np.array_equal(cls.cpu().numpy(), ocls)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6, 7])
+def test_catalog_equal(k):
+    S = scc()
+    cat = S.catalog(k, with_sigma=True, with_sigma_ij=(k <= 6))
+    assert np.array_equal(cat["codes"], O.catalog_codes(k))
+    for i, c in enumerate(cat["codes"][:400]):
+        assert cat["sigma"][i] == O.spanning_trees(int(c), k)
+        if cat["sigma_ij"] is not None:
+            assert np.array_equal(cat["sigma_ij"][i], O.spanning_trees_by_shape(int(c), k))
+
+
+@pytest.mark.timeout(300)
+def test_catalog_k8_matches_paper_and_oracle():
+    # Sec. 5.2: 11117 distinct 8-graphlets; codes equal the oracle's catalog
+    S = scc()
+    cat = S.catalog(8, with_sigma=True)
+    assert len(cat["codes"]) == 11117
+    assert np.array_equal(cat["codes"], O.catalog_codes(8))
+    rng = np.random.default_rng(1)
+    for i in rng.choice(11117, 50, replace=False):
+        assert cat["sigma"][i] == O.spanning_trees(int(cat["codes"][i]), 8)
+
+
+def test_ags_equal_on_star_plus_path():
+    k = 4
+    leaves, plen = 80, 9
+    edges = [(0, i) for i in range(1, leaves + 1)] + [(leaves + 1 + i, leaves + 2 + i) for i in range(plen - 1)]
+    g = gg.csr_from_edges(leaves + 1 + plen, np.array(edges, np.int64))
+    colors = gg.colors(g.n, k, seed=3)
+    gt, ot = build_pair(g, colors, k)
+    r_gpu = gt.ags(cbar=100, round_size=50, budget=6000, seed=11, stream_id=2)
+    r_orc = ot.ags(cbar=100, round_size=50, budget=6000, seed=11, stream=2)
+    for key in ["hits", "w", "n_j", "round_shapes"]:
+        assert np.array_equal(r_gpu[key], r_orc[key]), key
+
+
+def test_ags_equal_on_chung_lu_k5():
+    g = gg.chung_lu(3000, 12000, 2.2, 200, seed=31)
+    k = 5
+    gt, ot = build_pair(g, gg.colors(g.n, k, seed=32), k)
+    r_gpu = gt.ags(cbar=50, round_size=500, budget=20000, seed=8, stream_id=1)
+    r_orc = ot.ags(cbar=50, round_size=500, budget=20000, seed=8, stream=1)
+    for key in ["hits", "w", "n_j", "round_shapes"]:
+        assert np.array_equal(r_gpu[key], r_orc[key]), key
