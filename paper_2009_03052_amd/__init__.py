@@ -144,7 +144,7 @@ class Table:
     """The count table of one graph and colouring (``scc_build_table``)."""
 
     def __init__(self, graph: DeviceGraph, colors, k: int, rooting: int = ROOT_ZERO, max_bits: int = 128,
-                 validate: bool = False, stream=None, use_torch_allocator: bool = True):
+                 validate: bool = False, stream=None, use_torch_allocator: bool = True, hub_degree: int = 0):
         self.graph = graph
         self.colors = torch.as_tensor(np.asarray(colors) if not torch.is_tensor(colors) else colors,
                                       dtype=torch.uint8).to(graph.row_ptr.device).contiguous()
@@ -152,7 +152,8 @@ class Table:
         self._stream = stream
         csr = _Csr(graph.n, graph.nnz, graph.row_ptr.data_ptr(), graph.col_idx.data_ptr())
         opts = _BuildOpts(rooting, max_bits, _stream_ptr(stream),
-                          C.pointer(TORCH_ALLOCATOR) if use_torch_allocator else None, 0, 1 if validate else 0)
+                          C.pointer(TORCH_ALLOCATOR) if use_torch_allocator else None, hub_degree,
+                          1 if validate else 0)
         self._h = _P()
         _check(_lib.scc_build_table(C.byref(csr), _ptr(self.colors), k, C.byref(opts), C.byref(self._h)))
 

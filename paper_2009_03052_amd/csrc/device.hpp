@@ -16,6 +16,8 @@ struct LevelView {
     const uint64_t *off;
     const uint32_t *meta;      // len | wide << 31
     const u128 *N;             // sum of the vertex's counts at this level
+    const uint64_t *bm;        // presence bitmaps, BW words per vertex
+    int BW;
 };
 
 #define META_LEN(m) ((m) & 0x7fffffffu)
@@ -88,6 +90,22 @@ __device__ inline uint64_t wave_sum64(uint64_t x)
 }
 
 __device__ inline uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
+
+// Count of the entry with dense level position li (>= 0) at v, via the presence
+// bitmap: its rank among v's present entries is its position in the record.
+__device__ inline u128 record_at(const LevelView &L, int64_t v, int li)
+{
+    const uint64_t *bw = L.bm + (size_t)v * L.BW;
+    const int w = li >> 6;
+    const uint64_t word = bw[w];
+    if (!((word >> (li & 63)) & 1ull)) return 0;
+    uint32_t pos = (uint32_t)__popcll(word & ((1ull << (li & 63)) - 1ull));
+    for (int q = 0; q < w; q++) pos += (uint32_t)__popcll(bw[q]);
+    const uint32_t m = L.meta[v], len = META_LEN(m);
+    const uint64_t *rec = L.pool + L.off[v];
+    const uint32_t kw = key_words(len);
+    return mk128(rec[kw + pos], META_WIDE(m) ? rec[kw + len + pos] : 0);
+}
 
 // Count of a key in a stored record by binary search (0 if absent).
 __device__ inline u128 record_lookup(const LevelView &L, int64_t v, uint32_t key)

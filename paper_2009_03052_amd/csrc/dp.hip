@@ -78,89 +78,36 @@ __global__ void __launch_bounds__(WAVE) k_gather1(GraphView g, int k, uint64_t *
 }
 
 // ---------------------------------------------------------------------------
-// Bound pass for level h' = hs (>= 2): M_hs(v) = sum_{u~v} N_hs(u) (saturating),
-// whether any M needs 128 bits, whether any vertex of level hs+1 will need
-// 128-bit counts, and the gather's algorithmic byte count.
-// ---------------------------------------------------------------------------
-struct BoundArgs {
-    GraphView g;
-    int hs, k, zero_next;          // zero_next: level hs+1 == k under zero-rooting
-    int rows_zero;                 // gather rows restricted to colour-0 vertices
-    LevelView L;                   // level hs
-    const u128 *Nlev[SCC_KMAX + 1];
-    const u128 *Mlev[SCC_KMAX + 1];
-    u128 *Mout;
-    int WS;                        // entries of S_hs per vertex
-    unsigned long long *flags;     // [0] any M >= 2^64, [1] any U >= 2^64, [2] any U saturated, [3] bytes
-};
-
-__global__ void __launch_bounds__(WAVE) k_bound(BoundArgs A)
-{
-    const int64_t v = blockIdx.x;
-    const int lane = threadIdx.x;
-    const int cv = A.g.colors[v];
-    const int64_t a = A.g.row_ptr[v], b = A.g.row_ptr[v + 1];
-    u128 m = 0;
-    uint64_t bytes = 0;
-    for (int64_t e = a + lane; e < b; e += WAVE) {
-        int32_t u = A.g.col_idx[e];
-        m = sat_add(m, A.L.N[u]);
-        uint32_t mm = A.L.meta[u];
-        bytes += (uint64_t)META_LEN(mm) * (META_WIDE(mm) ? 18u : 10u);
-    }
-    m = wave_satsum128(m);
-    bytes = wave_sum64(bytes);
-    if (lane != 0) return;
-    A.Mout[v] = m;
-    if (hi64(m)) atomicOr(&A.flags[0], 1ull);
-    const bool row = !A.rows_zero || cv == 0;
-    if (row) atomicAdd(&A.flags[3], bytes + 4ull * (uint64_t)(b - a) + (uint64_t)A.WS * (hi64(m) ? 16u : 8u));
-    // bound of level hs + 1 at v
-    if (A.zero_next && cv != 0) return;
-    const int h = A.hs + 1;
-    u128 U = 0;
-    for (int hp = 1; hp < h; hp++) {
-        u128 Nv = hp == 1 ? (u128)1 : A.Nlev[hp][v];
-        u128 Mv = (h - hp == A.hs) ? m : A.Mlev[h - hp][v];
-        U = sat_add(U, sat_mul(Nv, Mv));
-    }
-    if (U == ~(u128)0) atomicOr(&A.flags[2], 1ull);
-    if (hi64(U)) atomicOr(&A.flags[1], 1ull);
-}
-
-// ---------------------------------------------------------------------------
-// Gather (the DP join): S_hs(v) = sum over neighbours of their level-hs records
+// Gather (the DP join): S_hs(v) = sum over neighbours of their level-hs records,
+// plus the bound M_hs(v) = sum_{u~v} N_hs(u) that decides 64- or 128-bit sums.
+// Rows of degree <= HUB_DEGREE: one wave per vertex, accumulating in LDS.
+// Larger rows: their neighbour list is cut into chunks of HUB_CHUNK, each chunk
+// reduced in LDS by one wave and merged into the row with global atomics.
 // ---------------------------------------------------------------------------
 struct GatherArgs {
     GraphView g;
-    int k, nkeys, WS, rows_zero;
+    int k, nkeys, WS, rows_zero, hub_degree;
     LevelView L;
-    const u128 *M;                 // M_hs
+    u128 *M;                       // out: M_hs (regular rows); in: hub rows
     const int16_t *key_sidx;       // [k * nkeys]
     uint64_t *Slo, *Shi;           // [n * WS]
+    const int32_t *chunk_v;        // hub chunks: vertex and first edge
+    const int64_t *chunk_e;
+    int *err;
 };
 
-__global__ void __launch_bounds__(WAVE) k_gather(GatherArgs A)
+// Adds the level-hs entries of neighbours col_idx[a..b) of v into the LDS sums.
+__device__ inline void gather_range(const GatherArgs &A, int cv, int64_t a, int64_t b, bool wideS,
+                                    uint64_t *acc_lo, uint64_t *acc_hi)
 {
-    extern __shared__ uint64_t sm[];
-    const int64_t v = blockIdx.x;
     const int lane = threadIdx.x;
-    const int cv = A.g.colors[v];
-    if (A.rows_zero && cv != 0) return;
-    const int WS = A.WS;
-    uint64_t *acc_lo = sm;
-    uint64_t *acc_hi = sm + WS;
-    const bool wideS = hi64(A.M[v]) != 0;
-    for (int i = lane; i < WS; i += WAVE) { acc_lo[i] = 0; acc_hi[i] = 0; }
-    __syncthreads();
     const int16_t *sidx = A.key_sidx + (size_t)cv * A.nkeys;
-    const int64_t a = A.g.row_ptr[v], b = A.g.row_ptr[v + 1];
     for (int64_t base = a; base < b; base += WAVE) {
         const int64_t e = base + lane;
         uint32_t len = 0, meta = 0;
         uint64_t off = 0;
         if (e < b) {
-            int32_t u = A.g.col_idx[e];
+            const int32_t u = A.g.col_idx[e];
             meta = A.L.meta[u];
             len = META_LEN(meta);
             if (len) off = A.L.off[u];
@@ -175,7 +122,7 @@ __global__ void __launch_bounds__(WAVE) k_gather(GatherArgs A)
             int j = 0;
 #pragma unroll
             for (int step = WAVE / 2; step >= 1; step >>= 1) {
-                uint32_t x = __shfl(incl, j + step - 1, WAVE);
+                const uint32_t x = __shfl(incl, j + step - 1, WAVE);
                 if (x <= p) j += step;
             }
             if (j > WAVE - 1) j = WAVE - 1;
@@ -195,14 +142,36 @@ __global__ void __launch_bounds__(WAVE) k_gather(GatherArgs A)
                         atomicAdd((unsigned long long *)&acc_lo[s], (unsigned long long)cl);
                     } else {
                         const uint64_t ch = META_WIDE(meta_j) ? rec[kw + len_j + ei] : 0;
-                        unsigned long long old = atomicAdd((unsigned long long *)&acc_lo[s], (unsigned long long)cl);
-                        uint64_t carry = (old + cl) < old ? 1u : 0u;
+                        const unsigned long long old = atomicAdd((unsigned long long *)&acc_lo[s], (unsigned long long)cl);
+                        const uint64_t carry = (old + cl) < old ? 1u : 0u;
                         if (ch + carry) atomicAdd((unsigned long long *)&acc_hi[s], (unsigned long long)(ch + carry));
                     }
                 }
             }
         }
     }
+}
+
+__global__ void __launch_bounds__(WAVE) k_gather(GatherArgs A)
+{
+    extern __shared__ uint64_t sm[];
+    const int64_t v = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int cv = A.g.colors[v];
+    if (A.rows_zero && cv != 0) return;
+    const int64_t a = A.g.row_ptr[v], b = A.g.row_ptr[v + 1];
+    if (b - a > A.hub_degree) return;      // hub rows have their own kernels
+    // bound: every entry of S_hs(v) is at most M_hs(v)
+    u128 m = 0;
+    for (int64_t e = a + lane; e < b; e += WAVE) m = sat_add(m, A.L.N[A.g.col_idx[e]]);
+    m = wave_satsum128(m);
+    const bool wideS = hi64(m) != 0;
+    const int WS = A.WS;
+    uint64_t *acc_lo = sm;
+    uint64_t *acc_hi = sm + WS;
+    for (int i = lane; i < WS; i += WAVE) { acc_lo[i] = 0; acc_hi[i] = 0; }
+    __syncthreads();
+    gather_range(A, cv, a, b, wideS, acc_lo, acc_hi);
     __syncthreads();
     uint64_t *Slo = A.Slo + (size_t)v * WS;
     for (int i = lane; i < WS; i += WAVE) Slo[i] = acc_lo[i];
@@ -210,6 +179,95 @@ __global__ void __launch_bounds__(WAVE) k_gather(GatherArgs A)
         uint64_t *Shi = A.Shi + (size_t)v * WS;
         for (int i = lane; i < WS; i += WAVE) Shi[i] = acc_hi[i];
     }
+    if (lane == 0) A.M[v] = m;
+}
+
+// hub rows, step 1: the bound M_hs(v) and cleared sums
+__global__ void __launch_bounds__(256) k_hub_prepare(GatherArgs A, const int32_t *hubs)
+{
+    __shared__ u128 part[256 / WAVE];
+    const int64_t v = hubs[blockIdx.x];
+    const int64_t a = A.g.row_ptr[v], b = A.g.row_ptr[v + 1];
+    u128 m = 0;
+    for (int64_t e = a + threadIdx.x; e < b; e += blockDim.x) m = sat_add(m, A.L.N[A.g.col_idx[e]]);
+    m = wave_satsum128(m);
+    if (lane_id() == 0) part[threadIdx.x / WAVE] = m;
+    for (int i = threadIdx.x; i < A.WS; i += blockDim.x) {
+        A.Slo[(size_t)v * A.WS + i] = 0;
+        A.Shi[(size_t)v * A.WS + i] = 0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        u128 t = 0;
+        for (int w = 0; w < (int)(blockDim.x / WAVE); w++) t = sat_add(t, part[w]);
+        A.M[v] = t;
+    }
+}
+
+// hub rows, step 2: one wave per chunk of HUB_CHUNK neighbours, merged with atomics
+__global__ void __launch_bounds__(WAVE) k_gather_hub(GatherArgs A, int chunk)
+{
+    extern __shared__ uint64_t sm[];
+    const int64_t v = A.chunk_v[blockIdx.x];
+    const int64_t a = A.chunk_e[blockIdx.x];
+    const int64_t b = min(A.g.row_ptr[v + 1], a + (int64_t)chunk);
+    const int lane = threadIdx.x;
+    const int cv = A.g.colors[v];
+    const bool wideS = hi64(A.M[v]) != 0;
+    const int WS = A.WS;
+    uint64_t *acc_lo = sm;
+    uint64_t *acc_hi = sm + WS;
+    for (int i = lane; i < WS; i += WAVE) { acc_lo[i] = 0; acc_hi[i] = 0; }
+    __syncthreads();
+    gather_range(A, cv, a, b, wideS, acc_lo, acc_hi);
+    __syncthreads();
+    unsigned long long *Slo = (unsigned long long *)(A.Slo + (size_t)v * WS);
+    unsigned long long *Shi = (unsigned long long *)(A.Shi + (size_t)v * WS);
+    for (int i = lane; i < WS; i += WAVE) {
+        const uint64_t lo = acc_lo[i], hi = acc_hi[i];
+        if (!lo && !hi) continue;
+        if (!wideS) {
+            atomicAdd(&Slo[i], (unsigned long long)lo);
+        } else {
+            const unsigned long long old = atomicAdd(&Slo[i], (unsigned long long)lo);
+            const uint64_t carry = (old + lo) < old ? 1u : 0u;
+            if (hi + carry) atomicAdd(&Shi[i], (unsigned long long)(hi + carry));
+        }
+    }
+}
+
+// algorithmic bytes of one gather launch (for reports): 4 d_v + neighbours'
+// records (10 B per 64-bit entry, 18 B per 128-bit entry) + the sums written
+__global__ void __launch_bounds__(256) k_gather_bytes(GraphView g, LevelView L, const u128 *M, int WS, int rows_zero,
+                                                      unsigned long long *out)
+{
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint64_t bytes = 0;
+    if (v < g.n && (!rows_zero || g.colors[v] == 0)) {
+        const int64_t a = g.row_ptr[v], b = g.row_ptr[v + 1];
+        bytes = 4ull * (uint64_t)(b - a) + (uint64_t)WS * (hi64(M[v]) ? 16u : 8u);
+        for (int64_t e = a; e < b; e++) {
+            const uint32_t m = L.meta[g.col_idx[e]];
+            bytes += (uint64_t)META_LEN(m) * (META_WIDE(m) ? 18u : 10u);
+        }
+    }
+    bytes = wave_sum64(bytes);
+    if (lane_id() == 0 && bytes) atomicAdd(out, (unsigned long long)bytes);
+}
+
+__global__ void k_hub_rows(GraphView g, const int32_t *hubs, int nhub, int64_t *rows)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nhub) return;
+    rows[2 * i] = g.row_ptr[hubs[i]];
+    rows[2 * i + 1] = g.row_ptr[hubs[i] + 1];
+}
+
+__global__ void k_hub_list(GraphView g, int hub_degree, int32_t *hubs, int *count)
+{
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= g.n) return;
+    if (g.row_ptr[v + 1] - g.row_ptr[v] > hub_degree) hubs[atomicAdd(count, 1)] = (int32_t)v;
 }
 
 // ---------------------------------------------------------------------------
@@ -379,11 +437,32 @@ __global__ void k_words(int64_t n, const uint32_t *meta, uint64_t *words)
 // copy each vertex's slot into the packed pool at its offset
 __global__ void __launch_bounds__(WAVE) k_pack(int64_t n, int W, const uint32_t *meta, const uint64_t *off_incl,
                                                const uint16_t *slot_key, const uint64_t *slot_lo,
-                                               const uint64_t *slot_hi, uint64_t *pool, uint64_t *off)
+                                               const uint64_t *slot_hi, uint64_t *pool, uint64_t *off,
+                                               const int16_t *key_xidx, int nkeys, const uint8_t *colors,
+                                               uint64_t *bm, int BW)
 {
     const int64_t v = blockIdx.x;
     const int lane = threadIdx.x;
     const uint32_t m = meta[v], len = META_LEN(m);
+    // presence bitmap over v's own entries (bit = position in the dense level-h layout)
+    {
+        const int16_t *xi = key_xidx + (size_t)colors[v] * nkeys;
+        for (int w = 0; w < BW; w++) {
+            uint64_t word = 0;
+            for (uint32_t e0 = 0; e0 < len; e0 += WAVE) {
+                const uint32_t e = e0 + lane;
+                int li = -1;
+                if (e < len) li = xi[slot_key[(size_t)v * W + e]];
+                const bool in = li >= 0 && (li >> 6) == w;
+                // lanes OR their bits into one word
+                uint64_t mine = in ? (1ull << (li & 63)) : 0ull;
+#pragma unroll
+                for (int d = WAVE / 2; d >= 1; d >>= 1) mine |= shfl64(mine, lane ^ d);
+                word |= mine;
+            }
+            if (lane == 0) bm[(size_t)v * BW + w] = word;
+        }
+    }
     const uint32_t words = len ? key_words(len) + len * (META_WIDE(m) ? 2u : 1u) : 0;
     const uint64_t start = off_incl[v] - words;
     if (lane == 0) off[v] = start;
@@ -568,7 +647,7 @@ scc_status scan_incl(scc_table *T_, const T *in, T *out, int64_t n)
 
 LevelView view(const TableLevel &l)
 {
-    return LevelView{l.pool, l.off, l.meta, l.N};
+    return LevelView{l.pool, l.off, l.meta, l.N, l.bm, l.BW};
 }
 
 }  // namespace
@@ -596,24 +675,69 @@ static scc_status build_levels(scc_table *T)
     hipStream_t st = T->stream;
     GraphView g{n, T->row_ptr, T->col_idx, T->colors};
     const bool zero = T->rooting == SCC_ROOT_ZERO;
+    const int hub_degree = T->hub_degree;
 
     unsigned long long *flags = (unsigned long long *)T->mem.get(8 * sizeof(unsigned long long));
     int *err = (int *)T->mem.get(16);
-    if (!flags || !err) return set_error(SCC_ENOMEM, "flags");
+    std::vector<void *> scratch{flags, err};
     struct Guard {
-        scc_table *T; void *a, *b;
-        ~Guard() { T->mem.put(a); T->mem.put(b); }
-    } guard{T, flags, err};
+        scc_table *T; std::vector<void *> *s;
+        ~Guard() { for (void *p : *s) T->mem.put(p); }
+    } guard{T, &scratch};
+    auto get = [&](size_t bytes) { void *p = T->mem.get(bytes); if (p) scratch.push_back(p); return p; };
+    if (!flags || !err) return set_error(SCC_ENOMEM, "flags");
 
     hipEvent_t e0, e1, g0, g1;
     HIP_TRY(hipEventCreate(&e0)); HIP_TRY(hipEventCreate(&e1));
     HIP_TRY(hipEventCreate(&g0)); HIP_TRY(hipEventCreate(&g1));
     struct EvGuard { hipEvent_t a, b, c, d; ~EvGuard() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); (void)hipEventDestroy(c); (void)hipEventDestroy(d); } } evg{e0, e1, g0, g1};
 
+    // hub rows and their neighbour chunks (the same for every level)
+    int nhub = 0;
+    int32_t *hubs = nullptr;
+    int32_t *chunk_v = nullptr;
+    int64_t *chunk_e = nullptr;
+    int64_t nchunk = 0;
+    if (n) {
+        hubs = (int32_t *)get((size_t)n * 4 + 8);
+        if (!hubs) return set_error(SCC_ENOMEM, "hub list");
+        HIP_TRY(hipMemsetAsync(err, 0, 16, st));
+        hipLaunchKernelGGL(k_hub_list, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g, hub_degree, hubs, err);
+        HIP_TRY(hipMemcpyAsync(&nhub, err, 4, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+    }
+    if (nhub) {
+        std::vector<int32_t> hh(nhub);
+        std::vector<int64_t> rp(2 * (size_t)nhub);
+        HIP_TRY(hipMemcpyAsync(hh.data(), hubs, (size_t)nhub * 4, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        std::sort(hh.begin(), hh.end());
+        int64_t *rows = (int64_t *)get((size_t)nhub * 16 + 16);
+        if (!rows) return set_error(SCC_ENOMEM, "hub rows");
+        HIP_TRY(hipMemcpyAsync(hubs, hh.data(), (size_t)nhub * 4, hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(k_hub_rows, dim3((unsigned)((nhub + 255) / 256)), dim3(256), 0, st, g, hubs, nhub, rows);
+        HIP_TRY(hipMemcpyAsync(rp.data(), rows, (size_t)nhub * 16, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        std::vector<int32_t> cv;
+        std::vector<int64_t> ce;
+        for (int i = 0; i < nhub; i++)
+            for (int64_t e = rp[2 * i]; e < rp[2 * i + 1]; e += T->hub_chunk) { cv.push_back(hh[i]); ce.push_back(e); }
+        nchunk = (int64_t)cv.size();
+        chunk_v = (int32_t *)get(cv.size() * 4 + 8);
+        chunk_e = (int64_t *)get(ce.size() * 8 + 8);
+        if (!chunk_v || !chunk_e) return set_error(SCC_ENOMEM, "hub chunks");
+        HIP_TRY(hipMemcpyAsync(chunk_v, cv.data(), cv.size() * 4, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(chunk_e, ce.data(), ce.size() * 8, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        T->hub_host.assign(hh.begin(), hh.end());
+        T->hub_rows_host = rp;
+    }
+    T->nhub = nhub;
+
     // level 1 neighbour sums
     TableSums &S1 = T->S[1];
-    S1.lo = (uint64_t *)T->alloc((size_t)n * (k - 1) * 8);
-    S1.M = (u128 *)T->alloc((size_t)n * 16);
+    S1.lo = (uint64_t *)T->alloc((size_t)n * (k - 1) * 8 + 8);
+    S1.M = (u128 *)T->alloc((size_t)n * 16 + 16);
     if (!S1.lo || !S1.M) return set_error(SCC_ENOMEM, "level-1 sums");
     HIP_TRY(hipEventRecord(g0, st));
     if (n) hipLaunchKernelGGL(k_gather1, dim3((unsigned)n), dim3(WAVE), 0, st, g, k, S1.lo, S1.M);
@@ -630,61 +754,38 @@ static scc_status build_levels(scc_table *T)
     // scratch slots for the combine, sized for the widest level
     int maxW = 0;
     for (int h = 2; h <= k; h++) maxW = std::max(maxW, HL.W[h]);
-    uint16_t *slot_key = (uint16_t *)T->mem.get((size_t)n * maxW * 2 + 256);
-    uint64_t *slot_lo = (uint64_t *)T->mem.get((size_t)n * maxW * 8 + 256);
-    uint64_t *slot_hi = nullptr;
-    uint64_t *words = (uint64_t *)T->mem.get((size_t)n * 8 + 256);
-    if (!slot_key || !slot_lo || !words) {
-        T->mem.put(slot_key); T->mem.put(slot_lo); T->mem.put(words);
-        return set_error(SCC_ENOMEM, "combine scratch (%lld bytes)", (long long)n * maxW * 10);
-    }
-    struct SlotGuard { scc_table *T; void **a, **b, **c, **d; ~SlotGuard() { T->mem.put(*a); T->mem.put(*b); T->mem.put(*c); T->mem.put(*d); } }
-        sg{T, (void **)&slot_key, (void **)&slot_lo, (void **)&slot_hi, (void **)&words};
+    uint16_t *slot_key = (uint16_t *)get((size_t)n * maxW * 2 + 256);
+    uint64_t *slot_lo = (uint64_t *)get((size_t)n * maxW * 8 + 256);
+    uint64_t *slot_hi = (uint64_t *)get((size_t)n * maxW * 8 + 256);
+    uint64_t *words = (uint64_t *)get((size_t)n * 8 + 256);
+    if (!slot_key || !slot_lo || !slot_hi || !words)
+        return set_error(SCC_ENOMEM, "combine scratch (%lld bytes)", (long long)n * maxW * 18);
 
     for (int h = 2; h <= k; h++) {
         const bool last = h == k;
         HIP_TRY(hipEventRecord(e0, st));
-        HIP_TRY(hipMemsetAsync(flags, 0, 8 * sizeof(unsigned long long), st));
         HIP_TRY(hipMemsetAsync(err, 0, 16, st));
         const int hs = h - 1;   // neighbour sums needed now
-        bool any_wide = false;
         if (hs >= 2) {
-            // bound and gather of level hs
             TableSums &Sx = T->S[hs];
-            Sx.M = (u128 *)T->alloc((size_t)n * 16);
-            if (!Sx.M) return set_error(SCC_ENOMEM, "bounds");
-            BoundArgs B{};
-            B.g = g; B.hs = hs; B.k = k; B.zero_next = zero && h == k; B.rows_zero = zero && h == k;
-            B.L = view(T->lev[hs]);
-            for (int q = 2; q < h; q++) B.Nlev[q] = T->lev[q].N;
-            for (int q = 1; q < hs; q++) B.Mlev[q] = T->S[q].M;
-            B.Mout = Sx.M; B.WS = HL.WS[hs]; B.flags = flags;
-            if (n) hipLaunchKernelGGL(k_bound, dim3((unsigned)n), dim3(WAVE), 0, st, B);
-            unsigned long long hf[4];
-            HIP_TRY(hipMemcpyAsync(hf, flags, sizeof hf, hipMemcpyDeviceToHost, st));
-            HIP_TRY(hipStreamSynchronize(st));
-            if (hf[2]) return set_error(SCC_EOVERFLOW, "a level-%d count may exceed 128 bits", h);
-            any_wide = hf[1] != 0;
-            T->gather_bytes[hs] = (double)hf[3];
             const size_t sz = (size_t)n * HL.WS[hs] * 8;
+            Sx.M = (u128 *)T->alloc((size_t)n * 16 + 16);
             Sx.lo = (uint64_t *)T->alloc(sz + 8);
-            if (!Sx.lo) return set_error(SCC_ENOMEM, "neighbour sums level %d (%zu bytes)", hs, sz);
-            if (hf[0]) {
-                Sx.hi = (uint64_t *)T->alloc(sz + 8);
-                if (!Sx.hi) return set_error(SCC_ENOMEM, "neighbour sums level %d (high words)", hs);
-            }
+            Sx.hi = (uint64_t *)T->alloc(sz + 8);
+            if (!Sx.M || !Sx.lo || !Sx.hi) return set_error(SCC_ENOMEM, "neighbour sums level %d (%zu bytes)", hs, 2 * sz);
             GatherArgs G{};
             G.g = g; G.k = k; G.nkeys = HL.nkeys; G.WS = HL.WS[hs]; G.rows_zero = zero && h == k;
+            G.hub_degree = hub_degree;
             G.L = view(T->lev[hs]); G.M = Sx.M; G.key_sidx = T->key_sidx; G.Slo = Sx.lo; G.Shi = Sx.hi;
+            G.chunk_v = chunk_v; G.chunk_e = chunk_e; G.err = err;
+            const size_t lds = (size_t)2 * HL.WS[hs] * 8;
             HIP_TRY(hipEventRecord(g0, st));
-            if (n) hipLaunchKernelGGL(k_gather, dim3((unsigned)n), dim3(WAVE), (size_t)2 * HL.WS[hs] * 8, st, G);
+            if (nhub) {
+                hipLaunchKernelGGL(k_hub_prepare, dim3((unsigned)nhub), dim3(256), 0, st, G, hubs);
+                hipLaunchKernelGGL(k_gather_hub, dim3((unsigned)nchunk), dim3(WAVE), lds, st, G, T->hub_chunk);
+            }
+            if (n) hipLaunchKernelGGL(k_gather, dim3((unsigned)n), dim3(WAVE), lds, st, G);
             HIP_TRY(hipEventRecord(g1, st));
-        } else {
-            // level 2 needs only level-1 sums; its bound is c <= d_v
-            any_wide = false;
-        }
-        if (T->max_bits < 128 && any_wide) {
-            // checked per vertex below; a 64-bit table rejects the level
         }
         // combine into slots
         TableLevel &Lv = T->lev[h];
@@ -692,10 +793,6 @@ static scc_status build_levels(scc_table *T)
         Lv.N = (u128 *)T->alloc((size_t)n * 16 + 16);
         Lv.off = (uint64_t *)T->alloc((size_t)n * 8 + 8);
         if (!Lv.meta || !Lv.N || !Lv.off) return set_error(SCC_ENOMEM, "level %d metadata", h);
-        if (any_wide && !slot_hi) {
-            slot_hi = (uint64_t *)T->mem.get((size_t)n * maxW * 8 + 256);
-            if (!slot_hi) return set_error(SCC_ENOMEM, "wide combine scratch");
-        }
         CombineArgs C{};
         C.g = g; C.L = T->dlut; C.h = h; C.zero_only = zero && last; C.max_bits = T->max_bits;
         for (int q = 2; q < h; q++) C.lev[q] = view(T->lev[q]);
@@ -726,8 +823,12 @@ static scc_status build_levels(scc_table *T)
         Lv.pool_words = total;
         Lv.pool = (uint64_t *)T->alloc((size_t)total * 8 + 64);
         if (!Lv.pool) return set_error(SCC_ENOMEM, "level %d pool (%llu words)", h, (unsigned long long)total);
+        Lv.BW = (HL.W[h] + 63) / 64;
+        Lv.bm = (uint64_t *)T->alloc((size_t)n * Lv.BW * 8 + 8);
+        if (!Lv.bm) return set_error(SCC_ENOMEM, "level %d bitmaps", h);
         if (n) hipLaunchKernelGGL(k_pack, dim3((unsigned)n), dim3(WAVE), 0, st, n, HL.W[h], Lv.meta, words,
-                                  slot_key, slot_lo, slot_hi, Lv.pool, Lv.off);
+                                  slot_key, slot_lo, slot_hi, Lv.pool, Lv.off, T->key_xidx, HL.nkeys, T->colors,
+                                  Lv.bm, Lv.BW);
         HIP_TRY(hipEventRecord(e1, st));
         HIP_TRY(hipMemsetAsync(flags, 0, 2 * sizeof(unsigned long long), st));
         if (n) hipLaunchKernelGGL(k_meta_sum, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, Lv.meta, flags);
@@ -741,6 +842,30 @@ static scc_status build_levels(scc_table *T)
         T->level_ms[h] = ms;
         HIP_TRY(hipGetLastError());
     }
+    return SCC_OK;
+}
+
+// algorithmic bytes of each gather launch, computed after the build on request
+static scc_status gather_stats(scc_table *T)
+{
+    if (T->stats_done) return SCC_OK;
+    const int64_t n = T->n;
+    hipStream_t st = T->stream;
+    GraphView g{n, T->row_ptr, T->col_idx, T->colors};
+    unsigned long long *acc = (unsigned long long *)T->mem.get(64);
+    if (!acc) return set_error(SCC_ENOMEM, "stats");
+    for (int hs = 2; hs < T->k; hs++) {
+        HIP_TRY(hipMemsetAsync(acc, 0, 8, st));
+        const bool rz = T->rooting == SCC_ROOT_ZERO && hs == T->k - 1;
+        if (n) hipLaunchKernelGGL(k_gather_bytes, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g,
+                                  view(T->lev[hs]), T->S[hs].M, T->hlut.WS[hs], rz ? 1 : 0, acc);
+        unsigned long long b = 0;
+        HIP_TRY(hipMemcpyAsync(&b, acc, 8, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        T->gather_bytes[hs] = (double)b;
+    }
+    T->mem.put(acc);
+    T->stats_done = true;
     return SCC_OK;
 }
 
@@ -831,6 +956,8 @@ extern "C" scc_status scc_build_table(const scc_csr *g, const uint8_t *colors, i
     T->row_ptr = g->row_ptr; T->col_idx = g->col_idx; T->colors = colors;
     T->stream = (hipStream_t)o.stream;
     T->mem.alloc = o.alloc; T->mem.stream = T->stream;
+    T->hub_degree = o.hub_degree > 0 ? o.hub_degree : 1024;
+    T->hub_chunk = 256;
     build_lut(k, &T->hlut);
 
     scc_status s = SCC_OK;
@@ -877,6 +1004,8 @@ extern "C" void scc_table_destroy(scc_table *t)
 extern "C" scc_status scc_table_info_get(const scc_table *t, scc_table_info *out)
 {
     if (!t || !out) return set_error(SCC_EINVAL, "NULL argument");
+    scc_status s = gather_stats(const_cast<scc_table *>(t));
+    if (s) return s;
     memset(out, 0, sizeof *out);
     out->n = t->n; out->k = t->k; out->rooting = t->rooting; out->num_unrooted = t->hlut.num_unr;
     for (int h = 1; h <= t->k; h++) {

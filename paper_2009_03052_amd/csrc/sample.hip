@@ -19,6 +19,11 @@ struct SampleArgs {
     const uint64_t *Slo[SCC_KMAX + 1];    // neighbour sums 1..k-1
     const uint64_t *Shi[SCC_KMAX + 1];
     const u128 *M[SCC_KMAX + 1];
+    const int16_t *key_xidx;              // [k * nkeys] dense own position of a key, or -1
+    int nkeys;
+    const int32_t *hub_index;             // [n] hub number or -1
+    const int64_t *hub_poff;              // [nhub * (k+1)]
+    const uint64_t *hub_pre;
     const u128 *pre;                      // running sums of admissible level-k totals
     u128 total;
     uint64_t seed, stream, first;
@@ -42,11 +47,41 @@ __device__ inline int first_exceeding(u128 incl, u128 target)
     return bal ? __ffsll((long long)bal) - 1 : -1;
 }
 
-// count of (T, C) with the given key at x (level h), level 1 handled implicitly
+// First index j in [0, len) with val(j) > target, for a non-decreasing val whose
+// last element exceeds target. 64-ary search: every round each lane probes one
+// point, so a range of len entries takes ceil(log64 len) dependent loads.
+template <typename F>
+__device__ inline int64_t wave_search(int64_t len, u128 target, F val)
+{
+    const int lane = lane_id();
+    int64_t lo = 0;
+    while (len > WAVE) {
+        const int64_t step = (len + WAVE - 1) / WAVE;
+        int64_t idx = lo + (int64_t)(lane + 1) * step - 1;
+        const int64_t last = lo + len - 1;
+        if (idx > last) idx = last;
+        const uint64_t bal = __ballot(val(idx) > target);
+        if (!bal) return -1;                                 // target not below the last value
+        const int f = __ffsll((long long)bal) - 1;
+        const int64_t nlo = lo + (int64_t)f * step;
+        const int64_t nhi = min(last, lo + (int64_t)(f + 1) * step - 1);
+        lo = nlo;
+        len = nhi - nlo + 1;
+    }
+    const bool p = lane < len && val(lo + lane) > target;
+    const uint64_t bal = __ballot(p);
+    if (!bal) return -1;
+    return lo + (__ffsll((long long)bal) - 1);
+}
+
+// count of (T, C) with the given key at x (level h >= 1)
 __device__ inline u128 own_count(const SampleArgs &A, int h, int64_t x, uint32_t key)
 {
-    if (h == 1) return (key == (uint32_t)A.g.colors[x]) ? 1 : 0;   // key of ({.}, {c}) is c
-    return record_lookup(A.lev[h], x, key);
+    const int cx = A.g.colors[x];
+    if (h == 1) return (key == (uint32_t)cx) ? 1 : 0;   // key of ({.}, {c}) is c
+    const int li = A.key_xidx[(size_t)cx * A.nkeys + key];
+    if (li < 0) return 0;
+    return record_at(A.lev[h], x, li);
 }
 
 __global__ void __launch_bounds__(WAVE) k_sample(SampleArgs A)
@@ -63,12 +98,11 @@ __global__ void __launch_bounds__(WAVE) k_sample(SampleArgs A)
         const uint64_t idx = A.first + (uint64_t)s;
         // (1) root: first vertex whose running sum exceeds X, then the entry of its record
         const u128 X = draw_below(A.total, A.seed, A.stream, idx, 0);
-        int64_t lo = 0, hi = A.g.n - 1;
-        while (lo < hi) {
-            int64_t mid = (lo + hi) >> 1;
-            if (A.pre[mid] > X) hi = mid; else lo = mid + 1;
+        const int64_t v = wave_search(A.g.n, X, [&](int64_t i) { return A.pre[i]; });
+        if (v < 0) {
+            if (lane == 0) atomicOr(A.err, 4);
+            continue;
         }
-        const int64_t v = lo;
         const u128 res = X - (v > 0 ? A.pre[v - 1] : (u128)0);
         const LevelView &Lk = A.lev[k];
         const uint32_t mk = Lk.meta[v], lenk = META_LEN(mk), kwk = key_words(lenk);
@@ -129,6 +163,7 @@ __global__ void __launch_bounds__(WAVE) k_sample(SampleArgs A)
             for (int i = 1; i <= hpp; i++) ncand = ncand * (h - 1 - hpp + i) / i;
             u128 w = 0, xprime = 0, sval = 0;
             uint32_t cpp = 0;
+            int sidx = 0;
             if (lane < ncand) {
                 // deposit the lane-th hpp-subset of the low h-1 positions onto R's bits
                 uint32_t pm = L.mask_s[hpp][lane], dep = 0, rr = R;
@@ -141,9 +176,9 @@ __global__ void __launch_bounds__(WAVE) k_sample(SampleArgs A)
                 const uint32_t kprime = L.off[hp] + a * L.bk[hp] + L.colex_k[C ^ cpp];
                 xprime = own_count(A, hp, x, kprime);
                 const int ws = L.WS[hpp];
-                const int si = b * L.bk1[hpp] + L.colex_s[compress_out(cpp, cx)];
-                const uint64_t slo = A.Slo[hpp][(size_t)x * ws + si];
-                const uint64_t shi = hi64(A.M[hpp][x]) ? A.Shi[hpp][(size_t)x * ws + si] : 0;
+                sidx = b * L.bk1[hpp] + L.colex_s[compress_out(cpp, cx)];
+                const uint64_t slo = A.Slo[hpp][(size_t)x * ws + sidx];
+                const uint64_t shi = hi64(A.M[hpp][x]) ? A.Shi[hpp][(size_t)x * ws + sidx] : 0;
                 sval = mk128(slo, shi);
                 w = xprime * sval;
             }
@@ -151,31 +186,48 @@ __global__ void __launch_bounds__(WAVE) k_sample(SampleArgs A)
             const int w1 = first_exceeding(incl1, Y);
             if (w1 < 0) { fail = true; break; }
             const uint32_t Cpp = __shfl(cpp, w1, WAVE);
+            const int Sidx = __shfl(sidx, w1, WAVE);
             const u128 Xp = shfl128(xprime, w1);
             const u128 Sv = shfl128(sval, w1);
             // stage 2: neighbour u of x with weight c(T''_{C''}, u), CSR order
             const u128 Z = draw_below(Sv, A.seed, A.stream, idx, 2 + 2 * dec);
             const uint32_t kpp = L.off[hpp] + b * L.bk[hpp] + L.colex_k[Cpp];
             const int64_t ra = A.g.row_ptr[x], rb = A.g.row_ptr[x + 1];
-            u128 run2 = 0;
             int64_t u = -1;
             u128 wu = 0;
-            for (int64_t base = ra; base < rb; base += WAVE) {
-                const int64_t e = base + lane;
-                u128 c = 0;
-                int32_t uu = -1;
-                if (e < rb) {
-                    uu = A.g.col_idx[e];
-                    c = own_count(A, hpp, uu, kpp);
+            const int hub = A.hub_index ? A.hub_index[x] : -1;
+            if (hub >= 0) {
+                // running sums over x's neighbours, precomputed per (hub, level, entry)
+                const int64_t d = rb - ra;
+                const int64_t base = A.hub_poff[(size_t)hub * (SCC_KMAX + 1) + hpp];
+                const uint64_t *plo = A.hub_pre + base + (size_t)Sidx * d;
+                const bool pw = hi64(A.M[hpp][x]) != 0;
+                const uint64_t *phi = A.hub_pre + base + (size_t)L.WS[hpp] * d + (size_t)Sidx * d;
+                auto P = [&](int64_t j) { return mk128(plo[j], pw ? phi[j] : 0); };
+                const int64_t j = wave_search(d, Z, P);
+                if (j >= 0) {
+                    u = A.g.col_idx[ra + j];
+                    wu = P(j) - (j > 0 ? P(j - 1) : (u128)0);
                 }
-                const u128 incl = run2 + wave_incl_scan128(c);
-                const int w2 = first_exceeding(incl, Z);
-                if (w2 >= 0) {
-                    u = __shfl(uu, w2, WAVE);
-                    wu = shfl128(c, w2);
-                    break;
+            } else {
+                u128 run2 = 0;
+                for (int64_t base = ra; base < rb; base += WAVE) {
+                    const int64_t e = base + lane;
+                    u128 c = 0;
+                    int32_t uu = -1;
+                    if (e < rb) {
+                        uu = A.g.col_idx[e];
+                        c = own_count(A, hpp, uu, kpp);
+                    }
+                    const u128 incl = run2 + wave_incl_scan128(c);
+                    const int w2 = first_exceeding(incl, Z);
+                    if (w2 >= 0) {
+                        u = __shfl(uu, w2, WAVE);
+                        wu = shfl128(c, w2);
+                        break;
+                    }
+                    run2 = shfl128(incl, WAVE - 1);
                 }
-                run2 = shfl128(incl, WAVE - 1);
             }
             if (u < 0) { fail = true; break; }
             if (lane == 0) {
@@ -200,6 +252,106 @@ __global__ void __launch_bounds__(WAVE) k_sample(SampleArgs A)
         }
         __syncthreads();
     }
+}
+
+// ---------------------------------------------------------------------------
+// Per-hub running sums for the neighbour draw. For hub x, level h'' and
+// neighbour-sum entry s (the (T'', C'') seen from x), row s of the (x, h'')
+// block holds sum_{i <= j} c(T''_{C''}, u_i) over x's neighbours u_0, u_1, ...
+// ---------------------------------------------------------------------------
+struct HubPreArgs {
+    GraphView g;
+    const DevLut *L;
+    int k, nkeys, zero;
+    LevelView lev[SCC_KMAX + 1];
+    const u128 *M[SCC_KMAX + 1];
+    const int16_t *key_sidx;
+    const int32_t *hubs;
+    const int64_t *hub_rows;     // [2 * nhub]
+    const int64_t *poff;         // [nhub * (k+1)]
+    uint64_t *pre;
+    const int32_t *chunk_hub;    // hub number of each chunk
+    const int64_t *chunk_e;      // first edge of each chunk
+    int chunk;
+};
+
+__global__ void __launch_bounds__(WAVE) k_hubpre_fill(HubPreArgs A)
+{
+    const int hi_ = A.chunk_hub[blockIdx.x];
+    const int hpp = blockIdx.y + 1;
+    const int64_t x = A.hubs[hi_];
+    const int64_t ra = A.hub_rows[2 * hi_], rb = A.hub_rows[2 * hi_ + 1], d = rb - ra;
+    const int64_t a = A.chunk_e[blockIdx.x], b = min(rb, a + (int64_t)A.chunk);
+    const int cx = A.g.colors[x];
+    if (A.zero && hpp == A.k - 1 && cx != 0) return;   // no block: x is never a root
+    const int WS = A.L->WS[hpp];
+    const bool pw = hi64(A.M[hpp][x]) != 0;
+    uint64_t *plo = A.pre + A.poff[(size_t)hi_ * (SCC_KMAX + 1) + hpp];
+    uint64_t *phi = plo + (size_t)WS * d;
+    const int16_t *sidx = A.key_sidx + (size_t)cx * A.nkeys;
+    for (int64_t e = a + threadIdx.x; e < b; e += WAVE) {
+        const int32_t u = A.g.col_idx[e];
+        const int64_t j = e - ra;
+        if (hpp == 1) {
+            const int cu = A.g.colors[u];
+            if (cu != cx) plo[(size_t)(cu < cx ? cu : cu - 1) * d + j] = 1;
+            continue;
+        }
+        const LevelView &Lv = A.lev[hpp];
+        const uint32_t m = Lv.meta[u], len = META_LEN(m);
+        if (!len) continue;
+        const uint64_t *rec = Lv.pool + Lv.off[u];
+        const uint32_t kw = key_words(len);
+        for (uint32_t q = 0; q < len; q++) {
+            const int s = sidx[((const uint16_t *)rec)[q]];
+            if (s < 0) continue;
+            plo[(size_t)s * d + j] = rec[kw + q];
+            if (pw) phi[(size_t)s * d + j] = META_WIDE(m) ? rec[kw + len + q] : 0;
+        }
+    }
+}
+
+// in-place inclusive scan of one row (hub, level, entry) per workgroup
+__global__ void __launch_bounds__(256) k_hubpre_scan(HubPreArgs A)
+{
+    __shared__ u128 wsum[256 / WAVE];
+    __shared__ u128 carry;
+    const int hi_ = blockIdx.x;
+    int y = blockIdx.y, hpp = 1;
+    while (hpp < A.k - 1 && y >= A.L->WS[hpp]) { y -= A.L->WS[hpp]; hpp++; }
+    if (y >= A.L->WS[hpp]) return;
+    const int64_t x = A.hubs[hi_];
+    if (A.zero && hpp == A.k - 1 && A.g.colors[x] != 0) return;   // no block: x is never a root
+    const int64_t d = A.hub_rows[2 * hi_ + 1] - A.hub_rows[2 * hi_];
+    const bool pw = hi64(A.M[hpp][x]) != 0;
+    uint64_t *plo = A.pre + A.poff[(size_t)hi_ * (SCC_KMAX + 1) + hpp] + (size_t)y * d;
+    uint64_t *phi = plo + (size_t)A.L->WS[hpp] * d;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int64_t b0 = 0; b0 < d; b0 += blockDim.x) {
+        const int64_t j = b0 + threadIdx.x;
+        u128 xv = 0;
+        if (j < d) xv = mk128(plo[j], pw ? phi[j] : 0);
+        u128 inc = wave_incl_scan128(xv);
+        if (lane_id() == WAVE - 1) wsum[threadIdx.x / WAVE] = inc;
+        __syncthreads();
+        u128 before = carry;
+        for (int w = 0; w < (int)(threadIdx.x / WAVE); w++) before += wsum[w];
+        inc += before;
+        if (j < d) {
+            plo[j] = lo64(inc);
+            if (pw) phi[j] = hi64(inc);
+        }
+        __syncthreads();
+        if (threadIdx.x == blockDim.x - 1) carry = inc;
+        __syncthreads();
+    }
+}
+
+__global__ void k_hub_index(const int32_t *hubs, int nhub, int32_t *index)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nhub) index[hubs[i]] = i;
 }
 
 __global__ void k_occ(GraphView g, const DevLut *Lp, LevelView lev_h, int h, int64_t v, int32_t key,
@@ -251,9 +403,111 @@ __global__ void __launch_bounds__(WAVE) k_export(int64_t n, LevelView Lv, int h1
     }
 }
 
-LevelView lview(const TableLevel &l) { return LevelView{l.pool, l.off, l.meta, l.N}; }
+LevelView lview(const TableLevel &l) { return LevelView{l.pool, l.off, l.meta, l.N, l.bm, l.BW}; }
 
 }  // namespace
+
+__global__ void k_hub_info(const int32_t *hubs, int nhub, int k, const uint8_t *colors, HubPreArgs A, uint8_t *out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nhub) return;
+    const int64_t x = hubs[i];
+    out[(size_t)i * (SCC_KMAX + 2)] = colors[x];
+    for (int h = 1; h < k; h++) out[(size_t)i * (SCC_KMAX + 2) + h] = hi64(A.M[h][x]) ? 1 : 0;
+}
+
+// Builds the per-hub running sums used by the sampler's neighbour draw. Hubs
+// are taken by decreasing degree while the tables fit in `budget` bytes.
+static scc_status ensure_hub_prefix(scc_table *T)
+{
+    std::lock_guard<std::mutex> g(T->hub_mu);
+    if (T->hubpre_ready) return SCC_OK;
+    const int k = T->k;
+    const int nh = (int)T->hub_host.size();
+    hipStream_t st = T->stream;
+    if (nh == 0 || k < 2) { T->hubpre_ready = true; return SCC_OK; }
+    const DevLut &HL = T->hlut;
+    HubPreArgs A{};
+    A.g = GraphView{T->n, T->row_ptr, T->col_idx, T->colors};
+    A.L = T->dlut; A.k = k; A.nkeys = HL.nkeys; A.zero = T->rooting == SCC_ROOT_ZERO;
+    for (int h = 2; h <= k; h++) A.lev[h] = lview(T->lev[h]);
+    for (int h = 1; h < k; h++) A.M[h] = T->S[h].M;
+    A.key_sidx = T->key_sidx;
+    std::vector<void *> tmp;
+    auto get = [&](size_t b) { void *p = T->mem.get(b); if (p) tmp.push_back(p); return p; };
+    struct Free { scc_table *T; std::vector<void *> *v; ~Free() { for (void *p : *v) T->mem.put(p); } } fr{T, &tmp};
+    int32_t *dh = (int32_t *)get((size_t)nh * 4);
+    uint8_t *dinfo = (uint8_t *)get((size_t)nh * (SCC_KMAX + 2));
+    if (!dh || !dinfo) return set_error(SCC_ENOMEM, "hub info");
+    HIP_TRY(hipMemcpyAsync(dh, T->hub_host.data(), (size_t)nh * 4, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_hub_info, dim3((unsigned)((nh + 255) / 256)), dim3(256), 0, st, dh, nh, k, T->colors, A, dinfo);
+    std::vector<uint8_t> info((size_t)nh * (SCC_KMAX + 2));
+    HIP_TRY(hipMemcpyAsync(info.data(), dinfo, info.size(), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    // choose hubs by decreasing degree within the budget
+    std::vector<int> order(nh);
+    for (int i = 0; i < nh; i++) order[i] = i;
+    auto deg = [&](int i) { return T->hub_rows_host[2 * i + 1] - T->hub_rows_host[2 * i]; };
+    std::sort(order.begin(), order.end(), [&](int a, int b) { return deg(a) > deg(b); });
+    const bool zero = T->rooting == SCC_ROOT_ZERO;
+    auto block_words = [&](int i, int h) -> int64_t {
+        if (zero && h == k - 1 && info[(size_t)i * (SCC_KMAX + 2)] != 0) return 0;   // never a root there
+        const int64_t w = (int64_t)HL.WS[h] * deg(i);
+        return info[(size_t)i * (SCC_KMAX + 2) + h] ? 2 * w : w;
+    };
+    const int64_t budget_words = T->hub_prefix_budget / 8;
+    std::vector<int> chosen;
+    int64_t total = 0;
+    for (int i : order) {
+        int64_t w = 0;
+        for (int h = 1; h < k; h++) w += block_words(i, h);
+        if (total + w > budget_words) break;
+        total += w;
+        chosen.push_back(i);
+    }
+    std::sort(chosen.begin(), chosen.end());
+    const int nc = (int)chosen.size();
+    T->hub_count_pre = nc;
+    if (nc == 0) { T->hubpre_ready = true; return SCC_OK; }
+    std::vector<int32_t> hubs(nc);
+    std::vector<int64_t> rows(2 * (size_t)nc), poff((size_t)nc * (SCC_KMAX + 1), 0);
+    std::vector<int32_t> ch;
+    std::vector<int64_t> ce;
+    int64_t at = 0;
+    for (int q = 0; q < nc; q++) {
+        const int i = chosen[q];
+        hubs[q] = T->hub_host[i];
+        rows[2 * q] = T->hub_rows_host[2 * i];
+        rows[2 * q + 1] = T->hub_rows_host[2 * i + 1];
+        for (int h = 1; h < k; h++) { poff[(size_t)q * (SCC_KMAX + 1) + h] = at; at += block_words(i, h); }
+        for (int64_t e = rows[2 * q]; e < rows[2 * q + 1]; e += 1024) { ch.push_back(q); ce.push_back(e); }
+    }
+    T->hub_pre = (uint64_t *)T->alloc((size_t)at * 8 + 8);
+    T->hub_poff = (int64_t *)T->alloc(poff.size() * 8);
+    T->hub_index = (int32_t *)T->alloc((size_t)T->n * 4 + 4);
+    int32_t *dhubs = (int32_t *)T->alloc((size_t)nc * 4);
+    int64_t *drows = (int64_t *)get(rows.size() * 8);
+    int32_t *dch = (int32_t *)get(ch.size() * 4);
+    int64_t *dce = (int64_t *)get(ce.size() * 8);
+    if (!T->hub_pre || !T->hub_poff || !T->hub_index || !dhubs || !drows || !dch || !dce)
+        return set_error(SCC_ENOMEM, "hub running sums (%lld bytes)", (long long)at * 8);
+    HIP_TRY(hipMemsetAsync(T->hub_pre, 0, (size_t)at * 8, st));
+    HIP_TRY(hipMemsetAsync(T->hub_index, 0xff, (size_t)T->n * 4, st));
+    HIP_TRY(hipMemcpyAsync(T->hub_poff, poff.data(), poff.size() * 8, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(dhubs, hubs.data(), (size_t)nc * 4, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(drows, rows.data(), rows.size() * 8, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(dch, ch.data(), ch.size() * 4, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(dce, ce.data(), ce.size() * 8, hipMemcpyHostToDevice, st));
+    A.hubs = dhubs; A.hub_rows = drows; A.poff = T->hub_poff; A.pre = T->hub_pre;
+    A.chunk_hub = dch; A.chunk_e = dce; A.chunk = 1024;
+    hipLaunchKernelGGL(k_hub_index, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, st, dhubs, nc, T->hub_index);
+    hipLaunchKernelGGL(k_hubpre_fill, dim3((unsigned)ch.size(), (unsigned)(k - 1)), dim3(WAVE), 0, st, A);
+    hipLaunchKernelGGL(k_hubpre_scan, dim3((unsigned)nc, (unsigned)HL.soff[k]), dim3(256), 0, st, A);
+    HIP_TRY(hipStreamSynchronize(st));
+    HIP_TRY(hipGetLastError());
+    T->hubpre_ready = true;
+    return SCC_OK;
+}
 
 scc_status table_prefix(scc_table *T, int shape, const u128 **pre, u128 *total)
 {
@@ -304,10 +558,14 @@ extern "C" scc_status scc_sample(const scc_table *tc, int32_t shape, int64_t n, 
     scc_status s = table_prefix(T, shape, &pre, &total);
     if (s) return s;
     if (total == 0) return set_error(SCC_EEMPTY, "no colourful %d-treelet to sample", T->k);
+    s = ensure_hub_prefix(T);
+    if (s) return s;
     hipStream_t st = stream ? (hipStream_t)stream : T->stream;
     int *err = (int *)T->mem.get(16);
     if (!err) return set_error(SCC_ENOMEM, "sample flags");
     SampleArgs A{};
+    A.key_xidx = T->key_xidx; A.nkeys = T->hlut.nkeys;
+    if (T->hub_count_pre) { A.hub_index = T->hub_index; A.hub_poff = T->hub_poff; A.hub_pre = T->hub_pre; }
     A.g = GraphView{T->n, T->row_ptr, T->col_idx, T->colors};
     A.L = T->dlut; A.k = T->k; A.shape = shape; A.zero = T->rooting == SCC_ROOT_ZERO;
     for (int h = 2; h <= T->k; h++) A.lev[h] = lview(T->lev[h]);

@@ -14,6 +14,8 @@ struct TableLevel {
     u128 *N = nullptr;          // [n] sum of the vertex's counts
     int64_t nnz = 0;
     int64_t wide = 0;
+    uint64_t *bm = nullptr;     // [n * BW] presence bitmaps over the dense level layout
+    int BW = 0;
 };
 
 struct TableSums {
@@ -49,6 +51,23 @@ struct scc_table {
     double gather_ms[SCC_KMAX + 1] = {0};
     double gather_bytes[SCC_KMAX + 1] = {0};
     int64_t bytes = 0;
+    int hub_degree = 1024;           // rows above this degree are gathered in chunks
+    int hub_chunk = 256;             // neighbours per chunk
+    int nhub = 0;
+    bool stats_done = false;
+    std::vector<int32_t> hub_host;   // hub vertices (ascending) and their row bounds
+    std::vector<int64_t> hub_rows_host;
+    // per-hub running sums over neighbours of every neighbour-sum entry, for the
+    // sampler's neighbour draw (built on the first sampling call)
+    bool hubpre_ready = false;
+    std::mutex hub_mu;
+    int hub_count_pre = 0;           // hubs that have running sums
+    int64_t hub_prefix_budget = (int64_t)8 << 30;
+    int32_t *hub_index = nullptr;    // [n] hub number or -1
+    int64_t *hub_poff = nullptr;     // [nhub * (k+1)] word offset of each (hub, level) block
+    uint64_t *hub_pre = nullptr;     // the running sums (low words, then high words if wide)
+    // root draw: every ROOT_STRIDE-th running sum, for a two-level search
+    u128 *pre_coarse = nullptr;
 
     void *alloc(size_t bytes_)
     {

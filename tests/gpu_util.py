@@ -12,10 +12,10 @@ def scc():
     return S
 
 
-def build_pair(g, colors, k, rooting=0, validate=True):
+def build_pair(g, colors, k, rooting=0, validate=True, hub_degree=0):
     S = scc()
     dg = S.DeviceGraph.from_graph(g)
-    gt = S.Table(dg, colors, k, rooting=rooting, validate=validate)
+    gt = S.Table(dg, colors, k, rooting=rooting, validate=validate, hub_degree=hub_degree)
     ot = O.Table(g, colors, k, rooting)
     return gt, ot
 

@@ -17,20 +17,23 @@ pytestmark = pytest.mark.gpu
 
 @pytest.mark.parametrize("k", [2, 3, 4, 5, 6, 7, 8])
 @pytest.mark.parametrize("rooting", [O.ROOT_ZERO, O.ROOT_ALL])
-def test_uniform_samples_equal(k, rooting):
+@pytest.mark.parametrize("hub_degree", [0, 5])
+def test_uniform_samples_equal(k, rooting, hub_degree):
+    # hub_degree = 5: rows of degree > 5 draw neighbours from per-hub running sums
     for name, g in random_graphs(k):
         colors = gg.colors(g.n, k, seed=5 * k + rooting)
-        gt, ot = build_pair(g, colors, k, rooting=rooting)
+        gt, ot = build_pair(g, colors, k, rooting=rooting, hub_degree=hub_degree)
         if ot.totals()[0] == 0:
             continue
         assert_samples_equal(gt, ot, 300, seed=1000 + k, stream=rooting, label=name)
 
 
 @pytest.mark.parametrize("k", [4, 5, 6, 7, 8])
-def test_shape_restricted_samples_equal(k):
+@pytest.mark.parametrize("hub_degree", [0, 12])
+def test_shape_restricted_samples_equal(k, hub_degree):
     g = gg.chung_lu(600, 2400, 2.2, 60, seed=50 + k)
     colors = gg.colors(g.n, k, seed=60 + k)
-    gt, ot = build_pair(g, colors, k)
+    gt, ot = build_pair(g, colors, k, hub_degree=hub_degree)
     t, tj = ot.totals()
     assert gt.totals() == (t, tj)
     for j, tot in enumerate(tj):

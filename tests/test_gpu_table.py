@@ -28,17 +28,20 @@ def test_tiny_workload_all_rootings():
 
 @pytest.mark.parametrize("k", [2, 3, 4, 5, 6, 7, 8])
 @pytest.mark.parametrize("rooting", [O.ROOT_ZERO, O.ROOT_ALL])
-def test_random_graphs_every_k(k, rooting):
+@pytest.mark.parametrize("hub_degree", [0, 6])
+def test_random_graphs_every_k(k, rooting, hub_degree):
+    # hub_degree = 6 sends every row of degree > 6 through the chunked hub gather
     for name, g in random_graphs(k):
         colors = gg.colors(g.n, k, seed=17 * k + rooting)
-        gt, ot = build_pair(g, colors, k, rooting=rooting)
-        assert_tables_equal(gt, ot, k, name)
+        gt, ot = build_pair(g, colors, k, rooting=rooting, hub_degree=hub_degree)
+        assert_tables_equal(gt, ot, k, f"{name} hub>{hub_degree}")
 
 
-def test_chung_lu_k6_multi_tile():
+@pytest.mark.parametrize("hub_degree", [0, 40])
+def test_chung_lu_k6_multi_tile(hub_degree):
     g = gg.chung_lu(20000, 100000, 2.1, 2000, seed=9)
     colors = gg.colors(g.n, 6, seed=10)
-    gt, ot = build_pair(g, colors, 6)
+    gt, ot = build_pair(g, colors, 6, hub_degree=hub_degree)
     assert_tables_equal(gt, ot, 6, "cl20k")
 
 
