@@ -125,13 +125,21 @@ typedef struct {
     uint64_t tj[32][2];        /* per unrooted shape j */
     double level_ms[9];        /* device time of level h (bound, gather, combine, pack) */
     double gather_ms[9];       /* device time of the neighbour-sum gather of level h */
-    double gather_bytes[9];    /* its algorithmic bytes: 4 d_v + neighbours' records
-                                  (10 B per 64-bit entry, 18 B per 128-bit entry)
-                                  + the dense neighbour sums written, over gathered rows */
+    int num_hubs;              /* rows gathered in chunks (degree above the hub threshold) */
 } scc_table_info;
 
-/* Table summary (host struct). Synchronises the table's stream once. */
+/* Table summary (host struct; no device work). */
 scc_status scc_table_info_get(const scc_table *t, scc_table_info *out);
+
+/*
+ * scc_gather_bytes -- algorithmic bytes of each level's neighbour-sum gather
+ * (for roofline reports): over the gathered rows v, 4 d_v (neighbour ids) +
+ * the neighbours' level-h records (10 B per entry of a 64-bit vertex, 18 B
+ * per entry of a 128-bit vertex) + the dense sums written (8 B per entry, 16 B
+ * for 128-bit rows). out: host double[9], out[h] for h = 1..k-1. Runs a
+ * counting kernel on the table's stream and synchronises it.
+ */
+scc_status scc_gather_bytes(const scc_table *t, double out[9]);
 
 /*
  * scc_occ -- database queries of Sec. 3: occ(T_C, v) (key >= 0: the count of

@@ -50,7 +50,7 @@ class TableInfo(C.Structure):
     _fields_ = [("n", C.c_int64), ("k", C.c_int), ("rooting", C.c_int), ("num_unrooted", C.c_int),
                 ("nnz", C.c_int64 * 9), ("wide_vertices", C.c_int64 * 9), ("bytes", C.c_int64),
                 ("t", C.c_uint64 * 2), ("tj", (C.c_uint64 * 2) * 32), ("level_ms", C.c_double * 9),
-                ("gather_ms", C.c_double * 9), ("gather_bytes", C.c_double * 9)]
+                ("gather_ms", C.c_double * 9), ("num_hubs", C.c_int)]
 
 
 _P = C.c_void_p
@@ -59,6 +59,7 @@ _SIGS = {
     "scc_build_table": (C.c_int, [C.POINTER(_Csr), _P, C.c_int, C.POINTER(_BuildOpts), C.POINTER(_P)]),
     "scc_table_destroy": (None, [_P]),
     "scc_table_info_get": (C.c_int, [_P, C.POINTER(TableInfo)]),
+    "scc_gather_bytes": (C.c_int, [_P, _P]),
     "scc_occ": (C.c_int, [_P, _i64, _i32, _P]),
     "scc_export_level": (C.c_int, [_P, C.c_int, C.POINTER(_i64), _P, _P, _P, _P, _P]),
     "scc_sample": (C.c_int, [_P, _i32, _i64, _u64, _u64, _u64, _P, _P, _P]),
@@ -172,6 +173,11 @@ class Table:
         out = TableInfo()
         _check(_lib.scc_table_info_get(self._h, C.byref(out)))
         return out
+
+    def gather_bytes(self) -> list:
+        out = (C.c_double * 9)()
+        _check(_lib.scc_gather_bytes(self._h, out))
+        return list(out)
 
     def totals(self):
         """(t, [t_j]) as Python ints."""

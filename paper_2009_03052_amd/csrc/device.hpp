@@ -8,22 +8,55 @@
 // ---------------------------------------------------------------------------
 // Table views passed to kernels
 // ---------------------------------------------------------------------------
-// One stored level h >= 2. Record of v (len entries, sorted by key) starts at
-// word off[v] of pool: ceil(len/4) words of uint16 keys, then len words of low
-// count bits, then, if the vertex is wide, len words of high bits.
+// One stored level h >= 2. The locator of v packs the record's word offset in
+// the pool (40 bits), its length (12 bits) and a 128-bit flag (1 bit). The
+// record (len entries, sorted by key) is: the vertex's level sum N (2 words),
+// ceil(len/4) words of uint16 keys, len words of low count bits and, for a
+// 128-bit vertex, len words of high bits. A vertex without entries has
+// locator 0 and no record.
 struct LevelView {
     const uint64_t *pool;
-    const uint64_t *off;
-    const uint32_t *meta;      // len | wide << 31
-    const u128 *N;             // sum of the vertex's counts at this level
+    const uint64_t *loc;       // [n] record locators
     const uint64_t *bm;        // presence bitmaps, BW words per vertex
     int BW;
 };
 
+#define LOC_OFF(l) ((l) & 0xffffffffffull)
+#define LOC_LEN(l) ((uint32_t)(((l) >> 40) & 0xfffu))
+#define LOC_WIDE(l) ((uint32_t)(((l) >> 52) & 1u))
+#define REC_HDR 2u
+
+// build-time record summary: len | wide << 31
 #define META_LEN(m) ((m) & 0x7fffffffu)
 #define META_WIDE(m) ((m) >> 31)
 
-__device__ inline uint32_t key_words(uint32_t len) { return (len + 3u) >> 2; }
+__host__ __device__ inline uint32_t key_words(uint32_t len) { return (len + 3u) >> 2; }
+__host__ __device__ inline uint64_t make_loc(uint64_t off, uint32_t len, uint32_t wide)
+{
+    return len ? (off | ((uint64_t)len << 40) | ((uint64_t)wide << 52)) : 0ull;
+}
+
+struct Rec {
+    const uint64_t *p;   // record start (the header)
+    uint32_t len, kw;
+    bool wide;
+    __device__ uint32_t key(uint32_t e) const { return ((const uint16_t *)(p + REC_HDR))[e]; }
+    __device__ uint64_t lo(uint32_t e) const { return p[REC_HDR + kw + e]; }
+    __device__ uint64_t hi(uint32_t e) const { return wide ? p[REC_HDR + kw + len + e] : 0; }
+    __device__ u128 cnt(uint32_t e) const { return mk128(lo(e), hi(e)); }
+    __device__ u128 N() const { return len ? mk128(p[0], p[1]) : (u128)0; }
+};
+
+__device__ inline Rec rec_of(const LevelView &L, int64_t v)
+{
+    const uint64_t l = L.loc[v];
+    Rec r;
+    r.len = LOC_LEN(l);
+    r.wide = LOC_WIDE(l) != 0;
+    r.kw = key_words(r.len);
+    r.p = L.pool + LOC_OFF(l);
+    return r;
+}
 
 struct GraphView {
     int64_t n;
@@ -101,30 +134,18 @@ __device__ inline u128 record_at(const LevelView &L, int64_t v, int li)
     if (!((word >> (li & 63)) & 1ull)) return 0;
     uint32_t pos = (uint32_t)__popcll(word & ((1ull << (li & 63)) - 1ull));
     for (int q = 0; q < w; q++) pos += (uint32_t)__popcll(bw[q]);
-    const uint32_t m = L.meta[v], len = META_LEN(m);
-    const uint64_t *rec = L.pool + L.off[v];
-    const uint32_t kw = key_words(len);
-    return mk128(rec[kw + pos], META_WIDE(m) ? rec[kw + len + pos] : 0);
+    return rec_of(L, v).cnt(pos);
 }
 
 // Count of a key in a stored record by binary search (0 if absent).
 __device__ inline u128 record_lookup(const LevelView &L, int64_t v, uint32_t key)
 {
-    uint32_t m = L.meta[v];
-    uint32_t len = META_LEN(m);
-    if (len == 0) return 0;
-    const uint64_t *rec = L.pool + L.off[v];
-    const uint16_t *keys = (const uint16_t *)rec;
-    uint32_t lo = 0, hi = len;
+    const Rec r = rec_of(L, v);
+    uint32_t lo = 0, hi = r.len;
     while (lo < hi) {
-        uint32_t mid = (lo + hi) >> 1;
-        uint32_t kk = keys[mid];
-        if (kk == key) {
-            uint32_t kw = key_words(len);
-            uint64_t cl = rec[kw + mid];
-            uint64_t ch = META_WIDE(m) ? rec[kw + len + mid] : 0;
-            return mk128(cl, ch);
-        }
+        const uint32_t mid = (lo + hi) >> 1;
+        const uint32_t kk = r.key(mid);
+        if (kk == key) return r.cnt(mid);
         if (kk < key) lo = mid + 1; else hi = mid;
     }
     return 0;

@@ -57,8 +57,8 @@ __global__ void k_validate(GraphView g, int k, int *err)
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(WAVE) k_gather1(GraphView g, int k, uint64_t *S1, u128 *M1)
 {
-    __shared__ unsigned cnt[SCC_KMAX];
-    const int64_t v = blockIdx.x;
+  __shared__ unsigned cnt[SCC_KMAX];
+  for (int64_t v = blockIdx.x; v < g.n; v += gridDim.x) {
     const int lane = threadIdx.x;
     const int cv = g.colors[v];
     if (lane < SCC_KMAX) cnt[lane] = 0;
@@ -75,6 +75,8 @@ __global__ void __launch_bounds__(WAVE) k_gather1(GraphView g, int k, uint64_t *
         S1[v * (k - 1) + pos] = cnt[lane];
     }
     if (lane == 0) M1[v] = (u128)(b - a);
+    __syncthreads();
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -104,14 +106,8 @@ __device__ inline void gather_range(const GatherArgs &A, int cv, int64_t a, int6
     const int16_t *sidx = A.key_sidx + (size_t)cv * A.nkeys;
     for (int64_t base = a; base < b; base += WAVE) {
         const int64_t e = base + lane;
-        uint32_t len = 0, meta = 0;
-        uint64_t off = 0;
-        if (e < b) {
-            const int32_t u = A.g.col_idx[e];
-            meta = A.L.meta[u];
-            len = META_LEN(meta);
-            if (len) off = A.L.off[u];
-        }
+        const uint64_t lc = e < b ? A.L.loc[A.g.col_idx[e]] : 0ull;
+        const uint32_t len = LOC_LEN(lc);
         const uint32_t incl = wave_incl_scan32(len);
         const uint32_t total = __shfl(incl, WAVE - 1, WAVE);
         // entries of this chunk of neighbours, flattened over the lanes
@@ -127,12 +123,11 @@ __device__ inline void gather_range(const GatherArgs &A, int cv, int64_t a, int6
             }
             if (j > WAVE - 1) j = WAVE - 1;
             const uint32_t incl_j = __shfl(incl, j, WAVE);
-            const uint32_t meta_j = __shfl(meta, j, WAVE);
-            const uint64_t off_j = shfl64(off, j);
+            const uint64_t lc_j = shfl64(lc, j);
             if (p < total) {
-                const uint32_t len_j = META_LEN(meta_j);
+                const uint32_t len_j = LOC_LEN(lc_j);
                 const uint32_t ei = p - (incl_j - len_j);
-                const uint64_t *rec = A.L.pool + off_j;
+                const uint64_t *rec = A.L.pool + LOC_OFF(lc_j) + REC_HDR;
                 const uint32_t kw = key_words(len_j);
                 const uint32_t key = ((const uint16_t *)rec)[ei];
                 const uint64_t cl = rec[kw + ei];
@@ -141,7 +136,7 @@ __device__ inline void gather_range(const GatherArgs &A, int cv, int64_t a, int6
                     if (!wideS) {
                         atomicAdd((unsigned long long *)&acc_lo[s], (unsigned long long)cl);
                     } else {
-                        const uint64_t ch = META_WIDE(meta_j) ? rec[kw + len_j + ei] : 0;
+                        const uint64_t ch = LOC_WIDE(lc_j) ? rec[kw + len_j + ei] : 0;
                         const unsigned long long old = atomicAdd((unsigned long long *)&acc_lo[s], (unsigned long long)cl);
                         const uint64_t carry = (old + cl) < old ? 1u : 0u;
                         if (ch + carry) atomicAdd((unsigned long long *)&acc_hi[s], (unsigned long long)(ch + carry));
@@ -152,10 +147,8 @@ __device__ inline void gather_range(const GatherArgs &A, int cv, int64_t a, int6
     }
 }
 
-__global__ void __launch_bounds__(WAVE) k_gather(GatherArgs A)
+__device__ inline void gather_vertex(const GatherArgs &A, int64_t v, uint64_t *sm)
 {
-    extern __shared__ uint64_t sm[];
-    const int64_t v = blockIdx.x;
     const int lane = threadIdx.x;
     const int cv = A.g.colors[v];
     if (A.rows_zero && cv != 0) return;
@@ -163,7 +156,7 @@ __global__ void __launch_bounds__(WAVE) k_gather(GatherArgs A)
     if (b - a > A.hub_degree) return;      // hub rows have their own kernels
     // bound: every entry of S_hs(v) is at most M_hs(v)
     u128 m = 0;
-    for (int64_t e = a + lane; e < b; e += WAVE) m = sat_add(m, A.L.N[A.g.col_idx[e]]);
+    for (int64_t e = a + lane; e < b; e += WAVE) m = sat_add(m, rec_of(A.L, A.g.col_idx[e]).N());
     m = wave_satsum128(m);
     const bool wideS = hi64(m) != 0;
     const int WS = A.WS;
@@ -182,6 +175,15 @@ __global__ void __launch_bounds__(WAVE) k_gather(GatherArgs A)
     if (lane == 0) A.M[v] = m;
 }
 
+__global__ void __launch_bounds__(WAVE) k_gather(GatherArgs A)
+{
+    extern __shared__ uint64_t sm[];
+    for (int64_t v = blockIdx.x; v < A.g.n; v += gridDim.x) {
+        gather_vertex(A, v, sm);
+        __syncthreads();
+    }
+}
+
 // hub rows, step 1: the bound M_hs(v) and cleared sums
 __global__ void __launch_bounds__(256) k_hub_prepare(GatherArgs A, const int32_t *hubs)
 {
@@ -189,7 +191,7 @@ __global__ void __launch_bounds__(256) k_hub_prepare(GatherArgs A, const int32_t
     const int64_t v = hubs[blockIdx.x];
     const int64_t a = A.g.row_ptr[v], b = A.g.row_ptr[v + 1];
     u128 m = 0;
-    for (int64_t e = a + threadIdx.x; e < b; e += blockDim.x) m = sat_add(m, A.L.N[A.g.col_idx[e]]);
+    for (int64_t e = a + threadIdx.x; e < b; e += blockDim.x) m = sat_add(m, rec_of(A.L, A.g.col_idx[e]).N());
     m = wave_satsum128(m);
     if (lane_id() == 0) part[threadIdx.x / WAVE] = m;
     for (int i = threadIdx.x; i < A.WS; i += blockDim.x) {
@@ -247,8 +249,8 @@ __global__ void __launch_bounds__(256) k_gather_bytes(GraphView g, LevelView L, 
         const int64_t a = g.row_ptr[v], b = g.row_ptr[v + 1];
         bytes = 4ull * (uint64_t)(b - a) + (uint64_t)WS * (hi64(M[v]) ? 16u : 8u);
         for (int64_t e = a; e < b; e++) {
-            const uint32_t m = L.meta[g.col_idx[e]];
-            bytes += (uint64_t)META_LEN(m) * (META_WIDE(m) ? 18u : 10u);
+            const uint64_t l = L.loc[g.col_idx[e]];
+            bytes += (uint64_t)LOC_LEN(l) * (LOC_WIDE(l) ? 18u : 10u);
         }
     }
     bytes = wave_sum64(bytes);
@@ -290,11 +292,9 @@ struct CombineArgs {
     int *err;                             // [0]: overflow
 };
 
-__global__ void __launch_bounds__(WAVE) k_combine(CombineArgs A)
+__device__ inline void combine_vertex(const CombineArgs &A, int64_t v, uint64_t *sm)
 {
-    extern __shared__ uint64_t sm[];
     const DevLut &L = *A.L;
-    const int64_t v = blockIdx.x;
     const int lane = threadIdx.x;
     const int h = A.h;
     const int cv = A.g.colors[v];
@@ -305,7 +305,7 @@ __global__ void __launch_bounds__(WAVE) k_combine(CombineArgs A)
     // per-vertex bound: U >= sum over (T, C) of beta_T c(T_C, v) >= every partial sum
     u128 U = 0;
     for (int hp = 1; hp < h; hp++) {
-        u128 Nv = hp == 1 ? (u128)1 : A.lev[hp].N[v];
+        u128 Nv = hp == 1 ? (u128)1 : rec_of(A.lev[hp], v).N();
         U = sat_add(U, sat_mul(Nv, A.M[h - hp][v]));
     }
     if (U == ~(u128)0 || bitlen128(U) > A.max_bits) {
@@ -320,16 +320,11 @@ __global__ void __launch_bounds__(WAVE) k_combine(CombineArgs A)
     if (lane == 0) Xlo[L.xoff[1]] = 1;   // level 1: the single node, coloured c_v
     const int16_t *xidx = A.key_xidx + (size_t)cv * L.nkeys;
     for (int hp = 2; hp < h; hp++) {
-        const LevelView &Lv = A.lev[hp];
-        const uint32_t m = Lv.meta[v], len = META_LEN(m);
-        if (!len) continue;
-        const uint64_t *rec = Lv.pool + Lv.off[v];
-        const uint32_t kw = key_words(len);
-        for (uint32_t e = lane; e < len; e += WAVE) {
-            uint32_t key = ((const uint16_t *)rec)[e];
-            int x = L.xoff[hp] + xidx[key];
-            Xlo[x] = rec[kw + e];
-            Xhi[x] = META_WIDE(m) ? rec[kw + len + e] : 0;
+        const Rec r = rec_of(A.lev[hp], v);
+        for (uint32_t e = lane; e < r.len; e += WAVE) {
+            const int x = L.xoff[hp] + xidx[r.key(e)];
+            Xlo[x] = r.lo(e);
+            Xhi[x] = r.hi(e);
         }
     }
     for (int hs = 1; hs < h; hs++) {
@@ -407,21 +402,34 @@ __global__ void __launch_bounds__(WAVE) k_combine(CombineArgs A)
     }
 }
 
-// stored entries and 128-bit vertices of a level
-__global__ void k_meta_sum(int64_t n, const uint32_t *meta, unsigned long long *out)
+__global__ void __launch_bounds__(WAVE) k_combine(CombineArgs A)
 {
-    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    extern __shared__ uint64_t sm[];
+    for (int64_t v = blockIdx.x; v < A.g.n; v += gridDim.x) {
+        combine_vertex(A, v, sm);
+        __syncthreads();
+    }
+}
+
+// stored entries and 128-bit vertices of a level
+__global__ void __launch_bounds__(256) k_meta_sum(int64_t n, const uint32_t *meta, unsigned long long *out)
+{
+    __shared__ uint64_t part[2][256 / WAVE];
     uint64_t len = 0, wide = 0;
-    if (v < n) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
         const uint32_t m = meta[v];
-        len = META_LEN(m);
-        wide = META_WIDE(m);
+        len += META_LEN(m);
+        wide += META_WIDE(m);
     }
     len = wave_sum64(len);
     wide = wave_sum64(wide);
-    if (lane_id() == 0 && (len || wide)) {
-        atomicAdd(&out[0], (unsigned long long)len);
-        atomicAdd(&out[1], (unsigned long long)wide);
+    if (lane_id() == 0) { part[0][threadIdx.x / WAVE] = len; part[1][threadIdx.x / WAVE] = wide; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t a = 0, b = 0;
+        for (int w = 0; w < 256 / WAVE; w++) { a += part[0][w]; b += part[1][w]; }
+        if (a) atomicAdd(&out[0], (unsigned long long)a);
+        if (b) atomicAdd(&out[1], (unsigned long long)b);
     }
 }
 
@@ -431,17 +439,17 @@ __global__ void k_words(int64_t n, const uint32_t *meta, uint64_t *words)
     int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
     uint32_t m = meta[v], len = META_LEN(m);
-    words[v] = len ? (uint64_t)key_words(len) + (uint64_t)len * (META_WIDE(m) ? 2u : 1u) : 0;
+    words[v] = len ? (uint64_t)REC_HDR + key_words(len) + (uint64_t)len * (META_WIDE(m) ? 2u : 1u) : 0;
 }
 
 // copy each vertex's slot into the packed pool at its offset
 __global__ void __launch_bounds__(WAVE) k_pack(int64_t n, int W, const uint32_t *meta, const uint64_t *off_incl,
                                                const uint16_t *slot_key, const uint64_t *slot_lo,
-                                               const uint64_t *slot_hi, uint64_t *pool, uint64_t *off,
+                                               const uint64_t *slot_hi, const u128 *Nv, uint64_t *pool, uint64_t *loc,
                                                const int16_t *key_xidx, int nkeys, const uint8_t *colors,
                                                uint64_t *bm, int BW)
 {
-    const int64_t v = blockIdx.x;
+  for (int64_t v = blockIdx.x; v < n; v += gridDim.x) {
     const int lane = threadIdx.x;
     const uint32_t m = meta[v], len = META_LEN(m);
     // presence bitmap over v's own entries (bit = position in the dense level-h layout)
@@ -463,17 +471,20 @@ __global__ void __launch_bounds__(WAVE) k_pack(int64_t n, int W, const uint32_t 
             if (lane == 0) bm[(size_t)v * BW + w] = word;
         }
     }
-    const uint32_t words = len ? key_words(len) + len * (META_WIDE(m) ? 2u : 1u) : 0;
-    const uint64_t start = off_incl[v] - words;
-    if (lane == 0) off[v] = start;
-    if (!len) return;
-    uint64_t *rec = pool + start;
     const uint32_t kw = key_words(len);
+    const uint32_t words = len ? REC_HDR + kw + len * (META_WIDE(m) ? 2u : 1u) : 0;
+    const uint64_t start = off_incl[v] - words;
+    if (lane == 0) loc[v] = make_loc(start, len, META_WIDE(m));
+    if (!len) continue;
+    uint64_t *rec = pool + start;
+    if (lane == 0) { rec[0] = lo64(Nv[v]); rec[1] = hi64(Nv[v]); }
+    rec += REC_HDR;
     uint16_t *keys = (uint16_t *)rec;
     for (uint32_t e = lane; e < kw * 4; e += WAVE) keys[e] = e < len ? slot_key[(size_t)v * W + e] : 0;
     for (uint32_t e = lane; e < len; e += WAVE) rec[kw + e] = slot_lo[(size_t)v * W + e];
     if (META_WIDE(m))
         for (uint32_t e = lane; e < len; e += WAVE) rec[kw + len + e] = slot_hi[(size_t)v * W + e];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -486,21 +497,14 @@ __global__ void __launch_bounds__(256) k_totals(GraphView g, const DevLut *Lp, L
     const int tid = threadIdx.x;
     const int nu = L.num_unr;
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + tid;
-    uint32_t len = 0, m = 0;
-    const uint64_t *rec = nullptr;
-    if (v < g.n && (!zero_only || g.colors[v] == 0)) {
-        m = Lk.meta[v];
-        len = META_LEN(m);
-        if (len) rec = Lk.pool + Lk.off[v];
-    }
+    Rec r{nullptr, 0, 0, false};
+    if (v < g.n && (!zero_only || g.colors[v] == 0)) r = rec_of(Lk, v);
     u128 e = 0;
-    const uint32_t kw = key_words(len);
     for (int j = 0; j < nu; j++) {
         u128 sj = 0;
-        for (uint32_t q = 0; q < len; q++) {
-            const uint32_t key = ((const uint16_t *)rec)[q];
-            const int t = (int)(key - L.off[L.k]) / L.bk[L.k];
-            if (L.unr_of[t] == j) sj += mk128(rec[kw + q], META_WIDE(m) ? rec[kw + len + q] : 0);
+        for (uint32_t q = 0; q < r.len; q++) {
+            const int t = (int)(r.key(q) - L.off[L.k]) / L.bk[L.k];
+            if (L.unr_of[t] == j) sj += r.cnt(q);
         }
         e += sj;
         sj = wave_sum128(sj);
@@ -515,13 +519,21 @@ __global__ void __launch_bounds__(256) k_totals(GraphView g, const DevLut *Lp, L
     }
 }
 
-__global__ void k_reduce_parts(const u128 *part, int nb, int nu, u128 *out)
+__global__ void __launch_bounds__(256) k_reduce_parts(const u128 *part, int nb, int nu, u128 *out)
 {
-    const int j = threadIdx.x;
+    __shared__ u128 ws[256 / WAVE];
+    const int j = blockIdx.x;
     if (j >= nu) return;
     u128 s = 0;
-    for (int b = 0; b < nb; b++) s += part[(size_t)b * 32 + j];
-    out[j] = s;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) s += part[(size_t)b * 32 + j];
+    s = wave_sum128(s);
+    if (lane_id() == 0) ws[threadIdx.x / WAVE] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        u128 t = 0;
+        for (int w = 0; w < 256 / WAVE; w++) t += ws[w];
+        out[j] = t;
+    }
 }
 
 __global__ void k_eta_shape(GraphView g, const DevLut *Lp, LevelView Lk, int zero_only, int shape, u128 *eta)
@@ -531,15 +543,10 @@ __global__ void k_eta_shape(GraphView g, const DevLut *Lp, LevelView Lk, int zer
     if (v >= g.n) return;
     u128 e = 0;
     if (!zero_only || g.colors[v] == 0) {
-        const uint32_t m = Lk.meta[v], len = META_LEN(m);
-        if (len) {
-            const uint64_t *rec = Lk.pool + Lk.off[v];
-            const uint32_t kw = key_words(len);
-            for (uint32_t q = 0; q < len; q++) {
-                const uint32_t key = ((const uint16_t *)rec)[q];
-                const int t = (key - L.off[L.k]) / L.bk[L.k];
-                if (L.unr_of[t] == shape) e += mk128(rec[kw + q], META_WIDE(m) ? rec[kw + len + q] : 0);
-            }
+        const Rec r = rec_of(Lk, v);
+        for (uint32_t q = 0; q < r.len; q++) {
+            const int t = (int)(r.key(q) - L.off[L.k]) / L.bk[L.k];
+            if (L.unr_of[t] == shape) e += r.cnt(q);
         }
     }
     eta[v] = e;
@@ -645,9 +652,14 @@ scc_status scan_incl(scc_table *T_, const T *in, T *out, int64_t n)
     return SCC_OK;
 }
 
+// grid-stride grids of one-wave workgroups, for kernels with even per-vertex work
+// (uneven ones, gather and combine, launch one workgroup per vertex and let the
+// dispatcher balance them)
+unsigned grid_of(int64_t n) { return (unsigned)std::min<int64_t>(n, 256 * 80); }
+
 LevelView view(const TableLevel &l)
 {
-    return LevelView{l.pool, l.off, l.meta, l.N, l.bm, l.BW};
+    return LevelView{l.pool, l.loc, l.bm, l.BW};
 }
 
 }  // namespace
@@ -740,7 +752,7 @@ static scc_status build_levels(scc_table *T)
     S1.M = (u128 *)T->alloc((size_t)n * 16 + 16);
     if (!S1.lo || !S1.M) return set_error(SCC_ENOMEM, "level-1 sums");
     HIP_TRY(hipEventRecord(g0, st));
-    if (n) hipLaunchKernelGGL(k_gather1, dim3((unsigned)n), dim3(WAVE), 0, st, g, k, S1.lo, S1.M);
+    if (n) hipLaunchKernelGGL(k_gather1, dim3(grid_of(n)), dim3(WAVE), 0, st, g, k, S1.lo, S1.M);
     HIP_TRY(hipEventRecord(g1, st));
     HIP_TRY(hipEventSynchronize(g1));
     {
@@ -758,7 +770,9 @@ static scc_status build_levels(scc_table *T)
     uint64_t *slot_lo = (uint64_t *)get((size_t)n * maxW * 8 + 256);
     uint64_t *slot_hi = (uint64_t *)get((size_t)n * maxW * 8 + 256);
     uint64_t *words = (uint64_t *)get((size_t)n * 8 + 256);
-    if (!slot_key || !slot_lo || !slot_hi || !words)
+    uint32_t *meta = (uint32_t *)get((size_t)n * 4 + 256);
+    u128 *Nsc = (u128 *)get((size_t)n * 16 + 256);
+    if (!slot_key || !slot_lo || !slot_hi || !words || !meta || !Nsc)
         return set_error(SCC_ENOMEM, "combine scratch (%lld bytes)", (long long)n * maxW * 18);
 
     for (int h = 2; h <= k; h++) {
@@ -789,23 +803,21 @@ static scc_status build_levels(scc_table *T)
         }
         // combine into slots
         TableLevel &Lv = T->lev[h];
-        Lv.meta = (uint32_t *)T->alloc((size_t)n * 4 + 8);
-        Lv.N = (u128 *)T->alloc((size_t)n * 16 + 16);
-        Lv.off = (uint64_t *)T->alloc((size_t)n * 8 + 8);
-        if (!Lv.meta || !Lv.N || !Lv.off) return set_error(SCC_ENOMEM, "level %d metadata", h);
+        Lv.loc = (uint64_t *)T->alloc((size_t)n * 8 + 8);
+        if (!Lv.loc) return set_error(SCC_ENOMEM, "level %d locators", h);
         CombineArgs C{};
         C.g = g; C.L = T->dlut; C.h = h; C.zero_only = zero && last; C.max_bits = T->max_bits;
         for (int q = 2; q < h; q++) C.lev[q] = view(T->lev[q]);
         for (int q = 1; q < h; q++) { C.Slo[q] = T->S[q].lo; C.Shi[q] = T->S[q].hi; C.M[q] = T->S[q].M; }
         C.key_xidx = T->key_xidx; C.W = HL.W[h];
         C.slot_key = slot_key; C.slot_lo = slot_lo; C.slot_hi = slot_hi;
-        C.meta = Lv.meta; C.Nout = Lv.N; C.err = err;
+        C.meta = meta; C.Nout = Nsc; C.err = err;
         const size_t lds = (size_t)(2 * HL.xoff[h] + 2 * HL.soff[h]) * 8;
         if (n) hipLaunchKernelGGL(k_combine, dim3((unsigned)n), dim3(WAVE), lds, st, C);
         int herr[4];
         HIP_TRY(hipMemcpyAsync(herr, err, sizeof herr, hipMemcpyDeviceToHost, st));
         // record sizes, offsets, pack
-        if (n) hipLaunchKernelGGL(k_words, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, Lv.meta, words);
+        if (n) hipLaunchKernelGGL(k_words, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, meta, words);
         HIP_TRY(hipStreamSynchronize(st));
         if (herr[0]) return set_error(SCC_EOVERFLOW, "a level-%d count needs more than %d bits", h, T->max_bits);
         if (hs >= 2) {
@@ -826,12 +838,12 @@ static scc_status build_levels(scc_table *T)
         Lv.BW = (HL.W[h] + 63) / 64;
         Lv.bm = (uint64_t *)T->alloc((size_t)n * Lv.BW * 8 + 8);
         if (!Lv.bm) return set_error(SCC_ENOMEM, "level %d bitmaps", h);
-        if (n) hipLaunchKernelGGL(k_pack, dim3((unsigned)n), dim3(WAVE), 0, st, n, HL.W[h], Lv.meta, words,
-                                  slot_key, slot_lo, slot_hi, Lv.pool, Lv.off, T->key_xidx, HL.nkeys, T->colors,
+        if (n) hipLaunchKernelGGL(k_pack, dim3(grid_of(n)), dim3(WAVE), 0, st, n, HL.W[h], meta, words,
+                                  slot_key, slot_lo, slot_hi, Nsc, Lv.pool, Lv.loc, T->key_xidx, HL.nkeys, T->colors,
                                   Lv.bm, Lv.BW);
         HIP_TRY(hipEventRecord(e1, st));
         HIP_TRY(hipMemsetAsync(flags, 0, 2 * sizeof(unsigned long long), st));
-        if (n) hipLaunchKernelGGL(k_meta_sum, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, Lv.meta, flags);
+        if (n) hipLaunchKernelGGL(k_meta_sum, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 1024)), dim3(256), 0, st, n, meta, flags);
         unsigned long long cnt2[2];
         HIP_TRY(hipMemcpyAsync(cnt2, flags, sizeof cnt2, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
@@ -883,7 +895,8 @@ static scc_status build_totals(scc_table *T)
     u128 *tjd = (u128 *)T->mem.get(32 * 16);
     if (!T->eta || !T->pre || !part || !tjd) { T->mem.put(part); T->mem.put(tjd); return set_error(SCC_ENOMEM, "totals"); }
     if (n) hipLaunchKernelGGL(k_totals, dim3((unsigned)nb), dim3(256), 0, st, g, T->dlut, view(T->lev[k]), zero ? 1 : 0, T->eta, part);
-    hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(32), 0, st, part, (int)(n ? nb : 0), T->hlut.num_unr, tjd);
+    hipLaunchKernelGGL(k_reduce_parts, dim3((unsigned)T->hlut.num_unr), dim3(256), 0, st, part, (int)(n ? nb : 0),
+                       T->hlut.num_unr, tjd);
     u128 tj[32];
     hipError_t e = hipMemcpyAsync(tj, tjd, sizeof tj, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -1001,11 +1014,18 @@ extern "C" void scc_table_destroy(scc_table *t)
     delete t;
 }
 
-extern "C" scc_status scc_table_info_get(const scc_table *t, scc_table_info *out)
+extern "C" scc_status scc_gather_bytes(const scc_table *t, double out[9])
 {
     if (!t || !out) return set_error(SCC_EINVAL, "NULL argument");
     scc_status s = gather_stats(const_cast<scc_table *>(t));
     if (s) return s;
+    for (int h = 0; h < 9; h++) out[h] = h <= t->k ? t->gather_bytes[h] : 0.0;
+    return SCC_OK;
+}
+
+extern "C" scc_status scc_table_info_get(const scc_table *t, scc_table_info *out)
+{
+    if (!t || !out) return set_error(SCC_EINVAL, "NULL argument");
     memset(out, 0, sizeof *out);
     out->n = t->n; out->k = t->k; out->rooting = t->rooting; out->num_unrooted = t->hlut.num_unr;
     for (int h = 1; h <= t->k; h++) {
@@ -1013,8 +1033,8 @@ extern "C" scc_status scc_table_info_get(const scc_table *t, scc_table_info *out
         out->wide_vertices[h] = t->lev[h].wide;
         out->level_ms[h] = t->level_ms[h];
         out->gather_ms[h] = t->gather_ms[h];
-        out->gather_bytes[h] = t->gather_bytes[h];
     }
+    out->num_hubs = t->nhub;
     out->bytes = t->bytes;
     out->t[0] = lo64(t->t); out->t[1] = hi64(t->t);
     for (int j = 0; j < t->hlut.num_unr; j++) { out->tj[j][0] = lo64(t->tj[j]); out->tj[j][1] = hi64(t->tj[j]); }

@@ -48,19 +48,26 @@ __device__ inline int first_exceeding(u128 incl, u128 target)
 }
 
 // First index j in [0, len) with val(j) > target, for a non-decreasing val whose
-// last element exceeds target. 64-ary search: every round each lane probes one
-// point, so a range of len entries takes ceil(log64 len) dependent loads.
+// last element exceeds target; -1 if it does not. While the range is large
+// every lane probes one point (64-way split: the probes of the first rounds are
+// shared by all samples and stay in cache); below 4096 entries only 8 lanes
+// probe (8-way split), which keeps the per-search traffic to a few cache lines.
 template <typename F>
 __device__ inline int64_t wave_search(int64_t len, u128 target, F val)
 {
     const int lane = lane_id();
     int64_t lo = 0;
     while (len > WAVE) {
-        const int64_t step = (len + WAVE - 1) / WAVE;
-        int64_t idx = lo + (int64_t)(lane + 1) * step - 1;
+        const int ways = len > 4096 ? WAVE : 8;
+        const int64_t step = (len + ways - 1) / ways;
         const int64_t last = lo + len - 1;
-        if (idx > last) idx = last;
-        const uint64_t bal = __ballot(val(idx) > target);
+        bool p = false;
+        if (lane < ways) {
+            int64_t idx = lo + (int64_t)(lane + 1) * step - 1;
+            if (idx > last) idx = last;
+            p = val(idx) > target;
+        }
+        const uint64_t bal = __ballot(p);
         if (!bal) return -1;                                 // target not below the last value
         const int f = __ffsll((long long)bal) - 1;
         const int64_t nlo = lo + (int64_t)f * step;
@@ -104,9 +111,8 @@ __global__ void __launch_bounds__(WAVE) k_sample(SampleArgs A)
             continue;
         }
         const u128 res = X - (v > 0 ? A.pre[v - 1] : (u128)0);
-        const LevelView &Lk = A.lev[k];
-        const uint32_t mk = Lk.meta[v], lenk = META_LEN(mk), kwk = key_words(lenk);
-        const uint64_t *reck = Lk.pool + (lenk ? Lk.off[v] : 0);
+        const Rec rk = rec_of(A.lev[k], v);
+        const uint32_t lenk = rk.len;
         u128 run = 0;
         uint32_t rkey = 0xffffffffu;
         u128 rcnt = 0;
@@ -115,10 +121,9 @@ __global__ void __launch_bounds__(WAVE) k_sample(SampleArgs A)
             u128 c = 0;
             uint32_t key = 0;
             if (e < lenk) {
-                key = ((const uint16_t *)reck)[e];
+                key = rk.key(e);
                 const int t = (int)(key - L.off[k]) / L.bk[k];
-                if (A.shape < 0 || L.unr_of[t] == A.shape)
-                    c = mk128(reck[kwk + e], META_WIDE(mk) ? reck[kwk + lenk + e] : 0);
+                if (A.shape < 0 || L.unr_of[t] == A.shape) c = rk.cnt(e);
             }
             const u128 incl = run + wave_incl_scan128(c);
             const int w = first_exceeding(incl, res);
@@ -272,79 +277,148 @@ struct HubPreArgs {
     uint64_t *pre;
     const int32_t *chunk_hub;    // hub number of each chunk
     const int64_t *chunk_e;      // first edge of each chunk
+    const int32_t *hub_first_chunk;
+    const int16_t *key_xidx;
+    u128 *part;                  // chunk totals, part_stride entries per chunk
+    int part_stride;
     int chunk;
 };
 
-__global__ void __launch_bounds__(WAVE) k_hubpre_fill(HubPreArgs A)
+// inclusive scan over a 256-thread workgroup (4 waves)
+__device__ inline u128 block256_incl_scan(u128 x, u128 *ws)
 {
-    const int hi_ = A.chunk_hub[blockIdx.x];
+    x = wave_incl_scan128(x);
+    if (lane_id() == WAVE - 1) ws[threadIdx.x / WAVE] = x;
+    __syncthreads();
+    u128 before = 0;
+    for (int w = 0; w < (int)(threadIdx.x / WAVE); w++) before += ws[w];
+    __syncthreads();
+    return x + before;
+}
+
+// one neighbour's record location, read once and reused for every entry
+struct NbrRec {
+    const uint64_t *rec;    // count words (low), after the keys
+    const uint64_t *bm;     // presence bitmap
+    uint32_t len;
+    bool wide;
+    int cu;
+};
+
+__device__ inline NbrRec nbr_load(const HubPreArgs &A, int hpp, int32_t u)
+{
+    NbrRec r{nullptr, nullptr, 0, false, 0};
+    if (u < 0) return r;
+    r.cu = A.g.colors[u];
+    if (hpp == 1) return r;
+    const LevelView &L = A.lev[hpp];
+    const Rec rr = rec_of(L, u);
+    r.len = rr.len;
+    r.wide = rr.wide;
+    r.bm = L.bm + (size_t)u * L.BW;
+    if (r.len) r.rec = rr.p + REC_HDR + rr.kw;
+    return r;
+}
+
+__device__ inline u128 nbr_count(const HubPreArgs &A, int hpp, const NbrRec &r, uint32_t key)
+{
+    if (hpp == 1) return key == (uint32_t)r.cu ? 1 : 0;
+    const int li = A.key_xidx[(size_t)r.cu * A.nkeys + key];
+    if (li < 0 || !r.len) return 0;
+    const uint64_t word = r.bm[li >> 6];
+    if (!((word >> (li & 63)) & 1ull)) return 0;
+    uint32_t pos = (uint32_t)__popcll(word & ((1ull << (li & 63)) - 1ull));
+    for (int q = 0; q < (li >> 6); q++) pos += (uint32_t)__popcll(r.bm[q]);
+    return mk128(r.rec[pos], r.wide ? r.rec[r.len + pos] : 0);
+}
+
+// pass 1: per (chunk of HUBPRE_CHUNK neighbours of a hub, level): the values of
+// every entry for every neighbour of the chunk, scanned within the chunk
+// (writes are coalesced along the neighbour axis); chunk totals go to `part`
+__global__ void __launch_bounds__(256) k_hubpre_chunk(HubPreArgs A)
+{
+    __shared__ uint32_t skey[192];
+    __shared__ u128 ws[256 / WAVE];
+    __shared__ u128 carry;
+    const int c = blockIdx.x;
+    const int q = A.chunk_hub[c];
     const int hpp = blockIdx.y + 1;
-    const int64_t x = A.hubs[hi_];
-    const int64_t ra = A.hub_rows[2 * hi_], rb = A.hub_rows[2 * hi_ + 1], d = rb - ra;
-    const int64_t a = A.chunk_e[blockIdx.x], b = min(rb, a + (int64_t)A.chunk);
+    const int64_t x = A.hubs[q];
     const int cx = A.g.colors[x];
-    if (A.zero && hpp == A.k - 1 && cx != 0) return;   // no block: x is never a root
-    const int WS = A.L->WS[hpp];
+    if (A.zero && hpp == A.k - 1 && cx != 0) return;   // no block: x is never a root there
+    const DevLut &L = *A.L;
+    const int WS = L.WS[hpp];
+    const int64_t ra = A.hub_rows[2 * q], rb = A.hub_rows[2 * q + 1], d = rb - ra;
+    const int64_t e0 = A.chunk_e[c], e1 = min(rb, e0 + (int64_t)A.chunk);
     const bool pw = hi64(A.M[hpp][x]) != 0;
-    uint64_t *plo = A.pre + A.poff[(size_t)hi_ * (SCC_KMAX + 1) + hpp];
+    uint64_t *plo = A.pre + A.poff[(size_t)q * (SCC_KMAX + 1) + hpp];
     uint64_t *phi = plo + (size_t)WS * d;
-    const int16_t *sidx = A.key_sidx + (size_t)cx * A.nkeys;
-    for (int64_t e = a + threadIdx.x; e < b; e += WAVE) {
-        const int32_t u = A.g.col_idx[e];
-        const int64_t j = e - ra;
-        if (hpp == 1) {
-            const int cu = A.g.colors[u];
-            if (cu != cx) plo[(size_t)(cu < cx ? cu : cu - 1) * d + j] = 1;
-            continue;
+    for (int t = threadIdx.x; t < WS; t += blockDim.x) {
+        const int rank = t / L.bk1[hpp], dc = t - rank * L.bk1[hpp];
+        const uint32_t C = expand_in(L.mask_s[hpp][dc], cx);
+        skey[t] = (uint32_t)(L.off[hpp] + rank * L.bk[hpp] + L.colex_k[C]);
+    }
+    int32_t u[4];
+    NbrRec nr[4];
+    for (int r = 0; r < 4; r++) {
+        const int64_t e = e0 + r * 256 + threadIdx.x;
+        u[r] = e < e1 ? A.g.col_idx[e] : -1;
+        nr[r] = nbr_load(A, hpp, u[r]);
+    }
+    __syncthreads();
+    for (int sidx = 0; sidx < WS; sidx++) {
+        const uint32_t key = skey[sidx];
+        u128 run = 0;
+        for (int r = 0; r < 4 && e0 + r * 256 < e1; r++) {
+            const u128 val = u[r] >= 0 ? nbr_count(A, hpp, nr[r], key) : (u128)0;
+            const u128 inc = block256_incl_scan(val, ws) + run;
+            const int64_t j = e0 + r * 256 + threadIdx.x - ra;
+            if (u[r] >= 0) {
+                plo[(size_t)sidx * d + j] = lo64(inc);
+                if (pw) phi[(size_t)sidx * d + j] = hi64(inc);
+            }
+            if (threadIdx.x == blockDim.x - 1) carry = inc;
+            __syncthreads();
+            run = carry;
+            __syncthreads();
         }
-        const LevelView &Lv = A.lev[hpp];
-        const uint32_t m = Lv.meta[u], len = META_LEN(m);
-        if (!len) continue;
-        const uint64_t *rec = Lv.pool + Lv.off[u];
-        const uint32_t kw = key_words(len);
-        for (uint32_t q = 0; q < len; q++) {
-            const int s = sidx[((const uint16_t *)rec)[q]];
-            if (s < 0) continue;
-            plo[(size_t)s * d + j] = rec[kw + q];
-            if (pw) phi[(size_t)s * d + j] = META_WIDE(m) ? rec[kw + len + q] : 0;
-        }
+        if (threadIdx.x == 0) A.part[(size_t)c * A.part_stride + L.soff[hpp] + sidx] = run;
     }
 }
 
-// in-place inclusive scan of one row (hub, level, entry) per workgroup
-__global__ void __launch_bounds__(256) k_hubpre_scan(HubPreArgs A)
+// pass 2: add the totals of a hub's earlier chunks to every later chunk
+__global__ void __launch_bounds__(256) k_hubpre_fix(HubPreArgs A)
 {
-    __shared__ u128 wsum[256 / WAVE];
-    __shared__ u128 carry;
-    const int hi_ = blockIdx.x;
-    int y = blockIdx.y, hpp = 1;
-    while (hpp < A.k - 1 && y >= A.L->WS[hpp]) { y -= A.L->WS[hpp]; hpp++; }
-    if (y >= A.L->WS[hpp]) return;
-    const int64_t x = A.hubs[hi_];
-    if (A.zero && hpp == A.k - 1 && A.g.colors[x] != 0) return;   // no block: x is never a root
-    const int64_t d = A.hub_rows[2 * hi_ + 1] - A.hub_rows[2 * hi_];
+    __shared__ u128 add[192];
+    const int c = blockIdx.x;
+    const int q = A.chunk_hub[c];
+    const int first = A.hub_first_chunk[q];
+    if (c == first) return;
+    const int hpp = blockIdx.y + 1;
+    const int64_t x = A.hubs[q];
+    if (A.zero && hpp == A.k - 1 && A.g.colors[x] != 0) return;
+    const DevLut &L = *A.L;
+    const int WS = L.WS[hpp];
+    const int64_t ra = A.hub_rows[2 * q], rb = A.hub_rows[2 * q + 1], d = rb - ra;
+    const int64_t e0 = A.chunk_e[c], e1 = min(rb, e0 + (int64_t)A.chunk);
     const bool pw = hi64(A.M[hpp][x]) != 0;
-    uint64_t *plo = A.pre + A.poff[(size_t)hi_ * (SCC_KMAX + 1) + hpp] + (size_t)y * d;
-    uint64_t *phi = plo + (size_t)A.L->WS[hpp] * d;
-    if (threadIdx.x == 0) carry = 0;
+    uint64_t *plo = A.pre + A.poff[(size_t)q * (SCC_KMAX + 1) + hpp];
+    uint64_t *phi = plo + (size_t)WS * d;
+    for (int t = threadIdx.x; t < WS; t += blockDim.x) {
+        u128 o = 0;
+        for (int cc = first; cc < c; cc++) o += A.part[(size_t)cc * A.part_stride + L.soff[hpp] + t];
+        add[t] = o;
+    }
     __syncthreads();
-    for (int64_t b0 = 0; b0 < d; b0 += blockDim.x) {
-        const int64_t j = b0 + threadIdx.x;
-        u128 xv = 0;
-        if (j < d) xv = mk128(plo[j], pw ? phi[j] : 0);
-        u128 inc = wave_incl_scan128(xv);
-        if (lane_id() == WAVE - 1) wsum[threadIdx.x / WAVE] = inc;
-        __syncthreads();
-        u128 before = carry;
-        for (int w = 0; w < (int)(threadIdx.x / WAVE); w++) before += wsum[w];
-        inc += before;
-        if (j < d) {
-            plo[j] = lo64(inc);
-            if (pw) phi[j] = hi64(inc);
-        }
-        __syncthreads();
-        if (threadIdx.x == blockDim.x - 1) carry = inc;
-        __syncthreads();
+    const int64_t len = e1 - e0;
+    for (int64_t i = threadIdx.x; i < (int64_t)WS * len; i += blockDim.x) {
+        const int sidx = (int)(i / len);
+        const int64_t j = e0 - ra + (i - (int64_t)sidx * len);
+        const u128 o = add[sidx];
+        const u128 cur = mk128(plo[(size_t)sidx * d + j], pw ? phi[(size_t)sidx * d + j] : 0);
+        const u128 nv = cur + o;
+        plo[(size_t)sidx * d + j] = lo64(nv);
+        if (pw) phi[(size_t)sidx * d + j] = hi64(nv);
     }
 }
 
@@ -363,11 +437,11 @@ __global__ void k_occ(GraphView g, const DevLut *Lp, LevelView lev_h, int h, int
     *out = record_lookup(lev_h, v, (uint32_t)key);
 }
 
-__global__ void k_len(int64_t n, const uint32_t *meta, int h1, const uint8_t *colors, uint64_t *len)
+__global__ void k_len(int64_t n, const uint64_t *loc, int h1, const uint8_t *colors, uint64_t *len)
 {
     int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
-    len[v] = h1 ? 1 : META_LEN(meta[v]);
+    len[v] = h1 ? 1 : LOC_LEN(loc[v]);
 }
 
 __global__ void __launch_bounds__(WAVE) k_export(int64_t n, LevelView Lv, int h1, const uint8_t *colors,
@@ -387,23 +461,20 @@ __global__ void __launch_bounds__(WAVE) k_export(int64_t n, LevelView Lv, int h1
         }
         return;
     }
-    const uint32_t m = Lv.meta[v], len = META_LEN(m);
-    const uint64_t start = end - len;
+    const Rec r = rec_of(Lv, v);
+    const uint64_t start = end - r.len;
     if (lane == 0) {
         off[v] = (int64_t)start;
         if (v == n - 1) off[n] = (int64_t)end;
     }
-    if (!len) return;
-    const uint64_t *rec = Lv.pool + Lv.off[v];
-    const uint32_t kw = key_words(len);
-    for (uint32_t e = lane; e < len; e += WAVE) {
-        key[start + e] = ((const uint16_t *)rec)[e];
-        lo[start + e] = rec[kw + e];
-        hi[start + e] = META_WIDE(m) ? rec[kw + len + e] : 0;
+    for (uint32_t e = lane; e < r.len; e += WAVE) {
+        key[start + e] = (uint16_t)r.key(e);
+        lo[start + e] = r.lo(e);
+        hi[start + e] = r.hi(e);
     }
 }
 
-LevelView lview(const TableLevel &l) { return LevelView{l.pool, l.off, l.meta, l.N, l.bm, l.BW}; }
+LevelView lview(const TableLevel &l) { return LevelView{l.pool, l.loc, l.bm, l.BW}; }
 
 }  // namespace
 
@@ -471,16 +542,18 @@ static scc_status ensure_hub_prefix(scc_table *T)
     if (nc == 0) { T->hubpre_ready = true; return SCC_OK; }
     std::vector<int32_t> hubs(nc);
     std::vector<int64_t> rows(2 * (size_t)nc), poff((size_t)nc * (SCC_KMAX + 1), 0);
-    std::vector<int32_t> ch;
+    std::vector<int32_t> ch, first(nc);
     std::vector<int64_t> ce;
     int64_t at = 0;
+    const int CH = 1024;
     for (int q = 0; q < nc; q++) {
         const int i = chosen[q];
         hubs[q] = T->hub_host[i];
         rows[2 * q] = T->hub_rows_host[2 * i];
         rows[2 * q + 1] = T->hub_rows_host[2 * i + 1];
         for (int h = 1; h < k; h++) { poff[(size_t)q * (SCC_KMAX + 1) + h] = at; at += block_words(i, h); }
-        for (int64_t e = rows[2 * q]; e < rows[2 * q + 1]; e += 1024) { ch.push_back(q); ce.push_back(e); }
+        first[q] = (int32_t)ch.size();
+        for (int64_t e = rows[2 * q]; e < rows[2 * q + 1]; e += CH) { ch.push_back(q); ce.push_back(e); }
     }
     T->hub_pre = (uint64_t *)T->alloc((size_t)at * 8 + 8);
     T->hub_poff = (int64_t *)T->alloc(poff.size() * 8);
@@ -489,9 +562,12 @@ static scc_status ensure_hub_prefix(scc_table *T)
     int64_t *drows = (int64_t *)get(rows.size() * 8);
     int32_t *dch = (int32_t *)get(ch.size() * 4);
     int64_t *dce = (int64_t *)get(ce.size() * 8);
-    if (!T->hub_pre || !T->hub_poff || !T->hub_index || !dhubs || !drows || !dch || !dce)
+    int32_t *dfirst = (int32_t *)get((size_t)nc * 4);
+    const int pstride = HL.soff[k];
+    u128 *dpart = (u128 *)get(ch.size() * (size_t)pstride * 16 + 16);
+    if (!T->hub_pre || !T->hub_poff || !T->hub_index || !dhubs || !drows || !dch || !dce || !dfirst || !dpart)
         return set_error(SCC_ENOMEM, "hub running sums (%lld bytes)", (long long)at * 8);
-    HIP_TRY(hipMemsetAsync(T->hub_pre, 0, (size_t)at * 8, st));
+    HIP_TRY(hipMemcpyAsync(dfirst, first.data(), (size_t)nc * 4, hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemsetAsync(T->hub_index, 0xff, (size_t)T->n * 4, st));
     HIP_TRY(hipMemcpyAsync(T->hub_poff, poff.data(), poff.size() * 8, hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(dhubs, hubs.data(), (size_t)nc * 4, hipMemcpyHostToDevice, st));
@@ -499,10 +575,11 @@ static scc_status ensure_hub_prefix(scc_table *T)
     HIP_TRY(hipMemcpyAsync(dch, ch.data(), ch.size() * 4, hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(dce, ce.data(), ce.size() * 8, hipMemcpyHostToDevice, st));
     A.hubs = dhubs; A.hub_rows = drows; A.poff = T->hub_poff; A.pre = T->hub_pre;
-    A.chunk_hub = dch; A.chunk_e = dce; A.chunk = 1024;
+    A.chunk_hub = dch; A.chunk_e = dce; A.chunk = CH; A.hub_first_chunk = dfirst;
+    A.key_xidx = T->key_xidx; A.part = dpart; A.part_stride = pstride;
     hipLaunchKernelGGL(k_hub_index, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, st, dhubs, nc, T->hub_index);
-    hipLaunchKernelGGL(k_hubpre_fill, dim3((unsigned)ch.size(), (unsigned)(k - 1)), dim3(WAVE), 0, st, A);
-    hipLaunchKernelGGL(k_hubpre_scan, dim3((unsigned)nc, (unsigned)HL.soff[k]), dim3(256), 0, st, A);
+    hipLaunchKernelGGL(k_hubpre_chunk, dim3((unsigned)ch.size(), (unsigned)(k - 1)), dim3(256), 0, st, A);
+    hipLaunchKernelGGL(k_hubpre_fix, dim3((unsigned)ch.size(), (unsigned)(k - 1)), dim3(256), 0, st, A);
     HIP_TRY(hipStreamSynchronize(st));
     HIP_TRY(hipGetLastError());
     T->hubpre_ready = true;
@@ -626,7 +703,7 @@ extern "C" scc_status scc_export_level(const scc_table *tc, int h, int64_t *nnz_
     }
     uint64_t *len = (uint64_t *)T->mem.get((size_t)n * 8);
     if (!len) return set_error(SCC_ENOMEM, "export scratch");
-    hipLaunchKernelGGL(k_len, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, T->lev[h].meta, h == 1, T->colors, len);
+    hipLaunchKernelGGL(k_len, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, T->lev[h].loc, h == 1, T->colors, len);
     hipStream_t keep = T->stream;
     T->stream = st;
     scc_status s = scan_u64(T, len, len, n);

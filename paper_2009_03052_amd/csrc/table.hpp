@@ -9,9 +9,7 @@
 struct TableLevel {
     uint64_t *pool = nullptr;   // packed records
     uint64_t pool_words = 0;
-    uint64_t *off = nullptr;    // [n] word offset of each record
-    uint32_t *meta = nullptr;   // [n] len | wide << 31
-    u128 *N = nullptr;          // [n] sum of the vertex's counts
+    uint64_t *loc = nullptr;    // [n] record locators
     int64_t nnz = 0;
     int64_t wide = 0;
     uint64_t *bm = nullptr;     // [n * BW] presence bitmaps over the dense level layout
