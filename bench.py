@@ -63,6 +63,26 @@ def cpu_baseline(full_m, samples):
     }
 
 
+def measured_traffic():
+    """HBM bytes per step of the gather kernels from the committed counter summary,
+    or None when the gather source changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "gather_mid_k6_hbm_traffic.txt")
+    src = os.path.join(ROOT, "paper_2009_03052_amd", "csrc", "dp.hip")
+    try:
+        fields = {}
+        for line in open(path):
+            parts = line.split()
+            if len(parts) >= 2:
+                fields[parts[0]] = parts[1]
+        cur = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        if fields.get("source_sha256") != cur:
+            return None
+        return float(fields["traffic_bytes_per_step"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -139,6 +159,7 @@ def main():
     gb = tab.gather_bytes()
     g_bytes = sum(gb[h] for h in range(2, k))
     achieved = g_bytes / (g_ms * 1e-3) / 1e9 if g_ms > 0 else 0.0
+    traffic = measured_traffic()
     out = {
         "metric": "DP table build s & colorful-treelet samples/sec, batched/served vs plain",
         "value": ns / dt,
@@ -153,7 +174,8 @@ def main():
         "level_ms": [round(info.level_ms[h], 3) for h in range(1, k + 1)],
         "table_bytes": int(info.bytes), "t": str(int(info.t[0]) | (int(info.t[1]) << 64)),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_unit": "bytes per step (4 gather launches), FETCH_SIZE x2.0 + WRITE_SIZE x1.0",
                      "kernel": "k_gather + k_gather_hub (neighbour-record gather of the DP, levels 2..k-1)",
                      "bytes_per_step": g_bytes, "ms_per_step": g_ms},
     }

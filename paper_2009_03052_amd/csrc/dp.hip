@@ -98,16 +98,25 @@ struct GatherArgs {
     int *err;
 };
 
-// Adds the level-hs entries of neighbours col_idx[a..b) of v into the LDS sums.
-__device__ inline void gather_range(const GatherArgs &A, int cv, int64_t a, int64_t b, bool wideS,
+// Adds the level-hs entries of neighbours col_idx[a..b) of v into the LDS sums
+// and returns (in every lane) the saturating sum of those neighbours' level
+// sums N. With wideS false only low words are added: exact whenever that
+// returned bound is below 2^64, since every entry and every partial sum is
+// at most the bound.
+__device__ inline u128 gather_range(const GatherArgs &A, int cv, int64_t a, int64_t b, bool wideS,
                                     uint64_t *acc_lo, uint64_t *acc_hi)
 {
     const int lane = threadIdx.x;
     const int16_t *sidx = A.key_sidx + (size_t)cv * A.nkeys;
+    u128 m = 0;
     for (int64_t base = a; base < b; base += WAVE) {
         const int64_t e = base + lane;
         const uint64_t lc = e < b ? A.L.loc[A.g.col_idx[e]] : 0ull;
         const uint32_t len = LOC_LEN(lc);
+        if (len) {
+            const uint64_t *hdr = A.L.pool + LOC_OFF(lc);
+            m = sat_add(m, mk128(hdr[0], hdr[1]));
+        }
         const uint32_t incl = wave_incl_scan32(len);
         const uint32_t total = __shfl(incl, WAVE - 1, WAVE);
         // entries of this chunk of neighbours, flattened over the lanes
@@ -145,6 +154,28 @@ __device__ inline void gather_range(const GatherArgs &A, int cv, int64_t a, int6
             }
         }
     }
+    return wave_satsum128(m);
+}
+
+// LDS sums of the neighbours in [a, b): 64-bit pass first, a 128-bit pass only
+// when the bound says 64 bits may not suffice
+__device__ inline u128 gather_sums(const GatherArgs &A, int cv, int64_t a, int64_t b, uint64_t *acc_lo,
+                                   uint64_t *acc_hi, bool &wideS)
+{
+    const int lane = threadIdx.x;
+    const int WS = A.WS;
+    for (int i = lane; i < WS; i += WAVE) { acc_lo[i] = 0; acc_hi[i] = 0; }
+    __syncthreads();
+    u128 m = gather_range(A, cv, a, b, false, acc_lo, acc_hi);
+    wideS = hi64(m) != 0;
+    if (wideS) {
+        __syncthreads();
+        for (int i = lane; i < WS; i += WAVE) { acc_lo[i] = 0; acc_hi[i] = 0; }
+        __syncthreads();
+        m = gather_range(A, cv, a, b, true, acc_lo, acc_hi);
+    }
+    __syncthreads();
+    return m;
 }
 
 __device__ inline void gather_vertex(const GatherArgs &A, int64_t v, uint64_t *sm)
@@ -154,18 +185,12 @@ __device__ inline void gather_vertex(const GatherArgs &A, int64_t v, uint64_t *s
     if (A.rows_zero && cv != 0) return;
     const int64_t a = A.g.row_ptr[v], b = A.g.row_ptr[v + 1];
     if (b - a > A.hub_degree) return;      // hub rows have their own kernels
-    // bound: every entry of S_hs(v) is at most M_hs(v)
-    u128 m = 0;
-    for (int64_t e = a + lane; e < b; e += WAVE) m = sat_add(m, rec_of(A.L, A.g.col_idx[e]).N());
-    m = wave_satsum128(m);
-    const bool wideS = hi64(m) != 0;
     const int WS = A.WS;
     uint64_t *acc_lo = sm;
     uint64_t *acc_hi = sm + WS;
-    for (int i = lane; i < WS; i += WAVE) { acc_lo[i] = 0; acc_hi[i] = 0; }
-    __syncthreads();
-    gather_range(A, cv, a, b, wideS, acc_lo, acc_hi);
-    __syncthreads();
+    bool wideS;
+    // bound: every entry of S_hs(v) is at most M_hs(v)
+    const u128 m = gather_sums(A, cv, a, b, acc_lo, acc_hi, wideS);
     uint64_t *Slo = A.Slo + (size_t)v * WS;
     for (int i = lane; i < WS; i += WAVE) Slo[i] = acc_lo[i];
     if (wideS) {
@@ -184,26 +209,27 @@ __global__ void __launch_bounds__(WAVE) k_gather(GatherArgs A)
     }
 }
 
-// hub rows, step 1: the bound M_hs(v) and cleared sums
+// hub rows, step 1: cleared sums and bound
 __global__ void __launch_bounds__(256) k_hub_prepare(GatherArgs A, const int32_t *hubs)
 {
-    __shared__ u128 part[256 / WAVE];
     const int64_t v = hubs[blockIdx.x];
-    const int64_t a = A.g.row_ptr[v], b = A.g.row_ptr[v + 1];
-    u128 m = 0;
-    for (int64_t e = a + threadIdx.x; e < b; e += blockDim.x) m = sat_add(m, rec_of(A.L, A.g.col_idx[e]).N());
-    m = wave_satsum128(m);
-    if (lane_id() == 0) part[threadIdx.x / WAVE] = m;
     for (int i = threadIdx.x; i < A.WS; i += blockDim.x) {
         A.Slo[(size_t)v * A.WS + i] = 0;
         A.Shi[(size_t)v * A.WS + i] = 0;
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        u128 t = 0;
-        for (int w = 0; w < (int)(blockDim.x / WAVE); w++) t = sat_add(t, part[w]);
-        A.M[v] = t;
-    }
+    if (threadIdx.x == 0) A.M[v] = 0;
+}
+
+// adds a 128-bit value to a 128-bit word pair with device atomics; returns
+// true when the sum leaves 128 bits
+__device__ inline bool atomic_add128(unsigned long long *lo_w, unsigned long long *hi_w, uint64_t lo, uint64_t hi)
+{
+    const unsigned long long old = atomicAdd(lo_w, (unsigned long long)lo);
+    const uint64_t carry = (old + lo) < old ? 1u : 0u;
+    const uint64_t add = hi + carry;
+    if (add == 0 && !(hi != 0 && carry)) return false;
+    const unsigned long long oldh = atomicAdd(hi_w, (unsigned long long)add);
+    return (oldh + add) < oldh || (carry && hi == ~0ull);
 }
 
 // hub rows, step 2: one wave per chunk of HUB_CHUNK neighbours, merged with atomics
@@ -215,27 +241,24 @@ __global__ void __launch_bounds__(WAVE) k_gather_hub(GatherArgs A, int chunk)
     const int64_t b = min(A.g.row_ptr[v + 1], a + (int64_t)chunk);
     const int lane = threadIdx.x;
     const int cv = A.g.colors[v];
-    const bool wideS = hi64(A.M[v]) != 0;
     const int WS = A.WS;
     uint64_t *acc_lo = sm;
     uint64_t *acc_hi = sm + WS;
-    for (int i = lane; i < WS; i += WAVE) { acc_lo[i] = 0; acc_hi[i] = 0; }
-    __syncthreads();
-    gather_range(A, cv, a, b, wideS, acc_lo, acc_hi);
-    __syncthreads();
+    bool wideS;
+    const u128 m = gather_sums(A, cv, a, b, acc_lo, acc_hi, wideS);
     unsigned long long *Slo = (unsigned long long *)(A.Slo + (size_t)v * WS);
     unsigned long long *Shi = (unsigned long long *)(A.Shi + (size_t)v * WS);
+    bool over = false;
     for (int i = lane; i < WS; i += WAVE) {
         const uint64_t lo = acc_lo[i], hi = acc_hi[i];
-        if (!lo && !hi) continue;
-        if (!wideS) {
-            atomicAdd(&Slo[i], (unsigned long long)lo);
-        } else {
-            const unsigned long long old = atomicAdd(&Slo[i], (unsigned long long)lo);
-            const uint64_t carry = (old + lo) < old ? 1u : 0u;
-            if (hi + carry) atomicAdd(&Shi[i], (unsigned long long)(hi + carry));
-        }
+        if (lo || hi) over |= atomic_add128(&Slo[i], &Shi[i], lo, hi);
     }
+    if (lane == 0) {
+        unsigned long long *Mw = (unsigned long long *)&A.M[v];
+        over |= atomic_add128(&Mw[0], &Mw[1], lo64(m), hi64(m));
+        if (m == ~(u128)0) over = true;
+    }
+    if (over) atomicOr(A.err, 2);   // the bound left 128 bits: the build reports overflow
 }
 
 // algorithmic bytes of one gather launch (for reports): 4 d_v + neighbours'
@@ -795,7 +818,7 @@ static scc_status build_levels(scc_table *T)
             const size_t lds = (size_t)2 * HL.WS[hs] * 8;
             HIP_TRY(hipEventRecord(g0, st));
             if (nhub) {
-                hipLaunchKernelGGL(k_hub_prepare, dim3((unsigned)nhub), dim3(256), 0, st, G, hubs);
+                hipLaunchKernelGGL(k_hub_prepare, dim3((unsigned)nhub), dim3(WAVE), 0, st, G, hubs);
                 hipLaunchKernelGGL(k_gather_hub, dim3((unsigned)nchunk), dim3(WAVE), lds, st, G, T->hub_chunk);
             }
             if (n) hipLaunchKernelGGL(k_gather, dim3((unsigned)n), dim3(WAVE), lds, st, G);
@@ -819,7 +842,8 @@ static scc_status build_levels(scc_table *T)
         // record sizes, offsets, pack
         if (n) hipLaunchKernelGGL(k_words, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, meta, words);
         HIP_TRY(hipStreamSynchronize(st));
-        if (herr[0]) return set_error(SCC_EOVERFLOW, "a level-%d count needs more than %d bits", h, T->max_bits);
+        if (herr[0] & 1) return set_error(SCC_EOVERFLOW, "a level-%d count needs more than %d bits", h, T->max_bits);
+        if (herr[0] & 2) return set_error(SCC_EOVERFLOW, "a level-%d neighbour sum may exceed 128 bits", h);
         if (hs >= 2) {
             float ms = 0;
             HIP_TRY(hipEventElapsedTime(&ms, g0, g1));
