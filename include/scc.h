@@ -235,6 +235,51 @@ scc_status scc_ags(const scc_table *t, int64_t cbar, int64_t round_size, int64_t
    DFS bitstring among their rootings. */
 int scc_num_unrooted(int k);
 
+/* One instance of a batched build: a graph (device pointers, as for
+   scc_build_table), its colours and its k. */
+typedef struct {
+    scc_csr g;
+    const uint8_t *colors;
+    int k;
+} scc_instance;
+
+typedef struct {
+    int tile;          /* vertices per work item; 0 = tuned or default (256) */
+    int hub_degree;    /* rows above this degree are gathered in chunks; 0 = tuned or default (1024) */
+    int autotune;      /* nonzero: when no choice is given and none is cached for a batch of the
+                          same shape, time candidate (tile, hub_degree) pairs on this batch and
+                          keep the fastest for later batches of the same shape */
+} scc_batch_opts;
+
+typedef struct {
+    int tile, hub_degree;      /* the schedule used */
+    int tuned;                 /* 1 when it came from the autotuner (now or cached) */
+    int grid;                  /* resident workgroups of the persistent launch */
+    int64_t items;             /* work items */
+    double launch_ms;          /* device time of the persistent launch */
+    double pack_ms;            /* host-observed time of packing and totals */
+    double total_ms;           /* launch + pack (excludes setup and tuning) */
+    double setup_ms;           /* allocation, lookup tables and tuning probes */
+    int nprobe;
+    int probe_tile[16], probe_hub[16];
+    double probe_ms[16];
+} scc_batch_report;
+
+/*
+ * scc_build_batch -- the build-up phase (Sec. 2.1, Eq. (1)) of many instances
+ * (graphs x colourings x k) in one persistent launch. The multi-threaded
+ * build of Sec. 3.4 assigns vertices to a thread pool; here vertex tiles of
+ * every instance and level are work items of one resident grid, ordered so
+ * that an item only waits for earlier ones. Each out[i] receives a table equal
+ * to what scc_build_table would build for instance i with the same options
+ * (bit for bit). opt applies to every instance (rooting, max_bits, stream,
+ * allocator; hub_degree and validate are ignored: the schedule decides the
+ * former). bopt and rep may be NULL. Errors as for scc_build_table; on error
+ * no table is returned.
+ */
+scc_status scc_build_batch(const scc_instance *inst, int n_inst, const scc_build_opts *opt,
+                           const scc_batch_opts *bopt, scc_table **out, scc_batch_report *rep);
+
 /* Frees per-k device lookup tables kept by scc_classify. */
 void scc_release_caches(void);
 

@@ -46,6 +46,27 @@ class _BuildOpts(C.Structure):
                 ("alloc", C.POINTER(_Allocator)), ("hub_degree", C.c_int), ("validate", C.c_int)]
 
 
+class _Instance(C.Structure):
+    _fields_ = [("g", _Csr), ("colors", C.c_void_p), ("k", C.c_int)]
+
+
+class _BatchOpts(C.Structure):
+    _fields_ = [("tile", C.c_int), ("hub_degree", C.c_int), ("autotune", C.c_int)]
+
+
+class BatchReport(C.Structure):
+    _fields_ = [("tile", C.c_int), ("hub_degree", C.c_int), ("tuned", C.c_int), ("grid", C.c_int),
+                ("items", C.c_int64), ("launch_ms", C.c_double), ("pack_ms", C.c_double),
+                ("total_ms", C.c_double), ("setup_ms", C.c_double), ("nprobe", C.c_int),
+                ("probe_tile", C.c_int * 16), ("probe_hub", C.c_int * 16), ("probe_ms", C.c_double * 16)]
+
+    def as_dict(self):
+        return {"tile": self.tile, "hub_degree": self.hub_degree, "tuned": bool(self.tuned), "grid": self.grid,
+                "items": self.items, "launch_ms": self.launch_ms, "pack_ms": self.pack_ms,
+                "total_ms": self.total_ms, "setup_ms": self.setup_ms,
+                "probes": [(self.probe_tile[i], self.probe_hub[i], self.probe_ms[i]) for i in range(self.nprobe)]}
+
+
 class TableInfo(C.Structure):
     _fields_ = [("n", C.c_int64), ("k", C.c_int), ("rooting", C.c_int), ("num_unrooted", C.c_int),
                 ("nnz", C.c_int64 * 9), ("wide_vertices", C.c_int64 * 9), ("bytes", C.c_int64),
@@ -66,6 +87,8 @@ _SIGS = {
     "scc_classify": (C.c_int, [_P, _P, _i64, _P, _P, _P]),
     "scc_catalog": (C.c_int, [C.c_int, C.POINTER(_i64), _P, _P, _P, _P]),
     "scc_ags": (C.c_int, [_P, _i64, _i64, _i64, _u64, _u64, _P, _P, _P, _P, C.POINTER(_i64), _P]),
+    "scc_build_batch": (C.c_int, [C.POINTER(_Instance), C.c_int, C.POINTER(_BuildOpts), C.POINTER(_BatchOpts),
+                                  C.POINTER(_P), C.POINTER(BatchReport)]),
     "scc_release_caches": (None, []),
     "scc_num_unrooted": (C.c_int, [C.c_int]),
     "scc_last_error": (C.c_char_p, []),
@@ -158,6 +181,12 @@ class Table:
         self._h = _P()
         _check(_lib.scc_build_table(C.byref(csr), _ptr(self.colors), k, C.byref(opts), C.byref(self._h)))
 
+    @classmethod
+    def _wrap(cls, handle, graph, colors, k):
+        t = cls.__new__(cls)
+        t.graph, t.colors, t.k, t._stream, t._h = graph, colors, k, None, _P(handle)
+        return t
+
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             _lib.scc_table_destroy(self._h)
@@ -242,6 +271,28 @@ class Table:
                             hits.ctypes.data_as(_P), w.ctypes.data_as(_P), nj.ctypes.data_as(_P),
                             shapes.ctypes.data_as(_P), C.byref(nr), _stream_ptr(stream)))
         return {"hits": hits, "w": w, "n_j": nj, "round_shapes": shapes[:nr.value]}
+
+
+def build_batch(instances, rooting: int = ROOT_ZERO, max_bits: int = 128, tile: int = 0, hub_degree: int = 0,
+                autotune: bool = False, stream=None, use_torch_allocator: bool = True):
+    """``scc_build_batch``: instances is a list of (DeviceGraph, colours, k).
+    Returns ([Table], report dict)."""
+    n = len(instances)
+    arr = (_Instance * n)()
+    keep = []
+    for i, (g, colors, k) in enumerate(instances):
+        col = torch.as_tensor(np.asarray(colors) if not torch.is_tensor(colors) else colors,
+                              dtype=torch.uint8).to(g.row_ptr.device).contiguous()
+        keep.append(col)
+        arr[i] = _Instance(_Csr(g.n, g.nnz, g.row_ptr.data_ptr(), g.col_idx.data_ptr()), col.data_ptr(), k)
+    opts = _BuildOpts(rooting, max_bits, _stream_ptr(stream),
+                      C.pointer(TORCH_ALLOCATOR) if use_torch_allocator else None, 0, 0)
+    bo = _BatchOpts(tile, hub_degree, 1 if autotune else 0)
+    outs = (_P * n)()
+    rep = BatchReport()
+    _check(_lib.scc_build_batch(arr, n, C.byref(opts), C.byref(bo), outs, C.byref(rep)))
+    tables = [Table._wrap(outs[i], instances[i][0], keep[i], instances[i][2]) for i in range(n)]
+    return tables, rep.as_dict()
 
 
 def num_classes(k: int) -> int:

@@ -20,6 +20,8 @@
 
 #include "table.hpp"
 
+#include <map>
+
 namespace {
 
 constexpr int MAXR = 7;    // ceil(max W_h / 64): W_h <= 420 for k <= 8
@@ -55,10 +57,9 @@ __global__ void k_validate(GraphView g, int k, int *err)
 // ---------------------------------------------------------------------------
 // Level-1 neighbour sums: S_1(v)[j] = number of neighbours of colour j != c_v
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(WAVE) k_gather1(GraphView g, int k, uint64_t *S1, u128 *M1)
+__device__ inline void gather1_vertex(const GraphView &g, int k, uint64_t *S1, u128 *M1, int64_t v, unsigned *cnt)
 {
-  __shared__ unsigned cnt[SCC_KMAX];
-  for (int64_t v = blockIdx.x; v < g.n; v += gridDim.x) {
+  {
     const int lane = threadIdx.x;
     const int cv = g.colors[v];
     if (lane < SCC_KMAX) cnt[lane] = 0;
@@ -79,6 +80,12 @@ __global__ void __launch_bounds__(WAVE) k_gather1(GraphView g, int k, uint64_t *
   }
 }
 
+__global__ void __launch_bounds__(WAVE) k_gather1(GraphView g, int k, uint64_t *S1, u128 *M1)
+{
+    __shared__ unsigned cnt[SCC_KMAX];
+    for (int64_t v = blockIdx.x; v < g.n; v += gridDim.x) gather1_vertex(g, k, S1, M1, v, cnt);
+}
+
 // ---------------------------------------------------------------------------
 // Gather (the DP join): S_hs(v) = sum over neighbours of their level-hs records,
 // plus the bound M_hs(v) = sum_{u~v} N_hs(u) that decides 64- or 128-bit sums.
@@ -86,10 +93,64 @@ __global__ void __launch_bounds__(WAVE) k_gather1(GraphView g, int k, uint64_t *
 // Larger rows: their neighbour list is cut into chunks of HUB_CHUNK, each chunk
 // reduced in LDS by one wave and merged into the row with global atomics.
 // ---------------------------------------------------------------------------
+// Records of one level seen by the gather and the combine: either the packed
+// pool (locators + records with a header) or, inside a batched launch, the
+// fixed-capacity per-vertex slots the combine writes (meta = len | wide << 31).
+// A per-vertex 64-bit handle carries what the accessors need: the locator, or
+// (vertex << 32 | meta).
+struct LevelSrc {
+    LevelView P;
+    const uint16_t *skey;
+    const uint64_t *slo, *shi;
+    const uint32_t *meta;
+    const u128 *N;
+    int W;
+};
+
+template <bool SLOTS> __device__ inline uint64_t src_handle(const LevelSrc &S, int64_t u)
+{
+    if (SLOTS) return ((uint64_t)u << 32) | S.meta[u];
+    return S.P.loc[u];
+}
+template <bool SLOTS> __device__ inline uint32_t h_len(uint64_t h) { return SLOTS ? META_LEN((uint32_t)h) : LOC_LEN(h); }
+template <bool SLOTS> __device__ inline bool h_wide(uint64_t h) { return SLOTS ? META_WIDE((uint32_t)h) != 0 : LOC_WIDE(h) != 0; }
+template <bool SLOTS> __device__ inline u128 h_N(const LevelSrc &S, uint64_t h)
+{
+    if (SLOTS) return h_len<true>(h) ? S.N[h >> 32] : (u128)0;
+    if (!LOC_LEN(h)) return 0;
+    const uint64_t *p = S.P.pool + LOC_OFF(h);
+    return mk128(p[0], p[1]);
+}
+// keys, low and high words of the entries of the record with handle h
+template <bool SLOTS> struct RecView {
+    const uint16_t *key;
+    const uint64_t *lo, *hi;   // hi is null for a 64-bit record
+    uint32_t len;
+};
+template <bool SLOTS> __device__ inline RecView<SLOTS> h_rec(const LevelSrc &S, uint64_t h)
+{
+    RecView<SLOTS> r;
+    r.len = h_len<SLOTS>(h);
+    const bool wide = h_wide<SLOTS>(h);
+    if (SLOTS) {
+        const size_t base = (size_t)(h >> 32) * S.W;
+        r.key = S.skey + base;
+        r.lo = S.slo + base;
+        r.hi = wide ? S.shi + base : nullptr;
+    } else {
+        const uint64_t *p = S.P.pool + LOC_OFF(h) + REC_HDR;
+        const uint32_t kw = key_words(r.len);
+        r.key = (const uint16_t *)p;
+        r.lo = p + kw;
+        r.hi = wide ? p + kw + r.len : nullptr;
+    }
+    return r;
+}
+
 struct GatherArgs {
     GraphView g;
     int k, nkeys, WS, rows_zero, hub_degree;
-    LevelView L;
+    LevelSrc L;
     u128 *M;                       // out: M_hs (regular rows); in: hub rows
     const int16_t *key_sidx;       // [k * nkeys]
     uint64_t *Slo, *Shi;           // [n * WS]
@@ -103,6 +164,7 @@ struct GatherArgs {
 // sums N. With wideS false only low words are added: exact whenever that
 // returned bound is below 2^64, since every entry and every partial sum is
 // at most the bound.
+template <bool SLOTS>
 __device__ inline u128 gather_range(const GatherArgs &A, int cv, int64_t a, int64_t b, bool wideS,
                                     uint64_t *acc_lo, uint64_t *acc_hi)
 {
@@ -111,12 +173,9 @@ __device__ inline u128 gather_range(const GatherArgs &A, int cv, int64_t a, int6
     u128 m = 0;
     for (int64_t base = a; base < b; base += WAVE) {
         const int64_t e = base + lane;
-        const uint64_t lc = e < b ? A.L.loc[A.g.col_idx[e]] : 0ull;
-        const uint32_t len = LOC_LEN(lc);
-        if (len) {
-            const uint64_t *hdr = A.L.pool + LOC_OFF(lc);
-            m = sat_add(m, mk128(hdr[0], hdr[1]));
-        }
+        const uint64_t hd = e < b ? src_handle<SLOTS>(A.L, A.g.col_idx[e]) : (SLOTS ? ~0ull << 32 : 0ull);
+        const uint32_t len = e < b ? h_len<SLOTS>(hd) : 0u;
+        if (len) m = sat_add(m, h_N<SLOTS>(A.L, hd));
         const uint32_t incl = wave_incl_scan32(len);
         const uint32_t total = __shfl(incl, WAVE - 1, WAVE);
         // entries of this chunk of neighbours, flattened over the lanes
@@ -132,20 +191,17 @@ __device__ inline u128 gather_range(const GatherArgs &A, int cv, int64_t a, int6
             }
             if (j > WAVE - 1) j = WAVE - 1;
             const uint32_t incl_j = __shfl(incl, j, WAVE);
-            const uint64_t lc_j = shfl64(lc, j);
+            const uint64_t hd_j = shfl64(hd, j);
             if (p < total) {
-                const uint32_t len_j = LOC_LEN(lc_j);
-                const uint32_t ei = p - (incl_j - len_j);
-                const uint64_t *rec = A.L.pool + LOC_OFF(lc_j) + REC_HDR;
-                const uint32_t kw = key_words(len_j);
-                const uint32_t key = ((const uint16_t *)rec)[ei];
-                const uint64_t cl = rec[kw + ei];
-                const int s = sidx[key];
+                const RecView<SLOTS> r = h_rec<SLOTS>(A.L, hd_j);
+                const uint32_t ei = p - (incl_j - r.len);
+                const uint64_t cl = r.lo[ei];
+                const int s = sidx[r.key[ei]];
                 if (s >= 0) {
                     if (!wideS) {
                         atomicAdd((unsigned long long *)&acc_lo[s], (unsigned long long)cl);
                     } else {
-                        const uint64_t ch = LOC_WIDE(lc_j) ? rec[kw + len_j + ei] : 0;
+                        const uint64_t ch = r.hi ? r.hi[ei] : 0;
                         const unsigned long long old = atomicAdd((unsigned long long *)&acc_lo[s], (unsigned long long)cl);
                         const uint64_t carry = (old + cl) < old ? 1u : 0u;
                         if (ch + carry) atomicAdd((unsigned long long *)&acc_hi[s], (unsigned long long)(ch + carry));
@@ -159,6 +215,7 @@ __device__ inline u128 gather_range(const GatherArgs &A, int cv, int64_t a, int6
 
 // LDS sums of the neighbours in [a, b): 64-bit pass first, a 128-bit pass only
 // when the bound says 64 bits may not suffice
+template <bool SLOTS>
 __device__ inline u128 gather_sums(const GatherArgs &A, int cv, int64_t a, int64_t b, uint64_t *acc_lo,
                                    uint64_t *acc_hi, bool &wideS)
 {
@@ -166,18 +223,19 @@ __device__ inline u128 gather_sums(const GatherArgs &A, int cv, int64_t a, int64
     const int WS = A.WS;
     for (int i = lane; i < WS; i += WAVE) { acc_lo[i] = 0; acc_hi[i] = 0; }
     __syncthreads();
-    u128 m = gather_range(A, cv, a, b, false, acc_lo, acc_hi);
+    u128 m = gather_range<SLOTS>(A, cv, a, b, false, acc_lo, acc_hi);
     wideS = hi64(m) != 0;
     if (wideS) {
         __syncthreads();
         for (int i = lane; i < WS; i += WAVE) { acc_lo[i] = 0; acc_hi[i] = 0; }
         __syncthreads();
-        m = gather_range(A, cv, a, b, true, acc_lo, acc_hi);
+        m = gather_range<SLOTS>(A, cv, a, b, true, acc_lo, acc_hi);
     }
     __syncthreads();
     return m;
 }
 
+template <bool SLOTS>
 __device__ inline void gather_vertex(const GatherArgs &A, int64_t v, uint64_t *sm)
 {
     const int lane = threadIdx.x;
@@ -190,7 +248,7 @@ __device__ inline void gather_vertex(const GatherArgs &A, int64_t v, uint64_t *s
     uint64_t *acc_hi = sm + WS;
     bool wideS;
     // bound: every entry of S_hs(v) is at most M_hs(v)
-    const u128 m = gather_sums(A, cv, a, b, acc_lo, acc_hi, wideS);
+    const u128 m = gather_sums<SLOTS>(A, cv, a, b, acc_lo, acc_hi, wideS);
     uint64_t *Slo = A.Slo + (size_t)v * WS;
     for (int i = lane; i < WS; i += WAVE) Slo[i] = acc_lo[i];
     if (wideS) {
@@ -204,20 +262,24 @@ __global__ void __launch_bounds__(WAVE) k_gather(GatherArgs A)
 {
     extern __shared__ uint64_t sm[];
     for (int64_t v = blockIdx.x; v < A.g.n; v += gridDim.x) {
-        gather_vertex(A, v, sm);
+        gather_vertex<false>(A, v, sm);
         __syncthreads();
     }
 }
 
 // hub rows, step 1: cleared sums and bound
-__global__ void __launch_bounds__(256) k_hub_prepare(GatherArgs A, const int32_t *hubs)
+__device__ inline void hub_zero(const GatherArgs &A, int64_t v)
 {
-    const int64_t v = hubs[blockIdx.x];
     for (int i = threadIdx.x; i < A.WS; i += blockDim.x) {
         A.Slo[(size_t)v * A.WS + i] = 0;
         A.Shi[(size_t)v * A.WS + i] = 0;
     }
     if (threadIdx.x == 0) A.M[v] = 0;
+}
+
+__global__ void __launch_bounds__(WAVE) k_hub_prepare(GatherArgs A, const int32_t *hubs)
+{
+    hub_zero(A, hubs[blockIdx.x]);
 }
 
 // adds a 128-bit value to a 128-bit word pair with device atomics; returns
@@ -232,20 +294,17 @@ __device__ inline bool atomic_add128(unsigned long long *lo_w, unsigned long lon
     return (oldh + add) < oldh || (carry && hi == ~0ull);
 }
 
-// hub rows, step 2: one wave per chunk of HUB_CHUNK neighbours, merged with atomics
-__global__ void __launch_bounds__(WAVE) k_gather_hub(GatherArgs A, int chunk)
+// hub rows, step 2: one wave per chunk of neighbours, merged with atomics
+template <bool SLOTS>
+__device__ inline void hub_chunk(const GatherArgs &A, int64_t v, int64_t a, int64_t b, uint64_t *sm)
 {
-    extern __shared__ uint64_t sm[];
-    const int64_t v = A.chunk_v[blockIdx.x];
-    const int64_t a = A.chunk_e[blockIdx.x];
-    const int64_t b = min(A.g.row_ptr[v + 1], a + (int64_t)chunk);
     const int lane = threadIdx.x;
     const int cv = A.g.colors[v];
     const int WS = A.WS;
     uint64_t *acc_lo = sm;
     uint64_t *acc_hi = sm + WS;
     bool wideS;
-    const u128 m = gather_sums(A, cv, a, b, acc_lo, acc_hi, wideS);
+    const u128 m = gather_sums<SLOTS>(A, cv, a, b, acc_lo, acc_hi, wideS);
     unsigned long long *Slo = (unsigned long long *)(A.Slo + (size_t)v * WS);
     unsigned long long *Shi = (unsigned long long *)(A.Shi + (size_t)v * WS);
     bool over = false;
@@ -259,6 +318,15 @@ __global__ void __launch_bounds__(WAVE) k_gather_hub(GatherArgs A, int chunk)
         if (m == ~(u128)0) over = true;
     }
     if (over) atomicOr(A.err, 2);   // the bound left 128 bits: the build reports overflow
+}
+
+__global__ void __launch_bounds__(WAVE) k_gather_hub(GatherArgs A, int chunk)
+{
+    extern __shared__ uint64_t sm[];
+    const int64_t v = A.chunk_v[blockIdx.x];
+    const int64_t a = A.chunk_e[blockIdx.x];
+    const int64_t b = min(A.g.row_ptr[v + 1], a + (int64_t)chunk);
+    hub_chunk<false>(A, v, a, b, sm);
 }
 
 // algorithmic bytes of one gather launch (for reports): 4 d_v + neighbours'
@@ -302,7 +370,7 @@ struct CombineArgs {
     GraphView g;
     const DevLut *L;
     int h, zero_only, max_bits;
-    LevelView lev[SCC_KMAX + 1];          // own levels 2..h-1
+    LevelSrc lev[SCC_KMAX + 1];           // own levels 2..h-1
     const uint64_t *Slo[SCC_KMAX + 1];    // neighbour sums 1..h-1
     const uint64_t *Shi[SCC_KMAX + 1];
     const u128 *M[SCC_KMAX + 1];
@@ -315,6 +383,7 @@ struct CombineArgs {
     int *err;                             // [0]: overflow
 };
 
+template <bool SLOTS>
 __device__ inline void combine_vertex(const CombineArgs &A, int64_t v, uint64_t *sm)
 {
     const DevLut &L = *A.L;
@@ -328,7 +397,7 @@ __device__ inline void combine_vertex(const CombineArgs &A, int64_t v, uint64_t 
     // per-vertex bound: U >= sum over (T, C) of beta_T c(T_C, v) >= every partial sum
     u128 U = 0;
     for (int hp = 1; hp < h; hp++) {
-        u128 Nv = hp == 1 ? (u128)1 : rec_of(A.lev[hp], v).N();
+        u128 Nv = hp == 1 ? (u128)1 : h_N<SLOTS>(A.lev[hp], src_handle<SLOTS>(A.lev[hp], v));
         U = sat_add(U, sat_mul(Nv, A.M[h - hp][v]));
     }
     if (U == ~(u128)0 || bitlen128(U) > A.max_bits) {
@@ -343,11 +412,11 @@ __device__ inline void combine_vertex(const CombineArgs &A, int64_t v, uint64_t 
     if (lane == 0) Xlo[L.xoff[1]] = 1;   // level 1: the single node, coloured c_v
     const int16_t *xidx = A.key_xidx + (size_t)cv * L.nkeys;
     for (int hp = 2; hp < h; hp++) {
-        const Rec r = rec_of(A.lev[hp], v);
+        const RecView<SLOTS> r = h_rec<SLOTS>(A.lev[hp], src_handle<SLOTS>(A.lev[hp], v));
         for (uint32_t e = lane; e < r.len; e += WAVE) {
-            const int x = L.xoff[hp] + xidx[r.key(e)];
-            Xlo[x] = r.lo(e);
-            Xhi[x] = r.hi(e);
+            const int x = L.xoff[hp] + xidx[r.key[e]];
+            Xlo[x] = r.lo[e];
+            Xhi[x] = r.hi ? r.hi[e] : 0;
         }
     }
     for (int hs = 1; hs < h; hs++) {
@@ -429,7 +498,7 @@ __global__ void __launch_bounds__(WAVE) k_combine(CombineArgs A)
 {
     extern __shared__ uint64_t sm[];
     for (int64_t v = blockIdx.x; v < A.g.n; v += gridDim.x) {
-        combine_vertex(A, v, sm);
+        combine_vertex<false>(A, v, sm);
         __syncthreads();
     }
 }
@@ -685,6 +754,13 @@ LevelView view(const TableLevel &l)
     return LevelView{l.pool, l.loc, l.bm, l.BW};
 }
 
+LevelSrc packed_src(const TableLevel &l)
+{
+    LevelSrc s{};
+    s.P = view(l);
+    return s;
+}
+
 }  // namespace
 
 scc_status scan_u128(scc_table *T, const u128 *in, u128 *out, int64_t n) { return scan_incl<u128>(T, in, out, n); }
@@ -813,7 +889,7 @@ static scc_status build_levels(scc_table *T)
             GatherArgs G{};
             G.g = g; G.k = k; G.nkeys = HL.nkeys; G.WS = HL.WS[hs]; G.rows_zero = zero && h == k;
             G.hub_degree = hub_degree;
-            G.L = view(T->lev[hs]); G.M = Sx.M; G.key_sidx = T->key_sidx; G.Slo = Sx.lo; G.Shi = Sx.hi;
+            G.L = packed_src(T->lev[hs]); G.M = Sx.M; G.key_sidx = T->key_sidx; G.Slo = Sx.lo; G.Shi = Sx.hi;
             G.chunk_v = chunk_v; G.chunk_e = chunk_e; G.err = err;
             const size_t lds = (size_t)2 * HL.WS[hs] * 8;
             HIP_TRY(hipEventRecord(g0, st));
@@ -830,7 +906,7 @@ static scc_status build_levels(scc_table *T)
         if (!Lv.loc) return set_error(SCC_ENOMEM, "level %d locators", h);
         CombineArgs C{};
         C.g = g; C.L = T->dlut; C.h = h; C.zero_only = zero && last; C.max_bits = T->max_bits;
-        for (int q = 2; q < h; q++) C.lev[q] = view(T->lev[q]);
+        for (int q = 2; q < h; q++) C.lev[q] = packed_src(T->lev[q]);
         for (int q = 1; q < h; q++) { C.Slo[q] = T->S[q].lo; C.Shi[q] = T->S[q].hi; C.M[q] = T->S[q].M; }
         C.key_xidx = T->key_xidx; C.W = HL.W[h];
         C.slot_key = slot_key; C.slot_lo = slot_lo; C.slot_hi = slot_hi;
@@ -1062,5 +1138,524 @@ extern "C" scc_status scc_table_info_get(const scc_table *t, scc_table_info *out
     out->bytes = t->bytes;
     out->t[0] = lo64(t->t); out->t[1] = hi64(t->t);
     for (int j = 0; j < t->hlut.num_unr; j++) { out->tj[j][0] = lo64(t->tj[j]); out->tj[j][1] = hi64(t->tj[j]); }
+    return SCC_OK;
+}
+
+// ===========================================================================
+// Batched build: many instances (graph x colouring x k) in one persistent
+// launch. Work items are (instance, level, phase, vertex tile) in a
+// topological order; a resident grid takes them with an in-order ticket
+// counter, and an item waits until the items it depends on have completed
+// (a per-(instance, level, phase) completion counter). Every item waits only
+// on items with smaller tickets, which are held by running workers that never
+// wait on later items, so the launch always drains. Inside the launch each
+// level's records live in fixed-capacity per-vertex slots; afterwards every
+// instance is packed into a standard table.
+// ===========================================================================
+namespace {
+
+enum { BI_G1 = 0, BI_COMBINE = 1, BI_GATHER = 2, BI_HUB = 3 };
+
+struct BItem {
+    int32_t inst;
+    int16_t h;
+    int16_t phase;
+    int32_t dep;      // completion counter waited on, -1 for none
+    int32_t need;     // count it must reach
+    int32_t done;     // counter incremented when this item completes
+    int32_t pad;
+    int64_t a, b, c;  // vertex range [a, b); hub chunk: vertex a, edges [b, c)
+};
+
+struct BInst {
+    GraphView g;
+    int k;
+    uint64_t *S1;
+    u128 *M1;
+    GatherArgs G[SCC_KMAX + 1];    // neighbour sums of level h (2..k-1)
+    CombineArgs C[SCC_KMAX + 1];   // counts of level h (2..k)
+};
+
+struct BatchArgs {
+    const BItem *items;
+    int64_t nitems;
+    const BInst *inst;
+    int *counters;
+    unsigned long long *ticket;
+    int *err;                      // [0] overflow bits, [1] waits that hit the time limit, [2] abort flag
+    unsigned long long wait_ticks; // limit of one wait in wall-clock ticks
+};
+
+__device__ inline long long wave_uniform64(unsigned long long x)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(x >> 32));
+    return (long long)(((uint64_t)hi << 32) | lo);
+}
+
+// One wave per worker. Nothing on the loop's control path is confined to one
+// lane: the ticket and completion atomics are issued by the whole wave with an
+// addend of 1 in lane 0 only, and the dependency poll runs in every lane with
+// its value made scalar. A lane-0-only region on each side of the back edge
+// could be merged across it by the compiler, giving the loop a divergent latch
+// at which lanes drift apart.
+__global__ void __launch_bounds__(WAVE) k_batch(BatchArgs B)
+{
+    extern __shared__ uint64_t sm[];
+    __shared__ unsigned cnt1[SCC_KMAX];
+    const int lane = threadIdx.x;
+    const unsigned one = lane == 0 ? 1u : 0u;
+    for (;;) {
+        const long long it = wave_uniform64(atomicAdd(B.ticket, (unsigned long long)one));
+        if (it >= B.nitems) break;
+        const BItem I = B.items[it];
+        int abort = __builtin_amdgcn_readfirstlane(
+            __hip_atomic_load(&B.err[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        if (I.dep >= 0 && !abort) {
+            const unsigned long long t0 = wall_clock64();
+            while (__builtin_amdgcn_readfirstlane(
+                       __hip_atomic_load(&B.counters[I.dep], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) < I.need) {
+                __builtin_amdgcn_s_sleep(2);
+                if (wall_clock64() - t0 > B.wait_ticks) {   // never expected: drain instead of waiting on
+                    atomicAdd(&B.err[1], (int)one);
+                    atomicMax(&B.err[2], 1);
+                    abort = 1;
+                    break;
+                }
+            }
+        }
+        __threadfence();       // acquire: the producers' writes are visible from here on
+        if (!abort) {
+            const BInst &P = B.inst[I.inst];
+            switch (I.phase) {
+            case BI_G1:
+                for (int64_t v = I.a; v < I.b; v++) gather1_vertex(P.g, P.k, P.S1, P.M1, v, cnt1);
+                break;
+            case BI_COMBINE:
+                for (int64_t v = I.a; v < I.b; v++) {
+                    combine_vertex<true>(P.C[I.h], v, sm);
+                    __syncthreads();
+                }
+                break;
+            case BI_GATHER:
+                for (int64_t v = I.a; v < I.b; v++) {
+                    gather_vertex<true>(P.G[I.h], v, sm);
+                    __syncthreads();
+                }
+                break;
+            default:
+                hub_chunk<true>(P.G[I.h], I.a, I.b, I.c, sm);
+                break;
+            }
+        }
+        __syncthreads();
+        __threadfence();       // release: this item's writes before its completion count
+        atomicAdd(&B.counters[I.done], (int)one);
+    }
+}
+
+struct BatchInstHost {
+    scc_table *T = nullptr;
+    std::vector<int32_t> hubs;           // ascending
+    std::vector<int64_t> hub_rows;       // [2 * nhub]
+    int32_t *hubs_dev = nullptr;
+    // slots per level
+    uint16_t *skey[SCC_KMAX + 1] = {};
+    uint64_t *slo[SCC_KMAX + 1] = {}, *shi[SCC_KMAX + 1] = {};
+    uint32_t *meta[SCC_KMAX + 1] = {};
+    u128 *N[SCC_KMAX + 1] = {};
+};
+
+// rows above hub_degree: sorted vertex ids and their row bounds
+scc_status find_hubs(scc_table *T, int hub_degree, std::vector<int32_t> &hh, std::vector<int64_t> &rp)
+{
+    hh.clear();
+    rp.clear();
+    const int64_t n = T->n;
+    if (!n) return SCC_OK;
+    hipStream_t st = T->stream;
+    GraphView g{n, T->row_ptr, T->col_idx, T->colors};
+    int32_t *hubs = (int32_t *)T->mem.get((size_t)n * 4 + 8);
+    int *cnt = (int *)T->mem.get(16);
+    if (!hubs || !cnt) { T->mem.put(hubs); T->mem.put(cnt); return set_error(SCC_ENOMEM, "hub list"); }
+    int nh = 0;
+    hipError_t e = hipMemsetAsync(cnt, 0, 4, st);
+    hipLaunchKernelGGL(k_hub_list, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g, hub_degree, hubs, cnt);
+    if (e == hipSuccess) e = hipMemcpyAsync(&nh, cnt, 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e == hipSuccess && nh) {
+        hh.resize(nh);
+        e = hipMemcpyAsync(hh.data(), hubs, (size_t)nh * 4, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        std::sort(hh.begin(), hh.end());
+        int64_t *rows = (int64_t *)T->mem.get((size_t)nh * 16 + 16);
+        if (!rows) e = hipErrorOutOfMemory;
+        if (e == hipSuccess) e = hipMemcpyAsync(hubs, hh.data(), (size_t)nh * 4, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess)
+            hipLaunchKernelGGL(k_hub_rows, dim3((unsigned)((nh + 255) / 256)), dim3(256), 0, st, g, hubs, nh, rows);
+        rp.resize(2 * (size_t)nh);
+        if (e == hipSuccess) e = hipMemcpyAsync(rp.data(), rows, (size_t)nh * 16, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        T->mem.put(rows);
+    }
+    T->mem.put(hubs);
+    T->mem.put(cnt);
+    if (e != hipSuccess) return set_error(SCC_EDEVICE, "hub list: %s", hipGetErrorString(e));
+    return SCC_OK;
+}
+
+struct TuneKey {
+    std::vector<int64_t> sig;
+    bool operator<(const TuneKey &o) const { return sig < o.sig; }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, std::pair<int, int>> g_tune;
+
+}  // namespace
+
+// the pack step of one level from explicit slot arrays (shared with the plain build)
+static scc_status pack_level(scc_table *T, int h, const uint32_t *meta, const u128 *Nsc, const uint16_t *slot_key,
+                             const uint64_t *slot_lo, const uint64_t *slot_hi, uint64_t *words,
+                             unsigned long long *flags)
+{
+    const DevLut &HL = T->hlut;
+    const int64_t n = T->n;
+    hipStream_t st = T->stream;
+    TableLevel &Lv = T->lev[h];
+    if (!Lv.loc) {
+        Lv.loc = (uint64_t *)T->alloc((size_t)n * 8 + 8);
+        if (!Lv.loc) return set_error(SCC_ENOMEM, "level %d locators", h);
+    }
+    if (n) hipLaunchKernelGGL(k_words, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, meta, words);
+    scc_status sst = scan_incl<uint64_t>(T, words, words, n);
+    if (sst) return sst;
+    uint64_t total = 0;
+    if (n) {
+        HIP_TRY(hipMemcpyAsync(&total, words + (n - 1), 8, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+    }
+    Lv.pool_words = total;
+    Lv.pool = (uint64_t *)T->alloc((size_t)total * 8 + 64);
+    Lv.BW = (HL.W[h] + 63) / 64;
+    Lv.bm = (uint64_t *)T->alloc((size_t)n * Lv.BW * 8 + 8);
+    if (!Lv.pool || !Lv.bm) return set_error(SCC_ENOMEM, "level %d pool (%llu words)", h, (unsigned long long)total);
+    if (n) hipLaunchKernelGGL(k_pack, dim3(grid_of(n)), dim3(WAVE), 0, st, n, HL.W[h], meta, words, slot_key, slot_lo,
+                              slot_hi, Nsc, Lv.pool, Lv.loc, T->key_xidx, HL.nkeys, T->colors, Lv.bm, Lv.BW);
+    HIP_TRY(hipMemsetAsync(flags, 0, 2 * sizeof(unsigned long long), st));
+    if (n) hipLaunchKernelGGL(k_meta_sum, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 1024)), dim3(256), 0, st, n,
+                              meta, flags);
+    unsigned long long cnt2[2];
+    HIP_TRY(hipMemcpyAsync(cnt2, flags, sizeof cnt2, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    Lv.nnz = (int64_t)cnt2[0];
+    Lv.wide = (int64_t)cnt2[1];
+    return SCC_OK;
+}
+
+static scc_table *new_table(const scc_csr *g, const uint8_t *colors, int k, const scc_build_opts &o)
+{
+    scc_table *T = new scc_table();
+    T->k = k; T->rooting = o.rooting; T->max_bits = o.max_bits;
+    T->n = g->n; T->nnz_g = g->nnz;
+    T->row_ptr = g->row_ptr; T->col_idx = g->col_idx; T->colors = colors;
+    T->stream = (hipStream_t)o.stream;
+    T->mem.alloc = o.alloc; T->mem.stream = T->stream;
+    T->hub_degree = o.hub_degree > 0 ? o.hub_degree : 1024;
+    T->hub_chunk = 256;
+    build_lut(k, &T->hlut);
+    return T;
+}
+
+// One persistent launch over all instances, for one (tile, hub) choice.
+// Assumes the per-instance storage exists; fills slots and neighbour sums.
+static scc_status batch_launch(std::vector<BatchInstHost> &H, int tile, int hub_degree, hipStream_t st,
+                               DevMem &mem, float *ms_out, int64_t *nitems_out, int *grid_out)
+{
+    const int ni = (int)H.size();
+    int kmax = 0;
+    for (auto &x : H) kmax = std::max(kmax, x.T->k);
+    // hubs for this threshold
+    std::vector<std::vector<int32_t>> hv(ni);
+    std::vector<std::vector<int64_t>> hr(ni);
+    for (int i = 0; i < ni; i++) {
+        scc_status s = find_hubs(H[i].T, hub_degree, hv[i], hr[i]);
+        if (s) return s;
+    }
+    // counters: per instance, S-ready[h] (h = 1..k-1) and X-ready[h] (h = 2..k)
+    auto cS = [&](int i, int h) { return i * 2 * (SCC_KMAX + 1) + h; };
+    auto cX = [&](int i, int h) { return i * 2 * (SCC_KMAX + 1) + (SCC_KMAX + 1) + h; };
+    std::vector<BItem> items;
+    std::vector<std::vector<int>> nS(ni, std::vector<int>(SCC_KMAX + 1, 0)), nX(ni, std::vector<int>(SCC_KMAX + 1, 0));
+    auto tiles = [&](int i, int16_t h, int16_t ph, int dep, int need, int done) {
+        int c = 0;
+        for (int64_t a = 0; a < H[i].T->n; a += tile) {
+            BItem it{};
+            it.inst = i; it.h = h; it.phase = ph; it.dep = dep; it.need = need; it.done = done;
+            it.a = a; it.b = std::min<int64_t>(H[i].T->n, a + tile);
+            items.push_back(it);
+            c++;
+        }
+        return c;
+    };
+    for (int i = 0; i < ni; i++) nS[i][1] = tiles(i, 1, BI_G1, -1, 0, cS(i, 1));
+    for (int h = 2; h <= kmax; h++) {
+        for (int i = 0; i < ni; i++)
+            if (H[i].T->k >= h) nX[i][h] = tiles(i, (int16_t)h, BI_COMBINE, cS(i, h - 1), nS[i][h - 1], cX(i, h));
+        for (int i = 0; i < ni; i++) {
+            if (H[i].T->k - 1 < h) continue;
+            int c = 0;
+            for (size_t q = 0; q < hv[i].size(); q++)
+                for (int64_t e = hr[i][2 * q]; e < hr[i][2 * q + 1]; e += H[i].T->hub_chunk) {
+                    BItem it{};
+                    it.inst = i; it.h = (int16_t)h; it.phase = BI_HUB; it.dep = cX(i, h); it.need = nX[i][h];
+                    it.done = cS(i, h);
+                    it.a = hv[i][q]; it.b = e; it.c = std::min(hr[i][2 * q + 1], e + H[i].T->hub_chunk);
+                    items.push_back(it);
+                    c++;
+                }
+            c += tiles(i, (int16_t)h, BI_GATHER, cX(i, h), nX[i][h], cS(i, h));
+            nS[i][h] = c;
+        }
+    }
+    // per-instance argument blocks
+    std::vector<BInst> inst(ni);
+    for (int i = 0; i < ni; i++) {
+        scc_table *T = H[i].T;
+        const DevLut &HL = T->hlut;
+        const int k = T->k;
+        const bool zero = T->rooting == SCC_ROOT_ZERO;
+        BInst &B = inst[i];
+        B.g = GraphView{T->n, T->row_ptr, T->col_idx, T->colors};
+        B.k = k;
+        B.S1 = T->S[1].lo; B.M1 = T->S[1].M;
+        auto slot_src = [&](int h) {
+            LevelSrc s{};
+            s.skey = H[i].skey[h]; s.slo = H[i].slo[h]; s.shi = H[i].shi[h];
+            s.meta = H[i].meta[h]; s.N = H[i].N[h]; s.W = HL.W[h];
+            return s;
+        };
+        for (int h = 2; h < k; h++) {
+            GatherArgs &G = B.G[h];
+            G.g = B.g; G.k = k; G.nkeys = HL.nkeys; G.WS = HL.WS[h]; G.rows_zero = zero && h == k - 1;
+            G.hub_degree = hub_degree;
+            G.L = slot_src(h); G.M = T->S[h].M; G.key_sidx = T->key_sidx; G.Slo = T->S[h].lo; G.Shi = T->S[h].hi;
+            G.err = nullptr;
+        }
+        for (int h = 2; h <= k; h++) {
+            CombineArgs &C = B.C[h];
+            C.g = B.g; C.L = T->dlut; C.h = h; C.zero_only = zero && h == k; C.max_bits = T->max_bits;
+            for (int q = 2; q < h; q++) C.lev[q] = slot_src(q);
+            for (int q = 1; q < h; q++) { C.Slo[q] = T->S[q].lo; C.Shi[q] = T->S[q].hi; C.M[q] = T->S[q].M; }
+            C.key_xidx = T->key_xidx; C.W = HL.W[h];
+            C.slot_key = H[i].skey[h]; C.slot_lo = H[i].slo[h]; C.slot_hi = H[i].shi[h];
+            C.meta = H[i].meta[h]; C.Nout = H[i].N[h];
+        }
+    }
+    const size_t ncount = (size_t)ni * 2 * (SCC_KMAX + 1);
+    BItem *ditems = (BItem *)mem.get(items.size() * sizeof(BItem) + 64);
+    BInst *dinst = (BInst *)mem.get(inst.size() * sizeof(BInst) + 64);
+    int *dcnt = (int *)mem.get(ncount * 4 + 64);
+    unsigned long long *dtick = (unsigned long long *)mem.get(64);
+    int *derr = (int *)mem.get(64);
+    struct Free { DevMem &m; void *p[5]; ~Free() { for (void *q : p) m.put(q); } } fr{mem, {ditems, dinst, dcnt, dtick, derr}};
+    if (!ditems || !dinst || !dcnt || !dtick || !derr) return set_error(SCC_ENOMEM, "batch work list");
+    for (int i = 0; i < ni; i++)
+        for (int h = 2; h < H[i].T->k; h++) inst[i].G[h].err = derr;
+    for (int i = 0; i < ni; i++)
+        for (int h = 2; h <= H[i].T->k; h++) inst[i].C[h].err = derr;
+    HIP_TRY(hipMemcpyAsync(ditems, items.data(), items.size() * sizeof(BItem), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(dinst, inst.data(), inst.size() * sizeof(BInst), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemsetAsync(dcnt, 0, ncount * 4, st));
+    HIP_TRY(hipMemsetAsync(dtick, 0, 8, st));
+    HIP_TRY(hipMemsetAsync(derr, 0, 16, st));
+    // cleared hub rows (their sums are merged with atomics)
+    for (int i = 0; i < ni; i++) {
+        if (hv[i].empty()) continue;
+        int32_t *dh = (int32_t *)mem.get(hv[i].size() * 4);
+        if (!dh) return set_error(SCC_ENOMEM, "hub ids");
+        HIP_TRY(hipMemcpyAsync(dh, hv[i].data(), hv[i].size() * 4, hipMemcpyHostToDevice, st));
+        for (int h = 2; h < H[i].T->k; h++)
+            hipLaunchKernelGGL(k_hub_prepare, dim3((unsigned)hv[i].size()), dim3(WAVE), 0, st, inst[i].G[h], dh);
+        HIP_TRY(hipStreamSynchronize(st));
+        mem.put(dh);
+    }
+    // LDS: the largest need over the instances' gathers and combines
+    size_t lds = 0;
+    for (int i = 0; i < ni; i++) {
+        const DevLut &HL = H[i].T->hlut;
+        for (int h = 2; h <= H[i].T->k; h++) {
+            lds = std::max(lds, (size_t)(2 * HL.xoff[h] + 2 * HL.soff[h]) * 8);
+            if (h < H[i].T->k) lds = std::max(lds, (size_t)2 * HL.WS[h] * 8);
+        }
+    }
+    int dev = 0, ncu = 0, per_cu = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch, WAVE, lds));
+    if (per_cu < 1) return set_error(SCC_EUNSUPPORTED, "batched launch does not fit a CU (LDS %zu)", lds);
+    const int grid = std::min<int64_t>((int64_t)ncu * per_cu, (int64_t)items.size());
+    int wc_khz = 0;
+    HIP_TRY(hipDeviceGetAttribute(&wc_khz, hipDeviceAttributeWallClockRate, dev));
+    if (wc_khz <= 0) wc_khz = 100000;
+    // a dependency wait longer than 10 s means something is wrong: the launch drains and reports it
+    BatchArgs BA{ditems, (int64_t)items.size(), dinst, dcnt, dtick, derr, (unsigned long long)wc_khz * 1000ull * 10ull};
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    HIP_TRY(hipEventRecord(e0, st));
+    hipLaunchKernelGGL(k_batch, dim3((unsigned)grid), dim3(WAVE), lds, st, BA);
+    HIP_TRY(hipEventRecord(e1, st));
+    HIP_TRY(hipEventSynchronize(e1));
+    float ms = 0;
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    int herr[4];
+    HIP_TRY(hipMemcpy(herr, derr, sizeof herr, hipMemcpyDeviceToHost));
+    HIP_TRY(hipGetLastError());
+    if (herr[1]) return set_error(SCC_EDEVICE, "batched launch: %d dependency waits hit the spin limit", herr[1]);
+    if (herr[0] & 1) return set_error(SCC_EOVERFLOW, "a count needs more than the allowed bits");
+    if (herr[0] & 2) return set_error(SCC_EOVERFLOW, "a neighbour sum may exceed 128 bits");
+    if (ms_out) *ms_out = ms;
+    if (nitems_out) *nitems_out = (int64_t)items.size();
+    if (grid_out) *grid_out = grid;
+    return SCC_OK;
+}
+
+extern "C" scc_status scc_build_batch(const scc_instance *inst, int n_inst, const scc_build_opts *opt,
+                                      const scc_batch_opts *bopt, scc_table **out, scc_batch_report *rep)
+{
+    if (!inst || !out || n_inst < 1) return set_error(SCC_EINVAL, "bad batch arguments");
+    for (int i = 0; i < n_inst; i++) out[i] = nullptr;
+    scc_build_opts o{};
+    if (opt) o = *opt;
+    if (o.max_bits == 0) o.max_bits = 128;
+    if (o.rooting != SCC_ROOT_ZERO && o.rooting != SCC_ROOT_ALL) return set_error(SCC_EINVAL, "bad rooting");
+    if (o.max_bits != 64 && o.max_bits != 128) return set_error(SCC_EINVAL, "max_bits must be 64 or 128");
+    scc_batch_opts bo{};
+    if (bopt) bo = *bopt;
+    hipStream_t st = (hipStream_t)o.stream;
+    auto t_start = std::chrono::steady_clock::now();
+    std::vector<BatchInstHost> H(n_inst);
+    auto fail = [&](scc_status s) {
+        for (auto &x : H) {
+            if (!x.T) continue;
+            for (int h = 0; h <= SCC_KMAX; h++) {
+                x.T->mem.put(x.skey[h]); x.T->mem.put(x.slo[h]); x.T->mem.put(x.shi[h]);
+                x.T->mem.put(x.meta[h]); x.T->mem.put(x.N[h]);
+            }
+            delete x.T;
+        }
+        return s;
+    };
+    // tables, lookup tables and storage
+    for (int i = 0; i < n_inst; i++) {
+        const scc_instance &I = inst[i];
+        if (I.k < 2 || I.k > SCC_KMAX) return fail(set_error(SCC_EINVAL, "instance %d: k = %d not in [2, 8]", i, I.k));
+        if (I.g.n < 0 || I.g.n >= ((int64_t)1 << 31) || (I.g.n > 0 && !I.g.row_ptr) || !I.colors)
+            return fail(set_error(SCC_EINVAL, "instance %d: bad graph", i));
+        scc_table *T = new_table(&I.g, I.colors, I.k, o);
+        H[i].T = T;
+        scc_status s = make_key_maps(T);
+        if (s) return fail(s);
+        const DevLut &HL = T->hlut;
+        const int64_t n = T->n;
+        T->S[1].lo = (uint64_t *)T->alloc((size_t)n * (I.k - 1) * 8 + 8);
+        T->S[1].M = (u128 *)T->alloc((size_t)n * 16 + 16);
+        if (!T->S[1].lo || !T->S[1].M) return fail(set_error(SCC_ENOMEM, "instance %d: level-1 sums", i));
+        for (int h = 2; h < I.k; h++) {
+            const size_t sz = (size_t)n * HL.WS[h] * 8 + 8;
+            T->S[h].lo = (uint64_t *)T->alloc(sz);
+            T->S[h].hi = (uint64_t *)T->alloc(sz);
+            T->S[h].M = (u128 *)T->alloc((size_t)n * 16 + 16);
+            if (!T->S[h].lo || !T->S[h].hi || !T->S[h].M) return fail(set_error(SCC_ENOMEM, "instance %d: sums", i));
+        }
+        for (int h = 2; h <= I.k; h++) {
+            const size_t w = (size_t)n * HL.W[h];
+            H[i].skey[h] = (uint16_t *)T->mem.get(w * 2 + 64);
+            H[i].slo[h] = (uint64_t *)T->mem.get(w * 8 + 64);
+            H[i].shi[h] = (uint64_t *)T->mem.get(w * 8 + 64);
+            H[i].meta[h] = (uint32_t *)T->mem.get((size_t)n * 4 + 64);
+            H[i].N[h] = (u128 *)T->mem.get((size_t)n * 16 + 64);
+            if (!H[i].skey[h] || !H[i].slo[h] || !H[i].shi[h] || !H[i].meta[h] || !H[i].N[h])
+                return fail(set_error(SCC_ENOMEM, "instance %d: level %d slots", i, h));
+        }
+    }
+    DevMem mem;
+    mem.alloc = o.alloc;
+    mem.stream = st;
+    // schedule: the caller's choice, a cached tuning result, or a timed probe
+    TuneKey key;
+    for (int i = 0; i < n_inst; i++) { key.sig.push_back(inst[i].g.n); key.sig.push_back(inst[i].g.nnz); key.sig.push_back(inst[i].k); }
+    int tile = bo.tile > 0 ? bo.tile : 256, hubd = bo.hub_degree > 0 ? bo.hub_degree : 1024;
+    bool tuned = false;
+    scc_batch_report R{};
+    if (bo.tile <= 0 && bo.hub_degree <= 0) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) { tile = it->second.first; hubd = it->second.second; tuned = true; }
+    }
+    if (bo.autotune && !tuned) {
+        const int tiles[] = {32, 128, 512, 2048};
+        const int hubs[] = {512, 2048};
+        float best = 1e30f;
+        for (int t : tiles)
+            for (int hd : hubs) {
+                float ms = 0;
+                scc_status s = batch_launch(H, t, hd, st, mem, &ms, nullptr, nullptr);
+                if (s) return fail(s);
+                if (R.nprobe < 16) { R.probe_tile[R.nprobe] = t; R.probe_hub[R.nprobe] = hd; R.probe_ms[R.nprobe] = ms; R.nprobe++; }
+                if (ms < best) { best = ms; tile = t; hubd = hd; }
+            }
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[key] = {tile, hubd};
+        tuned = true;
+    }
+    auto t_launch = std::chrono::steady_clock::now();
+    float ms = 0;
+    int64_t nitems = 0;
+    int grid = 0;
+    scc_status s = batch_launch(H, tile, hubd, st, mem, &ms, &nitems, &grid);
+    if (s) return fail(s);
+    auto t_pack = std::chrono::steady_clock::now();
+    // standard tables: pack every level, then totals
+    for (int i = 0; i < n_inst; i++) {
+        scc_table *T = H[i].T;
+        const int64_t n = T->n;
+        uint64_t *words = (uint64_t *)T->mem.get((size_t)n * 8 + 64);
+        unsigned long long *flags = (unsigned long long *)T->mem.get(64);
+        if (!words || !flags) { T->mem.put(words); T->mem.put(flags); return fail(set_error(SCC_ENOMEM, "pack scratch")); }
+        for (int h = 2; h <= T->k && !s; h++)
+            s = pack_level(T, h, H[i].meta[h], H[i].N[h], H[i].skey[h], H[i].slo[h], H[i].shi[h], words, flags);
+        T->mem.put(words);
+        T->mem.put(flags);
+        if (s) return fail(s);
+        for (int h = 2; h <= T->k; h++) {
+            T->mem.put(H[i].skey[h]); T->mem.put(H[i].slo[h]); T->mem.put(H[i].shi[h]);
+            T->mem.put(H[i].meta[h]); T->mem.put(H[i].N[h]);
+            H[i].skey[h] = nullptr; H[i].slo[h] = nullptr; H[i].shi[h] = nullptr; H[i].meta[h] = nullptr; H[i].N[h] = nullptr;
+        }
+        T->lev[1].nnz = T->n;
+        // hub list of the chosen threshold, for the sampler's running sums
+        std::vector<int32_t> hh;
+        std::vector<int64_t> rp;
+        s = find_hubs(T, hubd, hh, rp);
+        if (s) return fail(s);
+        T->hub_degree = hubd;
+        T->nhub = (int)hh.size();
+        T->hub_host = hh;
+        T->hub_rows_host = rp;
+        s = build_totals(T);
+        if (s) return fail(s);
+    }
+    auto t_end = std::chrono::steady_clock::now();
+    for (int i = 0; i < n_inst; i++) out[i] = H[i].T;
+    if (rep) {
+        R.tile = tile; R.hub_degree = hubd; R.items = nitems; R.grid = grid; R.launch_ms = ms; R.tuned = tuned ? 1 : 0;
+        R.pack_ms = std::chrono::duration<double, std::milli>(t_end - t_pack).count();
+        R.total_ms = std::chrono::duration<double, std::milli>(t_end - t_launch).count();
+        R.setup_ms = std::chrono::duration<double, std::milli>(t_launch - t_start).count();
+        *rep = R;
+    }
     return SCC_OK;
 }
