@@ -58,7 +58,10 @@ typedef struct scc_table scc_table;
 
 /* Device allocator hooks. alloc returns device memory of at least `bytes`
    bytes (or NULL); free releases it. Both are called on the caller's thread
-   with the build's stream in `stream`. */
+   with the build's stream in `stream`. free may be called while work that
+   uses the block is still queued on that stream: the allocator must hand the
+   block out again only in that stream's order (as a stream-ordered caching
+   allocator does), or wait for the stream first. */
 typedef struct {
     void *(*alloc)(size_t bytes, void *stream, void *ctx);
     void (*free)(void *ptr, void *stream, void *ctx);

@@ -24,7 +24,6 @@
 
 namespace {
 
-constexpr int MAXR = 7;    // ceil(max W_h / 64): W_h <= 420 for k <= 8
 
 // ---------------------------------------------------------------------------
 // CSR and colour validation (Sec. 1.3: simple undirected graph)
@@ -383,8 +382,13 @@ struct CombineArgs {
     int *err;                             // [0]: overflow
 };
 
+// Counts of vertex v at level h. The low words of v's own counts X and of its
+// neighbour sums S are staged in lo_area (LDS); high words are needed only when
+// v's bound U reaches 2^64 and are staged in hi_area. With hi_area null, such a
+// vertex is appended to wide_list instead and left for a second pass.
 template <bool SLOTS>
-__device__ inline void combine_vertex(const CombineArgs &A, int64_t v, uint64_t *sm)
+__device__ inline void combine_vertex(const CombineArgs &A, int64_t v, uint64_t *lo_area, uint64_t *hi_area,
+                                      int *wide_list, int *wide_count)
 {
     const DevLut &L = *A.L;
     const int lane = threadIdx.x;
@@ -405,9 +409,18 @@ __device__ inline void combine_vertex(const CombineArgs &A, int64_t v, uint64_t 
         return;
     }
     const bool wide = hi64(U) != 0;
-    const int XT = L.xoff[h], ST = L.soff[h];
-    uint64_t *Xlo = sm, *Xhi = sm + XT, *Slo = sm + 2 * XT, *Shi = sm + 2 * XT + ST;
-    for (int i = lane; i < XT; i += WAVE) { Xlo[i] = 0; Xhi[i] = 0; }
+    if (wide && !hi_area) {
+        if (lane == 0) wide_list[atomicAdd(wide_count, 1)] = (int)v;
+        return;
+    }
+    // below 2^64 every product and partial sum fits in the low words (U bounds them)
+    const int XT = L.xoff[h];
+    uint64_t *Xlo = lo_area, *Slo = lo_area + XT;
+    uint64_t *Xhi = hi_area, *Shi = hi_area + XT;
+    for (int i = lane; i < XT; i += WAVE) {
+        Xlo[i] = 0;
+        if (wide) Xhi[i] = 0;
+    }
     __syncthreads();
     if (lane == 0) Xlo[L.xoff[1]] = 1;   // level 1: the single node, coloured c_v
     const int16_t *xidx = A.key_xidx + (size_t)cv * L.nkeys;
@@ -416,7 +429,7 @@ __device__ inline void combine_vertex(const CombineArgs &A, int64_t v, uint64_t 
         for (uint32_t e = lane; e < r.len; e += WAVE) {
             const int x = L.xoff[hp] + xidx[r.key[e]];
             Xlo[x] = r.lo[e];
-            Xhi[x] = r.hi ? r.hi[e] : 0;
+            if (wide) Xhi[x] = r.hi ? r.hi[e] : 0;
         }
     }
     for (int hs = 1; hs < h; hs++) {
@@ -426,20 +439,27 @@ __device__ inline void combine_vertex(const CombineArgs &A, int64_t v, uint64_t 
         const uint64_t *gh = sw ? A.Shi[hs] + (size_t)v * ws : nullptr;
         for (int i = lane; i < ws; i += WAVE) {
             Slo[L.soff[hs] + i] = gl[i];
-            Shi[L.soff[hs] + i] = sw ? gh[i] : 0;
+            if (wide) Shi[L.soff[hs] + i] = sw ? gh[i] : 0;
         }
     }
     __syncthreads();
 
     const int Wh = L.W[h];
     const int nD = L.bk1[h - 1];
-    u128 val[MAXR];
-#pragma unroll
-    for (int r = 0; r < MAXR; r++) {
-        val[r] = 0;
-        const int o = r * WAVE + lane;
+    // each lane evaluates outputs o = r * 64 + lane; the nonzero ones are compacted
+    // into v's slot right away (ballot + prefix count keeps ascending key order)
+    uint32_t cnt = 0;
+    u128 nsum = 0;
+    uint16_t *sk = A.slot_key + (size_t)v * A.W;
+    uint64_t *sl = A.slot_lo + (size_t)v * A.W;
+    uint64_t *sh = wide ? A.slot_hi + (size_t)v * A.W : nullptr;
+    for (int o0 = 0; o0 < Wh; o0 += WAVE) {
+        const int o = o0 + lane;
+        u128 val = 0;
+        int t = 0, dc = 0;
         if (o < Wh) {
-            const int t = o / nD, dc = o - t * nD;
+            t = o / nD;
+            dc = o - t * nD;
             const int hp = L.dec_hp[h][t], hpp = h - hp;
             const int xb = L.xoff[hp] + L.dec_a[h][t] * L.bk1[hp - 1];
             const int sb = L.soff[hpp] + L.dec_b[h][t] * L.bk1[hpp];
@@ -461,29 +481,18 @@ __device__ inline void combine_vertex(const CombineArgs &A, int64_t v, uint64_t 
                 }
             }
             const int beta = L.dec_beta[h][t];
-            val[r] = beta == 1 ? acc : div_small(acc, (uint32_t)beta);
+            val = beta == 1 ? acc : div_small(acc, (uint32_t)beta);
         }
-    }
-    // compaction into v's slot: ballot + prefix count keeps ascending key order
-    uint32_t cnt = 0;
-    u128 nsum = 0;
-    uint16_t *sk = A.slot_key + (size_t)v * A.W;
-    uint64_t *sl = A.slot_lo + (size_t)v * A.W;
-    uint64_t *sh = wide ? A.slot_hi + (size_t)v * A.W : nullptr;
-#pragma unroll
-    for (int r = 0; r < MAXR; r++) {
-        const int o = r * WAVE + lane;
-        const bool nz = o < Wh && val[r] != 0;
+        const bool nz = val != 0;
         const uint64_t bal = __ballot(nz);
         if (nz) {
             const uint32_t pos = cnt + (uint32_t)__popcll(bal & lanemask_lt());
-            const int t = o / nD, dc = o - t * nD;
             const uint32_t D = L.mask_s[h - 1][dc];
             const uint32_t C = expand_in(D, cv) | (1u << cv);
             sk[pos] = (uint16_t)(L.off[h] + t * L.bk[h] + L.colex_k[C]);
-            sl[pos] = lo64(val[r]);
-            if (wide) sh[pos] = hi64(val[r]);
-            nsum += val[r];
+            sl[pos] = lo64(val);
+            if (wide) sh[pos] = hi64(val);
+            nsum += val;
         }
         cnt += (uint32_t)__popcll(bal);
     }
@@ -494,11 +503,26 @@ __device__ inline void combine_vertex(const CombineArgs &A, int64_t v, uint64_t 
     }
 }
 
-__global__ void __launch_bounds__(WAVE) k_combine(CombineArgs A)
+// one workgroup per vertex, low words in LDS; vertices that need 128 bits are
+// listed for k_combine_wide
+__global__ void __launch_bounds__(WAVE) k_combine(CombineArgs A, int *wide_list, int *wide_count)
 {
     extern __shared__ uint64_t sm[];
     for (int64_t v = blockIdx.x; v < A.g.n; v += gridDim.x) {
-        combine_vertex<false>(A, v, sm);
+        combine_vertex<false>(A, v, sm, nullptr, wide_list, wide_count);
+        __syncthreads();
+    }
+}
+
+// the listed vertices, with high words in LDS as well (lds = 2 (xoff_h + soff_h) words)
+__global__ void __launch_bounds__(WAVE) k_combine_wide(CombineArgs A, const int *wide_list, const int *wide_count)
+{
+    extern __shared__ uint64_t sm[];
+    const int cnt = __builtin_amdgcn_readfirstlane(*wide_count);
+    const int lo_words = A.L->xoff[A.h] + A.L->soff[A.h];
+    for (int i = blockIdx.x; i < cnt; i += gridDim.x) {
+        const int v = __builtin_amdgcn_readfirstlane(wide_list[i]);
+        combine_vertex<false>(A, v, sm, sm + lo_words, nullptr, nullptr);
         __syncthreads();
     }
 }
@@ -534,49 +558,48 @@ __global__ void k_words(int64_t n, const uint32_t *meta, uint64_t *words)
     words[v] = len ? (uint64_t)REC_HDR + key_words(len) + (uint64_t)len * (META_WIDE(m) ? 2u : 1u) : 0;
 }
 
-// copy each vertex's slot into the packed pool at its offset
+// copy each vertex's slot into the packed pool at its offset, in one pass that
+// also sets the presence bitmap (bit = position in the dense level-h layout)
 __global__ void __launch_bounds__(WAVE) k_pack(int64_t n, int W, const uint32_t *meta, const uint64_t *off_incl,
                                                const uint16_t *slot_key, const uint64_t *slot_lo,
                                                const uint64_t *slot_hi, const u128 *Nv, uint64_t *pool, uint64_t *loc,
                                                const int16_t *key_xidx, int nkeys, const uint8_t *colors,
                                                uint64_t *bm, int BW)
 {
-  for (int64_t v = blockIdx.x; v < n; v += gridDim.x) {
+    __shared__ unsigned long long bits[8];   // BW <= ceil(420 / 64)
     const int lane = threadIdx.x;
-    const uint32_t m = meta[v], len = META_LEN(m);
-    // presence bitmap over v's own entries (bit = position in the dense level-h layout)
-    {
-        const int16_t *xi = key_xidx + (size_t)colors[v] * nkeys;
-        for (int w = 0; w < BW; w++) {
-            uint64_t word = 0;
-            for (uint32_t e0 = 0; e0 < len; e0 += WAVE) {
-                const uint32_t e = e0 + lane;
-                int li = -1;
-                if (e < len) li = xi[slot_key[(size_t)v * W + e]];
-                const bool in = li >= 0 && (li >> 6) == w;
-                // lanes OR their bits into one word
-                uint64_t mine = in ? (1ull << (li & 63)) : 0ull;
-#pragma unroll
-                for (int d = WAVE / 2; d >= 1; d >>= 1) mine |= shfl64(mine, lane ^ d);
-                word |= mine;
+    for (int64_t v = blockIdx.x; v < n; v += gridDim.x) {
+        const uint32_t m = meta[v], len = META_LEN(m);
+        if (lane < BW) bits[lane] = 0;
+        __syncthreads();
+        const uint32_t kw = key_words(len);
+        const uint32_t words = len ? REC_HDR + kw + len * (META_WIDE(m) ? 2u : 1u) : 0;
+        const uint64_t start = off_incl[v] - words;
+        if (lane == 0) loc[v] = make_loc(start, len, META_WIDE(m));
+        if (len) {
+            uint64_t *rec = pool + start;
+            if (lane == 0) { rec[0] = lo64(Nv[v]); rec[1] = hi64(Nv[v]); }
+            rec += REC_HDR;
+            uint16_t *keys = (uint16_t *)rec;
+            const int16_t *xi = key_xidx + (size_t)colors[v] * nkeys;
+            const size_t base = (size_t)v * W;
+            for (uint32_t e = lane; e < kw * 4; e += WAVE) {
+                uint16_t key = 0;
+                if (e < len) {
+                    key = slot_key[base + e];
+                    const int li = xi[key];
+                    if (li >= 0) atomicOr(&bits[li >> 6], 1ull << (li & 63));
+                }
+                keys[e] = key;
             }
-            if (lane == 0) bm[(size_t)v * BW + w] = word;
+            for (uint32_t e = lane; e < len; e += WAVE) rec[kw + e] = slot_lo[base + e];
+            if (META_WIDE(m))
+                for (uint32_t e = lane; e < len; e += WAVE) rec[kw + len + e] = slot_hi[base + e];
         }
+        __syncthreads();
+        if (lane < BW) bm[(size_t)v * BW + lane] = bits[lane];
+        __syncthreads();
     }
-    const uint32_t kw = key_words(len);
-    const uint32_t words = len ? REC_HDR + kw + len * (META_WIDE(m) ? 2u : 1u) : 0;
-    const uint64_t start = off_incl[v] - words;
-    if (lane == 0) loc[v] = make_loc(start, len, META_WIDE(m));
-    if (!len) continue;
-    uint64_t *rec = pool + start;
-    if (lane == 0) { rec[0] = lo64(Nv[v]); rec[1] = hi64(Nv[v]); }
-    rec += REC_HDR;
-    uint16_t *keys = (uint16_t *)rec;
-    for (uint32_t e = lane; e < kw * 4; e += WAVE) keys[e] = e < len ? slot_key[(size_t)v * W + e] : 0;
-    for (uint32_t e = lane; e < len; e += WAVE) rec[kw + e] = slot_lo[(size_t)v * W + e];
-    if (META_WIDE(m))
-        for (uint32_t e = lane; e < len; e += WAVE) rec[kw + len + e] = slot_hi[(size_t)v * W + e];
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -728,6 +751,136 @@ __global__ void __launch_bounds__(SCAN_T) k_scan_apply(const T *in, T *out, int6
     }
 }
 
+// ---------------------------------------------------------------------------
+// Packing many (instance, level) jobs at once (the batched build): record sizes
+// and their running sums, then the records, with one launch per step for all
+// jobs (blockIdx.y = job).
+// ---------------------------------------------------------------------------
+struct PackJobDev {
+    int64_t n;
+    int W, BW, nkeys, pad;
+    const uint32_t *meta;
+    uint64_t *words;                 // out: inclusive running sums of record sizes
+    uint64_t *bsum;                  // scan scratch, one per SCAN_TILE vertices
+    const uint16_t *skey;
+    const uint64_t *slo, *shi;
+    const u128 *N;
+    uint64_t *pool, *loc, *bm;
+    const int16_t *key_xidx;
+    const uint8_t *colors;
+    unsigned long long *stats;       // [0] stored entries, [1] 128-bit vertices (added to)
+    uint64_t *total;                 // out: pool words
+};
+
+__device__ inline uint64_t rec_words(uint32_t m)
+{
+    const uint32_t len = META_LEN(m);
+    return len ? (uint64_t)REC_HDR + key_words(len) + (uint64_t)len * (META_WIDE(m) ? 2u : 1u) : 0;
+}
+
+__global__ void __launch_bounds__(SCAN_T) k_mpack_sums(const PackJobDev *Js)
+{
+    __shared__ uint64_t sh[SCAN_T / WAVE];
+    const PackJobDev J = Js[blockIdx.y];
+    const int64_t nb = (J.n + SCAN_TILE - 1) / SCAN_TILE;
+    if ((int64_t)blockIdx.x >= nb) return;
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    uint64_t s = 0;
+    for (int i = 0; i < SCAN_I; i++) {
+        const int64_t idx = base + (int64_t)threadIdx.x * SCAN_I + i;
+        if (idx < J.n) s += rec_words(J.meta[idx]);
+    }
+    const uint64_t incl = block_incl_scan<uint64_t>(s, sh);
+    if (threadIdx.x == SCAN_T - 1) J.bsum[blockIdx.x] = incl;
+}
+
+__global__ void __launch_bounds__(SCAN_T) k_mpack_top(const PackJobDev *Js)
+{
+    __shared__ uint64_t sh[SCAN_T / WAVE];
+    __shared__ uint64_t carry;
+    const PackJobDev J = Js[blockIdx.x];
+    const int64_t nb = (J.n + SCAN_TILE - 1) / SCAN_TILE;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int64_t base = 0; base < nb; base += SCAN_T) {
+        const int64_t idx = base + threadIdx.x;
+        const uint64_t x = idx < nb ? J.bsum[idx] : 0;
+        const uint64_t incl = block_incl_scan<uint64_t>(x, sh);
+        const uint64_t c = carry;
+        if (idx < nb) J.bsum[idx] = c + incl - x;
+        __syncthreads();
+        if (threadIdx.x == SCAN_T - 1) carry = c + incl;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *J.total = carry;
+}
+
+__global__ void __launch_bounds__(SCAN_T) k_mpack_apply(const PackJobDev *Js)
+{
+    __shared__ uint64_t sh[SCAN_T / WAVE];
+    const PackJobDev J = Js[blockIdx.y];
+    const int64_t nb = (J.n + SCAN_TILE - 1) / SCAN_TILE;
+    if ((int64_t)blockIdx.x >= nb) return;
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_I;
+    uint64_t v[SCAN_I];
+    uint64_t s = 0;
+    for (int i = 0; i < SCAN_I; i++) {
+        v[i] = (base + i < J.n) ? rec_words(J.meta[base + i]) : 0;
+        s += v[i];
+    }
+    const uint64_t incl = block_incl_scan<uint64_t>(s, sh);
+    uint64_t run = J.bsum[blockIdx.x] + incl - s;
+    for (int i = 0; i < SCAN_I; i++) {
+        run += v[i];
+        if (base + i < J.n) J.words[base + i] = run;
+    }
+}
+
+// the records of every job (one wave per vertex, as k_pack), plus the level's
+// stored entries and 128-bit vertices
+__global__ void __launch_bounds__(WAVE) k_mpack(const PackJobDev *Js)
+{
+    __shared__ unsigned long long bits[8];   // BW <= ceil(420 / 64)
+    const PackJobDev J = Js[blockIdx.y];
+    const int lane = threadIdx.x;
+    uint64_t nlen = 0, nwide = 0;
+    for (int64_t v = blockIdx.x; v < J.n; v += gridDim.x) {
+        const uint32_t m = J.meta[v], len = META_LEN(m);
+        nlen += len;
+        nwide += META_WIDE(m);
+        if (lane < J.BW) bits[lane] = 0;
+        __syncthreads();
+        const uint32_t kw = key_words(len);
+        const uint64_t start = J.words[v] - rec_words(m);
+        if (lane == 0) J.loc[v] = make_loc(start, len, META_WIDE(m));
+        if (len) {
+            uint64_t *rec = J.pool + start;
+            if (lane == 0) { rec[0] = lo64(J.N[v]); rec[1] = hi64(J.N[v]); }
+            rec += REC_HDR;
+            uint16_t *keys = (uint16_t *)rec;
+            const int16_t *xi = J.key_xidx + (size_t)J.colors[v] * J.nkeys;
+            const size_t base = (size_t)v * J.W;
+            for (uint32_t e = lane; e < kw * 4; e += WAVE) {
+                uint16_t key = 0;
+                if (e < len) {
+                    key = J.skey[base + e];
+                    const int li = xi[key];
+                    if (li >= 0) atomicOr(&bits[li >> 6], 1ull << (li & 63));
+                }
+                keys[e] = key;
+            }
+            for (uint32_t e = lane; e < len; e += WAVE) rec[kw + e] = J.slo[base + e];
+            if (META_WIDE(m))
+                for (uint32_t e = lane; e < len; e += WAVE) rec[kw + len + e] = J.shi[base + e];
+        }
+        __syncthreads();
+        if (lane < J.BW) J.bm[(size_t)v * J.BW + lane] = bits[lane];
+        __syncthreads();
+    }
+    if (lane == 0 && nlen) atomicAdd(&J.stats[0], (unsigned long long)nlen);
+    if (lane == 0 && nwide) atomicAdd(&J.stats[1], (unsigned long long)nwide);
+}
+
 template <typename T>
 scc_status scan_incl(scc_table *T_, const T *in, T *out, int64_t n)
 {
@@ -738,8 +891,8 @@ scc_status scan_incl(scc_table *T_, const T *in, T *out, int64_t n)
     hipLaunchKernelGGL(k_scan_sums<T>, dim3((unsigned)nb), dim3(SCAN_T), 0, T_->stream, in, n, bsum);
     hipLaunchKernelGGL(k_scan_top<T>, dim3(1), dim3(SCAN_T), 0, T_->stream, bsum, nb);
     hipLaunchKernelGGL(k_scan_apply<T>, dim3((unsigned)nb), dim3(SCAN_T), 0, T_->stream, in, out, n, bsum);
-    hipError_t e = hipStreamSynchronize(T_->stream);
-    T_->mem.put(bsum);
+    T_->mem.put(bsum);   // stream-ordered release: reused only by later work on this stream
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return set_error(SCC_EDEVICE, "scan: %s", hipGetErrorString(e));
     return SCC_OK;
 }
@@ -788,20 +941,32 @@ static scc_status build_levels(scc_table *T)
     const bool zero = T->rooting == SCC_ROOT_ZERO;
     const int hub_degree = T->hub_degree;
 
-    unsigned long long *flags = (unsigned long long *)T->mem.get(8 * sizeof(unsigned long long));
     int *err = (int *)T->mem.get(16);
-    std::vector<void *> scratch{flags, err};
+    std::vector<void *> scratch{err};
     struct Guard {
         scc_table *T; std::vector<void *> *s;
         ~Guard() { for (void *p : *s) T->mem.put(p); }
     } guard{T, &scratch};
     auto get = [&](size_t bytes) { void *p = T->mem.get(bytes); if (p) scratch.push_back(p); return p; };
-    if (!flags || !err) return set_error(SCC_ENOMEM, "flags");
+    if (!err) return set_error(SCC_ENOMEM, "flags");
 
-    hipEvent_t e0, e1, g0, g1;
-    HIP_TRY(hipEventCreate(&e0)); HIP_TRY(hipEventCreate(&e1));
-    HIP_TRY(hipEventCreate(&g0)); HIP_TRY(hipEventCreate(&g1));
-    struct EvGuard { hipEvent_t a, b, c, d; ~EvGuard() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); (void)hipEventDestroy(c); (void)hipEventDestroy(d); } } evg{e0, e1, g0, g1};
+    // per-level start/end events (whole level, and its gather), read once at the end
+    hipEvent_t ev[SCC_KMAX + 1][2] = {}, gev[SCC_KMAX + 1][2] = {};
+    struct EvGuard {
+        hipEvent_t (*a)[2], (*b)[2];
+        ~EvGuard() {
+            for (int h = 0; h <= SCC_KMAX; h++)
+                for (int j = 0; j < 2; j++) {
+                    if (a[h][j]) (void)hipEventDestroy(a[h][j]);
+                    if (b[h][j]) (void)hipEventDestroy(b[h][j]);
+                }
+        }
+    } evg{ev, gev};
+    for (int h = 1; h <= k; h++)
+        for (int j = 0; j < 2; j++) {
+            HIP_TRY(hipEventCreate(&ev[h][j]));
+            HIP_TRY(hipEventCreate(&gev[h][j]));
+        }
 
     // hub rows and their neighbour chunks (the same for every level)
     int nhub = 0;
@@ -850,17 +1015,10 @@ static scc_status build_levels(scc_table *T)
     S1.lo = (uint64_t *)T->alloc((size_t)n * (k - 1) * 8 + 8);
     S1.M = (u128 *)T->alloc((size_t)n * 16 + 16);
     if (!S1.lo || !S1.M) return set_error(SCC_ENOMEM, "level-1 sums");
-    HIP_TRY(hipEventRecord(g0, st));
+    HIP_TRY(hipEventRecord(ev[1][0], st));
     if (n) hipLaunchKernelGGL(k_gather1, dim3(grid_of(n)), dim3(WAVE), 0, st, g, k, S1.lo, S1.M);
-    HIP_TRY(hipEventRecord(g1, st));
-    HIP_TRY(hipEventSynchronize(g1));
-    {
-        float ms = 0;
-        HIP_TRY(hipEventElapsedTime(&ms, g0, g1));
-        T->gather_ms[1] = ms;
-        T->gather_bytes[1] = (double)n * 8.0 + (double)T->nnz_g * 5.0 + (double)n * (k - 1) * 8.0;
-        T->level_ms[1] = ms;
-    }
+    HIP_TRY(hipEventRecord(ev[1][1], st));
+    T->gather_bytes[1] = (double)n * 8.0 + (double)T->nnz_g * 5.0 + (double)n * (k - 1) * 8.0;
 
     // scratch slots for the combine, sized for the widest level
     int maxW = 0;
@@ -871,13 +1029,14 @@ static scc_status build_levels(scc_table *T)
     uint64_t *words = (uint64_t *)get((size_t)n * 8 + 256);
     uint32_t *meta = (uint32_t *)get((size_t)n * 4 + 256);
     u128 *Nsc = (u128 *)get((size_t)n * 16 + 256);
-    if (!slot_key || !slot_lo || !slot_hi || !words || !meta || !Nsc)
+    int *wide_list = (int *)get((size_t)n * 4 + 256);
+    if (!slot_key || !slot_lo || !slot_hi || !words || !meta || !Nsc || !wide_list)
         return set_error(SCC_ENOMEM, "combine scratch (%lld bytes)", (long long)n * maxW * 18);
 
     for (int h = 2; h <= k; h++) {
         const bool last = h == k;
-        HIP_TRY(hipEventRecord(e0, st));
-        HIP_TRY(hipMemsetAsync(err, 0, 16, st));
+        HIP_TRY(hipEventRecord(ev[h][0], st));
+        HIP_TRY(hipMemsetAsync(err, 0, 16, st));   // [0] flags, [1] wide vertices
         const int hs = h - 1;   // neighbour sums needed now
         if (hs >= 2) {
             TableSums &Sx = T->S[hs];
@@ -892,15 +1051,15 @@ static scc_status build_levels(scc_table *T)
             G.L = packed_src(T->lev[hs]); G.M = Sx.M; G.key_sidx = T->key_sidx; G.Slo = Sx.lo; G.Shi = Sx.hi;
             G.chunk_v = chunk_v; G.chunk_e = chunk_e; G.err = err;
             const size_t lds = (size_t)2 * HL.WS[hs] * 8;
-            HIP_TRY(hipEventRecord(g0, st));
+            HIP_TRY(hipEventRecord(gev[hs][0], st));
             if (nhub) {
                 hipLaunchKernelGGL(k_hub_prepare, dim3((unsigned)nhub), dim3(WAVE), 0, st, G, hubs);
                 hipLaunchKernelGGL(k_gather_hub, dim3((unsigned)nchunk), dim3(WAVE), lds, st, G, T->hub_chunk);
             }
             if (n) hipLaunchKernelGGL(k_gather, dim3((unsigned)n), dim3(WAVE), lds, st, G);
-            HIP_TRY(hipEventRecord(g1, st));
+            HIP_TRY(hipEventRecord(gev[hs][1], st));
         }
-        // combine into slots
+        // combine into slots: a vertex needing 128 bits waits for the second kernel
         TableLevel &Lv = T->lev[h];
         Lv.loc = (uint64_t *)T->alloc((size_t)n * 8 + 8);
         if (!Lv.loc) return set_error(SCC_ENOMEM, "level %d locators", h);
@@ -911,27 +1070,23 @@ static scc_status build_levels(scc_table *T)
         C.key_xidx = T->key_xidx; C.W = HL.W[h];
         C.slot_key = slot_key; C.slot_lo = slot_lo; C.slot_hi = slot_hi;
         C.meta = meta; C.Nout = Nsc; C.err = err;
-        const size_t lds = (size_t)(2 * HL.xoff[h] + 2 * HL.soff[h]) * 8;
-        if (n) hipLaunchKernelGGL(k_combine, dim3((unsigned)n), dim3(WAVE), lds, st, C);
-        int herr[4];
-        HIP_TRY(hipMemcpyAsync(herr, err, sizeof herr, hipMemcpyDeviceToHost, st));
-        // record sizes, offsets, pack
+        const size_t lds = (size_t)(HL.xoff[h] + HL.soff[h]) * 8;
+        if (n) {
+            hipLaunchKernelGGL(k_combine, dim3((unsigned)n), dim3(WAVE), lds, st, C, wide_list, err + 1);
+            hipLaunchKernelGGL(k_combine_wide, dim3((unsigned)std::min<int64_t>(n, 1024)), dim3(WAVE), 2 * lds, st, C,
+                               wide_list, err + 1);
+        }
+        // record sizes and offsets; the pool size and the error flags in one read
         if (n) hipLaunchKernelGGL(k_words, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, meta, words);
+        scc_status sst = scan_incl<uint64_t>(T, words, words, n);
+        if (sst) return sst;
+        int herr[4] = {0, 0, 0, 0};
+        uint64_t total = 0;
+        HIP_TRY(hipMemcpyAsync(herr, err, sizeof herr, hipMemcpyDeviceToHost, st));
+        if (n) HIP_TRY(hipMemcpyAsync(&total, words + (n - 1), 8, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
         if (herr[0] & 1) return set_error(SCC_EOVERFLOW, "a level-%d count needs more than %d bits", h, T->max_bits);
         if (herr[0] & 2) return set_error(SCC_EOVERFLOW, "a level-%d neighbour sum may exceed 128 bits", h);
-        if (hs >= 2) {
-            float ms = 0;
-            HIP_TRY(hipEventElapsedTime(&ms, g0, g1));
-            T->gather_ms[hs] = ms;
-        }
-        scc_status sst = scan_incl<uint64_t>(T, words, words, n);
-        if (sst) return sst;
-        uint64_t total = 0;
-        if (n) {
-            HIP_TRY(hipMemcpyAsync(&total, words + (n - 1), 8, hipMemcpyDeviceToHost, st));
-            HIP_TRY(hipStreamSynchronize(st));
-        }
         Lv.pool_words = total;
         Lv.pool = (uint64_t *)T->alloc((size_t)total * 8 + 64);
         if (!Lv.pool) return set_error(SCC_ENOMEM, "level %d pool (%llu words)", h, (unsigned long long)total);
@@ -941,18 +1096,22 @@ static scc_status build_levels(scc_table *T)
         if (n) hipLaunchKernelGGL(k_pack, dim3(grid_of(n)), dim3(WAVE), 0, st, n, HL.W[h], meta, words,
                                   slot_key, slot_lo, slot_hi, Nsc, Lv.pool, Lv.loc, T->key_xidx, HL.nkeys, T->colors,
                                   Lv.bm, Lv.BW);
-        HIP_TRY(hipEventRecord(e1, st));
-        HIP_TRY(hipMemsetAsync(flags, 0, 2 * sizeof(unsigned long long), st));
-        if (n) hipLaunchKernelGGL(k_meta_sum, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 1024)), dim3(256), 0, st, n, meta, flags);
-        unsigned long long cnt2[2];
-        HIP_TRY(hipMemcpyAsync(cnt2, flags, sizeof cnt2, hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipStreamSynchronize(st));
-        Lv.nnz = (int64_t)cnt2[0];
-        Lv.wide = (int64_t)cnt2[1];
-        float ms = 0;
-        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-        T->level_ms[h] = ms;
+        HIP_TRY(hipEventRecord(ev[h][1], st));
+        if (n) hipLaunchKernelGGL(k_meta_sum, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 1024)), dim3(256), 0, st,
+                                  n, meta, (unsigned long long *)T->dsum + 2 * h);
         HIP_TRY(hipGetLastError());
+    }
+    // every level's duration (the stream is drained by the totals that follow)
+    HIP_TRY(hipEventSynchronize(ev[k][1]));
+    for (int h = 1; h <= k; h++) {
+        float ms = 0;
+        HIP_TRY(hipEventElapsedTime(&ms, ev[h][0], ev[h][1]));
+        T->level_ms[h] = ms;
+        if (h == 1) T->gather_ms[1] = ms;
+        if (h >= 2 && h < k) {
+            HIP_TRY(hipEventElapsedTime(&ms, gev[h][0], gev[h][1]));
+            T->gather_ms[h] = ms;
+        }
     }
     return SCC_OK;
 }
@@ -981,7 +1140,13 @@ static scc_status gather_stats(scc_table *T)
     return SCC_OK;
 }
 
-static scc_status build_totals(scc_table *T)
+// Level-k totals, launch half: eta and its running sums, the per-shape totals
+// and the root total land in the device summary; nothing waits for the device.
+constexpr int DSUM_TJ = 2 * (SCC_KMAX + 1);     // u64 index of the 32 per-shape totals
+constexpr int DSUM_TOT = DSUM_TJ + 64;           // u64 index of the root total
+constexpr int DSUM_WORDS = DSUM_TOT + 2;
+
+static scc_status totals_launch(scc_table *T)
 {
     const int k = T->k;
     const int64_t n = T->n;
@@ -992,28 +1157,47 @@ static scc_status build_totals(scc_table *T)
     T->pre = (u128 *)T->alloc((size_t)n * 16 + 16);
     const int64_t nb = std::max<int64_t>(1, (n + 255) / 256);
     u128 *part = (u128 *)T->mem.get((size_t)nb * 32 * 16);
-    u128 *tjd = (u128 *)T->mem.get(32 * 16);
-    if (!T->eta || !T->pre || !part || !tjd) { T->mem.put(part); T->mem.put(tjd); return set_error(SCC_ENOMEM, "totals"); }
+    if (!T->eta || !T->pre || !part) { T->mem.put(part); return set_error(SCC_ENOMEM, "totals"); }
+    u128 *tjd = (u128 *)(T->dsum + DSUM_TJ);
     if (n) hipLaunchKernelGGL(k_totals, dim3((unsigned)nb), dim3(256), 0, st, g, T->dlut, view(T->lev[k]), zero ? 1 : 0, T->eta, part);
     hipLaunchKernelGGL(k_reduce_parts, dim3((unsigned)T->hlut.num_unr), dim3(256), 0, st, part, (int)(n ? nb : 0),
                        T->hlut.num_unr, tjd);
-    u128 tj[32];
-    hipError_t e = hipMemcpyAsync(tj, tjd, sizeof tj, hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    T->mem.put(part);
-    T->mem.put(tjd);
-    if (e != hipSuccess) return set_error(SCC_EDEVICE, "totals: %s", hipGetErrorString(e));
+    T->mem.put(part);   // stream-ordered
     scc_status s = scan_u128(T, T->eta, T->pre, n);
     if (s) return s;
-    u128 tot = 0;
-    if (n) {
-        HIP_TRY(hipMemcpyAsync(&tot, T->pre + (n - 1), 16, hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipStreamSynchronize(st));
+    if (n) HIP_TRY(hipMemcpyAsync(T->dsum + DSUM_TOT, T->pre + (n - 1), 16, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipGetLastError());
+    return SCC_OK;
+}
+
+// finish half: one read of the device summary (waits for the table's stream)
+static scc_status totals_finish(scc_table *T)
+{
+    uint64_t h[DSUM_WORDS];
+    hipError_t e = hipMemcpyAsync(h, T->dsum, sizeof h, hipMemcpyDeviceToHost, T->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(T->stream);
+    if (e != hipSuccess) return set_error(SCC_EDEVICE, "totals: %s", hipGetErrorString(e));
+    const int k = T->k;
+    const bool zero = T->rooting == SCC_ROOT_ZERO;
+    for (int lv = 2; lv <= k; lv++) {
+        T->lev[lv].nnz = (int64_t)h[2 * lv];
+        T->lev[lv].wide = (int64_t)h[2 * lv + 1];
     }
+    T->lev[1].nnz = T->n;
+    const u128 tot = T->n ? mk128(h[DSUM_TOT], h[DSUM_TOT + 1]) : (u128)0;
     T->root_total = tot;
-    for (int j = 0; j < T->hlut.num_unr; j++) T->tj[j] = zero ? tj[j] : tj[j] / (u128)k;
+    for (int j = 0; j < T->hlut.num_unr; j++) {
+        const u128 tj = mk128(h[DSUM_TJ + 2 * j], h[DSUM_TJ + 2 * j + 1]);
+        T->tj[j] = zero ? tj : tj / (u128)k;
+    }
     T->t = zero ? tot : tot / (u128)k;
     return SCC_OK;
+}
+
+static scc_status build_totals(scc_table *T)
+{
+    scc_status s = totals_launch(T);
+    return s ? s : totals_finish(T);
 }
 
 static scc_status make_key_maps(scc_table *T)
@@ -1039,7 +1223,9 @@ static scc_status make_key_maps(scc_table *T)
     T->key_sidx = (int16_t *)T->alloc(sidx.size() * 2);
     T->key_xidx = (int16_t *)T->alloc(xidx.size() * 2);
     T->dlut = (DevLut *)T->alloc(sizeof(DevLut));
-    if (!T->key_sidx || !T->key_xidx || !T->dlut) return set_error(SCC_ENOMEM, "lookup tables");
+    T->dsum = (uint64_t *)T->alloc(DSUM_WORDS * 8);
+    if (!T->key_sidx || !T->key_xidx || !T->dlut || !T->dsum) return set_error(SCC_ENOMEM, "lookup tables");
+    HIP_TRY(hipMemsetAsync(T->dsum, 0, DSUM_WORDS * 8, T->stream));
     HIP_TRY(hipMemcpyAsync(T->key_sidx, sidx.data(), sidx.size() * 2, hipMemcpyHostToDevice, T->stream));
     HIP_TRY(hipMemcpyAsync(T->key_xidx, xidx.data(), xidx.size() * 2, hipMemcpyHostToDevice, T->stream));
     HIP_TRY(hipMemcpyAsync(T->dlut, &T->hlut, sizeof(DevLut), hipMemcpyHostToDevice, T->stream));
@@ -1177,13 +1363,15 @@ struct BInst {
 };
 
 struct BatchArgs {
-    const BItem *items;
+    const BItem *__restrict__ items;
     int64_t nitems;
-    const BInst *inst;
+    const BInst *__restrict__ inst;
     int *counters;
     unsigned long long *ticket;
     int *err;                      // [0] overflow bits, [1] waits that hit the time limit, [2] abort flag
     unsigned long long wait_ticks; // limit of one wait in wall-clock ticks
+    uint64_t *hi_scratch;          // per worker: high words of X and S for vertices that need 128 bits
+    int64_t hi_stride;             // words per worker
 };
 
 __device__ inline long long wave_uniform64(unsigned long long x)
@@ -1224,16 +1412,20 @@ __global__ void __launch_bounds__(WAVE) k_batch(BatchArgs B)
                 }
             }
         }
-        __threadfence();       // acquire: the producers' writes are visible from here on
+        // acquire: the producers' writes are visible from here on
+        if (I.dep >= 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         if (!abort) {
-            const BInst &P = B.inst[I.inst];
+            // the instance blocks do not change during the launch: reading them through
+            // the constant address space keeps their fields in scalar registers
+            const BInst &P = *(const BInst *)((const __attribute__((address_space(4))) BInst *)B.inst + I.inst);
             switch (I.phase) {
             case BI_G1:
                 for (int64_t v = I.a; v < I.b; v++) gather1_vertex(P.g, P.k, P.S1, P.M1, v, cnt1);
                 break;
             case BI_COMBINE:
                 for (int64_t v = I.a; v < I.b; v++) {
-                    combine_vertex<true>(P.C[I.h], v, sm);
+                    combine_vertex<true>(P.C[I.h], v, sm, B.hi_scratch + (size_t)blockIdx.x * B.hi_stride, nullptr,
+                                         nullptr);
                     __syncthreads();
                 }
                 break;
@@ -1249,9 +1441,44 @@ __global__ void __launch_bounds__(WAVE) k_batch(BatchArgs B)
             }
         }
         __syncthreads();
-        __threadfence();       // release: this item's writes before its completion count
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");   // this item's writes before its completion count
         atomicAdd(&B.counters[I.done], (int)one);
     }
+}
+
+// vertex bounds of the cost-split items: item q of s covers the vertices whose
+// running cost (degree + SPLIT_C0 per vertex) lies in [q total / s, (q + 1) total / s)
+constexpr int64_t SPLIT_C0 = 16;
+
+__global__ void k_item_bounds(BItem *items, int64_t nitems, const BInst *inst)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nitems) return;
+    BItem I = items[i];
+    if (I.pad != 1) return;
+    const GraphView g = inst[I.inst].g;
+    const int64_t e0 = g.row_ptr[0];
+    const u128 total = (u128)(g.row_ptr[g.n] - e0 + SPLIT_C0 * g.n);
+    const int64_t s = I.b;
+    int64_t b[2];
+    for (int r = 0; r < 2; r++) {
+        const int64_t q = I.a + r;
+        if (q <= 0) { b[r] = 0; continue; }
+        if (q >= s) { b[r] = g.n; continue; }
+        // smallest v with cost(v) * s >= q * total
+        const u128 target = (u128)q * total;
+        int64_t lo = 0, hi = g.n;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            const u128 c = (u128)(g.row_ptr[mid] - e0 + SPLIT_C0 * mid) * (u128)s;
+            if (c >= target) hi = mid; else lo = mid + 1;
+        }
+        b[r] = lo;
+    }
+    I.a = b[0];
+    I.b = b[1];
+    I.pad = 0;
+    items[i] = I;
 }
 
 struct BatchInstHost {
@@ -1266,41 +1493,58 @@ struct BatchInstHost {
     u128 *N[SCC_KMAX + 1] = {};
 };
 
-// rows above hub_degree: sorted vertex ids and their row bounds
-scc_status find_hubs(scc_table *T, int hub_degree, std::vector<int32_t> &hh, std::vector<int64_t> &rp)
+// rows above hub_degree in every instance: sorted vertex ids and their row
+// bounds, with three waits for the whole batch
+scc_status find_hubs_all(std::vector<BatchInstHost> &H, int hub_degree, hipStream_t st, DevMem &mem,
+                         std::vector<std::vector<int32_t>> &hv, std::vector<std::vector<int64_t>> &hr)
 {
-    hh.clear();
-    rp.clear();
-    const int64_t n = T->n;
-    if (!n) return SCC_OK;
-    hipStream_t st = T->stream;
-    GraphView g{n, T->row_ptr, T->col_idx, T->colors};
-    int32_t *hubs = (int32_t *)T->mem.get((size_t)n * 4 + 8);
-    int *cnt = (int *)T->mem.get(16);
-    if (!hubs || !cnt) { T->mem.put(hubs); T->mem.put(cnt); return set_error(SCC_ENOMEM, "hub list"); }
-    int nh = 0;
-    hipError_t e = hipMemsetAsync(cnt, 0, 4, st);
-    hipLaunchKernelGGL(k_hub_list, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g, hub_degree, hubs, cnt);
-    if (e == hipSuccess) e = hipMemcpyAsync(&nh, cnt, 4, hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e == hipSuccess && nh) {
-        hh.resize(nh);
-        e = hipMemcpyAsync(hh.data(), hubs, (size_t)nh * 4, hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess) e = hipStreamSynchronize(st);
-        std::sort(hh.begin(), hh.end());
-        int64_t *rows = (int64_t *)T->mem.get((size_t)nh * 16 + 16);
-        if (!rows) e = hipErrorOutOfMemory;
-        if (e == hipSuccess) e = hipMemcpyAsync(hubs, hh.data(), (size_t)nh * 4, hipMemcpyHostToDevice, st);
-        if (e == hipSuccess)
-            hipLaunchKernelGGL(k_hub_rows, dim3((unsigned)((nh + 255) / 256)), dim3(256), 0, st, g, hubs, nh, rows);
-        rp.resize(2 * (size_t)nh);
-        if (e == hipSuccess) e = hipMemcpyAsync(rp.data(), rows, (size_t)nh * 16, hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess) e = hipStreamSynchronize(st);
-        T->mem.put(rows);
+    const int ni = (int)H.size();
+    hv.assign(ni, {});
+    hr.assign(ni, {});
+    std::vector<int32_t *> ids(ni, nullptr);
+    int *cnt = (int *)mem.get((size_t)ni * 4 + 64);
+    struct Free {
+        DevMem &m; std::vector<int32_t *> &a; int *c;
+        ~Free() { for (auto *p : a) m.put(p); m.put(c); }
+    } fr{mem, ids, cnt};
+    if (!cnt) return set_error(SCC_ENOMEM, "hub counts");
+    HIP_TRY(hipMemsetAsync(cnt, 0, (size_t)ni * 4, st));
+    for (int i = 0; i < ni; i++) {
+        scc_table *T = H[i].T;
+        if (!T->n) continue;
+        ids[i] = (int32_t *)mem.get((size_t)T->n * 4 + 8);
+        if (!ids[i]) return set_error(SCC_ENOMEM, "hub list");
+        GraphView g{T->n, T->row_ptr, T->col_idx, T->colors};
+        hipLaunchKernelGGL(k_hub_list, dim3((unsigned)((T->n + 255) / 256)), dim3(256), 0, st, g, hub_degree, ids[i],
+                           cnt + i);
     }
-    T->mem.put(hubs);
-    T->mem.put(cnt);
-    if (e != hipSuccess) return set_error(SCC_EDEVICE, "hub list: %s", hipGetErrorString(e));
+    std::vector<int> nh(ni, 0);
+    HIP_TRY(hipMemcpyAsync(nh.data(), cnt, (size_t)ni * 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    bool any = false;
+    for (int i = 0; i < ni; i++) {
+        if (!nh[i]) continue;
+        any = true;
+        hv[i].resize(nh[i]);
+        HIP_TRY(hipMemcpyAsync(hv[i].data(), ids[i], (size_t)nh[i] * 4, hipMemcpyDeviceToHost, st));
+    }
+    if (!any) return SCC_OK;
+    HIP_TRY(hipStreamSynchronize(st));
+    std::vector<int64_t *> rows(ni, nullptr);
+    struct FreeRows { DevMem &m; std::vector<int64_t *> &a; ~FreeRows() { for (auto *p : a) m.put(p); } } frr{mem, rows};
+    for (int i = 0; i < ni; i++) {
+        if (!nh[i]) continue;
+        std::sort(hv[i].begin(), hv[i].end());
+        scc_table *T = H[i].T;
+        rows[i] = (int64_t *)mem.get((size_t)nh[i] * 16 + 16);
+        if (!rows[i]) return set_error(SCC_ENOMEM, "hub rows");
+        HIP_TRY(hipMemcpyAsync(ids[i], hv[i].data(), (size_t)nh[i] * 4, hipMemcpyHostToDevice, st));
+        GraphView g{T->n, T->row_ptr, T->col_idx, T->colors};
+        hipLaunchKernelGGL(k_hub_rows, dim3((unsigned)((nh[i] + 255) / 256)), dim3(256), 0, st, g, ids[i], nh[i], rows[i]);
+        hr[i].resize(2 * (size_t)nh[i]);
+        HIP_TRY(hipMemcpyAsync(hr[i].data(), rows[i], (size_t)nh[i] * 16, hipMemcpyDeviceToHost, st));
+    }
+    HIP_TRY(hipStreamSynchronize(st));
     return SCC_OK;
 }
 
@@ -1312,45 +1556,6 @@ std::mutex g_tune_mu;
 std::map<TuneKey, std::pair<int, int>> g_tune;
 
 }  // namespace
-
-// the pack step of one level from explicit slot arrays (shared with the plain build)
-static scc_status pack_level(scc_table *T, int h, const uint32_t *meta, const u128 *Nsc, const uint16_t *slot_key,
-                             const uint64_t *slot_lo, const uint64_t *slot_hi, uint64_t *words,
-                             unsigned long long *flags)
-{
-    const DevLut &HL = T->hlut;
-    const int64_t n = T->n;
-    hipStream_t st = T->stream;
-    TableLevel &Lv = T->lev[h];
-    if (!Lv.loc) {
-        Lv.loc = (uint64_t *)T->alloc((size_t)n * 8 + 8);
-        if (!Lv.loc) return set_error(SCC_ENOMEM, "level %d locators", h);
-    }
-    if (n) hipLaunchKernelGGL(k_words, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, meta, words);
-    scc_status sst = scan_incl<uint64_t>(T, words, words, n);
-    if (sst) return sst;
-    uint64_t total = 0;
-    if (n) {
-        HIP_TRY(hipMemcpyAsync(&total, words + (n - 1), 8, hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipStreamSynchronize(st));
-    }
-    Lv.pool_words = total;
-    Lv.pool = (uint64_t *)T->alloc((size_t)total * 8 + 64);
-    Lv.BW = (HL.W[h] + 63) / 64;
-    Lv.bm = (uint64_t *)T->alloc((size_t)n * Lv.BW * 8 + 8);
-    if (!Lv.pool || !Lv.bm) return set_error(SCC_ENOMEM, "level %d pool (%llu words)", h, (unsigned long long)total);
-    if (n) hipLaunchKernelGGL(k_pack, dim3(grid_of(n)), dim3(WAVE), 0, st, n, HL.W[h], meta, words, slot_key, slot_lo,
-                              slot_hi, Nsc, Lv.pool, Lv.loc, T->key_xidx, HL.nkeys, T->colors, Lv.bm, Lv.BW);
-    HIP_TRY(hipMemsetAsync(flags, 0, 2 * sizeof(unsigned long long), st));
-    if (n) hipLaunchKernelGGL(k_meta_sum, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 1024)), dim3(256), 0, st, n,
-                              meta, flags);
-    unsigned long long cnt2[2];
-    HIP_TRY(hipMemcpyAsync(cnt2, flags, sizeof cnt2, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    Lv.nnz = (int64_t)cnt2[0];
-    Lv.wide = (int64_t)cnt2[1];
-    return SCC_OK;
-}
 
 static scc_table *new_table(const scc_csr *g, const uint8_t *colors, int k, const scc_build_opts &o)
 {
@@ -1369,16 +1574,15 @@ static scc_table *new_table(const scc_csr *g, const uint8_t *colors, int k, cons
 // One persistent launch over all instances, for one (tile, hub) choice.
 // Assumes the per-instance storage exists; fills slots and neighbour sums.
 static scc_status batch_launch(std::vector<BatchInstHost> &H, int tile, int hub_degree, hipStream_t st,
-                               DevMem &mem, float *ms_out, int64_t *nitems_out, int *grid_out)
+                               DevMem &mem, float *ms_out, int64_t *nitems_out, int *grid_out,
+                               std::vector<std::vector<int32_t>> &hv, std::vector<std::vector<int64_t>> &hr)
 {
     const int ni = (int)H.size();
     int kmax = 0;
     for (auto &x : H) kmax = std::max(kmax, x.T->k);
     // hubs for this threshold
-    std::vector<std::vector<int32_t>> hv(ni);
-    std::vector<std::vector<int64_t>> hr(ni);
-    for (int i = 0; i < ni; i++) {
-        scc_status s = find_hubs(H[i].T, hub_degree, hv[i], hr[i]);
+    {
+        scc_status s = find_hubs_all(H, hub_degree, st, mem, hv, hr);
         if (s) return s;
     }
     // counters: per instance, S-ready[h] (h = 1..k-1) and X-ready[h] (h = 2..k)
@@ -1386,21 +1590,28 @@ static scc_status batch_launch(std::vector<BatchInstHost> &H, int tile, int hub_
     auto cX = [&](int i, int h) { return i * 2 * (SCC_KMAX + 1) + (SCC_KMAX + 1) + h; };
     std::vector<BItem> items;
     std::vector<std::vector<int>> nS(ni, std::vector<int>(SCC_KMAX + 1, 0)), nX(ni, std::vector<int>(SCC_KMAX + 1, 0));
-    auto tiles = [&](int i, int16_t h, int16_t ph, int dep, int need, int done) {
-        int c = 0;
-        for (int64_t a = 0; a < H[i].T->n; a += tile) {
+    // Each (instance, phase) is cut into nt items: ceil(n / tile), but at least
+    // min(64, ceil(n / 32)) so that a small instance still spreads over many
+    // workers. Combine items are runs of consecutive vertices (their work hardly
+    // depends on the degree); gather items are ranges of equal edge cost, whose
+    // vertex bounds k_item_bounds finds on the device.
+    auto tiles = [&](int i, int16_t h, int16_t ph, int dep, int need, int done, bool by_cost) {
+        const int64_t n = H[i].T->n;
+        const int64_t nt = std::max<int64_t>((n + tile - 1) / tile, std::min<int64_t>(64, (n + 31) / 32));
+        const int64_t per = nt ? (n + nt - 1) / nt : 0;
+        for (int64_t q = 0; q < nt; q++) {
             BItem it{};
             it.inst = i; it.h = h; it.phase = ph; it.dep = dep; it.need = need; it.done = done;
-            it.a = a; it.b = std::min<int64_t>(H[i].T->n, a + tile);
+            if (by_cost) { it.pad = 1; it.a = q; it.b = nt; }
+            else { it.a = std::min<int64_t>(n, q * per); it.b = std::min<int64_t>(n, (q + 1) * per); }
             items.push_back(it);
-            c++;
         }
-        return c;
+        return (int)nt;
     };
-    for (int i = 0; i < ni; i++) nS[i][1] = tiles(i, 1, BI_G1, -1, 0, cS(i, 1));
+    for (int i = 0; i < ni; i++) nS[i][1] = tiles(i, 1, BI_G1, -1, 0, cS(i, 1), true);
     for (int h = 2; h <= kmax; h++) {
         for (int i = 0; i < ni; i++)
-            if (H[i].T->k >= h) nX[i][h] = tiles(i, (int16_t)h, BI_COMBINE, cS(i, h - 1), nS[i][h - 1], cX(i, h));
+            if (H[i].T->k >= h) nX[i][h] = tiles(i, (int16_t)h, BI_COMBINE, cS(i, h - 1), nS[i][h - 1], cX(i, h), false);
         for (int i = 0; i < ni; i++) {
             if (H[i].T->k - 1 < h) continue;
             int c = 0;
@@ -1413,7 +1624,7 @@ static scc_status batch_launch(std::vector<BatchInstHost> &H, int tile, int hub_
                     items.push_back(it);
                     c++;
                 }
-            c += tiles(i, (int16_t)h, BI_GATHER, cX(i, h), nX[i][h], cS(i, h));
+            c += tiles(i, (int16_t)h, BI_GATHER, cX(i, h), nX[i][h], cS(i, h), true);
             nS[i][h] = c;
         }
     }
@@ -1476,18 +1687,21 @@ static scc_status batch_launch(std::vector<BatchInstHost> &H, int tile, int hub_
         HIP_TRY(hipMemcpyAsync(dh, hv[i].data(), hv[i].size() * 4, hipMemcpyHostToDevice, st));
         for (int h = 2; h < H[i].T->k; h++)
             hipLaunchKernelGGL(k_hub_prepare, dim3((unsigned)hv[i].size()), dim3(WAVE), 0, st, inst[i].G[h], dh);
-        HIP_TRY(hipStreamSynchronize(st));
-        mem.put(dh);
+        mem.put(dh);   // stream-ordered
     }
-    // LDS: the largest need over the instances' gathers and combines
+    // LDS: the largest need over the instances' gathers and combines (low words;
+    // a combine's high words go to the worker's global scratch)
     size_t lds = 0;
+    int64_t hi_stride = 0;
     for (int i = 0; i < ni; i++) {
         const DevLut &HL = H[i].T->hlut;
         for (int h = 2; h <= H[i].T->k; h++) {
-            lds = std::max(lds, (size_t)(2 * HL.xoff[h] + 2 * HL.soff[h]) * 8);
+            lds = std::max(lds, (size_t)(HL.xoff[h] + HL.soff[h]) * 8);
+            hi_stride = std::max<int64_t>(hi_stride, HL.xoff[h] + HL.soff[h]);
             if (h < H[i].T->k) lds = std::max(lds, (size_t)2 * HL.WS[h] * 8);
         }
     }
+    hi_stride = (hi_stride + 31) & ~(int64_t)31;
     int dev = 0, ncu = 0, per_cu = 0;
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
@@ -1497,8 +1711,14 @@ static scc_status batch_launch(std::vector<BatchInstHost> &H, int tile, int hub_
     int wc_khz = 0;
     HIP_TRY(hipDeviceGetAttribute(&wc_khz, hipDeviceAttributeWallClockRate, dev));
     if (wc_khz <= 0) wc_khz = 100000;
+    uint64_t *dhi = (uint64_t *)mem.get((size_t)grid * hi_stride * 8 + 64);
+    if (!dhi) return set_error(SCC_ENOMEM, "batch high-word scratch");
+    struct FreeHi { DevMem &m; void *p; ~FreeHi() { m.put(p); } } frh{mem, dhi};
+    hipLaunchKernelGGL(k_item_bounds, dim3((unsigned)((items.size() + 255) / 256)), dim3(256), 0, st, ditems,
+                       (int64_t)items.size(), dinst);
     // a dependency wait longer than 10 s means something is wrong: the launch drains and reports it
-    BatchArgs BA{ditems, (int64_t)items.size(), dinst, dcnt, dtick, derr, (unsigned long long)wc_khz * 1000ull * 10ull};
+    BatchArgs BA{ditems, (int64_t)items.size(), dinst, dcnt, dtick, derr, (unsigned long long)wc_khz * 1000ull * 10ull,
+                 dhi, hi_stride};
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
@@ -1596,13 +1816,15 @@ extern "C" scc_status scc_build_batch(const scc_instance *inst, int n_inst, cons
         if (it != g_tune.end()) { tile = it->second.first; hubd = it->second.second; tuned = true; }
     }
     if (bo.autotune && !tuned) {
-        const int tiles[] = {32, 128, 512, 2048};
-        const int hubs[] = {512, 2048};
+        const int tiles[] = {128, 256, 512, 1024};
+        const int hubs[] = {512, 2048, 8192};
         float best = 1e30f;
         for (int t : tiles)
             for (int hd : hubs) {
                 float ms = 0;
-                scc_status s = batch_launch(H, t, hd, st, mem, &ms, nullptr, nullptr);
+                std::vector<std::vector<int32_t>> hv;
+                std::vector<std::vector<int64_t>> hr;
+                scc_status s = batch_launch(H, t, hd, st, mem, &ms, nullptr, nullptr, hv, hr);
                 if (s) return fail(s);
                 if (R.nprobe < 16) { R.probe_tile[R.nprobe] = t; R.probe_hub[R.nprobe] = hd; R.probe_ms[R.nprobe] = ms; R.nprobe++; }
                 if (ms < best) { best = ms; tile = t; hubd = hd; }
@@ -1615,37 +1837,107 @@ extern "C" scc_status scc_build_batch(const scc_instance *inst, int n_inst, cons
     float ms = 0;
     int64_t nitems = 0;
     int grid = 0;
-    scc_status s = batch_launch(H, tile, hubd, st, mem, &ms, &nitems, &grid);
+    std::vector<std::vector<int32_t>> hub_v;
+    std::vector<std::vector<int64_t>> hub_r;
+    scc_status s = batch_launch(H, tile, hubd, st, mem, &ms, &nitems, &grid, hub_v, hub_r);
     if (s) return fail(s);
     auto t_pack = std::chrono::steady_clock::now();
-    // standard tables: pack every level, then totals
+    // standard tables, every (instance, level) at once: record sizes and running
+    // sums, one read of all pool sizes, one allocation per instance for its pools,
+    // locators and bitmaps, then the records; then the totals and one read per table
+    std::vector<PackJobDev> jobs;
+    std::vector<std::pair<int, int>> job_of;   // (instance, level)
+    std::vector<void *> pack_scratch;
+    struct FreeScratch {
+        std::vector<void *> &v; DevMem &m;
+        ~FreeScratch() { for (void *p : v) m.put(p); }
+    } frs{pack_scratch, mem};
+    auto sget = [&](size_t bytes) { void *p = mem.get(bytes); if (p) pack_scratch.push_back(p); return p; };
+    int64_t maxn = 0, maxnb = 1;
     for (int i = 0; i < n_inst; i++) {
         scc_table *T = H[i].T;
         const int64_t n = T->n;
-        uint64_t *words = (uint64_t *)T->mem.get((size_t)n * 8 + 64);
-        unsigned long long *flags = (unsigned long long *)T->mem.get(64);
-        if (!words || !flags) { T->mem.put(words); T->mem.put(flags); return fail(set_error(SCC_ENOMEM, "pack scratch")); }
-        for (int h = 2; h <= T->k && !s; h++)
-            s = pack_level(T, h, H[i].meta[h], H[i].N[h], H[i].skey[h], H[i].slo[h], H[i].shi[h], words, flags);
-        T->mem.put(words);
-        T->mem.put(flags);
-        if (s) return fail(s);
+        maxn = std::max(maxn, n);
+        const int64_t nb = std::max<int64_t>(1, (n + SCAN_TILE - 1) / SCAN_TILE);
+        maxnb = std::max(maxnb, nb);
+        uint64_t *words = (uint64_t *)sget((size_t)n * 8 * (T->k - 1) + 64);
+        uint64_t *bsum = (uint64_t *)sget((size_t)nb * 8 * (T->k - 1) + 64);
+        if (!words || !bsum) return fail(set_error(SCC_ENOMEM, "pack scratch"));
         for (int h = 2; h <= T->k; h++) {
+            PackJobDev J{};
+            J.n = n; J.W = T->hlut.W[h]; J.BW = (J.W + 63) / 64; J.nkeys = T->hlut.nkeys;
+            J.meta = H[i].meta[h]; J.words = words + (size_t)n * (h - 2); J.bsum = bsum + (size_t)nb * (h - 2);
+            J.skey = H[i].skey[h]; J.slo = H[i].slo[h]; J.shi = H[i].shi[h]; J.N = H[i].N[h];
+            J.key_xidx = T->key_xidx; J.colors = T->colors;
+            J.stats = (unsigned long long *)T->dsum + 2 * h;
+            jobs.push_back(J);
+            job_of.push_back({i, h});
+        }
+    }
+    const int nj = (int)jobs.size();
+    uint64_t *dtot = (uint64_t *)sget((size_t)nj * 8 + 64);
+    PackJobDev *djobs = (PackJobDev *)sget((size_t)nj * sizeof(PackJobDev) + 64);
+    if (!dtot || !djobs) return fail(set_error(SCC_ENOMEM, "pack jobs"));
+    for (int j = 0; j < nj; j++) jobs[j].total = dtot + j;
+    HIP_TRY(hipMemcpyAsync(djobs, jobs.data(), (size_t)nj * sizeof(PackJobDev), hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_mpack_sums, dim3((unsigned)maxnb, (unsigned)nj), dim3(SCAN_T), 0, st, djobs);
+    hipLaunchKernelGGL(k_mpack_top, dim3((unsigned)nj), dim3(SCAN_T), 0, st, djobs);
+    hipLaunchKernelGGL(k_mpack_apply, dim3((unsigned)maxnb, (unsigned)nj), dim3(SCAN_T), 0, st, djobs);
+    std::vector<uint64_t> htot(nj);
+    HIP_TRY(hipMemcpyAsync(htot.data(), dtot, (size_t)nj * 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    {
+        int j = 0;
+        for (int i = 0; i < n_inst; i++) {
+            scc_table *T = H[i].T;
+            const int64_t n = T->n;
+            size_t pool_w = 0, bm_w = 0;
+            for (int h = 2; h <= T->k; h++) {
+                pool_w += (size_t)htot[j + h - 2] + 8;
+                bm_w += (size_t)n * ((T->hlut.W[h] + 63) / 64);
+            }
+            uint64_t *pool = (uint64_t *)T->alloc(pool_w * 8 + 64);
+            uint64_t *loc = (uint64_t *)T->alloc((size_t)n * 8 * (T->k - 1) + 64);
+            uint64_t *bm = (uint64_t *)T->alloc(bm_w * 8 + 64);
+            if (!pool || !loc || !bm) return fail(set_error(SCC_ENOMEM, "instance %d pools (%zu words)", i, pool_w));
+            size_t po = 0, bo = 0;
+            for (int h = 2; h <= T->k; h++, j++) {
+                TableLevel &Lv = T->lev[h];
+                Lv.pool = pool + po;
+                Lv.pool_words = htot[j];
+                Lv.loc = loc + (size_t)n * (h - 2);
+                Lv.BW = jobs[j].BW;
+                Lv.bm = bm + bo;
+                po += (size_t)htot[j] + 8;
+                bo += (size_t)n * Lv.BW;
+                jobs[j].pool = Lv.pool; jobs[j].loc = Lv.loc; jobs[j].bm = Lv.bm;
+            }
+        }
+    }
+    HIP_TRY(hipMemcpyAsync(djobs, jobs.data(), (size_t)nj * sizeof(PackJobDev), hipMemcpyHostToDevice, st));
+    if (maxn)
+        hipLaunchKernelGGL(k_mpack, dim3((unsigned)std::min<int64_t>(maxn, 2048), (unsigned)nj), dim3(WAVE), 0, st, djobs);
+    for (int i = 0; i < n_inst; i++)
+        for (int h = 2; h <= H[i].T->k; h++) {   // stream-ordered releases
+            scc_table *T = H[i].T;
             T->mem.put(H[i].skey[h]); T->mem.put(H[i].slo[h]); T->mem.put(H[i].shi[h]);
             T->mem.put(H[i].meta[h]); T->mem.put(H[i].N[h]);
-            H[i].skey[h] = nullptr; H[i].slo[h] = nullptr; H[i].shi[h] = nullptr; H[i].meta[h] = nullptr; H[i].N[h] = nullptr;
+            H[i].skey[h] = nullptr; H[i].slo[h] = nullptr; H[i].shi[h] = nullptr;
+            H[i].meta[h] = nullptr; H[i].N[h] = nullptr;
         }
-        T->lev[1].nnz = T->n;
+    HIP_TRY(hipGetLastError());
+    for (int i = 0; i < n_inst; i++) {
+        scc_table *T = H[i].T;
         // hub list of the chosen threshold, for the sampler's running sums
-        std::vector<int32_t> hh;
-        std::vector<int64_t> rp;
-        s = find_hubs(T, hubd, hh, rp);
-        if (s) return fail(s);
         T->hub_degree = hubd;
-        T->nhub = (int)hh.size();
-        T->hub_host = hh;
-        T->hub_rows_host = rp;
-        s = build_totals(T);
+        T->nhub = (int)hub_v[i].size();
+        T->hub_host = hub_v[i];
+        T->hub_rows_host = hub_r[i];
+        s = totals_launch(T);
+        if (s) return fail(s);
+    }
+    for (int i = 0; i < n_inst; i++) {
+        s = totals_finish(H[i].T);
         if (s) return fail(s);
     }
     auto t_end = std::chrono::steady_clock::now();

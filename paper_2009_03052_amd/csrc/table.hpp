@@ -41,6 +41,9 @@ struct scc_table {
     u128 t = 0;                      // colourful k-treelet copies
     u128 tj[32] = {0};
     u128 root_total = 0;             // sum of eta (k * t under SCC_ROOT_ALL)
+    // device summary read once at the end of a build: [2h], [2h+1] = stored entries and
+    // 128-bit vertices of level h; then 32 u128 per-shape totals; then the root total
+    uint64_t *dsum = nullptr;
     std::map<int, u128 *> pre_shape; // per unrooted shape: running sums, built on demand
     std::map<int, u128> tot_shape;
     std::mutex mu;
