@@ -283,6 +283,96 @@ typedef struct {
 scc_status scc_build_batch(const scc_instance *inst, int n_inst, const scc_build_opts *opt,
                            const scc_batch_opts *bopt, scc_table **out, scc_batch_report *rep);
 
+/* ------------------------------------------------------------------------
+ * Serving. A server keeps tables resident and answers sampling requests: it
+ * admits them in submission order while their outputs fit a device-memory
+ * budget, and interleaves the samples of all admitted requests into steps of
+ * one sampler launch, so that a request arriving while others run starts at
+ * the next step (continuous batching). Every sample is fixed by its table,
+ * shape and (seed, stream, index) as in scc_sample, so a request's rows are the
+ * same alone and inside any mix of requests. AGS sessions run the rounds of
+ * adaptive graphlet sampling (Sec. 4.1) as requests; a session's rounds run
+ * one after another, each with the shape chosen after the previous rounds,
+ * exactly as scc_ags chooses them.
+ * ------------------------------------------------------------------------ */
+typedef struct scc_server scc_server;
+
+typedef struct {
+    const scc_table *const *tables; /* resident tables, borrowed: they must outlive the server */
+    int n_tables;
+    int64_t hbm_budget;      /* bytes of device memory for the outputs of admitted requests,
+                                allocated once at creation (0 = 1 GiB) */
+    int max_pending;         /* submitted requests waiting for admission; beyond it
+                                scc_server_submit returns EBUSY (0 = 4096) */
+    int max_active;          /* admitted requests that run at once (0 = 256) */
+    int64_t step_samples;    /* samples per step when many requests share it (0 = 2^18) */
+    int64_t chunk;           /* smallest share of a request in one step (0 = 8192) */
+    int grid;                /* sampler workgroups (one wave each) per step (0 = 8192) */
+    int fifo;                /* nonzero: one whole request per step, in submission order
+                                (the plain first-in first-out server, for comparison) */
+    void *stream;            /* hipStream_t of the server's work (NULL: its own stream) */
+    const scc_allocator *alloc; /* for the budget and the server's buffers (NULL: hipMalloc) */
+} scc_server_opts;
+
+enum { SCC_REQ_SAMPLE = 0, SCC_REQ_AGS_ROUND = 1 };
+
+typedef struct {
+    int kind;                /* SCC_REQ_SAMPLE or SCC_REQ_AGS_ROUND */
+    int table;               /* index into scc_server_opts.tables */
+    int shape;               /* SAMPLE: -1 uniform, else an unrooted shape id (AGS: the session's) */
+    int classify;            /* SAMPLE: nonzero to also return classes (AGS rounds always classify) */
+    int session;             /* AGS_ROUND: id from scc_server_ags_open, on the same table */
+    int64_t n;               /* samples, >= 1 */
+    uint64_t seed, stream_id, first_index; /* SAMPLE: as for scc_sample (AGS: the session's, the
+                                             round starting where the previous one ended) */
+} scc_request;
+
+typedef struct {
+    int64_t id;
+    int status;              /* SCC_OK, EDEVICE, or EBUSY for a request dropped at destruction */
+    int k, shape;            /* shape the rows were drawn with */
+    int64_t n;
+    uint64_t first_index;    /* random index of row 0 */
+    const int32_t *verts;    /* device, n x k as scc_sample; valid until scc_server_release */
+    const int8_t *parent;    /* device, n x k */
+    const uint32_t *cls;     /* device, n classes as scc_classify, or NULL */
+    double t_submit, t_admit, t_start, t_done; /* seconds since the server was created */
+} scc_result;
+
+typedef struct {
+    int64_t submitted, completed, rejected, samples, steps;
+    int64_t arena_peak, arena_used;   /* bytes of the budget in use: most ever, now */
+    double busy_s;           /* host time spent waiting for steps to finish */
+    double span_s;           /* first submission to last completion */
+    double p50_ms, p99_ms, mean_ms, max_ms; /* latency, submission to completion */
+} scc_server_stats;
+
+/* Builds every running sum the tables' samplers need (all shapes), the class
+   lookup tables, the budget arena and the step buffers, then starts the
+   server's thread. Errors: EINVAL, ENOMEM, EDEVICE, or a table's EEMPTY. */
+scc_status scc_server_create(const scc_server_opts *opt, scc_server **out);
+/* Opens an AGS session on table `table` with threshold cbar and random stream
+   (seed, stream_id); EEMPTY when the table has no colourful k-treelet. */
+scc_status scc_server_ags_open(scc_server *s, int table, int64_t cbar, uint64_t seed, uint64_t stream_id,
+                               int *session);
+/* A session's state after its finished rounds, as scc_ags reports it
+   (hits, w and n_j sized as there; up to `cap` round shapes). */
+scc_status scc_server_ags_result(scc_server *s, int session, int64_t *hits, double *w, int64_t *n_j,
+                                 int32_t *round_shapes, int64_t cap, int64_t *n_rounds);
+/* Queues a request. EBUSY: max_pending requests already wait (not queued);
+   ENOMEM: its outputs alone exceed the budget; EINVAL; EEMPTY: nothing to sample. */
+scc_status scc_server_submit(scc_server *s, const scc_request *req, int64_t *id);
+/* Waits up to timeout_s seconds for a request; EBUSY if it has not finished.
+   One waiter per request. */
+scc_status scc_server_wait(scc_server *s, int64_t id, double timeout_s, scc_result *out);
+/* Returns a finished request's outputs to the budget (EBUSY while it runs);
+   its result pointers are invalid afterwards. */
+scc_status scc_server_release(scc_server *s, int64_t id);
+scc_status scc_server_get_stats(scc_server *s, scc_server_stats *out);
+/* Stops the server: requests not yet started are dropped (status EBUSY), the
+   steps in flight finish, and every buffer of the server is freed. */
+void scc_server_destroy(scc_server *s);
+
 /* Frees per-k device lookup tables kept by scc_classify. */
 void scc_release_caches(void);
 

@@ -7,7 +7,9 @@ Importing this package fails loudly when the library is missing.
 
 The names follow the C ABI in ``include/scc.h``: :class:`Table` wraps
 ``scc_build_table`` and the queries on a table (``occ``, ``export_level``,
-``sample``, ``classify``, ``ags``); :func:`catalog` wraps ``scc_catalog``.
+``sample``, ``classify``, ``ags``); :func:`catalog` wraps ``scc_catalog``;
+:func:`build_batch` wraps ``scc_build_batch``; :class:`Server` wraps the
+``scc_server_*`` calls.
 """
 from __future__ import annotations
 
@@ -74,6 +76,34 @@ class TableInfo(C.Structure):
                 ("gather_ms", C.c_double * 9), ("num_hubs", C.c_int)]
 
 
+class _ServerOpts(C.Structure):
+    _fields_ = [("tables", C.POINTER(C.c_void_p)), ("n_tables", C.c_int), ("hbm_budget", C.c_int64),
+                ("max_pending", C.c_int), ("max_active", C.c_int), ("step_samples", C.c_int64), ("chunk", C.c_int64),
+                ("grid", C.c_int), ("fifo", C.c_int), ("stream", C.c_void_p), ("alloc", C.POINTER(_Allocator))]
+
+
+class _Request(C.Structure):
+    _fields_ = [("kind", C.c_int), ("table", C.c_int), ("shape", C.c_int), ("classify", C.c_int),
+                ("session", C.c_int), ("n", C.c_int64), ("seed", C.c_uint64), ("stream_id", C.c_uint64),
+                ("first_index", C.c_uint64)]
+
+
+class _Result(C.Structure):
+    _fields_ = [("id", C.c_int64), ("status", C.c_int), ("k", C.c_int), ("shape", C.c_int), ("n", C.c_int64),
+                ("first_index", C.c_uint64), ("verts", C.c_void_p), ("parent", C.c_void_p), ("cls", C.c_void_p),
+                ("t_submit", C.c_double), ("t_admit", C.c_double), ("t_start", C.c_double), ("t_done", C.c_double)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("rejected", C.c_int64), ("samples", C.c_int64),
+                ("steps", C.c_int64), ("arena_peak", C.c_int64), ("arena_used", C.c_int64), ("busy_s", C.c_double),
+                ("span_s", C.c_double), ("p50_ms", C.c_double), ("p99_ms", C.c_double), ("mean_ms", C.c_double),
+                ("max_ms", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 _P = C.c_void_p
 _i64, _u64, _i32 = C.c_int64, C.c_uint64, C.c_int32
 _SIGS = {
@@ -89,6 +119,14 @@ _SIGS = {
     "scc_ags": (C.c_int, [_P, _i64, _i64, _i64, _u64, _u64, _P, _P, _P, _P, C.POINTER(_i64), _P]),
     "scc_build_batch": (C.c_int, [C.POINTER(_Instance), C.c_int, C.POINTER(_BuildOpts), C.POINTER(_BatchOpts),
                                   C.POINTER(_P), C.POINTER(BatchReport)]),
+    "scc_server_create": (C.c_int, [C.POINTER(_ServerOpts), C.POINTER(_P)]),
+    "scc_server_ags_open": (C.c_int, [_P, C.c_int, _i64, _u64, _u64, C.POINTER(C.c_int)]),
+    "scc_server_ags_result": (C.c_int, [_P, C.c_int, _P, _P, _P, _P, _i64, C.POINTER(_i64)]),
+    "scc_server_submit": (C.c_int, [_P, C.POINTER(_Request), C.POINTER(_i64)]),
+    "scc_server_wait": (C.c_int, [_P, _i64, C.c_double, C.POINTER(_Result)]),
+    "scc_server_release": (C.c_int, [_P, _i64]),
+    "scc_server_get_stats": (C.c_int, [_P, C.POINTER(ServerStats)]),
+    "scc_server_destroy": (None, [_P]),
     "scc_release_caches": (None, []),
     "scc_num_unrooted": (C.c_int, [C.c_int]),
     "scc_last_error": (C.c_char_p, []),
@@ -293,6 +331,103 @@ def build_batch(instances, rooting: int = ROOT_ZERO, max_bits: int = 128, tile: 
     _check(_lib.scc_build_batch(arr, n, C.byref(opts), C.byref(bo), outs, C.byref(rep)))
     tables = [Table._wrap(outs[i], instances[i][0], keep[i], instances[i][2]) for i in range(n)]
     return tables, rep.as_dict()
+
+
+REQ_SAMPLE, REQ_AGS_ROUND = 0, 1
+
+
+class _DeviceArray:
+    """A device buffer of the library seen through __cuda_array_interface__ (no copy)."""
+
+    def __init__(self, ptr: int, shape: tuple, typestr: str):
+        self.__cuda_array_interface__ = {"shape": shape, "typestr": typestr, "data": (int(ptr), False),
+                                         "version": 2, "strides": None}
+
+
+def _device_view(ptr, shape, typestr):
+    if not ptr or 0 in shape:
+        return None
+    return torch.as_tensor(_DeviceArray(ptr, shape, typestr), device="cuda")
+
+
+class Server:
+    """``scc_server_*``: resident tables, admission by a device-memory budget,
+    continuous batching of sample and AGS-round requests."""
+
+    def __init__(self, tables, hbm_budget: int = 1 << 30, max_pending: int = 0, max_active: int = 0,
+                 step_samples: int = 0, chunk: int = 0, grid: int = 0, fifo: bool = False, stream=None,
+                 use_torch_allocator: bool = True):
+        self.tables = list(tables)
+        arr = (C.c_void_p * len(self.tables))(*[t._h.value for t in self.tables])
+        self._arr = arr
+        opts = _ServerOpts(C.cast(arr, C.POINTER(C.c_void_p)), len(self.tables), int(hbm_budget), max_pending,
+                           max_active, step_samples, chunk, grid, 1 if fifo else 0,
+                           C.c_void_p(stream.cuda_stream) if stream is not None else None,
+                           C.pointer(TORCH_ALLOCATOR) if use_torch_allocator else None)
+        h = _P()
+        _check(_lib.scc_server_create(C.byref(opts), C.byref(h)))
+        self._h = h
+
+    def ags_open(self, table: int, cbar: int, seed: int, stream_id: int = 0) -> int:
+        sid = C.c_int()
+        _check(_lib.scc_server_ags_open(self._h, table, cbar, seed, stream_id, C.byref(sid)))
+        return sid.value
+
+    def ags_result(self, session: int, table: int, cap: int = 1 << 16):
+        k = self.tables[table].k
+        s = num_classes(k)
+        nu = self.tables[table].info().num_unrooted
+        hits = np.zeros(s, np.int64)
+        w = np.zeros(s, np.float64)
+        nj = np.zeros(nu, np.int64)
+        shapes = np.zeros(cap, np.int32)
+        nr = _i64()
+        _check(_lib.scc_server_ags_result(self._h, session, hits.ctypes.data_as(_P), w.ctypes.data_as(_P),
+                                          nj.ctypes.data_as(_P), shapes.ctypes.data_as(_P), cap, C.byref(nr)))
+        return {"hits": hits, "w": w, "n_j": nj, "round_shapes": shapes[:min(nr.value, cap)]}
+
+    def submit(self, table: int, n: int, seed: int = 0, stream_id: int = 0, first_index: int = 0, shape: int = -1,
+               classify: bool = False, session: int = -1) -> int:
+        """A sample request, or (session >= 0) the next round of an AGS session."""
+        kind = REQ_AGS_ROUND if session >= 0 else REQ_SAMPLE
+        q = _Request(kind, table, shape, 1 if classify else 0, max(session, 0), n, seed, stream_id, first_index)
+        rid = _i64()
+        _check(_lib.scc_server_submit(self._h, C.byref(q), C.byref(rid)))
+        return rid.value
+
+    def wait(self, rid: int, timeout: float = 120.0, copy: bool = True):
+        r = _Result()
+        _check(_lib.scc_server_wait(self._h, rid, float(timeout), C.byref(r)))
+        out = {"id": r.id, "status": r.status, "k": r.k, "shape": r.shape, "n": r.n, "first_index": r.first_index,
+               "t_submit": r.t_submit, "t_admit": r.t_admit, "t_start": r.t_start, "t_done": r.t_done}
+        v = _device_view(r.verts, (r.n, r.k), "<i4")
+        p = _device_view(r.parent, (r.n, r.k), "|i1")
+        c = _device_view(r.cls, (r.n,), "<u4")
+        if copy:
+            v = v.clone() if v is not None else None
+            p = p.clone() if p is not None else None
+            c = c.clone() if c is not None else None
+        out.update(verts=v, parent=p, cls=c)
+        return out
+
+    def release(self, rid: int):
+        _check(_lib.scc_server_release(self._h, rid))
+
+    def stats(self):
+        st = ServerStats()
+        _check(_lib.scc_server_get_stats(self._h, C.byref(st)))
+        return st.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.scc_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def num_classes(k: int) -> int:

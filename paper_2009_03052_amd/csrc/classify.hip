@@ -17,7 +17,8 @@
 #include <functional>
 #include <unordered_map>
 
-#include "table.hpp"
+#include "ags.hpp"
+#include "sampler.hpp"
 
 namespace {
 
@@ -157,30 +158,61 @@ __device__ inline bool has_edge(const GraphView &g, int32_t a, int32_t b)
     return false;
 }
 
-__global__ void k_classify(GraphView g, int k, const int32_t *verts, int64_t n, const uint16_t *lut,
-                           uint32_t *out_code, uint32_t *out_class)
+// induced adjacency code of one sample (bit q for the q-th pair i < j) and its
+// class through the lookup table; 0xffffffff for both when a vertex id is invalid
+__device__ inline uint32_t classify_row(const GraphView &g, int k, const int32_t *row, const uint16_t *lut,
+                                        uint32_t *code_out)
 {
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n) return;
     int32_t vs[SCC_KMAX];
     bool ok = true;
     for (int i = 0; i < k; i++) {
-        vs[i] = verts[s * k + i];
+        vs[i] = row[i];
         ok = ok && vs[i] >= 0 && vs[i] < g.n;
     }
     if (!ok) {
-        if (out_code) out_code[s] = 0xffffffffu;
-        out_class[s] = 0xffffffffu;
-        return;
+        *code_out = 0xffffffffu;
+        return 0xffffffffu;
     }
     uint32_t code = 0;
     int q = 0;
     for (int i = 0; i < k; i++)
         for (int j = i + 1; j < k; j++, q++)
             if (has_edge(g, vs[i], vs[j])) code |= 1u << q;
-    if (out_code) out_code[s] = code;
+    *code_out = code;
     const uint16_t c = lut[code];
-    out_class[s] = c == 0xffff ? 0xffffffffu : (uint32_t)c;
+    return c == 0xffff ? 0xffffffffu : (uint32_t)c;
+}
+
+__global__ void k_classify(GraphView g, int k, const int32_t *verts, int64_t n, const uint16_t *lut,
+                           uint32_t *out_code, uint32_t *out_class)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    uint32_t code;
+    const uint32_t c = classify_row(g, k, verts + s * k, lut, &code);
+    if (out_code) out_code[s] = code;
+    out_class[s] = c;
+}
+
+// classes of the rows of a serving step (requests without a class output are skipped)
+__global__ void k_serve_classify(const ServeClassArgs *args, const ServeChunk *ch, const int64_t *cend, int nch,
+                                 int64_t total)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= total) return;
+    int lo = 0, hi = nch - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (cend[mid] > s) hi = mid; else lo = mid + 1;
+    }
+    const ServeChunk C = ch[lo];
+    const ServeClassArgs &A = args[C.arg];
+    if (!A.cls) return;
+    const int64_t r = C.off + (s - (cend[lo] - C.count));
+    uint32_t code;
+    const uint32_t c = classify_row(A.g, A.k, A.verts + r * A.k, A.lut, &code);
+    A.cls[r] = c;
+    if (A.hist && c < A.nclass) atomicAdd(&A.hist[c], 1ull);
 }
 
 __global__ void k_hist(const uint32_t *cls, int64_t n, uint32_t nclass, unsigned long long *hist)
@@ -377,79 +409,83 @@ extern "C" void scc_release_caches(void)
     }
 }
 
-extern "C" scc_status scc_ags(const scc_table *tc, int64_t cbar, int64_t round_size, int64_t budget, uint64_t seed,
-                              uint64_t stream_id, int64_t *hits, double *w_out, int64_t *n_j, int32_t *round_shapes,
-                              int64_t *n_rounds, void *stream)
+void launch_serve_classify(const ServeClassArgs *args, const ServeChunk *ch, const int64_t *cend, int nch,
+                           int64_t total, hipStream_t st)
 {
-    scc_table *T = const_cast<scc_table *>(tc);
-    if (!T || !hits || !w_out || !n_j || !n_rounds) return set_error(SCC_EINVAL, "NULL argument");
-    if (cbar < 1 || round_size < 1 || budget < 0) return set_error(SCC_EINVAL, "bad AGS parameters");
-    const int k = T->k;
-    hipStream_t st = stream ? (hipStream_t)stream : T->stream;
+    if (total <= 0 || nch <= 0) return;
+    hipLaunchKernelGGL(k_serve_classify, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, args, ch, cend, nch,
+                       total);
+}
+
+scc_status class_lut(int k, hipStream_t st, const uint16_t **lut, int *num_classes)
+{
     ClassData *cd;
     scc_status s = ensure_classes(k, st, &cd);
     if (s) return s;
-    const int S = (int)cd->codes.size(), NS = T->hlut.num_unr;
-    std::vector<int64_t> c(S, 0), nj(NS, 0);
-    std::vector<double> w(S, 0.0), tjd(NS);
-    std::vector<char> cov(S, 0), sig_ok(S, 0);
-    std::vector<int64_t> sig((size_t)S * NS, 0);
+    *lut = cd->lut;
+    if (num_classes) *num_classes = (int)cd->codes.size();
+    return SCC_OK;
+}
+
+scc_status AgsState::init(const scc_table *T, int64_t cbar_, hipStream_t st)
+{
+    k = T->k;
+    ClassData *cd;
+    scc_status s = ensure_classes(k, st, &cd);
+    if (s) return s;
+    codes = cd->codes;
+    S = (int)codes.size();
+    NS = T->hlut.num_unr;
+    cbar = cbar_;
+    c.assign(S, 0); nj.assign(NS, 0); w.assign(S, 0.0); tjd.assign(NS, 0.0);
+    cov.assign(S, 0); sig_ok.assign(S, 0); sig.assign((size_t)S * NS, 0);
+    shapes.clear();
+    drawn = 0; ncov = 0; j = -1;
     for (int q = 0; q < NS; q++) tjd[q] = (double)T->tj[q];
-    int j = -1;
     for (int q = 0; q < NS; q++)
         if (T->tj[q] > 0 && (j < 0 || T->tj[q] > T->tj[j])) j = q;
     if (j < 0) return set_error(SCC_EEMPTY, "no colourful %d-treelet", k);
-    int32_t *dv = (int32_t *)T->mem.get((size_t)round_size * k * 4);
-    int8_t *dp = (int8_t *)T->mem.get((size_t)round_size * k);
-    uint32_t *dc = (uint32_t *)T->mem.get((size_t)round_size * 4);
-    unsigned long long *dh = (unsigned long long *)T->mem.get((size_t)S * 8);
-    std::vector<unsigned long long> hh(S);
-    auto done = [&](scc_status r) { T->mem.put(dv); T->mem.put(dp); T->mem.put(dc); T->mem.put(dh); return r; };
-    if (!dv || !dp || !dc || !dh) return done(set_error(SCC_ENOMEM, "AGS buffers"));
-    int64_t drawn = 0, nr = 0, ncov = 0;
-    while (ncov < S && drawn + round_size <= budget) {
-        s = scc_sample(T, j, round_size, seed, stream_id, (uint64_t)drawn, dv, dp, st);
-        if (s) return done(s);
-        s = scc_classify(T, dv, round_size, nullptr, dc, st);
-        if (s) return done(s);
-        if (hipMemsetAsync(dh, 0, (size_t)S * 8, st) != hipSuccess) return done(set_error(SCC_EDEVICE, "AGS memset"));
-        hipLaunchKernelGGL(k_hist, dim3((unsigned)((round_size + 255) / 256)), dim3(256), 0, st, dc, round_size, (uint32_t)S, dh);
-        if (hipMemcpyAsync(hh.data(), dh, (size_t)S * 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
-            hipStreamSynchronize(st) != hipSuccess)
-            return done(set_error(SCC_EDEVICE, "AGS histogram"));
-        if (round_shapes) round_shapes[nr] = j;
-        nr++;
-        drawn += round_size;
-        nj[j] += round_size;
-        for (int i = 0; i < S; i++) {
-            if (!hh[i]) continue;
-            c[i] += (int64_t)hh[i];
-            if (!sig_ok[i]) { spanning_trees_by_shape_host(cd->codes[i], k, &sig[(size_t)i * NS]); sig_ok[i] = 1; }
-        }
-        bool newcov = false;
-        for (int i = 0; i < S; i++)
-            if (!cov[i] && c[i] >= cbar) { cov[i] = 1; ncov++; newcov = true; }
-        if (newcov && ncov < S) {
-            for (int i = 0; i < S; i++) {
-                if (!cov[i]) continue;
-                double acc = 0.0;
-                for (int q = 0; q < NS; q++)
-                    if (tjd[q] > 0) acc += (double)nj[q] * (double)sig[(size_t)i * NS + q] / tjd[q];
-                w[i] = acc;
-            }
-            int best = -1;
-            double bv = 0.0;
-            for (int q = 0; q < NS; q++) {
-                if (!(tjd[q] > 0)) continue;
-                double acc = 0.0;
-                for (int i = 0; i < S; i++)
-                    if (cov[i]) acc += (double)sig[(size_t)i * NS + q] * (double)c[i] / w[i];
-                acc /= tjd[q];
-                if (best < 0 || acc < bv) { best = q; bv = acc; }
-            }
-            j = best;
-        }
+    return SCC_OK;
+}
+
+void AgsState::add_round(int64_t n, const unsigned long long *hh)
+{
+    shapes.push_back(j);
+    drawn += n;
+    nj[j] += n;
+    for (int i = 0; i < S; i++) {
+        if (!hh[i]) continue;
+        c[i] += (int64_t)hh[i];
+        if (!sig_ok[i]) { spanning_trees_by_shape_host(codes[i], k, &sig[(size_t)i * NS]); sig_ok[i] = 1; }
     }
+    bool newcov = false;
+    for (int i = 0; i < S; i++)
+        if (!cov[i] && c[i] >= cbar) { cov[i] = 1; ncov++; newcov = true; }
+    if (!newcov || ncov >= S) return;
+    // w_i = sum_j n_j sigma_ij / t_j over covered classes, then the shape that
+    // minimises (1/t_j) sum_{i covered} sigma_ij c_i / w_i (ties: smaller j)
+    for (int i = 0; i < S; i++) {
+        if (!cov[i]) continue;
+        double acc = 0.0;
+        for (int q = 0; q < NS; q++)
+            if (tjd[q] > 0) acc += (double)nj[q] * (double)sig[(size_t)i * NS + q] / tjd[q];
+        w[i] = acc;
+    }
+    int best = -1;
+    double bv = 0.0;
+    for (int q = 0; q < NS; q++) {
+        if (!(tjd[q] > 0)) continue;
+        double acc = 0.0;
+        for (int i = 0; i < S; i++)
+            if (cov[i]) acc += (double)sig[(size_t)i * NS + q] * (double)c[i] / w[i];
+        acc /= tjd[q];
+        if (best < 0 || acc < bv) { best = q; bv = acc; }
+    }
+    j = best;
+}
+
+void AgsState::result(int64_t *hits, double *w_out, int64_t *n_j) const
+{
     for (int i = 0; i < S; i++) {
         double acc = 0.0;
         if (sig_ok[i])
@@ -459,6 +495,43 @@ extern "C" scc_status scc_ags(const scc_table *tc, int64_t cbar, int64_t round_s
         w_out[i] = acc;
     }
     for (int q = 0; q < NS; q++) n_j[q] = nj[q];
-    *n_rounds = nr;
+}
+
+extern "C" scc_status scc_ags(const scc_table *tc, int64_t cbar, int64_t round_size, int64_t budget, uint64_t seed,
+                              uint64_t stream_id, int64_t *hits, double *w_out, int64_t *n_j, int32_t *round_shapes,
+                              int64_t *n_rounds, void *stream)
+{
+    scc_table *T = const_cast<scc_table *>(tc);
+    if (!T || !hits || !w_out || !n_j || !n_rounds) return set_error(SCC_EINVAL, "NULL argument");
+    if (cbar < 1 || round_size < 1 || budget < 0) return set_error(SCC_EINVAL, "bad AGS parameters");
+    const int k = T->k;
+    hipStream_t st = stream ? (hipStream_t)stream : T->stream;
+    AgsState A;
+    scc_status s = A.init(T, cbar, st);
+    if (s) return s;
+    const int S = A.S;
+    int32_t *dv = (int32_t *)T->mem.get((size_t)round_size * k * 4);
+    int8_t *dp = (int8_t *)T->mem.get((size_t)round_size * k);
+    uint32_t *dc = (uint32_t *)T->mem.get((size_t)round_size * 4);
+    unsigned long long *dh = (unsigned long long *)T->mem.get((size_t)S * 8);
+    std::vector<unsigned long long> hh(S);
+    auto done = [&](scc_status r) { T->mem.put(dv); T->mem.put(dp); T->mem.put(dc); T->mem.put(dh); return r; };
+    if (!dv || !dp || !dc || !dh) return done(set_error(SCC_ENOMEM, "AGS buffers"));
+    while (!A.covered() && A.drawn + round_size <= budget) {
+        s = scc_sample(T, A.j, round_size, seed, stream_id, (uint64_t)A.drawn, dv, dp, st);
+        if (s) return done(s);
+        s = scc_classify(T, dv, round_size, nullptr, dc, st);
+        if (s) return done(s);
+        if (hipMemsetAsync(dh, 0, (size_t)S * 8, st) != hipSuccess) return done(set_error(SCC_EDEVICE, "AGS memset"));
+        hipLaunchKernelGGL(k_hist, dim3((unsigned)((round_size + 255) / 256)), dim3(256), 0, st, dc, round_size, (uint32_t)S, dh);
+        if (hipMemcpyAsync(hh.data(), dh, (size_t)S * 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return done(set_error(SCC_EDEVICE, "AGS histogram"));
+        A.add_round(round_size, hh.data());
+    }
+    A.result(hits, w_out, n_j);
+    if (round_shapes)
+        for (size_t r = 0; r < A.shapes.size(); r++) round_shapes[r] = A.shapes[r];
+    *n_rounds = (int64_t)A.shapes.size();
     return done(SCC_OK);
 }

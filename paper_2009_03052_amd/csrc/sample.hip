@@ -7,31 +7,10 @@
 // whose running sum exceeds the drawn integer wins.
 #include <cstring>
 
-#include "table.hpp"
+#include "sampler.hpp"
 
 namespace {
 
-struct SampleArgs {
-    GraphView g;
-    const DevLut *L;
-    int k, shape, zero;
-    LevelView lev[SCC_KMAX + 1];          // 2..k
-    const uint64_t *Slo[SCC_KMAX + 1];    // neighbour sums 1..k-1
-    const uint64_t *Shi[SCC_KMAX + 1];
-    const u128 *M[SCC_KMAX + 1];
-    const int16_t *key_xidx;              // [k * nkeys] dense own position of a key, or -1
-    int nkeys;
-    const int32_t *hub_index;             // [n] hub number or -1
-    const int64_t *hub_poff;              // [nhub * (k+1)]
-    const uint64_t *hub_pre;
-    const u128 *pre;                      // running sums of admissible level-k totals
-    u128 total;
-    uint64_t seed, stream, first;
-    int64_t nsamp;
-    int32_t *verts;
-    int8_t *par;
-    int *err;
-};
 
 __device__ inline int key_level(const DevLut &L, uint32_t key)
 {
@@ -91,170 +70,205 @@ __device__ inline u128 own_count(const SampleArgs &A, int h, int64_t x, uint32_t
     return record_at(A.lev[h], x, li);
 }
 
-__global__ void __launch_bounds__(WAVE) k_sample(SampleArgs A)
+// LDS of one wave's sample: the vertices found so far with their parents, and
+// the stack of pending decompositions (key, position of its root, count)
+struct SampleLds {
+    int32_t sv[SCC_KMAX];
+    int8_t par[SCC_KMAX];
+    uint32_t st_key[2 * SCC_KMAX];
+    int st_pos[2 * SCC_KMAX];
+    u128 st_cnt[2 * SCC_KMAX];
+};
+
+// Sample number r of A's stream (random index A.first + r) into row r of
+// A.verts / A.par, by the whole wave. Returns 0, or an error bit (1: the root
+// entry draw fell off the record, 2: a decomposition draw failed, 4: the root
+// vertex draw fell off the running sums); none is expected for a consistent table.
+__device__ inline int sample_one(const SampleArgs &A, int64_t r, SampleLds &W)
 {
-    __shared__ int32_t sv[SCC_KMAX];
-    __shared__ int8_t sp_par[SCC_KMAX];
-    __shared__ uint32_t st_key[2 * SCC_KMAX];
-    __shared__ int st_pos[2 * SCC_KMAX];
-    __shared__ u128 st_cnt[2 * SCC_KMAX];
+    int32_t *sv = W.sv;
+    int8_t *sp_par = W.par;
+    uint32_t *st_key = W.st_key;
+    int *st_pos = W.st_pos;
+    u128 *st_cnt = W.st_cnt;
     const DevLut &L = *A.L;
     const int lane = lane_id();
     const int k = A.k;
-    for (int64_t s = blockIdx.x; s < A.nsamp; s += gridDim.x) {
-        const uint64_t idx = A.first + (uint64_t)s;
-        // (1) root: first vertex whose running sum exceeds X, then the entry of its record
-        const u128 X = draw_below(A.total, A.seed, A.stream, idx, 0);
-        const int64_t v = wave_search(A.g.n, X, [&](int64_t i) { return A.pre[i]; });
-        if (v < 0) {
-            if (lane == 0) atomicOr(A.err, 4);
-            continue;
+    const uint64_t idx = A.first + (uint64_t)r;
+    // (1) root: first vertex whose running sum exceeds X, then the entry of its record
+    const u128 X = draw_below(A.total, A.seed, A.stream, idx, 0);
+    const int64_t v = wave_search(A.g.n, X, [&](int64_t i) { return A.pre[i]; });
+    if (v < 0) return 4;
+    const u128 res = X - (v > 0 ? A.pre[v - 1] : (u128)0);
+    const Rec rk = rec_of(A.lev[k], v);
+    const uint32_t lenk = rk.len;
+    u128 run = 0;
+    uint32_t rkey = 0xffffffffu;
+    u128 rcnt = 0;
+    for (uint32_t b0 = 0; b0 < lenk; b0 += WAVE) {
+        const uint32_t e = b0 + lane;
+        u128 c = 0;
+        uint32_t key = 0;
+        if (e < lenk) {
+            key = rk.key(e);
+            const int t = (int)(key - L.off[k]) / L.bk[k];
+            if (A.shape < 0 || L.unr_of[t] == A.shape) c = rk.cnt(e);
         }
-        const u128 res = X - (v > 0 ? A.pre[v - 1] : (u128)0);
-        const Rec rk = rec_of(A.lev[k], v);
-        const uint32_t lenk = rk.len;
-        u128 run = 0;
-        uint32_t rkey = 0xffffffffu;
-        u128 rcnt = 0;
-        for (uint32_t b0 = 0; b0 < lenk; b0 += WAVE) {
-            const uint32_t e = b0 + lane;
-            u128 c = 0;
-            uint32_t key = 0;
-            if (e < lenk) {
-                key = rk.key(e);
-                const int t = (int)(key - L.off[k]) / L.bk[k];
-                if (A.shape < 0 || L.unr_of[t] == A.shape) c = rk.cnt(e);
+        const u128 incl = run + wave_incl_scan128(c);
+        const int w = first_exceeding(incl, res);
+        if (w >= 0) {
+            rkey = __shfl(key, w, WAVE);
+            rcnt = shfl128(c, w);
+            break;
+        }
+        run = shfl128(incl, WAVE - 1);
+    }
+    if (rkey == 0xffffffffu) return 1;
+    if (lane == 0) {
+        sv[0] = (int32_t)v; sp_par[0] = -1;
+        st_key[0] = rkey; st_pos[0] = 0; st_cnt[0] = rcnt;
+    }
+    __syncthreads();
+    int nv = 1, sp = 1, dec = 0;
+    bool fail = false;
+    // (2) decompose, LIFO: (T', C \ C'', x) is processed before (T'', C'', u)
+    while (sp > 0 && !fail) {
+        sp--;
+        const uint32_t key = st_key[sp];
+        const int pos = st_pos[sp];
+        const u128 cT = st_cnt[sp];
+        __syncthreads();
+        const int h = key_level(L, key);
+        if (h == 1) continue;
+        const int rel = (int)key - L.off[h];
+        const int t = rel / L.bk[h];
+        const uint32_t C = L.mask_k[h][rel - t * L.bk[h]];
+        const int64_t x = sv[pos];
+        const int cx = A.g.colors[x];
+        const int hp = L.dec_hp[h][t], hpp = h - hp, a = L.dec_a[h][t], b = L.dec_b[h][t];
+        const int beta = L.dec_beta[h][t];
+        const u128 Y = draw_below((u128)beta * cT, A.seed, A.stream, idx, 1 + 2 * dec);
+        // stage 1: C'' among the |T''|-subsets of C \ {c_x}, ascending bitmask
+        const uint32_t R = C & ~(1u << cx);
+        int ncand = 1;
+        for (int i = 1; i <= hpp; i++) ncand = ncand * (h - 1 - hpp + i) / i;
+        u128 w = 0, xprime = 0, sval = 0;
+        uint32_t cpp = 0;
+        int sidx = 0;
+        if (lane < ncand) {
+            // deposit the lane-th hpp-subset of the low h-1 positions onto R's bits
+            uint32_t pm = L.mask_s[hpp][lane], dep = 0, rr = R;
+            for (int q = 0; rr; q++) {
+                const uint32_t bit = rr & (~rr + 1u);
+                if (pm >> q & 1u) dep |= bit;
+                rr &= rr - 1u;
             }
-            const u128 incl = run + wave_incl_scan128(c);
-            const int w = first_exceeding(incl, res);
-            if (w >= 0) {
-                rkey = __shfl(key, w, WAVE);
-                rcnt = shfl128(c, w);
-                break;
+            cpp = dep;
+            const uint32_t kprime = L.off[hp] + a * L.bk[hp] + L.colex_k[C ^ cpp];
+            xprime = own_count(A, hp, x, kprime);
+            const int ws = L.WS[hpp];
+            sidx = b * L.bk1[hpp] + L.colex_s[compress_out(cpp, cx)];
+            const uint64_t slo = A.Slo[hpp][(size_t)x * ws + sidx];
+            const uint64_t shi = hi64(A.M[hpp][x]) ? A.Shi[hpp][(size_t)x * ws + sidx] : 0;
+            sval = mk128(slo, shi);
+            w = xprime * sval;
+        }
+        const u128 incl1 = wave_incl_scan128(w);
+        const int w1 = first_exceeding(incl1, Y);
+        if (w1 < 0) { fail = true; break; }
+        const uint32_t Cpp = __shfl(cpp, w1, WAVE);
+        const int Sidx = __shfl(sidx, w1, WAVE);
+        const u128 Xp = shfl128(xprime, w1);
+        const u128 Sv = shfl128(sval, w1);
+        // stage 2: neighbour u of x with weight c(T''_{C''}, u), CSR order
+        const u128 Z = draw_below(Sv, A.seed, A.stream, idx, 2 + 2 * dec);
+        const uint32_t kpp = L.off[hpp] + b * L.bk[hpp] + L.colex_k[Cpp];
+        const int64_t ra = A.g.row_ptr[x], rb = A.g.row_ptr[x + 1];
+        int64_t u = -1;
+        u128 wu = 0;
+        const int hub = A.hub_index ? A.hub_index[x] : -1;
+        if (hub >= 0) {
+            // running sums over x's neighbours, precomputed per (hub, level, entry)
+            const int64_t d = rb - ra;
+            const int64_t base = A.hub_poff[(size_t)hub * (SCC_KMAX + 1) + hpp];
+            const uint64_t *plo = A.hub_pre + base + (size_t)Sidx * d;
+            const bool pw = hi64(A.M[hpp][x]) != 0;
+            const uint64_t *phi = A.hub_pre + base + (size_t)L.WS[hpp] * d + (size_t)Sidx * d;
+            auto P = [&](int64_t j) { return mk128(plo[j], pw ? phi[j] : 0); };
+            const int64_t j = wave_search(d, Z, P);
+            if (j >= 0) {
+                u = A.g.col_idx[ra + j];
+                wu = P(j) - (j > 0 ? P(j - 1) : (u128)0);
             }
-            run = shfl128(incl, WAVE - 1);
+        } else {
+            u128 run2 = 0;
+            for (int64_t base = ra; base < rb; base += WAVE) {
+                const int64_t e = base + lane;
+                u128 c = 0;
+                int32_t uu = -1;
+                if (e < rb) {
+                    uu = A.g.col_idx[e];
+                    c = own_count(A, hpp, uu, kpp);
+                }
+                const u128 incl = run2 + wave_incl_scan128(c);
+                const int w2 = first_exceeding(incl, Z);
+                if (w2 >= 0) {
+                    u = __shfl(uu, w2, WAVE);
+                    wu = shfl128(c, w2);
+                    break;
+                }
+                run2 = shfl128(incl, WAVE - 1);
+            }
         }
-        if (rkey == 0xffffffffu) {
-            if (lane == 0) atomicOr(A.err, 1);
-            continue;
-        }
+        if (u < 0) { fail = true; break; }
         if (lane == 0) {
-            sv[0] = (int32_t)v; sp_par[0] = -1;
-            st_key[0] = rkey; st_pos[0] = 0; st_cnt[0] = rcnt;
+            sv[nv] = (int32_t)u;
+            sp_par[nv] = (int8_t)pos;
+            st_key[sp] = kpp; st_pos[sp] = nv; st_cnt[sp] = wu;
+            st_key[sp + 1] = L.off[hp] + a * L.bk[hp] + L.colex_k[C ^ Cpp];
+            st_pos[sp + 1] = pos; st_cnt[sp + 1] = Xp;
         }
         __syncthreads();
-        int nv = 1, sp = 1, dec = 0;
-        bool fail = false;
-        // (2) decompose, LIFO: (T', C \ C'', x) is processed before (T'', C'', u)
-        while (sp > 0 && !fail) {
-            sp--;
-            const uint32_t key = st_key[sp];
-            const int pos = st_pos[sp];
-            const u128 cT = st_cnt[sp];
-            __syncthreads();
-            const int h = key_level(L, key);
-            if (h == 1) continue;
-            const int rel = (int)key - L.off[h];
-            const int t = rel / L.bk[h];
-            const uint32_t C = L.mask_k[h][rel - t * L.bk[h]];
-            const int64_t x = sv[pos];
-            const int cx = A.g.colors[x];
-            const int hp = L.dec_hp[h][t], hpp = h - hp, a = L.dec_a[h][t], b = L.dec_b[h][t];
-            const int beta = L.dec_beta[h][t];
-            const u128 Y = draw_below((u128)beta * cT, A.seed, A.stream, idx, 1 + 2 * dec);
-            // stage 1: C'' among the |T''|-subsets of C \ {c_x}, ascending bitmask
-            const uint32_t R = C & ~(1u << cx);
-            int ncand = 1;
-            for (int i = 1; i <= hpp; i++) ncand = ncand * (h - 1 - hpp + i) / i;
-            u128 w = 0, xprime = 0, sval = 0;
-            uint32_t cpp = 0;
-            int sidx = 0;
-            if (lane < ncand) {
-                // deposit the lane-th hpp-subset of the low h-1 positions onto R's bits
-                uint32_t pm = L.mask_s[hpp][lane], dep = 0, rr = R;
-                for (int q = 0; rr; q++) {
-                    const uint32_t bit = rr & (~rr + 1u);
-                    if (pm >> q & 1u) dep |= bit;
-                    rr &= rr - 1u;
-                }
-                cpp = dep;
-                const uint32_t kprime = L.off[hp] + a * L.bk[hp] + L.colex_k[C ^ cpp];
-                xprime = own_count(A, hp, x, kprime);
-                const int ws = L.WS[hpp];
-                sidx = b * L.bk1[hpp] + L.colex_s[compress_out(cpp, cx)];
-                const uint64_t slo = A.Slo[hpp][(size_t)x * ws + sidx];
-                const uint64_t shi = hi64(A.M[hpp][x]) ? A.Shi[hpp][(size_t)x * ws + sidx] : 0;
-                sval = mk128(slo, shi);
-                w = xprime * sval;
-            }
-            const u128 incl1 = wave_incl_scan128(w);
-            const int w1 = first_exceeding(incl1, Y);
-            if (w1 < 0) { fail = true; break; }
-            const uint32_t Cpp = __shfl(cpp, w1, WAVE);
-            const int Sidx = __shfl(sidx, w1, WAVE);
-            const u128 Xp = shfl128(xprime, w1);
-            const u128 Sv = shfl128(sval, w1);
-            // stage 2: neighbour u of x with weight c(T''_{C''}, u), CSR order
-            const u128 Z = draw_below(Sv, A.seed, A.stream, idx, 2 + 2 * dec);
-            const uint32_t kpp = L.off[hpp] + b * L.bk[hpp] + L.colex_k[Cpp];
-            const int64_t ra = A.g.row_ptr[x], rb = A.g.row_ptr[x + 1];
-            int64_t u = -1;
-            u128 wu = 0;
-            const int hub = A.hub_index ? A.hub_index[x] : -1;
-            if (hub >= 0) {
-                // running sums over x's neighbours, precomputed per (hub, level, entry)
-                const int64_t d = rb - ra;
-                const int64_t base = A.hub_poff[(size_t)hub * (SCC_KMAX + 1) + hpp];
-                const uint64_t *plo = A.hub_pre + base + (size_t)Sidx * d;
-                const bool pw = hi64(A.M[hpp][x]) != 0;
-                const uint64_t *phi = A.hub_pre + base + (size_t)L.WS[hpp] * d + (size_t)Sidx * d;
-                auto P = [&](int64_t j) { return mk128(plo[j], pw ? phi[j] : 0); };
-                const int64_t j = wave_search(d, Z, P);
-                if (j >= 0) {
-                    u = A.g.col_idx[ra + j];
-                    wu = P(j) - (j > 0 ? P(j - 1) : (u128)0);
-                }
-            } else {
-                u128 run2 = 0;
-                for (int64_t base = ra; base < rb; base += WAVE) {
-                    const int64_t e = base + lane;
-                    u128 c = 0;
-                    int32_t uu = -1;
-                    if (e < rb) {
-                        uu = A.g.col_idx[e];
-                        c = own_count(A, hpp, uu, kpp);
-                    }
-                    const u128 incl = run2 + wave_incl_scan128(c);
-                    const int w2 = first_exceeding(incl, Z);
-                    if (w2 >= 0) {
-                        u = __shfl(uu, w2, WAVE);
-                        wu = shfl128(c, w2);
-                        break;
-                    }
-                    run2 = shfl128(incl, WAVE - 1);
-                }
-            }
-            if (u < 0) { fail = true; break; }
-            if (lane == 0) {
-                sv[nv] = (int32_t)u;
-                sp_par[nv] = (int8_t)pos;
-                st_key[sp] = kpp; st_pos[sp] = nv; st_cnt[sp] = wu;
-                st_key[sp + 1] = L.off[hp] + a * L.bk[hp] + L.colex_k[C ^ Cpp];
-                st_pos[sp + 1] = pos; st_cnt[sp + 1] = Xp;
-            }
-            __syncthreads();
-            nv++;
-            sp += 2;
-            dec++;
+        nv++;
+        sp += 2;
+        dec++;
+    }
+    if (fail || nv != k) return 2;
+    if (lane < k) {
+        A.verts[(size_t)r * k + lane] = sv[lane];
+        A.par[(size_t)r * k + lane] = sp_par[lane];
+    }
+    return 0;
+}
+
+__global__ void __launch_bounds__(WAVE) k_sample(SampleArgs A)
+{
+    __shared__ SampleLds W;
+    for (int64_t s = blockIdx.x; s < A.nsamp; s += gridDim.x) {
+        const int e = sample_one(A, s, W);
+        if (e && lane_id() == 0) atomicOr(A.err, e);
+        __syncthreads();
+    }
+}
+
+// A serving step: rows of many requests (each with its own table, shape and
+// random stream), flattened; row s belongs to the first chunk whose running end
+// exceeds s. The grid strides over the rows.
+__global__ void __launch_bounds__(WAVE) k_serve_sample(const SampleArgs *args, const ServeChunk *ch,
+                                                      const int64_t *cend, int nch, int64_t total, int *err)
+{
+    __shared__ SampleLds W;
+    for (int64_t s = blockIdx.x; s < total; s += gridDim.x) {
+        int lo = 0, hi = nch - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (cend[mid] > s) hi = mid; else lo = mid + 1;
         }
-        if (fail || nv != k) {
-            if (lane == 0) atomicOr(A.err, 2);
-            continue;
-        }
-        if (lane < k) {
-            A.verts[(size_t)s * k + lane] = sv[lane];
-            A.par[(size_t)s * k + lane] = sp_par[lane];
-        }
+        const ServeChunk C = ch[lo];
+        const int64_t r = C.off + (s - (cend[lo] - C.count));
+        const SampleArgs &A = *(const SampleArgs *)((const __attribute__((address_space(4))) SampleArgs *)args + C.arg);
+        const int e = sample_one(A, r, W);
+        if (e && lane_id() == 0) atomicOr(err, e);
         __syncthreads();
     }
 }
@@ -620,6 +634,46 @@ scc_status table_prefix(scc_table *T, int shape, const u128 **pre, u128 *total)
     return SCC_OK;
 }
 
+scc_status prepare_sampling(scc_table *T, int shape, SampleArgs *out)
+{
+    const u128 *pre;
+    u128 total;
+    scc_status s = table_prefix(T, shape, &pre, &total);
+    if (s) return s;
+    if (total == 0) return set_error(SCC_EEMPTY, "no colourful %d-treelet to sample", T->k);
+    s = ensure_hub_prefix(T);
+    if (s) return s;
+    SampleArgs A{};
+    A.key_xidx = T->key_xidx; A.nkeys = T->hlut.nkeys;
+    if (T->hub_count_pre) { A.hub_index = T->hub_index; A.hub_poff = T->hub_poff; A.hub_pre = T->hub_pre; }
+    A.g = GraphView{T->n, T->row_ptr, T->col_idx, T->colors};
+    A.L = T->dlut; A.k = T->k; A.shape = shape; A.zero = T->rooting == SCC_ROOT_ZERO;
+    for (int h = 2; h <= T->k; h++) A.lev[h] = lview(T->lev[h]);
+    for (int h = 1; h < T->k; h++) { A.Slo[h] = T->S[h].lo; A.Shi[h] = T->S[h].hi; A.M[h] = T->S[h].M; }
+    A.pre = pre; A.total = total;
+    *out = A;
+    return SCC_OK;
+}
+
+scc_status prepare_all_sampling(scc_table *T)
+{
+    SampleArgs A;
+    for (int shape = -1; shape < T->hlut.num_unr; shape++) {
+        if (shape >= 0 && T->tj[shape] == 0) continue;
+        scc_status s = prepare_sampling(T, shape, &A);
+        if (s && s != SCC_EEMPTY) return s;
+    }
+    return SCC_OK;
+}
+
+void launch_serve_sample(const SampleArgs *args, const ServeChunk *ch, const int64_t *cend, int nch, int64_t total,
+                         int *err, int grid, hipStream_t st)
+{
+    if (total <= 0 || nch <= 0) return;
+    hipLaunchKernelGGL(k_serve_sample, dim3((unsigned)std::min<int64_t>(total, grid)), dim3(WAVE), 0, st, args, ch, cend,
+                       nch, total, err);
+}
+
 extern "C" scc_status scc_sample(const scc_table *tc, int32_t shape, int64_t n, uint64_t seed,
                                  uint64_t stream_id, uint64_t first_index, int32_t *out_verts,
                                  int8_t *out_parent, void *stream)
@@ -630,24 +684,13 @@ extern "C" scc_status scc_sample(const scc_table *tc, int32_t shape, int64_t n, 
     if (shape < -1 || shape >= T->hlut.num_unr) return set_error(SCC_EINVAL, "shape %d out of range", shape);
     if (n == 0) return SCC_OK;
     if (!out_verts || !out_parent) return set_error(SCC_EINVAL, "output NULL");
-    const u128 *pre;
-    u128 total;
-    scc_status s = table_prefix(T, shape, &pre, &total);
-    if (s) return s;
-    if (total == 0) return set_error(SCC_EEMPTY, "no colourful %d-treelet to sample", T->k);
-    s = ensure_hub_prefix(T);
+    SampleArgs A;
+    scc_status s = prepare_sampling(T, shape, &A);
     if (s) return s;
     hipStream_t st = stream ? (hipStream_t)stream : T->stream;
     int *err = (int *)T->mem.get(16);
     if (!err) return set_error(SCC_ENOMEM, "sample flags");
-    SampleArgs A{};
-    A.key_xidx = T->key_xidx; A.nkeys = T->hlut.nkeys;
-    if (T->hub_count_pre) { A.hub_index = T->hub_index; A.hub_poff = T->hub_poff; A.hub_pre = T->hub_pre; }
-    A.g = GraphView{T->n, T->row_ptr, T->col_idx, T->colors};
-    A.L = T->dlut; A.k = T->k; A.shape = shape; A.zero = T->rooting == SCC_ROOT_ZERO;
-    for (int h = 2; h <= T->k; h++) A.lev[h] = lview(T->lev[h]);
-    for (int h = 1; h < T->k; h++) { A.Slo[h] = T->S[h].lo; A.Shi[h] = T->S[h].hi; A.M[h] = T->S[h].M; }
-    A.pre = pre; A.total = total; A.seed = seed; A.stream = stream_id; A.first = first_index;
+    A.seed = seed; A.stream = stream_id; A.first = first_index;
     A.nsamp = n; A.verts = out_verts; A.par = out_parent; A.err = err;
     hipError_t e = hipMemsetAsync(err, 0, 4, st);
     const int64_t grid = std::min<int64_t>(n, (int64_t)1 << 20);
