@@ -29,47 +29,63 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=1)
-    p.add_argument("--samples", type=int, default=1_000_000)
+    p.add_argument("--samples", type=int, default=None, help="samples per step (default: the workload's)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--small", action="store_true", help="small graph (for quick checks)")
-    p.add_argument("--workload", default="mid", choices=["mid", "batching"],
-                   help="mid (default): the plain method on the mid graph; batching: 48 instances, plain vs one batched launch")
+    p.add_argument("--workload", default="mid", choices=["mid", "large", "batching", "serving"],
+                   help="mid (default) / large: the plain method on the mid / large graph; batching: 48 "
+                        "instances, plain vs one "
+                        "batched launch; serving: three resident k=7 tables under a Poisson request mix, continuous "
+                        "batching vs first-in first-out")
+    p.add_argument("--requests", type=int, default=2000, help="serving: requests per run")
+    p.add_argument("--window", type=float, default=40.0, help="serving: longest arrival window per run (s)")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="also run a plain 1 GiB device copy (reference for HBM traffic counters)")
     return p.parse_args()
 
 
-def cpu_baseline(full_m, samples):
+PLAIN = {
+    "mid": dict(n=1_000_000, m=10_000_000, gamma=2.1, wmax=5e4, gseed=2, k=6, cseed=12, samples=1_000_000,
+                sseed=22, oracle_scale=8, traffic="gather_mid_k6_hbm_traffic.txt",
+                label="mid: Chung-Lu n=1e6 m=1e7 exponent 2.1 w_max=5e4, k=6, zero-rooting"),
+    "large": dict(n=4_000_000, m=60_000_000, gamma=2.3, wmax=2e5, gseed=3, k=8, cseed=13, samples=10_000_000,
+                  sseed=23, oracle_scale=64, traffic="gather_large_k8_hbm_traffic.txt",
+                  label="large: Chung-Lu n=4e6 m=6e7 exponent 2.3 w_max=2e5, k=8, zero-rooting",
+                  ags=dict(cbar=1000, round_size=100_000, budget=20_000_000, seed=33)),
+}
+
+
+def cpu_baseline(cfg, full_m, samples):
     """The oracle, as is, on a bounded sample of the workload (single thread)."""
     import graphgen as gg
     import oracle as O
-    scale = 8
-    n, m = 1_000_000 // scale, 10_000_000 // scale
-    g = gg.chung_lu(n, m, 2.1, 5e4 / scale, seed=2)
-    colors = gg.colors(g.n, 6, seed=12)
+    scale = cfg["oracle_scale"]
+    n, m, k = cfg["n"] // scale, cfg["m"] // scale, cfg["k"]
+    g = gg.chung_lu(n, m, cfg["gamma"], cfg["wmax"] / scale, seed=cfg["gseed"])
+    colors = gg.colors(g.n, k, seed=cfg["cseed"])
     t0 = time.perf_counter()
-    tab = O.Table(g, colors, 6, O.ROOT_ZERO)
+    tab = O.Table(g, colors, k, O.ROOT_ZERO)
     t_build = time.perf_counter() - t0
     ns = 300
     t0 = time.perf_counter()
-    v, _ = tab.sample(ns, seed=22)
-    O.classify(g, 6, v)
+    v, _ = tab.sample(ns, seed=cfg["sseed"])
+    O.classify(g, k, v)
     t_samp = (time.perf_counter() - t0) / ns
     est_step = t_build * (full_m / g.m) + samples * t_samp
     return {
         "value": samples / est_step, "unit": "samples/s", "cores": 1, "kind": "oracle",
         "sample": (f"oracle build on a 1/{scale}-scale graph of the same family (Chung-Lu n={n}, m={g.m}, "
-                   f"exponent 2.1, w_max={5e4 / scale:.0f}) took {t_build:.2f} s, scaled by edges to m={full_m}; "
-                   f"sampling+classification {t_samp * 1e3:.2f} ms/sample measured on {ns} samples of that table; "
-                   f"value = {samples} / (scaled build + {samples} samples)"),
+                   f"exponent {cfg['gamma']}, w_max={cfg['wmax'] / scale:.0f}, k={k}) took {t_build:.2f} s, scaled "
+                   f"by edges to m={full_m}; sampling+classification {t_samp * 1e3:.2f} ms/sample measured on {ns} "
+                   f"samples of that table; value = {samples} / (scaled build + {samples} samples)"),
     }
 
 
-def measured_traffic():
+def measured_traffic(name):
     """HBM bytes per step of the gather kernels from the committed counter summary,
     or None when the gather source changed since the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "gather_mid_k6_hbm_traffic.txt")
+    path = os.path.join(ROOT, "profiles", name)
     src = os.path.join(ROOT, "paper_2009_03052_amd", "csrc", "dp.hip")
     try:
         fields = {}
@@ -162,6 +178,151 @@ def run_batching(a):
     print(json.dumps(out), flush=True)
 
 
+def serving_tables():
+    """Three Chung-Lu graphs, n = 2e6, m = 3e7, exponents 2.1 / 2.4 / 2.8, w_max = 1e5, k = 7."""
+    import graphgen as gg
+    out = []
+    for i, gam in enumerate((2.1, 2.4, 2.8)):
+        g = gg.chung_lu(2_000_000, 30_000_000, gam, 1e5, seed=6 + i)
+        out.append((g, gg.colors(g.n, 7, seed=16 + i), 7))
+        print(f"# serving graph {i}: n={g.n} m={g.m} d_max={int(g.degrees().max())}", file=sys.stderr, flush=True)
+    return out
+
+
+def serving_trace(count, seed=31):
+    """Request mix: sizes log-uniform in [1e3, 1e6]; half uniform samples (classified) on a
+    random graph, half AGS rounds from one client per graph; unit-mean exponential gaps."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    sizes = np.exp(rng.uniform(np.log(1e3), np.log(1e6), count)).astype(np.int64)
+    ags = rng.random(count) < 0.5
+    graph = rng.integers(0, 3, count)
+    seeds = rng.integers(1, 1 << 40, count)
+    gaps = rng.exponential(1.0, count)
+    return [dict(n=int(sizes[i]), ags=bool(ags[i]), graph=int(graph[i]), seed=int(seeds[i]), gap=float(gaps[i]))
+            for i in range(count)]
+
+
+def drive(srv, trace, rate, sessions, window):
+    """Submits `trace` at Poisson arrival times (rate per second; rate = inf: all at once) from one
+    thread, waits for and releases the results in order from another; returns the server's stats."""
+    import queue
+    import threading
+    q = queue.Queue()
+    t0 = time.perf_counter()
+    at = 0.0
+    arrivals = []
+    for r in trace:
+        at += r["gap"] / rate if rate != float("inf") else 0.0
+        arrivals.append(at)
+
+    def submitter():
+        for i, r in enumerate(trace):
+            if arrivals[i] > window:
+                break
+            dt = arrivals[i] - (time.perf_counter() - t0)
+            if dt > 0:
+                time.sleep(dt)
+            if r["ags"]:
+                rid = srv.submit(r["graph"], r["n"], session=sessions[r["graph"]])
+            else:
+                rid = srv.submit(r["graph"], r["n"], seed=r["seed"], stream_id=i, classify=True)
+            q.put(rid)
+        q.put(None)
+
+    def waiter():
+        done = 0
+        while True:
+            rid = q.get()
+            if rid is None:
+                break
+            srv.wait(rid, timeout=900.0, copy=False)
+            srv.release(rid)
+            done += 1
+            if done % 250 == 0:
+                print(f"#   {done} requests done", file=sys.stderr, flush=True)
+
+    ts = [threading.Thread(target=submitter), threading.Thread(target=waiter)]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    st = srv.stats()
+    st["wall_s"] = time.perf_counter() - t0
+    st["samples_per_s"] = st["samples"] / st["span_s"] if st["span_s"] > 0 else 0.0
+    return st
+
+
+def run_serving(a):
+    import torch
+
+    import paper_2009_03052_amd as scc
+    torch.cuda.set_device(0)
+    raw = serving_tables()
+    tabs = []
+    build_s = []
+    for g, c, k in raw:
+        dg = scc.DeviceGraph.from_graph(g)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tabs.append(scc.Table(dg, torch.as_tensor(c).cuda(), k, rooting=scc.ROOT_ZERO))
+        torch.cuda.synchronize()
+        build_s.append(time.perf_counter() - t0)
+        print(f"# table built in {build_s[-1]:.3f} s, {tabs[-1].info().bytes / 1e9:.1f} GB", file=sys.stderr, flush=True)
+    trace = serving_trace(a.requests)
+    opts = dict(hbm_budget=24 << 30, step_samples=1 << 16, chunk=4096, max_active=512)
+    cbar = 1000
+
+    def server(fifo):
+        srv = scc.Server(tabs, fifo=fifo, **opts)
+        sessions = [srv.ags_open(t, cbar=cbar, seed=900 + t, stream_id=t) for t in range(len(tabs))]
+        return srv, sessions
+
+    # saturated rates: a burst of the first requests, all submitted at once, in each mode
+    sat = {}
+    for name, fifo in (("continuous", False), ("fifo", True)):
+        srv, sess = server(fifo)
+        sat[name] = drive(srv, trace[:min(300, len(trace))], float("inf"), sess, 1e9)["samples_per_s"]
+        srv.close()
+        print(f"# saturated {name}: {sat[name] / 1e6:.1f} M samples/s", file=sys.stderr, flush=True)
+    burst = {"samples_per_s": sat["continuous"]}
+    mean_n = sum(r["n"] for r in trace) / len(trace)
+    sat_req = burst["samples_per_s"] / mean_n
+    rate = 0.7 * sat_req
+    print(f"# saturated: {burst['samples_per_s'] / 1e6:.1f} M samples/s = {sat_req:.1f} requests/s; "
+          f"Poisson rate {rate:.1f}/s", file=sys.stderr, flush=True)
+    res = {}
+    for name, fifo in (("continuous", False), ("fifo", True)):
+        srv, sess = server(fifo)
+        res[name] = drive(srv, trace, rate, sess, a.window)
+        srv.close()
+        r = res[name]
+        print(f"# {name}: {r['completed']} requests, {r['samples_per_s'] / 1e6:.1f} M samples/s, "
+              f"p50 {r['p50_ms']:.1f} ms, p99 {r['p99_ms']:.1f} ms", file=sys.stderr, flush=True)
+    c, f = res["continuous"], res["fifo"]
+    keep = ("completed", "samples", "steps", "span_s", "samples_per_s", "p50_ms", "p99_ms", "mean_ms", "max_ms",
+            "arena_peak")
+    out = {
+        "metric": "DP table build s & colorful-treelet samples/sec, batched/served vs plain",
+        "value": c["samples_per_s"], "unit": "samples/s served (continuous batching, Poisson arrivals at 0.7x "
+                                             "saturation, submission to completion)",
+        "n_gpus": 1, "steps": c["completed"], "warmup": 0, "ms_per_step": c["mean_ms"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u64/u128", "data": "synthetic",
+        "config": {"workload": "serving: 3 resident k=7 tables (Chung-Lu n=2e6 m=3e7, exponents 2.1/2.4/2.8, "
+                               "w_max=1e5), requests of 1e3..1e6 samples (log-uniform), half uniform+classified, "
+                               "half AGS rounds from 3 clients, Poisson arrivals",
+                   "requests": len(trace), "arrival_rate_per_s": rate, "window_s": a.window},
+        "table_build_s": build_s,
+        "saturated_samples_per_s": sat["continuous"], "saturated_samples_per_s_fifo": sat["fifo"],
+        "saturated_throughput_vs_fifo": sat["continuous"] / sat["fifo"] if sat["fifo"] > 0 else None,
+        "continuous": {k: c[k] for k in keep}, "fifo": {k: f[k] for k in keep},
+        "p99_speedup_vs_fifo": f["p99_ms"] / c["p99_ms"] if c["p99_ms"] > 0 else None,
+        "p50_speedup_vs_fifo": f["p50_ms"] / c["p50_ms"] if c["p50_ms"] > 0 else None,
+        "throughput_vs_fifo": c["samples_per_s"] / f["samples_per_s"] if f["samples_per_s"] > 0 else None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -169,6 +330,8 @@ def main():
         sys.exit(2)
     if a.workload == "batching":
         return run_batching(a)
+    if a.workload == "serving":
+        return run_serving(a)
     import torch
 
     import graphgen as gg
@@ -184,15 +347,17 @@ def main():
         torch.cuda.synchronize()
         del src, dst
         print("# calibration copy of 1073741824 bytes done", file=sys.stderr, flush=True)
+    cfg = PLAIN[a.workload]
     if a.small:
-        g = gg.chung_lu(100_000, 1_000_000, 2.1, 5e3, seed=2)
+        g = gg.chung_lu(cfg["n"] // 10, cfg["m"] // 10, cfg["gamma"], cfg["wmax"] / 10, seed=cfg["gseed"])
     else:
-        g = gg.chung_lu(1_000_000, 10_000_000, 2.1, 5e4, seed=2)
-    k = 6
-    colors = gg.colors(g.n, k, seed=12)
+        g = gg.chung_lu(cfg["n"], cfg["m"], cfg["gamma"], cfg["wmax"], seed=cfg["gseed"])
+    k = cfg["k"]
+    colors = gg.colors(g.n, k, seed=cfg["cseed"])
     dg = scc.DeviceGraph.from_graph(g)
     dcol = torch.as_tensor(colors).cuda()
-    ns = a.samples
+    ns = a.samples if a.samples is not None else cfg["samples"]
+    sseed = cfg["sseed"]
     verts = torch.empty((ns, k), dtype=torch.int32, device="cuda")
     par = torch.empty((ns, k), dtype=torch.int8, device="cuda")
     code = torch.empty(ns, dtype=torch.int32, device="cuda")
@@ -201,7 +366,7 @@ def main():
 
     def step():
         tab = scc.Table(dg, dcol, k, rooting=scc.ROOT_ZERO)
-        tab.sample(ns, seed=22, out=(verts, par))
+        tab.sample(ns, seed=sseed, out=(verts, par))
         tab.classify(verts, out=(code, cls))
         return tab
 
@@ -225,7 +390,7 @@ def main():
     ev[0].record()
     tab = scc.Table(dg, dcol, k, rooting=scc.ROOT_ZERO)
     ev[1].record()
-    tab.sample(ns, seed=22, out=(verts, par))
+    tab.sample(ns, seed=sseed, out=(verts, par))
     ev[2].record()
     tab.classify(verts, out=(code, cls))
     ev[3].record()
@@ -240,7 +405,22 @@ def main():
     gb = tab.gather_bytes()
     g_bytes = sum(gb[h] for h in range(2, k))
     achieved = g_bytes / (g_ms * 1e-3) / 1e9 if g_ms > 0 else 0.0
-    traffic = measured_traffic()
+    traffic = measured_traffic(cfg["traffic"])
+    ags = None
+    if "ags" in cfg:
+        A = cfg["ags"]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = tab.ags(cbar=A["cbar"], round_size=A["round_size"], budget=A["budget"], seed=A["seed"])
+        torch.cuda.synchronize()
+        t_ags = time.perf_counter() - t0
+        drawn = int(r["n_j"].sum())
+        ags = {"cbar": A["cbar"], "round_size": A["round_size"], "budget": A["budget"],
+               "rounds": int(len(r["round_shapes"])), "samples": drawn, "seconds": t_ags,
+               "samples_per_s": drawn / t_ags if t_ags > 0 else 0.0,
+               "classes_hit": int((r["hits"] > 0).sum()), "classes_covered": int((r["hits"] >= A["cbar"]).sum()),
+               "shapes_used": sorted(set(int(x) for x in r["round_shapes"]))}
+        print(f"# AGS: {ags['rounds']} rounds, {drawn} samples in {t_ags:.2f} s", file=sys.stderr, flush=True)
     out = {
         "metric": "DP table build s & colorful-treelet samples/sec, batched/served vs plain",
         "value": ns / dt,
@@ -248,20 +428,21 @@ def main():
         "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": dt * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64/u128",
         "data": "synthetic",
-        "config": {"workload": "mid: Chung-Lu n=1e6 m=1e7 exponent 2.1 w_max=5e4, k=6, zero-rooting, "
-                               f"{ns} uniform samples + classification",
+        "config": {"workload": cfg["label"] + f", {ns} uniform samples + classification",
                    "n": g.n, "m": g.m, "d_max": int(g.degrees().max()), "k": k, "samples": ns},
         "build_s": build_ms / 1e3, "sample_per_s": ns / (samp_ms / 1e3), "classify_per_s": ns / (cls_ms / 1e3),
         "level_ms": [round(info.level_ms[h], 3) for h in range(1, k + 1)],
         "table_bytes": int(info.bytes), "t": str(int(info.t[0]) | (int(info.t[1]) << 64)),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "traffic_unit": "bytes per step (4 gather launches), FETCH_SIZE x2.0 + WRITE_SIZE x1.0",
+                     "traffic_unit": f"bytes per step ({k - 2} gather launches), FETCH_SIZE x2.0 + WRITE_SIZE x1.0",
                      "kernel": "k_gather + k_gather_hub (neighbour-record gather of the DP, levels 2..k-1)",
                      "bytes_per_step": g_bytes, "ms_per_step": g_ms},
     }
+    if ags is not None:
+        out["ags"] = ags
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(g.m, ns)
+        out["cpu_baseline"] = cpu_baseline(cfg, g.m, ns)
     print(json.dumps(out), flush=True)
 
 

@@ -80,11 +80,10 @@ def csr_from_edges(n: int, edges: np.ndarray) -> Graph:
         key = np.unique(u[keep] * n + v[keep])
         u = key // n
         v = key % n
-        src = np.concatenate([u, v])
-        dst = np.concatenate([v, u])
-        order = np.argsort(src * n + dst, kind="stable")
-        src = src[order]
-        dst = dst[order]
+        # both directions; the keys are distinct, so sorting them orders the arcs
+        arcs = np.sort(np.concatenate([u * n + v, v * n + u]))
+        src = arcs // n
+        dst = arcs % n
     else:
         src = np.zeros(0, np.int64)
         dst = np.zeros(0, np.int64)
@@ -92,6 +91,18 @@ def csr_from_edges(n: int, edges: np.ndarray) -> Graph:
     row_ptr = np.zeros(n + 1, dtype=np.int64)
     np.cumsum(counts, out=row_ptr[1:])
     return Graph(n, row_ptr, dst.astype(np.int32))
+
+
+def _first_occurrences(x: np.ndarray) -> np.ndarray:
+    """Ascending positions of the first occurrence of each distinct value of x
+    (what np.unique(x, return_index=True) gives, sorted), with a multi-threaded
+    stable sort."""
+    import torch
+    sv, perm = torch.sort(torch.from_numpy(np.ascontiguousarray(x)), stable=True)
+    head = torch.ones(sv.shape[0], dtype=torch.bool)
+    if sv.shape[0] > 1:
+        head[1:] = sv[1:] != sv[:-1]
+    return np.sort(perm[head].numpy())
 
 
 def _distinct_edges(n: int, m: int, draw, max_rounds: int = 64) -> np.ndarray:
@@ -109,9 +120,7 @@ def _distinct_edges(n: int, m: int, draw, max_rounds: int = 64) -> np.ndarray:
         ok = lo != hi
         new = lo[ok] * n + hi[ok]
         allk = np.concatenate([keys, new])
-        _, first = np.unique(allk, return_index=True)
-        first.sort()
-        keys = allk[first]
+        keys = allk[_first_occurrences(allk)]
         if keys.shape[0] >= m:
             keys = keys[:m]
             break
@@ -146,11 +155,19 @@ def chung_lu_weights(n: int, m: int, gamma: float, wmax: float) -> np.ndarray:
         raise ValueError("no i0 gives the requested edge count")
     for _ in range(200):
         mid = np.sqrt(lo * hi)
+        if mid == lo or mid == hi:
+            break   # adjacent doubles: later steps change nothing
         if total(mid) < 2 * m:
             lo = mid
         else:
             hi = mid
     return wmax * np.power(1.0 + i / hi, -alpha)
+
+
+def _search_right(cdf: np.ndarray, x: np.ndarray) -> np.ndarray:
+    """np.searchsorted(cdf, x, side="right"), multi-threaded."""
+    import torch
+    return torch.searchsorted(torch.from_numpy(cdf), torch.from_numpy(x), right=True).numpy().astype(np.int64)
 
 
 def chung_lu(n: int, m: int, gamma: float, wmax: float, seed: int) -> Graph:
@@ -161,8 +178,8 @@ def chung_lu(n: int, m: int, gamma: float, wmax: float, seed: int) -> Graph:
     cdf /= cdf[-1]
 
     def draw(c):
-        a = np.searchsorted(cdf, rng.random(c), side="right")
-        b = np.searchsorted(cdf, rng.random(c), side="right")
+        a = _search_right(cdf, rng.random(c))
+        b = _search_right(cdf, rng.random(c))
         np.minimum(a, n - 1, out=a)
         np.minimum(b, n - 1, out=b)
         return a.astype(np.int64), b.astype(np.int64)

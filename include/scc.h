@@ -373,7 +373,9 @@ scc_status scc_server_get_stats(scc_server *s, scc_server_stats *out);
    steps in flight finish, and every buffer of the server is freed. */
 void scc_server_destroy(scc_server *s);
 
-/* Frees per-k device lookup tables kept by scc_classify. */
+/* Frees the per-k class data kept by scc_classify, scc_catalog and AGS (device
+   lookup tables, spanning-tree counts). Call only when no classification, AGS
+   run or server is in progress. */
 void scc_release_caches(void);
 
 /* Thread-local message for the last non-OK status of this thread. */

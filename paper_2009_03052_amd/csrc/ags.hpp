@@ -15,7 +15,7 @@ struct AgsState {
     std::vector<int64_t> c, nj;
     std::vector<double> w, tjd;
     std::vector<char> cov, sig_ok;
-    std::vector<int64_t> sig;             // sigma_ij, filled for classes once hit
+    std::vector<const int64_t *> sig;     // sigma_ij row of each class once hit (process-wide cache)
     std::vector<int32_t> shapes;          // shape of every round so far
     int64_t drawn = 0, ncov = 0;
     int j = -1;                           // shape of the next round
@@ -30,5 +30,8 @@ struct AgsState {
     void result(int64_t *hits, double *w_out, int64_t *n_j) const;
 };
 
+// sigma_ij rows (spanning trees of each unrooted shape) of classes `ids` of k,
+// computed on host threads on first use and kept for the process
+void class_sigma_rows(int k, const std::vector<int> &ids, std::vector<const int64_t *> &rows);
 // the k-graphlet class lookup table on the device (built once per k)
 scc_status class_lut(int k, hipStream_t st, const uint16_t **lut, int *num_classes);

@@ -15,6 +15,8 @@
 #include <cmath>
 #include <cstring>
 #include <functional>
+#include <mutex>
+#include <thread>
 #include <unordered_map>
 
 #include "ags.hpp"
@@ -231,6 +233,7 @@ struct ClassData {
     std::vector<uint32_t> codes;      // canonical code of each class
     std::vector<int64_t> sigma;       // spanning trees
     std::vector<std::vector<int64_t>> sigma_ij;   // per class, computed on demand
+    std::mutex sig_mu;
 };
 
 std::mutex g_cls_mu;
@@ -259,7 +262,8 @@ scc_status ensure_classes(int k, hipStream_t st, ClassData **out)
     scc_status s = scan_u32(&tmp, rank, rank, (int64_t)ncodes);
     if (s) { cleanup(); (void)hipFree(lut); return s; }
     uint32_t nclass = 0;
-    if (hipMemcpy(&nclass, rank + (ncodes - 1), 4, hipMemcpyDeviceToHost) != hipSuccess) {
+    if (hipMemcpyAsync(&nclass, rank + (ncodes - 1), 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
         cleanup(); (void)hipFree(lut);
         return set_error(SCC_EDEVICE, "class count");
     }
@@ -312,39 +316,66 @@ int64_t spanning_trees_host(uint32_t code, int k)
     return (int64_t)det;
 }
 
+// unrooted shape of every labelled tree on k nodes, by edge code: the trees are
+// the decodings of the k^(k-2) Pruefer sequences (Cayley); built once per k
+const std::unordered_map<uint32_t, uint8_t> &tree_shapes(int k)
+{
+    static std::once_flag once[SCC_KMAX + 1];
+    static std::unordered_map<uint32_t, uint8_t> maps[SCC_KMAX + 1];
+    std::call_once(once[k], [k] {
+        auto &m = maps[k];
+        auto add = [&](const int *eu, const int *ev) {
+            uint32_t code = 0, adj[SCC_KMAX] = {0};
+            for (int e = 0; e < k - 1; e++) {
+                code |= 1u << pair_id(std::min(eu[e], ev[e]), std::max(eu[e], ev[e]), k);
+                adj[eu[e]] |= 1u << ev[e];
+                adj[ev[e]] |= 1u << eu[e];
+            }
+            m.emplace(code, (uint8_t)tree_unrooted_id(k, adj));
+        };
+        if (k < 2) return;
+        int64_t total = 1;
+        for (int i = 0; i < k - 2; i++) total *= k;
+        int seq[SCC_KMAX], eu[SCC_KMAX], ev[SCC_KMAX], deg[SCC_KMAX];
+        for (int64_t x = 0; x < total; x++) {
+            int64_t y = x;
+            for (int i = 0; i < k - 2; i++) { seq[i] = (int)(y % k); y /= k; }
+            for (int i = 0; i < k; i++) deg[i] = 1;
+            for (int i = 0; i < k - 2; i++) deg[seq[i]]++;
+            for (int i = 0; i < k - 2; i++) {
+                int leaf = 0;
+                while (deg[leaf] != 1) leaf++;
+                eu[i] = leaf; ev[i] = seq[i];
+                deg[leaf]--; deg[seq[i]]--;
+            }
+            int a = -1, b = -1;
+            for (int i = 0; i < k; i++)
+                if (deg[i] == 1) { if (a < 0) a = i; else b = i; }
+            eu[k - 2] = a; ev[k - 2] = b;
+            add(eu, ev);
+        }
+    });
+    return maps[k];
+}
+
 // spanning trees of a graphlet by unrooted shape: a depth-first choice of k-1
 // edges that never closes a cycle (every acyclic (k-1)-edge set on k vertices
 // is a spanning tree); each tree's shape is looked up through its edge code
 void spanning_trees_by_shape_host(uint32_t code, int k, int64_t *out)
 {
-    static std::mutex memo_mu;
-    static std::unordered_map<uint64_t, int> memo;   // (k, tree code) -> shape
     const int nu = unrooted_count(k);
     for (int j = 0; j < nu; j++) out[j] = 0;
     if (k == 1) { out[0] = 1; return; }
+    const auto &shapes = tree_shapes(k);
     int eu[32], ev[32], ne = 0;
     for (int i = 0; i < k; i++)
         for (int j = i + 1; j < k; j++)
             if (code >> pair_id(i, j, k) & 1u) { eu[ne] = i; ev[ne] = j; ne++; }
     int comp[SCC_KMAX];
     for (int i = 0; i < k; i++) comp[i] = i;
-    // recursive lambda over edge index with the component labels
     std::function<void(int, int, uint32_t)> rec = [&](int e, int chosen, uint32_t tcode) {
         if (chosen == k - 1) {
-            const uint64_t key = ((uint64_t)k << 32) | tcode;
-            int sh;
-            {
-                std::lock_guard<std::mutex> g(memo_mu);
-                auto it = memo.find(key);
-                if (it != memo.end()) sh = it->second;
-                else {
-                    uint32_t adj[SCC_KMAX];
-                    code_to_adj(tcode, k, adj);
-                    sh = tree_unrooted_id(k, adj);
-                    memo.emplace(key, sh);
-                }
-            }
-            out[sh]++;
+            out[shapes.at(tcode)]++;
             return;
         }
         if (ne - e < (k - 1) - chosen) return;
@@ -396,7 +427,11 @@ extern "C" scc_status scc_catalog(int k, int64_t *num_classes, uint32_t *codes, 
         for (int64_t i = 0; i < nc; i++) sigma[i] = spanning_trees_host(cd->codes[i], k);
     if (sigma_ij) {
         const int nu = unrooted_count(k);
-        for (int64_t i = 0; i < nc; i++) spanning_trees_by_shape_host(cd->codes[i], k, sigma_ij + i * nu);
+        std::vector<int> ids((size_t)nc);
+        for (int64_t i = 0; i < nc; i++) ids[i] = (int)i;
+        std::vector<const int64_t *> rows;
+        class_sigma_rows(k, ids, rows);
+        for (int64_t i = 0; i < nc; i++) memcpy(sigma_ij + i * nu, rows[i], (size_t)nu * 8);
     }
     return SCC_OK;
 }
@@ -415,6 +450,36 @@ void launch_serve_classify(const ServeClassArgs *args, const ServeChunk *ch, con
     if (total <= 0 || nch <= 0) return;
     hipLaunchKernelGGL(k_serve_classify, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, args, ch, cend, nch,
                        total);
+}
+
+void class_sigma_rows(int k, const std::vector<int> &ids, std::vector<const int64_t *> &rows)
+{
+    ClassData *cd = g_cls[k];          // built by ensure_classes before any AGS state exists
+    const int nu = unrooted_count(k);
+    std::vector<int> todo;
+    {
+        std::lock_guard<std::mutex> lk(cd->sig_mu);
+        for (int i : ids)
+            if (cd->sigma_ij[i].empty()) todo.push_back(i);
+    }
+    if (!todo.empty()) {
+        std::vector<std::vector<int64_t>> res(todo.size(), std::vector<int64_t>(nu));
+        const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+        const size_t nt = std::min<size_t>(hw, (todo.size() + 7) / 8);
+        auto work = [&](size_t t) {
+            for (size_t q = t; q < todo.size(); q += nt) spanning_trees_by_shape_host(cd->codes[todo[q]], k, res[q].data());
+        };
+        std::vector<std::thread> th;
+        for (size_t t = 1; t < nt; t++) th.emplace_back(work, t);
+        work(0);
+        for (auto &x : th) x.join();
+        std::lock_guard<std::mutex> lk(cd->sig_mu);
+        for (size_t q = 0; q < todo.size(); q++)
+            if (cd->sigma_ij[todo[q]].empty()) cd->sigma_ij[todo[q]] = std::move(res[q]);
+    }
+    std::lock_guard<std::mutex> lk(cd->sig_mu);
+    rows.resize(ids.size());
+    for (size_t q = 0; q < ids.size(); q++) rows[q] = cd->sigma_ij[ids[q]].data();
 }
 
 scc_status class_lut(int k, hipStream_t st, const uint16_t **lut, int *num_classes)
@@ -438,7 +503,7 @@ scc_status AgsState::init(const scc_table *T, int64_t cbar_, hipStream_t st)
     NS = T->hlut.num_unr;
     cbar = cbar_;
     c.assign(S, 0); nj.assign(NS, 0); w.assign(S, 0.0); tjd.assign(NS, 0.0);
-    cov.assign(S, 0); sig_ok.assign(S, 0); sig.assign((size_t)S * NS, 0);
+    cov.assign(S, 0); sig_ok.assign(S, 0); sig.assign(S, nullptr);
     shapes.clear();
     drawn = 0; ncov = 0; j = -1;
     for (int q = 0; q < NS; q++) tjd[q] = (double)T->tj[q];
@@ -453,10 +518,16 @@ void AgsState::add_round(int64_t n, const unsigned long long *hh)
     shapes.push_back(j);
     drawn += n;
     nj[j] += n;
+    std::vector<int> fresh;
     for (int i = 0; i < S; i++) {
         if (!hh[i]) continue;
         c[i] += (int64_t)hh[i];
-        if (!sig_ok[i]) { spanning_trees_by_shape_host(codes[i], k, &sig[(size_t)i * NS]); sig_ok[i] = 1; }
+        if (!sig_ok[i]) { fresh.push_back(i); sig_ok[i] = 1; }
+    }
+    if (!fresh.empty()) {
+        std::vector<const int64_t *> rows;
+        class_sigma_rows(k, fresh, rows);
+        for (size_t q = 0; q < fresh.size(); q++) sig[fresh[q]] = rows[q];
     }
     bool newcov = false;
     for (int i = 0; i < S; i++)
@@ -468,7 +539,7 @@ void AgsState::add_round(int64_t n, const unsigned long long *hh)
         if (!cov[i]) continue;
         double acc = 0.0;
         for (int q = 0; q < NS; q++)
-            if (tjd[q] > 0) acc += (double)nj[q] * (double)sig[(size_t)i * NS + q] / tjd[q];
+            if (tjd[q] > 0) acc += (double)nj[q] * (double)sig[i][q] / tjd[q];
         w[i] = acc;
     }
     int best = -1;
@@ -477,7 +548,7 @@ void AgsState::add_round(int64_t n, const unsigned long long *hh)
         if (!(tjd[q] > 0)) continue;
         double acc = 0.0;
         for (int i = 0; i < S; i++)
-            if (cov[i]) acc += (double)sig[(size_t)i * NS + q] * (double)c[i] / w[i];
+            if (cov[i]) acc += (double)sig[i][q] * (double)c[i] / w[i];
         acc /= tjd[q];
         if (best < 0 || acc < bv) { best = q; bv = acc; }
     }
@@ -490,7 +561,7 @@ void AgsState::result(int64_t *hits, double *w_out, int64_t *n_j) const
         double acc = 0.0;
         if (sig_ok[i])
             for (int q = 0; q < NS; q++)
-                if (tjd[q] > 0) acc += (double)nj[q] * (double)sig[(size_t)i * NS + q] / tjd[q];
+                if (tjd[q] > 0) acc += (double)nj[q] * (double)sig[i][q] / tjd[q];
         hits[i] = c[i];
         w_out[i] = acc;
     }

@@ -886,12 +886,14 @@ scc_status scan_incl(scc_table *T_, const T *in, T *out, int64_t n)
 {
     if (n <= 0) return SCC_OK;
     const int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
-    T *bsum = (T *)T_->mem.get(nb * sizeof(T));
+    DevMem m = T_->mem;        // scratch ordered on the stream the scan runs on
+    m.stream = T_->stream;
+    T *bsum = (T *)m.get(nb * sizeof(T));
     if (!bsum) return set_error(SCC_ENOMEM, "scan scratch");
     hipLaunchKernelGGL(k_scan_sums<T>, dim3((unsigned)nb), dim3(SCAN_T), 0, T_->stream, in, n, bsum);
     hipLaunchKernelGGL(k_scan_top<T>, dim3(1), dim3(SCAN_T), 0, T_->stream, bsum, nb);
     hipLaunchKernelGGL(k_scan_apply<T>, dim3((unsigned)nb), dim3(SCAN_T), 0, T_->stream, in, out, n, bsum);
-    T_->mem.put(bsum);   // stream-ordered release: reused only by later work on this stream
+    m.put(bsum);   // stream-ordered release: reused only by later work on this stream
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return set_error(SCC_EDEVICE, "scan: %s", hipGetErrorString(e));
     return SCC_OK;

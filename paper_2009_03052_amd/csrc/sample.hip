@@ -201,23 +201,33 @@ __device__ inline int sample_one(const SampleArgs &A, int64_t r, SampleLds &W)
                 wu = P(j) - (j > 0 ? P(j - 1) : (u128)0);
             }
         } else {
+            // CSR order, 4 x 64 neighbours per round: every lane issues the loads of
+            // its 4 neighbours before using any, then the 4 groups are scanned in order
             u128 run2 = 0;
-            for (int64_t base = ra; base < rb; base += WAVE) {
-                const int64_t e = base + lane;
-                u128 c = 0;
-                int32_t uu = -1;
-                if (e < rb) {
-                    uu = A.g.col_idx[e];
-                    c = own_count(A, hpp, uu, kpp);
+            bool found = false;
+            for (int64_t base = ra; base < rb && !found; base += 4 * WAVE) {
+                int32_t uu[4];
+                u128 c[4];
+#pragma unroll
+                for (int g4 = 0; g4 < 4; g4++) {
+                    const int64_t e = base + g4 * WAVE + lane;
+                    uu[g4] = e < rb ? A.g.col_idx[e] : -1;
                 }
-                const u128 incl = run2 + wave_incl_scan128(c);
-                const int w2 = first_exceeding(incl, Z);
-                if (w2 >= 0) {
-                    u = __shfl(uu, w2, WAVE);
-                    wu = shfl128(c, w2);
-                    break;
+#pragma unroll
+                for (int g4 = 0; g4 < 4; g4++) c[g4] = uu[g4] >= 0 ? own_count(A, hpp, uu[g4], kpp) : (u128)0;
+#pragma unroll
+                for (int g4 = 0; g4 < 4; g4++) {
+                    if (found) break;
+                    const u128 incl = run2 + wave_incl_scan128(c[g4]);
+                    const int w2 = first_exceeding(incl, Z);
+                    if (w2 >= 0) {
+                        u = __shfl(uu[g4], w2, WAVE);
+                        wu = shfl128(c[g4], w2);
+                        found = true;
+                    } else {
+                        run2 = shfl128(incl, WAVE - 1);
+                    }
                 }
-                run2 = shfl128(incl, WAVE - 1);
             }
         }
         if (u < 0) { fail = true; break; }
@@ -241,7 +251,9 @@ __device__ inline int sample_one(const SampleArgs &A, int64_t r, SampleLds &W)
     return 0;
 }
 
-__global__ void __launch_bounds__(WAVE) k_sample(SampleArgs A)
+// four waves per SIMD fit without spilling; the draws are latency-bound, so
+// more waves in flight beat more registers
+__global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4, 8))) k_sample(SampleArgs A)
 {
     __shared__ SampleLds W;
     for (int64_t s = blockIdx.x; s < A.nsamp; s += gridDim.x) {
@@ -254,7 +266,7 @@ __global__ void __launch_bounds__(WAVE) k_sample(SampleArgs A)
 // A serving step: rows of many requests (each with its own table, shape and
 // random stream), flattened; row s belongs to the first chunk whose running end
 // exceeds s. The grid strides over the rows.
-__global__ void __launch_bounds__(WAVE) k_serve_sample(const SampleArgs *args, const ServeChunk *ch,
+__global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4, 8))) k_serve_sample(const SampleArgs *args, const ServeChunk *ch,
                                                       const int64_t *cend, int nch, int64_t total, int *err)
 {
     __shared__ SampleLds W;

@@ -103,6 +103,7 @@ struct Session {
 constexpr int STEP_BUFS = 2;
 
 struct StepBuf {
+    hipStream_t stream = nullptr;    // the step buffers alternate between two streams
     SampleArgs *hargs = nullptr, *dargs = nullptr;
     ServeClassArgs *hcls = nullptr, *dcls = nullptr;
     ServeChunk *hch = nullptr, *dch = nullptr;
@@ -124,7 +125,7 @@ double now_s(std::chrono::steady_clock::time_point t0)
 struct scc_server {
     std::vector<scc_table *> tables;
     scc_server_opts o{};
-    hipStream_t st = nullptr, side = nullptr;
+    hipStream_t st = nullptr, st2 = nullptr, side = nullptr;
     bool own_stream = false;
     DevMem mem;
     uint8_t *arena_base = nullptr;
@@ -202,7 +203,9 @@ void scc_server::activate_rounds_locked()
         r.first = s.next_first;
         s.next_first += (uint64_t)r.q.n;
         s.busy = true;
-        (void)hipMemsetAsync(s.dhist, 0, (size_t)s.st.S * 8, st);   // this round's class histogram
+        // this round's class histogram, cleared before any of its steps (on either stream) runs
+        (void)hipMemsetAsync(s.dhist, 0, (size_t)s.st.S * 8, side);
+        (void)hipStreamSynchronize(side);
         active.push_back(r.id);
     }
 }
@@ -263,6 +266,7 @@ scc_status scc_server::launch_step(int b)
 {
     StepBuf &B = sb[b];
     const int n = B.nch;
+    hipStream_t st = B.stream;
     HIP_TRY(hipMemsetAsync(B.derr, 0, 4, st));
     HIP_TRY(hipMemcpyAsync(B.dargs, B.hargs, (size_t)n * sizeof(SampleArgs), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(B.dcls, B.hcls, (size_t)n * sizeof(ServeClassArgs), hipMemcpyHostToDevice, st));
@@ -313,39 +317,55 @@ void scc_server::complete_step_locked(int b, std::unique_lock<std::mutex> &lk)
 void scc_server::run()
 {
     std::unique_lock<std::mutex> lk(mu);
-    std::deque<int> inflight;
-    int next = 0;
+    bool busy[STEP_BUFS] = {};
     for (;;) {
         admit_locked();
         activate_rounds_locked();
-        if (stop && inflight.empty()) break;
-        if (!stop && (int)inflight.size() < STEP_BUFS && build_step_locked(next)) {
-            const int b = next;
-            next = (next + 1) % STEP_BUFS;
+        int nbusy = 0, free_b = -1;
+        for (int b = 0; b < STEP_BUFS; b++) {
+            if (busy[b]) nbusy++;
+            else if (free_b < 0) free_b = b;
+        }
+        if (stop && nbusy == 0) break;
+        // a free buffer and work: launch a step on that buffer's stream
+        // the first-in first-out mode runs one request at a time: one step in flight
+        const int max_inflight = o.fifo ? 1 : STEP_BUFS;
+        if (!stop && free_b >= 0 && nbusy < max_inflight && build_step_locked(free_b)) {
             lk.unlock();
-            const scc_status s = launch_step(b);
+            const scc_status s = launch_step(free_b);
             lk.lock();
             if (s) {
                 fatal = s;
-                for (int64_t id : sb[b].req) reqs[id].status = s;
+                for (int64_t id : sb[free_b].req) reqs[id].status = s;
             }
-            inflight.push_back(b);
+            busy[free_b] = true;
             continue;
         }
-        if (!inflight.empty()) {
-            const int b = inflight.front();
-            inflight.pop_front();
+        if (nbusy) {
+            // finish whichever step is done first (the two streams overlap)
             lk.unlock();
+            int done = -1;
+            hipError_t e = hipSuccess;
             const auto w0 = std::chrono::steady_clock::now();
-            const hipError_t e = hipEventSynchronize(sb[b].ev);
+            while (done < 0) {
+                for (int b = 0; b < STEP_BUFS && done < 0; b++) {
+                    if (!busy[b]) continue;
+                    const hipError_t q = hipEventQuery(sb[b].ev);
+                    if (q == hipErrorNotReady) continue;
+                    done = b;
+                    e = q;
+                }
+                if (done < 0) std::this_thread::sleep_for(std::chrono::microseconds(50));
+            }
             const double waited = std::chrono::duration<double>(std::chrono::steady_clock::now() - w0).count();
             lk.lock();
             busy_s += waited;
+            busy[done] = false;
             if (e != hipSuccess) {
                 fatal = SCC_EDEVICE;
-                for (int64_t id : sb[b].req) reqs[id].status = SCC_EDEVICE;
+                for (int64_t id : sb[done].req) reqs[id].status = SCC_EDEVICE;
             }
-            complete_step_locked(b, lk);
+            complete_step_locked(done, lk);
             continue;
         }
         cv_work.wait_for(lk, std::chrono::milliseconds(20));
@@ -385,8 +405,11 @@ extern "C" scc_status scc_server_create(const scc_server_opts *opts, scc_server 
         S->own_stream = true;
     }
     S->mem.stream = S->st;
-    if (hipStreamCreateWithFlags(&S->side, hipStreamNonBlocking) != hipSuccess)
-        return fail(set_error(SCC_EDEVICE, "server side stream"));
+    if (hipStreamCreateWithFlags(&S->side, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&S->st2, hipStreamNonBlocking) != hipSuccess)
+        return fail(set_error(SCC_EDEVICE, "server streams"));
+    S->sb[0].stream = S->st;
+    S->sb[1].stream = S->st2;
     // everything the loop needs is built and allocated here, on the caller's thread
     for (int i = 0; i < opts->n_tables; i++) {
         scc_table *T = const_cast<scc_table *>(opts->tables[i]);
@@ -600,6 +623,7 @@ extern "C" void scc_server_destroy(scc_server *S)
         S->th.join();
     }
     if (S->st) (void)hipStreamSynchronize(S->st);
+    if (S->st2) (void)hipStreamSynchronize(S->st2);
     if (S->side) (void)hipStreamSynchronize(S->side);
     for (StepBuf &B : S->sb) {
         if (B.hargs) (void)hipHostFree(B.hargs);
@@ -614,6 +638,7 @@ extern "C" void scc_server_destroy(scc_server *S)
     S->mem.put(S->arena_base);
     if (S->st) (void)hipStreamSynchronize(S->st);
     if (S->side) (void)hipStreamDestroy(S->side);
+    if (S->st2) (void)hipStreamDestroy(S->st2);
     if (S->own_stream && S->st) (void)hipStreamDestroy(S->st);
     delete S;
 }

@@ -89,6 +89,20 @@ def test_catalog_equal(k):
 
 
 @pytest.mark.timeout(300)
+@pytest.mark.parametrize("k", [7, 8])
+def test_catalog_sigma_ij_large_k(k):
+    # spanning trees by shape at k = 7, 8 (the tree-shape table and the threaded cache)
+    S = scc()
+    cat = S.catalog(k, with_sigma=True, with_sigma_ij=True)
+    rng = np.random.default_rng(k)
+    pick = rng.choice(len(cat["codes"]), 40, replace=False)
+    for i in list(pick) + [len(cat["codes"]) - 1]:
+        c = int(cat["codes"][i])
+        assert np.array_equal(cat["sigma_ij"][i], O.spanning_trees_by_shape(c, k)), i
+        assert cat["sigma_ij"][i].sum() == cat["sigma"][i]
+
+
+@pytest.mark.timeout(300)
 def test_catalog_k8_matches_paper_and_oracle():
     # Sec. 5.2: 11117 distinct 8-graphlets; codes equal the oracle's catalog
     S = scc()
