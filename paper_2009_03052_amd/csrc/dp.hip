@@ -149,6 +149,7 @@ template <bool SLOTS> __device__ inline RecView<SLOTS> h_rec(const LevelSrc &S, 
 struct GatherArgs {
     GraphView g;
     int k, nkeys, WS, rows_zero, hub_degree;
+    int key_lo, key_n;             // keys of the gathered level: [key_lo, key_lo + key_n), key_n <= GATHER_MAX_KEYS
     LevelSrc L;
     u128 *M;                       // out: M_hs (regular rows); in: hub rows
     const int16_t *key_sidx;       // [k * nkeys]
@@ -158,17 +159,20 @@ struct GatherArgs {
     int *err;
 };
 
+// most keys on one level: r_6 C(8, 6) = 560 at k = 8
+constexpr int GATHER_MAX_KEYS = 576;
+inline size_t gather_lds(int WS) { return (size_t)2 * WS * 8 + GATHER_MAX_KEYS * 2; }
+
 // Adds the level-hs entries of neighbours col_idx[a..b) of v into the LDS sums
 // and returns (in every lane) the saturating sum of those neighbours' level
 // sums N. With wideS false only low words are added: exact whenever that
 // returned bound is below 2^64, since every entry and every partial sum is
 // at most the bound.
 template <bool SLOTS>
-__device__ inline u128 gather_range(const GatherArgs &A, int cv, int64_t a, int64_t b, bool wideS,
-                                    uint64_t *acc_lo, uint64_t *acc_hi)
+__device__ inline u128 gather_range(const GatherArgs &A, int64_t a, int64_t b, bool wideS, uint64_t *acc_lo,
+                                    uint64_t *acc_hi, const int16_t *ssm)
 {
     const int lane = threadIdx.x;
-    const int16_t *sidx = A.key_sidx + (size_t)cv * A.nkeys;
     u128 m = 0;
     for (int64_t base = a; base < b; base += WAVE) {
         const int64_t e = base + lane;
@@ -177,34 +181,48 @@ __device__ inline u128 gather_range(const GatherArgs &A, int cv, int64_t a, int6
         if (len) m = sat_add(m, h_N<SLOTS>(A.L, hd));
         const uint32_t incl = wave_incl_scan32(len);
         const uint32_t total = __shfl(incl, WAVE - 1, WAVE);
-        // entries of this chunk of neighbours, flattened over the lanes
-        for (uint32_t p0 = 0; p0 < total; p0 += WAVE) {
-            const uint32_t p = p0 + lane;
-            // owner neighbour j: number of lanes whose inclusive count is <= p
-            // (fixed six steps, so every lane takes part in every shuffle)
-            int j = 0;
+        // entries of this chunk of neighbours, flattened over the lanes; every lane
+        // takes 4 entries per round and issues their loads before using any
+        for (uint32_t p0 = 0; p0 < total; p0 += 4 * WAVE) {
+            uint32_t key[4];
+            uint64_t cl[4], ch[4];
+            bool ok[4];
 #pragma unroll
-            for (int step = WAVE / 2; step >= 1; step >>= 1) {
-                const uint32_t x = __shfl(incl, j + step - 1, WAVE);
-                if (x <= p) j += step;
+            for (int q = 0; q < 4; q++) {
+                const uint32_t p = p0 + q * WAVE + lane;
+                // owner neighbour j: number of lanes whose inclusive count is <= p
+                // (fixed six steps, so every lane takes part in every shuffle)
+                int j = 0;
+#pragma unroll
+                for (int step = WAVE / 2; step >= 1; step >>= 1) {
+                    const uint32_t x = __shfl(incl, j + step - 1, WAVE);
+                    if (x <= p) j += step;
+                }
+                if (j > WAVE - 1) j = WAVE - 1;
+                const uint32_t incl_j = __shfl(incl, j, WAVE);
+                const uint64_t hd_j = shfl64(hd, j);
+                ok[q] = p < total;
+                key[q] = 0;
+                cl[q] = ch[q] = 0;
+                if (ok[q]) {
+                    const RecView<SLOTS> r = h_rec<SLOTS>(A.L, hd_j);
+                    const uint32_t ei = p - (incl_j - r.len);
+                    key[q] = r.key[ei];
+                    cl[q] = r.lo[ei];
+                    if (wideS && r.hi) ch[q] = r.hi[ei];
+                }
             }
-            if (j > WAVE - 1) j = WAVE - 1;
-            const uint32_t incl_j = __shfl(incl, j, WAVE);
-            const uint64_t hd_j = shfl64(hd, j);
-            if (p < total) {
-                const RecView<SLOTS> r = h_rec<SLOTS>(A.L, hd_j);
-                const uint32_t ei = p - (incl_j - r.len);
-                const uint64_t cl = r.lo[ei];
-                const int s = sidx[r.key[ei]];
-                if (s >= 0) {
-                    if (!wideS) {
-                        atomicAdd((unsigned long long *)&acc_lo[s], (unsigned long long)cl);
-                    } else {
-                        const uint64_t ch = r.hi ? r.hi[ei] : 0;
-                        const unsigned long long old = atomicAdd((unsigned long long *)&acc_lo[s], (unsigned long long)cl);
-                        const uint64_t carry = (old + cl) < old ? 1u : 0u;
-                        if (ch + carry) atomicAdd((unsigned long long *)&acc_hi[s], (unsigned long long)(ch + carry));
-                    }
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                if (!ok[q]) continue;
+                const int s = ssm[key[q] - A.key_lo];
+                if (s < 0) continue;
+                if (!wideS) {
+                    atomicAdd((unsigned long long *)&acc_lo[s], (unsigned long long)cl[q]);
+                } else {
+                    const unsigned long long old = atomicAdd((unsigned long long *)&acc_lo[s], (unsigned long long)cl[q]);
+                    const uint64_t carry = (old + cl[q]) < old ? 1u : 0u;
+                    if (ch[q] + carry) atomicAdd((unsigned long long *)&acc_hi[s], (unsigned long long)(ch[q] + carry));
                 }
             }
         }
@@ -214,21 +232,25 @@ __device__ inline u128 gather_range(const GatherArgs &A, int cv, int64_t a, int6
 
 // LDS sums of the neighbours in [a, b): 64-bit pass first, a 128-bit pass only
 // when the bound says 64 bits may not suffice
+// LDS: acc_lo[WS], acc_hi[WS], then the index slice of colour cv (GATHER_MAX_KEYS int16)
 template <bool SLOTS>
 __device__ inline u128 gather_sums(const GatherArgs &A, int cv, int64_t a, int64_t b, uint64_t *acc_lo,
                                    uint64_t *acc_hi, bool &wideS)
 {
     const int lane = threadIdx.x;
     const int WS = A.WS;
+    int16_t *ssm = (int16_t *)(acc_hi + WS);
+    const int16_t *sidx = A.key_sidx + (size_t)cv * A.nkeys + A.key_lo;
+    for (int i = lane; i < A.key_n; i += WAVE) ssm[i] = sidx[i];
     for (int i = lane; i < WS; i += WAVE) { acc_lo[i] = 0; acc_hi[i] = 0; }
     __syncthreads();
-    u128 m = gather_range<SLOTS>(A, cv, a, b, false, acc_lo, acc_hi);
+    u128 m = gather_range<SLOTS>(A, a, b, false, acc_lo, acc_hi, ssm);
     wideS = hi64(m) != 0;
     if (wideS) {
         __syncthreads();
         for (int i = lane; i < WS; i += WAVE) { acc_lo[i] = 0; acc_hi[i] = 0; }
         __syncthreads();
-        m = gather_range<SLOTS>(A, cv, a, b, true, acc_lo, acc_hi);
+        m = gather_range<SLOTS>(A, a, b, true, acc_lo, acc_hi, ssm);
     }
     __syncthreads();
     return m;
@@ -1049,10 +1071,11 @@ static scc_status build_levels(scc_table *T)
             if (!Sx.M || !Sx.lo || !Sx.hi) return set_error(SCC_ENOMEM, "neighbour sums level %d (%zu bytes)", hs, 2 * sz);
             GatherArgs G{};
             G.g = g; G.k = k; G.nkeys = HL.nkeys; G.WS = HL.WS[hs]; G.rows_zero = zero && h == k;
+            G.key_lo = HL.off[hs]; G.key_n = HL.r[hs] * HL.bk[hs];
             G.hub_degree = hub_degree;
             G.L = packed_src(T->lev[hs]); G.M = Sx.M; G.key_sidx = T->key_sidx; G.Slo = Sx.lo; G.Shi = Sx.hi;
             G.chunk_v = chunk_v; G.chunk_e = chunk_e; G.err = err;
-            const size_t lds = (size_t)2 * HL.WS[hs] * 8;
+            const size_t lds = gather_lds(HL.WS[hs]);
             HIP_TRY(hipEventRecord(gev[hs][0], st));
             if (nhub) {
                 hipLaunchKernelGGL(k_hub_prepare, dim3((unsigned)nhub), dim3(WAVE), 0, st, G, hubs);
@@ -1650,6 +1673,7 @@ static scc_status batch_launch(std::vector<BatchInstHost> &H, int tile, int hub_
         for (int h = 2; h < k; h++) {
             GatherArgs &G = B.G[h];
             G.g = B.g; G.k = k; G.nkeys = HL.nkeys; G.WS = HL.WS[h]; G.rows_zero = zero && h == k - 1;
+            G.key_lo = HL.off[h]; G.key_n = HL.r[h] * HL.bk[h];
             G.hub_degree = hub_degree;
             G.L = slot_src(h); G.M = T->S[h].M; G.key_sidx = T->key_sidx; G.Slo = T->S[h].lo; G.Shi = T->S[h].hi;
             G.err = nullptr;
@@ -1700,7 +1724,7 @@ static scc_status batch_launch(std::vector<BatchInstHost> &H, int tile, int hub_
         for (int h = 2; h <= H[i].T->k; h++) {
             lds = std::max(lds, (size_t)(HL.xoff[h] + HL.soff[h]) * 8);
             hi_stride = std::max<int64_t>(hi_stride, HL.xoff[h] + HL.soff[h]);
-            if (h < H[i].T->k) lds = std::max(lds, (size_t)2 * HL.WS[h] * 8);
+            if (h < H[i].T->k) lds = std::max(lds, gather_lds(HL.WS[h]));
         }
     }
     hi_stride = (hi_stride + 31) & ~(int64_t)31;
