@@ -152,7 +152,8 @@ def run_batching(a):
 
     plain()
     rep0 = batched()      # tunes once (probes), later calls reuse the choice
-    print(f"# tuned: tile={rep0['tile']} hub={rep0['hub_degree']} probes={rep0['probes']}", file=sys.stderr, flush=True)
+    print(f"# tuned: tile={rep0['tile']} hub={rep0['hub_degree']} waves={rep0['waves']} probes={rep0['probes']}",
+          file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     tp = []
     tb = []

@@ -250,12 +250,14 @@ typedef struct {
     int tile;          /* vertices per work item; 0 = tuned or default (256) */
     int hub_degree;    /* rows above this degree are gathered in chunks; 0 = tuned or default (1024) */
     int autotune;      /* nonzero: when no choice is given and none is cached for a batch of the
-                          same shape, time candidate (tile, hub_degree) pairs on this batch and
-                          keep the fastest for later batches of the same shape */
+                          same shape, time candidate (tile, hub_degree, waves) schedules on this
+                          batch and keep the fastest for later batches of the same shape */
+    int waves;         /* worker register budget: 8 = eight waves per SIMD (a few spills),
+                          0 = tuned or the compiler's own (about five waves per SIMD) */
 } scc_batch_opts;
 
 typedef struct {
-    int tile, hub_degree;      /* the schedule used */
+    int tile, hub_degree, waves; /* the schedule used */
     int tuned;                 /* 1 when it came from the autotuner (now or cached) */
     int grid;                  /* resident workgroups of the persistent launch */
     int64_t items;             /* work items */
@@ -264,7 +266,7 @@ typedef struct {
     double total_ms;           /* launch + pack (excludes setup and tuning) */
     double setup_ms;           /* allocation, lookup tables and tuning probes */
     int nprobe;
-    int probe_tile[16], probe_hub[16];
+    int probe_tile[16], probe_hub[16], probe_waves[16];
     double probe_ms[16];
 } scc_batch_report;
 

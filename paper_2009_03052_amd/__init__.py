@@ -53,20 +53,22 @@ class _Instance(C.Structure):
 
 
 class _BatchOpts(C.Structure):
-    _fields_ = [("tile", C.c_int), ("hub_degree", C.c_int), ("autotune", C.c_int)]
+    _fields_ = [("tile", C.c_int), ("hub_degree", C.c_int), ("autotune", C.c_int), ("waves", C.c_int)]
 
 
 class BatchReport(C.Structure):
-    _fields_ = [("tile", C.c_int), ("hub_degree", C.c_int), ("tuned", C.c_int), ("grid", C.c_int),
-                ("items", C.c_int64), ("launch_ms", C.c_double), ("pack_ms", C.c_double),
+    _fields_ = [("tile", C.c_int), ("hub_degree", C.c_int), ("waves", C.c_int), ("tuned", C.c_int),
+                ("grid", C.c_int), ("items", C.c_int64), ("launch_ms", C.c_double), ("pack_ms", C.c_double),
                 ("total_ms", C.c_double), ("setup_ms", C.c_double), ("nprobe", C.c_int),
-                ("probe_tile", C.c_int * 16), ("probe_hub", C.c_int * 16), ("probe_ms", C.c_double * 16)]
+                ("probe_tile", C.c_int * 16), ("probe_hub", C.c_int * 16), ("probe_waves", C.c_int * 16),
+                ("probe_ms", C.c_double * 16)]
 
     def as_dict(self):
-        return {"tile": self.tile, "hub_degree": self.hub_degree, "tuned": bool(self.tuned), "grid": self.grid,
-                "items": self.items, "launch_ms": self.launch_ms, "pack_ms": self.pack_ms,
+        return {"tile": self.tile, "hub_degree": self.hub_degree, "waves": self.waves, "tuned": bool(self.tuned),
+                "grid": self.grid, "items": self.items, "launch_ms": self.launch_ms, "pack_ms": self.pack_ms,
                 "total_ms": self.total_ms, "setup_ms": self.setup_ms,
-                "probes": [(self.probe_tile[i], self.probe_hub[i], self.probe_ms[i]) for i in range(self.nprobe)]}
+                "probes": [(self.probe_tile[i], self.probe_hub[i], self.probe_waves[i], self.probe_ms[i])
+                           for i in range(self.nprobe)]}
 
 
 class TableInfo(C.Structure):
@@ -312,7 +314,7 @@ class Table:
 
 
 def build_batch(instances, rooting: int = ROOT_ZERO, max_bits: int = 128, tile: int = 0, hub_degree: int = 0,
-                autotune: bool = False, stream=None, use_torch_allocator: bool = True):
+                autotune: bool = False, stream=None, use_torch_allocator: bool = True, waves: int = 0):
     """``scc_build_batch``: instances is a list of (DeviceGraph, colours, k).
     Returns ([Table], report dict)."""
     n = len(instances)
@@ -325,7 +327,7 @@ def build_batch(instances, rooting: int = ROOT_ZERO, max_bits: int = 128, tile: 
         arr[i] = _Instance(_Csr(g.n, g.nnz, g.row_ptr.data_ptr(), g.col_idx.data_ptr()), col.data_ptr(), k)
     opts = _BuildOpts(rooting, max_bits, _stream_ptr(stream),
                       C.pointer(TORCH_ALLOCATOR) if use_torch_allocator else None, 0, 0)
-    bo = _BatchOpts(tile, hub_degree, 1 if autotune else 0)
+    bo = _BatchOpts(tile, hub_degree, 1 if autotune else 0, waves)
     outs = (_P * n)()
     rep = BatchReport()
     _check(_lib.scc_build_batch(arr, n, C.byref(opts), C.byref(bo), outs, C.byref(rep)))

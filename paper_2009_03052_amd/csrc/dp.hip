@@ -580,48 +580,76 @@ __global__ void k_words(int64_t n, const uint32_t *meta, uint64_t *words)
     words[v] = len ? (uint64_t)REC_HDR + key_words(len) + (uint64_t)len * (META_WIDE(m) ? 2u : 1u) : 0;
 }
 
-// copy each vertex's slot into the packed pool at its offset, in one pass that
-// also sets the presence bitmap (bit = position in the dense level-h layout)
-__global__ void __launch_bounds__(WAVE) k_pack(int64_t n, int W, const uint32_t *meta, const uint64_t *off_incl,
-                                               const uint16_t *slot_key, const uint64_t *slot_lo,
-                                               const uint64_t *slot_hi, const u128 *Nv, uint64_t *pool, uint64_t *loc,
-                                               const int16_t *key_xidx, int nkeys, const uint8_t *colors,
-                                               uint64_t *bm, int BW)
+// Packing: each vertex's slot is copied into the pool at its offset, in one
+// pass that also sets the presence bitmap (bit = position in the dense level-h
+// layout). Records are short, so 16 lanes take one vertex and a wave packs four
+// at a time. Returns the vertex's (stored entries, 128-bit flag) in lane 0 of its
+// group.
+struct PackView {
+    int64_t n;
+    int W, BW, nkeys;
+    const uint32_t *meta;
+    const uint64_t *off_incl;        // inclusive running sums of record sizes
+    const uint16_t *skey;
+    const uint64_t *slo, *shi;
+    const u128 *N;
+    uint64_t *pool, *loc, *bm;
+    const int16_t *key_xidx;
+    const uint8_t *colors;
+};
+
+__device__ inline uint64_t rec_words(uint32_t m)
 {
-    __shared__ unsigned long long bits[8];   // BW <= ceil(420 / 64)
-    const int lane = threadIdx.x;
-    for (int64_t v = blockIdx.x; v < n; v += gridDim.x) {
-        const uint32_t m = meta[v], len = META_LEN(m);
-        if (lane < BW) bits[lane] = 0;
-        __syncthreads();
+    const uint32_t len = META_LEN(m);
+    return len ? (uint64_t)REC_HDR + key_words(len) + (uint64_t)len * (META_WIDE(m) ? 2u : 1u) : 0;
+}
+
+__device__ inline void pack_four(const PackView &P, int64_t v0, unsigned long long (*bits)[8], uint64_t &nlen,
+                                 uint64_t &nwide)
+{
+    const int lane = threadIdx.x, g = lane >> 4, l = lane & 15;
+    const int64_t v = v0 + g;
+    const bool act = v < P.n;
+    const uint32_t m = act ? P.meta[v] : 0u, len = META_LEN(m);
+    if (act && l == 0) { nlen += len; nwide += META_WIDE(m); }
+    if (l < P.BW) bits[g][l] = 0;
+    __syncthreads();
+    if (act) {
         const uint32_t kw = key_words(len);
-        const uint32_t words = len ? REC_HDR + kw + len * (META_WIDE(m) ? 2u : 1u) : 0;
-        const uint64_t start = off_incl[v] - words;
-        if (lane == 0) loc[v] = make_loc(start, len, META_WIDE(m));
+        const uint64_t start = P.off_incl[v] - rec_words(m);
+        if (l == 0) P.loc[v] = make_loc(start, len, META_WIDE(m));
         if (len) {
-            uint64_t *rec = pool + start;
-            if (lane == 0) { rec[0] = lo64(Nv[v]); rec[1] = hi64(Nv[v]); }
+            uint64_t *rec = P.pool + start;
+            if (l == 0) { rec[0] = lo64(P.N[v]); rec[1] = hi64(P.N[v]); }
             rec += REC_HDR;
             uint16_t *keys = (uint16_t *)rec;
-            const int16_t *xi = key_xidx + (size_t)colors[v] * nkeys;
-            const size_t base = (size_t)v * W;
-            for (uint32_t e = lane; e < kw * 4; e += WAVE) {
+            const int16_t *xi = P.key_xidx + (size_t)P.colors[v] * P.nkeys;
+            const size_t base = (size_t)v * P.W;
+            for (uint32_t e = l; e < kw * 4; e += 16) {
                 uint16_t key = 0;
                 if (e < len) {
-                    key = slot_key[base + e];
+                    key = P.skey[base + e];
                     const int li = xi[key];
-                    if (li >= 0) atomicOr(&bits[li >> 6], 1ull << (li & 63));
+                    if (li >= 0) atomicOr(&bits[g][li >> 6], 1ull << (li & 63));
                 }
                 keys[e] = key;
             }
-            for (uint32_t e = lane; e < len; e += WAVE) rec[kw + e] = slot_lo[base + e];
+            for (uint32_t e = l; e < len; e += 16) rec[kw + e] = P.slo[base + e];
             if (META_WIDE(m))
-                for (uint32_t e = lane; e < len; e += WAVE) rec[kw + len + e] = slot_hi[base + e];
+                for (uint32_t e = l; e < len; e += 16) rec[kw + len + e] = P.shi[base + e];
         }
-        __syncthreads();
-        if (lane < BW) bm[(size_t)v * BW + lane] = bits[lane];
-        __syncthreads();
     }
+    __syncthreads();
+    if (act && l < P.BW) P.bm[(size_t)v * P.BW + l] = bits[g][l];
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(WAVE) k_pack(PackView P)
+{
+    __shared__ unsigned long long bits[4][8];   // BW <= ceil(420 / 64)
+    uint64_t nlen = 0, nwide = 0;
+    for (int64_t v0 = (int64_t)blockIdx.x * 4; v0 < P.n; v0 += (int64_t)gridDim.x * 4)
+        pack_four(P, v0, bits, nlen, nwide);
 }
 
 // ---------------------------------------------------------------------------
@@ -794,12 +822,6 @@ struct PackJobDev {
     uint64_t *total;                 // out: pool words
 };
 
-__device__ inline uint64_t rec_words(uint32_t m)
-{
-    const uint32_t len = META_LEN(m);
-    return len ? (uint64_t)REC_HDR + key_words(len) + (uint64_t)len * (META_WIDE(m) ? 2u : 1u) : 0;
-}
-
 __global__ void __launch_bounds__(SCAN_T) k_mpack_sums(const PackJobDev *Js)
 {
     __shared__ uint64_t sh[SCAN_T / WAVE];
@@ -858,49 +880,21 @@ __global__ void __launch_bounds__(SCAN_T) k_mpack_apply(const PackJobDev *Js)
     }
 }
 
-// the records of every job (one wave per vertex, as k_pack), plus the level's
-// stored entries and 128-bit vertices
+// the records of every job (as k_pack), plus the level's stored entries and
+// 128-bit vertices
 __global__ void __launch_bounds__(WAVE) k_mpack(const PackJobDev *Js)
 {
-    __shared__ unsigned long long bits[8];   // BW <= ceil(420 / 64)
+    __shared__ unsigned long long bits[4][8];
     const PackJobDev J = Js[blockIdx.y];
-    const int lane = threadIdx.x;
+    PackView P{J.n, J.W, J.BW, J.nkeys, J.meta, J.words, J.skey, J.slo, J.shi, J.N, J.pool, J.loc, J.bm,
+               J.key_xidx, J.colors};
     uint64_t nlen = 0, nwide = 0;
-    for (int64_t v = blockIdx.x; v < J.n; v += gridDim.x) {
-        const uint32_t m = J.meta[v], len = META_LEN(m);
-        nlen += len;
-        nwide += META_WIDE(m);
-        if (lane < J.BW) bits[lane] = 0;
-        __syncthreads();
-        const uint32_t kw = key_words(len);
-        const uint64_t start = J.words[v] - rec_words(m);
-        if (lane == 0) J.loc[v] = make_loc(start, len, META_WIDE(m));
-        if (len) {
-            uint64_t *rec = J.pool + start;
-            if (lane == 0) { rec[0] = lo64(J.N[v]); rec[1] = hi64(J.N[v]); }
-            rec += REC_HDR;
-            uint16_t *keys = (uint16_t *)rec;
-            const int16_t *xi = J.key_xidx + (size_t)J.colors[v] * J.nkeys;
-            const size_t base = (size_t)v * J.W;
-            for (uint32_t e = lane; e < kw * 4; e += WAVE) {
-                uint16_t key = 0;
-                if (e < len) {
-                    key = J.skey[base + e];
-                    const int li = xi[key];
-                    if (li >= 0) atomicOr(&bits[li >> 6], 1ull << (li & 63));
-                }
-                keys[e] = key;
-            }
-            for (uint32_t e = lane; e < len; e += WAVE) rec[kw + e] = J.slo[base + e];
-            if (META_WIDE(m))
-                for (uint32_t e = lane; e < len; e += WAVE) rec[kw + len + e] = J.shi[base + e];
-        }
-        __syncthreads();
-        if (lane < J.BW) J.bm[(size_t)v * J.BW + lane] = bits[lane];
-        __syncthreads();
-    }
-    if (lane == 0 && nlen) atomicAdd(&J.stats[0], (unsigned long long)nlen);
-    if (lane == 0 && nwide) atomicAdd(&J.stats[1], (unsigned long long)nwide);
+    for (int64_t v0 = (int64_t)blockIdx.x * 4; v0 < J.n; v0 += (int64_t)gridDim.x * 4)
+        pack_four(P, v0, bits, nlen, nwide);
+    nlen = wave_sum64(nlen);
+    nwide = wave_sum64(nwide);
+    if (threadIdx.x == 0 && nlen) atomicAdd(&J.stats[0], (unsigned long long)nlen);
+    if (threadIdx.x == 0 && nwide) atomicAdd(&J.stats[1], (unsigned long long)nwide);
 }
 
 template <typename T>
@@ -1118,9 +1112,11 @@ static scc_status build_levels(scc_table *T)
         Lv.BW = (HL.W[h] + 63) / 64;
         Lv.bm = (uint64_t *)T->alloc((size_t)n * Lv.BW * 8 + 8);
         if (!Lv.bm) return set_error(SCC_ENOMEM, "level %d bitmaps", h);
-        if (n) hipLaunchKernelGGL(k_pack, dim3(grid_of(n)), dim3(WAVE), 0, st, n, HL.W[h], meta, words,
-                                  slot_key, slot_lo, slot_hi, Nsc, Lv.pool, Lv.loc, T->key_xidx, HL.nkeys, T->colors,
-                                  Lv.bm, Lv.BW);
+        if (n) {
+            PackView P{n, HL.W[h], Lv.BW, HL.nkeys, meta, words, slot_key, slot_lo, slot_hi, Nsc, Lv.pool, Lv.loc,
+                       Lv.bm, T->key_xidx, T->colors};
+            hipLaunchKernelGGL(k_pack, dim3(grid_of((n + 3) / 4)), dim3(WAVE), 0, st, P);
+        }
         HIP_TRY(hipEventRecord(ev[h][1], st));
         if (n) hipLaunchKernelGGL(k_meta_sum, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 1024)), dim3(256), 0, st,
                                   n, meta, (unsigned long long *)T->dsum + 2 * h);
@@ -1412,7 +1408,7 @@ __device__ inline long long wave_uniform64(unsigned long long x)
 // its value made scalar. A lane-0-only region on each side of the back edge
 // could be merged across it by the compiler, giving the loop a divergent latch
 // at which lanes drift apart.
-__global__ void __launch_bounds__(WAVE) k_batch(BatchArgs B)
+__device__ __attribute__((always_inline)) inline void batch_worker(BatchArgs B)
 {
     extern __shared__ uint64_t sm[];
     __shared__ unsigned cnt1[SCC_KMAX];
@@ -1469,6 +1465,14 @@ __global__ void __launch_bounds__(WAVE) k_batch(BatchArgs B)
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");   // this item's writes before its completion count
         atomicAdd(&B.counters[I.done], (int)one);
     }
+}
+
+// Two register budgets of the same worker: the compiler's own (about five waves
+// per SIMD) and eight waves per SIMD (a few spills); the schedule autotuner times both.
+__global__ void __launch_bounds__(WAVE) k_batch(BatchArgs B) { batch_worker(B); }
+__global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(8, 8))) k_batch_w8(BatchArgs B)
+{
+    batch_worker(B);
 }
 
 // vertex bounds of the cost-split items: item q of s covers the vertices whose
@@ -1578,7 +1582,8 @@ struct TuneKey {
     bool operator<(const TuneKey &o) const { return sig < o.sig; }
 };
 std::mutex g_tune_mu;
-std::map<TuneKey, std::pair<int, int>> g_tune;
+struct TuneVal { int tile, hub, waves; };
+std::map<TuneKey, TuneVal> g_tune;
 
 }  // namespace
 
@@ -1598,10 +1603,11 @@ static scc_table *new_table(const scc_csr *g, const uint8_t *colors, int k, cons
 
 // One persistent launch over all instances, for one (tile, hub) choice.
 // Assumes the per-instance storage exists; fills slots and neighbour sums.
-static scc_status batch_launch(std::vector<BatchInstHost> &H, int tile, int hub_degree, hipStream_t st,
+static scc_status batch_launch(std::vector<BatchInstHost> &H, int tile, int hub_degree, int waves, hipStream_t st,
                                DevMem &mem, float *ms_out, int64_t *nitems_out, int *grid_out,
                                std::vector<std::vector<int32_t>> &hv, std::vector<std::vector<int64_t>> &hr)
 {
+    const void *kern = waves == 8 ? (const void *)k_batch_w8 : (const void *)k_batch;
     const int ni = (int)H.size();
     int kmax = 0;
     for (auto &x : H) kmax = std::max(kmax, x.T->k);
@@ -1731,7 +1737,7 @@ static scc_status batch_launch(std::vector<BatchInstHost> &H, int tile, int hub_
     int dev = 0, ncu = 0, per_cu = 0;
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch, WAVE, lds));
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, WAVE, lds));
     if (per_cu < 1) return set_error(SCC_EUNSUPPORTED, "batched launch does not fit a CU (LDS %zu)", lds);
     const int grid = std::min<int64_t>((int64_t)ncu * per_cu, (int64_t)items.size());
     int wc_khz = 0;
@@ -1749,7 +1755,8 @@ static scc_status batch_launch(std::vector<BatchInstHost> &H, int tile, int hub_
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     HIP_TRY(hipEventRecord(e0, st));
-    hipLaunchKernelGGL(k_batch, dim3((unsigned)grid), dim3(WAVE), lds, st, BA);
+    if (waves == 8) hipLaunchKernelGGL(k_batch_w8, dim3((unsigned)grid), dim3(WAVE), lds, st, BA);
+    else hipLaunchKernelGGL(k_batch, dim3((unsigned)grid), dim3(WAVE), lds, st, BA);
     HIP_TRY(hipEventRecord(e1, st));
     HIP_TRY(hipEventSynchronize(e1));
     float ms = 0;
@@ -1834,29 +1841,35 @@ extern "C" scc_status scc_build_batch(const scc_instance *inst, int n_inst, cons
     TuneKey key;
     for (int i = 0; i < n_inst; i++) { key.sig.push_back(inst[i].g.n); key.sig.push_back(inst[i].g.nnz); key.sig.push_back(inst[i].k); }
     int tile = bo.tile > 0 ? bo.tile : 256, hubd = bo.hub_degree > 0 ? bo.hub_degree : 1024;
+    int waves = bo.waves == 8 ? 8 : 0;
     bool tuned = false;
     scc_batch_report R{};
-    if (bo.tile <= 0 && bo.hub_degree <= 0) {
+    if (bo.tile <= 0 && bo.hub_degree <= 0 && bo.waves <= 0) {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune.find(key);
-        if (it != g_tune.end()) { tile = it->second.first; hubd = it->second.second; tuned = true; }
+        if (it != g_tune.end()) { tile = it->second.tile; hubd = it->second.hub; waves = it->second.waves; tuned = true; }
     }
     if (bo.autotune && !tuned) {
-        const int tiles[] = {128, 256, 512, 1024};
-        const int hubs[] = {512, 2048, 8192};
+        const int tiles[] = {128, 256, 512};
+        const int hubs[] = {512, 2048};
+        const int wv[] = {0, 8};
         float best = 1e30f;
-        for (int t : tiles)
-            for (int hd : hubs) {
-                float ms = 0;
-                std::vector<std::vector<int32_t>> hv;
-                std::vector<std::vector<int64_t>> hr;
-                scc_status s = batch_launch(H, t, hd, st, mem, &ms, nullptr, nullptr, hv, hr);
-                if (s) return fail(s);
-                if (R.nprobe < 16) { R.probe_tile[R.nprobe] = t; R.probe_hub[R.nprobe] = hd; R.probe_ms[R.nprobe] = ms; R.nprobe++; }
-                if (ms < best) { best = ms; tile = t; hubd = hd; }
-            }
+        for (int w : wv)
+            for (int t : tiles)
+                for (int hd : hubs) {
+                    float ms = 0;
+                    std::vector<std::vector<int32_t>> hv;
+                    std::vector<std::vector<int64_t>> hr;
+                    scc_status s = batch_launch(H, t, hd, w, st, mem, &ms, nullptr, nullptr, hv, hr);
+                    if (s) return fail(s);
+                    if (R.nprobe < 16) {
+                        R.probe_tile[R.nprobe] = t; R.probe_hub[R.nprobe] = hd; R.probe_waves[R.nprobe] = w;
+                        R.probe_ms[R.nprobe] = ms; R.nprobe++;
+                    }
+                    if (ms < best) { best = ms; tile = t; hubd = hd; waves = w; }
+                }
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_tune[key] = {tile, hubd};
+        g_tune[key] = {tile, hubd, waves};
         tuned = true;
     }
     auto t_launch = std::chrono::steady_clock::now();
@@ -1865,7 +1878,7 @@ extern "C" scc_status scc_build_batch(const scc_instance *inst, int n_inst, cons
     int grid = 0;
     std::vector<std::vector<int32_t>> hub_v;
     std::vector<std::vector<int64_t>> hub_r;
-    scc_status s = batch_launch(H, tile, hubd, st, mem, &ms, &nitems, &grid, hub_v, hub_r);
+    scc_status s = batch_launch(H, tile, hubd, waves, st, mem, &ms, &nitems, &grid, hub_v, hub_r);
     if (s) return fail(s);
     auto t_pack = std::chrono::steady_clock::now();
     // standard tables, every (instance, level) at once: record sizes and running
@@ -1942,7 +1955,8 @@ extern "C" scc_status scc_build_batch(const scc_instance *inst, int n_inst, cons
     }
     HIP_TRY(hipMemcpyAsync(djobs, jobs.data(), (size_t)nj * sizeof(PackJobDev), hipMemcpyHostToDevice, st));
     if (maxn)
-        hipLaunchKernelGGL(k_mpack, dim3((unsigned)std::min<int64_t>(maxn, 2048), (unsigned)nj), dim3(WAVE), 0, st, djobs);
+        hipLaunchKernelGGL(k_mpack, dim3((unsigned)std::min<int64_t>((maxn + 3) / 4, 2048), (unsigned)nj), dim3(WAVE), 0,
+                           st, djobs);
     for (int i = 0; i < n_inst; i++)
         for (int h = 2; h <= H[i].T->k; h++) {   // stream-ordered releases
             scc_table *T = H[i].T;
@@ -1969,7 +1983,8 @@ extern "C" scc_status scc_build_batch(const scc_instance *inst, int n_inst, cons
     auto t_end = std::chrono::steady_clock::now();
     for (int i = 0; i < n_inst; i++) out[i] = H[i].T;
     if (rep) {
-        R.tile = tile; R.hub_degree = hubd; R.items = nitems; R.grid = grid; R.launch_ms = ms; R.tuned = tuned ? 1 : 0;
+        R.tile = tile; R.hub_degree = hubd; R.waves = waves; R.items = nitems; R.grid = grid; R.launch_ms = ms;
+        R.tuned = tuned ? 1 : 0;
         R.pack_ms = std::chrono::duration<double, std::milli>(t_end - t_pack).count();
         R.total_ms = std::chrono::duration<double, std::milli>(t_end - t_launch).count();
         R.setup_ms = std::chrono::duration<double, std::milli>(t_launch - t_start).count();

@@ -42,12 +42,13 @@ def plain(S, g, colors, k, rooting):
 
 
 @pytest.mark.parametrize("rooting", [0, 1])
-@pytest.mark.parametrize("tile,hub", [(0, 0), (7, 16), (1000, 40)])
-def test_batch_equals_plain(rooting, tile, hub):
+@pytest.mark.parametrize("tile,hub,waves", [(0, 0, 0), (7, 16, 8), (1000, 40, 0), (64, 1024, 8)])
+def test_batch_equals_plain(rooting, tile, hub, waves):
     S = scc()
     inst = instances()
     dev = [(S.DeviceGraph.from_graph(g), c, k) for g, c, k in inst]
-    tabs, rep = S.build_batch(dev, rooting=rooting, tile=tile, hub_degree=hub)
+    tabs, rep = S.build_batch(dev, rooting=rooting, tile=tile, hub_degree=hub, waves=waves)
+    assert rep["waves"] == waves
     assert rep["items"] > 0 and rep["grid"] > 0
     for (g, c, k), bt in zip(inst, tabs):
         pt = plain(S, g, c, k, rooting)
