@@ -11,6 +11,9 @@
 
 namespace {
 
+// the hub running sums keep one value per HUB_BLOCK neighbours (one wave's scan)
+constexpr int64_t HUB_BLOCK = WAVE;
+
 
 __device__ inline int key_level(const DevLut &L, uint32_t key)
 {
@@ -188,17 +191,30 @@ __device__ inline int sample_one(const SampleArgs &A, int64_t r, SampleLds &W)
         u128 wu = 0;
         const int hub = A.hub_index ? A.hub_index[x] : -1;
         if (hub >= 0) {
-            // running sums over x's neighbours, precomputed per (hub, level, entry)
-            const int64_t d = rb - ra;
+            // running sums over x's neighbours at the end of every block of HUB_BLOCK
+            // neighbours, precomputed per (hub, level, entry): search the block, then
+            // scan its neighbours from the running sum before it
+            const int64_t d = rb - ra, nb = (d + HUB_BLOCK - 1) / HUB_BLOCK;
             const int64_t base = A.hub_poff[(size_t)hub * (SCC_KMAX + 1) + hpp];
-            const uint64_t *plo = A.hub_pre + base + (size_t)Sidx * d;
+            const uint64_t *plo = A.hub_pre + base + (size_t)Sidx * nb;
             const bool pw = hi64(A.M[hpp][x]) != 0;
-            const uint64_t *phi = A.hub_pre + base + (size_t)L.WS[hpp] * d + (size_t)Sidx * d;
+            const uint64_t *phi = A.hub_pre + base + (size_t)L.WS[hpp] * nb + (size_t)Sidx * nb;
             auto P = [&](int64_t j) { return mk128(plo[j], pw ? phi[j] : 0); };
-            const int64_t j = wave_search(d, Z, P);
-            if (j >= 0) {
-                u = A.g.col_idx[ra + j];
-                wu = P(j) - (j > 0 ? P(j - 1) : (u128)0);
+            const int64_t b = wave_search(nb, Z, P);
+            if (b >= 0) {
+                const int64_t e = ra + b * HUB_BLOCK + lane;
+                u128 c = 0;
+                int32_t uu = -1;
+                if (e < rb) {
+                    uu = A.g.col_idx[e];
+                    c = own_count(A, hpp, uu, kpp);
+                }
+                const u128 incl = (b > 0 ? P(b - 1) : (u128)0) + wave_incl_scan128(c);
+                const int w2 = first_exceeding(incl, Z);
+                if (w2 >= 0) {
+                    u = __shfl(uu, w2, WAVE);
+                    wu = shfl128(c, w2);
+                }
             }
         } else {
             // CSR order, 4 x 64 neighbours per round: every lane issues the loads of
@@ -377,8 +393,9 @@ __global__ void __launch_bounds__(256) k_hubpre_chunk(HubPreArgs A)
     const int64_t ra = A.hub_rows[2 * q], rb = A.hub_rows[2 * q + 1], d = rb - ra;
     const int64_t e0 = A.chunk_e[c], e1 = min(rb, e0 + (int64_t)A.chunk);
     const bool pw = hi64(A.M[hpp][x]) != 0;
+    const int64_t nb = (d + HUB_BLOCK - 1) / HUB_BLOCK;
     uint64_t *plo = A.pre + A.poff[(size_t)q * (SCC_KMAX + 1) + hpp];
-    uint64_t *phi = plo + (size_t)WS * d;
+    uint64_t *phi = plo + (size_t)WS * nb;
     for (int t = threadIdx.x; t < WS; t += blockDim.x) {
         const int rank = t / L.bk1[hpp], dc = t - rank * L.bk1[hpp];
         const uint32_t C = expand_in(L.mask_s[hpp][dc], cx);
@@ -399,9 +416,9 @@ __global__ void __launch_bounds__(256) k_hubpre_chunk(HubPreArgs A)
             const u128 val = u[r] >= 0 ? nbr_count(A, hpp, nr[r], key) : (u128)0;
             const u128 inc = block256_incl_scan(val, ws) + run;
             const int64_t j = e0 + r * 256 + threadIdx.x - ra;
-            if (u[r] >= 0) {
-                plo[(size_t)sidx * d + j] = lo64(inc);
-                if (pw) phi[(size_t)sidx * d + j] = hi64(inc);
+            if (u[r] >= 0 && ((j % HUB_BLOCK) == HUB_BLOCK - 1 || j == d - 1)) {   // end of a block
+                plo[(size_t)sidx * nb + j / HUB_BLOCK] = lo64(inc);
+                if (pw) phi[(size_t)sidx * nb + j / HUB_BLOCK] = hi64(inc);
             }
             if (threadIdx.x == blockDim.x - 1) carry = inc;
             __syncthreads();
@@ -428,23 +445,25 @@ __global__ void __launch_bounds__(256) k_hubpre_fix(HubPreArgs A)
     const int64_t ra = A.hub_rows[2 * q], rb = A.hub_rows[2 * q + 1], d = rb - ra;
     const int64_t e0 = A.chunk_e[c], e1 = min(rb, e0 + (int64_t)A.chunk);
     const bool pw = hi64(A.M[hpp][x]) != 0;
+    const int64_t nb = (d + HUB_BLOCK - 1) / HUB_BLOCK;
     uint64_t *plo = A.pre + A.poff[(size_t)q * (SCC_KMAX + 1) + hpp];
-    uint64_t *phi = plo + (size_t)WS * d;
+    uint64_t *phi = plo + (size_t)WS * nb;
     for (int t = threadIdx.x; t < WS; t += blockDim.x) {
         u128 o = 0;
         for (int cc = first; cc < c; cc++) o += A.part[(size_t)cc * A.part_stride + L.soff[hpp] + t];
         add[t] = o;
     }
     __syncthreads();
-    const int64_t len = e1 - e0;
+    // the chunk's blocks (chunks start on block boundaries)
+    const int64_t b0 = (e0 - ra) / HUB_BLOCK, b1 = (e1 - ra + HUB_BLOCK - 1) / HUB_BLOCK, len = b1 - b0;
     for (int64_t i = threadIdx.x; i < (int64_t)WS * len; i += blockDim.x) {
         const int sidx = (int)(i / len);
-        const int64_t j = e0 - ra + (i - (int64_t)sidx * len);
+        const int64_t j = b0 + (i - (int64_t)sidx * len);
         const u128 o = add[sidx];
-        const u128 cur = mk128(plo[(size_t)sidx * d + j], pw ? phi[(size_t)sidx * d + j] : 0);
+        const u128 cur = mk128(plo[(size_t)sidx * nb + j], pw ? phi[(size_t)sidx * nb + j] : 0);
         const u128 nv = cur + o;
-        plo[(size_t)sidx * d + j] = lo64(nv);
-        if (pw) phi[(size_t)sidx * d + j] = hi64(nv);
+        plo[(size_t)sidx * nb + j] = lo64(nv);
+        if (pw) phi[(size_t)sidx * nb + j] = hi64(nv);
     }
 }
 
@@ -549,7 +568,7 @@ static scc_status ensure_hub_prefix(scc_table *T)
     const bool zero = T->rooting == SCC_ROOT_ZERO;
     auto block_words = [&](int i, int h) -> int64_t {
         if (zero && h == k - 1 && info[(size_t)i * (SCC_KMAX + 2)] != 0) return 0;   // never a root there
-        const int64_t w = (int64_t)HL.WS[h] * deg(i);
+        const int64_t w = (int64_t)HL.WS[h] * ((deg(i) + HUB_BLOCK - 1) / HUB_BLOCK);
         return info[(size_t)i * (SCC_KMAX + 2) + h] ? 2 * w : w;
     };
     const int64_t budget_words = T->hub_prefix_budget / 8;
