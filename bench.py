@@ -228,16 +228,20 @@ def drive(srv, trace, rate, sessions, window):
                 rid = srv.submit(r["graph"], r["n"], session=sessions[r["graph"]])
             else:
                 rid = srv.submit(r["graph"], r["n"], seed=r["seed"], stream_id=i, classify=True)
-            q.put(rid)
+            q.put((rid, "ags" if r["ags"] else "uniform"))
         q.put(None)
+
+    lat = {"uniform": [], "ags": []}
 
     def waiter():
         done = 0
         while True:
-            rid = q.get()
-            if rid is None:
+            item = q.get()
+            if item is None:
                 break
-            srv.wait(rid, timeout=900.0, copy=False)
+            rid, kind = item
+            r = srv.wait(rid, timeout=900.0, copy=False)
+            lat[kind].append(r["t_done"] - r["t_submit"])
             srv.release(rid)
             done += 1
             if done % 250 == 0:
@@ -250,6 +254,11 @@ def drive(srv, trace, rate, sessions, window):
         t.join()
     st = srv.stats()
     st["wall_s"] = time.perf_counter() - t0
+    for kind, xs in lat.items():
+        xs = sorted(xs)
+        if xs:
+            st[f"{kind}_p50_ms"] = 1e3 * xs[max(0, int(0.5 * len(xs) + 0.5) - 1)]
+            st[f"{kind}_p99_ms"] = 1e3 * xs[max(0, min(len(xs), int(0.99 * len(xs) + 0.5)) - 1)]
     st["samples_per_s"] = st["samples"] / st["span_s"] if st["span_s"] > 0 else 0.0
     return st
 
@@ -274,8 +283,8 @@ def run_serving(a):
     opts = dict(hbm_budget=24 << 30, step_samples=1 << 16, chunk=4096, max_active=512)
     cbar = 1000
 
-    def server(fifo):
-        srv = scc.Server(tabs, fifo=fifo, **opts)
+    def server(fifo, ags_weight=1.0):
+        srv = scc.Server(tabs, fifo=fifo, ags_weight=ags_weight, **opts)
         sessions = [srv.ags_open(t, cbar=cbar, seed=900 + t, stream_id=t) for t in range(len(tabs))]
         return srv, sessions
 
@@ -293,16 +302,19 @@ def run_serving(a):
     print(f"# saturated: {burst['samples_per_s'] / 1e6:.1f} M samples/s = {sat_req:.1f} requests/s; "
           f"Poisson rate {rate:.1f}/s", file=sys.stderr, flush=True)
     res = {}
-    for name, fifo in (("continuous", False), ("fifo", True)):
-        srv, sess = server(fifo)
+    for name, fifo, aw in (("continuous", False, 1.0), ("continuous_ags4", False, 4.0),
+                           ("continuous_ags16", False, 16.0), ("fifo", True, 1.0)):
+        srv, sess = server(fifo, aw)
         res[name] = drive(srv, trace, rate, sess, a.window)
         srv.close()
         r = res[name]
         print(f"# {name}: {r['completed']} requests, {r['samples_per_s'] / 1e6:.1f} M samples/s, "
-              f"p50 {r['p50_ms']:.1f} ms, p99 {r['p99_ms']:.1f} ms", file=sys.stderr, flush=True)
+              f"p50 {r['p50_ms']:.1f} ms, p99 {r['p99_ms']:.1f} ms; uniform p50/p99 "
+              f"{r.get('uniform_p50_ms', 0):.1f}/{r.get('uniform_p99_ms', 0):.1f} ms, AGS rounds p50/p99 "
+              f"{r.get('ags_p50_ms', 0):.1f}/{r.get('ags_p99_ms', 0):.1f} ms", file=sys.stderr, flush=True)
     c, f = res["continuous"], res["fifo"]
     keep = ("completed", "samples", "steps", "span_s", "samples_per_s", "p50_ms", "p99_ms", "mean_ms", "max_ms",
-            "arena_peak")
+            "arena_peak", "uniform_p50_ms", "uniform_p99_ms", "ags_p50_ms", "ags_p99_ms")
     out = {
         "metric": "DP table build s & colorful-treelet samples/sec, batched/served vs plain",
         "value": c["samples_per_s"], "unit": "samples/s served (continuous batching, Poisson arrivals at 0.7x "
@@ -317,6 +329,8 @@ def run_serving(a):
         "saturated_samples_per_s": sat["continuous"], "saturated_samples_per_s_fifo": sat["fifo"],
         "saturated_throughput_vs_fifo": sat["continuous"] / sat["fifo"] if sat["fifo"] > 0 else None,
         "continuous": {k: c[k] for k in keep}, "fifo": {k: f[k] for k in keep},
+        "continuous_ags_weight_4": {k: res["continuous_ags4"][k] for k in keep},
+        "continuous_ags_weight_16": {k: res["continuous_ags16"][k] for k in keep},
         "p99_speedup_vs_fifo": f["p99_ms"] / c["p99_ms"] if c["p99_ms"] > 0 else None,
         "p50_speedup_vs_fifo": f["p50_ms"] / c["p50_ms"] if c["p50_ms"] > 0 else None,
         "throughput_vs_fifo": c["samples_per_s"] / f["samples_per_s"] if f["samples_per_s"] > 0 else None,

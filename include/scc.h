@@ -312,6 +312,8 @@ typedef struct {
     int grid;                /* sampler workgroups (one wave each) per step (0 = 8192) */
     int fifo;                /* nonzero: one whole request per step, in submission order
                                 (the plain first-in first-out server, for comparison) */
+    double ags_weight;       /* share of a step an AGS round gets relative to a sample
+                                request (a session's later rounds wait for it); 0 = 1 */
     void *stream;            /* hipStream_t of the server's work (NULL: its own stream) */
     const scc_allocator *alloc; /* for the budget and the server's buffers (NULL: hipMalloc) */
 } scc_server_opts;

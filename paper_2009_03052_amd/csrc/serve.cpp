@@ -211,7 +211,8 @@ void scc_server::activate_rounds_locked()
 }
 
 // chunks of the next step: one per active request with unassigned rows, round
-// robin, each up to max(chunk, step / active); FIFO mode: the oldest request, whole
+// robin, each up to max(chunk, its weighted share of the step); FIFO mode: the
+// oldest request, whole
 bool scc_server::build_step_locked(int b)
 {
     StepBuf &B = sb[b];
@@ -228,11 +229,17 @@ bool scc_server::build_step_locked(int b)
         const int64_t id = *std::min_element(cand.begin(), cand.end());
         cand.assign(1, id);
     }
-    const int64_t quota = o.fifo ? INT64_MAX : std::max<int64_t>(o.chunk, o.step_samples / (int64_t)cand.size());
+    // weighted shares of the step: an AGS round (which holds up its session's later
+    // rounds) weighs ags_weight, a sample request 1; every share is at least `chunk`
+    double wsum = 0;
+    for (int64_t id : cand) wsum += reqs[id].q.kind == SCC_REQ_AGS_ROUND ? o.ags_weight : 1.0;
     const size_t nc = cand.size();
     for (size_t q = 0; q < nc; q++) {
         const int64_t id = cand[(rr + q) % nc];
         Request &r = reqs[id];
+        const double w = r.q.kind == SCC_REQ_AGS_ROUND ? o.ags_weight : 1.0;
+        const int64_t quota = o.fifo ? INT64_MAX
+                                     : std::max<int64_t>(o.chunk, (int64_t)((double)o.step_samples * w / wsum));
         const int64_t c = std::min(quota, r.q.n - r.assigned);
         if (r.assigned == 0) r.t_start = now_s(t0);
         const int a = B.nch;
@@ -391,6 +398,7 @@ extern "C" scc_status scc_server_create(const scc_server_opts *opts, scc_server 
     if (S->o.step_samples <= 0) S->o.step_samples = (int64_t)1 << 18;
     if (S->o.chunk <= 0) S->o.chunk = 8192;
     if (S->o.grid <= 0) S->o.grid = 8192;
+    if (!(S->o.ags_weight > 0)) S->o.ags_weight = 1.0;
     S->max_active = S->o.max_active;
     S->mem.alloc = S->o.alloc;
     auto fail = [&](scc_status s) {
