@@ -25,6 +25,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 ROOT_ZERO = 0
 ROOT_ALL = 1
+ROOT_BALANCED = 2   # round skipping: level k-1 skipped, level k at designated balanced rootings
 
 OK, EINVAL, ENOMEM, EOVERFLOW, EEMPTY = 0, -1, -2, -3, -5
 
@@ -82,6 +83,10 @@ def lib():
             "orc_spanning_trees": (i64, [u32, C.c_int]),
             "orc_spanning_trees_by_shape": (C.c_int, [u32, C.c_int, P]),
             "orc_ags": (C.c_int, [P, i64, i64, i64, u64, u64, P, P, P, P, P]),
+            "orc_balanced_rank": (C.c_int, [C.c_int, C.c_int]),
+            "orc_balanced_orbit": (C.c_int, [C.c_int, C.c_int]),
+            "orc_star_class": (C.c_int, [C.c_int]),
+            "orc_star_count": (C.c_int, [P, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -133,6 +138,20 @@ def num_unrooted(h: int) -> int:
 
 def shape_unrooted(h: int, r: int) -> int:
     return lib().orc_shape_unrooted(h, r)
+
+
+def balanced_rank(h: int, j: int) -> int:
+    """Designated (balanced) rooted rank of unrooted h-shape j, -1 for the star."""
+    return lib().orc_balanced_rank(h, j)
+
+
+def balanced_orbit(h: int, j: int) -> int:
+    """Nodes of a copy of unrooted shape j at which the designated rooting occurs."""
+    return lib().orc_balanced_orbit(h, j)
+
+
+def star_class(h: int) -> int:
+    return lib().orc_star_class(h)
 
 
 def key(k: int, h: int, rank: int, mask: int) -> int:
@@ -204,6 +223,12 @@ class Table:
         out = np.zeros(2, np.uint64)
         _check(lib().orc_occ(self._h, v, key, _p(out)))
         return _u128(out[0], out[1])
+
+    def star_count(self) -> int:
+        """Uncoloured k-stars of the graph: sum over v of binom(d_v, k-1)."""
+        out = np.zeros(2, np.uint64)
+        _check(lib().orc_star_count(self._h, _p(out)))
+        return int(out[0]) | (int(out[1]) << 64)
 
     def sample(self, n: int, seed: int, stream: int = 0, shape: int = -1, first_index: int = 0):
         """(verts int32[n, k], parent int8[n, k])."""

@@ -36,7 +36,7 @@
 typedef unsigned __int128 u128;
 
 enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ENOMEM = -2, ORC_EOVERFLOW = -3, ORC_EEMPTY = -5 };
-enum { ORC_ROOT_ZERO = 0, ORC_ROOT_ALL = 1 };
+enum { ORC_ROOT_ZERO = 0, ORC_ROOT_ALL = 1, ORC_ROOT_BALANCED = 2 };
 
 #define KMAX 8
 #define MAXSH 128  /* r_8 = 115 rooted shapes on 8 nodes */
@@ -205,6 +205,54 @@ static void build_shapes(void)
     }
     shapes_ready = 1;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Round skipping (Sec. 3.5, balanced treelet decomposition). A rooted shape  */
+/* is balanced when its canonical decomposition splits it into two trees of   */
+/* at least 2 and at most h-2 nodes. Every unrooted h-shape except the star   */
+/* has a balanced rooting (root at an end of an edge whose removal leaves two */
+/* trees of >= 2 nodes). The designated rooting of an unrooted shape is its   */
+/* smallest balanced rooted rank; its orbit is the number of nodes of a copy  */
+/* at which the rooting gives that rank, i.e. how often a copy is counted.   */
+/* ------------------------------------------------------------------------- */
+static int bal_rank[KMAX + 1][MAXSH];    /* per unrooted class, -1 for none */
+static int bal_orbit[KMAX + 1][MAXSH];
+static int star_class[KMAX + 1];
+static int bal_ready;
+
+static void build_balanced(void)
+{
+    if (bal_ready) return;
+    build_shapes();
+    for (int h = 1; h <= KMAX; h++) {
+        char star[SLEN] = {0};
+        for (int i = 0; i < h - 1; i++) strcat(star, "10");
+        star_class[h] = sh_unr[h][rank_of(h, star)];
+        for (int j = 0; j < unr_n[h]; j++) { bal_rank[h][j] = -1; bal_orbit[h][j] = 0; }
+        for (int r = 0; r < sh_n[h]; r++) {
+            if (h < 4) continue;
+            const int hpp = h - sh_hp[h][r];
+            if (hpp < 2 || hpp > h - 2) continue;
+            int *b = &bal_rank[h][sh_unr[h][r]];
+            if (*b < 0 || r < *b) *b = r;
+        }
+        for (int j = 0; j < unr_n[h]; j++) {
+            if (bal_rank[h][j] < 0) continue;
+            tree_t t;
+            parse_tree(sh_s[h][bal_rank[h][j]], &t);
+            for (int x = 0; x < t.nn; x++) {
+                char cs[SLEN];
+                canon_at(&t, x, -1, cs);
+                bal_orbit[h][j] += rank_of(h, cs) == bal_rank[h][j];
+            }
+        }
+    }
+    bal_ready = 1;
+}
+
+int orc_balanced_rank(int h, int j) { build_balanced(); return (h >= 1 && h <= KMAX && j >= 0 && j < unr_n[h]) ? bal_rank[h][j] : -1; }
+int orc_balanced_orbit(int h, int j) { build_balanced(); return (h >= 1 && h <= KMAX && j >= 0 && j < unr_n[h]) ? bal_orbit[h][j] : 0; }
+int orc_star_class(int h) { build_balanced(); return (h >= 2 && h <= KMAX) ? star_class[h] : -1; }
 
 /* shape queries for tests */
 int orc_num_shapes(int h) { build_shapes(); return (h >= 1 && h <= KMAX) ? sh_n[h] : -1; }
@@ -398,7 +446,9 @@ int orc_build(int64_t n, const int64_t *row_ptr, const int32_t *col_idx,
 {
     *out = NULL;
     if (k < 2 || k > KMAX) { set_err("k must be in [2, 8]"); return ORC_EINVAL; }
-    if (rooting != ORC_ROOT_ZERO && rooting != ORC_ROOT_ALL) { set_err("bad rooting"); return ORC_EINVAL; }
+    if (rooting != ORC_ROOT_ZERO && rooting != ORC_ROOT_ALL && rooting != ORC_ROOT_BALANCED) { set_err("bad rooting"); return ORC_EINVAL; }
+    if (rooting == ORC_ROOT_BALANCED && k < 4) { set_err("round skipping needs k >= 4"); return ORC_EINVAL; }
+    build_balanced();
     int st = orc_check_csr(n, row_ptr, col_idx);
     if (st) return st;
     for (int64_t v = 0; v < n; v++)
@@ -438,8 +488,12 @@ int orc_build(int64_t n, const int64_t *row_ptr, const int32_t *col_idx,
     for (int h = 2; h <= k; h++) {
         recbuf rb = {0};
         T->off[h] = malloc((n + 1) * sizeof(int64_t));
+        /* round skipping: level k-1 is not built; level k holds only the designated
+           (balanced) rooting of every non-star shape, at every vertex */
+        const int skip = rooting == ORC_ROOT_BALANCED && h == k - 1;
         for (int64_t v = 0; v < n; v++) {
             T->off[h][v] = rb.len;
+            if (skip) continue;
             if (h == k && rooting == ORC_ROOT_ZERO && colors[v] != 0) continue;
             unsigned cv = 1u << colors[v];
             /* S(., v) for every size below h, and v's own X(., v) */
@@ -462,6 +516,7 @@ int orc_build(int64_t n, const int64_t *row_ptr, const int32_t *col_idx,
             /* Eq. (1) for every shape of size h and every colour set containing c_v */
             int b = binom(k, h);
             for (int r = 0; r < sh_n[h]; r++) {
+                if (h == k && rooting == ORC_ROOT_BALANCED && bal_rank[k][sh_unr[k][r]] != r) continue;
                 int hp = sh_hp[h][r], hpp = h - hp;
                 int a = sh_a[h][r], bb = sh_b[h][r], beta = sh_beta[h][r];
                 for (int ci = 0; ci < b; ci++) {
@@ -526,6 +581,16 @@ int orc_build(int64_t n, const int64_t *row_ptr, const int32_t *col_idx,
         tsum /= (u128)k;
         for (int j = 0; j < unr_n[k]; j++) T->tj[j] /= (u128)k;
     }
+    if (rooting == ORC_ROOT_BALANCED) {
+        /* every copy is counted once per node of its designated root's orbit */
+        tsum = 0;
+        for (int j = 0; j < unr_n[k]; j++) {
+            if (bal_rank[k][j] < 0) continue;
+            if (T->tj[j] % (u128)bal_orbit[k][j]) { set_err("internal: shape total not divisible by its orbit"); orc_table_free(T); return ORC_EINVAL; }
+            T->tj[j] /= (u128)bal_orbit[k][j];
+            tsum += T->tj[j];
+        }
+    }
     T->t = tsum;
     *out = T;
     return ORC_OK;
@@ -554,6 +619,24 @@ void orc_totals(const orc_table *T, uint64_t t[2], uint64_t *tj /* 2 * num_unroo
 void orc_eta(const orc_table *T, uint64_t *out /* 2n */)
 {
     for (int64_t v = 0; v < T->n; v++) { out[2 * v] = (uint64_t)T->eta[v]; out[2 * v + 1] = (uint64_t)(T->eta[v] >> 64); }
+}
+
+/* number of (uncoloured) k-stars of G: sum over v of binom(d_v, k-1) */
+static u128 binom128(int64_t n, int r)
+{
+    if (n < r) return 0;
+    u128 c = 1;
+    for (int i = 1; i <= r; i++) c = c * (u128)(n - r + i) / (u128)i;   /* exact at every step */
+    return c;
+}
+
+int orc_star_count(const orc_table *T, uint64_t out[2])
+{
+    u128 s = 0;
+    for (int64_t v = 0; v < T->n; v++)
+        if (add_ck(&s, binom128(T->row_ptr[v + 1] - T->row_ptr[v], T->k - 1))) { set_err("star count overflows"); return ORC_EOVERFLOW; }
+    out[0] = (uint64_t)s; out[1] = (uint64_t)(s >> 64);
+    return ORC_OK;
 }
 
 /* occ(T_C, v) by key, or occ(v) = eta_v with key = -1 (Sec. 3, database operations) */
@@ -645,16 +728,13 @@ static int admissible(const orc_table *T, int key, int shape)
 
 static int is_root(const orc_table *T, int64_t v)
 {
-    return T->rooting == ORC_ROOT_ALL || T->colors[v] == 0;
+    return T->rooting != ORC_ROOT_ZERO || T->colors[v] == 0;
 }
 
-int orc_sample(const orc_table *T, int shape, int64_t nsamp, uint64_t seed, uint64_t stream,
-               uint64_t first_index, int32_t *out_verts, int8_t *out_parent)
+/* running sums over vertices of the admissible level-k weight (shape -1: all) */
+static int make_pre(const orc_table *T, int shape, u128 **out)
 {
     const int k = T->k;
-    const keyspace *ks = &T->ks;
-    if (shape >= unr_n[k]) { set_err("shape id out of range"); return ORC_EINVAL; }
-    /* per-vertex admissible weight and its running sum */
     u128 *pre = malloc((T->n + 1) * sizeof(u128));
     if (!pre) return ORC_ENOMEM;
     pre[0] = 0;
@@ -666,78 +746,167 @@ int orc_sample(const orc_table *T, int shape, int64_t nsamp, uint64_t seed, uint
         pre[v + 1] = pre[v];
         if (add_ck(&pre[v + 1], w)) { free(pre); set_err("total overflows 128 bits"); return ORC_EOVERFLOW; }
     }
-    u128 tot = pre[T->n];
-    if (tot == 0) { free(pre); set_err("no colourful k-treelet to sample"); return ORC_EEMPTY; }
+    *out = pre;
+    return ORC_OK;
+}
 
+/* One sample of the given admissibility (running sums `pre`) into verts/par;
+   the root uses draw doff, the i-th decomposition draws doff + 1 + 2i (C'')
+   and doff + 2 + 2i (u). */
+static int sample_one(const orc_table *T, int shape, const u128 *pre, uint64_t seed, uint64_t stream, uint64_t idx,
+                      uint32_t doff, int32_t *verts, int8_t *par)
+{
+    const int k = T->k;
+    const keyspace *ks = &T->ks;
+    u128 X = uniform_below(pre[T->n], seed, stream, idx, doff);
+    int64_t lo = 0, hi = T->n;   /* first v with pre[v+1] > X */
+    while (lo < hi) { int64_t mid = (lo + hi) / 2; if (pre[mid + 1] > X) hi = mid; else lo = mid + 1; }
+    int64_t v = lo;
+    u128 res = X - pre[v], cum = 0;
+    int rkey = -1;
+    for (int64_t q = T->off[k][v]; q < T->off[k][v + 1]; q++) {
+        if (!admissible(T, T->key[k][q], shape)) continue;
+        cum += T->cnt[k][q];
+        if (cum > res) { rkey = T->key[k][q]; break; }
+    }
+    if (rkey < 0) { set_err("internal: root draw fell off the record"); return ORC_EINVAL; }
+
+    int nv = 0;
+    verts[nv] = (int32_t)v; par[nv] = -1; nv++;
+    struct { int key; int pos; } stack[2 * KMAX];
+    int sp = 0;
+    stack[sp].key = rkey; stack[sp].pos = 0; sp++;
+    int dec = 0;
+    while (sp > 0) {
+        sp--;
+        int key = stack[sp].key, pos = stack[sp].pos;
+        int h, r; unsigned C;
+        key_decode(ks, key, &h, &r, &C);
+        if (h == 1) continue;
+        int64_t x = verts[pos];
+        unsigned cv = 1u << T->colors[x];
+        int hp = sh_hp[h][r], hpp = h - hp, a = sh_a[h][r], b = sh_b[h][r];
+        u128 cT = lookup(T, h, x, key);
+        u128 Y = uniform_below((u128)sh_beta[h][r] * cT, seed, stream, idx, doff + 1 + 2 * dec);
+        /* stage 1: C'' subset of C \ {c_x}, |C''| = |T''|, ascending bitmask */
+        unsigned rest = C & ~cv, Cpp = 0;
+        u128 run = 0, Spick = 0;
+        int found = 0;
+        for (unsigned m = 0; m < (1u << k); m++) {
+            if ((m & ~rest) || popc(m) != hpp) continue;
+            int kpp = key_of(ks, hpp, b, m);
+            u128 Ssum = 0;
+            for (int64_t e = T->row_ptr[x]; e < T->row_ptr[x + 1]; e++)
+                Ssum += lookup(T, hpp, T->col_idx[e], kpp);
+            u128 w = lookup(T, hp, x, key_of(ks, hp, a, C ^ m)) * Ssum;
+            run += w;
+            if (run > Y) { Cpp = m; Spick = Ssum; found = 1; break; }
+        }
+        if (!found) { set_err("internal: colour-set draw fell off"); return ORC_EINVAL; }
+        /* stage 2: neighbour u with weight c(T''_{C''}, u) */
+        int kpp = key_of(ks, hpp, b, Cpp);
+        u128 Z = uniform_below(Spick, seed, stream, idx, doff + 2 + 2 * dec);
+        u128 run2 = 0;
+        int64_t u = -1;
+        for (int64_t e = T->row_ptr[x]; e < T->row_ptr[x + 1]; e++) {
+            run2 += lookup(T, hpp, T->col_idx[e], kpp);
+            if (run2 > Z) { u = T->col_idx[e]; break; }
+        }
+        if (u < 0) { set_err("internal: neighbour draw fell off"); return ORC_EINVAL; }
+        int upos = nv;
+        verts[nv] = (int32_t)u; par[nv] = (int8_t)pos; nv++;
+        dec++;
+        stack[sp].key = kpp; stack[sp].pos = upos; sp++;
+        stack[sp].key = key_of(ks, hp, a, C ^ Cpp); stack[sp].pos = pos; sp++;
+    }
+    return ORC_OK;
+}
+
+/* Uncoloured k-stars (round skipping, Sec. 3.5): the centre v with probability
+   proportional to binom(d_v, k-1) (draw 0), then k-1 distinct neighbours, the
+   i-th uniform among those not taken yet (draw 1 + i): position r of the
+   remaining d_v - i neighbours, where a taken position is refilled by the last
+   remaining one. Leaves come in draw order, each with parent 0. */
+static int sample_stars(const orc_table *T, int64_t nsamp, uint64_t seed, uint64_t stream, uint64_t first_index,
+                        int32_t *out_verts, int8_t *out_parent)
+{
+    const int k = T->k;
+    u128 *pre = malloc((T->n + 1) * sizeof(u128));
+    if (!pre) return ORC_ENOMEM;
+    pre[0] = 0;
+    for (int64_t v = 0; v < T->n; v++) {
+        pre[v + 1] = pre[v];
+        if (add_ck(&pre[v + 1], binom128(T->row_ptr[v + 1] - T->row_ptr[v], k - 1))) { free(pre); set_err("star count overflows"); return ORC_EOVERFLOW; }
+    }
+    if (pre[T->n] == 0) { free(pre); set_err("no k-star to sample"); return ORC_EEMPTY; }
     for (int64_t s = 0; s < nsamp; s++) {
         uint64_t idx = first_index + (uint64_t)s;
         int32_t *verts = out_verts + s * k;
         int8_t *par = out_parent + s * k;
-        /* root draw */
-        u128 X = uniform_below(tot, seed, stream, idx, 0);
-        int64_t lo = 0, hi = T->n;   /* first v with pre[v+1] > X */
+        u128 X = uniform_below(pre[T->n], seed, stream, idx, 0);
+        int64_t lo = 0, hi = T->n;
         while (lo < hi) { int64_t mid = (lo + hi) / 2; if (pre[mid + 1] > X) hi = mid; else lo = mid + 1; }
-        int64_t v = lo;
-        u128 res = X - pre[v], cum = 0;
-        int rkey = -1;
-        for (int64_t q = T->off[k][v]; q < T->off[k][v + 1]; q++) {
-            if (!admissible(T, T->key[k][q], shape)) continue;
-            cum += T->cnt[k][q];
-            if (cum > res) { rkey = T->key[k][q]; break; }
-        }
-        if (rkey < 0) { free(pre); set_err("internal: root draw fell off the record"); return ORC_EINVAL; }
-
-        int nv = 0;
-        verts[nv] = (int32_t)v; par[nv] = -1; nv++;
-        struct { int key; int pos; } stack[2 * KMAX];
-        int sp = 0;
-        stack[sp].key = rkey; stack[sp].pos = 0; sp++;
-        int dec = 0;
-        while (sp > 0) {
-            sp--;
-            int key = stack[sp].key, pos = stack[sp].pos;
-            int h, r; unsigned C;
-            key_decode(ks, key, &h, &r, &C);
-            if (h == 1) continue;
-            int64_t x = verts[pos];
-            unsigned cv = 1u << T->colors[x];
-            int hp = sh_hp[h][r], hpp = h - hp, a = sh_a[h][r], b = sh_b[h][r];
-            u128 cT = lookup(T, h, x, key);
-            u128 Y = uniform_below((u128)sh_beta[h][r] * cT, seed, stream, idx, 1 + 2 * dec);
-            /* stage 1: C'' subset of C \ {c_x}, |C''| = |T''|, ascending bitmask */
-            unsigned rest = C & ~cv, Cpp = 0;
-            u128 run = 0, Spick = 0;
-            int found = 0;
-            for (unsigned m = 0; m < (1u << k); m++) {
-                if ((m & ~rest) || popc(m) != hpp) continue;
-                int kpp = key_of(ks, hpp, b, m);
-                u128 Ssum = 0;
-                for (int64_t e = T->row_ptr[x]; e < T->row_ptr[x + 1]; e++)
-                    Ssum += lookup(T, hpp, T->col_idx[e], kpp);
-                u128 w = lookup(T, hp, x, key_of(ks, hp, a, C ^ m)) * Ssum;
-                run += w;
-                if (run > Y) { Cpp = m; Spick = Ssum; found = 1; break; }
-            }
-            if (!found) { free(pre); set_err("internal: colour-set draw fell off"); return ORC_EINVAL; }
-            /* stage 2: neighbour u with weight c(T''_{C''}, u) */
-            int kpp = key_of(ks, hpp, b, Cpp);
-            u128 Z = uniform_below(Spick, seed, stream, idx, 2 + 2 * dec);
-            u128 run2 = 0;
-            int64_t u = -1;
-            for (int64_t e = T->row_ptr[x]; e < T->row_ptr[x + 1]; e++) {
-                run2 += lookup(T, hpp, T->col_idx[e], kpp);
-                if (run2 > Z) { u = T->col_idx[e]; break; }
-            }
-            if (u < 0) { free(pre); set_err("internal: neighbour draw fell off"); return ORC_EINVAL; }
-            int upos = nv;
-            verts[nv] = (int32_t)u; par[nv] = (int8_t)pos; nv++;
-            dec++;
-            stack[sp].key = kpp; stack[sp].pos = upos; sp++;
-            stack[sp].key = key_of(ks, hp, a, C ^ Cpp); stack[sp].pos = pos; sp++;
+        const int64_t v = lo, d = T->row_ptr[v + 1] - T->row_ptr[v];
+        verts[0] = (int32_t)v; par[0] = -1;
+        int64_t mpos[KMAX], mval[KMAX];   /* positions refilled so far */
+        int nm = 0;
+        for (int i = 0; i < k - 1; i++) {
+            int64_t r = (int64_t)uniform_below((u128)(d - i), seed, stream, idx, 1 + i);
+            int64_t got = r, last = d - 1 - i, lastval = last;
+            for (int q = 0; q < nm; q++) { if (mpos[q] == r) got = mval[q]; if (mpos[q] == last) lastval = mval[q]; }
+            verts[1 + i] = T->col_idx[T->row_ptr[v] + got];
+            par[1 + i] = 0;
+            int q = 0;
+            while (q < nm && mpos[q] != r) q++;
+            if (q == nm) nm++;
+            mpos[q] = r; mval[q] = lastval;
         }
     }
     free(pre);
     return ORC_OK;
+}
+
+int orc_sample(const orc_table *T, int shape, int64_t nsamp, uint64_t seed, uint64_t stream,
+               uint64_t first_index, int32_t *out_verts, int8_t *out_parent)
+{
+    const int k = T->k;
+    if (shape >= unr_n[k]) { set_err("shape id out of range"); return ORC_EINVAL; }
+    const int bal = T->rooting == ORC_ROOT_BALANCED;
+    if (bal && shape == star_class[k]) return sample_stars(T, nsamp, seed, stream, first_index, out_verts, out_parent);
+    /* shape-first under round skipping: draw 0 picks the shape (weight t_j),
+       then the shape's sample follows with every draw index shifted by one */
+    const int first = bal && shape < 0;
+    u128 *pre[MAXSH] = {0};
+    int st = ORC_OK;
+    if (first) {
+        for (int j = 0; j < unr_n[k] && !st; j++)
+            if (bal_rank[k][j] >= 0 && T->tj[j] > 0) st = make_pre(T, j, &pre[j]);
+    } else {
+        st = make_pre(T, shape, &pre[0]);
+    }
+    if (st) { for (int j = 0; j < MAXSH; j++) free(pre[j]); return st; }
+    if ((first && T->t == 0) || (!first && pre[0][T->n] == 0)) {
+        for (int j = 0; j < MAXSH; j++) free(pre[j]);
+        set_err("no colourful k-treelet to sample");
+        return ORC_EEMPTY;
+    }
+    for (int64_t s = 0; s < nsamp && !st; s++) {
+        uint64_t idx = first_index + (uint64_t)s;
+        if (first) {
+            u128 X = uniform_below(T->t, seed, stream, idx, 0), cum = 0;
+            int j = 0;
+            for (; j < unr_n[k]; j++) {
+                if (bal_rank[k][j] < 0) continue;
+                cum += T->tj[j];
+                if (cum > X) break;
+            }
+            st = sample_one(T, j, pre[j], seed, stream, idx, 1, out_verts + s * k, out_parent + s * k);
+        } else {
+            st = sample_one(T, shape, pre[0], seed, stream, idx, 0, out_verts + s * k, out_parent + s * k);
+        }
+    }
+    for (int j = 0; j < MAXSH; j++) free(pre[j]);
+    return st;
 }
 
 /* ------------------------------------------------------------------------- */
@@ -1005,6 +1174,7 @@ int orc_ags(const orc_table *T, int64_t cbar, int64_t round_size, int64_t budget
             uint64_t seed, uint64_t stream,
             int64_t *out_hits, double *out_w, int64_t *out_nj, int32_t *out_rounds_shape, int64_t *out_nrounds)
 {
+    if (T->rooting == ORC_ROOT_BALANCED) { set_err("AGS needs zero-rooting or all rootings"); return ORC_EINVAL; }
     const int k = T->k;
     int st = build_catalog(k);
     if (st) return st;
