@@ -52,7 +52,7 @@ typedef enum {
     SCC_EUNSUPPORTED = -7  /* valid request this build does not support */
 } scc_status;
 
-enum { SCC_ROOT_ZERO = 0, SCC_ROOT_ALL = 1 };
+enum { SCC_ROOT_ZERO = 0, SCC_ROOT_ALL = 1, SCC_ROOT_BALANCED = 2 };
 
 typedef struct scc_table scc_table;
 
@@ -78,7 +78,15 @@ typedef struct {
 typedef struct {
     int rooting;               /* SCC_ROOT_ZERO (default): level k kept at colour-0
                                   vertices only (zero-rooting, Sec. 3.4);
-                                  SCC_ROOT_ALL: at every vertex (Eq. (1) as is) */
+                                  SCC_ROOT_ALL: at every vertex (Eq. (1) as is);
+                                  SCC_ROOT_BALANCED: round skipping (Sec. 3.5, the
+                                  balanced decomposition), k >= 4: level k-1 is not
+                                  built and level k holds, at every vertex, only the
+                                  designated rooting of each non-star unrooted shape
+                                  (scc_balanced_rooting); stars are counted in closed
+                                  form and sampled directly (scc_sample). Not
+                                  supported by scc_build_batch, scc_ags and AGS
+                                  sessions of the server (SCC_EINVAL). */
     int max_bits;              /* 64 or 128 (0 = 128): widest count allowed */
     void *stream;              /* hipStream_t for all work of the build */
     const scc_allocator *alloc;/* NULL: hipMalloc / hipFree */
@@ -100,6 +108,10 @@ typedef struct {
  * tables"); level k is stored at colour-0 vertices (SCC_ROOT_ZERO) or at all
  * vertices (SCC_ROOT_ALL). Then computes the per-vertex level-k totals eta_v,
  * their running sum over vertices, the total t and per-unrooted-shape totals t_j.
+ * Under SCC_ROOT_BALANCED, t_j of a non-star shape is its level-k sum divided
+ * by the designated rooting's orbit, the star's t_j is 0 and t is the sum of
+ * the non-star t_j; the number of uncoloured k-stars is in scc_table_info.stars
+ * (SCC_EOVERFLOW if it needs more than 128 bits).
  *
  * g, colors: device pointers, borrowed for the lifetime of the table (the
  * sampler and classifier read them); the caller keeps them alive and unchanged.
@@ -129,6 +141,8 @@ typedef struct {
     double level_ms[9];        /* device time of level h (bound, gather, combine, pack) */
     double gather_ms[9];       /* device time of the neighbour-sum gather of level h */
     int num_hubs;              /* rows gathered in chunks (degree above the hub threshold) */
+    uint64_t stars[2];         /* SCC_ROOT_BALANCED: uncoloured k-stars of the graph,
+                                  sum_v binom(d_v, k-1) (lo, hi); 0 otherwise */
 } scc_table_info;
 
 /* Table summary (host struct; no device work). */
@@ -147,7 +161,8 @@ scc_status scc_gather_bytes(const scc_table *t, double out[9]);
 /*
  * scc_occ -- database queries of Sec. 3: occ(T_C, v) (key >= 0: the count of
  * the coloured rooted treelet with that key at v) or occ(v) (key = -1: eta_v,
- * the number of colourful k-treelet copies stored at v). out: host uint64[2]
+ * the number of colourful k-treelet copies stored at v; under SCC_ROOT_BALANCED
+ * the designated rootings at v, level k-1 being empty). out: host uint64[2]
  * (lo, hi). Errors: SCC_EINVAL for v or key out of range.
  */
 scc_status scc_occ(const scc_table *t, int64_t v, int32_t key, uint64_t out[2]);
@@ -178,6 +193,19 @@ scc_status scc_export_level(const scc_table *t, int h, int64_t *nnz_out,
  * (sample index, draw << 32 | attempt, 0, 0), masked to the bit length of N-1
  * and rejected when >= N; draw 0 is the root, draws 1 + 2i and 2 + 2i belong
  * to the i-th decomposition. Sample s uses index first_index + s.
+ *
+ * Tables built with SCC_ROOT_BALANCED (round skipping, Sec. 3.5): level k
+ * holds only designated rootings, so shape = -1 draws the shape first: draw 0
+ * picks the non-star shape j with probability t_j / t (first j, ascending,
+ * whose running sum of t_j exceeds a uniform integer below t), then shape j is
+ * sampled as above with every draw number increased by 1. shape = the star
+ * (scc_star_shape) draws an uncoloured k-star of the graph uniformly: the
+ * centre v with probability binom(d_v, k-1) / stars (draw 0, running sums over
+ * vertices ascending), then k-1 distinct neighbours, the i-th at position r,
+ * uniform below d_v - i (draw 1 + i), among the remaining ones, where a taken
+ * position is refilled by the last remaining neighbour (CSR positions, a
+ * partial Fisher-Yates shuffle); the leaves follow the centre in draw order,
+ * each with parent 0.
  *
  * out_verts: device int32[n * k], vertex ids in discovery order, root first.
  * out_parent: device int8[n * k], position of each vertex's parent (-1 for the
@@ -237,6 +265,19 @@ scc_status scc_ags(const scc_table *t, int64_t cbar, int64_t round_size, int64_t
    outside [1, 8]. Shape ids j in [0, this) order the shapes by the smallest
    DFS bitstring among their rootings. */
 int scc_num_unrooted(int k);
+
+/* Round skipping (Sec. 3.5): the designated rooting of unrooted k-shape j, the
+   smallest rooted rank (ascending DFS bitstring among the rooted k-shapes)
+   whose canonical decomposition splits the tree into two trees of 2..k-2
+   nodes. Returns -1 for the k-star, which has no such rooting, for k < 4 and
+   for j or k out of range. *orbit (if not NULL) receives the number of nodes
+   of a copy at which rooting it gives the designated rooted shape (0 when
+   -1 is returned): SCC_ROOT_BALANCED counts every copy that many times. */
+int scc_balanced_rooting(int k, int j, int *orbit);
+
+/* Unrooted shape id of the k-star (the tree with one centre and k-1 leaves),
+   -1 if k is outside [2, 8]. */
+int scc_star_shape(int k);
 
 /* One instance of a batched build: a graph (device pointers, as for
    scc_build_table), its colours and its k. */

@@ -23,7 +23,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libscc.so")
 
 OK, EINVAL, ENOMEM, EOVERFLOW, EDEVICE, EEMPTY, EBUSY, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
-ROOT_ZERO, ROOT_ALL = 0, 1
+ROOT_ZERO, ROOT_ALL, ROOT_BALANCED = 0, 1, 2
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with paper_2009_03052_amd/build.py "
@@ -75,7 +75,7 @@ class TableInfo(C.Structure):
     _fields_ = [("n", C.c_int64), ("k", C.c_int), ("rooting", C.c_int), ("num_unrooted", C.c_int),
                 ("nnz", C.c_int64 * 9), ("wide_vertices", C.c_int64 * 9), ("bytes", C.c_int64),
                 ("t", C.c_uint64 * 2), ("tj", (C.c_uint64 * 2) * 32), ("level_ms", C.c_double * 9),
-                ("gather_ms", C.c_double * 9), ("num_hubs", C.c_int)]
+                ("gather_ms", C.c_double * 9), ("num_hubs", C.c_int), ("stars", C.c_uint64 * 2)]
 
 
 class _ServerOpts(C.Structure):
@@ -132,6 +132,8 @@ _SIGS = {
     "scc_server_destroy": (None, [_P]),
     "scc_release_caches": (None, []),
     "scc_num_unrooted": (C.c_int, [C.c_int]),
+    "scc_balanced_rooting": (C.c_int, [C.c_int, C.c_int, C.POINTER(C.c_int)]),
+    "scc_star_shape": (C.c_int, [C.c_int]),
     "scc_last_error": (C.c_char_p, []),
     "scc_version": (C.c_char_p, []),
 }
@@ -253,6 +255,11 @@ class Table:
         """(t, [t_j]) as Python ints."""
         i = self.info()
         return _u128(i.t[0], i.t[1]), [_u128(i.tj[j][0], i.tj[j][1]) for j in range(i.num_unrooted)]
+
+    def star_count(self) -> int:
+        """Uncoloured k-stars of the graph (tables built with ROOT_BALANCED; else 0)."""
+        i = self.info()
+        return _u128(i.stars[0], i.stars[1])
 
     def occ(self, v: int, key: int = -1) -> int:
         out = (C.c_uint64 * 2)()
@@ -431,6 +438,21 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def num_unrooted(k: int) -> int:
+    return _lib.scc_num_unrooted(k)
+
+
+def balanced_rooting(k: int, j: int):
+    """(designated rooted rank, orbit) of unrooted k-shape j under round skipping; (-1, 0) for the star."""
+    orb = C.c_int(0)
+    r = _lib.scc_balanced_rooting(k, j, C.byref(orb))
+    return r, orb.value
+
+
+def star_shape(k: int) -> int:
+    return _lib.scc_star_shape(k)
 
 
 def num_classes(k: int) -> int:

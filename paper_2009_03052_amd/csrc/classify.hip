@@ -575,6 +575,8 @@ extern "C" scc_status scc_ags(const scc_table *tc, int64_t cbar, int64_t round_s
     scc_table *T = const_cast<scc_table *>(tc);
     if (!T || !hits || !w_out || !n_j || !n_rounds) return set_error(SCC_EINVAL, "NULL argument");
     if (cbar < 1 || round_size < 1 || budget < 0) return set_error(SCC_EINVAL, "bad AGS parameters");
+    if (T->rooting == SCC_ROOT_BALANCED)
+        return set_error(SCC_EINVAL, "AGS needs zero-rooting or all rootings (round skipping drops stars from t_j)");
     const int k = T->k;
     hipStream_t st = stream ? (hipStream_t)stream : T->stream;
     AgsState A;

@@ -391,6 +391,7 @@ struct CombineArgs {
     GraphView g;
     const DevLut *L;
     int h, zero_only, max_bits;
+    int bal;                              // level k under round skipping: designated shapes only
     LevelSrc lev[SCC_KMAX + 1];           // own levels 2..h-1
     const uint64_t *Slo[SCC_KMAX + 1];    // neighbour sums 1..h-1
     const uint64_t *Shi[SCC_KMAX + 1];
@@ -420,9 +421,12 @@ __device__ inline void combine_vertex(const CombineArgs &A, int64_t v, uint64_t 
         if (lane == 0) { A.meta[v] = 0; A.Nout[v] = 0; }
         return;
     }
-    // per-vertex bound: U >= sum over (T, C) of beta_T c(T_C, v) >= every partial sum
+    // per-vertex bound: U >= sum over (T, C) of beta_T c(T_C, v) >= every partial sum.
+    // Under round skipping both parts of a designated shape have 2..h-2 nodes, so
+    // only those part sizes are bounded and staged (level h-1 is not built).
+    const int plo = A.bal ? 2 : 1, phi = A.bal ? h - 2 : h - 1;
     u128 U = 0;
-    for (int hp = 1; hp < h; hp++) {
+    for (int hp = plo; hp <= phi; hp++) {
         u128 Nv = hp == 1 ? (u128)1 : h_N<SLOTS>(A.lev[hp], src_handle<SLOTS>(A.lev[hp], v));
         U = sat_add(U, sat_mul(Nv, A.M[h - hp][v]));
     }
@@ -446,7 +450,7 @@ __device__ inline void combine_vertex(const CombineArgs &A, int64_t v, uint64_t 
     __syncthreads();
     if (lane == 0) Xlo[L.xoff[1]] = 1;   // level 1: the single node, coloured c_v
     const int16_t *xidx = A.key_xidx + (size_t)cv * L.nkeys;
-    for (int hp = 2; hp < h; hp++) {
+    for (int hp = 2; hp <= phi; hp++) {
         const RecView<SLOTS> r = h_rec<SLOTS>(A.lev[hp], src_handle<SLOTS>(A.lev[hp], v));
         for (uint32_t e = lane; e < r.len; e += WAVE) {
             const int x = L.xoff[hp] + xidx[r.key[e]];
@@ -454,7 +458,7 @@ __device__ inline void combine_vertex(const CombineArgs &A, int64_t v, uint64_t 
             if (wide) Xhi[x] = r.hi ? r.hi[e] : 0;
         }
     }
-    for (int hs = 1; hs < h; hs++) {
+    for (int hs = 1; hs <= phi; hs++) {
         const int ws = L.WS[hs];
         const uint64_t *gl = A.Slo[hs] + (size_t)v * ws;
         const bool sw = hi64(A.M[hs][v]) != 0;
@@ -479,7 +483,7 @@ __device__ inline void combine_vertex(const CombineArgs &A, int64_t v, uint64_t 
         const int o = o0 + lane;
         u128 val = 0;
         int t = 0, dc = 0;
-        if (o < Wh) {
+        if (o < Wh && !(A.bal && !L.designated[o / nD])) {
             t = o / nD;
             dc = o - t * nD;
             const int hp = L.dec_hp[h][t], hpp = h - hp;
@@ -699,6 +703,30 @@ __global__ void __launch_bounds__(256) k_reduce_parts(const u128 *part, int nb, 
         for (int w = 0; w < 256 / WAVE; w++) t += ws[w];
         out[j] = t;
     }
+}
+
+// Round skipping (Sec. 3.5): the uncoloured k-stars centred at v, binom(d_v, k-1),
+// by the exact recurrence c_i = c_{i-1} (d - r + i) / i; flags a product that
+// does not fit 128 bits
+__global__ void k_star_weight(GraphView g, int r, u128 *w, unsigned long long *flag)
+{
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= g.n) return;
+    const int64_t d = g.row_ptr[v + 1] - g.row_ptr[v];
+    u128 c = d >= r ? 1 : 0;
+    for (int i = 1; i <= r && c; i++) {
+        const u128 p = sat_mul(c, (u128)(d - r + i));
+        if (p == ~(u128)0) { atomicOr(flag, 1ull); c = 0; break; }
+        c = div_small(p, (uint32_t)i);
+    }
+    w[v] = c;
+}
+
+// a running sum wrapped modulo 2^128 exactly where it decreases
+__global__ void k_wrap_check(const u128 *pre, int64_t n, unsigned long long *flag)
+{
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= 1 && v < n && pre[v] < pre[v - 1]) atomicOr(flag, 1ull);
 }
 
 __global__ void k_eta_shape(GraphView g, const DevLut *Lp, LevelView Lk, int zero_only, int shape, u128 *eta)
@@ -957,6 +985,8 @@ static scc_status build_levels(scc_table *T)
     hipStream_t st = T->stream;
     GraphView g{n, T->row_ptr, T->col_idx, T->colors};
     const bool zero = T->rooting == SCC_ROOT_ZERO;
+    // round skipping (Sec. 3.5): level k-1 and its neighbour sums are not built
+    const bool bal = T->rooting == SCC_ROOT_BALANCED;
     const int hub_degree = T->hub_degree;
 
     int *err = (int *)T->mem.get(16);
@@ -1056,7 +1086,7 @@ static scc_status build_levels(scc_table *T)
         HIP_TRY(hipEventRecord(ev[h][0], st));
         HIP_TRY(hipMemsetAsync(err, 0, 16, st));   // [0] flags, [1] wide vertices
         const int hs = h - 1;   // neighbour sums needed now
-        if (hs >= 2) {
+        if (hs >= 2 && !(bal && hs == k - 1)) {
             TableSums &Sx = T->S[hs];
             const size_t sz = (size_t)n * HL.WS[hs] * 8;
             Sx.M = (u128 *)T->alloc((size_t)n * 16 + 16);
@@ -1082,8 +1112,20 @@ static scc_status build_levels(scc_table *T)
         TableLevel &Lv = T->lev[h];
         Lv.loc = (uint64_t *)T->alloc((size_t)n * 8 + 8);
         if (!Lv.loc) return set_error(SCC_ENOMEM, "level %d locators", h);
+        if (bal && h == k - 1) {
+            // skipped level: every record empty (its entry count stays 0 in the summary)
+            Lv.pool = (uint64_t *)T->alloc(64);
+            if (!Lv.pool) return set_error(SCC_ENOMEM, "level %d", h);
+            Lv.pool_words = 0;
+            Lv.BW = 0;
+            Lv.bm = nullptr;
+            HIP_TRY(hipMemsetAsync(Lv.loc, 0, (size_t)n * 8 + 8, st));
+            HIP_TRY(hipEventRecord(ev[h][1], st));
+            continue;
+        }
         CombineArgs C{};
         C.g = g; C.L = T->dlut; C.h = h; C.zero_only = zero && last; C.max_bits = T->max_bits;
+        C.bal = bal && last;
         for (int q = 2; q < h; q++) C.lev[q] = packed_src(T->lev[q]);
         for (int q = 1; q < h; q++) { C.Slo[q] = T->S[q].lo; C.Shi[q] = T->S[q].hi; C.M[q] = T->S[q].M; }
         C.key_xidx = T->key_xidx; C.W = HL.W[h];
@@ -1129,7 +1171,7 @@ static scc_status build_levels(scc_table *T)
         HIP_TRY(hipEventElapsedTime(&ms, ev[h][0], ev[h][1]));
         T->level_ms[h] = ms;
         if (h == 1) T->gather_ms[1] = ms;
-        if (h >= 2 && h < k) {
+        if (h >= 2 && h < k && !(bal && h == k - 1)) {
             HIP_TRY(hipEventElapsedTime(&ms, gev[h][0], gev[h][1]));
             T->gather_ms[h] = ms;
         }
@@ -1147,6 +1189,7 @@ static scc_status gather_stats(scc_table *T)
     unsigned long long *acc = (unsigned long long *)T->mem.get(64);
     if (!acc) return set_error(SCC_ENOMEM, "stats");
     for (int hs = 2; hs < T->k; hs++) {
+        if (T->rooting == SCC_ROOT_BALANCED && hs == T->k - 1) { T->gather_bytes[hs] = 0; continue; }
         HIP_TRY(hipMemsetAsync(acc, 0, 8, st));
         const bool rz = T->rooting == SCC_ROOT_ZERO && hs == T->k - 1;
         if (n) hipLaunchKernelGGL(k_gather_bytes, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g,
@@ -1165,7 +1208,9 @@ static scc_status gather_stats(scc_table *T)
 // and the root total land in the device summary; nothing waits for the device.
 constexpr int DSUM_TJ = 2 * (SCC_KMAX + 1);     // u64 index of the 32 per-shape totals
 constexpr int DSUM_TOT = DSUM_TJ + 64;           // u64 index of the root total
-constexpr int DSUM_WORDS = DSUM_TOT + 2;
+constexpr int DSUM_STAR = DSUM_TOT + 2;          // uncoloured k-stars (round skipping)
+constexpr int DSUM_SFLAG = DSUM_STAR + 2;        // nonzero: the star count overflowed
+constexpr int DSUM_WORDS = DSUM_SFLAG + 1;
 
 static scc_status totals_launch(scc_table *T)
 {
@@ -1187,6 +1232,21 @@ static scc_status totals_launch(scc_table *T)
     scc_status s = scan_u128(T, T->eta, T->pre, n);
     if (s) return s;
     if (n) HIP_TRY(hipMemcpyAsync(T->dsum + DSUM_TOT, T->pre + (n - 1), 16, hipMemcpyDeviceToDevice, st));
+    if (T->rooting == SCC_ROOT_BALANCED) {
+        // stars: per-vertex counts, their running sums (the direct star sampler's
+        // centre draw) and the total
+        T->star_pre = (u128 *)T->alloc((size_t)n * 16 + 16);
+        if (!T->star_pre) return set_error(SCC_ENOMEM, "star counts");
+        unsigned long long *flag = (unsigned long long *)(T->dsum + DSUM_SFLAG);
+        const unsigned blocks = (unsigned)((n + 255) / 256);
+        if (n) hipLaunchKernelGGL(k_star_weight, dim3(blocks), dim3(256), 0, st, g, k - 1, T->star_pre, flag);
+        s = scan_u128(T, T->star_pre, T->star_pre, n);
+        if (s) return s;
+        if (n) {
+            hipLaunchKernelGGL(k_wrap_check, dim3(blocks), dim3(256), 0, st, T->star_pre, n, flag);
+            HIP_TRY(hipMemcpyAsync(T->dsum + DSUM_STAR, T->star_pre + (n - 1), 16, hipMemcpyDeviceToDevice, st));
+        }
+    }
     HIP_TRY(hipGetLastError());
     return SCC_OK;
 }
@@ -1207,6 +1267,27 @@ static scc_status totals_finish(scc_table *T)
     T->lev[1].nnz = T->n;
     const u128 tot = T->n ? mk128(h[DSUM_TOT], h[DSUM_TOT + 1]) : (u128)0;
     T->root_total = tot;
+    if (T->rooting == SCC_ROOT_BALANCED) {
+        // every copy of a non-star shape is counted once per node of its
+        // designated rooting's orbit
+        if (h[DSUM_SFLAG]) return set_error(SCC_EOVERFLOW, "the number of %d-stars needs more than 128 bits", k);
+        T->stars = T->n ? mk128(h[DSUM_STAR], h[DSUM_STAR + 1]) : (u128)0;
+        u128 t = 0;
+        for (int j = 0; j < T->hlut.num_unr; j++) {
+            const u128 tj = mk128(h[DSUM_TJ + 2 * j], h[DSUM_TJ + 2 * j + 1]);
+            const int orb = T->hlut.bal_orbit[j];
+            if (orb == 0) {
+                if (tj) return set_error(SCC_EINVAL, "internal: counts of the star at level %d", k);
+                T->tj[j] = 0;
+                continue;
+            }
+            if (tj % (u128)orb) return set_error(SCC_EINVAL, "internal: shape %d total not divisible by its orbit", j);
+            T->tj[j] = tj / (u128)orb;
+            t += T->tj[j];
+        }
+        T->t = t;
+        return SCC_OK;
+    }
     for (int j = 0; j < T->hlut.num_unr; j++) {
         const u128 tj = mk128(h[DSUM_TJ + 2 * j], h[DSUM_TJ + 2 * j + 1]);
         T->tj[j] = zero ? tj : tj / (u128)k;
@@ -1266,7 +1347,9 @@ extern "C" scc_status scc_build_table(const scc_csr *g, const uint8_t *colors, i
         return set_error(SCC_EINVAL, "bad CSR pointers");
     scc_build_opts o{};
     if (opt) o = *opt;
-    if (o.rooting != SCC_ROOT_ZERO && o.rooting != SCC_ROOT_ALL) return set_error(SCC_EINVAL, "bad rooting");
+    if (o.rooting != SCC_ROOT_ZERO && o.rooting != SCC_ROOT_ALL && o.rooting != SCC_ROOT_BALANCED)
+        return set_error(SCC_EINVAL, "bad rooting");
+    if (o.rooting == SCC_ROOT_BALANCED && k < 4) return set_error(SCC_EINVAL, "round skipping needs k >= 4 (k = %d)", k);
     if (o.max_bits == 0) o.max_bits = 128;
     if (o.max_bits != 64 && o.max_bits != 128) return set_error(SCC_EINVAL, "max_bits must be 64 or 128");
 
@@ -1345,6 +1428,7 @@ extern "C" scc_status scc_table_info_get(const scc_table *t, scc_table_info *out
     out->bytes = t->bytes;
     out->t[0] = lo64(t->t); out->t[1] = hi64(t->t);
     for (int j = 0; j < t->hlut.num_unr; j++) { out->tj[j][0] = lo64(t->tj[j]); out->tj[j][1] = hi64(t->tj[j]); }
+    out->stars[0] = lo64(t->stars); out->stars[1] = hi64(t->stars);
     return SCC_OK;
 }
 
@@ -1687,6 +1771,7 @@ static scc_status batch_launch(std::vector<BatchInstHost> &H, int tile, int hub_
         for (int h = 2; h <= k; h++) {
             CombineArgs &C = B.C[h];
             C.g = B.g; C.L = T->dlut; C.h = h; C.zero_only = zero && h == k; C.max_bits = T->max_bits;
+            C.bal = 0;
             for (int q = 2; q < h; q++) C.lev[q] = slot_src(q);
             for (int q = 1; q < h; q++) { C.Slo[q] = T->S[q].lo; C.Shi[q] = T->S[q].hi; C.M[q] = T->S[q].M; }
             C.key_xidx = T->key_xidx; C.W = HL.W[h];
@@ -1783,6 +1868,7 @@ extern "C" scc_status scc_build_batch(const scc_instance *inst, int n_inst, cons
     scc_build_opts o{};
     if (opt) o = *opt;
     if (o.max_bits == 0) o.max_bits = 128;
+    if (o.rooting == SCC_ROOT_BALANCED) return set_error(SCC_EINVAL, "round skipping is not supported by the batched build");
     if (o.rooting != SCC_ROOT_ZERO && o.rooting != SCC_ROOT_ALL) return set_error(SCC_EINVAL, "bad rooting");
     if (o.max_bits != 64 && o.max_bits != 128) return set_error(SCC_EINVAL, "max_bits must be 64 or 128");
     scc_batch_opts bo{};

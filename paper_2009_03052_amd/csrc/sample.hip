@@ -83,12 +83,51 @@ struct SampleLds {
     u128 st_cnt[2 * SCC_KMAX];
 };
 
+// An uncoloured k-star (round skipping, Sec. 3.5): the centre v by its running
+// sum of binom(d_v, k-1) (draw 0), then the i-th leaf at position r uniform
+// below d_v - i (draw 1 + i) among the neighbours not taken yet, where a taken
+// position is refilled by the last remaining one. Every lane makes the same
+// draws; lane q < i holds the q-th refilled position and its current value.
+__device__ inline int sample_star(const SampleArgs &A, int64_t r)
+{
+    const int lane = lane_id();
+    const int k = A.k;
+    const uint64_t idx = A.first + (uint64_t)r;
+    const u128 X = draw_below(A.total, A.seed, A.stream, idx, 0);
+    const int64_t v = wave_search(A.g.n, X, [&](int64_t i) { return A.pre[i]; });
+    if (v < 0) return 4;
+    const int64_t ra = A.g.row_ptr[v], d = A.g.row_ptr[v + 1] - ra;
+    if (d < k - 1) return 4;
+    int64_t mpos = -1, mval = 0;     // this lane's refilled position
+    int nm = 0;
+    int32_t leaf = (int32_t)v;
+    for (int i = 0; i < k - 1; i++) {
+        const int64_t rr = (int64_t)draw_below((u128)(d - i), A.seed, A.stream, idx, 1 + i);
+        const int64_t last = d - 1 - i;
+        const uint64_t hit = __ballot(lane < nm && mpos == rr);
+        const uint64_t hitl = __ballot(lane < nm && mpos == last);
+        const int64_t got = hit ? (int64_t)shfl64((uint64_t)mval, __ffsll((long long)hit) - 1) : rr;
+        const int64_t lastval = hitl ? (int64_t)shfl64((uint64_t)mval, __ffsll((long long)hitl) - 1) : last;
+        if (lane == 1 + i) leaf = A.g.col_idx[ra + got];
+        const int q = hit ? __ffsll((long long)hit) - 1 : nm;
+        if (lane == q) { mpos = rr; mval = lastval; }
+        if (!hit) nm++;
+    }
+    if (lane < k) {
+        A.verts[(size_t)r * k + lane] = leaf;
+        A.par[(size_t)r * k + lane] = lane == 0 ? -1 : 0;
+    }
+    return 0;
+}
+
 // Sample number r of A's stream (random index A.first + r) into row r of
 // A.verts / A.par, by the whole wave. Returns 0, or an error bit (1: the root
 // entry draw fell off the record, 2: a decomposition draw failed, 4: the root
-// vertex draw fell off the running sums); none is expected for a consistent table.
+// vertex (or shape) draw fell off its running sums); none is expected for a
+// consistent table.
 __device__ inline int sample_one(const SampleArgs &A, int64_t r, SampleLds &W)
 {
+    if (A.mode == 2) return sample_star(A, r);
     int32_t *sv = W.sv;
     int8_t *sp_par = W.par;
     uint32_t *st_key = W.st_key;
@@ -98,11 +137,27 @@ __device__ inline int sample_one(const SampleArgs &A, int64_t r, SampleLds &W)
     const int lane = lane_id();
     const int k = A.k;
     const uint64_t idx = A.first + (uint64_t)r;
+    int shape = A.shape;
+    const u128 *pre = A.pre;
+    u128 total = A.total;
+    uint32_t doff = 0;   // draw numbers start here
+    if (A.mode == 1) {
+        // shape first: j with running sum of t_j (ascending) exceeding X0, then
+        // shape j's draws numbered from 1
+        const u128 X0 = draw_below(A.total, A.seed, A.stream, idx, 0);
+        const u128 incl = wave_incl_scan128(lane < L.num_unr ? A.stj[lane] : (u128)0);
+        const int j = first_exceeding(incl, X0);
+        if (j < 0) return 4;
+        shape = j;
+        pre = A.spre[j];
+        total = pre[A.g.n - 1];
+        doff = 1;
+    }
     // (1) root: first vertex whose running sum exceeds X, then the entry of its record
-    const u128 X = draw_below(A.total, A.seed, A.stream, idx, 0);
-    const int64_t v = wave_search(A.g.n, X, [&](int64_t i) { return A.pre[i]; });
+    const u128 X = draw_below(total, A.seed, A.stream, idx, doff);
+    const int64_t v = wave_search(A.g.n, X, [&](int64_t i) { return pre[i]; });
     if (v < 0) return 4;
-    const u128 res = X - (v > 0 ? A.pre[v - 1] : (u128)0);
+    const u128 res = X - (v > 0 ? pre[v - 1] : (u128)0);
     const Rec rk = rec_of(A.lev[k], v);
     const uint32_t lenk = rk.len;
     u128 run = 0;
@@ -115,7 +170,7 @@ __device__ inline int sample_one(const SampleArgs &A, int64_t r, SampleLds &W)
         if (e < lenk) {
             key = rk.key(e);
             const int t = (int)(key - L.off[k]) / L.bk[k];
-            if (A.shape < 0 || L.unr_of[t] == A.shape) c = rk.cnt(e);
+            if (shape < 0 || L.unr_of[t] == shape) c = rk.cnt(e);
         }
         const u128 incl = run + wave_incl_scan128(c);
         const int w = first_exceeding(incl, res);
@@ -150,7 +205,7 @@ __device__ inline int sample_one(const SampleArgs &A, int64_t r, SampleLds &W)
         const int cx = A.g.colors[x];
         const int hp = L.dec_hp[h][t], hpp = h - hp, a = L.dec_a[h][t], b = L.dec_b[h][t];
         const int beta = L.dec_beta[h][t];
-        const u128 Y = draw_below((u128)beta * cT, A.seed, A.stream, idx, 1 + 2 * dec);
+        const u128 Y = draw_below((u128)beta * cT, A.seed, A.stream, idx, doff + 1 + 2 * dec);
         // stage 1: C'' among the |T''|-subsets of C \ {c_x}, ascending bitmask
         const uint32_t R = C & ~(1u << cx);
         int ncand = 1;
@@ -184,7 +239,7 @@ __device__ inline int sample_one(const SampleArgs &A, int64_t r, SampleLds &W)
         const u128 Xp = shfl128(xprime, w1);
         const u128 Sv = shfl128(sval, w1);
         // stage 2: neighbour u of x with weight c(T''_{C''}, u), CSR order
-        const u128 Z = draw_below(Sv, A.seed, A.stream, idx, 2 + 2 * dec);
+        const u128 Z = draw_below(Sv, A.seed, A.stream, idx, doff + 2 + 2 * dec);
         const uint32_t kpp = L.off[hpp] + b * L.bk[hpp] + L.colex_k[Cpp];
         const int64_t ra = A.g.row_ptr[x], rb = A.g.row_ptr[x + 1];
         int64_t u = -1;
@@ -310,6 +365,7 @@ struct HubPreArgs {
     GraphView g;
     const DevLut *L;
     int k, nkeys, zero;
+    int bal;                     // round skipping: level k-1 is not built
     LevelView lev[SCC_KMAX + 1];
     const u128 *M[SCC_KMAX + 1];
     const int16_t *key_sidx;
@@ -388,6 +444,7 @@ __global__ void __launch_bounds__(256) k_hubpre_chunk(HubPreArgs A)
     const int64_t x = A.hubs[q];
     const int cx = A.g.colors[x];
     if (A.zero && hpp == A.k - 1 && cx != 0) return;   // no block: x is never a root there
+    if (A.bal && hpp == A.k - 1) return;                // no block: the level is skipped
     const DevLut &L = *A.L;
     const int WS = L.WS[hpp];
     const int64_t ra = A.hub_rows[2 * q], rb = A.hub_rows[2 * q + 1], d = rb - ra;
@@ -440,6 +497,7 @@ __global__ void __launch_bounds__(256) k_hubpre_fix(HubPreArgs A)
     const int hpp = blockIdx.y + 1;
     const int64_t x = A.hubs[q];
     if (A.zero && hpp == A.k - 1 && A.g.colors[x] != 0) return;
+    if (A.bal && hpp == A.k - 1) return;
     const DevLut &L = *A.L;
     const int WS = L.WS[hpp];
     const int64_t ra = A.hub_rows[2 * q], rb = A.hub_rows[2 * q + 1], d = rb - ra;
@@ -529,7 +587,7 @@ __global__ void k_hub_info(const int32_t *hubs, int nhub, int k, const uint8_t *
     if (i >= nhub) return;
     const int64_t x = hubs[i];
     out[(size_t)i * (SCC_KMAX + 2)] = colors[x];
-    for (int h = 1; h < k; h++) out[(size_t)i * (SCC_KMAX + 2) + h] = hi64(A.M[h][x]) ? 1 : 0;
+    for (int h = 1; h < k; h++) out[(size_t)i * (SCC_KMAX + 2) + h] = A.M[h] && hi64(A.M[h][x]) ? 1 : 0;
 }
 
 // Builds the per-hub running sums used by the sampler's neighbour draw. Hubs
@@ -546,6 +604,7 @@ static scc_status ensure_hub_prefix(scc_table *T)
     HubPreArgs A{};
     A.g = GraphView{T->n, T->row_ptr, T->col_idx, T->colors};
     A.L = T->dlut; A.k = k; A.nkeys = HL.nkeys; A.zero = T->rooting == SCC_ROOT_ZERO;
+    A.bal = T->rooting == SCC_ROOT_BALANCED;
     for (int h = 2; h <= k; h++) A.lev[h] = lview(T->lev[h]);
     for (int h = 1; h < k; h++) A.M[h] = T->S[h].M;
     A.key_sidx = T->key_sidx;
@@ -568,6 +627,7 @@ static scc_status ensure_hub_prefix(scc_table *T)
     const bool zero = T->rooting == SCC_ROOT_ZERO;
     auto block_words = [&](int i, int h) -> int64_t {
         if (zero && h == k - 1 && info[(size_t)i * (SCC_KMAX + 2)] != 0) return 0;   // never a root there
+        if (A.bal && h == k - 1) return 0;                                             // level not built
         const int64_t w = (int64_t)HL.WS[h] * ((deg(i) + HUB_BLOCK - 1) / HUB_BLOCK);
         return info[(size_t)i * (SCC_KMAX + 2) + h] ? 2 * w : w;
     };
@@ -665,16 +725,61 @@ scc_status table_prefix(scc_table *T, int shape, const u128 **pre, u128 *total)
     return SCC_OK;
 }
 
+// Round skipping, shape -1: every non-star shape's root running sums and the
+// device arrays of the shape-first draw (built once per table).
+static scc_status ensure_shape_first(scc_table *T)
+{
+    const int nu = T->hlut.num_unr;
+    std::vector<const u128 *> ptr(32, nullptr);
+    for (int j = 0; j < nu; j++) {
+        if (T->hlut.bal_rank[j] < 0 || T->tj[j] == 0) continue;
+        u128 tot;
+        scc_status s = table_prefix(T, j, &ptr[j], &tot);
+        if (s) return s;
+    }
+    std::lock_guard<std::mutex> g(T->mu);
+    if (T->bal_spre) return SCC_OK;
+    const u128 **dp = (const u128 **)T->alloc(32 * sizeof(u128 *));
+    u128 *dt = (u128 *)T->alloc(32 * sizeof(u128));
+    if (!dp || !dt) return set_error(SCC_ENOMEM, "shape-first tables");
+    std::vector<u128> tj(32, 0);
+    for (int j = 0; j < nu; j++) tj[j] = T->hlut.bal_rank[j] >= 0 ? T->tj[j] : 0;
+    HIP_TRY(hipMemcpyAsync(dp, ptr.data(), 32 * sizeof(u128 *), hipMemcpyHostToDevice, T->stream));
+    HIP_TRY(hipMemcpyAsync(dt, tj.data(), 32 * sizeof(u128), hipMemcpyHostToDevice, T->stream));
+    HIP_TRY(hipStreamSynchronize(T->stream));
+    T->bal_spre = dp;
+    T->bal_stj = dt;
+    return SCC_OK;
+}
+
 scc_status prepare_sampling(scc_table *T, int shape, SampleArgs *out)
 {
-    const u128 *pre;
-    u128 total;
-    scc_status s = table_prefix(T, shape, &pre, &total);
+    const bool bal = T->rooting == SCC_ROOT_BALANCED;
+    const u128 *pre = nullptr;
+    u128 total = 0;
+    int mode = 0;
+    scc_status s = SCC_OK;
+    if (bal && shape == T->hlut.star_unr) {
+        mode = 2;
+        pre = T->star_pre;
+        total = T->stars;
+        if (total == 0) return set_error(SCC_EEMPTY, "no %d-star to sample", T->k);
+    } else if (bal && shape < 0) {
+        mode = 1;
+        total = T->t;
+        if (total == 0) return set_error(SCC_EEMPTY, "no colourful %d-treelet to sample", T->k);
+        s = ensure_shape_first(T);
+    } else {
+        s = table_prefix(T, shape, &pre, &total);
+        if (!s && total == 0) return set_error(SCC_EEMPTY, "no colourful %d-treelet to sample", T->k);
+    }
     if (s) return s;
-    if (total == 0) return set_error(SCC_EEMPTY, "no colourful %d-treelet to sample", T->k);
     s = ensure_hub_prefix(T);
     if (s) return s;
     SampleArgs A{};
+    A.mode = mode;
+    A.spre = T->bal_spre;
+    A.stj = T->bal_stj;
     A.key_xidx = T->key_xidx; A.nkeys = T->hlut.nkeys;
     if (T->hub_count_pre) { A.hub_index = T->hub_index; A.hub_poff = T->hub_poff; A.hub_pre = T->hub_pre; }
     A.g = GraphView{T->n, T->row_ptr, T->col_idx, T->colors};
@@ -690,7 +795,7 @@ scc_status prepare_all_sampling(scc_table *T)
 {
     SampleArgs A;
     for (int shape = -1; shape < T->hlut.num_unr; shape++) {
-        if (shape >= 0 && T->tj[shape] == 0) continue;
+        if (sample_weight(T, shape) == 0) continue;
         scc_status s = prepare_sampling(T, shape, &A);
         if (s && s != SCC_EEMPTY) return s;
     }

@@ -19,6 +19,12 @@ struct SampleArgs {
     const uint64_t *hub_pre;
     const u128 *pre;                      // running sums of admissible level-k totals
     u128 total;
+    // 0: the draw above; 1: shape first (round skipping, shape -1): total = t,
+    // spre[j] / stj[j] = shape j's root running sums and t_j (0 for the star);
+    // 2: uncoloured k-stars, pre / total = their running sums over centres
+    int mode;
+    const u128 *const *spre;
+    const u128 *stj;
     uint64_t seed, stream, first;
     int64_t nsamp;
     int32_t *verts;

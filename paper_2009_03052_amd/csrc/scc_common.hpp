@@ -38,6 +38,14 @@ struct DevLut {
     uint8_t dec_b[SCC_KMAX + 1][SCC_MAXSH];    // rank of T''
     uint8_t dec_beta[SCC_KMAX + 1][SCC_MAXSH]; // beta_T
     uint8_t unr_of[SCC_MAXSH];                 // unrooted id of each rooted k-shape
+    // Round skipping (Sec. 3.5): the designated rooting of each unrooted k-shape
+    // is its smallest rooted rank whose canonical decomposition splits it into
+    // two trees of 2..k-2 nodes (-1: the star, which has none; every shape for
+    // k < 4); its orbit is the number of nodes of a copy that give that rooting.
+    int8_t bal_rank[32];
+    uint8_t bal_orbit[32];
+    uint8_t designated[SCC_MAXSH];             // 1 for the designated rooted k-shapes
+    int star_unr;                              // unrooted id of the k-star
     uint8_t colex_s[128];                      // rank of a (k-1)-bit mask among masks of equal size
     uint8_t mask_s[SCC_KMAX][64];              // [size][rank] -> (k-1)-bit mask
     uint8_t colex_k[256];                      // rank of a k-bit mask among masks of equal size

@@ -427,7 +427,7 @@ extern "C" scc_status scc_server_create(const scc_server_opts *opts, scc_server 
         std::vector<SampleArgs> b(T->hlut.num_unr + 1);
         for (int shape = -1; shape < T->hlut.num_unr; shape++) {
             SampleArgs A{};
-            if (shape < 0 ? T->t > 0 : T->tj[shape] > 0) {
+            if (sample_weight(T, shape) > 0) {
                 s = prepare_sampling(T, shape, &A);
                 if (s) return fail(s);
             }
@@ -474,6 +474,8 @@ extern "C" scc_status scc_server_ags_open(scc_server *S, int table, int64_t cbar
     if (!S || !session) return set_error(SCC_EINVAL, "NULL argument");
     if (table < 0 || table >= (int)S->tables.size()) return set_error(SCC_EINVAL, "table %d out of range", table);
     if (cbar < 1) return set_error(SCC_EINVAL, "cbar < 1");
+    if (S->tables[table]->rooting == SCC_ROOT_BALANCED)
+        return set_error(SCC_EINVAL, "AGS sessions need zero-rooting or all rootings");
     Session s;
     s.table = table;
     s.seed = seed;
@@ -511,7 +513,7 @@ extern "C" scc_status scc_server_submit(scc_server *S, const scc_request *q, int
     const scc_table *T = S->tables[q->table];
     if (q->kind == SCC_REQ_SAMPLE) {
         if (q->shape < -1 || q->shape >= T->hlut.num_unr) return set_error(SCC_EINVAL, "shape %d out of range", q->shape);
-        if (q->shape < 0 ? T->t == 0 : T->tj[q->shape] == 0)
+        if (sample_weight(T, q->shape) == 0)
             return set_error(SCC_EEMPTY, "no colourful %d-treelet of this shape", T->k);
     } else if (q->kind == SCC_REQ_AGS_ROUND) {
         std::lock_guard<std::mutex> lk(S->mu);

@@ -41,6 +41,13 @@ struct scc_table {
     u128 t = 0;                      // colourful k-treelet copies
     u128 tj[32] = {0};
     u128 root_total = 0;             // sum of eta (k * t under SCC_ROOT_ALL)
+    // round skipping: running sums of the uncoloured k-stars per vertex, their
+    // total, and (built on the first uniform sampling call) the device arrays of
+    // the shape-first draw: per-shape root running sums and totals t_j
+    u128 *star_pre = nullptr;
+    u128 stars = 0;
+    const u128 **bal_spre = nullptr;
+    u128 *bal_stj = nullptr;
     // device summary read once at the end of a build: [2h], [2h+1] = stored entries and
     // 128-bit vertices of level h; then 32 u128 per-shape totals; then the root total
     uint64_t *dsum = nullptr;
@@ -94,6 +101,15 @@ struct scc_table {
         for (void *p : owned) mem.put(p);
     }
 };
+
+// What a sampling call of this shape draws from (shape -1: t; under round
+// skipping the star draws from the uncoloured stars); 0 means nothing to sample.
+inline u128 sample_weight(const scc_table *T, int shape)
+{
+    if (shape < 0) return T->t;
+    if (T->rooting == SCC_ROOT_BALANCED && shape == T->hlut.star_unr) return T->stars;
+    return T->tj[shape];
+}
 
 // Running sums of admissible level-k totals for one unrooted shape (or all, shape < 0).
 scc_status table_prefix(scc_table *T, int shape, const u128 **pre, u128 *total);

@@ -232,6 +232,24 @@ void build_lut(int k, DevLut *L)
         }
     L->num_unr = g_unr_n[k];
     for (int q = 0; q < S.r[k]; q++) L->unr_of[q] = (uint8_t)g_unr_of[k][q];
+    // designated (balanced) rootings and their orbits
+    uint32_t star = 0;
+    for (int i = 0; i < k - 1; i++) star = (star << 2) | 2u;
+    L->star_unr = k >= 2 ? g_unr_of[k][rank_of(k, star)] : 0;
+    for (int j = 0; j < 32; j++) { L->bal_rank[j] = -1; L->bal_orbit[j] = 0; }
+    for (int q = 0; k >= 4 && q < S.r[k]; q++) {
+        const int hpp = k - L->dec_hp[k][q];
+        if (hpp < 2 || hpp > k - 2) continue;
+        int8_t &b = L->bal_rank[g_unr_of[k][q]];
+        if (b < 0 || q < b) b = (int8_t)q;
+    }
+    for (int j = 0; j < L->num_unr; j++) {
+        if (L->bal_rank[j] < 0) continue;
+        L->designated[L->bal_rank[j]] = 1;
+        uint32_t adj[16];
+        const int nn = parse(S.bits[k][L->bal_rank[j]], 2 * (k - 1), adj);
+        for (int x = 0; x < nn; x++) L->bal_orbit[j] += rank_of(k, canon(adj, x, -1).bits) == L->bal_rank[j];
+    }
     int cnt[SCC_KMAX + 1] = {0};
     for (uint32_t m = 0; m < (1u << (k - 1)); m++) {
         int p = __builtin_popcount(m);
@@ -278,6 +296,24 @@ scc_status set_error(scc_status st, const char *fmt, ...)
 extern "C" const char *scc_last_error(void) { return t_err; }
 extern "C" const char *scc_version(void) { return "scc-mi355x 0.1 (gfx950)"; }
 extern "C" int scc_num_unrooted(int k) { return (k >= 1 && k <= SCC_KMAX) ? unrooted_count(k) : -1; }
+
+extern "C" int scc_balanced_rooting(int k, int j, int *orbit)
+{
+    if (orbit) *orbit = 0;
+    if (k < 1 || k > SCC_KMAX || j < 0 || j >= unrooted_count(k)) return -1;
+    DevLut L;
+    build_lut(k, &L);
+    if (orbit) *orbit = L.bal_orbit[j];
+    return L.bal_rank[j];
+}
+
+extern "C" int scc_star_shape(int k)
+{
+    if (k < 2 || k > SCC_KMAX) return -1;
+    DevLut L;
+    build_lut(k, &L);
+    return L.star_unr;
+}
 
 void *DevMem::get(size_t bytes)
 {
