@@ -101,6 +101,41 @@ def measured_traffic(name):
         return None
 
 
+def round_skipping(scc, dg, dcol, k, ns, sseed, verts, par, zinfo, zbuild_ms):
+    """The same graph and colouring with round skipping (balanced rooting, level
+    k-1 skipped, stars sampled directly): build, shape-first uniform sampling and
+    star sampling, next to the zero-rooting build of the plain step."""
+    import torch
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    torch.cuda.synchronize()
+    ev[0].record()
+    bt = scc.Table(dg, dcol, k, rooting=scc.ROOT_BALANCED)
+    ev[1].record()
+    bt.sample(ns, seed=sseed, out=(verts, par))
+    ev[2].record()
+    bt.sample(ns, seed=sseed, shape=scc.star_shape(k), out=(verts, par))
+    ev[3].record()
+    torch.cuda.synchronize()
+    bi = bt.info()
+    star = scc.star_shape(k)
+    u = lambda x: int(x[0]) | (int(x[1]) << 64)
+    match = all(u(bi.tj[j]) == (0 if j == star else u(zinfo.tj[j])) for j in range(bi.num_unrooted))
+    b_ms = ev[0].elapsed_time(ev[1])
+    out = {"build_s": b_ms / 1e3, "zero_rooting_build_s": zbuild_ms / 1e3,
+           "build_saving": 1 - b_ms / zbuild_ms if zbuild_ms > 0 else None,
+           "table_bytes": int(bi.bytes), "zero_rooting_table_bytes": int(zinfo.bytes),
+           "bytes_saving": 1 - bi.bytes / zinfo.bytes if zinfo.bytes else None,
+           "level_ms": [round(bi.level_ms[h], 3) for h in range(1, k + 1)],
+           "sample_per_s": ns / (ev[1].elapsed_time(ev[2]) / 1e3),
+           "star_sample_per_s": ns / (ev[2].elapsed_time(ev[3]) / 1e3),
+           "t_non_star": str(u(bi.t)), "stars": str(u(bi.stars)),
+           "non_star_totals_equal_zero_rooting": match}
+    del bt
+    print(f"# round skipping: build {b_ms:.1f} ms vs {zbuild_ms:.1f} ms, {bi.bytes / 1e9:.2f} GB vs "
+          f"{zinfo.bytes / 1e9:.2f} GB, totals match {match}", file=sys.stderr, flush=True)
+    return out
+
+
 def batching_instances():
     """16 colourings of a Chung-Lu graph (n=5e5, m~5e6, exponent 2.2, w_max=2.5e4) and 32
     uneven ER/BA graphs (n log-uniform in [1e3, 1e5], mean degree 4 + (i mod 17)); k = 5 + (i mod 3)."""
@@ -436,6 +471,7 @@ def main():
                "classes_hit": int((r["hits"] > 0).sum()), "classes_covered": int((r["hits"] >= A["cbar"]).sum()),
                "shapes_used": sorted(set(int(x) for x in r["round_shapes"]))}
         print(f"# AGS: {ags['rounds']} rounds, {drawn} samples in {t_ags:.2f} s", file=sys.stderr, flush=True)
+    rs = round_skipping(scc, dg, dcol, k, ns, sseed, verts, par, info, build_ms)
     out = {
         "metric": "DP table build s & colorful-treelet samples/sec, batched/served vs plain",
         "value": ns / dt,
@@ -456,6 +492,7 @@ def main():
     }
     if ags is not None:
         out["ags"] = ags
+    out["round_skipping"] = rs
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, g.m, ns)
     print(json.dumps(out), flush=True)

@@ -427,6 +427,7 @@ __device__ inline void combine_vertex(const CombineArgs &A, int64_t v, uint64_t 
     const int plo = A.bal ? 2 : 1, phi = A.bal ? h - 2 : h - 1;
     u128 U = 0;
     for (int hp = plo; hp <= phi; hp++) {
+        if (!A.M[h - hp]) continue;   // sums not built: no evaluated term uses them
         u128 Nv = hp == 1 ? (u128)1 : h_N<SLOTS>(A.lev[hp], src_handle<SLOTS>(A.lev[hp], v));
         U = sat_add(U, sat_mul(Nv, A.M[h - hp][v]));
     }
@@ -434,12 +435,19 @@ __device__ inline void combine_vertex(const CombineArgs &A, int64_t v, uint64_t 
         if (lane == 0) { atomicOr(A.err, 1); A.meta[v] = 0; A.Nout[v] = 0; }
         return;
     }
-    const bool wide = hi64(U) != 0;
+    // owide: some output or partial sum may reach 2^64 (accumulate and store 128
+    // bits); wide: some input has high words too (stage them). Below 2^64 every
+    // product and partial sum fits in the low words (U bounds them).
+    const bool owide = hi64(U) != 0;
+    bool wide = false;
+    if (owide) {
+        for (int hp = 2; hp <= phi; hp++) wide |= h_wide<SLOTS>(src_handle<SLOTS>(A.lev[hp], v));
+        for (int hs = 1; hs <= phi; hs++) wide |= A.M[hs] && hi64(A.M[hs][v]) != 0;
+    }
     if (wide && !hi_area) {
         if (lane == 0) wide_list[atomicAdd(wide_count, 1)] = (int)v;
         return;
     }
-    // below 2^64 every product and partial sum fits in the low words (U bounds them)
     const int XT = L.xoff[h];
     uint64_t *Xlo = lo_area, *Slo = lo_area + XT;
     uint64_t *Xhi = hi_area, *Shi = hi_area + XT;
@@ -459,6 +467,7 @@ __device__ inline void combine_vertex(const CombineArgs &A, int64_t v, uint64_t 
         }
     }
     for (int hs = 1; hs <= phi; hs++) {
+        if (!A.Slo[hs]) continue;
         const int ws = L.WS[hs];
         const uint64_t *gl = A.Slo[hs] + (size_t)v * ws;
         const bool sw = hi64(A.M[hs][v]) != 0;
@@ -478,7 +487,7 @@ __device__ inline void combine_vertex(const CombineArgs &A, int64_t v, uint64_t 
     u128 nsum = 0;
     uint16_t *sk = A.slot_key + (size_t)v * A.W;
     uint64_t *sl = A.slot_lo + (size_t)v * A.W;
-    uint64_t *sh = wide ? A.slot_hi + (size_t)v * A.W : nullptr;
+    uint64_t *sh = owide ? A.slot_hi + (size_t)v * A.W : nullptr;
     for (int o0 = 0; o0 < Wh; o0 += WAVE) {
         const int o = o0 + lane;
         u128 val = 0;
@@ -494,11 +503,14 @@ __device__ inline void combine_vertex(const CombineArgs &A, int64_t v, uint64_t 
             for (int i = 1; i <= hp - 1; i++) nsplit = nsplit * (h - 1 - (hp - 1) + i) / i;
             const int tb = L.term_base[h][hp] + dc * nsplit;
             u128 acc = 0;
-            if (!wide) {
+            if (!owide) {
                 uint64_t a64 = 0;
                 for (int i = 0; i < nsplit; i++)
                     a64 += Xlo[xb + L.term_x[tb + i]] * Slo[sb + L.term_s[tb + i]];
                 acc = a64;
+            } else if (!wide) {
+                for (int i = 0; i < nsplit; i++)
+                    acc += (u128)Xlo[xb + L.term_x[tb + i]] * Slo[sb + L.term_s[tb + i]];
             } else {
                 for (int i = 0; i < nsplit; i++) {
                     const int xi = xb + L.term_x[tb + i], si = sb + L.term_s[tb + i];
@@ -517,14 +529,14 @@ __device__ inline void combine_vertex(const CombineArgs &A, int64_t v, uint64_t 
             const uint32_t C = expand_in(D, cv) | (1u << cv);
             sk[pos] = (uint16_t)(L.off[h] + t * L.bk[h] + L.colex_k[C]);
             sl[pos] = lo64(val);
-            if (wide) sh[pos] = hi64(val);
+            if (owide) sh[pos] = hi64(val);
             nsum += val;
         }
         cnt += (uint32_t)__popcll(bal);
     }
     nsum = wave_sum128(nsum);
     if (lane == 0) {
-        A.meta[v] = cnt | (wide ? 0x80000000u : 0u);
+        A.meta[v] = cnt | (owide ? 0x80000000u : 0u);
         A.Nout[v] = nsum;
     }
 }
@@ -985,8 +997,13 @@ static scc_status build_levels(scc_table *T)
     hipStream_t st = T->stream;
     GraphView g{n, T->row_ptr, T->col_idx, T->colors};
     const bool zero = T->rooting == SCC_ROOT_ZERO;
-    // round skipping (Sec. 3.5): level k-1 and its neighbour sums are not built
+    // round skipping (Sec. 3.5): level k-1 is not built, and of the neighbour sums
+    // above level k-3 only those the designated decompositions use (|T''| = hs)
     const bool bal = T->rooting == SCC_ROOT_BALANCED;
+    bool s_need[SCC_KMAX + 1];
+    for (int hs = 0; hs <= SCC_KMAX; hs++) s_need[hs] = !bal || hs <= k - 3;
+    for (int q = 0; bal && q < HL.r[k]; q++)
+        if (HL.designated[q]) s_need[k - HL.dec_hp[k][q]] = true;
     const int hub_degree = T->hub_degree;
 
     int *err = (int *)T->mem.get(16);
@@ -1086,7 +1103,7 @@ static scc_status build_levels(scc_table *T)
         HIP_TRY(hipEventRecord(ev[h][0], st));
         HIP_TRY(hipMemsetAsync(err, 0, 16, st));   // [0] flags, [1] wide vertices
         const int hs = h - 1;   // neighbour sums needed now
-        if (hs >= 2 && !(bal && hs == k - 1)) {
+        if (hs >= 2 && s_need[hs]) {
             TableSums &Sx = T->S[hs];
             const size_t sz = (size_t)n * HL.WS[hs] * 8;
             Sx.M = (u128 *)T->alloc((size_t)n * 16 + 16);
@@ -1171,7 +1188,7 @@ static scc_status build_levels(scc_table *T)
         HIP_TRY(hipEventElapsedTime(&ms, ev[h][0], ev[h][1]));
         T->level_ms[h] = ms;
         if (h == 1) T->gather_ms[1] = ms;
-        if (h >= 2 && h < k && !(bal && h == k - 1)) {
+        if (h >= 2 && h < k && s_need[h]) {
             HIP_TRY(hipEventElapsedTime(&ms, gev[h][0], gev[h][1]));
             T->gather_ms[h] = ms;
         }
@@ -1189,7 +1206,7 @@ static scc_status gather_stats(scc_table *T)
     unsigned long long *acc = (unsigned long long *)T->mem.get(64);
     if (!acc) return set_error(SCC_ENOMEM, "stats");
     for (int hs = 2; hs < T->k; hs++) {
-        if (T->rooting == SCC_ROOT_BALANCED && hs == T->k - 1) { T->gather_bytes[hs] = 0; continue; }
+        if (!T->S[hs].M) { T->gather_bytes[hs] = 0; continue; }   // not built (round skipping)
         HIP_TRY(hipMemsetAsync(acc, 0, 8, st));
         const bool rz = T->rooting == SCC_ROOT_ZERO && hs == T->k - 1;
         if (n) hipLaunchKernelGGL(k_gather_bytes, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g,

@@ -365,7 +365,6 @@ struct HubPreArgs {
     GraphView g;
     const DevLut *L;
     int k, nkeys, zero;
-    int bal;                     // round skipping: level k-1 is not built
     LevelView lev[SCC_KMAX + 1];
     const u128 *M[SCC_KMAX + 1];
     const int16_t *key_sidx;
@@ -444,7 +443,7 @@ __global__ void __launch_bounds__(256) k_hubpre_chunk(HubPreArgs A)
     const int64_t x = A.hubs[q];
     const int cx = A.g.colors[x];
     if (A.zero && hpp == A.k - 1 && cx != 0) return;   // no block: x is never a root there
-    if (A.bal && hpp == A.k - 1) return;                // no block: the level is skipped
+    if (!A.M[hpp]) return;                              // no block: sums not built
     const DevLut &L = *A.L;
     const int WS = L.WS[hpp];
     const int64_t ra = A.hub_rows[2 * q], rb = A.hub_rows[2 * q + 1], d = rb - ra;
@@ -497,7 +496,7 @@ __global__ void __launch_bounds__(256) k_hubpre_fix(HubPreArgs A)
     const int hpp = blockIdx.y + 1;
     const int64_t x = A.hubs[q];
     if (A.zero && hpp == A.k - 1 && A.g.colors[x] != 0) return;
-    if (A.bal && hpp == A.k - 1) return;
+    if (!A.M[hpp]) return;
     const DevLut &L = *A.L;
     const int WS = L.WS[hpp];
     const int64_t ra = A.hub_rows[2 * q], rb = A.hub_rows[2 * q + 1], d = rb - ra;
@@ -604,7 +603,6 @@ static scc_status ensure_hub_prefix(scc_table *T)
     HubPreArgs A{};
     A.g = GraphView{T->n, T->row_ptr, T->col_idx, T->colors};
     A.L = T->dlut; A.k = k; A.nkeys = HL.nkeys; A.zero = T->rooting == SCC_ROOT_ZERO;
-    A.bal = T->rooting == SCC_ROOT_BALANCED;
     for (int h = 2; h <= k; h++) A.lev[h] = lview(T->lev[h]);
     for (int h = 1; h < k; h++) A.M[h] = T->S[h].M;
     A.key_sidx = T->key_sidx;
@@ -627,7 +625,7 @@ static scc_status ensure_hub_prefix(scc_table *T)
     const bool zero = T->rooting == SCC_ROOT_ZERO;
     auto block_words = [&](int i, int h) -> int64_t {
         if (zero && h == k - 1 && info[(size_t)i * (SCC_KMAX + 2)] != 0) return 0;   // never a root there
-        if (A.bal && h == k - 1) return 0;                                             // level not built
+        if (!T->S[h].M) return 0;                                                      // sums not built
         const int64_t w = (int64_t)HL.WS[h] * ((deg(i) + HUB_BLOCK - 1) / HUB_BLOCK);
         return info[(size_t)i * (SCC_KMAX + 2) + h] ? 2 * w : w;
     };
