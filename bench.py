@@ -31,6 +31,8 @@ def parse():
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--samples", type=int, default=None, help="samples per step (default: the workload's)")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-round-skipping", action="store_true",
+                   help="leave out the extra round-skipping build (counter runs: only the plain step's kernels)")
     p.add_argument("--small", action="store_true", help="small graph (for quick checks)")
     p.add_argument("--workload", default="mid", choices=["mid", "large", "batching", "serving"],
                    help="mid (default) / large: the plain method on the mid / large graph; batching: 48 "
@@ -471,7 +473,7 @@ def main():
                "classes_hit": int((r["hits"] > 0).sum()), "classes_covered": int((r["hits"] >= A["cbar"]).sum()),
                "shapes_used": sorted(set(int(x) for x in r["round_shapes"]))}
         print(f"# AGS: {ags['rounds']} rounds, {drawn} samples in {t_ags:.2f} s", file=sys.stderr, flush=True)
-    rs = round_skipping(scc, dg, dcol, k, ns, sseed, verts, par, info, build_ms)
+    rs = None if a.no_round_skipping else round_skipping(scc, dg, dcol, k, ns, sseed, verts, par, info, build_ms)
     out = {
         "metric": "DP table build s & colorful-treelet samples/sec, batched/served vs plain",
         "value": ns / dt,
@@ -492,7 +494,8 @@ def main():
     }
     if ags is not None:
         out["ags"] = ags
-    out["round_skipping"] = rs
+    if rs is not None:
+        out["round_skipping"] = rs
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, g.m, ns)
     print(json.dumps(out), flush=True)
