@@ -489,7 +489,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_unit": f"bytes per step ({k - 2} gather launches), FETCH_SIZE x2.0 + WRITE_SIZE x1.0",
-                     "kernel": "k_gather + k_gather_hub (neighbour-record gather of the DP, levels 2..k-1)",
+                     "kernel": "k_gather_group + k_gather_list + k_gather_hub + k_hub_prepare (neighbour-record gather of the DP, levels 2..k-1)",
                      "bytes_per_step": g_bytes, "ms_per_step": g_ms},
     }
     if ags is not None:

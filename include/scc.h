@@ -93,7 +93,14 @@ typedef struct {
     int hub_degree;            /* gather rows of at least this degree are split over
                                   many workgroups; 0 = library default */
     int validate;              /* nonzero: check the CSR and colours on the device first */
+    int gather_mode;           /* neighbour-sum gather of the rows below the hub threshold:
+                                  SCC_GATHER_AUTO (0) chooses per level from the level's
+                                  record sizes; SCC_GATHER_GROUPED: rows of at most 64
+                                  neighbours several to a wave; SCC_GATHER_ROW: one
+                                  row per wave. Results are identical in every mode. */
 } scc_build_opts;
+
+enum { SCC_GATHER_AUTO = 0, SCC_GATHER_GROUPED = 1, SCC_GATHER_ROW = 2 };
 
 /*
  * scc_build_table -- the build-up phase (Sec. 2.1, Eq. (1)).

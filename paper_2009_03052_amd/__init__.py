@@ -24,6 +24,7 @@ LIB_PATH = os.path.join(_HERE, "libscc.so")
 
 OK, EINVAL, ENOMEM, EOVERFLOW, EDEVICE, EEMPTY, EBUSY, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
 ROOT_ZERO, ROOT_ALL, ROOT_BALANCED = 0, 1, 2
+GATHER_AUTO, GATHER_GROUPED, GATHER_ROW = 0, 1, 2
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with paper_2009_03052_amd/build.py "
@@ -45,7 +46,8 @@ class _Csr(C.Structure):
 
 class _BuildOpts(C.Structure):
     _fields_ = [("rooting", C.c_int), ("max_bits", C.c_int), ("stream", C.c_void_p),
-                ("alloc", C.POINTER(_Allocator)), ("hub_degree", C.c_int), ("validate", C.c_int)]
+                ("alloc", C.POINTER(_Allocator)), ("hub_degree", C.c_int), ("validate", C.c_int),
+                ("gather_mode", C.c_int)]
 
 
 class _Instance(C.Structure):
@@ -211,7 +213,8 @@ class Table:
     """The count table of one graph and colouring (``scc_build_table``)."""
 
     def __init__(self, graph: DeviceGraph, colors, k: int, rooting: int = ROOT_ZERO, max_bits: int = 128,
-                 validate: bool = False, stream=None, use_torch_allocator: bool = True, hub_degree: int = 0):
+                 validate: bool = False, stream=None, use_torch_allocator: bool = True, hub_degree: int = 0,
+                 gather_mode: int = 0):
         self.graph = graph
         self.colors = torch.as_tensor(np.asarray(colors) if not torch.is_tensor(colors) else colors,
                                       dtype=torch.uint8).to(graph.row_ptr.device).contiguous()
@@ -220,7 +223,7 @@ class Table:
         csr = _Csr(graph.n, graph.nnz, graph.row_ptr.data_ptr(), graph.col_idx.data_ptr())
         opts = _BuildOpts(rooting, max_bits, _stream_ptr(stream),
                           C.pointer(TORCH_ALLOCATOR) if use_torch_allocator else None, hub_degree,
-                          1 if validate else 0)
+                          1 if validate else 0, gather_mode)
         self._h = _P()
         _check(_lib.scc_build_table(C.byref(csr), _ptr(self.colors), k, C.byref(opts), C.byref(self._h)))
 

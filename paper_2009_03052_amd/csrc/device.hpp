@@ -88,6 +88,19 @@ __device__ inline u128 wave_incl_scan128(u128 x)
     return x;
 }
 
+// inclusive scan that saturates at 2^128 - 1 instead of wrapping
+__device__ inline u128 wave_incl_satscan128(u128 x)
+{
+    const int lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        uint64_t l = (uint64_t)__shfl_up((unsigned long long)lo64(x), d, WAVE);
+        uint64_t h = (uint64_t)__shfl_up((unsigned long long)hi64(x), d, WAVE);
+        if (lane >= d) x = sat_add(x, mk128(l, h));
+    }
+    return x;
+}
+
 __device__ inline uint32_t wave_incl_scan32(uint32_t x)
 {
     const int lane = lane_id();

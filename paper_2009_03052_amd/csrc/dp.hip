@@ -157,11 +157,13 @@ struct GatherArgs {
     const int32_t *chunk_v;        // hub chunks: vertex and first edge
     const int64_t *chunk_e;
     int *err;
+    const DevLut *Lut;             // grouped rows: the level's (rank, colour set) per key
+    int hs, bk1;                   // gathered level and binom(k-1, hs)
 };
 
 // most keys on one level: r_6 C(8, 6) = 560 at k = 8
 constexpr int GATHER_MAX_KEYS = 576;
-inline size_t gather_lds(int WS) { return (size_t)2 * WS * 8 + GATHER_MAX_KEYS * 2; }
+__host__ __device__ inline size_t gather_lds(int WS) { return (size_t)2 * WS * 8 + GATHER_MAX_KEYS * 2; }
 
 // Adds the level-hs entries of neighbours col_idx[a..b) of v into the LDS sums
 // and returns (in every lane) the saturating sum of those neighbours' level
@@ -279,11 +281,182 @@ __device__ inline void gather_vertex(const GatherArgs &A, int64_t v, uint64_t *s
     if (lane == 0) A.M[v] = m;
 }
 
+// one row per wave, every row below the hub threshold
 __global__ void __launch_bounds__(WAVE) k_gather(GatherArgs A)
 {
     extern __shared__ uint64_t sm[];
     for (int64_t v = blockIdx.x; v < A.g.n; v += gridDim.x) {
         gather_vertex<false>(A, v, sm);
+        __syncthreads();
+    }
+}
+
+// rows from a list (the rows between the grouped ones and the hubs)
+__global__ void __launch_bounds__(WAVE) k_gather_list(GatherArgs A, const int32_t *rows)
+{
+    extern __shared__ uint64_t sm[];
+    gather_vertex<false>(A, rows[blockIdx.x], sm);
+}
+
+// ---------------------------------------------------------------------------
+// Low-degree rows in groups: one wave gathers G consecutive vertices of degree
+// at most GROUP_DEG (and not above the hub threshold), so that the neighbours
+// and record entries of several rows fill the lanes; most rows of a
+// heavy-tailed graph have a handful of neighbours. The sums of the group's
+// rows accumulate in G rows of LDS; the slot of a key at a colour-c vertex is
+// rank(T'') binom(k-1, hs) + colex of C'' without c, from a per-level table of
+// (rank, colour set) and the colex table, shared by every colour.
+// ---------------------------------------------------------------------------
+constexpr int GROUP_DEG = 64;
+constexpr int GROUP_MAX = 8;
+// SCC_GATHER_AUTO groups a level when at least half the rows have at most
+// GROUP_LOW_DEG neighbours and the level's records average at most GROUP_WORDS
+// pool words (about 32 entries): then a wave per row leaves most lanes idle
+constexpr int GROUP_LOW_DEG = 8;
+constexpr int GROUP_WORDS = 40;
+
+inline int group_size(int WS) { return std::max(2, std::min(GROUP_MAX, 512 / std::max(1, WS))); }
+inline size_t group_lds(int WS, int G)
+{
+    return (size_t)G * WS * 8 + (gather_lds(WS) + 7) / 8 * 8 + GATHER_MAX_KEYS * 2 + 128;
+}
+
+template <bool SLOTS>
+__device__ inline void gather_group(const GatherArgs &A, int64_t v0, int G, uint64_t *acc, const uint16_t *kinfo,
+                                    const uint8_t *colex, uint64_t *wsm)
+{
+    const int lane = threadIdx.x;
+    const int WS = A.WS;
+    const int nv = (int)min((int64_t)G, A.g.n - v0);
+    const int64_t small = min((int64_t)GROUP_DEG, (int64_t)A.hub_degree);
+    // lane j < nv describes vertex v0 + j
+    int64_t ra = 0;
+    uint32_t dj = 0;
+    int cvj = 0;
+    bool mine = false;
+    if (lane < nv) {
+        const int64_t v = v0 + lane;
+        ra = A.g.row_ptr[v];
+        const int64_t d = A.g.row_ptr[v + 1] - ra;
+        cvj = A.g.colors[v];
+        mine = d <= small && !(A.rows_zero && cvj != 0);
+        dj = mine ? (uint32_t)d : 0u;
+    }
+    const uint64_t mine_mask = __ballot(mine);
+    if (!mine_mask) return;
+    const uint32_t dincl = wave_incl_scan32(dj);
+    const uint32_t E = __shfl(dincl, WAVE - 1, WAVE);
+    for (int i = lane; i < nv * WS; i += WAVE) acc[i] = 0;
+    __syncthreads();
+    u128 mj = 0;   // lane j < nv: bound of vertex v0 + j (sum of its neighbours' level sums)
+    for (uint32_t p0 = 0; p0 < E; p0 += WAVE) {
+        const uint32_t p = p0 + lane;
+        // slot of edge position p: the number of slots whose inclusive degree is <= p
+        int js = 0;
+#pragma unroll
+        for (int step = GROUP_MAX / 2; step >= 1; step >>= 1) {
+            const uint32_t x = __shfl(dincl, js + step - 1, WAVE);
+            if (x <= p) js += step;
+        }
+        const uint32_t dincl_s = __shfl(dincl, js, WAVE);
+        const uint32_t d_s = __shfl(dj, js, WAVE);
+        const int64_t ra_s = (int64_t)shfl64((uint64_t)ra, js);
+        uint64_t hd = SLOTS ? ~0ull << 32 : 0ull;
+        uint32_t len = 0;
+        u128 nval = 0;
+        if (p < E) {
+            hd = src_handle<SLOTS>(A.L, A.g.col_idx[ra_s + (int64_t)(p - (dincl_s - d_s))]);
+            len = h_len<SLOTS>(hd);
+            if (len) nval = h_N<SLOTS>(A.L, hd);
+        }
+        // each slot's lanes are contiguous: its bound grows by their segment of the scan
+        const u128 incl_n = wave_incl_satscan128(nval);
+        const int sa = (int)max(dincl - dj, p0) - (int)p0;
+        const int sb = (int)min(dincl, p0 + WAVE) - (int)p0;
+        const u128 before = shfl128(incl_n, max(sa - 1, 0));
+        const u128 last = shfl128(incl_n, max(sb - 1, 0));
+        if (lane < nv && sb > sa) {
+            const u128 seg = last == ~(u128)0 ? ~(u128)0 : last - (sa > 0 ? before : (u128)0);
+            mj = sat_add(mj, seg);
+        }
+        // the entries of these neighbours, flattened, 4 per lane per round
+        const uint32_t incl = wave_incl_scan32(len);
+        const uint32_t total = __shfl(incl, WAVE - 1, WAVE);
+        for (uint32_t q0 = 0; q0 < total; q0 += 4 * WAVE) {
+            uint32_t key[4];
+            uint64_t cl[4];
+            int slot[4], cv[4];
+            bool ok[4];
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const uint32_t pe = q0 + q * WAVE + lane;
+                int j = 0;
+#pragma unroll
+                for (int step = WAVE / 2; step >= 1; step >>= 1) {
+                    const uint32_t x = __shfl(incl, j + step - 1, WAVE);
+                    if (x <= pe) j += step;
+                }
+                if (j > WAVE - 1) j = WAVE - 1;
+                const uint32_t incl_j = __shfl(incl, j, WAVE);
+                const uint64_t hd_j = shfl64(hd, j);
+                slot[q] = __shfl(js, j, WAVE);
+                cv[q] = __shfl(cvj, slot[q], WAVE);
+                ok[q] = pe < total;
+                key[q] = 0;
+                cl[q] = 0;
+                if (ok[q]) {
+                    const RecView<SLOTS> r = h_rec<SLOTS>(A.L, hd_j);
+                    const uint32_t ei = pe - (incl_j - r.len);
+                    key[q] = r.key[ei];
+                    cl[q] = r.lo[ei];
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                if (!ok[q]) continue;
+                const uint32_t km = kinfo[key[q] - A.key_lo];
+                const uint32_t C = km & 0xffu;
+                if (C >> cv[q] & 1u) continue;   // a colour set holding c_v is not summed
+                const int s = (int)(km >> 8) * A.bk1 + colex[compress_out(C, cv[q])];
+                atomicAdd((unsigned long long *)&acc[slot[q] * WS + s], (unsigned long long)cl[q]);
+            }
+        }
+    }
+    __syncthreads();
+    // rows whose bound reaches 2^64 are redone alone with 128-bit sums
+    const uint64_t wide_mask = __ballot(lane < nv && mine && hi64(mj) != 0);
+    uint64_t *Slo = A.Slo + (size_t)v0 * WS;
+    for (int i = lane; i < nv * WS; i += WAVE) {
+        const int j = i / WS;
+        if ((mine_mask >> j & 1u) && !(wide_mask >> j & 1u)) Slo[i] = acc[i];
+    }
+    if (lane < nv && mine && !(wide_mask >> lane & 1u)) A.M[v0 + lane] = mj;
+    for (uint64_t wm = wide_mask; wm; wm &= wm - 1) {
+        __syncthreads();
+        gather_vertex<SLOTS>(A, v0 + (__ffsll((long long)wm) - 1), wsm);
+    }
+}
+
+// LDS: G * WS sums, the single-row area for 128-bit rows, the key table, the colex table
+__global__ void __launch_bounds__(WAVE) k_gather_group(GatherArgs A, int G)
+{
+    extern __shared__ uint64_t sm[];
+    const int WS = A.WS;
+    uint64_t *acc = sm;
+    uint64_t *wsm = acc + (size_t)G * WS;
+    uint16_t *kinfo = (uint16_t *)(wsm + (gather_lds(WS) + 7) / 8);
+    uint8_t *colex = (uint8_t *)(kinfo + GATHER_MAX_KEYS);
+    const DevLut &L = *A.Lut;
+    const int bk = L.bk[A.hs];
+    for (int i = threadIdx.x; i < A.key_n; i += WAVE) {
+        const int t = i / bk;
+        kinfo[i] = (uint16_t)((t << 8) | L.mask_k[A.hs][i - t * bk]);
+    }
+    for (int i = threadIdx.x; i < 128; i += WAVE) colex[i] = L.colex_s[i];
+    __syncthreads();
+    const int64_t ng = (A.g.n + G - 1) / G;
+    for (int64_t gi = blockIdx.x; gi < ng; gi += gridDim.x) {
+        gather_group<false>(A, gi * G, G, acc, kinfo, colex, wsm);
         __syncthreads();
     }
 }
@@ -382,6 +555,19 @@ __global__ void k_hub_list(GraphView g, int hub_degree, int32_t *hubs, int *coun
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= g.n) return;
     if (g.row_ptr[v + 1] - g.row_ptr[v] > hub_degree) hubs[atomicAdd(count, 1)] = (int32_t)v;
+}
+
+// hub rows (count[0]), the rows between the grouped ones and the hubs
+// (count[1]) and the number of rows of at most GROUP_LOW_DEG neighbours (count[2])
+__global__ void k_row_lists(GraphView g, int hub_degree, int32_t *hubs, int32_t *mids, int *count)
+{
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t d = v < g.n ? g.row_ptr[v + 1] - g.row_ptr[v] : 0;
+    const uint64_t low = __ballot(v < g.n && d <= GROUP_LOW_DEG);
+    if (lane_id() == 0 && low) atomicAdd(&count[2], __popcll(low));
+    if (v >= g.n) return;
+    if (d > hub_degree) hubs[atomicAdd(&count[0], 1)] = (int32_t)v;
+    else if (d > GROUP_DEG) mids[atomicAdd(&count[1], 1)] = (int32_t)v;
 }
 
 // ---------------------------------------------------------------------------
@@ -1033,19 +1219,27 @@ static scc_status build_levels(scc_table *T)
             HIP_TRY(hipEventCreate(&gev[h][j]));
         }
 
-    // hub rows and their neighbour chunks (the same for every level)
-    int nhub = 0;
-    int32_t *hubs = nullptr;
+    // hub rows and their neighbour chunks, and the rows between the grouped
+    // low-degree ones and the hubs (the same for every level)
+    int nhub = 0, nmid = 0;
+    int64_t low_rows = 0;
+    int32_t *hubs = nullptr, *mids = nullptr;
     int32_t *chunk_v = nullptr;
     int64_t *chunk_e = nullptr;
     int64_t nchunk = 0;
     if (n) {
         hubs = (int32_t *)get((size_t)n * 4 + 8);
-        if (!hubs) return set_error(SCC_ENOMEM, "hub list");
+        mids = (int32_t *)get((size_t)n * 4 + 8);
+        if (!hubs || !mids) return set_error(SCC_ENOMEM, "row lists");
         HIP_TRY(hipMemsetAsync(err, 0, 16, st));
-        hipLaunchKernelGGL(k_hub_list, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g, hub_degree, hubs, err);
-        HIP_TRY(hipMemcpyAsync(&nhub, err, 4, hipMemcpyDeviceToHost, st));
+        hipLaunchKernelGGL(k_row_lists, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g, hub_degree, hubs, mids,
+                           err);
+        int cnt[3] = {0, 0, 0};
+        HIP_TRY(hipMemcpyAsync(cnt, err, 12, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
+        nhub = cnt[0];
+        nmid = cnt[1];
+        low_rows = cnt[2];
     }
     if (nhub) {
         std::vector<int32_t> hh(nhub);
@@ -1116,13 +1310,28 @@ static scc_status build_levels(scc_table *T)
             G.hub_degree = hub_degree;
             G.L = packed_src(T->lev[hs]); G.M = Sx.M; G.key_sidx = T->key_sidx; G.Slo = Sx.lo; G.Shi = Sx.hi;
             G.chunk_v = chunk_v; G.chunk_e = chunk_e; G.err = err;
+            G.Lut = T->dlut; G.hs = hs; G.bk1 = HL.bk1[hs];
             const size_t lds = gather_lds(HL.WS[hs]);
+            const int gs = group_size(HL.WS[hs]);
+            const int64_t ngroups = (n + gs - 1) / gs;
             HIP_TRY(hipEventRecord(gev[hs][0], st));
             if (nhub) {
                 hipLaunchKernelGGL(k_hub_prepare, dim3((unsigned)nhub), dim3(WAVE), 0, st, G, hubs);
                 hipLaunchKernelGGL(k_gather_hub, dim3((unsigned)nchunk), dim3(WAVE), lds, st, G, T->hub_chunk);
             }
-            if (n) hipLaunchKernelGGL(k_gather, dim3((unsigned)n), dim3(WAVE), lds, st, G);
+            // grouped low-degree rows pay off while records are short; long records
+            // fill a wave from a few neighbours already
+            const bool grouped = T->gather_mode == SCC_GATHER_GROUPED ||
+                                 (T->gather_mode == SCC_GATHER_AUTO && n && 2 * low_rows >= n &&
+                                  T->lev[hs].pool_words <= (uint64_t)GROUP_WORDS * n);
+            if (grouped) {
+                if (nmid) hipLaunchKernelGGL(k_gather_list, dim3((unsigned)nmid), dim3(WAVE), lds, st, G, mids);
+                if (n)
+                    hipLaunchKernelGGL(k_gather_group, dim3((unsigned)std::min<int64_t>(ngroups, 16384)), dim3(WAVE),
+                                       group_lds(HL.WS[hs], gs), st, G, gs);
+            } else if (n) {
+                hipLaunchKernelGGL(k_gather, dim3((unsigned)n), dim3(WAVE), lds, st, G);
+            }
             HIP_TRY(hipEventRecord(gev[hs][1], st));
         }
         // combine into slots: a vertex needing 128 bits waits for the second kernel
@@ -1378,6 +1587,11 @@ extern "C" scc_status scc_build_table(const scc_csr *g, const uint8_t *colors, i
     T->mem.alloc = o.alloc; T->mem.stream = T->stream;
     T->hub_degree = o.hub_degree > 0 ? o.hub_degree : 1024;
     T->hub_chunk = 256;
+    if (o.gather_mode < SCC_GATHER_AUTO || o.gather_mode > SCC_GATHER_ROW) {
+        delete T;
+        return set_error(SCC_EINVAL, "bad gather_mode %d", o.gather_mode);
+    }
+    T->gather_mode = o.gather_mode;
     build_lut(k, &T->hlut);
 
     scc_status s = SCC_OK;

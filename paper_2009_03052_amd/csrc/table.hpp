@@ -61,6 +61,7 @@ struct scc_table {
     int64_t bytes = 0;
     int hub_degree = 1024;           // rows above this degree are gathered in chunks
     int hub_chunk = 256;             // neighbours per chunk
+    int gather_mode = SCC_GATHER_AUTO;
     int nhub = 0;
     bool stats_done = false;
     std::vector<int32_t> hub_host;   // hub vertices (ascending) and their row bounds

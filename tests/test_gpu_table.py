@@ -37,28 +37,43 @@ def test_random_graphs_every_k(k, rooting, hub_degree):
         assert_tables_equal(gt, ot, k, f"{name} hub>{hub_degree}")
 
 
+@pytest.mark.parametrize("k", [3, 5, 7, 8])
+@pytest.mark.parametrize("gather_mode", [1, 2])
+def test_random_graphs_both_gather_modes(k, gather_mode):
+    # grouped low-degree rows (1) and one row per wave (2), hub rows forced too
+    for name, g in random_graphs(k):
+        colors = gg.colors(g.n, k, seed=19 * k + gather_mode)
+        for hub_degree in (0, 12):
+            gt, ot = build_pair(g, colors, k, hub_degree=hub_degree, gather_mode=gather_mode)
+            assert_tables_equal(gt, ot, k, f"{name} gather mode {gather_mode} hub>{hub_degree}")
+
+
 @pytest.mark.parametrize("hub_degree", [0, 40])
-def test_chung_lu_k6_multi_tile(hub_degree):
+@pytest.mark.parametrize("gather_mode", [0, 1, 2])
+def test_chung_lu_k6_multi_tile(hub_degree, gather_mode):
     g = gg.chung_lu(20000, 100000, 2.1, 2000, seed=9)
     colors = gg.colors(g.n, 6, seed=10)
-    gt, ot = build_pair(g, colors, 6, hub_degree=hub_degree)
+    gt, ot = build_pair(g, colors, 6, hub_degree=hub_degree, gather_mode=gather_mode)
     assert_tables_equal(gt, ot, 6, "cl20k")
 
 
-def test_chung_lu_k8():
+@pytest.mark.parametrize("gather_mode", [1, 2])
+def test_chung_lu_k8(gather_mode):
     g = gg.chung_lu(3000, 12000, 2.3, 300, seed=13)
     colors = gg.colors(g.n, 8, seed=14)
-    gt, ot = build_pair(g, colors, 8)
+    gt, ot = build_pair(g, colors, 8, gather_mode=gather_mode)
     assert_tables_equal(gt, ot, 8, "cl3k-k8")
 
 
-def test_counts_beyond_64_bits():
-    # a 6-star at a hub of degree 2^16 has about 1e22 copies (Sec. 3.2 footnote)
+@pytest.mark.parametrize("gather_mode", [1, 2])
+def test_counts_beyond_64_bits(gather_mode):
+    # a 6-star at a hub of degree 2^16 has about 1e22 copies (Sec. 3.2 footnote);
+    # the leaves' neighbour sums need 128 bits (grouped rows redo them alone)
     leaves = 1 << 16
     edges = [(0, i) for i in range(1, leaves + 1)] + [(i, i + 1) for i in range(1, 200)]
     g = gg.csr_from_edges(leaves + 1, np.array(edges, np.int64))
     colors = np.concatenate([[0], (np.arange(leaves) % 5) + 1]).astype(np.uint8)
-    gt, ot = build_pair(g, colors, 6)
+    gt, ot = build_pair(g, colors, 6, gather_mode=gather_mode)
     assert_tables_equal(gt, ot, 6, "wide star")
     t, _ = gt.totals()
     assert t > 2 ** 64
@@ -68,6 +83,20 @@ def test_counts_beyond_64_bits():
     with pytest.raises(S.SccError) as e:
         S.Table(S.DeviceGraph.from_graph(g), colors, 6, max_bits=64)
     assert e.value.status == S.EOVERFLOW
+
+
+@pytest.mark.parametrize("gather_mode", [1, 2])
+def test_low_degree_rows_with_128_bit_sums(gather_mode):
+    # a hub of 2^17 leaves at k = 7, all rootings: the hub's level-6 sum exceeds
+    # 2^64, so the leaves (rows of one or two neighbours, grouped in mode 1) need
+    # 128-bit neighbour sums at level 6 and are redone alone
+    leaves = 1 << 17
+    edges = [(0, i) for i in range(1, leaves + 1)] + [(i, i + 1) for i in range(1, 200)]
+    g = gg.csr_from_edges(leaves + 1, np.array(edges, np.int64))
+    colors = np.concatenate([[0], (np.arange(leaves) % 6) + 1]).astype(np.uint8)
+    gt, ot = build_pair(g, colors, 7, rooting=O.ROOT_ALL, gather_mode=gather_mode)
+    assert_tables_equal(gt, ot, 7, "hub k7")
+    assert gt.occ(0, -1) > 2 ** 64
 
 
 def test_degenerate_graphs():
@@ -98,6 +127,9 @@ def test_invalid_inputs():
     dg = S.DeviceGraph.from_graph(g)
     with pytest.raises(S.SccError) as e:
         S.Table(dg, np.zeros(20, np.uint8), 9)
+    assert e.value.status == S.EINVAL
+    with pytest.raises(S.SccError) as e:
+        S.Table(dg, gg.colors(20, 4, seed=2), 4, gather_mode=3)
     assert e.value.status == S.EINVAL
     bad_colors = gg.colors(20, 4, seed=2)
     bad_colors[3] = 4
