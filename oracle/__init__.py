@@ -75,6 +75,8 @@ def lib():
             "orc_occ": (C.c_int, [P, i64, C.c_int, P]),
             "orc_philox4x64": (None, [P, P, P]),
             "orc_uniform_below": (C.c_int, [u64, u64, u64, u64, u64, u32, P]),
+            "orc_color_biased": (C.c_int, [i64, C.c_int, u32, u64, u64, P]),
+            "orc_colour_set_prob": (C.c_double, [C.c_int, u32, C.c_int, C.c_int]),
             "orc_sample": (C.c_int, [P, C.c_int, i64, u64, u64, u64, P, P]),
             "orc_canonical_code": (u32, [u32, C.c_int]),
             "orc_num_classes": (C.c_int, [C.c_int]),
@@ -271,6 +273,22 @@ def uniform_below(N: int, seed: int, stream: int, idx: int, draw: int) -> int:
     out = np.zeros(2, np.uint64)
     _check(lib().orc_uniform_below(N & (2**64 - 1), N >> 64, seed, stream, idx, draw, _p(out)))
     return _u128(out[0], out[1])
+
+
+def lambda_units(lam: float) -> int:
+    """lambda in units of 2^-32 (the biased colouring's exact parameter)"""
+    return int(round(lam * 2 ** 32))
+
+
+def color_biased(n: int, k: int, L: int, seed: int, stream: int = 0) -> np.ndarray:
+    """Biased colouring (Sec. 3.5): colour 0 w.p. 1 - (k-1) L/2^32, others L/2^32 each."""
+    out = np.zeros(max(n, 1), np.uint8)
+    _check(lib().orc_color_biased(n, k, L, seed, stream, _p(out)))
+    return out[:n]
+
+
+def colour_set_prob(k: int, L: int, j: int, has_zero: bool) -> float:
+    return float(lib().orc_colour_set_prob(k, L, j, 1 if has_zero else 0))
 
 
 # --------------------------------------------------------------------------

@@ -20,6 +20,8 @@
  *   - induced-graphlet classification by a minimum-over-permutations
  *     adjacency code, spanning-tree numbers (Sec. 4.4 "Graphlet manipulations")
  *   - AGS, adaptive graphlet sampling (Sec. 4.1, Algorithm AGS)
+ *   - round skipping: balanced rootings, direct star sampling (Sec. 3.5)
+ *   - biased colourings and the probability of a colour set (Sec. 3.5)
  *
  * Parity status: every function here is pinned by a CPU test (brute force on
  * tiny graphs, closed forms, printed constants, library cross-checks), except
@@ -703,6 +705,43 @@ int orc_uniform_below(uint64_t nlo, uint64_t nhi, uint64_t seed, uint64_t stream
     u128 r = uniform_below((u128)nhi << 64 | nlo, seed, stream, idx, draw);
     out[0] = (uint64_t)r; out[1] = (uint64_t)(r >> 64);
     return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Biased colouring (Sec. 3.5, "Biased coloring"): colour 0 with probability  */
+/* 1 - (k-1) lambda, each colour i in [1, k) with probability lambda. lambda  */
+/* is L / 2^32 for an integer L with (k-1) L <= 2^32, so the law is exact: the */
+/* colour of v is read off r = the low 32 bits of the first Philox output for */
+/* key (seed, stream) and counter (v, 0, 1, 0): colour 0 while               */
+/* r < 2^32 - (k-1) L, else 1 + (r - (2^32 - (k-1) L)) / L.                  */
+/* ------------------------------------------------------------------------- */
+int orc_color_biased(int64_t n, int k, uint32_t L, uint64_t seed, uint64_t stream, uint8_t *out)
+{
+    if (k < 2 || k > KMAX || n < 0) { set_err("bad n or k"); return ORC_EINVAL; }
+    const uint64_t span = (uint64_t)(k - 1) * L;
+    if (L == 0 || span > ((uint64_t)1 << 32)) { set_err("lambda out of range"); return ORC_EINVAL; }
+    const uint64_t t0 = ((uint64_t)1 << 32) - span;
+    for (int64_t v = 0; v < n; v++) {
+        uint64_t ctr[4] = { (uint64_t)v, 0, 1, 0 }, key[2] = { seed, stream }, o[4];
+        orc_philox4x64(ctr, key, o);
+        const uint64_t r = o[0] & 0xffffffffULL;
+        out[v] = r < t0 ? 0 : (uint8_t)(1 + (r - t0) / L);
+    }
+    return ORC_OK;
+}
+
+/* Probability that a given j-vertex set receives exactly the colour set C   */
+/* (|C| = j, one vertex per colour) under that law: j! lambda^j when 0 is not */
+/* in C, j! lambda^(j-1) (1 - (k-1) lambda) when it is. For j = k this is the  */
+/* probability that a k-vertex set is colourful (p_k for the estimates).      */
+double orc_colour_set_prob(int k, uint32_t L, int j, int has_zero)
+{
+    const double lam = (double)L / 4294967296.0;
+    double p = 1.0;
+    for (int i = 2; i <= j; i++) p *= i;
+    for (int i = 0; i < (has_zero ? j - 1 : j); i++) p *= lam;
+    if (has_zero) p *= 1.0 - (double)(k - 1) * lam;
+    return p;
 }
 
 /* ------------------------------------------------------------------------- */
