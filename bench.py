@@ -32,7 +32,8 @@ def parse():
     p.add_argument("--samples", type=int, default=None, help="samples per step (default: the workload's)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-round-skipping", action="store_true",
-                   help="leave out the extra round-skipping build (counter runs: only the plain step's kernels)")
+                   help="leave out the extra round-skipping and biased-colouring builds (counter runs: only the "
+                        "plain step's kernels)")
     p.add_argument("--small", action="store_true", help="small graph (for quick checks)")
     p.add_argument("--workload", default="mid", choices=["mid", "large", "batching", "serving"],
                    help="mid (default) / large: the plain method on the mid / large graph; batching: 48 "
@@ -48,10 +49,10 @@ def parse():
 
 PLAIN = {
     "mid": dict(n=1_000_000, m=10_000_000, gamma=2.1, wmax=5e4, gseed=2, k=6, cseed=12, samples=1_000_000,
-                sseed=22, oracle_scale=8, traffic="gather_mid_k6_hbm_traffic.txt",
+                sseed=22, oracle_scale=8, traffic="gather_mid_k6_hbm_traffic.txt", biased_lambda=0.02,
                 label="mid: Chung-Lu n=1e6 m=1e7 exponent 2.1 w_max=5e4, k=6, zero-rooting"),
     "large": dict(n=4_000_000, m=60_000_000, gamma=2.3, wmax=2e5, gseed=3, k=8, cseed=13, samples=10_000_000,
-                  sseed=23, oracle_scale=64, traffic="gather_large_k8_hbm_traffic.txt",
+                  sseed=23, oracle_scale=64, traffic="gather_large_k8_hbm_traffic.txt", biased_lambda=0.01,
                   label="large: Chung-Lu n=4e6 m=6e7 exponent 2.3 w_max=2e5, k=8, zero-rooting",
                   ags=dict(cbar=1000, round_size=100_000, budget=20_000_000, seed=33)),
 }
@@ -135,6 +136,35 @@ def round_skipping(scc, dg, dcol, k, ns, sseed, verts, par, zinfo, zbuild_ms):
     del bt
     print(f"# round skipping: build {b_ms:.1f} ms vs {zbuild_ms:.1f} ms, {bi.bytes / 1e9:.2f} GB vs "
           f"{zinfo.bytes / 1e9:.2f} GB, totals match {match}", file=sys.stderr, flush=True)
+    return out
+
+
+def biased_colouring(scc, dg, k, lam, cseed, ns, sseed, verts, par, zinfo, zbuild_ms):
+    """The same graph under a biased colouring (Sec. 3.5): colour 0 with
+    probability 1 - (k-1) lambda, others lambda each; build, sampling, and the
+    estimate t / p_k of the number of k-treelet copies next to the uniform one."""
+    import torch
+    dcol = scc.color_biased(dg.n, k, lam, seed=cseed)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    torch.cuda.synchronize()
+    ev[0].record()
+    bt = scc.Table(dg, dcol, k, rooting=scc.ROOT_ZERO)
+    ev[1].record()
+    bt.sample(ns, seed=sseed, out=(verts, par))
+    ev[2].record()
+    torch.cuda.synchronize()
+    bi = bt.info()
+    u = lambda x: int(x[0]) | (int(x[1]) << 64)
+    pb, pu = scc.colorful_probability(k, lam), scc.colorful_probability(k)
+    b_ms = ev[0].elapsed_time(ev[1])
+    est_b, est_u = u(bi.t) / pb, u(zinfo.t) / pu
+    out = {"lambda": lam, "p_k": pb, "p_k_uniform": pu, "build_s": b_ms / 1e3, "uniform_build_s": zbuild_ms / 1e3,
+           "table_bytes": int(bi.bytes), "uniform_table_bytes": int(zinfo.bytes),
+           "sample_per_s": ns / (ev[1].elapsed_time(ev[2]) / 1e3), "t": str(u(bi.t)),
+           "treelets_estimate": est_b, "uniform_treelets_estimate": est_u, "estimate_ratio": est_b / est_u}
+    del bt
+    print(f"# biased colouring lambda={lam}: build {b_ms:.1f} ms vs {zbuild_ms:.1f} ms, {bi.bytes / 1e9:.2f} GB vs "
+          f"{zinfo.bytes / 1e9:.2f} GB, estimate ratio {est_b / est_u:.4f}", file=sys.stderr, flush=True)
     return out
 
 
@@ -474,6 +504,8 @@ def main():
                "shapes_used": sorted(set(int(x) for x in r["round_shapes"]))}
         print(f"# AGS: {ags['rounds']} rounds, {drawn} samples in {t_ags:.2f} s", file=sys.stderr, flush=True)
     rs = None if a.no_round_skipping else round_skipping(scc, dg, dcol, k, ns, sseed, verts, par, info, build_ms)
+    bc = None if a.no_round_skipping else biased_colouring(scc, dg, k, cfg["biased_lambda"], cfg["cseed"], ns, sseed,
+                                                           verts, par, info, build_ms)
     out = {
         "metric": "DP table build s & colorful-treelet samples/sec, batched/served vs plain",
         "value": ns / dt,
@@ -496,6 +528,8 @@ def main():
         out["ags"] = ags
     if rs is not None:
         out["round_skipping"] = rs
+    if bc is not None:
+        out["biased_colouring"] = bc
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, g.m, ns)
     print(json.dumps(out), flush=True)

@@ -260,8 +260,10 @@ scc_status scc_catalog(int k, int64_t *num_classes, uint32_t *codes, int64_t *si
  * to the smaller j). Stops when every class is covered or the next round would
  * exceed `budget` samples. round_size = 1 is the algorithm as printed.
  * Outputs (host): hits int64[N_k]; w double[N_k] (0 for classes never hit;
- * c_i / w_i estimates the colourful count of class i, divide by k!/k^k for the
- * count in the graph); n_j int64[num_unrooted]; round_shapes int32[budget /
+ * c_i / w_i estimates the colourful count of class i, divide by p_k =
+ * scc_colour_set_probability(k, lambda, k, 1) of the colouring's law (k!/k^k
+ * for uniform colours) for the count in the graph); n_j int64[num_unrooted];
+ * round_shapes int32[budget /
  * round_size] or NULL; *n_rounds.
  */
 scc_status scc_ags(const scc_table *t, int64_t cbar, int64_t round_size, int64_t budget,
@@ -285,6 +287,33 @@ int scc_balanced_rooting(int k, int j, int *orbit);
 /* Unrooted shape id of the k-star (the tree with one centre and k-1 leaves),
    -1 if k is outside [2, 8]. */
 int scc_star_shape(int k);
+
+/*
+ * scc_color_biased -- a biased colouring (Sec. 3.5, "Biased coloring"): colour
+ * 0 with probability 1 - (k-1) lambda, each colour in [1, k) with probability
+ * lambda. lambda is used as L / 2^32 with L = lambda * 2^32 rounded to the
+ * nearest integer, 1 <= L < 2^32 and (k-1) L <= 2^32, so the law is exact: the
+ * colour of v is read off the low 32 bits r of the first output of
+ * Philox4x64-10 with key (seed, stream_id) and counter (v, 0, 1, 0): colour 0
+ * while r < 2^32 - (k-1) L, else 1 + (r - (2^32 - (k-1) L)) / L.
+ * colors: device uint8[n], caller-owned; enqueued on `stream`.
+ * Errors: SCC_EINVAL (k outside [2, 8], n < 0, lambda out of range).
+ */
+scc_status scc_color_biased(int64_t n, int k, double lambda, uint64_t seed, uint64_t stream_id,
+                            uint8_t *colors, void *stream);
+
+/*
+ * scc_colour_set_probability -- the probability that a given set of j vertices
+ * receives a given colour set C of size j (one vertex per colour): j!/k^j for
+ * independent uniform colours (lambda <= 0); under the biased law with
+ * parameter lambda (quantised as in scc_color_biased) j! lambda^j when colour
+ * 0 is not in C (has_zero = 0) and j! lambda^(j-1) (1 - (k-1) lambda) when it
+ * is. With j = k and has_zero = 1 it is p_k, the probability that a k-vertex
+ * set is colourful: t / p_k estimates the number of k-treelet copies of G and
+ * (c_i / w_i) / p_k the number of copies of graphlet class i (scc_ags).
+ * Returns -1 for arguments out of range. Host only.
+ */
+double scc_colour_set_probability(int k, double lambda, int j, int has_zero);
 
 /* One instance of a batched build: a graph (device pointers, as for
    scc_build_table), its colours and its k. */

@@ -136,6 +136,8 @@ _SIGS = {
     "scc_num_unrooted": (C.c_int, [C.c_int]),
     "scc_balanced_rooting": (C.c_int, [C.c_int, C.c_int, C.POINTER(C.c_int)]),
     "scc_star_shape": (C.c_int, [C.c_int]),
+    "scc_color_biased": (C.c_int, [_i64, C.c_int, C.c_double, _u64, _u64, _P, _P]),
+    "scc_colour_set_probability": (C.c_double, [C.c_int, C.c_double, C.c_int, C.c_int]),
     "scc_last_error": (C.c_char_p, []),
     "scc_version": (C.c_char_p, []),
 }
@@ -456,6 +458,24 @@ def balanced_rooting(k: int, j: int):
 
 def star_shape(k: int) -> int:
     return _lib.scc_star_shape(k)
+
+
+def color_biased(n: int, k: int, lam: float, seed: int, stream_id: int = 0, device="cuda", stream=None,
+                 out: torch.Tensor | None = None) -> torch.Tensor:
+    """``scc_color_biased``: uint8[n] device colours under the biased law (Sec. 3.5)."""
+    col = out if out is not None else torch.empty(max(n, 1), dtype=torch.uint8, device=device)
+    _check(_lib.scc_color_biased(n, k, lam, seed, stream_id, _ptr(col), _stream_ptr(stream)))
+    return col[:n]
+
+
+def colour_set_probability(k: int, lam: float, j: int, has_zero: bool = True) -> float:
+    """Probability that j given vertices get a given j-colour set (lam <= 0: uniform colours)."""
+    return float(_lib.scc_colour_set_probability(k, lam, j, 1 if has_zero else 0))
+
+
+def colorful_probability(k: int, lam: float = 0.0) -> float:
+    """p_k: probability that a k-vertex set is colourful (uniform colours when lam <= 0)."""
+    return colour_set_probability(k, lam, k, True)
 
 
 def num_classes(k: int) -> int:
