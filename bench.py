@@ -32,8 +32,8 @@ def parse():
     p.add_argument("--samples", type=int, default=None, help="samples per step (default: the workload's)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-round-skipping", action="store_true",
-                   help="leave out the extra round-skipping and biased-colouring builds (counter runs: only the "
-                        "plain step's kernels)")
+                   help="leave out the extra round-skipping, biased-colouring and variable-length builds "
+                        "(counter runs: only the plain step's kernels)")
     p.add_argument("--small", action="store_true", help="small graph (for quick checks)")
     p.add_argument("--workload", default="mid", choices=["mid", "large", "batching", "serving"],
                    help="mid (default) / large: the plain method on the mid / large graph; batching: 48 "
@@ -165,6 +165,31 @@ def biased_colouring(scc, dg, k, lam, cseed, ns, sseed, verts, par, zinfo, zbuil
     del bt
     print(f"# biased colouring lambda={lam}: build {b_ms:.1f} ms vs {zbuild_ms:.1f} ms, {bi.bytes / 1e9:.2f} GB vs "
           f"{zinfo.bytes / 1e9:.2f} GB, estimate ratio {est_b / est_u:.4f}", file=sys.stderr, flush=True)
+    return out
+
+
+def variable_length(scc, dg, dcol, k, ns, sseed, verts, par, zinfo):
+    """The same table re-encoded with variable-length counts (Sec. 3.5): build
+    (with the sampler's running sums, then the re-encoding), record bytes and
+    sampling rate next to the fixed layout."""
+    import torch
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    torch.cuda.synchronize()
+    ev[0].record()
+    vt = scc.Table(dg, dcol, k, rooting=scc.ROOT_ZERO, vlc=True)
+    ev[1].record()
+    vt.sample(ns, seed=sseed, out=(verts, par))
+    ev[2].record()
+    torch.cuda.synchronize()
+    vi = vt.info()
+    out = {"build_s": ev[0].elapsed_time(ev[1]) / 1e3, "record_bytes": int(vi.record_bytes),
+           "fixed_record_bytes": int(zinfo.record_bytes),
+           "record_saving": 1 - vi.record_bytes / zinfo.record_bytes if zinfo.record_bytes else None,
+           "table_bytes": int(vi.bytes), "fixed_table_bytes": int(zinfo.bytes),
+           "sample_per_s": ns / (ev[1].elapsed_time(ev[2]) / 1e3)}
+    del vt
+    print(f"# variable-length counts: build {out['build_s'] * 1e3:.1f} ms (with sampling preparation), records "
+          f"{vi.record_bytes / 1e9:.2f} GB vs {zinfo.record_bytes / 1e9:.2f} GB", file=sys.stderr, flush=True)
     return out
 
 
@@ -506,6 +531,7 @@ def main():
     rs = None if a.no_round_skipping else round_skipping(scc, dg, dcol, k, ns, sseed, verts, par, info, build_ms)
     bc = None if a.no_round_skipping else biased_colouring(scc, dg, k, cfg["biased_lambda"], cfg["cseed"], ns, sseed,
                                                            verts, par, info, build_ms)
+    vl = None if a.no_round_skipping else variable_length(scc, dg, dcol, k, ns, sseed, verts, par, info)
     out = {
         "metric": "DP table build s & colorful-treelet samples/sec, batched/served vs plain",
         "value": ns / dt,
@@ -530,6 +556,8 @@ def main():
         out["round_skipping"] = rs
     if bc is not None:
         out["biased_colouring"] = bc
+    if vl is not None:
+        out["variable_length_counts"] = vl
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, g.m, ns)
     print(json.dumps(out), flush=True)

@@ -98,6 +98,12 @@ typedef struct {
                                   record sizes; SCC_GATHER_GROUPED: rows of at most 64
                                   neighbours several to a wave; SCC_GATHER_ROW: one
                                   row per wave. Results are identical in every mode. */
+    int vlc;                   /* nonzero: after the build, re-encode every stored level
+                                  with variable-length counts (Sec. 3.5): per entry a
+                                  u16 of key (11 bits) and byte length l (5 bits), the
+                                  count in l bytes, a byte-offset checkpoint every 32
+                                  entries. The sampler's running sums are built first.
+                                  Every query and sample is unchanged, bit for bit. */
 } scc_build_opts;
 
 enum { SCC_GATHER_AUTO = 0, SCC_GATHER_GROUPED = 1, SCC_GATHER_ROW = 2 };
@@ -150,6 +156,8 @@ typedef struct {
     int num_hubs;              /* rows gathered in chunks (degree above the hub threshold) */
     uint64_t stars[2];         /* SCC_ROOT_BALANCED: uncoloured k-stars of the graph,
                                   sum_v binom(d_v, k-1) (lo, hi); 0 otherwise */
+    int64_t record_bytes;      /* bytes of the stored records of levels 2..k */
+    int vlc;                   /* records in the variable-length layout */
 } scc_table_info;
 
 /* Table summary (host struct; no device work). */

@@ -47,7 +47,7 @@ class _Csr(C.Structure):
 class _BuildOpts(C.Structure):
     _fields_ = [("rooting", C.c_int), ("max_bits", C.c_int), ("stream", C.c_void_p),
                 ("alloc", C.POINTER(_Allocator)), ("hub_degree", C.c_int), ("validate", C.c_int),
-                ("gather_mode", C.c_int)]
+                ("gather_mode", C.c_int), ("vlc", C.c_int)]
 
 
 class _Instance(C.Structure):
@@ -77,7 +77,8 @@ class TableInfo(C.Structure):
     _fields_ = [("n", C.c_int64), ("k", C.c_int), ("rooting", C.c_int), ("num_unrooted", C.c_int),
                 ("nnz", C.c_int64 * 9), ("wide_vertices", C.c_int64 * 9), ("bytes", C.c_int64),
                 ("t", C.c_uint64 * 2), ("tj", (C.c_uint64 * 2) * 32), ("level_ms", C.c_double * 9),
-                ("gather_ms", C.c_double * 9), ("num_hubs", C.c_int), ("stars", C.c_uint64 * 2)]
+                ("gather_ms", C.c_double * 9), ("num_hubs", C.c_int), ("stars", C.c_uint64 * 2),
+                ("record_bytes", C.c_int64), ("vlc", C.c_int)]
 
 
 class _ServerOpts(C.Structure):
@@ -216,7 +217,7 @@ class Table:
 
     def __init__(self, graph: DeviceGraph, colors, k: int, rooting: int = ROOT_ZERO, max_bits: int = 128,
                  validate: bool = False, stream=None, use_torch_allocator: bool = True, hub_degree: int = 0,
-                 gather_mode: int = 0):
+                 gather_mode: int = 0, vlc: bool = False):
         self.graph = graph
         self.colors = torch.as_tensor(np.asarray(colors) if not torch.is_tensor(colors) else colors,
                                       dtype=torch.uint8).to(graph.row_ptr.device).contiguous()
@@ -225,7 +226,7 @@ class Table:
         csr = _Csr(graph.n, graph.nnz, graph.row_ptr.data_ptr(), graph.col_idx.data_ptr())
         opts = _BuildOpts(rooting, max_bits, _stream_ptr(stream),
                           C.pointer(TORCH_ALLOCATOR) if use_torch_allocator else None, hub_degree,
-                          1 if validate else 0, gather_mode)
+                          1 if validate else 0, gather_mode, 1 if vlc else 0)
         self._h = _P()
         _check(_lib.scc_build_table(C.byref(csr), _ptr(self.colors), k, C.byref(opts), C.byref(self._h)))
 

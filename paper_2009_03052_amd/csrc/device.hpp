@@ -19,6 +19,7 @@ struct LevelView {
     const uint64_t *loc;       // [n] record locators
     const uint64_t *bm;        // presence bitmaps, BW words per vertex
     int BW;
+    int vlc;                   // records in the variable-length layout (below)
 };
 
 #define LOC_OFF(l) ((l) & 0xffffffffffull)
@@ -36,14 +37,61 @@ __host__ __device__ inline uint64_t make_loc(uint64_t off, uint32_t len, uint32_
     return len ? (off | ((uint64_t)len << 40) | ((uint64_t)wide << 52)) : 0ull;
 }
 
+// Variable-length records (Sec. 3.5, "Variable-length counts"): after the
+// level sum N, one u16 per entry holding the key (11 bits) and the count's
+// length in bytes (5 bits), ceil(len/4) words; then the byte offset of every
+// 32nd entry's count (u16 each, ceil(ceil(len/32)/4) words); then the counts,
+// little-endian, byte after byte. An entry's offset is its checkpoint plus
+// the lengths of the entries between, summed four headers per word.
+constexpr uint32_t VLC_CK = 32;
+__host__ __device__ inline uint32_t vlc_ck_words(uint32_t len) { return ((len + VLC_CK - 1) / VLC_CK + 3) / 4; }
+__device__ inline uint32_t vlc_len4(uint64_t w)
+{
+    return (uint32_t)((((w >> 11) & 0x001F001F001F001Full) * 0x0001000100010001ull) >> 48);
+}
+__device__ inline uint32_t vlc_bytes(u128 c)
+{
+    const int b = bitlen128(c);
+    return b ? (uint32_t)(b + 7) / 8 : 1u;
+}
+
 struct Rec {
     const uint64_t *p;   // record start (the header)
     uint32_t len, kw;
     bool wide;
-    __device__ uint32_t key(uint32_t e) const { return ((const uint16_t *)(p + REC_HDR))[e]; }
-    __device__ uint64_t lo(uint32_t e) const { return p[REC_HDR + kw + e]; }
-    __device__ uint64_t hi(uint32_t e) const { return wide ? p[REC_HDR + kw + len + e] : 0; }
-    __device__ u128 cnt(uint32_t e) const { return mk128(lo(e), hi(e)); }
+    bool vlc;
+    __device__ uint32_t key(uint32_t e) const
+    {
+        const uint32_t h = ((const uint16_t *)(p + REC_HDR))[e];
+        return vlc ? (h & 0x7ffu) : h;
+    }
+    __device__ u128 vcnt(uint32_t e) const
+    {
+        const uint16_t *hd = (const uint16_t *)(p + REC_HDR);
+        const uint32_t ckw = vlc_ck_words(len);
+        uint32_t off = ((const uint16_t *)(p + REC_HDR + kw))[e / VLC_CK];
+        const uint64_t *hw = p + REC_HDR + (e & ~(VLC_CK - 1)) / 4;
+        const uint32_t full = (e % VLC_CK) / 4, rem = e % 4;
+        for (uint32_t i = 0; i < full; i++) off += vlc_len4(hw[i]);
+        if (rem) off += vlc_len4(hw[full] & ((1ull << (16 * rem)) - 1ull));
+        const uint32_t l = hd[e] >> 11;
+        const uint64_t *cw = p + REC_HDR + kw + ckw + off / 8;
+        const uint32_t sh = (off % 8) * 8, end = off % 8 + l;
+        const uint64_t w0 = cw[0], w1 = end > 8 ? cw[1] : 0, w2 = end > 16 ? cw[2] : 0;
+        uint64_t lo = sh ? (w0 >> sh) | (w1 << (64 - sh)) : w0;
+        uint64_t hi = sh ? (w1 >> sh) | (w2 << (64 - sh)) : w1;
+        if (l < 8) { lo &= (1ull << (8 * l)) - 1ull; hi = 0; }
+        else if (l == 8) hi = 0;
+        else if (l < 16) hi &= (1ull << (8 * (l - 8))) - 1ull;
+        return mk128(lo, hi);
+    }
+    __device__ u128 cnt(uint32_t e) const
+    {
+        if (vlc) return vcnt(e);
+        return mk128(p[REC_HDR + kw + e], wide ? p[REC_HDR + kw + len + e] : 0);
+    }
+    __device__ uint64_t lo(uint32_t e) const { return lo64(cnt(e)); }
+    __device__ uint64_t hi(uint32_t e) const { return hi64(cnt(e)); }
     __device__ u128 N() const { return len ? mk128(p[0], p[1]) : (u128)0; }
 };
 
@@ -53,6 +101,7 @@ __device__ inline Rec rec_of(const LevelView &L, int64_t v)
     Rec r;
     r.len = LOC_LEN(l);
     r.wide = LOC_WIDE(l) != 0;
+    r.vlc = L.vlc != 0;
     r.kw = key_words(r.len);
     r.p = L.pool + LOC_OFF(l);
     return r;

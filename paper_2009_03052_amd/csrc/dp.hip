@@ -903,6 +903,63 @@ __global__ void __launch_bounds__(256) k_reduce_parts(const u128 *part, int nb, 
     }
 }
 
+// ---------------------------------------------------------------------------
+// Variable-length counts (Sec. 3.5): re-encoding of a finished level. Pass 1
+// sizes every record in the new layout, a scan places them, pass 2 writes
+// them: per chunk of 64 entries a wave scan of the byte lengths gives each
+// count's offset.
+// ---------------------------------------------------------------------------
+__device__ inline uint32_t vlc_rec_words(uint32_t len, uint64_t bytes)
+{
+    return len ? (uint32_t)(REC_HDR + key_words(len) + vlc_ck_words(len) + (bytes + 7) / 8) : 0u;
+}
+
+__global__ void __launch_bounds__(WAVE) k_vlc_size(int64_t n, LevelView L, uint64_t *words)
+{
+    for (int64_t v = blockIdx.x; v < n; v += gridDim.x) {
+        const Rec r = rec_of(L, v);
+        uint64_t b = 0;
+        for (uint32_t e = threadIdx.x; e < r.len; e += WAVE) b += vlc_bytes(r.cnt(e));
+        b = wave_sum64(b);
+        if (threadIdx.x == 0) words[v] = vlc_rec_words(r.len, b);
+    }
+}
+
+__global__ void __launch_bounds__(WAVE) k_vlc_write(int64_t n, LevelView L, const uint64_t *incl, uint64_t *pool,
+                                                    uint64_t *loc)
+{
+    const int lane = threadIdx.x;
+    for (int64_t v = blockIdx.x; v < n; v += gridDim.x) {
+        const Rec r = rec_of(L, v);
+        const uint64_t start = v ? incl[v - 1] : 0;
+        if (lane == 0) loc[v] = make_loc(start, r.len, 0);
+        if (!r.len) continue;
+        uint64_t *p = pool + start;
+        if (lane < 2) p[lane] = r.p[lane];   // level sum N
+        uint16_t *hd = (uint16_t *)(p + REC_HDR);
+        uint16_t *ck = (uint16_t *)(p + REC_HDR + key_words(r.len));
+        uint8_t *cb = (uint8_t *)(p + REC_HDR + key_words(r.len) + vlc_ck_words(r.len));
+        uint32_t base = 0;
+        for (uint32_t e0 = 0; e0 < r.len; e0 += WAVE) {
+            const uint32_t e = e0 + lane;
+            u128 c = 0;
+            uint32_t l = 0;
+            if (e < r.len) {
+                c = r.cnt(e);
+                l = vlc_bytes(c);
+            }
+            const uint32_t incl_l = wave_incl_scan32(l);
+            const uint32_t off = base + incl_l - l;
+            if (e < r.len) {
+                hd[e] = (uint16_t)(r.key(e) | (l << 11));
+                if (e % VLC_CK == 0) ck[e / VLC_CK] = (uint16_t)off;
+                for (uint32_t i = 0; i < l; i++) cb[off + i] = (uint8_t)(c >> (8 * i));
+            }
+            base += __shfl(incl_l, WAVE - 1, WAVE);
+        }
+    }
+}
+
 // Round skipping (Sec. 3.5): the uncoloured k-stars centred at v, binom(d_v, k-1),
 // by the exact recurrence c_i = c_{i-1} (d - r + i) / i; flags a product that
 // does not fit 128 bits
@@ -1148,7 +1205,7 @@ unsigned grid_of(int64_t n) { return (unsigned)std::min<int64_t>(n, 256 * 80); }
 
 LevelView view(const TableLevel &l)
 {
-    return LevelView{l.pool, l.loc, l.bm, l.BW};
+    return LevelView{l.pool, l.loc, l.bm, l.BW, l.vlc ? 1 : 0};
 }
 
 LevelSrc packed_src(const TableLevel &l)
@@ -1528,6 +1585,45 @@ static scc_status build_totals(scc_table *T)
     return s ? s : totals_finish(T);
 }
 
+// Re-encodes every stored level with variable-length counts (Sec. 3.5). The
+// sampler's running sums are prepared first, from the fixed layout; every
+// reader after this point goes through the layout-aware record view.
+static scc_status compact_levels(scc_table *T)
+{
+    scc_status s = prepare_all_sampling(T);
+    if (s) return s;
+    const int64_t n = T->n;
+    hipStream_t st = T->stream;
+    const unsigned grid = (unsigned)std::min<int64_t>(std::max<int64_t>(n, 1), 65536);
+    for (int h = 2; h <= T->k; h++) {
+        TableLevel &Lv = T->lev[h];
+        uint64_t *words = (uint64_t *)T->mem.get((size_t)n * 8 + 8);
+        if (!words) return set_error(SCC_ENOMEM, "record sizes");
+        struct Put { scc_table *T; uint64_t *w; ~Put() { T->mem.put(w); } } put{T, words};
+        if (n) hipLaunchKernelGGL(k_vlc_size, dim3(grid), dim3(WAVE), 0, st, n, view(Lv), words);
+        s = scan_u64(T, words, words, n);
+        if (s) return s;
+        uint64_t total = 0;
+        if (n) HIP_TRY(hipMemcpyAsync(&total, words + (n - 1), 8, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        uint64_t *pool = (uint64_t *)T->alloc((size_t)total * 8 + 64);
+        uint64_t *loc = (uint64_t *)T->alloc((size_t)n * 8 + 8);
+        if (!pool || !loc) return set_error(SCC_ENOMEM, "level %d variable-length records (%llu words)", h,
+                                            (unsigned long long)total);
+        if (n) hipLaunchKernelGGL(k_vlc_write, dim3(grid), dim3(WAVE), 0, st, n, view(Lv), words, pool, loc);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipStreamSynchronize(st));
+        T->release(Lv.pool, (size_t)Lv.pool_words * 8 + 64);
+        T->release(Lv.loc, (size_t)n * 8 + 8);
+        Lv.pool = pool;
+        Lv.loc = loc;
+        Lv.pool_words = total;
+        Lv.vlc = true;
+    }
+    T->vlc = true;
+    return SCC_OK;
+}
+
 static scc_status make_key_maps(scc_table *T)
 {
     const DevLut &L = T->hlut;
@@ -1623,6 +1719,7 @@ extern "C" scc_status scc_build_table(const scc_csr *g, const uint8_t *colors, i
     if (!s) s = build_levels(T);
     if (!s) s = build_totals(T);
     if (!s) T->lev[1].nnz = T->n;
+    if (!s && o.vlc) s = compact_levels(T);
     if (s) { delete T; return s; }
     *out = T;
     return SCC_OK;
@@ -1660,6 +1757,8 @@ extern "C" scc_status scc_table_info_get(const scc_table *t, scc_table_info *out
     out->t[0] = lo64(t->t); out->t[1] = hi64(t->t);
     for (int j = 0; j < t->hlut.num_unr; j++) { out->tj[j][0] = lo64(t->tj[j]); out->tj[j][1] = hi64(t->tj[j]); }
     out->stars[0] = lo64(t->stars); out->stars[1] = hi64(t->stars);
+    for (int h = 2; h <= t->k; h++) out->record_bytes += (int64_t)t->lev[h].pool_words * 8;
+    out->vlc = t->vlc ? 1 : 0;
     return SCC_OK;
 }
 

@@ -576,7 +576,7 @@ __global__ void __launch_bounds__(WAVE) k_export(int64_t n, LevelView Lv, int h1
     }
 }
 
-LevelView lview(const TableLevel &l) { return LevelView{l.pool, l.loc, l.bm, l.BW}; }
+LevelView lview(const TableLevel &l) { return LevelView{l.pool, l.loc, l.bm, l.BW, l.vlc ? 1 : 0}; }
 
 }  // namespace
 
@@ -599,6 +599,7 @@ static scc_status ensure_hub_prefix(scc_table *T)
     const int nh = (int)T->hub_host.size();
     hipStream_t st = T->stream;
     if (nh == 0 || k < 2) { T->hubpre_ready = true; return SCC_OK; }
+    if (T->vlc) return set_error(SCC_EINVAL, "internal: hub running sums after the variable-length re-encoding");
     const DevLut &HL = T->hlut;
     HubPreArgs A{};
     A.g = GraphView{T->n, T->row_ptr, T->col_idx, T->colors};

@@ -14,6 +14,7 @@ struct TableLevel {
     int64_t wide = 0;
     uint64_t *bm = nullptr;     // [n * BW] presence bitmaps over the dense level layout
     int BW = 0;
+    bool vlc = false;           // records in the variable-length layout
 };
 
 struct TableSums {
@@ -62,6 +63,7 @@ struct scc_table {
     int hub_degree = 1024;           // rows above this degree are gathered in chunks
     int hub_chunk = 256;             // neighbours per chunk
     int gather_mode = SCC_GATHER_AUTO;
+    bool vlc = false;                // levels re-encoded with variable-length counts after the build
     int nhub = 0;
     bool stats_done = false;
     std::vector<int32_t> hub_host;   // hub vertices (ascending) and their row bounds
@@ -112,6 +114,8 @@ inline u128 sample_weight(const scc_table *T, int shape)
     return T->tj[shape];
 }
 
+// Every hub's neighbour running sums and every shape's root running sums.
+scc_status prepare_all_sampling(scc_table *T);
 // Running sums of admissible level-k totals for one unrooted shape (or all, shape < 0).
 scc_status table_prefix(scc_table *T, int shape, const u128 **pre, u128 *total);
 // Inclusive running sum of n u128 values on the stream (scratch from T's allocator).
