@@ -159,7 +159,15 @@ struct GatherArgs {
     int *err;
     const DevLut *Lut;             // grouped rows: the level's (rank, colour set) per key
     int hs, bk1;                   // gathered level and binom(k-1, hs)
+    // high words in compact rows: hrow[v] = row of v in Shi (hubs first, then the
+    // other rows whose bound reaches 2^64, appended to wide_rows by the 64-bit
+    // pass); null: Shi has a row for every vertex
+    int32_t *hrow;
+    int32_t *wide_rows;
+    int *wide_count;
 };
+
+__device__ inline size_t hi_row(const int32_t *hrow, int64_t v) { return hrow ? (size_t)hrow[v] : (size_t)v; }
 
 // most keys on one level: r_6 C(8, 6) = 560 at k = 8
 constexpr int GATHER_MAX_KEYS = 576;
@@ -235,9 +243,12 @@ __device__ inline u128 gather_range(const GatherArgs &A, int64_t a, int64_t b, b
 // LDS sums of the neighbours in [a, b): 64-bit pass first, a 128-bit pass only
 // when the bound says 64 bits may not suffice
 // LDS: acc_lo[WS], acc_hi[WS], then the index slice of colour cv (GATHER_MAX_KEYS int16)
+// mode: GS_BOTH (64-bit pass, then 128-bit if the bound needs it), GS_DEFER
+// (64-bit pass only; wideS reports the need), GS_WIDE (128-bit pass only)
+enum { GS_BOTH = 0, GS_DEFER = 1, GS_WIDE = 2 };
 template <bool SLOTS>
 __device__ inline u128 gather_sums(const GatherArgs &A, int cv, int64_t a, int64_t b, uint64_t *acc_lo,
-                                   uint64_t *acc_hi, bool &wideS)
+                                   uint64_t *acc_hi, bool &wideS, int mode = GS_BOTH)
 {
     const int lane = threadIdx.x;
     const int WS = A.WS;
@@ -246,9 +257,13 @@ __device__ inline u128 gather_sums(const GatherArgs &A, int cv, int64_t a, int64
     for (int i = lane; i < A.key_n; i += WAVE) ssm[i] = sidx[i];
     for (int i = lane; i < WS; i += WAVE) { acc_lo[i] = 0; acc_hi[i] = 0; }
     __syncthreads();
-    u128 m = gather_range<SLOTS>(A, a, b, false, acc_lo, acc_hi, ssm);
-    wideS = hi64(m) != 0;
-    if (wideS) {
+    u128 m = 0;
+    wideS = mode == GS_WIDE;
+    if (!wideS) {
+        m = gather_range<SLOTS>(A, a, b, false, acc_lo, acc_hi, ssm);
+        wideS = hi64(m) != 0;
+    }
+    if (wideS && mode != GS_DEFER) {
         __syncthreads();
         for (int i = lane; i < WS; i += WAVE) { acc_lo[i] = 0; acc_hi[i] = 0; }
         __syncthreads();
@@ -258,8 +273,10 @@ __device__ inline u128 gather_sums(const GatherArgs &A, int cv, int64_t a, int64
     return m;
 }
 
+// GS_DEFER: a row whose bound reaches 2^64 is only listed (its 128-bit pass
+// runs, GS_WIDE, once its compact high-word row exists)
 template <bool SLOTS>
-__device__ inline void gather_vertex(const GatherArgs &A, int64_t v, uint64_t *sm)
+__device__ inline void gather_vertex(const GatherArgs &A, int64_t v, uint64_t *sm, int mode = GS_BOTH)
 {
     const int lane = threadIdx.x;
     const int cv = A.g.colors[v];
@@ -271,11 +288,15 @@ __device__ inline void gather_vertex(const GatherArgs &A, int64_t v, uint64_t *s
     uint64_t *acc_hi = sm + WS;
     bool wideS;
     // bound: every entry of S_hs(v) is at most M_hs(v)
-    const u128 m = gather_sums<SLOTS>(A, cv, a, b, acc_lo, acc_hi, wideS);
+    const u128 m = gather_sums<SLOTS>(A, cv, a, b, acc_lo, acc_hi, wideS, mode);
+    if (wideS && mode == GS_DEFER) {
+        if (lane == 0) A.wide_rows[atomicAdd(A.wide_count, 1)] = (int32_t)v;
+        return;
+    }
     uint64_t *Slo = A.Slo + (size_t)v * WS;
     for (int i = lane; i < WS; i += WAVE) Slo[i] = acc_lo[i];
     if (wideS) {
-        uint64_t *Shi = A.Shi + (size_t)v * WS;
+        uint64_t *Shi = A.Shi + hi_row(A.hrow, v) * WS;
         for (int i = lane; i < WS; i += WAVE) Shi[i] = acc_hi[i];
     }
     if (lane == 0) A.M[v] = m;
@@ -286,7 +307,7 @@ __global__ void __launch_bounds__(WAVE) k_gather(GatherArgs A)
 {
     extern __shared__ uint64_t sm[];
     for (int64_t v = blockIdx.x; v < A.g.n; v += gridDim.x) {
-        gather_vertex<false>(A, v, sm);
+        gather_vertex<false>(A, v, sm, A.hrow ? GS_DEFER : GS_BOTH);
         __syncthreads();
     }
 }
@@ -295,7 +316,23 @@ __global__ void __launch_bounds__(WAVE) k_gather(GatherArgs A)
 __global__ void __launch_bounds__(WAVE) k_gather_list(GatherArgs A, const int32_t *rows)
 {
     extern __shared__ uint64_t sm[];
-    gather_vertex<false>(A, rows[blockIdx.x], sm);
+    gather_vertex<false>(A, rows[blockIdx.x], sm, A.hrow ? GS_DEFER : GS_BOTH);
+}
+
+// the listed rows whose bound reaches 2^64 (one per workgroup), 128-bit pass
+// into their compact high-word rows
+__global__ void __launch_bounds__(WAVE) k_gather_wide(GatherArgs A)
+{
+    extern __shared__ uint64_t sm[];
+    gather_vertex<false>(A, __builtin_amdgcn_readfirstlane(A.wide_rows[blockIdx.x]), sm, GS_WIDE);
+}
+
+// hrow[rows[i]] = base + i
+__global__ void k_set_rows(int32_t *hrow, const int32_t *rows, const int *count, int64_t fixed, int32_t base)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t cnt = count ? (int64_t)*count : fixed;
+    if (i < cnt) hrow[rows[i]] = base + (int32_t)i;
 }
 
 // ---------------------------------------------------------------------------
@@ -431,9 +468,18 @@ __device__ inline void gather_group(const GatherArgs &A, int64_t v0, int G, uint
         if ((mine_mask >> j & 1u) && !(wide_mask >> j & 1u)) Slo[i] = acc[i];
     }
     if (lane < nv && mine && !(wide_mask >> lane & 1u)) A.M[v0 + lane] = mj;
-    for (uint64_t wm = wide_mask; wm; wm &= wm - 1) {
-        __syncthreads();
-        gather_vertex<SLOTS>(A, v0 + (__ffsll((long long)wm) - 1), wsm);
+    if (A.hrow) {
+        // listed for the 128-bit pass once their high-word rows exist
+        const int nw = __popcll(wide_mask);
+        int base = 0;
+        if (nw && lane == 0) base = atomicAdd(A.wide_count, nw);
+        base = __shfl(base, 0, WAVE);
+        if (wide_mask >> lane & 1u) A.wide_rows[base + __popcll(wide_mask & lanemask_lt())] = (int32_t)(v0 + lane);
+    } else {
+        for (uint64_t wm = wide_mask; wm; wm &= wm - 1) {
+            __syncthreads();
+            gather_vertex<SLOTS>(A, v0 + (__ffsll((long long)wm) - 1), wsm);
+        }
     }
 }
 
@@ -464,9 +510,10 @@ __global__ void __launch_bounds__(WAVE) k_gather_group(GatherArgs A, int G)
 // hub rows, step 1: cleared sums and bound
 __device__ inline void hub_zero(const GatherArgs &A, int64_t v)
 {
+    const size_t hr = hi_row(A.hrow, v);
     for (int i = threadIdx.x; i < A.WS; i += blockDim.x) {
         A.Slo[(size_t)v * A.WS + i] = 0;
-        A.Shi[(size_t)v * A.WS + i] = 0;
+        A.Shi[hr * A.WS + i] = 0;
     }
     if (threadIdx.x == 0) A.M[v] = 0;
 }
@@ -500,7 +547,7 @@ __device__ inline void hub_chunk(const GatherArgs &A, int64_t v, int64_t a, int6
     bool wideS;
     const u128 m = gather_sums<SLOTS>(A, cv, a, b, acc_lo, acc_hi, wideS);
     unsigned long long *Slo = (unsigned long long *)(A.Slo + (size_t)v * WS);
-    unsigned long long *Shi = (unsigned long long *)(A.Shi + (size_t)v * WS);
+    unsigned long long *Shi = (unsigned long long *)(A.Shi + hi_row(A.hrow, v) * WS);
     bool over = false;
     for (int i = lane; i < WS; i += WAVE) {
         const uint64_t lo = acc_lo[i], hi = acc_hi[i];
@@ -581,6 +628,7 @@ struct CombineArgs {
     LevelSrc lev[SCC_KMAX + 1];           // own levels 2..h-1
     const uint64_t *Slo[SCC_KMAX + 1];    // neighbour sums 1..h-1
     const uint64_t *Shi[SCC_KMAX + 1];
+    const int32_t *Shrow[SCC_KMAX + 1];   // compact high-word rows, or null (one per vertex)
     const u128 *M[SCC_KMAX + 1];
     const int16_t *key_xidx;              // [k * nkeys]
     int W;                                // slot capacity = W_h
@@ -657,7 +705,7 @@ __device__ inline void combine_vertex(const CombineArgs &A, int64_t v, uint64_t 
         const int ws = L.WS[hs];
         const uint64_t *gl = A.Slo[hs] + (size_t)v * ws;
         const bool sw = hi64(A.M[hs][v]) != 0;
-        const uint64_t *gh = sw ? A.Shi[hs] + (size_t)v * ws : nullptr;
+        const uint64_t *gh = sw ? A.Shi[hs] + hi_row(A.Shrow[hs], v) * ws : nullptr;
         for (int i = lane; i < ws; i += WAVE) {
             Slo[L.soff[hs] + i] = gl[i];
             if (wide) Shi[L.soff[hs] + i] = sw ? gh[i] : 0;
@@ -1257,6 +1305,8 @@ static scc_status build_levels(scc_table *T)
     } guard{T, &scratch};
     auto get = [&](size_t bytes) { void *p = T->mem.get(bytes); if (p) scratch.push_back(p); return p; };
     if (!err) return set_error(SCC_ENOMEM, "flags");
+    int32_t *gwide = (int32_t *)get((size_t)n * 4 + 256);   // rows whose neighbour sums need 128 bits
+    if (!gwide) return set_error(SCC_ENOMEM, "wide rows");
 
     // per-level start/end events (whole level, and its gather), read once at the end
     hipEvent_t ev[SCC_KMAX + 1][2] = {}, gev[SCC_KMAX + 1][2] = {};
@@ -1359,23 +1409,21 @@ static scc_status build_levels(scc_table *T)
             const size_t sz = (size_t)n * HL.WS[hs] * 8;
             Sx.M = (u128 *)T->alloc((size_t)n * 16 + 16);
             Sx.lo = (uint64_t *)T->alloc(sz + 8);
-            Sx.hi = (uint64_t *)T->alloc(sz + 8);
-            if (!Sx.M || !Sx.lo || !Sx.hi) return set_error(SCC_ENOMEM, "neighbour sums level %d (%zu bytes)", hs, 2 * sz);
+            Sx.hrow = (int32_t *)T->alloc((size_t)n * 4 + 8);
+            if (!Sx.M || !Sx.lo || !Sx.hrow) return set_error(SCC_ENOMEM, "neighbour sums level %d (%zu bytes)", hs, sz);
+            HIP_TRY(hipMemsetAsync(Sx.hrow, 0xff, (size_t)n * 4 + 8, st));
             GatherArgs G{};
             G.g = g; G.k = k; G.nkeys = HL.nkeys; G.WS = HL.WS[hs]; G.rows_zero = zero && h == k;
             G.key_lo = HL.off[hs]; G.key_n = HL.r[hs] * HL.bk[hs];
             G.hub_degree = hub_degree;
-            G.L = packed_src(T->lev[hs]); G.M = Sx.M; G.key_sidx = T->key_sidx; G.Slo = Sx.lo; G.Shi = Sx.hi;
+            G.L = packed_src(T->lev[hs]); G.M = Sx.M; G.key_sidx = T->key_sidx; G.Slo = Sx.lo; G.Shi = nullptr;
             G.chunk_v = chunk_v; G.chunk_e = chunk_e; G.err = err;
             G.Lut = T->dlut; G.hs = hs; G.bk1 = HL.bk1[hs];
+            G.hrow = Sx.hrow; G.wide_rows = gwide; G.wide_count = err + 2;
             const size_t lds = gather_lds(HL.WS[hs]);
             const int gs = group_size(HL.WS[hs]);
             const int64_t ngroups = (n + gs - 1) / gs;
             HIP_TRY(hipEventRecord(gev[hs][0], st));
-            if (nhub) {
-                hipLaunchKernelGGL(k_hub_prepare, dim3((unsigned)nhub), dim3(WAVE), 0, st, G, hubs);
-                hipLaunchKernelGGL(k_gather_hub, dim3((unsigned)nchunk), dim3(WAVE), lds, st, G, T->hub_chunk);
-            }
             // grouped low-degree rows pay off while records are short; long records
             // fill a wave from a few neighbours already
             const bool grouped = T->gather_mode == SCC_GATHER_GROUPED ||
@@ -1389,6 +1437,26 @@ static scc_status build_levels(scc_table *T)
             } else if (n) {
                 hipLaunchKernelGGL(k_gather, dim3((unsigned)n), dim3(WAVE), lds, st, G);
             }
+            // high words only for the hubs (merged across chunks) and the listed
+            // rows whose bound reaches 2^64, in compact rows: hubs first
+            int nw = 0;
+            HIP_TRY(hipMemcpyAsync(&nw, err + 2, 4, hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            Sx.hi_rows = (int64_t)nhub + nw;
+            Sx.hi = (uint64_t *)T->alloc((size_t)Sx.hi_rows * HL.WS[hs] * 8 + 8);
+            if (!Sx.hi) return set_error(SCC_ENOMEM, "neighbour sums level %d, high words", hs);
+            G.Shi = Sx.hi;
+            if (nhub)
+                hipLaunchKernelGGL(k_set_rows, dim3((unsigned)((nhub + 255) / 256)), dim3(256), 0, st, Sx.hrow, hubs,
+                                   (const int *)nullptr, (int64_t)nhub, 0);
+            if (nw)
+                hipLaunchKernelGGL(k_set_rows, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, st, Sx.hrow, gwide,
+                                   (const int *)nullptr, (int64_t)nw, nhub);
+            if (nhub) {
+                hipLaunchKernelGGL(k_hub_prepare, dim3((unsigned)nhub), dim3(WAVE), 0, st, G, hubs);
+                hipLaunchKernelGGL(k_gather_hub, dim3((unsigned)nchunk), dim3(WAVE), lds, st, G, T->hub_chunk);
+            }
+            if (nw) hipLaunchKernelGGL(k_gather_wide, dim3((unsigned)nw), dim3(WAVE), lds, st, G);
             HIP_TRY(hipEventRecord(gev[hs][1], st));
         }
         // combine into slots: a vertex needing 128 bits waits for the second kernel
@@ -1410,7 +1478,9 @@ static scc_status build_levels(scc_table *T)
         C.g = g; C.L = T->dlut; C.h = h; C.zero_only = zero && last; C.max_bits = T->max_bits;
         C.bal = bal && last;
         for (int q = 2; q < h; q++) C.lev[q] = packed_src(T->lev[q]);
-        for (int q = 1; q < h; q++) { C.Slo[q] = T->S[q].lo; C.Shi[q] = T->S[q].hi; C.M[q] = T->S[q].M; }
+        for (int q = 1; q < h; q++) {
+            C.Slo[q] = T->S[q].lo; C.Shi[q] = T->S[q].hi; C.Shrow[q] = T->S[q].hrow; C.M[q] = T->S[q].M;
+        }
         C.key_xidx = T->key_xidx; C.W = HL.W[h];
         C.slot_key = slot_key; C.slot_lo = slot_lo; C.slot_hi = slot_hi;
         C.meta = meta; C.Nout = Nsc; C.err = err;

@@ -227,7 +227,8 @@ __device__ inline int sample_one(const SampleArgs &A, int64_t r, SampleLds &W)
             const int ws = L.WS[hpp];
             sidx = b * L.bk1[hpp] + L.colex_s[compress_out(cpp, cx)];
             const uint64_t slo = A.Slo[hpp][(size_t)x * ws + sidx];
-            const uint64_t shi = hi64(A.M[hpp][x]) ? A.Shi[hpp][(size_t)x * ws + sidx] : 0;
+            const uint64_t shi =
+                hi64(A.M[hpp][x]) ? A.Shi[hpp][(A.Shrow[hpp] ? (size_t)A.Shrow[hpp][x] : (size_t)x) * ws + sidx] : 0;
             sval = mk128(slo, shi);
             w = xprime * sval;
         }
@@ -784,7 +785,9 @@ scc_status prepare_sampling(scc_table *T, int shape, SampleArgs *out)
     A.g = GraphView{T->n, T->row_ptr, T->col_idx, T->colors};
     A.L = T->dlut; A.k = T->k; A.shape = shape; A.zero = T->rooting == SCC_ROOT_ZERO;
     for (int h = 2; h <= T->k; h++) A.lev[h] = lview(T->lev[h]);
-    for (int h = 1; h < T->k; h++) { A.Slo[h] = T->S[h].lo; A.Shi[h] = T->S[h].hi; A.M[h] = T->S[h].M; }
+    for (int h = 1; h < T->k; h++) {
+        A.Slo[h] = T->S[h].lo; A.Shi[h] = T->S[h].hi; A.Shrow[h] = T->S[h].hrow; A.M[h] = T->S[h].M;
+    }
     A.pre = pre; A.total = total;
     *out = A;
     return SCC_OK;

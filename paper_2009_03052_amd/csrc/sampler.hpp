@@ -11,6 +11,7 @@ struct SampleArgs {
     LevelView lev[SCC_KMAX + 1];          // 2..k
     const uint64_t *Slo[SCC_KMAX + 1];    // neighbour sums 1..k-1
     const uint64_t *Shi[SCC_KMAX + 1];
+    const int32_t *Shrow[SCC_KMAX + 1];   // compact high-word rows, or null (one row per vertex)
     const u128 *M[SCC_KMAX + 1];
     const int16_t *key_xidx;              // [k * nkeys] dense own position of a key, or -1
     int nkeys;

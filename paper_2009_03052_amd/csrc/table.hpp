@@ -19,7 +19,9 @@ struct TableLevel {
 
 struct TableSums {
     uint64_t *lo = nullptr;     // [n * WS_h]
-    uint64_t *hi = nullptr;     // [n * WS_h] when some vertex needs 128 bits
+    uint64_t *hi = nullptr;     // high words: [hi_rows * WS_h] rows hrow[v], or [n * WS_h] when hrow is null
+    int32_t *hrow = nullptr;    // [n] compact high-word row of v (hubs, then rows with M_h(v) >= 2^64), or -1
+    int64_t hi_rows = 0;
     u128 *M = nullptr;          // [n] sum over neighbours of N_h
 };
 
