@@ -165,6 +165,11 @@ struct GatherArgs {
     int32_t *hrow;
     int32_t *wide_rows;
     int *wide_count;
+    // the sampler's hub running sums built with the gather: each hub chunk (one
+    // block of HUB_BLOCK neighbours) stores its sums as its block's (null: not)
+    uint64_t *hub_pre;
+    const int64_t *hub_poff;       // [nhub * (SCC_KMAX + 1)] word offset of each (hub, level) block area
+    const int32_t *chunk_q;        // hub number of each chunk
 };
 
 __device__ inline size_t hi_row(const int32_t *hrow, int64_t v) { return hrow ? (size_t)hrow[v] : (size_t)v; }
@@ -537,7 +542,7 @@ __device__ inline bool atomic_add128(unsigned long long *lo_w, unsigned long lon
 
 // hub rows, step 2: one wave per chunk of neighbours, merged with atomics
 template <bool SLOTS>
-__device__ inline void hub_chunk(const GatherArgs &A, int64_t v, int64_t a, int64_t b, uint64_t *sm)
+__device__ inline void hub_chunk(const GatherArgs &A, int64_t v, int64_t a, int64_t b, uint64_t *sm, int q = -1)
 {
     const int lane = threadIdx.x;
     const int cv = A.g.colors[v];
@@ -559,6 +564,73 @@ __device__ inline void hub_chunk(const GatherArgs &A, int64_t v, int64_t a, int6
         if (m == ~(u128)0) over = true;
     }
     if (over) atomicOr(A.err, 2);   // the bound left 128 bits: the build reports overflow
+    if (A.hub_pre && q >= 0 && !(A.rows_zero && cv != 0)) {
+        // this chunk is block (a - row start) / HUB_BLOCK of the hub's running sums
+        const int64_t ra = A.g.row_ptr[v], d = A.g.row_ptr[v + 1] - ra;
+        const int64_t nb = (d + HUB_BLOCK - 1) / HUB_BLOCK, blk = (a - ra) / HUB_BLOCK;
+        uint64_t *plo = A.hub_pre + A.hub_poff[(size_t)q * (SCC_KMAX + 1) + A.hs];
+        uint64_t *phi = plo + (size_t)WS * nb;
+        for (int i = lane; i < WS; i += WAVE) {
+            plo[(size_t)i * nb + blk] = acc_lo[i];
+            phi[(size_t)i * nb + blk] = acc_hi[i];
+        }
+    }
+}
+
+// level-1 block sums of the hub running sums: neighbours of each colour per block
+__global__ void __launch_bounds__(WAVE) k_hub_l1_blocks(GraphView g, int k, const int32_t *hubs,
+                                                        const int64_t *chunk_e, const int32_t *chunk_q,
+                                                        uint64_t *hub_pre, const int64_t *hub_poff)
+{
+    const int lane = threadIdx.x;
+    const int q = chunk_q[blockIdx.x];
+    const int64_t x = hubs[q];
+    const int cx = g.colors[x];
+    const int64_t ra = g.row_ptr[x], rb = g.row_ptr[x + 1], a = chunk_e[blockIdx.x];
+    const int64_t nb = (rb - ra + HUB_BLOCK - 1) / HUB_BLOCK, blk = (a - ra) / HUB_BLOCK;
+    const int64_t e = a + lane;
+    int j = -1;
+    if (e < rb && lane < HUB_BLOCK) {
+        const int cu = g.colors[g.col_idx[e]];
+        if (cu != cx) j = cu < cx ? cu : cu - 1;   // the S_1 entry of colour set {c_u} seen from x
+    }
+    uint64_t *plo = hub_pre + hub_poff[(size_t)q * (SCC_KMAX + 1) + 1];
+    uint64_t *phi = plo + (size_t)(k - 1) * nb;
+    for (int i = 0; i < k - 1; i++) {
+        const uint64_t c = (uint64_t)__popcll(__ballot(j == i));
+        if (lane == 0) {
+            plo[(size_t)i * nb + blk] = c;
+            phi[(size_t)i * nb + blk] = 0;
+        }
+    }
+}
+
+// block sums -> running sums at block ends, in place: one wave per (hub, entry),
+// 64 blocks per step; high words kept only where the hub's bound M reaches 2^64
+__global__ void __launch_bounds__(WAVE) k_hub_block_scan(GraphView g, const int32_t *hubs, int WS, int hs,
+                                                         int rows_zero, const u128 *M, uint64_t *hub_pre,
+                                                         const int64_t *hub_poff)
+{
+    const int q = blockIdx.x / WS, i = blockIdx.x - q * WS;
+    const int64_t x = hubs[q];
+    if (rows_zero && g.colors[x] != 0) return;
+    const int64_t nb = (g.row_ptr[x + 1] - g.row_ptr[x] + HUB_BLOCK - 1) / HUB_BLOCK;
+    uint64_t *plo = hub_pre + hub_poff[(size_t)q * (SCC_KMAX + 1) + hs];
+    uint64_t *phi = plo + (size_t)WS * nb;
+    plo += (size_t)i * nb;
+    phi += (size_t)i * nb;
+    const bool pw = hi64(M[x]) != 0;
+    u128 carry = 0;
+    for (int64_t b0 = 0; b0 < nb; b0 += WAVE) {
+        const int64_t b = b0 + threadIdx.x;
+        const u128 val = b < nb ? mk128(plo[b], phi[b]) : (u128)0;
+        const u128 run = carry + wave_incl_scan128(val);
+        if (b < nb) {
+            plo[b] = lo64(run);
+            if (pw) phi[b] = hi64(run);
+        }
+        carry = shfl128(run, WAVE - 1);
+    }
 }
 
 __global__ void __launch_bounds__(WAVE) k_gather_hub(GatherArgs A, int chunk)
@@ -567,7 +639,7 @@ __global__ void __launch_bounds__(WAVE) k_gather_hub(GatherArgs A, int chunk)
     const int64_t v = A.chunk_v[blockIdx.x];
     const int64_t a = A.chunk_e[blockIdx.x];
     const int64_t b = min(A.g.row_ptr[v + 1], a + (int64_t)chunk);
-    hub_chunk<false>(A, v, a, b, sm);
+    hub_chunk<false>(A, v, a, b, sm, A.chunk_q ? A.chunk_q[blockIdx.x] : -1);
 }
 
 // algorithmic bytes of one gather launch (for reports): 4 d_v + neighbours'
@@ -1331,9 +1403,10 @@ static scc_status build_levels(scc_table *T)
     int nhub = 0, nmid = 0;
     int64_t low_rows = 0;
     int32_t *hubs = nullptr, *mids = nullptr;
-    int32_t *chunk_v = nullptr;
+    int32_t *chunk_v = nullptr, *chunk_q = nullptr;
     int64_t *chunk_e = nullptr;
     int64_t nchunk = 0;
+    bool fused = false;   // hub running sums built with the gather
     if (n) {
         hubs = (int32_t *)get((size_t)n * 4 + 8);
         mids = (int32_t *)get((size_t)n * 4 + 8);
@@ -1360,16 +1433,46 @@ static scc_status build_levels(scc_table *T)
         hipLaunchKernelGGL(k_hub_rows, dim3((unsigned)((nhub + 255) / 256)), dim3(256), 0, st, g, hubs, nhub, rows);
         HIP_TRY(hipMemcpyAsync(rp.data(), rows, (size_t)nhub * 16, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
-        std::vector<int32_t> cv;
+        // the sampler's hub running sums come with the gather when every hub's
+        // blocks fit the budget: chunks are then single blocks of HUB_BLOCK
+        std::vector<int64_t> poff((size_t)nhub * (SCC_KMAX + 1), 0);
+        int64_t at = 0;
+        for (int i = 0; i < nhub; i++) {
+            const int64_t nb = (rp[2 * i + 1] - rp[2 * i] + HUB_BLOCK - 1) / HUB_BLOCK;
+            for (int h = 1; h < k; h++) {
+                poff[(size_t)i * (SCC_KMAX + 1) + h] = at;
+                if (h == 1 || s_need[h]) at += 2 * (int64_t)HL.WS[h] * nb;
+            }
+        }
+        fused = at * 8 <= T->hub_prefix_budget;
+        if (fused) {
+            T->hub_chunk = (int)HUB_BLOCK;
+            T->hub_pre = (uint64_t *)T->alloc((size_t)at * 8 + 8);
+            T->hub_poff = (int64_t *)T->alloc(poff.size() * 8);
+            T->hub_index = (int32_t *)T->alloc((size_t)n * 4 + 4);
+            if (!T->hub_pre || !T->hub_poff || !T->hub_index)
+                return set_error(SCC_ENOMEM, "hub running sums (%lld bytes)", (long long)at * 8);
+            HIP_TRY(hipMemcpyAsync(T->hub_poff, poff.data(), poff.size() * 8, hipMemcpyHostToDevice, st));
+            HIP_TRY(hipMemsetAsync(T->hub_index, 0xff, (size_t)n * 4 + 4, st));
+            hipLaunchKernelGGL(k_set_rows, dim3((unsigned)((nhub + 255) / 256)), dim3(256), 0, st, T->hub_index, hubs,
+                               (const int *)nullptr, (int64_t)nhub, 0);
+        }
+        std::vector<int32_t> cv, cq;
         std::vector<int64_t> ce;
         for (int i = 0; i < nhub; i++)
-            for (int64_t e = rp[2 * i]; e < rp[2 * i + 1]; e += T->hub_chunk) { cv.push_back(hh[i]); ce.push_back(e); }
+            for (int64_t e = rp[2 * i]; e < rp[2 * i + 1]; e += T->hub_chunk) {
+                cv.push_back(hh[i]);
+                ce.push_back(e);
+                cq.push_back(i);
+            }
         nchunk = (int64_t)cv.size();
         chunk_v = (int32_t *)get(cv.size() * 4 + 8);
         chunk_e = (int64_t *)get(ce.size() * 8 + 8);
-        if (!chunk_v || !chunk_e) return set_error(SCC_ENOMEM, "hub chunks");
+        chunk_q = (int32_t *)get(cq.size() * 4 + 8);
+        if (!chunk_v || !chunk_e || !chunk_q) return set_error(SCC_ENOMEM, "hub chunks");
         HIP_TRY(hipMemcpyAsync(chunk_v, cv.data(), cv.size() * 4, hipMemcpyHostToDevice, st));
         HIP_TRY(hipMemcpyAsync(chunk_e, ce.data(), ce.size() * 8, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(chunk_q, cq.data(), cq.size() * 4, hipMemcpyHostToDevice, st));
         HIP_TRY(hipStreamSynchronize(st));
         T->hub_host.assign(hh.begin(), hh.end());
         T->hub_rows_host = rp;
@@ -1383,6 +1486,12 @@ static scc_status build_levels(scc_table *T)
     if (!S1.lo || !S1.M) return set_error(SCC_ENOMEM, "level-1 sums");
     HIP_TRY(hipEventRecord(ev[1][0], st));
     if (n) hipLaunchKernelGGL(k_gather1, dim3(grid_of(n)), dim3(WAVE), 0, st, g, k, S1.lo, S1.M);
+    if (fused) {
+        hipLaunchKernelGGL(k_hub_l1_blocks, dim3((unsigned)nchunk), dim3(WAVE), 0, st, g, k, hubs, chunk_e, chunk_q,
+                           T->hub_pre, T->hub_poff);
+        hipLaunchKernelGGL(k_hub_block_scan, dim3((unsigned)((int64_t)nhub * (k - 1))), dim3(WAVE), 0, st, g, hubs,
+                           k - 1, 1, 0, S1.M, T->hub_pre, T->hub_poff);
+    }
     HIP_TRY(hipEventRecord(ev[1][1], st));
     T->gather_bytes[1] = (double)n * 8.0 + (double)T->nnz_g * 5.0 + (double)n * (k - 1) * 8.0;
 
@@ -1420,6 +1529,7 @@ static scc_status build_levels(scc_table *T)
             G.chunk_v = chunk_v; G.chunk_e = chunk_e; G.err = err;
             G.Lut = T->dlut; G.hs = hs; G.bk1 = HL.bk1[hs];
             G.hrow = Sx.hrow; G.wide_rows = gwide; G.wide_count = err + 2;
+            if (fused) { G.hub_pre = T->hub_pre; G.hub_poff = T->hub_poff; G.chunk_q = chunk_q; }
             const size_t lds = gather_lds(HL.WS[hs]);
             const int gs = group_size(HL.WS[hs]);
             const int64_t ngroups = (n + gs - 1) / gs;
@@ -1458,6 +1568,10 @@ static scc_status build_levels(scc_table *T)
             }
             if (nw) hipLaunchKernelGGL(k_gather_wide, dim3((unsigned)nw), dim3(WAVE), lds, st, G);
             HIP_TRY(hipEventRecord(gev[hs][1], st));
+            // the sampler's hub running sums of this level (not part of the gather)
+            if (fused)
+                hipLaunchKernelGGL(k_hub_block_scan, dim3((unsigned)((int64_t)nhub * HL.WS[hs])), dim3(WAVE), 0, st, g,
+                                   hubs, HL.WS[hs], hs, G.rows_zero, Sx.M, T->hub_pre, T->hub_poff);
         }
         // combine into slots: a vertex needing 128 bits waits for the second kernel
         TableLevel &Lv = T->lev[h];
@@ -1516,6 +1630,10 @@ static scc_status build_levels(scc_table *T)
         if (n) hipLaunchKernelGGL(k_meta_sum, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 1024)), dim3(256), 0, st,
                                   n, meta, (unsigned long long *)T->dsum + 2 * h);
         HIP_TRY(hipGetLastError());
+    }
+    if (fused) {
+        T->hub_count_pre = nhub;
+        T->hubpre_ready = true;
     }
     // every level's duration (the stream is drained by the totals that follow)
     HIP_TRY(hipEventSynchronize(ev[k][1]));

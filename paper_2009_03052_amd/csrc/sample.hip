@@ -11,8 +11,6 @@
 
 namespace {
 
-// the hub running sums keep one value per HUB_BLOCK neighbours (one wave's scan)
-constexpr int64_t HUB_BLOCK = WAVE;
 
 
 __device__ inline int key_level(const DevLut &L, uint32_t key)

@@ -6,6 +6,9 @@
 
 #include "device.hpp"
 
+// the sampler's hub running sums keep one value per HUB_BLOCK neighbours
+constexpr int64_t HUB_BLOCK = 64;
+
 struct TableLevel {
     uint64_t *pool = nullptr;   // packed records
     uint64_t pool_words = 0;
