@@ -61,6 +61,50 @@ __device__ inline int64_t wave_search(int64_t len, u128 target, F val)
     return lo + (__ffsll((long long)bal) - 1);
 }
 
+// The draws of one sample, computed together: lane l holds the Philox block of
+// (draw l % 16, attempt l / 16), so a draw reads its first four attempts from
+// four lanes; later attempts (probability below 1/16) are computed one by one.
+// The values are those of draw_below, bit for bit.
+struct DrawCache {
+    uint64_t lo, hi;
+};
+
+__device__ inline DrawCache draw_cache(uint64_t seed, uint64_t stream, uint64_t idx)
+{
+    const uint32_t lane = (uint32_t)lane_id();
+    uint64_t c[4] = {idx, ((uint64_t)(lane % 16) << 32) | (lane / 16), 0, 0};
+    philox4x64_10(c, seed, stream);
+    return DrawCache{c[0], c[1]};
+}
+
+__device__ inline uint64_t readlane64(uint64_t x, int src)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, src);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), src);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ inline u128 draw_cached(const DrawCache &D, u128 N, uint64_t seed, uint64_t stream, uint64_t idx,
+                                   uint32_t draw)
+{
+    if (N <= 1) return 0;
+    if (draw >= 16) return draw_below(N, seed, stream, idx, draw);
+    const int bits = bitlen128(N - 1);
+    const u128 mask = bits >= 128 ? ~(u128)0 : (((u128)1 << bits) - 1);
+    for (uint32_t att = 0; att < 4; att++) {
+        const int src = (int)(draw + 16 * att);
+        const u128 x = mk128(readlane64(D.lo, src), readlane64(D.hi, src)) & mask;
+        if (x < N) return x;
+    }
+    for (uint32_t att = 4; att < 4096u; att++) {
+        uint64_t c[4] = {idx, ((uint64_t)draw << 32) | att, 0, 0};
+        philox4x64_10(c, seed, stream);
+        const u128 x = mk128(c[0], c[1]) & mask;
+        if (x < N) return x;
+    }
+    return N - 1;
+}
+
 // count of (T, C) with the given key at x (level h >= 1)
 __device__ inline u128 own_count(const SampleArgs &A, int h, int64_t x, uint32_t key)
 {
@@ -91,7 +135,8 @@ __device__ inline int sample_star(const SampleArgs &A, int64_t r)
     const int lane = lane_id();
     const int k = A.k;
     const uint64_t idx = A.first + (uint64_t)r;
-    const u128 X = draw_below(A.total, A.seed, A.stream, idx, 0);
+    const DrawCache D = draw_cache(A.seed, A.stream, idx);
+    const u128 X = draw_cached(D, A.total, A.seed, A.stream, idx, 0);
     const int64_t v = wave_search(A.g.n, X, [&](int64_t i) { return A.pre[i]; });
     if (v < 0) return 4;
     const int64_t ra = A.g.row_ptr[v], d = A.g.row_ptr[v + 1] - ra;
@@ -100,7 +145,7 @@ __device__ inline int sample_star(const SampleArgs &A, int64_t r)
     int nm = 0;
     int32_t leaf = (int32_t)v;
     for (int i = 0; i < k - 1; i++) {
-        const int64_t rr = (int64_t)draw_below((u128)(d - i), A.seed, A.stream, idx, 1 + i);
+        const int64_t rr = (int64_t)draw_cached(D, (u128)(d - i), A.seed, A.stream, idx, 1 + i);
         const int64_t last = d - 1 - i;
         const uint64_t hit = __ballot(lane < nm && mpos == rr);
         const uint64_t hitl = __ballot(lane < nm && mpos == last);
@@ -135,6 +180,7 @@ __device__ inline int sample_one(const SampleArgs &A, int64_t r, SampleLds &W)
     const int lane = lane_id();
     const int k = A.k;
     const uint64_t idx = A.first + (uint64_t)r;
+    const DrawCache D = draw_cache(A.seed, A.stream, idx);
     int shape = A.shape;
     const u128 *pre = A.pre;
     u128 total = A.total;
@@ -142,7 +188,7 @@ __device__ inline int sample_one(const SampleArgs &A, int64_t r, SampleLds &W)
     if (A.mode == 1) {
         // shape first: j with running sum of t_j (ascending) exceeding X0, then
         // shape j's draws numbered from 1
-        const u128 X0 = draw_below(A.total, A.seed, A.stream, idx, 0);
+        const u128 X0 = draw_cached(D, A.total, A.seed, A.stream, idx, 0);
         const u128 incl = wave_incl_scan128(lane < L.num_unr ? A.stj[lane] : (u128)0);
         const int j = first_exceeding(incl, X0);
         if (j < 0) return 4;
@@ -152,7 +198,7 @@ __device__ inline int sample_one(const SampleArgs &A, int64_t r, SampleLds &W)
         doff = 1;
     }
     // (1) root: first vertex whose running sum exceeds X, then the entry of its record
-    const u128 X = draw_below(total, A.seed, A.stream, idx, doff);
+    const u128 X = draw_cached(D, total, A.seed, A.stream, idx, doff);
     const int64_t v = wave_search(A.g.n, X, [&](int64_t i) { return pre[i]; });
     if (v < 0) return 4;
     const u128 res = X - (v > 0 ? pre[v - 1] : (u128)0);
@@ -203,7 +249,7 @@ __device__ inline int sample_one(const SampleArgs &A, int64_t r, SampleLds &W)
         const int cx = A.g.colors[x];
         const int hp = L.dec_hp[h][t], hpp = h - hp, a = L.dec_a[h][t], b = L.dec_b[h][t];
         const int beta = L.dec_beta[h][t];
-        const u128 Y = draw_below((u128)beta * cT, A.seed, A.stream, idx, doff + 1 + 2 * dec);
+        const u128 Y = draw_cached(D, (u128)beta * cT, A.seed, A.stream, idx, doff + 1 + 2 * dec);
         // stage 1: C'' among the |T''|-subsets of C \ {c_x}, ascending bitmask
         const uint32_t R = C & ~(1u << cx);
         int ncand = 1;
@@ -238,7 +284,7 @@ __device__ inline int sample_one(const SampleArgs &A, int64_t r, SampleLds &W)
         const u128 Xp = shfl128(xprime, w1);
         const u128 Sv = shfl128(sval, w1);
         // stage 2: neighbour u of x with weight c(T''_{C''}, u), CSR order
-        const u128 Z = draw_below(Sv, A.seed, A.stream, idx, doff + 2 + 2 * dec);
+        const u128 Z = draw_cached(D, Sv, A.seed, A.stream, idx, doff + 2 + 2 * dec);
         const uint32_t kpp = L.off[hpp] + b * L.bk[hpp] + L.colex_k[Cpp];
         const int64_t ra = A.g.row_ptr[x], rb = A.g.row_ptr[x + 1];
         int64_t u = -1;
@@ -336,6 +382,8 @@ __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4, 8)
 // A serving step: rows of many requests (each with its own table, shape and
 // random stream), flattened; row s belongs to the first chunk whose running end
 // exceeds s. The grid strides over the rows.
+// (four waves per SIMD even at the cost of a few spilled registers: measured
+// faster than three waves without spills)
 __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4, 8))) k_serve_sample(const SampleArgs *args, const ServeChunk *ch,
                                                       const int64_t *cend, int nch, int64_t total, int *err)
 {
