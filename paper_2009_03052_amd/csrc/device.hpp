@@ -125,64 +125,87 @@ __device__ inline uint64_t shfl64(uint64_t x, int src)
 }
 __device__ inline u128 shfl128(u128 x, int src) { return mk128(shfl64(lo64(x), src), shfl64(hi64(x), src)); }
 
+// Wave scans on DPP lane moves (no LDS round trips), all 64 lanes active:
+// row_shr 1, 2, 4, 8 scan each row of 16 lanes; row_bcast 15 then adds a row's
+// last lane to the next row (rows 1 and 3), row_bcast 31 adds lane 31 to rows 2
+// and 3. Lanes a move does not reach, or whose source is outside the row,
+// receive 0.
+enum { DPP_SHR1 = 0x111, DPP_SHR2 = 0x112, DPP_SHR4 = 0x114, DPP_SHR8 = 0x118, DPP_BC15 = 0x142, DPP_BC31 = 0x143 };
+
+template <int CTRL, int ROWS>
+__device__ inline uint32_t dpp32(uint32_t x)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROWS, 0xf, true);
+}
+template <int CTRL, int ROWS>
+__device__ inline uint64_t dpp64(uint64_t x)
+{
+    return ((uint64_t)dpp32<CTRL, ROWS>((uint32_t)(x >> 32)) << 32) | dpp32<CTRL, ROWS>((uint32_t)x);
+}
+template <int CTRL, int ROWS>
+__device__ inline u128 dpp128(u128 x)
+{
+    return mk128(dpp64<CTRL, ROWS>(lo64(x)), dpp64<CTRL, ROWS>(hi64(x)));
+}
+
 __device__ inline u128 wave_incl_scan128(u128 x)
 {
-    const int lane = lane_id();
-#pragma unroll
-    for (int d = 1; d < WAVE; d <<= 1) {
-        uint64_t l = (uint64_t)__shfl_up((unsigned long long)lo64(x), d, WAVE);
-        uint64_t h = (uint64_t)__shfl_up((unsigned long long)hi64(x), d, WAVE);
-        if (lane >= d) x += mk128(l, h);
-    }
+    x += dpp128<DPP_SHR1, 0xf>(x);
+    x += dpp128<DPP_SHR2, 0xf>(x);
+    x += dpp128<DPP_SHR4, 0xf>(x);
+    x += dpp128<DPP_SHR8, 0xf>(x);
+    x += dpp128<DPP_BC15, 0xa>(x);
+    x += dpp128<DPP_BC31, 0xc>(x);
     return x;
 }
 
 // inclusive scan that saturates at 2^128 - 1 instead of wrapping
 __device__ inline u128 wave_incl_satscan128(u128 x)
 {
-    const int lane = lane_id();
-#pragma unroll
-    for (int d = 1; d < WAVE; d <<= 1) {
-        uint64_t l = (uint64_t)__shfl_up((unsigned long long)lo64(x), d, WAVE);
-        uint64_t h = (uint64_t)__shfl_up((unsigned long long)hi64(x), d, WAVE);
-        if (lane >= d) x = sat_add(x, mk128(l, h));
-    }
+    x = sat_add(x, dpp128<DPP_SHR1, 0xf>(x));
+    x = sat_add(x, dpp128<DPP_SHR2, 0xf>(x));
+    x = sat_add(x, dpp128<DPP_SHR4, 0xf>(x));
+    x = sat_add(x, dpp128<DPP_SHR8, 0xf>(x));
+    x = sat_add(x, dpp128<DPP_BC15, 0xa>(x));
+    x = sat_add(x, dpp128<DPP_BC31, 0xc>(x));
     return x;
 }
 
 __device__ inline uint32_t wave_incl_scan32(uint32_t x)
 {
-    const int lane = lane_id();
-#pragma unroll
-    for (int d = 1; d < WAVE; d <<= 1) {
-        uint32_t y = __shfl_up(x, d, WAVE);
-        if (lane >= d) x += y;
-    }
+    x += dpp32<DPP_SHR1, 0xf>(x);
+    x += dpp32<DPP_SHR2, 0xf>(x);
+    x += dpp32<DPP_SHR4, 0xf>(x);
+    x += dpp32<DPP_SHR8, 0xf>(x);
+    x += dpp32<DPP_BC15, 0xa>(x);
+    x += dpp32<DPP_BC31, 0xc>(x);
     return x;
 }
 
-__device__ inline u128 wave_sum128(u128 x)
+__device__ inline uint64_t wave_incl_scan64(uint64_t x)
 {
-#pragma unroll
-    for (int d = WAVE / 2; d >= 1; d >>= 1)
-        x += mk128(shfl64(lo64(x), lane_id() ^ d), shfl64(hi64(x), lane_id() ^ d));
+    x += dpp64<DPP_SHR1, 0xf>(x);
+    x += dpp64<DPP_SHR2, 0xf>(x);
+    x += dpp64<DPP_SHR4, 0xf>(x);
+    x += dpp64<DPP_SHR8, 0xf>(x);
+    x += dpp64<DPP_BC15, 0xa>(x);
+    x += dpp64<DPP_BC31, 0xc>(x);
     return x;
 }
 
-__device__ inline u128 wave_satsum128(u128 x)
+// value of lane 63, uniform
+__device__ inline uint64_t last_lane64(uint64_t x)
 {
-#pragma unroll
-    for (int d = WAVE / 2; d >= 1; d >>= 1)
-        x = sat_add(x, mk128(shfl64(lo64(x), lane_id() ^ d), shfl64(hi64(x), lane_id() ^ d)));
-    return x;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, WAVE - 1);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), WAVE - 1);
+    return ((uint64_t)hi << 32) | lo;
 }
+__device__ inline u128 last_lane128(u128 x) { return mk128(last_lane64(lo64(x)), last_lane64(hi64(x))); }
 
-__device__ inline uint64_t wave_sum64(uint64_t x)
-{
-#pragma unroll
-    for (int d = WAVE / 2; d >= 1; d >>= 1) x += shfl64(x, lane_id() ^ d);
-    return x;
-}
+// totals over the wave, in every lane
+__device__ inline u128 wave_sum128(u128 x) { return last_lane128(wave_incl_scan128(x)); }
+__device__ inline u128 wave_satsum128(u128 x) { return last_lane128(wave_incl_satscan128(x)); }
+__device__ inline uint64_t wave_sum64(uint64_t x) { return last_lane64(wave_incl_scan64(x)); }
 
 __device__ inline uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
 
