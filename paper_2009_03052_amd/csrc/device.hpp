@@ -193,6 +193,17 @@ __device__ inline uint64_t wave_incl_scan64(uint64_t x)
     return x;
 }
 
+__device__ inline uint32_t wave_incl_max32(uint32_t x)
+{
+    x = max(x, dpp32<DPP_SHR1, 0xf>(x));
+    x = max(x, dpp32<DPP_SHR2, 0xf>(x));
+    x = max(x, dpp32<DPP_SHR4, 0xf>(x));
+    x = max(x, dpp32<DPP_SHR8, 0xf>(x));
+    x = max(x, dpp32<DPP_BC15, 0xa>(x));
+    x = max(x, dpp32<DPP_BC31, 0xc>(x));
+    return x;
+}
+
 // value of lane 63, uniform
 __device__ inline uint64_t last_lane64(uint64_t x)
 {

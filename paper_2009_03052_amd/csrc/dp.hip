@@ -176,7 +176,41 @@ __device__ inline size_t hi_row(const int32_t *hrow, int64_t v) { return hrow ? 
 
 // most keys on one level: r_6 C(8, 6) = 560 at k = 8
 constexpr int GATHER_MAX_KEYS = 576;
-__host__ __device__ inline size_t gather_lds(int WS) { return (size_t)2 * WS * 8 + GATHER_MAX_KEYS * 2; }
+// Entries of a chunk of 64 neighbours are spread over the lanes 256 at a time;
+// the neighbour owning entry position p is found by marking where every
+// neighbour's entries start and taking a running maximum over the positions.
+struct OwnerLds {
+    uint32_t mark[4 * WAVE];   // 1 + the neighbour lane whose entries start here, or 0
+    uint64_t hd[WAVE];         // record handle of each neighbour lane
+    uint32_t start[WAVE];      // first entry position of each neighbour lane
+    uint32_t tag[WAVE];        // grouped rows: slot | colour << 8 of the lane's row
+};
+
+__host__ __device__ inline size_t gather_lds(int WS)
+{
+    return (size_t)2 * WS * 8 + GATHER_MAX_KEYS * 2 + sizeof(OwnerLds);
+}
+
+// owners own[q] of positions q0 + q * WAVE + lane (q = 0..3) among the chunk's
+// neighbour lanes, each holding its first position s and entry count len
+__device__ inline void round_owners(OwnerLds &O, uint32_t q0, uint32_t s, uint32_t len, int own[4])
+{
+    const int lane = lane_id();
+#pragma unroll
+    for (int q = 0; q < 4; q++) O.mark[q * WAVE + lane] = 0;
+    __syncthreads();
+    if (len && s >= q0 && s < q0 + 4 * WAVE) O.mark[s - q0] = (uint32_t)lane + 1;
+    __syncthreads();
+    // 1 + the owner of position q0: the last lane with entries starting at or before it
+    const uint64_t before = __ballot(len != 0 && s <= q0);
+    uint32_t carry = before ? (uint32_t)(WAVE - __clzll((long long)before)) : 0u;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        const uint32_t m = max(wave_incl_max32(O.mark[q * WAVE + lane]), carry);
+        carry = (uint32_t)__builtin_amdgcn_readlane((int)m, WAVE - 1);
+        own[q] = (int)m - 1;
+    }
+}
 
 // Adds the level-hs entries of neighbours col_idx[a..b) of v into the LDS sums
 // and returns (in every lane) the saturating sum of those neighbours' level
@@ -185,7 +219,7 @@ __host__ __device__ inline size_t gather_lds(int WS) { return (size_t)2 * WS * 8
 // at most the bound.
 template <bool SLOTS>
 __device__ inline u128 gather_range(const GatherArgs &A, int64_t a, int64_t b, bool wideS, uint64_t *acc_lo,
-                                    uint64_t *acc_hi, const int16_t *ssm)
+                                    uint64_t *acc_hi, const int16_t *ssm, OwnerLds &O)
 {
     const int lane = threadIdx.x;
     u128 m = 0;
@@ -195,33 +229,27 @@ __device__ inline u128 gather_range(const GatherArgs &A, int64_t a, int64_t b, b
         const uint32_t len = e < b ? h_len<SLOTS>(hd) : 0u;
         if (len) m = sat_add(m, h_N<SLOTS>(A.L, hd));
         const uint32_t incl = wave_incl_scan32(len);
-        const uint32_t total = __shfl(incl, WAVE - 1, WAVE);
+        const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, WAVE - 1);
+        const uint32_t first = incl - len;
+        O.hd[lane] = hd;
+        O.start[lane] = first;
         // entries of this chunk of neighbours, flattened over the lanes; every lane
         // takes 4 entries per round and issues their loads before using any
         for (uint32_t p0 = 0; p0 < total; p0 += 4 * WAVE) {
             uint32_t key[4];
             uint64_t cl[4], ch[4];
             bool ok[4];
+            int own[4];
+            round_owners(O, p0, first, len, own);
 #pragma unroll
             for (int q = 0; q < 4; q++) {
                 const uint32_t p = p0 + q * WAVE + lane;
-                // owner neighbour j: number of lanes whose inclusive count is <= p
-                // (fixed six steps, so every lane takes part in every shuffle)
-                int j = 0;
-#pragma unroll
-                for (int step = WAVE / 2; step >= 1; step >>= 1) {
-                    const uint32_t x = __shfl(incl, j + step - 1, WAVE);
-                    if (x <= p) j += step;
-                }
-                if (j > WAVE - 1) j = WAVE - 1;
-                const uint32_t incl_j = __shfl(incl, j, WAVE);
-                const uint64_t hd_j = shfl64(hd, j);
                 ok[q] = p < total;
                 key[q] = 0;
                 cl[q] = ch[q] = 0;
                 if (ok[q]) {
-                    const RecView<SLOTS> r = h_rec<SLOTS>(A.L, hd_j);
-                    const uint32_t ei = p - (incl_j - r.len);
+                    const RecView<SLOTS> r = h_rec<SLOTS>(A.L, O.hd[own[q]]);
+                    const uint32_t ei = p - O.start[own[q]];
                     key[q] = r.key[ei];
                     cl[q] = r.lo[ei];
                     if (wideS && r.hi) ch[q] = r.hi[ei];
@@ -241,6 +269,7 @@ __device__ inline u128 gather_range(const GatherArgs &A, int64_t a, int64_t b, b
                 }
             }
         }
+        __syncthreads();   // the next chunk rewrites the lane table
     }
     return wave_satsum128(m);
 }
@@ -258,6 +287,7 @@ __device__ inline u128 gather_sums(const GatherArgs &A, int cv, int64_t a, int64
     const int lane = threadIdx.x;
     const int WS = A.WS;
     int16_t *ssm = (int16_t *)(acc_hi + WS);
+    OwnerLds &O = *(OwnerLds *)(ssm + GATHER_MAX_KEYS);
     const int16_t *sidx = A.key_sidx + (size_t)cv * A.nkeys + A.key_lo;
     for (int i = lane; i < A.key_n; i += WAVE) ssm[i] = sidx[i];
     for (int i = lane; i < WS; i += WAVE) { acc_lo[i] = 0; acc_hi[i] = 0; }
@@ -265,14 +295,14 @@ __device__ inline u128 gather_sums(const GatherArgs &A, int cv, int64_t a, int64
     u128 m = 0;
     wideS = mode == GS_WIDE;
     if (!wideS) {
-        m = gather_range<SLOTS>(A, a, b, false, acc_lo, acc_hi, ssm);
+        m = gather_range<SLOTS>(A, a, b, false, acc_lo, acc_hi, ssm, O);
         wideS = hi64(m) != 0;
     }
     if (wideS && mode != GS_DEFER) {
         __syncthreads();
         for (int i = lane; i < WS; i += WAVE) { acc_lo[i] = 0; acc_hi[i] = 0; }
         __syncthreads();
-        m = gather_range<SLOTS>(A, a, b, true, acc_lo, acc_hi, ssm);
+        m = gather_range<SLOTS>(A, a, b, true, acc_lo, acc_hi, ssm, O);
     }
     __syncthreads();
     return m;
@@ -386,6 +416,7 @@ __device__ inline void gather_group(const GatherArgs &A, int64_t v0, int G, uint
     }
     const uint64_t mine_mask = __ballot(mine);
     if (!mine_mask) return;
+    OwnerLds &O = *(OwnerLds *)((int16_t *)(wsm + 2 * WS) + GATHER_MAX_KEYS);
     const uint32_t dincl = wave_incl_scan32(dj);
     const uint32_t E = __shfl(dincl, WAVE - 1, WAVE);
     for (int i = lane; i < nv * WS; i += WAVE) acc[i] = 0;
@@ -423,32 +454,32 @@ __device__ inline void gather_group(const GatherArgs &A, int64_t v0, int G, uint
         }
         // the entries of these neighbours, flattened, 4 per lane per round
         const uint32_t incl = wave_incl_scan32(len);
-        const uint32_t total = __shfl(incl, WAVE - 1, WAVE);
+        const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, WAVE - 1);
+        const uint32_t first = incl - len;
+        const int cv_s = __shfl(cvj, js, WAVE);
+        O.hd[lane] = hd;
+        O.start[lane] = first;
+        O.tag[lane] = (uint32_t)js | ((uint32_t)cv_s << 8);
         for (uint32_t q0 = 0; q0 < total; q0 += 4 * WAVE) {
             uint32_t key[4];
             uint64_t cl[4];
             int slot[4], cv[4];
             bool ok[4];
+            int own[4];
+            round_owners(O, q0, first, len, own);
 #pragma unroll
             for (int q = 0; q < 4; q++) {
                 const uint32_t pe = q0 + q * WAVE + lane;
-                int j = 0;
-#pragma unroll
-                for (int step = WAVE / 2; step >= 1; step >>= 1) {
-                    const uint32_t x = __shfl(incl, j + step - 1, WAVE);
-                    if (x <= pe) j += step;
-                }
-                if (j > WAVE - 1) j = WAVE - 1;
-                const uint32_t incl_j = __shfl(incl, j, WAVE);
-                const uint64_t hd_j = shfl64(hd, j);
-                slot[q] = __shfl(js, j, WAVE);
-                cv[q] = __shfl(cvj, slot[q], WAVE);
                 ok[q] = pe < total;
                 key[q] = 0;
                 cl[q] = 0;
+                slot[q] = cv[q] = 0;
                 if (ok[q]) {
-                    const RecView<SLOTS> r = h_rec<SLOTS>(A.L, hd_j);
-                    const uint32_t ei = pe - (incl_j - r.len);
+                    const uint32_t tag = O.tag[own[q]];
+                    slot[q] = (int)(tag & 0xffu);
+                    cv[q] = (int)(tag >> 8);
+                    const RecView<SLOTS> r = h_rec<SLOTS>(A.L, O.hd[own[q]]);
+                    const uint32_t ei = pe - O.start[own[q]];
                     key[q] = r.key[ei];
                     cl[q] = r.lo[ei];
                 }
@@ -463,6 +494,7 @@ __device__ inline void gather_group(const GatherArgs &A, int64_t v0, int G, uint
                 atomicAdd((unsigned long long *)&acc[slot[q] * WS + s], (unsigned long long)cl[q]);
             }
         }
+        __syncthreads();   // the next chunk rewrites the lane table
     }
     __syncthreads();
     // rows whose bound reaches 2^64 are redone alone with 128-bit sums
