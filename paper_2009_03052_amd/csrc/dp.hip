@@ -712,13 +712,22 @@ __global__ void k_hub_list(GraphView g, int hub_degree, int32_t *hubs, int *coun
 // (count[1]) and the number of rows of at most GROUP_LOW_DEG neighbours (count[2])
 __global__ void k_row_lists(GraphView g, int hub_degree, int32_t *hubs, int32_t *mids, int *count)
 {
+    // one atomic per wave and list: lanes take consecutive places by their rank
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t d = v < g.n ? g.row_ptr[v + 1] - g.row_ptr[v] : 0;
     const uint64_t low = __ballot(v < g.n && d <= GROUP_LOW_DEG);
-    if (lane_id() == 0 && low) atomicAdd(&count[2], __popcll(low));
-    if (v >= g.n) return;
-    if (d > hub_degree) hubs[atomicAdd(&count[0], 1)] = (int32_t)v;
-    else if (d > GROUP_DEG) mids[atomicAdd(&count[1], 1)] = (int32_t)v;
+    const bool hub = v < g.n && d > hub_degree, mid = v < g.n && !hub && d > GROUP_DEG;
+    const uint64_t hm = __ballot(hub), mm = __ballot(mid);
+    int hbase = 0, mbase = 0;
+    if (lane_id() == 0) {
+        if (low) atomicAdd(&count[2], __popcll(low));
+        if (hm) hbase = atomicAdd(&count[0], __popcll(hm));
+        if (mm) mbase = atomicAdd(&count[1], __popcll(mm));
+    }
+    hbase = __shfl(hbase, 0, WAVE);
+    mbase = __shfl(mbase, 0, WAVE);
+    if (hub) hubs[hbase + __popcll(hm & lanemask_lt())] = (int32_t)v;
+    if (mid) mids[mbase + __popcll(mm & lanemask_lt())] = (int32_t)v;
 }
 
 // ---------------------------------------------------------------------------
