@@ -375,15 +375,15 @@ def run_serving(a):
     opts = dict(hbm_budget=24 << 30, step_samples=1 << 16, chunk=4096, max_active=512)
     cbar = 1000
 
-    def server(fifo, ags_weight=1.0):
-        srv = scc.Server(tabs, fifo=fifo, ags_weight=ags_weight, **opts)
+    def server(fifo, ags_weight=1.0, age_tau=0.0):
+        srv = scc.Server(tabs, fifo=fifo, ags_weight=ags_weight, age_tau=age_tau, **opts)
         sessions = [srv.ags_open(t, cbar=cbar, seed=900 + t, stream_id=t) for t in range(len(tabs))]
         return srv, sessions
 
     # saturated rates: a burst of the first requests, all submitted at once, in each mode
     sat = {}
     for name, fifo in (("continuous", False), ("fifo", True)):
-        srv, sess = server(fifo)
+        srv, sess = server(fifo, 1.0, 0.0 if fifo else 0.01)
         sat[name] = drive(srv, trace[:min(300, len(trace))], float("inf"), sess, 1e9)["samples_per_s"]
         srv.close()
         print(f"# saturated {name}: {sat[name] / 1e6:.1f} M samples/s", file=sys.stderr, flush=True)
@@ -394,9 +394,12 @@ def run_serving(a):
     print(f"# saturated: {burst['samples_per_s'] / 1e6:.1f} M samples/s = {sat_req:.1f} requests/s; "
           f"Poisson rate {rate:.1f}/s", file=sys.stderr, flush=True)
     res = {}
-    for name, fifo, aw in (("continuous", False, 1.0), ("continuous_ags4", False, 4.0),
-                           ("continuous_ags16", False, 16.0), ("fifo", True, 1.0)):
-        srv, sess = server(fifo, aw)
+    # continuous: shares weighted by age (tau 10 ms), which bounds the tail of large
+    # requests; the plain equal shares and heavier AGS rounds are reported beside it
+    for name, fifo, aw, tau in (("continuous", False, 1.0, 0.01), ("continuous_equal", False, 1.0, 0.0),
+                                ("continuous_ags16", False, 16.0, 0.0), ("continuous_age2ms", False, 1.0, 0.002),
+                                ("fifo", True, 1.0, 0.0)):
+        srv, sess = server(fifo, aw, tau)
         res[name] = drive(srv, trace, rate, sess, a.window)
         srv.close()
         r = res[name]
@@ -409,8 +412,8 @@ def run_serving(a):
             "arena_peak", "uniform_p50_ms", "uniform_p99_ms", "ags_p50_ms", "ags_p99_ms")
     out = {
         "metric": "DP table build s & colorful-treelet samples/sec, batched/served vs plain",
-        "value": c["samples_per_s"], "unit": "samples/s served (continuous batching, Poisson arrivals at 0.7x "
-                                             "saturation, submission to completion)",
+        "value": c["samples_per_s"], "unit": "samples/s served (continuous batching with age-weighted shares, "
+                                             "Poisson arrivals at 0.7x saturation, submission to completion)",
         "n_gpus": 1, "steps": c["completed"], "warmup": 0, "ms_per_step": c["mean_ms"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u64/u128", "data": "synthetic",
         "config": {"workload": "serving: 3 resident k=7 tables (Chung-Lu n=2e6 m=3e7, exponents 2.1/2.4/2.8, "
@@ -421,8 +424,10 @@ def run_serving(a):
         "saturated_samples_per_s": sat["continuous"], "saturated_samples_per_s_fifo": sat["fifo"],
         "saturated_throughput_vs_fifo": sat["continuous"] / sat["fifo"] if sat["fifo"] > 0 else None,
         "continuous": {k: c[k] for k in keep}, "fifo": {k: f[k] for k in keep},
-        "continuous_ags_weight_4": {k: res["continuous_ags4"][k] for k in keep},
-        "continuous_ags_weight_16": {k: res["continuous_ags16"][k] for k in keep},
+        "age_tau_s": 0.01,
+        "continuous_equal_shares": {k: res["continuous_equal"][k] for k in keep},
+        "continuous_equal_ags_weight_16": {k: res["continuous_ags16"][k] for k in keep},
+        "continuous_age_tau_2ms": {k: res["continuous_age2ms"][k] for k in keep},
         "p99_speedup_vs_fifo": f["p99_ms"] / c["p99_ms"] if c["p99_ms"] > 0 else None,
         "p50_speedup_vs_fifo": f["p50_ms"] / c["p50_ms"] if c["p50_ms"] > 0 else None,
         "throughput_vs_fifo": c["samples_per_s"] / f["samples_per_s"] if f["samples_per_s"] > 0 else None,

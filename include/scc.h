@@ -401,6 +401,9 @@ typedef struct {
                                 request (a session's later rounds wait for it); 0 = 1 */
     void *stream;            /* hipStream_t of the server's work (NULL: its own stream) */
     const scc_allocator *alloc; /* for the budget and the server's buffers (NULL: hipMalloc) */
+    double age_tau;          /* > 0: a request's share also grows with its age, by the
+                                factor 1 + (seconds since submission) / age_tau, so that
+                                long-waiting requests finish first (tail latency); 0: off */
 } scc_server_opts;
 
 enum { SCC_REQ_SAMPLE = 0, SCC_REQ_AGS_ROUND = 1 };

@@ -230,14 +230,20 @@ bool scc_server::build_step_locked(int b)
         cand.assign(1, id);
     }
     // weighted shares of the step: an AGS round (which holds up its session's later
-    // rounds) weighs ags_weight, a sample request 1; every share is at least `chunk`
+    // rounds) weighs ags_weight, a sample request 1, times 1 + age / age_tau when
+    // age weighting is on; every share is at least `chunk`
+    const double tnow = now_s(t0);
+    auto weight = [&](const Request &r) {
+        const double w = r.q.kind == SCC_REQ_AGS_ROUND ? o.ags_weight : 1.0;
+        return o.age_tau > 0 ? w * (1.0 + (tnow - r.t_submit) / o.age_tau) : w;
+    };
     double wsum = 0;
-    for (int64_t id : cand) wsum += reqs[id].q.kind == SCC_REQ_AGS_ROUND ? o.ags_weight : 1.0;
+    for (int64_t id : cand) wsum += weight(reqs[id]);
     const size_t nc = cand.size();
     for (size_t q = 0; q < nc; q++) {
         const int64_t id = cand[(rr + q) % nc];
         Request &r = reqs[id];
-        const double w = r.q.kind == SCC_REQ_AGS_ROUND ? o.ags_weight : 1.0;
+        const double w = weight(r);
         const int64_t quota = o.fifo ? INT64_MAX
                                      : std::max<int64_t>(o.chunk, (int64_t)((double)o.step_samples * w / wsum));
         const int64_t c = std::min(quota, r.q.n - r.assigned);
