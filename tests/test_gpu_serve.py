@@ -6,7 +6,7 @@ per table. Each sample request must equal scc_sample / scc_classify called on
 its own with the same (table, shape, seed, stream, first index), and one is
 also checked against the oracle; each AGS session must pick the shapes and
 reach the counts of scc_ags with the same round size (and of the oracle's AGS).
-The first-in first-out mode must give the same rows. Admission: a request that
+The first-in first-out mode and age-weighted shares must give the same rows. Admission: a request that
 does not fit the budget waits until earlier outputs are released; a request
 larger than the budget is refused with ENOMEM, and a full queue with EBUSY.
 """
@@ -139,14 +139,18 @@ def test_fifo_mode_gives_the_same_rows():
     reqs = _requests(tabs, 12, seed=11)
     mix = S.Server([t[3] for t in tabs], hbm_budget=32 << 20, step_samples=2048, chunk=128)
     fifo = S.Server([t[3] for t in tabs], hbm_budget=32 << 20, fifo=True)
+    aged = S.Server([t[3] for t in tabs], hbm_budget=32 << 20, step_samples=2048, chunk=128, age_tau=0.002)
     a = _run(mix, reqs, [], 0, 1)
     b = _run(fifo, reqs, [], 0, 1)
-    for ra, rb in zip(a, b):
+    c = _run(aged, reqs, [], 0, 1)
+    for ra, rb, rc in zip(a, b, c):
         assert np.array_equal(ra["verts"].cpu().numpy(), rb["verts"].cpu().numpy())
         assert np.array_equal(ra["parent"].cpu().numpy(), rb["parent"].cpu().numpy())
+        assert np.array_equal(ra["verts"].cpu().numpy(), rc["verts"].cpu().numpy())
     assert fifo.stats()["steps"] >= len(reqs)
     mix.close()
     fifo.close()
+    aged.close()
 
 
 def test_admission_by_budget():
