@@ -317,22 +317,22 @@ __device__ inline int sample_one(const SampleArgs &A, int64_t r, SampleLds &W)
                 }
             }
         } else {
-            // CSR order, 4 x 64 neighbours per round: every lane issues the loads of
-            // its 4 neighbours before using any, then the 4 groups are scanned in order
+            // CSR order, 2 x 64 neighbours per round: every lane issues the loads of
+            // its 2 neighbours before using any, then the 2 groups are scanned in order
             u128 run2 = 0;
             bool found = false;
-            for (int64_t base = ra; base < rb && !found; base += 4 * WAVE) {
-                int32_t uu[4];
-                u128 c[4];
+            for (int64_t base = ra; base < rb && !found; base += 2 * WAVE) {
+                int32_t uu[2];
+                u128 c[2];
 #pragma unroll
-                for (int g4 = 0; g4 < 4; g4++) {
+                for (int g4 = 0; g4 < 2; g4++) {
                     const int64_t e = base + g4 * WAVE + lane;
                     uu[g4] = e < rb ? A.g.col_idx[e] : -1;
                 }
 #pragma unroll
-                for (int g4 = 0; g4 < 4; g4++) c[g4] = uu[g4] >= 0 ? own_count(A, hpp, uu[g4], kpp) : (u128)0;
+                for (int g4 = 0; g4 < 2; g4++) c[g4] = uu[g4] >= 0 ? own_count(A, hpp, uu[g4], kpp) : (u128)0;
 #pragma unroll
-                for (int g4 = 0; g4 < 4; g4++) {
+                for (int g4 = 0; g4 < 2; g4++) {
                     if (found) break;
                     const u128 incl = run2 + wave_incl_scan128(c[g4]);
                     const int w2 = first_exceeding(incl, Z);
@@ -367,9 +367,9 @@ __device__ inline int sample_one(const SampleArgs &A, int64_t r, SampleLds &W)
     return 0;
 }
 
-// four waves per SIMD fit without spilling; the draws are latency-bound, so
-// more waves in flight beat more registers
-__global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4, 8))) k_sample(SampleArgs A)
+// the draws are latency-bound: five waves per SIMD (a few registers spilled)
+// measured faster than four without spills and than six
+__global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(5, 8))) k_sample(SampleArgs A)
 {
     __shared__ SampleLds W;
     for (int64_t s = blockIdx.x; s < A.nsamp; s += gridDim.x) {
