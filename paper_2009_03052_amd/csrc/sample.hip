@@ -382,9 +382,8 @@ __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(5, 8)
 // A serving step: rows of many requests (each with its own table, shape and
 // random stream), flattened; row s belongs to the first chunk whose running end
 // exceeds s. The grid strides over the rows.
-// (four waves per SIMD even at the cost of a few spilled registers: measured
-// faster than three waves without spills)
-__global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4, 8))) k_serve_sample(const SampleArgs *args, const ServeChunk *ch,
+// (five waves per SIMD, as the plain sampler)
+__global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(5, 8))) k_serve_sample(const SampleArgs *args, const ServeChunk *ch,
                                                       const int64_t *cend, int nch, int64_t total, int *err)
 {
     __shared__ SampleLds W;
