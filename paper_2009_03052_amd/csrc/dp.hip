@@ -709,25 +709,30 @@ __global__ void k_hub_list(GraphView g, int hub_degree, int32_t *hubs, int *coun
 }
 
 // hub rows (count[0]), the rows between the grouped ones and the hubs
-// (count[1]) and the number of rows of at most GROUP_LOW_DEG neighbours (count[2])
-__global__ void k_row_lists(GraphView g, int hub_degree, int32_t *hubs, int32_t *mids, int *count)
+// (count[1]), the number of rows of at most GROUP_LOW_DEG neighbours (count[2])
+// and the colour-0 rows (count[3]), each list in no particular order
+__global__ void k_row_lists(GraphView g, int hub_degree, int32_t *hubs, int32_t *mids, int32_t *zrows, int *count)
 {
     // one atomic per wave and list: lanes take consecutive places by their rank
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t d = v < g.n ? g.row_ptr[v + 1] - g.row_ptr[v] : 0;
     const uint64_t low = __ballot(v < g.n && d <= GROUP_LOW_DEG);
     const bool hub = v < g.n && d > hub_degree, mid = v < g.n && !hub && d > GROUP_DEG;
-    const uint64_t hm = __ballot(hub), mm = __ballot(mid);
-    int hbase = 0, mbase = 0;
+    const bool zero = v < g.n && g.colors[v] == 0;
+    const uint64_t hm = __ballot(hub), mm = __ballot(mid), zm = __ballot(zero);
+    int hbase = 0, mbase = 0, zbase = 0;
     if (lane_id() == 0) {
         if (low) atomicAdd(&count[2], __popcll(low));
         if (hm) hbase = atomicAdd(&count[0], __popcll(hm));
         if (mm) mbase = atomicAdd(&count[1], __popcll(mm));
+        if (zm) zbase = atomicAdd(&count[3], __popcll(zm));
     }
     hbase = __shfl(hbase, 0, WAVE);
     mbase = __shfl(mbase, 0, WAVE);
+    zbase = __shfl(zbase, 0, WAVE);
     if (hub) hubs[hbase + __popcll(hm & lanemask_lt())] = (int32_t)v;
     if (mid) mids[mbase + __popcll(mm & lanemask_lt())] = (int32_t)v;
+    if (zero) zrows[zbase + __popcll(zm & lanemask_lt())] = (int32_t)v;
 }
 
 // ---------------------------------------------------------------------------
@@ -751,6 +756,10 @@ struct CombineArgs {
     u128 *Nout;
     int *err;                             // [0]: overflow
 };
+
+__device__ inline void combine_outputs(const CombineArgs &A, int64_t v, int cv, const uint64_t *Xlo,
+                                       const uint64_t *Slo, const uint64_t *Xhi, const uint64_t *Shi, bool owide,
+                                       bool wide);
 
 // Counts of vertex v at level h. The low words of v's own counts X and of its
 // neighbour sums S are staged in lo_area (LDS); high words are needed only when
@@ -825,11 +834,22 @@ __device__ inline void combine_vertex(const CombineArgs &A, int64_t v, uint64_t 
         }
     }
     __syncthreads();
+    combine_outputs(A, v, cv, Xlo, Slo, Xhi, Shi, owide, wide);
+}
 
+// The outputs of vertex v at level h from its staged counts (X) and neighbour
+// sums (S): lane o evaluates outputs o, o + 64, ..., and the nonzero ones are
+// compacted into v's slot right away (ballot + prefix count keeps ascending
+// key order).
+__device__ inline void combine_outputs(const CombineArgs &A, int64_t v, int cv, const uint64_t *Xlo,
+                                       const uint64_t *Slo, const uint64_t *Xhi, const uint64_t *Shi, bool owide,
+                                       bool wide)
+{
+    const DevLut &L = *A.L;
+    const int lane = threadIdx.x;
+    const int h = A.h;
     const int Wh = L.W[h];
     const int nD = L.bk1[h - 1];
-    // each lane evaluates outputs o = r * 64 + lane; the nonzero ones are compacted
-    // into v's slot right away (ballot + prefix count keeps ascending key order)
     uint32_t cnt = 0;
     u128 nsum = 0;
     uint16_t *sk = A.slot_key + (size_t)v * A.W;
@@ -888,17 +908,140 @@ __device__ inline void combine_vertex(const CombineArgs &A, int64_t v, uint64_t 
     }
 }
 
+// The same counts for a packed table, with the loads ordered for latency: every
+// load that depends on v alone goes out first (lane q < PMAX + 1 takes level q's
+// record handle and neighbour-sum bound; every lane takes its first word of each
+// level's neighbour sums), then the level sums and the first entry per lane of
+// each own record, then the key index of those entries. A wave thus waits about
+// two memory latencies before the products instead of one per dependent step.
+// PMAX bounds the levels unrolled (PMAX >= h - 1); longer rows and records are
+// finished by loops, and high words (wide) are staged by loops as well.
+template <int PMAX>
+__device__ inline void combine_vertex_pf(const CombineArgs &A, int64_t v, uint64_t *lo_area, uint64_t *hi_area,
+                                         int *wide_list, int *wide_count)
+{
+    const DevLut &L = *A.L;
+    const int lane = threadIdx.x;
+    const int h = A.h;
+    const int cv = A.g.colors[v];
+    if (A.zero_only && cv != 0) {
+        if (lane == 0) { A.meta[v] = 0; A.Nout[v] = 0; }
+        return;
+    }
+    const int plo = A.bal ? 2 : 1, phi = A.bal ? h - 2 : h - 1;
+    const uint64_t *locp = nullptr, *poolp = nullptr;
+    const u128 *mp = nullptr;
+#pragma unroll
+    for (int q = 1; q <= PMAX; q++)
+        if (lane == q && q <= phi) {
+            mp = A.M[q];
+            if (q >= 2) { locp = A.lev[q].P.loc; poolp = A.lev[q].P.pool; }
+        }
+    const uint64_t hd = locp ? locp[v] : 0ull;      // lane q: handle of v's level-q record
+    const u128 Mq = mp ? mp[v] : (u128)0;            // lane q: M_q(v) (0: sums not built)
+    uint64_t sw[PMAX + 1];
+#pragma unroll
+    for (int q = 1; q <= PMAX; q++) {
+        sw[q] = 0;
+        if (q <= phi && A.Slo[q] && lane < L.WS[q]) sw[q] = A.Slo[q][(size_t)v * L.WS[q] + lane];
+    }
+    const uint64_t *rp = LOC_LEN(hd) ? poolp + LOC_OFF(hd) : nullptr;
+    const u128 Nq = rp ? mk128(rp[0], rp[1]) : (u128)0;
+    uint32_t ek[PMAX + 1];
+    uint64_t el[PMAX + 1];
+#pragma unroll
+    for (int q = 2; q <= PMAX; q++) {
+        ek[q] = 0;
+        el[q] = 0;
+        if (q <= phi) {
+            const uint64_t hq = readlane64(hd, q);
+            const uint32_t len = LOC_LEN(hq);
+            if ((uint32_t)lane < len) {
+                const uint64_t *p = A.lev[q].P.pool + LOC_OFF(hq) + REC_HDR;
+                ek[q] = ((const uint16_t *)p)[lane];
+                el[q] = p[key_words(len) + lane];
+            }
+        }
+    }
+    // bound: lane hp contributes N_hp(v) M_{h-hp}(v) (level 1: N = 1)
+    const u128 Mpair = shfl128(Mq, (h - lane) & (WAVE - 1));
+    u128 term = 0;
+    if (lane >= plo && lane <= phi) term = sat_mul(lane == 1 ? (u128)1 : Nq, Mpair);
+    const u128 U = wave_satsum128(term);
+    if (U == ~(u128)0 || bitlen128(U) > A.max_bits) {
+        if (lane == 0) { atomicOr(A.err, 1); A.meta[v] = 0; A.Nout[v] = 0; }
+        return;
+    }
+    const bool owide = hi64(U) != 0;
+    bool wide = false;
+    if (owide)
+        wide = __ballot(lane <= phi && ((lane >= 2 && LOC_WIDE(hd)) || (lane >= 1 && hi64(Mq) != 0))) != 0;
+    if (wide && !hi_area) {
+        if (lane == 0) wide_list[atomicAdd(wide_count, 1)] = (int)v;
+        return;
+    }
+    const int XT = L.xoff[h];
+    uint64_t *Xlo = lo_area, *Slo = lo_area + XT;
+    uint64_t *Xhi = hi_area, *Shi = hi_area + XT;
+    for (int i = lane; i < XT; i += WAVE) {
+        Xlo[i] = 0;
+        if (wide) Xhi[i] = 0;
+    }
+#pragma unroll
+    for (int q = 1; q <= PMAX; q++)
+        if (q <= phi && A.Slo[q] && lane < L.WS[q]) Slo[L.soff[q] + lane] = sw[q];
+    for (int hs = 1; hs <= phi; hs++) {
+        if (!A.Slo[hs]) continue;
+        const int ws = L.WS[hs];
+        const uint64_t *gl = A.Slo[hs] + (size_t)v * ws;
+        for (int i = WAVE + lane; i < ws; i += WAVE) Slo[L.soff[hs] + i] = gl[i];
+        if (wide) {
+            const bool sw128 = hi64(A.M[hs][v]) != 0;
+            const uint64_t *gh = sw128 ? A.Shi[hs] + hi_row(A.Shrow[hs], v) * ws : nullptr;
+            for (int i = lane; i < ws; i += WAVE) Shi[L.soff[hs] + i] = sw128 ? gh[i] : 0;
+        }
+    }
+    __syncthreads();
+    if (lane == 0) Xlo[L.xoff[1]] = 1;   // level 1: the single node, coloured c_v
+    const int16_t *xidx = A.key_xidx + (size_t)cv * L.nkeys;
+#pragma unroll
+    for (int q = 2; q <= PMAX; q++) {
+        if (q > phi) continue;
+        const uint64_t hq = readlane64(hd, q);
+        const uint32_t len = LOC_LEN(hq);
+        if ((uint32_t)lane < len) Xlo[L.xoff[q] + xidx[ek[q]]] = el[q];
+        if (len > WAVE || wide) {
+            const uint64_t *p = A.lev[q].P.pool + LOC_OFF(hq) + REC_HDR;
+            const uint32_t kw = key_words(len);
+            const bool rw = LOC_WIDE(hq) != 0;
+            for (uint32_t e = lane; e < len; e += WAVE) {
+                const int x = L.xoff[q] + xidx[((const uint16_t *)p)[e]];
+                if (e >= WAVE) Xlo[x] = p[kw + e];
+                if (wide) Xhi[x] = rw ? p[kw + len + e] : 0;
+            }
+        }
+    }
+    __syncthreads();
+    combine_outputs(A, v, cv, Xlo, Slo, Xhi, Shi, owide, wide);
+}
+
 // one workgroup per vertex, low words in LDS; vertices that need 128 bits are
 // listed for k_combine_wide
 // eight waves per SIMD (one register below the compiler's own choice): the
 // combine waits on memory, and the extra waves measured 9 % faster
+template <int PMAX>
 __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(8, 8))) k_combine(CombineArgs A, int *wide_list, int *wide_count)
 {
     extern __shared__ uint64_t sm[];
-    for (int64_t v = blockIdx.x; v < A.g.n; v += gridDim.x) {
-        combine_vertex<false>(A, v, sm, nullptr, wide_list, wide_count);
-        __syncthreads();
-    }
+    if ((int64_t)blockIdx.x < A.g.n) combine_vertex_pf<PMAX>(A, blockIdx.x, sm, nullptr, wide_list, wide_count);
+}
+
+// the listed vertices only (level k under zero-rooting: the colour-0 vertices)
+template <int PMAX>
+__global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(8, 8))) k_combine_list(CombineArgs A, const int32_t *rows, int *wide_list, int *wide_count)
+{
+    extern __shared__ uint64_t sm[];
+    combine_vertex_pf<PMAX>(A, __builtin_amdgcn_readfirstlane(rows[blockIdx.x]), sm, nullptr, wide_list, wide_count);
 }
 
 // the listed vertices, with high words in LDS as well (lds = 2 (xoff_h + soff_h) words)
@@ -909,7 +1052,7 @@ __global__ void __launch_bounds__(WAVE) k_combine_wide(CombineArgs A, const int 
     const int lo_words = A.L->xoff[A.h] + A.L->soff[A.h];
     for (int i = blockIdx.x; i < cnt; i += gridDim.x) {
         const int v = __builtin_amdgcn_readfirstlane(wide_list[i]);
-        combine_vertex<false>(A, v, sm, sm + lo_words, nullptr, nullptr);
+        combine_vertex_pf<SCC_KMAX - 1>(A, v, sm, sm + lo_words, nullptr, nullptr);
         __syncthreads();
     }
 }
@@ -1395,6 +1538,20 @@ void launch_eta_shape(scc_table *T, int shape, u128 *eta)
 // ---------------------------------------------------------------------------
 // Host orchestration
 // ---------------------------------------------------------------------------
+// one workgroup per vertex, or per listed vertex (rows non-null)
+template <int PMAX>
+static void launch_combine(const CombineArgs &C, int64_t n, const int32_t *rows, int64_t nrows, size_t lds,
+                           hipStream_t st, int *wide_list, int *wide_count)
+{
+    if (rows) {
+        if (nrows)
+            hipLaunchKernelGGL(k_combine_list<PMAX>, dim3((unsigned)nrows), dim3(WAVE), lds, st, C, rows, wide_list,
+                               wide_count);
+    } else {
+        hipLaunchKernelGGL(k_combine<PMAX>, dim3((unsigned)n), dim3(WAVE), lds, st, C, wide_list, wide_count);
+    }
+}
+
 static scc_status build_levels(scc_table *T)
 {
     const DevLut &HL = T->hlut;
@@ -1443,9 +1600,9 @@ static scc_status build_levels(scc_table *T)
 
     // hub rows and their neighbour chunks, and the rows between the grouped
     // low-degree ones and the hubs (the same for every level)
-    int nhub = 0, nmid = 0;
+    int nhub = 0, nmid = 0, nzero = 0;
     int64_t low_rows = 0;
-    int32_t *hubs = nullptr, *mids = nullptr;
+    int32_t *hubs = nullptr, *mids = nullptr, *zrows = nullptr;
     int32_t *chunk_v = nullptr, *chunk_q = nullptr;
     int64_t *chunk_e = nullptr;
     int64_t nchunk = 0;
@@ -1453,16 +1610,18 @@ static scc_status build_levels(scc_table *T)
     if (n) {
         hubs = (int32_t *)get((size_t)n * 4 + 8);
         mids = (int32_t *)get((size_t)n * 4 + 8);
-        if (!hubs || !mids) return set_error(SCC_ENOMEM, "row lists");
+        zrows = (int32_t *)get((size_t)n * 4 + 8);
+        if (!hubs || !mids || !zrows) return set_error(SCC_ENOMEM, "row lists");
         HIP_TRY(hipMemsetAsync(err, 0, 16, st));
         hipLaunchKernelGGL(k_row_lists, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g, hub_degree, hubs, mids,
-                           err);
-        int cnt[3] = {0, 0, 0};
-        HIP_TRY(hipMemcpyAsync(cnt, err, 12, hipMemcpyDeviceToHost, st));
+                           zrows, err);
+        int cnt[4] = {0, 0, 0, 0};
+        HIP_TRY(hipMemcpyAsync(cnt, err, 16, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
         nhub = cnt[0];
         nmid = cnt[1];
         low_rows = cnt[2];
+        nzero = cnt[3];
     }
     if (nhub) {
         std::vector<int32_t> hh(nhub);
@@ -1587,6 +1746,8 @@ static scc_status build_levels(scc_table *T)
                 if (n)
                     hipLaunchKernelGGL(k_gather_group, dim3((unsigned)std::min<int64_t>(ngroups, 16384)), dim3(WAVE),
                                        group_lds(HL.WS[hs], gs), st, G, gs);
+            } else if (G.rows_zero) {
+                if (nzero) hipLaunchKernelGGL(k_gather_list, dim3((unsigned)nzero), dim3(WAVE), lds, st, G, zrows);
             } else if (n) {
                 hipLaunchKernelGGL(k_gather, dim3((unsigned)n), dim3(WAVE), lds, st, G);
             }
@@ -1643,7 +1804,16 @@ static scc_status build_levels(scc_table *T)
         C.meta = meta; C.Nout = Nsc; C.err = err;
         const size_t lds = (size_t)(HL.xoff[h] + HL.soff[h]) * 8;
         if (n) {
-            hipLaunchKernelGGL(k_combine, dim3((unsigned)n), dim3(WAVE), lds, st, C, wide_list, err + 1);
+            // level k under zero-rooting: only the colour-0 vertices have records
+            const bool zl = C.zero_only != 0;
+            if (zl) {
+                HIP_TRY(hipMemsetAsync(meta, 0, (size_t)n * 4, st));
+                HIP_TRY(hipMemsetAsync(Nsc, 0, (size_t)n * 16, st));
+            }
+            const int phi = C.bal ? h - 2 : h - 1;
+            if (phi <= 3) launch_combine<3>(C, n, zl ? zrows : nullptr, nzero, lds, st, wide_list, err + 1);
+            else if (phi <= 5) launch_combine<5>(C, n, zl ? zrows : nullptr, nzero, lds, st, wide_list, err + 1);
+            else launch_combine<SCC_KMAX - 1>(C, n, zl ? zrows : nullptr, nzero, lds, st, wide_list, err + 1);
             hipLaunchKernelGGL(k_combine_wide, dim3((unsigned)std::min<int64_t>(n, 1024)), dim3(WAVE), 2 * lds, st, C,
                                wide_list, err + 1);
         }

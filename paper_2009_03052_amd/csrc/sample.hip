@@ -77,12 +77,6 @@ __device__ inline DrawCache draw_cache(uint64_t seed, uint64_t stream, uint64_t 
     return DrawCache{c[0], c[1]};
 }
 
-__device__ inline uint64_t readlane64(uint64_t x, int src)
-{
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, src);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), src);
-    return ((uint64_t)hi << 32) | lo;
-}
 
 __device__ inline u128 draw_cached(const DrawCache &D, u128 N, uint64_t seed, uint64_t stream, uint64_t idx,
                                    uint32_t draw)
