@@ -908,45 +908,82 @@ __device__ inline void combine_outputs(const CombineArgs &A, int64_t v, int cv, 
     }
 }
 
-// The same counts for a packed table, with the loads ordered for latency: every
-// load that depends on v alone goes out first (lane q < PMAX + 1 takes level q's
-// record handle and neighbour-sum bound; every lane takes its first word of each
-// level's neighbour sums), then the level sums and the first entry per lane of
-// each own record, then the key index of those entries. A wave thus waits about
-// two memory latencies before the products instead of one per dependent step.
-// PMAX bounds the levels unrolled (PMAX >= h - 1); longer rows and records are
-// finished by loops, and high words (wide) are staged by loops as well.
-template <int PMAX>
+// Copies nwords 64-bit words from global memory to LDS with direct-to-LDS dword
+// loads (lane l moves dword l of each block of 64): the data never occupies
+// registers. The loads count in vmcnt like any other; wait before reading dst.
+__device__ inline void lds_dma_words(const uint64_t *src, uint64_t *dst, int nwords)
+{
+    const int lane = threadIdx.x;
+    const int nd = 2 * nwords;
+    for (int b = 0; b < nd; b += WAVE)
+        if (b + lane < nd)
+            __builtin_amdgcn_global_load_lds(
+                (const __attribute__((address_space(1))) void *)((const uint32_t *)src + b + lane),
+                (__attribute__((address_space(3))) void *)((uint32_t *)dst + b), 4, 0, 0);
+}
+// s_waitcnt vmcnt(0): every vector memory load of the wave, direct-to-LDS ones included, has landed
+__device__ inline void wait_vm_all() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+// The same counts with the loads ordered for latency: every load that depends
+// on v alone goes out first (lane q <= PMAX takes level q's record handle and
+// neighbour-sum bound; the neighbour sums themselves go to LDS, by direct
+// loads with DMA, else through a register per lane and level), then the level
+// sums and the first entry per lane of each own record, then the key index of
+// those entries. A wave thus waits about two memory latencies before the
+// products instead of one per dependent step. PMAX bounds the levels unrolled
+// (PMAX >= h - 1); longer rows and records are finished by loops, and high
+// words (wide) are staged by loops as well.
+template <bool SLOTS, int PMAX, bool DMA>
 __device__ inline void combine_vertex_pf(const CombineArgs &A, int64_t v, uint64_t *lo_area, uint64_t *hi_area,
                                          int *wide_list, int *wide_count)
 {
     const DevLut &L = *A.L;
     const int lane = threadIdx.x;
     const int h = A.h;
-    const int cv = A.g.colors[v];
-    if (A.zero_only && cv != 0) {
-        if (lane == 0) { A.meta[v] = 0; A.Nout[v] = 0; }
-        return;
+    int cv = 0;
+    if (A.zero_only) {   // level k: colour-0 vertices only
+        cv = A.g.colors[v];
+        if (cv != 0) {
+            if (lane == 0) { A.meta[v] = 0; A.Nout[v] = 0; }
+            return;
+        }
     }
     const int plo = A.bal ? 2 : 1, phi = A.bal ? h - 2 : h - 1;
+    const int XT = L.xoff[h];
+    uint64_t *Xlo = lo_area, *Slo = lo_area + XT;
+    uint64_t *Xhi = hi_area, *Shi = hi_area + XT;
+    if (DMA)
+        for (int hs = 1; hs <= phi; hs++)
+            if (A.Slo[hs]) lds_dma_words(A.Slo[hs] + (size_t)v * L.WS[hs], Slo + L.soff[hs], L.WS[hs]);
+    if (!A.zero_only) cv = A.g.colors[v];
+    // lane q: handle of v's level-q record (q >= 2) and M_q(v) (0: sums not built)
     const uint64_t *locp = nullptr, *poolp = nullptr;
-    const u128 *mp = nullptr;
+    const uint32_t *metap = nullptr;
+    const u128 *Np = nullptr, *mp = nullptr;
 #pragma unroll
     for (int q = 1; q <= PMAX; q++)
         if (lane == q && q <= phi) {
             mp = A.M[q];
-            if (q >= 2) { locp = A.lev[q].P.loc; poolp = A.lev[q].P.pool; }
+            if (q >= 2) {
+                if (SLOTS) { metap = A.lev[q].meta; Np = A.lev[q].N; }
+                else { locp = A.lev[q].P.loc; poolp = A.lev[q].P.pool; }
+            }
         }
-    const uint64_t hd = locp ? locp[v] : 0ull;      // lane q: handle of v's level-q record
-    const u128 Mq = mp ? mp[v] : (u128)0;            // lane q: M_q(v) (0: sums not built)
+    uint64_t hd = 0;
+    if (SLOTS) hd = ((uint64_t)v << 32) | (metap ? metap[v] : 0u);
+    else hd = locp ? locp[v] : 0ull;
+    const u128 Mq = mp ? mp[v] : (u128)0;
     uint64_t sw[PMAX + 1];
 #pragma unroll
     for (int q = 1; q <= PMAX; q++) {
         sw[q] = 0;
-        if (q <= phi && A.Slo[q] && lane < L.WS[q]) sw[q] = A.Slo[q][(size_t)v * L.WS[q] + lane];
+        if (!DMA && q <= phi && A.Slo[q] && lane < L.WS[q]) sw[q] = A.Slo[q][(size_t)v * L.WS[q] + lane];
     }
-    const uint64_t *rp = LOC_LEN(hd) ? poolp + LOC_OFF(hd) : nullptr;
-    const u128 Nq = rp ? mk128(rp[0], rp[1]) : (u128)0;
+    u128 Nq = 0;
+    if (h_len<SLOTS>(hd)) {
+        if (SLOTS) Nq = Np[v];
+        else { const uint64_t *rp = poolp + LOC_OFF(hd); Nq = mk128(rp[0], rp[1]); }
+    }
     uint32_t ek[PMAX + 1];
     uint64_t el[PMAX + 1];
 #pragma unroll
@@ -954,12 +991,10 @@ __device__ inline void combine_vertex_pf(const CombineArgs &A, int64_t v, uint64
         ek[q] = 0;
         el[q] = 0;
         if (q <= phi) {
-            const uint64_t hq = readlane64(hd, q);
-            const uint32_t len = LOC_LEN(hq);
-            if ((uint32_t)lane < len) {
-                const uint64_t *p = A.lev[q].P.pool + LOC_OFF(hq) + REC_HDR;
-                ek[q] = ((const uint16_t *)p)[lane];
-                el[q] = p[key_words(len) + lane];
+            const RecView<SLOTS> r = h_rec<SLOTS>(A.lev[q], readlane64(hd, q));
+            if ((uint32_t)lane < r.len) {
+                ek[q] = r.key[lane];
+                el[q] = r.lo[lane];
             }
         }
     }
@@ -969,32 +1004,34 @@ __device__ inline void combine_vertex_pf(const CombineArgs &A, int64_t v, uint64
     if (lane >= plo && lane <= phi) term = sat_mul(lane == 1 ? (u128)1 : Nq, Mpair);
     const u128 U = wave_satsum128(term);
     if (U == ~(u128)0 || bitlen128(U) > A.max_bits) {
+        if (DMA) wait_vm_all();   // no load may land in LDS after the area is handed on
         if (lane == 0) { atomicOr(A.err, 1); A.meta[v] = 0; A.Nout[v] = 0; }
         return;
     }
     const bool owide = hi64(U) != 0;
     bool wide = false;
     if (owide)
-        wide = __ballot(lane <= phi && ((lane >= 2 && LOC_WIDE(hd)) || (lane >= 1 && hi64(Mq) != 0))) != 0;
+        wide = __ballot(lane <= phi && ((lane >= 2 && h_wide<SLOTS>(hd)) || (lane >= 1 && hi64(Mq) != 0))) != 0;
     if (wide && !hi_area) {
+        if (DMA) wait_vm_all();
         if (lane == 0) wide_list[atomicAdd(wide_count, 1)] = (int)v;
         return;
     }
-    const int XT = L.xoff[h];
-    uint64_t *Xlo = lo_area, *Slo = lo_area + XT;
-    uint64_t *Xhi = hi_area, *Shi = hi_area + XT;
     for (int i = lane; i < XT; i += WAVE) {
         Xlo[i] = 0;
         if (wide) Xhi[i] = 0;
     }
+    if (!DMA) {
 #pragma unroll
-    for (int q = 1; q <= PMAX; q++)
-        if (q <= phi && A.Slo[q] && lane < L.WS[q]) Slo[L.soff[q] + lane] = sw[q];
+        for (int q = 1; q <= PMAX; q++)
+            if (q <= phi && A.Slo[q] && lane < L.WS[q]) Slo[L.soff[q] + lane] = sw[q];
+    }
     for (int hs = 1; hs <= phi; hs++) {
         if (!A.Slo[hs]) continue;
         const int ws = L.WS[hs];
         const uint64_t *gl = A.Slo[hs] + (size_t)v * ws;
-        for (int i = WAVE + lane; i < ws; i += WAVE) Slo[L.soff[hs] + i] = gl[i];
+        if (!DMA)
+            for (int i = WAVE + lane; i < ws; i += WAVE) Slo[L.soff[hs] + i] = gl[i];
         if (wide) {
             const bool sw128 = hi64(A.M[hs][v]) != 0;
             const uint64_t *gh = sw128 ? A.Shi[hs] + hi_row(A.Shrow[hs], v) * ws : nullptr;
@@ -1007,20 +1044,17 @@ __device__ inline void combine_vertex_pf(const CombineArgs &A, int64_t v, uint64
 #pragma unroll
     for (int q = 2; q <= PMAX; q++) {
         if (q > phi) continue;
-        const uint64_t hq = readlane64(hd, q);
-        const uint32_t len = LOC_LEN(hq);
-        if ((uint32_t)lane < len) Xlo[L.xoff[q] + xidx[ek[q]]] = el[q];
-        if (len > WAVE || wide) {
-            const uint64_t *p = A.lev[q].P.pool + LOC_OFF(hq) + REC_HDR;
-            const uint32_t kw = key_words(len);
-            const bool rw = LOC_WIDE(hq) != 0;
-            for (uint32_t e = lane; e < len; e += WAVE) {
-                const int x = L.xoff[q] + xidx[((const uint16_t *)p)[e]];
-                if (e >= WAVE) Xlo[x] = p[kw + e];
-                if (wide) Xhi[x] = rw ? p[kw + len + e] : 0;
+        const RecView<SLOTS> r = h_rec<SLOTS>(A.lev[q], readlane64(hd, q));
+        if ((uint32_t)lane < r.len) Xlo[L.xoff[q] + xidx[ek[q]]] = el[q];
+        if (r.len > WAVE || wide) {
+            for (uint32_t e = lane; e < r.len; e += WAVE) {
+                const int x = L.xoff[q] + xidx[r.key[e]];
+                if (e >= WAVE) Xlo[x] = r.lo[e];
+                if (wide) Xhi[x] = r.hi ? r.hi[e] : 0;
             }
         }
     }
+    if (DMA) wait_vm_all();
     __syncthreads();
     combine_outputs(A, v, cv, Xlo, Slo, Xhi, Shi, owide, wide);
 }
@@ -1033,7 +1067,7 @@ template <int PMAX>
 __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(8, 8))) k_combine(CombineArgs A, int *wide_list, int *wide_count)
 {
     extern __shared__ uint64_t sm[];
-    if ((int64_t)blockIdx.x < A.g.n) combine_vertex_pf<PMAX>(A, blockIdx.x, sm, nullptr, wide_list, wide_count);
+    if ((int64_t)blockIdx.x < A.g.n) combine_vertex_pf<false, PMAX, false>(A, blockIdx.x, sm, nullptr, wide_list, wide_count);
 }
 
 // the listed vertices only (level k under zero-rooting: the colour-0 vertices)
@@ -1041,7 +1075,7 @@ template <int PMAX>
 __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(8, 8))) k_combine_list(CombineArgs A, const int32_t *rows, int *wide_list, int *wide_count)
 {
     extern __shared__ uint64_t sm[];
-    combine_vertex_pf<PMAX>(A, __builtin_amdgcn_readfirstlane(rows[blockIdx.x]), sm, nullptr, wide_list, wide_count);
+    combine_vertex_pf<false, PMAX, false>(A, __builtin_amdgcn_readfirstlane(rows[blockIdx.x]), sm, nullptr, wide_list, wide_count);
 }
 
 // the listed vertices, with high words in LDS as well (lds = 2 (xoff_h + soff_h) words)
@@ -1052,7 +1086,7 @@ __global__ void __launch_bounds__(WAVE) k_combine_wide(CombineArgs A, const int 
     const int lo_words = A.L->xoff[A.h] + A.L->soff[A.h];
     for (int i = blockIdx.x; i < cnt; i += gridDim.x) {
         const int v = __builtin_amdgcn_readfirstlane(wide_list[i]);
-        combine_vertex_pf<SCC_KMAX - 1>(A, v, sm, sm + lo_words, nullptr, nullptr);
+        combine_vertex_pf<false, SCC_KMAX - 1, false>(A, v, sm, sm + lo_words, nullptr, nullptr);
         __syncthreads();
     }
 }
@@ -2260,8 +2294,9 @@ __device__ __attribute__((always_inline)) inline void batch_worker(BatchArgs B)
                 break;
             case BI_COMBINE:
                 for (int64_t v = I.a; v < I.b; v++) {
-                    combine_vertex<true>(P.C[I.h], v, sm, B.hi_scratch + (size_t)blockIdx.x * B.hi_stride, nullptr,
-                                         nullptr);
+                    combine_vertex_pf<true, SCC_KMAX - 1, true>(P.C[I.h], v, sm,
+                                                                B.hi_scratch + (size_t)blockIdx.x * B.hi_stride,
+                                                                nullptr, nullptr);
                     __syncthreads();
                 }
                 break;
