@@ -193,6 +193,23 @@ def variable_length(scc, dg, dcol, k, ns, sseed, verts, par, zinfo):
     return out
 
 
+def random_read_ceiling(scc, torch):
+    """Device rate of reads of 64- and 128-byte records at random positions of a
+    4 GiB zero-filled buffer (2^24 reads, best of 3): the neighbour-record
+    gather's access pattern at the memory system's own limit, next to the
+    8 TB/s sequential peak."""
+    n_reads = 1 << 24
+    buf = torch.zeros(1 << 29, dtype=torch.int64, device="cuda")
+    out = {"buffer_bytes": buf.numel() * 8, "reads": n_reads}
+    for rb in (64, 128):
+        ms = min(scc.probe_random_reads(buf, rb, n_reads, salt=s) for s in range(3))
+        out[f"GBs_{rb}B"] = n_reads * rb / ms / 1e6
+        out[f"frac_of_peak_{rb}B"] = out[f"GBs_{rb}B"] / HBM_PEAK_GBS
+    del buf
+    torch.cuda.empty_cache()
+    return out
+
+
 def batching_instances():
     """16 colourings of a Chung-Lu graph (n=5e5, m~5e6, exponent 2.2, w_max=2.5e4) and 32
     uneven ER/BA graphs (n log-uniform in [1e3, 1e5], mean degree 4 + (i mod 17)); k = 5 + (i mod 3)."""
@@ -537,6 +554,9 @@ def main():
     bc = None if a.no_round_skipping else biased_colouring(scc, dg, k, cfg["biased_lambda"], cfg["cseed"], ns, sseed,
                                                            verts, par, info, build_ms)
     vl = None if a.no_round_skipping else variable_length(scc, dg, dcol, k, ns, sseed, verts, par, info)
+    rr = random_read_ceiling(scc, torch)
+    print(f"# random reads: {rr['GBs_64B']:.0f} GB/s (64 B), {rr['GBs_128B']:.0f} GB/s (128 B)", file=sys.stderr,
+          flush=True)
     out = {
         "metric": "DP table build s & colorful-treelet samples/sec, batched/served vs plain",
         "value": ns / dt,
@@ -555,6 +575,7 @@ def main():
                      "kernel": "k_gather_group + k_gather_list + k_gather_hub + k_hub_prepare (neighbour-record gather of the DP, levels 2..k-1)",
                      "bytes_per_step": g_bytes, "ms_per_step": g_ms},
     }
+    out["random_read_ceiling"] = rr
     if ags is not None:
         out["ags"] = ags
     if rs is not None:

@@ -323,6 +323,23 @@ scc_status scc_color_biased(int64_t n, int k, double lambda, uint64_t seed, uint
  */
 double scc_colour_set_probability(int k, double lambda, int j, int has_zero);
 
+/*
+ * scc_probe_random_reads -- a measurement aid for roofline reports, not part
+ * of the method: the device time of n_reads reads of record_bytes bytes each
+ * (a multiple of 8 in [8, 256]) at random record-aligned positions of buf,
+ * the access pattern of the neighbour-record gather. Read r loads record
+ * mix(r + salt) mod (buf_bytes / record_bytes), one 8-byte word per lane of a
+ * group of record_bytes / 8 lanes (mix: a 64-bit finaliser of MurmurHash3).
+ * buf: device, caller-owned, 8-byte aligned, zero-filled (a loaded word equal
+ * to a fixed nonzero constant is stored to sink, which keeps the loads; with
+ * zeros it never happens). sink: device uint64, caller-owned.
+ * n_reads * record_bytes / 8 <= 2^31. *ms_out: the kernel's duration (HIP
+ * events on `stream`, which the call synchronises).
+ * Errors: SCC_EINVAL (null pointer, sizes out of range), SCC_EDEVICE.
+ */
+scc_status scc_probe_random_reads(const void *buf, uint64_t buf_bytes, int record_bytes, int64_t n_reads,
+                                  uint64_t salt, uint64_t *sink, void *stream, float *ms_out);
+
 /* One instance of a batched build: a graph (device pointers, as for
    scc_build_table), its colours and its k. */
 typedef struct {

@@ -117,6 +117,7 @@ _SIGS = {
     "scc_table_destroy": (None, [_P]),
     "scc_table_info_get": (C.c_int, [_P, C.POINTER(TableInfo)]),
     "scc_gather_bytes": (C.c_int, [_P, _P]),
+    "scc_probe_random_reads": (C.c_int, [_P, _u64, C.c_int, _i64, _u64, _P, _P, C.POINTER(C.c_float)]),
     "scc_occ": (C.c_int, [_P, _i64, _i32, _P]),
     "scc_export_level": (C.c_int, [_P, C.c_int, C.POINTER(_i64), _P, _P, _P, _P, _P]),
     "scc_sample": (C.c_int, [_P, _i32, _i64, _u64, _u64, _u64, _P, _P, _P]),
@@ -467,6 +468,15 @@ def color_biased(n: int, k: int, lam: float, seed: int, stream_id: int = 0, devi
     col = out if out is not None else torch.empty(max(n, 1), dtype=torch.uint8, device=device)
     _check(_lib.scc_color_biased(n, k, lam, seed, stream_id, _ptr(col), _stream_ptr(stream)))
     return col[:n]
+
+
+def probe_random_reads(buf: torch.Tensor, record_bytes: int, n_reads: int, salt: int = 0, stream=None) -> float:
+    """``scc_probe_random_reads``: device ms of n_reads random record reads from buf (zero-filled, on the GPU)."""
+    sink = torch.zeros(1, dtype=torch.int64, device=buf.device)
+    ms = C.c_float(0)
+    _check(_lib.scc_probe_random_reads(_ptr(buf), buf.numel() * buf.element_size(), record_bytes, n_reads, salt,
+                                       _ptr(sink), _stream_ptr(stream), C.byref(ms)))
+    return float(ms.value)
 
 
 def colour_set_probability(k: int, lam: float, j: int, has_zero: bool = True) -> float:

@@ -2292,20 +2292,40 @@ __device__ __attribute__((always_inline)) inline void batch_worker(BatchArgs B)
             case BI_G1:
                 for (int64_t v = I.a; v < I.b; v++) gather1_vertex(P.g, P.k, P.S1, P.M1, v, cnt1);
                 break;
-            case BI_COMBINE:
-                for (int64_t v = I.a; v < I.b; v++) {
-                    combine_vertex_pf<true, SCC_KMAX - 1, true>(P.C[I.h], v, sm,
-                                                                B.hi_scratch + (size_t)blockIdx.x * B.hi_stride,
-                                                                nullptr, nullptr);
-                    __syncthreads();
+            case BI_COMBINE: {
+                // 64 vertices at a time; at level k under zero-rooting only the colour-0
+                // ones, the others getting empty records here (one load for 64 vertices
+                // instead of one dependent load each)
+                const CombineArgs &C = P.C[I.h];
+                uint64_t *hi = B.hi_scratch + (size_t)blockIdx.x * B.hi_stride;
+                for (int64_t b0 = I.a; b0 < I.b; b0 += WAVE) {
+                    const int64_t vv = b0 + lane;
+                    bool z = vv < I.b;
+                    if (z && C.zero_only) {
+                        z = C.g.colors[vv] == 0;
+                        if (!z) { C.meta[vv] = 0; C.Nout[vv] = 0; }
+                    }
+                    for (uint64_t m = __ballot(z); m; m &= m - 1) {
+                        combine_vertex_pf<true, SCC_KMAX - 1, true>(C, b0 + (__ffsll((long long)m) - 1), sm, hi,
+                                                                    nullptr, nullptr);
+                        __syncthreads();
+                    }
                 }
                 break;
-            case BI_GATHER:
-                for (int64_t v = I.a; v < I.b; v++) {
-                    gather_vertex<true>(P.G[I.h], v, sm);
-                    __syncthreads();
+            }
+            case BI_GATHER: {
+                // 64 rows at a time; at level k-1 under zero-rooting only the colour-0 ones
+                const GatherArgs &G = P.G[I.h];
+                for (int64_t b0 = I.a; b0 < I.b; b0 += WAVE) {
+                    const int64_t vv = b0 + lane;
+                    const bool z = vv < I.b && (!G.rows_zero || G.g.colors[vv] == 0);
+                    for (uint64_t m = __ballot(z); m; m &= m - 1) {
+                        gather_vertex<true>(G, b0 + (__ffsll((long long)m) - 1), sm);
+                        __syncthreads();
+                    }
                 }
                 break;
+            }
             default:
                 hub_chunk<true>(P.G[I.h], I.a, I.b, I.c, sm);
                 break;

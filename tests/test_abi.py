@@ -32,3 +32,15 @@ def test_binding_covers_the_header():
     assert "gfx950" in scc.version()
     assert scc._lib.scc_num_unrooted(8) == 23
     assert scc._lib.scc_num_unrooted(9) == -1
+
+
+def test_probe_rejects_bad_arguments():
+    # argument checks only: every case returns before any device work
+    import paper_2009_03052_amd as scc
+    buf = (ctypes.c_uint64 * 64)()
+    sink = (ctypes.c_uint64 * 1)()
+    ms = ctypes.c_float(0)
+    f = scc._lib.scc_probe_random_reads
+    for nbytes, rb, n in [(512, 12, 4), (512, 0, 4), (512, 264, 4), (512, 64, -1), (512, 64, 1 << 30), (4, 64, 4)]:
+        assert f(buf, nbytes, rb, n, 0, sink, None, ctypes.byref(ms)) == scc.EINVAL, (nbytes, rb, n)
+    assert f(None, 512, 64, 4, 0, sink, None, ctypes.byref(ms)) == scc.EINVAL
