@@ -2489,7 +2489,23 @@ static scc_status batch_launch(std::vector<BatchInstHost> &H, int tile, int hub_
     // counters: per instance, S-ready[h] (h = 1..k-1) and X-ready[h] (h = 2..k)
     auto cS = [&](int i, int h) { return i * 2 * (SCC_KMAX + 1) + h; };
     auto cX = [&](int i, int h) { return i * 2 * (SCC_KMAX + 1) + (SCC_KMAX + 1) + h; };
+    // the exact item count first (the list reaches ~10^6 items of 48 bytes, so
+    // growing it by doubling would copy it many times over)
+    auto ntiles = [&](int i) {
+        const int64_t n = H[i].T->n;
+        return std::max<int64_t>((n + tile - 1) / tile, std::min<int64_t>(64, (n + 31) / 32));
+    };
+    size_t nitems_all = 0;
+    for (int i = 0; i < ni; i++) {
+        const int k = H[i].T->k;
+        nitems_all += (size_t)ntiles(i) * (size_t)(1 + (k - 1) + (k - 2));   // level 1, combines, gathers
+        for (size_t q = 0; q < hv[i].size(); q++) {
+            const int64_t d = hr[i][2 * q + 1] - hr[i][2 * q];
+            nitems_all += (size_t)((d + H[i].T->hub_chunk - 1) / H[i].T->hub_chunk) * (size_t)std::max(0, k - 2);
+        }
+    }
     std::vector<BItem> items;
+    items.reserve(nitems_all);
     std::vector<std::vector<int>> nS(ni, std::vector<int>(SCC_KMAX + 1, 0)), nX(ni, std::vector<int>(SCC_KMAX + 1, 0));
     // Each (instance, phase) is cut into nt items: ceil(n / tile), but at least
     // min(64, ceil(n / 32)) so that a small instance still spreads over many
@@ -2498,7 +2514,7 @@ static scc_status batch_launch(std::vector<BatchInstHost> &H, int tile, int hub_
     // vertex bounds k_item_bounds finds on the device.
     auto tiles = [&](int i, int16_t h, int16_t ph, int dep, int need, int done, bool by_cost) {
         const int64_t n = H[i].T->n;
-        const int64_t nt = std::max<int64_t>((n + tile - 1) / tile, std::min<int64_t>(64, (n + 31) / 32));
+        const int64_t nt = ntiles(i);
         const int64_t per = nt ? (n + nt - 1) / nt : 0;
         for (int64_t q = 0; q < nt; q++) {
             BItem it{};
