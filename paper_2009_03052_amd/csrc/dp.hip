@@ -2063,7 +2063,10 @@ static scc_status make_key_maps(scc_table *T)
 {
     const DevLut &L = T->hlut;
     const int k = T->k;
-    std::vector<int16_t> sidx((size_t)k * L.nkeys, -1), xidx((size_t)k * L.nkeys, -1);
+    // both maps live in the table's host copy, so that their uploads need no wait here
+    const size_t nk = (size_t)k * L.nkeys;
+    T->key_maps_host.assign(2 * nk, (int16_t)-1);
+    int16_t *sidx = T->key_maps_host.data(), *xidx = sidx + nk;
     for (int h = 1; h <= k; h++)
         for (int t = 0; t < L.r[h]; t++)
             for (int ci = 0; ci < L.bk[h]; ci++) {
@@ -2079,16 +2082,15 @@ static scc_status make_key_maps(scc_table *T)
                     }
                 }
             }
-    T->key_sidx = (int16_t *)T->alloc(sidx.size() * 2);
-    T->key_xidx = (int16_t *)T->alloc(xidx.size() * 2);
+    T->key_sidx = (int16_t *)T->alloc(nk * 2);
+    T->key_xidx = (int16_t *)T->alloc(nk * 2);
     T->dlut = (DevLut *)T->alloc(sizeof(DevLut));
     T->dsum = (uint64_t *)T->alloc(DSUM_WORDS * 8);
     if (!T->key_sidx || !T->key_xidx || !T->dlut || !T->dsum) return set_error(SCC_ENOMEM, "lookup tables");
     HIP_TRY(hipMemsetAsync(T->dsum, 0, DSUM_WORDS * 8, T->stream));
-    HIP_TRY(hipMemcpyAsync(T->key_sidx, sidx.data(), sidx.size() * 2, hipMemcpyHostToDevice, T->stream));
-    HIP_TRY(hipMemcpyAsync(T->key_xidx, xidx.data(), xidx.size() * 2, hipMemcpyHostToDevice, T->stream));
+    HIP_TRY(hipMemcpyAsync(T->key_sidx, sidx, nk * 2, hipMemcpyHostToDevice, T->stream));
+    HIP_TRY(hipMemcpyAsync(T->key_xidx, xidx, nk * 2, hipMemcpyHostToDevice, T->stream));
     HIP_TRY(hipMemcpyAsync(T->dlut, &T->hlut, sizeof(DevLut), hipMemcpyHostToDevice, T->stream));
-    HIP_TRY(hipStreamSynchronize(T->stream));
     return SCC_OK;
 }
 
@@ -2385,7 +2387,8 @@ struct BatchInstHost {
     std::vector<int32_t> hubs;           // ascending
     std::vector<int64_t> hub_rows;       // [2 * nhub]
     int32_t *hubs_dev = nullptr;
-    // slots per level
+    // slots per level, carved from one allocation (slab)
+    void *slab = nullptr;
     uint16_t *skey[SCC_KMAX + 1] = {};
     uint64_t *slo[SCC_KMAX + 1] = {}, *shi[SCC_KMAX + 1] = {};
     uint32_t *meta[SCC_KMAX + 1] = {};
@@ -2681,10 +2684,7 @@ extern "C" scc_status scc_build_batch(const scc_instance *inst, int n_inst, cons
     auto fail = [&](scc_status s) {
         for (auto &x : H) {
             if (!x.T) continue;
-            for (int h = 0; h <= SCC_KMAX; h++) {
-                x.T->mem.put(x.skey[h]); x.T->mem.put(x.slo[h]); x.T->mem.put(x.shi[h]);
-                x.T->mem.put(x.meta[h]); x.T->mem.put(x.N[h]);
-            }
+            x.T->mem.put(x.slab);
             delete x.T;
         }
         return s;
@@ -2701,25 +2701,36 @@ extern "C" scc_status scc_build_batch(const scc_instance *inst, int n_inst, cons
         if (s) return fail(s);
         const DevLut &HL = T->hlut;
         const int64_t n = T->n;
-        T->S[1].lo = (uint64_t *)T->alloc((size_t)n * (I.k - 1) * 8 + 8);
-        T->S[1].M = (u128 *)T->alloc((size_t)n * 16 + 16);
-        if (!T->S[1].lo || !T->S[1].M) return fail(set_error(SCC_ENOMEM, "instance %d: level-1 sums", i));
+        // the neighbour sums of every level in one allocation owned by the table, the
+        // slots of every level in another (parts on 256-byte boundaries)
+        auto part = [](size_t b) { return (b + 255) & ~(size_t)255; };
+        size_t sum_bytes = part((size_t)n * (I.k - 1) * 8 + 8) + part((size_t)n * 16 + 16);
+        for (int h = 2; h < I.k; h++) sum_bytes += 2 * part((size_t)n * HL.WS[h] * 8 + 8) + part((size_t)n * 16 + 16);
+        char *sums = (char *)T->alloc(sum_bytes + 256);
+        if (!sums) return fail(set_error(SCC_ENOMEM, "instance %d: sums (%zu bytes)", i, sum_bytes));
+        T->S[1].lo = (uint64_t *)sums; sums += part((size_t)n * (I.k - 1) * 8 + 8);
+        T->S[1].M = (u128 *)sums; sums += part((size_t)n * 16 + 16);
         for (int h = 2; h < I.k; h++) {
-            const size_t sz = (size_t)n * HL.WS[h] * 8 + 8;
-            T->S[h].lo = (uint64_t *)T->alloc(sz);
-            T->S[h].hi = (uint64_t *)T->alloc(sz);
-            T->S[h].M = (u128 *)T->alloc((size_t)n * 16 + 16);
-            if (!T->S[h].lo || !T->S[h].hi || !T->S[h].M) return fail(set_error(SCC_ENOMEM, "instance %d: sums", i));
+            const size_t sz = part((size_t)n * HL.WS[h] * 8 + 8);
+            T->S[h].lo = (uint64_t *)sums; sums += sz;
+            T->S[h].hi = (uint64_t *)sums; sums += sz;
+            T->S[h].M = (u128 *)sums; sums += part((size_t)n * 16 + 16);
         }
+        size_t slab_bytes = 0;
         for (int h = 2; h <= I.k; h++) {
             const size_t w = (size_t)n * HL.W[h];
-            H[i].skey[h] = (uint16_t *)T->mem.get(w * 2 + 64);
-            H[i].slo[h] = (uint64_t *)T->mem.get(w * 8 + 64);
-            H[i].shi[h] = (uint64_t *)T->mem.get(w * 8 + 64);
-            H[i].meta[h] = (uint32_t *)T->mem.get((size_t)n * 4 + 64);
-            H[i].N[h] = (u128 *)T->mem.get((size_t)n * 16 + 64);
-            if (!H[i].skey[h] || !H[i].slo[h] || !H[i].shi[h] || !H[i].meta[h] || !H[i].N[h])
-                return fail(set_error(SCC_ENOMEM, "instance %d: level %d slots", i, h));
+            slab_bytes += part(w * 2) + 2 * part(w * 8) + part((size_t)n * 4) + part((size_t)n * 16);
+        }
+        char *slab = (char *)T->mem.get(slab_bytes + 256);
+        if (!slab) return fail(set_error(SCC_ENOMEM, "instance %d: slots (%zu bytes)", i, slab_bytes));
+        H[i].slab = slab;
+        for (int h = 2; h <= I.k; h++) {
+            const size_t w = (size_t)n * HL.W[h];
+            H[i].skey[h] = (uint16_t *)slab; slab += part(w * 2);
+            H[i].slo[h] = (uint64_t *)slab; slab += part(w * 8);
+            H[i].shi[h] = (uint64_t *)slab; slab += part(w * 8);
+            H[i].meta[h] = (uint32_t *)slab; slab += part((size_t)n * 4);
+            H[i].N[h] = (u128 *)slab; slab += part((size_t)n * 16);
         }
     }
     DevMem mem;
@@ -2845,14 +2856,14 @@ extern "C" scc_status scc_build_batch(const scc_instance *inst, int n_inst, cons
     if (maxn)
         hipLaunchKernelGGL(k_mpack, dim3((unsigned)std::min<int64_t>((maxn + 3) / 4, 2048), (unsigned)nj), dim3(WAVE), 0,
                            st, djobs);
-    for (int i = 0; i < n_inst; i++)
-        for (int h = 2; h <= H[i].T->k; h++) {   // stream-ordered releases
-            scc_table *T = H[i].T;
-            T->mem.put(H[i].skey[h]); T->mem.put(H[i].slo[h]); T->mem.put(H[i].shi[h]);
-            T->mem.put(H[i].meta[h]); T->mem.put(H[i].N[h]);
+    for (int i = 0; i < n_inst; i++) {   // stream-ordered releases
+        H[i].T->mem.put(H[i].slab);
+        H[i].slab = nullptr;
+        for (int h = 2; h <= H[i].T->k; h++) {
             H[i].skey[h] = nullptr; H[i].slo[h] = nullptr; H[i].shi[h] = nullptr;
             H[i].meta[h] = nullptr; H[i].N[h] = nullptr;
         }
+    }
     HIP_TRY(hipGetLastError());
     for (int i = 0; i < n_inst; i++) {
         scc_table *T = H[i].T;

@@ -71,6 +71,7 @@ struct scc_table {
     bool vlc = false;                // levels re-encoded with variable-length counts after the build
     int nhub = 0;
     bool stats_done = false;
+    std::vector<int16_t> key_maps_host;   // host copy of key_sidx then key_xidx (source of their uploads)
     std::vector<int32_t> hub_host;   // hub vertices (ascending) and their row bounds
     std::vector<int64_t> hub_rows_host;
     // per-hub running sums over neighbours of every neighbour-sum entry, for the
