@@ -212,6 +212,13 @@ __device__ inline uint64_t last_lane64(uint64_t x)
     return ((uint64_t)hi << 32) | lo;
 }
 __device__ inline u128 last_lane128(u128 x) { return mk128(last_lane64(lo64(x)), last_lane64(hi64(x))); }
+// value of the first active lane, in every lane (scalar)
+__device__ inline uint64_t readfirst64(uint64_t x)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(x >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
 // value of lane src (uniform src), in every lane
 __device__ inline uint64_t readlane64(uint64_t x, int src)
 {

@@ -230,16 +230,18 @@ __device__ inline int sample_one(const SampleArgs &A, int64_t r, SampleLds &W)
     // (2) decompose, LIFO: (T', C \ C'', x) is processed before (T'', C'', u)
     while (sp > 0 && !fail) {
         sp--;
-        const uint32_t key = st_key[sp];
-        const int pos = st_pos[sp];
-        const u128 cT = st_cnt[sp];
+        // every lane reads the same LDS words: made scalar, so that the per-level
+        // arrays below are addressed from scalar registers
+        const uint32_t key = (uint32_t)__builtin_amdgcn_readfirstlane((int)st_key[sp]);
+        const int pos = __builtin_amdgcn_readfirstlane(st_pos[sp]);
+        const u128 cT = mk128(readfirst64(lo64(st_cnt[sp])), readfirst64(hi64(st_cnt[sp])));
         __syncthreads();
         const int h = key_level(L, key);
         if (h == 1) continue;
         const int rel = (int)key - L.off[h];
         const int t = rel / L.bk[h];
         const uint32_t C = L.mask_k[h][rel - t * L.bk[h]];
-        const int64_t x = sv[pos];
+        const int64_t x = __builtin_amdgcn_readfirstlane(sv[pos]);
         const int cx = A.g.colors[x];
         const int hp = L.dec_hp[h][t], hpp = h - hp, a = L.dec_a[h][t], b = L.dec_b[h][t];
         const int beta = L.dec_beta[h][t];
