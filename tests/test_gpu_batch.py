@@ -88,3 +88,22 @@ def test_batch_with_wide_counts():
     tabs, _ = S.build_batch(dev)
     assert_tables_equal(tabs[0], O.Table(g, colors, 6), 6, "wide star in a batch")
     assert tabs[0].totals()[0] > 2 ** 64
+
+
+def test_batch_zero_rooting_colour_zero_sparse():
+    # zero-rooting: the level-k combine and the level k-1 gather visit only the
+    # colour-0 vertices of each tile (none, one, or about a k-th of them)
+    S = scc()
+    inst = []
+    for i, k in enumerate([4, 6, 7]):
+        g = gg.chung_lu(3000, 12000, 2.2, 300, seed=40 + i)
+        c = (gg.colors(g.n, k - 1, seed=60 + i) + 1).astype(np.uint8)      # no colour 0
+        inst.append((g, c, k))
+        c1 = c.copy()
+        c1[[5, 1500, 2999]] = 0                                               # three colour-0 vertices
+        inst.append((g, c1, k))
+        inst.append((g, gg.colors(g.n, k, seed=70 + i), k))                   # uniform colours
+    dev = [(S.DeviceGraph.from_graph(g), c, k) for g, c, k in inst]
+    tabs, _ = S.build_batch(dev, tile=100, hub_degree=64, waves=8)
+    for (g, c, k), bt in zip(inst, tabs):
+        assert_tables_equal(bt, O.Table(g, c, k, O.ROOT_ZERO), k, f"batch colour-0 n={g.n} k={k}")

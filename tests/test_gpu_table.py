@@ -121,6 +121,22 @@ def test_degenerate_graphs():
     assert gt.totals()[0] == 0
 
 
+@pytest.mark.parametrize("k", [3, 6])
+def test_no_colour_zero_vertex(k):
+    # zero-rooting with no vertex of colour 0: level k and its colour-0 row lists
+    # are empty (no launch over them), every lower level is still stored
+    g = gg.chung_lu(3000, 15000, 2.2, 300, seed=31)
+    colors = (gg.colors(g.n, k - 1, seed=32) + 1).astype(np.uint8)
+    gt, ot = build_pair(g, colors, k)
+    assert_tables_equal(gt, ot, k, "no colour 0")
+    assert gt.totals()[0] == 0
+    # a single colour-0 vertex: level k holds its records only
+    colors[17] = 0
+    gt, ot = build_pair(g, colors, k)
+    assert_tables_equal(gt, ot, k, "one colour-0 vertex")
+    assert gt.info().nnz[k] == ot.level_nnz(k)
+
+
 def test_invalid_inputs():
     S = scc()
     g = gg.erdos_renyi(20, 40, seed=1)
