@@ -79,10 +79,42 @@ __device__ inline void gather1_vertex(const GraphView &g, int k, uint64_t *S1, u
   }
 }
 
+// Level-1 sums of the vertices v0 + lane (< v1) with at most GATHER1_LANE_DEG
+// neighbours, one vertex per lane: eight 8-bit colour counters packed in one
+// word. Returns the ballot of the lanes whose vertex has more neighbours (left
+// to gather1_vertex).
+constexpr int GATHER1_LANE_DEG = 64;
+__device__ inline uint64_t gather1_lanes(const GraphView &g, int k, uint64_t *S1, u128 *M1, int64_t v0, int64_t v1)
+{
+    const int64_t v = v0 + lane_id();
+    bool big = false;
+    if (v < v1) {
+        const int64_t a = g.row_ptr[v], b = g.row_ptr[v + 1];
+        if (b - a > GATHER1_LANE_DEG) {
+            big = true;
+        } else {
+            const int cv = g.colors[v];
+            uint64_t packed = 0;   // byte c: neighbours of colour c
+            for (int64_t e = a; e < b; e++) packed += 1ull << (8 * g.colors[g.col_idx[e]]);
+            for (int c = 0, pos = 0; c < k; c++) {
+                if (c == cv) continue;
+                S1[v * (k - 1) + pos] = (packed >> (8 * c)) & 0xffu;
+                pos++;
+            }
+            M1[v] = (u128)(b - a);
+        }
+    }
+    return __ballot(big);
+}
+
+// one block of 64 vertices per wave (grid-stride), longer rows by the whole wave
 __global__ void __launch_bounds__(WAVE) k_gather1(GraphView g, int k, uint64_t *S1, u128 *M1)
 {
     __shared__ unsigned cnt[SCC_KMAX];
-    for (int64_t v = blockIdx.x; v < g.n; v += gridDim.x) gather1_vertex(g, k, S1, M1, v, cnt);
+    for (int64_t v0 = (int64_t)blockIdx.x * WAVE; v0 < g.n; v0 += (int64_t)gridDim.x * WAVE) {
+        for (uint64_t m = gather1_lanes(g, k, S1, M1, v0, min(g.n, v0 + WAVE)); m; m &= m - 1)
+            gather1_vertex(g, k, S1, M1, v0 + (__ffsll((long long)m) - 1), cnt);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -710,29 +742,51 @@ __global__ void k_hub_list(GraphView g, int hub_degree, int32_t *hubs, int *coun
 
 // hub rows (count[0]), the rows between the grouped ones and the hubs
 // (count[1]), the number of rows of at most GROUP_LOW_DEG neighbours (count[2])
-// and the colour-0 rows (count[3]), each list in no particular order
-__global__ void k_row_lists(GraphView g, int hub_degree, int32_t *hubs, int32_t *mids, int32_t *zrows, int *count)
+// and the colour-0 rows (count[3]), each list in no particular order. One atomic
+// per list and block of ROW_LIST_T rows: the four counters are shared by the
+// whole grid.
+constexpr int ROW_LIST_T = 1024;
+__global__ void __launch_bounds__(ROW_LIST_T) k_row_lists(GraphView g, int hub_degree, int32_t *hubs, int32_t *mids,
+                                                           int32_t *zrows, int *count)
 {
-    // one atomic per wave and list: lanes take consecutive places by their rank
+    __shared__ int wcnt[ROW_LIST_T / WAVE][4];   // per wave: hubs, mids, colour-0 rows, low rows
+    __shared__ int wbase[ROW_LIST_T / WAVE][3];
+    const int w = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t d = v < g.n ? g.row_ptr[v + 1] - g.row_ptr[v] : 0;
-    const uint64_t low = __ballot(v < g.n && d <= GROUP_LOW_DEG);
     const bool hub = v < g.n && d > hub_degree, mid = v < g.n && !hub && d > GROUP_DEG;
     const bool zero = v < g.n && g.colors[v] == 0;
     const uint64_t hm = __ballot(hub), mm = __ballot(mid), zm = __ballot(zero);
-    int hbase = 0, mbase = 0, zbase = 0;
+    const uint64_t low = __ballot(v < g.n && d <= GROUP_LOW_DEG);
     if (lane_id() == 0) {
-        if (low) atomicAdd(&count[2], __popcll(low));
-        if (hm) hbase = atomicAdd(&count[0], __popcll(hm));
-        if (mm) mbase = atomicAdd(&count[1], __popcll(mm));
-        if (zm) zbase = atomicAdd(&count[3], __popcll(zm));
+        wcnt[w][0] = __popcll(hm);
+        wcnt[w][1] = __popcll(mm);
+        wcnt[w][2] = __popcll(zm);
+        wcnt[w][3] = __popcll(low);
     }
-    hbase = __shfl(hbase, 0, WAVE);
-    mbase = __shfl(mbase, 0, WAVE);
-    zbase = __shfl(zbase, 0, WAVE);
-    if (hub) hubs[hbase + __popcll(hm & lanemask_lt())] = (int32_t)v;
-    if (mid) mids[mbase + __popcll(mm & lanemask_lt())] = (int32_t)v;
-    if (zero) zrows[zbase + __popcll(zm & lanemask_lt())] = (int32_t)v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int tot[4] = {0, 0, 0, 0};
+        for (int q = 0; q < nw; q++)
+            for (int l = 0; l < 3; l++) {
+                wbase[q][l] = tot[l];
+                tot[l] += wcnt[q][l];
+            }
+        for (int q = 0; q < nw; q++) tot[3] += wcnt[q][3];
+        const int b0 = tot[0] ? atomicAdd(&count[0], tot[0]) : 0;
+        const int b1 = tot[1] ? atomicAdd(&count[1], tot[1]) : 0;
+        const int b2 = tot[2] ? atomicAdd(&count[3], tot[2]) : 0;
+        if (tot[3]) atomicAdd(&count[2], tot[3]);
+        for (int q = 0; q < nw; q++) {
+            wbase[q][0] += b0;
+            wbase[q][1] += b1;
+            wbase[q][2] += b2;
+        }
+    }
+    __syncthreads();
+    if (hub) hubs[wbase[w][0] + __popcll(hm & lanemask_lt())] = (int32_t)v;
+    if (mid) mids[wbase[w][1] + __popcll(mm & lanemask_lt())] = (int32_t)v;
+    if (zero) zrows[wbase[w][2] + __popcll(zm & lanemask_lt())] = (int32_t)v;
 }
 
 // ---------------------------------------------------------------------------
@@ -1647,8 +1701,8 @@ static scc_status build_levels(scc_table *T)
         zrows = (int32_t *)get((size_t)n * 4 + 8);
         if (!hubs || !mids || !zrows) return set_error(SCC_ENOMEM, "row lists");
         HIP_TRY(hipMemsetAsync(err, 0, 16, st));
-        hipLaunchKernelGGL(k_row_lists, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g, hub_degree, hubs, mids,
-                           zrows, err);
+        hipLaunchKernelGGL(k_row_lists, dim3((unsigned)((n + ROW_LIST_T - 1) / ROW_LIST_T)), dim3(ROW_LIST_T), 0, st, g,
+                           hub_degree, hubs, mids, zrows, err);
         int cnt[4] = {0, 0, 0, 0};
         HIP_TRY(hipMemcpyAsync(cnt, err, 16, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
@@ -1721,7 +1775,7 @@ static scc_status build_levels(scc_table *T)
     S1.M = (u128 *)T->alloc((size_t)n * 16 + 16);
     if (!S1.lo || !S1.M) return set_error(SCC_ENOMEM, "level-1 sums");
     HIP_TRY(hipEventRecord(ev[1][0], st));
-    if (n) hipLaunchKernelGGL(k_gather1, dim3(grid_of(n)), dim3(WAVE), 0, st, g, k, S1.lo, S1.M);
+    if (n) hipLaunchKernelGGL(k_gather1, dim3(grid_of((n + WAVE - 1) / WAVE)), dim3(WAVE), 0, st, g, k, S1.lo, S1.M);
     if (fused) {
         hipLaunchKernelGGL(k_hub_l1_blocks, dim3((unsigned)nchunk), dim3(WAVE), 0, st, g, k, hubs, chunk_e, chunk_q,
                            T->hub_pre, T->hub_poff);
@@ -2292,7 +2346,9 @@ __device__ __attribute__((always_inline)) inline void batch_worker(BatchArgs B)
             const BInst &P = *(const BInst *)((const __attribute__((address_space(4))) BInst *)B.inst + I.inst);
             switch (I.phase) {
             case BI_G1:
-                for (int64_t v = I.a; v < I.b; v++) gather1_vertex(P.g, P.k, P.S1, P.M1, v, cnt1);
+                for (int64_t v0 = I.a; v0 < I.b; v0 += WAVE)
+                    for (uint64_t m = gather1_lanes(P.g, P.k, P.S1, P.M1, v0, min(I.b, v0 + WAVE)); m; m &= m - 1)
+                        gather1_vertex(P.g, P.k, P.S1, P.M1, v0 + (__ffsll((long long)m) - 1), cnt1);
                 break;
             case BI_COMBINE: {
                 // 64 vertices at a time; at level k under zero-rooting only the colour-0
