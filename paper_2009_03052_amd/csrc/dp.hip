@@ -79,23 +79,32 @@ __device__ inline void gather1_vertex(const GraphView &g, int k, uint64_t *S1, u
   }
 }
 
-// Level-1 sums of the vertices v0 + lane (< v1) with at most GATHER1_LANE_DEG
+// Level-1 sums of the vertices v0 + lane (< v1) with at most lane_deg (<= 64)
 // neighbours, one vertex per lane: eight 8-bit colour counters packed in one
 // word. Returns the ballot of the lanes whose vertex has more neighbours (left
-// to gather1_vertex).
-constexpr int GATHER1_LANE_DEG = 64;
-__device__ inline uint64_t gather1_lanes(const GraphView &g, int k, uint64_t *S1, u128 *M1, int64_t v0, int64_t v1)
+// to the caller).
+constexpr int64_t GATHER1_LANE_DEG = 64;
+__device__ inline uint64_t gather1_lanes(const GraphView &g, int k, uint64_t *S1, u128 *M1, int64_t v0, int64_t v1,
+                                         int64_t lane_deg)
 {
     const int64_t v = v0 + lane_id();
     bool big = false;
     if (v < v1) {
         const int64_t a = g.row_ptr[v], b = g.row_ptr[v + 1];
-        if (b - a > GATHER1_LANE_DEG) {
+        if (b - a > lane_deg) {
             big = true;
         } else {
             const int cv = g.colors[v];
             uint64_t packed = 0;   // byte c: neighbours of colour c
-            for (int64_t e = a; e < b; e++) packed += 1ull << (8 * g.colors[g.col_idx[e]]);
+            int64_t e = a;
+            for (; e + 4 <= b; e += 4) {   // four ids, then four colours, in flight together
+                int32_t u[4];
+#pragma unroll
+                for (int j = 0; j < 4; j++) u[j] = g.col_idx[e + j];
+#pragma unroll
+                for (int j = 0; j < 4; j++) packed += 1ull << (8 * g.colors[u[j]]);
+            }
+            for (; e < b; e++) packed += 1ull << (8 * g.colors[g.col_idx[e]]);
             for (int c = 0, pos = 0; c < k; c++) {
                 if (c == cv) continue;
                 S1[v * (k - 1) + pos] = (packed >> (8 * c)) & 0xffu;
@@ -107,14 +116,46 @@ __device__ inline uint64_t gather1_lanes(const GraphView &g, int k, uint64_t *S1
     return __ballot(big);
 }
 
-// one block of 64 vertices per wave (grid-stride), longer rows by the whole wave
-__global__ void __launch_bounds__(WAVE) k_gather1(GraphView g, int k, uint64_t *S1, u128 *M1)
+// one block of 64 vertices per wave (grid-stride), longer rows by the whole
+// wave; rows above hub_degree only get zero sums and their degree here, their
+// counts coming from k_gather1_hub's chunks
+__global__ void __launch_bounds__(WAVE) k_gather1(GraphView g, int k, uint64_t *S1, u128 *M1, int64_t hub_degree)
 {
     __shared__ unsigned cnt[SCC_KMAX];
     for (int64_t v0 = (int64_t)blockIdx.x * WAVE; v0 < g.n; v0 += (int64_t)gridDim.x * WAVE) {
-        for (uint64_t m = gather1_lanes(g, k, S1, M1, v0, min(g.n, v0 + WAVE)); m; m &= m - 1)
-            gather1_vertex(g, k, S1, M1, v0 + (__ffsll((long long)m) - 1), cnt);
+        for (uint64_t m = gather1_lanes(g, k, S1, M1, v0, min(g.n, v0 + WAVE), min(GATHER1_LANE_DEG, hub_degree)); m;
+             m &= m - 1) {
+            const int64_t v = v0 + (__ffsll((long long)m) - 1);
+            const int64_t d = g.row_ptr[v + 1] - g.row_ptr[v];
+            if (d <= hub_degree) {
+                gather1_vertex(g, k, S1, M1, v, cnt);
+            } else {
+                if (lane_id() < k - 1) S1[v * (k - 1) + lane_id()] = 0;
+                if (lane_id() == 0) M1[v] = (u128)d;
+            }
+        }
     }
+}
+
+// level-1 counts of a hub row, one chunk of its neighbours per workgroup, added
+// into the row (zeroed by k_gather1, which runs first)
+__global__ void __launch_bounds__(WAVE) k_gather1_hub(GraphView g, int k, const int32_t *chunk_v,
+                                                      const int64_t *chunk_e, int chunk, uint64_t *S1)
+{
+    __shared__ unsigned cnt[SCC_KMAX];
+    const int lane = threadIdx.x;
+    const int64_t v = chunk_v[blockIdx.x];
+    const int64_t a = chunk_e[blockIdx.x], b = min(g.row_ptr[v + 1], a + (int64_t)chunk);
+    const int cv = g.colors[v];
+    if (lane < SCC_KMAX) cnt[lane] = 0;
+    __syncthreads();
+    for (int64_t e = a + lane; e < b; e += WAVE) {
+        const int cu = g.colors[g.col_idx[e]];
+        if (cu != cv) atomicAdd(&cnt[cu], 1u);
+    }
+    __syncthreads();
+    if (lane < k && lane != cv && cnt[lane])
+        atomicAdd((unsigned long long *)&S1[v * (k - 1) + (lane < cv ? lane : lane - 1)], (unsigned long long)cnt[lane]);
 }
 
 // ---------------------------------------------------------------------------
@@ -1775,7 +1816,12 @@ static scc_status build_levels(scc_table *T)
     S1.M = (u128 *)T->alloc((size_t)n * 16 + 16);
     if (!S1.lo || !S1.M) return set_error(SCC_ENOMEM, "level-1 sums");
     HIP_TRY(hipEventRecord(ev[1][0], st));
-    if (n) hipLaunchKernelGGL(k_gather1, dim3(grid_of((n + WAVE - 1) / WAVE)), dim3(WAVE), 0, st, g, k, S1.lo, S1.M);
+    if (n)
+        hipLaunchKernelGGL(k_gather1, dim3(grid_of((n + WAVE - 1) / WAVE)), dim3(WAVE), 0, st, g, k, S1.lo, S1.M,
+                           (int64_t)(nhub ? hub_degree : INT64_MAX));
+    if (nhub)
+        hipLaunchKernelGGL(k_gather1_hub, dim3((unsigned)nchunk), dim3(WAVE), 0, st, g, k, chunk_v, chunk_e, T->hub_chunk,
+                           S1.lo);
     if (fused) {
         hipLaunchKernelGGL(k_hub_l1_blocks, dim3((unsigned)nchunk), dim3(WAVE), 0, st, g, k, hubs, chunk_e, chunk_q,
                            T->hub_pre, T->hub_poff);
@@ -2347,7 +2393,8 @@ __device__ __attribute__((always_inline)) inline void batch_worker(BatchArgs B)
             switch (I.phase) {
             case BI_G1:
                 for (int64_t v0 = I.a; v0 < I.b; v0 += WAVE)
-                    for (uint64_t m = gather1_lanes(P.g, P.k, P.S1, P.M1, v0, min(I.b, v0 + WAVE)); m; m &= m - 1)
+                    for (uint64_t m = gather1_lanes(P.g, P.k, P.S1, P.M1, v0, min(I.b, v0 + WAVE), GATHER1_LANE_DEG); m;
+                         m &= m - 1)
                         gather1_vertex(P.g, P.k, P.S1, P.M1, v0 + (__ffsll((long long)m) - 1), cnt1);
                 break;
             case BI_COMBINE: {
