@@ -1971,7 +1971,8 @@ static scc_status build_levels(scc_table *T)
         if (n) {
             PackView P{n, HL.W[h], Lv.BW, HL.nkeys, meta, words, slot_key, slot_lo, slot_hi, Nsc, Lv.pool, Lv.loc,
                        Lv.bm, T->key_xidx, T->colors};
-            hipLaunchKernelGGL(k_pack, dim3(grid_of((n + 3) / 4)), dim3(WAVE), 0, st, P);
+            // one group of four vertices per wave: the waves' dependent loads overlap
+            hipLaunchKernelGGL(k_pack, dim3((unsigned)((n + 3) / 4)), dim3(WAVE), 0, st, P);
         }
         HIP_TRY(hipEventRecord(ev[h][1], st));
         if (n) hipLaunchKernelGGL(k_meta_sum, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 1024)), dim3(256), 0, st,
