@@ -49,7 +49,7 @@ typedef enum {
     SCC_EDEVICE = -4,      /* a HIP runtime error */
     SCC_EEMPTY = -5,       /* nothing to sample: the requested total is 0 */
     SCC_EBUSY = -6,        /* server full: request not admitted */
-    SCC_EUNSUPPORTED = -7  /* valid request this build does not support */
+    SCC_EUNSUPPORTED = -7  /* valid request the library does not support */
 } scc_status;
 
 enum { SCC_ROOT_ZERO = 0, SCC_ROOT_ALL = 1, SCC_ROOT_BALANCED = 2 };
