@@ -944,7 +944,9 @@ __device__ inline void combine_outputs(const CombineArgs &A, int64_t v, int cv, 
     const int lane = threadIdx.x;
     const int h = A.h;
     const int Wh = L.W[h];
-    const int nD = L.bk1[h - 1];
+    // one descriptor and one key per output (see DevLut::out): few table reads per lane
+    const uint32_t ob = L.out_off[h];
+    const uint16_t *okey = L.out_key[cv] + ob;
     uint32_t cnt = 0;
     u128 nsum = 0;
     uint16_t *sk = A.slot_key + (size_t)v * A.W;
@@ -953,43 +955,39 @@ __device__ inline void combine_outputs(const CombineArgs &A, int64_t v, int cv, 
     for (int o0 = 0; o0 < Wh; o0 += WAVE) {
         const int o = o0 + lane;
         u128 val = 0;
-        int t = 0, dc = 0;
-        if (o < Wh && !(A.bal && !L.designated[o / nD])) {
-            t = o / nD;
-            dc = o - t * nD;
-            const int hp = L.dec_hp[h][t], hpp = h - hp;
-            const int xb = L.xoff[hp] + L.dec_a[h][t] * L.bk1[hp - 1];
-            const int sb = L.soff[hpp] + L.dec_b[h][t] * L.bk1[hpp];
-            // number of splits = binom(h-1, hp-1)
-            int nsplit = 1;
-            for (int i = 1; i <= hp - 1; i++) nsplit = nsplit * (h - 1 - (hp - 1) + i) / i;
-            const int tb = L.term_base[h][hp] + dc * nsplit;
+        const uint64_t d = o < Wh ? L.out[ob + o] : 0ull;
+        if (o < Wh && !(A.bal && !(d >> 63))) {
+            const int xb = (int)(d & 0xffffu), sb = (int)((d >> 16) & 0xffffu), tb = (int)((d >> 32) & 0xffffu);
+            const int nsplit = (int)((d >> 48) & 0xffu);
             u128 acc = 0;
             if (!owide) {
                 uint64_t a64 = 0;
-                for (int i = 0; i < nsplit; i++)
-                    a64 += Xlo[xb + L.term_x[tb + i]] * Slo[sb + L.term_s[tb + i]];
+                for (int i = 0; i < nsplit; i++) {
+                    const uint32_t xs = L.term_xs[tb + i];
+                    a64 += Xlo[xb + (xs & 0xffu)] * Slo[sb + (xs >> 8)];
+                }
                 acc = a64;
             } else if (!wide) {
-                for (int i = 0; i < nsplit; i++)
-                    acc += (u128)Xlo[xb + L.term_x[tb + i]] * Slo[sb + L.term_s[tb + i]];
+                for (int i = 0; i < nsplit; i++) {
+                    const uint32_t xs = L.term_xs[tb + i];
+                    acc += (u128)Xlo[xb + (xs & 0xffu)] * Slo[sb + (xs >> 8)];
+                }
             } else {
                 for (int i = 0; i < nsplit; i++) {
-                    const int xi = xb + L.term_x[tb + i], si = sb + L.term_s[tb + i];
+                    const uint32_t xs = L.term_xs[tb + i];
+                    const int xi = xb + (int)(xs & 0xffu), si = sb + (int)(xs >> 8);
                     u128 x = mk128(Xlo[xi], Xhi[xi]), s = mk128(Slo[si], Shi[si]);
                     acc += x * s;
                 }
             }
-            const int beta = L.dec_beta[h][t];
-            val = beta == 1 ? acc : div_small(acc, (uint32_t)beta);
+            const uint32_t beta = (uint32_t)((d >> 56) & 0x7fu);
+            val = beta == 1 ? acc : div_small(acc, beta);
         }
         const bool nz = val != 0;
         const uint64_t bal = __ballot(nz);
         if (nz) {
             const uint32_t pos = cnt + (uint32_t)__popcll(bal & lanemask_lt());
-            const uint32_t D = L.mask_s[h - 1][dc];
-            const uint32_t C = expand_in(D, cv) | (1u << cv);
-            sk[pos] = (uint16_t)(L.off[h] + t * L.bk[h] + L.colex_k[C]);
+            sk[pos] = okey[o];
             sl[pos] = lo64(val);
             if (owide) sh[pos] = hi64(val);
             nsum += val;

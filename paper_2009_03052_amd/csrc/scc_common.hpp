@@ -58,6 +58,17 @@ struct DevLut {
     uint16_t term_base[SCC_KMAX + 1][SCC_KMAX + 1];
     uint8_t term_x[2200];
     uint8_t term_s[2200];
+    // The same, read once per output: output o of level h (o = t binom(k-1, h-1)
+    // + dc) has descriptor out[out_off[h] + o] with bits 0-15 the staging offset
+    // of its T' block (xoff + rank T' binom(k-1, |T'|-1)), 16-31 that of its T''
+    // block, 32-47 its first term, 48-55 its number of splits, 56-62 beta_T and
+    // bit 63 set when T is a designated level-k shape; its key at a colour-c
+    // vertex is out_key[c][out_off[h] + o]; term_xs[i] = term_x[i] | term_s[i] << 8.
+    // (sum over h of W_h is 1376 at k = 8)
+    uint32_t out_off[SCC_KMAX + 2];
+    uint64_t out[1400];
+    uint16_t out_key[SCC_KMAX][1400];
+    uint16_t term_xs[2200];
 };
 
 // Host-side treelet algebra (treelets.cpp).

@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <functional>
+#include <memory>
 #include <mutex>
 
 #include "scc_common.hpp"
@@ -277,6 +278,28 @@ void build_lut(int k, DevLut *L)
                 }
             }
         }
+    for (int i = 0; i < nt; i++) L->term_xs[i] = (uint16_t)(L->term_x[i] | (L->term_s[i] << 8));
+    // per-output descriptors and keys of every level
+    uint32_t no = 0;
+    for (int h = 2; h <= k; h++) {
+        L->out_off[h] = no;
+        const int nD = L->bk1[h - 1];
+        for (int o = 0; o < L->W[h]; o++, no++) {
+            const int t = o / nD, dc = o - t * nD;
+            const int hp = L->dec_hp[h][t], hpp = h - hp;
+            const uint64_t xb = (uint64_t)(L->xoff[hp] + L->dec_a[h][t] * L->bk1[hp - 1]);
+            const uint64_t sb = (uint64_t)(L->soff[hpp] + L->dec_b[h][t] * L->bk1[hpp]);
+            const uint64_t nsplit = (uint64_t)binom(h - 1, hp - 1);
+            const uint64_t tb = L->term_base[h][hp] + (uint64_t)dc * nsplit;
+            const uint64_t desig = (h == k && L->designated[t]) ? 1u : 0u;
+            L->out[no] = xb | (sb << 16) | (tb << 32) | (nsplit << 48) | ((uint64_t)L->dec_beta[h][t] << 56) | (desig << 63);
+            const uint32_t D = L->mask_s[h - 1][dc];
+            for (int c = 0; c < k; c++) {
+                const uint32_t C = expand_in(D, c) | (1u << c);
+                L->out_key[c][no] = (uint16_t)(L->off[h] + t * L->bk[h] + L->colex_k[C]);
+            }
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -301,18 +324,18 @@ extern "C" int scc_balanced_rooting(int k, int j, int *orbit)
 {
     if (orbit) *orbit = 0;
     if (k < 1 || k > SCC_KMAX || j < 0 || j >= unrooted_count(k)) return -1;
-    DevLut L;
-    build_lut(k, &L);
-    if (orbit) *orbit = L.bal_orbit[j];
-    return L.bal_rank[j];
+    std::unique_ptr<DevLut> L(new DevLut);   // ~50 KB: not on the caller's stack
+    build_lut(k, L.get());
+    if (orbit) *orbit = L->bal_orbit[j];
+    return L->bal_rank[j];
 }
 
 extern "C" int scc_star_shape(int k)
 {
     if (k < 2 || k > SCC_KMAX) return -1;
-    DevLut L;
-    build_lut(k, &L);
-    return L.star_unr;
+    std::unique_ptr<DevLut> L(new DevLut);
+    build_lut(k, L.get());
+    return L->star_unr;
 }
 
 void *DevMem::get(size_t bytes)
