@@ -78,6 +78,10 @@ __device__ inline DrawCache draw_cache(uint64_t seed, uint64_t stream, uint64_t 
 }
 
 
+// value of lane src (src uniform), as a scalar
+__device__ inline uint32_t readlane32(uint32_t x, int src) { return (uint32_t)__builtin_amdgcn_readlane((int)x, src); }
+__device__ inline u128 readlane128(u128 x, int src) { return mk128(readlane64(lo64(x), src), readlane64(hi64(x), src)); }
+
 __device__ inline u128 draw_cached(const DrawCache &D, u128 N, uint64_t seed, uint64_t stream, uint64_t idx,
                                    uint32_t draw)
 {
@@ -213,11 +217,11 @@ __device__ inline int sample_one(const SampleArgs &A, int64_t r, SampleLds &W)
         const u128 incl = run + wave_incl_scan128(c);
         const int w = first_exceeding(incl, res);
         if (w >= 0) {
-            rkey = __shfl(key, w, WAVE);
-            rcnt = shfl128(c, w);
+            rkey = readlane32(key, w);
+            rcnt = readlane128(c, w);
             break;
         }
-        run = shfl128(incl, WAVE - 1);
+        run = readlane128(incl, WAVE - 1);
     }
     if (rkey == 0xffffffffu) return 1;
     if (lane == 0) {
@@ -275,10 +279,11 @@ __device__ inline int sample_one(const SampleArgs &A, int64_t r, SampleLds &W)
         const u128 incl1 = wave_incl_scan128(w);
         const int w1 = first_exceeding(incl1, Y);
         if (w1 < 0) { fail = true; break; }
-        const uint32_t Cpp = __shfl(cpp, w1, WAVE);
-        const int Sidx = __shfl(sidx, w1, WAVE);
-        const u128 Xp = shfl128(xprime, w1);
-        const u128 Sv = shfl128(sval, w1);
+        // the chosen candidate's values, read from its lane as scalars
+        const uint32_t Cpp = readlane32(cpp, w1);
+        const int Sidx = (int)readlane32((uint32_t)sidx, w1);
+        const u128 Xp = readlane128(xprime, w1);
+        const u128 Sv = readlane128(sval, w1);
         // stage 2: neighbour u of x with weight c(T''_{C''}, u), CSR order
         const u128 Z = draw_cached(D, Sv, A.seed, A.stream, idx, doff + 2 + 2 * dec);
         const uint32_t kpp = L.off[hpp] + b * L.bk[hpp] + L.colex_k[Cpp];
@@ -308,8 +313,8 @@ __device__ inline int sample_one(const SampleArgs &A, int64_t r, SampleLds &W)
                 const u128 incl = (b > 0 ? P(b - 1) : (u128)0) + wave_incl_scan128(c);
                 const int w2 = first_exceeding(incl, Z);
                 if (w2 >= 0) {
-                    u = __shfl(uu, w2, WAVE);
-                    wu = shfl128(c, w2);
+                    u = (int32_t)readlane32((uint32_t)uu, w2);
+                    wu = readlane128(c, w2);
                 }
             }
         } else {
@@ -333,11 +338,11 @@ __device__ inline int sample_one(const SampleArgs &A, int64_t r, SampleLds &W)
                     const u128 incl = run2 + wave_incl_scan128(c[g4]);
                     const int w2 = first_exceeding(incl, Z);
                     if (w2 >= 0) {
-                        u = __shfl(uu[g4], w2, WAVE);
-                        wu = shfl128(c[g4], w2);
+                        u = (int32_t)readlane32((uint32_t)uu[g4], w2);
+                        wu = readlane128(c[g4], w2);
                         found = true;
                     } else {
-                        run2 = shfl128(incl, WAVE - 1);
+                        run2 = readlane128(incl, WAVE - 1);
                     }
                 }
             }
