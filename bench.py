@@ -40,6 +40,9 @@ def parse():
                         "instances, plain vs one "
                         "batched launch; serving: three resident k=7 tables under a Poisson request mix, continuous "
                         "batching vs first-in first-out")
+    p.add_argument("--serve-step", type=int, default=1 << 18,
+                   help="serving: samples per step of the continuous-batching server (its share granularity; "
+                        "2^18 is the library's default)")
     p.add_argument("--requests", type=int, default=2000, help="serving: requests per run")
     p.add_argument("--window", type=float, default=40.0, help="serving: longest arrival window per run (s)")
     p.add_argument("--calibrate-copy", action="store_true",
@@ -389,7 +392,7 @@ def run_serving(a):
         build_s.append(time.perf_counter() - t0)
         print(f"# table built in {build_s[-1]:.3f} s, {tabs[-1].info().bytes / 1e9:.1f} GB", file=sys.stderr, flush=True)
     trace = serving_trace(a.requests)
-    opts = dict(hbm_budget=24 << 30, step_samples=1 << 16, chunk=4096, max_active=512)
+    opts = dict(hbm_budget=24 << 30, step_samples=a.serve_step, chunk=4096, max_active=512)
     cbar = 1000
 
     def server(fifo, ags_weight=1.0, age_tau=0.0):
