@@ -147,8 +147,9 @@ __device__ inline int sample_star(const SampleArgs &A, int64_t r)
         const int64_t last = d - 1 - i;
         const uint64_t hit = __ballot(lane < nm && mpos == rr);
         const uint64_t hitl = __ballot(lane < nm && mpos == last);
-        const int64_t got = hit ? (int64_t)shfl64((uint64_t)mval, __ffsll((long long)hit) - 1) : rr;
-        const int64_t lastval = hitl ? (int64_t)shfl64((uint64_t)mval, __ffsll((long long)hitl) - 1) : last;
+        // (the hit lanes are the wave's common choice: their values read as scalars)
+        const int64_t got = hit ? (int64_t)readlane64((uint64_t)mval, __ffsll((long long)hit) - 1) : rr;
+        const int64_t lastval = hitl ? (int64_t)readlane64((uint64_t)mval, __ffsll((long long)hitl) - 1) : last;
         if (lane == 1 + i) leaf = A.g.col_idx[ra + got];
         const int q = hit ? __ffsll((long long)hit) - 1 : nm;
         if (lane == q) { mpos = rr; mval = lastval; }
