@@ -1050,7 +1050,9 @@ __device__ inline void combine_vertex_pf(const CombineArgs &A, int64_t v, uint64
             if (A.Slo[hs]) lds_dma_words(A.Slo[hs] + (size_t)v * L.WS[hs], Slo + L.soff[hs], L.WS[hs]);
     if (!A.zero_only) cv = A.g.colors[v];
     // lane q: handle of v's level-q record (q >= 2) and M_q(v) (0: sums not built)
-    const uint64_t *locp = nullptr, *poolp = nullptr;
+    // packed levels of one bitmap word also give each lane q that word: bit l marks
+    // dense position l, and the entry there is the popcount of the bits below l
+    const uint64_t *locp = nullptr, *poolp = nullptr, *bmp = nullptr;
     const uint32_t *metap = nullptr;
     const u128 *Np = nullptr, *mp = nullptr;
 #pragma unroll
@@ -1059,12 +1061,16 @@ __device__ inline void combine_vertex_pf(const CombineArgs &A, int64_t v, uint64
             mp = A.M[q];
             if (q >= 2) {
                 if (SLOTS) { metap = A.lev[q].meta; Np = A.lev[q].N; }
-                else { locp = A.lev[q].P.loc; poolp = A.lev[q].P.pool; }
+                else {
+                    locp = A.lev[q].P.loc; poolp = A.lev[q].P.pool;
+                    if (A.lev[q].P.BW == 1) bmp = A.lev[q].P.bm;
+                }
             }
         }
     uint64_t hd = 0;
     if (SLOTS) hd = ((uint64_t)v << 32) | (metap ? metap[v] : 0u);
     else hd = locp ? locp[v] : 0ull;
+    const uint64_t bmw = bmp ? bmp[v] : 0ull;
     const u128 Mq = mp ? mp[v] : (u128)0;
     uint64_t sw[PMAX + 1];
 #pragma unroll
@@ -1085,7 +1091,10 @@ __device__ inline void combine_vertex_pf(const CombineArgs &A, int64_t v, uint64
         el[q] = 0;
         if (q <= phi) {
             const RecView<SLOTS> r = h_rec<SLOTS>(A.lev[q], readlane64(hd, q));
-            if ((uint32_t)lane < r.len) {
+            if (!SLOTS && A.lev[q].P.BW == 1) {
+                const uint64_t word = readlane64(bmw, q);
+                if ((word >> lane) & 1ull) el[q] = r.lo[__popcll(word & ((1ull << lane) - 1ull))];
+            } else if ((uint32_t)lane < r.len) {
                 ek[q] = r.key[lane];
                 el[q] = r.lo[lane];
             }
@@ -1138,7 +1147,11 @@ __device__ inline void combine_vertex_pf(const CombineArgs &A, int64_t v, uint64
     for (int q = 2; q <= PMAX; q++) {
         if (q > phi) continue;
         const RecView<SLOTS> r = h_rec<SLOTS>(A.lev[q], readlane64(hd, q));
-        if ((uint32_t)lane < r.len) Xlo[L.xoff[q] + xidx[ek[q]]] = el[q];
+        if (!SLOTS && A.lev[q].P.BW == 1) {
+            if ((readlane64(bmw, q) >> lane) & 1ull) Xlo[L.xoff[q] + lane] = el[q];
+        } else if ((uint32_t)lane < r.len) {
+            Xlo[L.xoff[q] + xidx[ek[q]]] = el[q];
+        }
         if (r.len > WAVE || wide) {
             for (uint32_t e = lane; e < r.len; e += WAVE) {
                 const int x = L.xoff[q] + xidx[r.key[e]];
