@@ -1709,7 +1709,9 @@ static scc_status build_levels(scc_table *T)
         if (HL.designated[q]) s_need[k - HL.dec_hp[k][q]] = true;
     const int hub_degree = T->hub_degree;
 
-    int *err = (int *)T->mem.get(16);
+    // [0] flags, [1] wide vertices, [2] wide gather rows; bytes 16..23 receive
+    // a level's pool size, so that one read returns it with the flags
+    int *err = (int *)T->mem.get(32);
     std::vector<void *> scratch{err};
     struct Guard {
         scc_table *T; std::vector<void *> *s;
@@ -1897,25 +1899,35 @@ static scc_status build_levels(scc_table *T)
                 hipLaunchKernelGGL(k_gather, dim3((unsigned)n), dim3(WAVE), lds, st, G);
             }
             // high words only for the hubs (merged across chunks) and the listed
-            // rows whose bound reaches 2^64, in compact rows: hubs first
-            int nw = 0;
-            HIP_TRY(hipMemcpyAsync(&nw, err + 2, 4, hipMemcpyDeviceToHost, st));
-            HIP_TRY(hipStreamSynchronize(st));
-            Sx.hi_rows = (int64_t)nhub + nw;
-            Sx.hi = (uint64_t *)T->alloc((size_t)Sx.hi_rows * HL.WS[hs] * 8 + 8);
+            // rows whose bound reaches 2^64, in compact rows: hubs first. The hubs'
+            // rows are known now, so their gather runs while the count of wide
+            // rows comes back; with wide rows the array grows and the hub rows move.
+            const size_t row_bytes = (size_t)HL.WS[hs] * 8;
+            Sx.hi_rows = nhub;
+            Sx.hi = (uint64_t *)T->alloc((size_t)nhub * row_bytes + 8);
             if (!Sx.hi) return set_error(SCC_ENOMEM, "neighbour sums level %d, high words", hs);
             G.Shi = Sx.hi;
-            if (nhub)
+            if (nhub) {
                 hipLaunchKernelGGL(k_set_rows, dim3((unsigned)((nhub + 255) / 256)), dim3(256), 0, st, Sx.hrow, hubs,
                                    (const int *)nullptr, (int64_t)nhub, 0);
-            if (nw)
-                hipLaunchKernelGGL(k_set_rows, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, st, Sx.hrow, gwide,
-                                   (const int *)nullptr, (int64_t)nw, nhub);
-            if (nhub) {
                 hipLaunchKernelGGL(k_hub_prepare, dim3((unsigned)nhub), dim3(WAVE), 0, st, G, hubs);
                 hipLaunchKernelGGL(k_gather_hub, dim3((unsigned)nchunk), dim3(WAVE), lds, st, G, T->hub_chunk);
             }
-            if (nw) hipLaunchKernelGGL(k_gather_wide, dim3((unsigned)nw), dim3(WAVE), lds, st, G);
+            int nw = 0;
+            HIP_TRY(hipMemcpyAsync(&nw, err + 2, 4, hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            if (nw) {
+                uint64_t *hi = (uint64_t *)T->alloc((size_t)(nhub + nw) * row_bytes + 8);
+                if (!hi) return set_error(SCC_ENOMEM, "neighbour sums level %d, high words", hs);
+                if (nhub) HIP_TRY(hipMemcpyAsync(hi, Sx.hi, (size_t)nhub * row_bytes, hipMemcpyDeviceToDevice, st));
+                T->release(Sx.hi, (size_t)nhub * row_bytes + 8);
+                Sx.hi = hi;
+                Sx.hi_rows = (int64_t)nhub + nw;
+                G.Shi = hi;
+                hipLaunchKernelGGL(k_set_rows, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, st, Sx.hrow, gwide,
+                                   (const int *)nullptr, (int64_t)nw, nhub);
+                hipLaunchKernelGGL(k_gather_wide, dim3((unsigned)nw), dim3(WAVE), lds, st, G);
+            }
             HIP_TRY(hipEventRecord(gev[hs][1], st));
             // the sampler's hub running sums of this level (not part of the gather)
             if (fused)
@@ -1926,7 +1938,14 @@ static scc_status build_levels(scc_table *T)
         TableLevel &Lv = T->lev[h];
         Lv.loc = (uint64_t *)T->alloc((size_t)n * 8 + 8);
         if (!Lv.loc) return set_error(SCC_ENOMEM, "level %d locators", h);
-        if (bal && h == k - 1) {
+        const bool skipped = bal && h == k - 1;
+        if (!skipped) {
+            // sized by the level's width alone: allocated while the GPU still works
+            Lv.BW = (HL.W[h] + 63) / 64;
+            Lv.bm = (uint64_t *)T->alloc((size_t)n * Lv.BW * 8 + 8);
+            if (!Lv.bm) return set_error(SCC_ENOMEM, "level %d bitmaps", h);
+        }
+        if (skipped) {
             // skipped level: every record empty (its entry count stays 0 in the summary)
             Lv.pool = (uint64_t *)T->alloc(64);
             if (!Lv.pool) return set_error(SCC_ENOMEM, "level %d", h);
@@ -1966,19 +1985,17 @@ static scc_status build_levels(scc_table *T)
         if (n) hipLaunchKernelGGL(k_words, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, meta, words);
         scc_status sst = scan_incl<uint64_t>(T, words, words, n);
         if (sst) return sst;
-        int herr[4] = {0, 0, 0, 0};
-        uint64_t total = 0;
-        HIP_TRY(hipMemcpyAsync(herr, err, sizeof herr, hipMemcpyDeviceToHost, st));
-        if (n) HIP_TRY(hipMemcpyAsync(&total, words + (n - 1), 8, hipMemcpyDeviceToHost, st));
+        struct { int f[4]; uint64_t total; } hr{};
+        if (n) HIP_TRY(hipMemcpyAsync(err + 4, words + (n - 1), 8, hipMemcpyDeviceToDevice, st));
+        HIP_TRY(hipMemcpyAsync(&hr, err, sizeof hr, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
+        const int *herr = hr.f;
+        const uint64_t total = n ? hr.total : 0;
         if (herr[0] & 1) return set_error(SCC_EOVERFLOW, "a level-%d count needs more than %d bits", h, T->max_bits);
         if (herr[0] & 2) return set_error(SCC_EOVERFLOW, "a level-%d neighbour sum may exceed 128 bits", h);
         Lv.pool_words = total;
         Lv.pool = (uint64_t *)T->alloc((size_t)total * 8 + 64);
         if (!Lv.pool) return set_error(SCC_ENOMEM, "level %d pool (%llu words)", h, (unsigned long long)total);
-        Lv.BW = (HL.W[h] + 63) / 64;
-        Lv.bm = (uint64_t *)T->alloc((size_t)n * Lv.BW * 8 + 8);
-        if (!Lv.bm) return set_error(SCC_ENOMEM, "level %d bitmaps", h);
         if (n) {
             PackView P{n, HL.W[h], Lv.BW, HL.nkeys, meta, words, slot_key, slot_lo, slot_hi, Nsc, Lv.pool, Lv.loc,
                        Lv.bm, T->key_xidx, T->colors};
