@@ -936,6 +936,9 @@ __device__ inline void combine_vertex(const CombineArgs &A, int64_t v, uint64_t 
 // sums (S): lane o evaluates outputs o, o + 64, ..., and the nonzero ones are
 // compacted into v's slot right away (ballot + prefix count keeps ascending
 // key order).
+// x s modulo 2^128 (the vertex's bound keeps every product below it)
+__device__ inline u128 mul_64x128(uint64_t x, u128 s) { return (u128)x * lo64(s) + ((u128)(x * hi64(s)) << 64); }
+
 __device__ inline void combine_outputs(const CombineArgs &A, int64_t v, int cv, const uint64_t *Xlo,
                                        const uint64_t *Slo, const uint64_t *Xhi, const uint64_t *Shi, bool owide,
                                        bool wide)
@@ -971,6 +974,13 @@ __device__ inline void combine_outputs(const CombineArgs &A, int64_t v, int cv, 
                 for (int i = 0; i < nsplit; i++) {
                     const uint32_t xs = L.term_xs[tb + i];
                     acc += (u128)Xlo[xb + (xs & 0xffu)] * Slo[sb + (xs >> 8)];
+                }
+            } else if (!Xhi) {
+                // own counts in 64 bits, neighbour sums in 128
+                for (int i = 0; i < nsplit; i++) {
+                    const uint32_t xs = L.term_xs[tb + i];
+                    const int xi = xb + (int)(xs & 0xffu), si = sb + (int)(xs >> 8);
+                    acc += mul_64x128(Xlo[xi], mk128(Slo[si], Shi[si]));
                 }
             } else {
                 for (int i = 0; i < nsplit; i++) {
@@ -1028,7 +1038,7 @@ __device__ inline void wait_vm_all() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 // words (wide) are staged by loops as well.
 template <bool SLOTS, int PMAX, bool DMA>
 __device__ inline void combine_vertex_pf(const CombineArgs &A, int64_t v, uint64_t *lo_area, uint64_t *hi_area,
-                                         int *wide_list, int *wide_count)
+                                         int *wide_list, int *wide_count, bool own_hi = true)
 {
     const DevLut &L = *A.L;
     const int lane = threadIdx.x;
@@ -1044,7 +1054,8 @@ __device__ inline void combine_vertex_pf(const CombineArgs &A, int64_t v, uint64
     const int plo = A.bal ? 2 : 1, phi = A.bal ? h - 2 : h - 1;
     const int XT = L.xoff[h];
     uint64_t *Xlo = lo_area, *Slo = lo_area + XT;
-    uint64_t *Xhi = hi_area, *Shi = hi_area + XT;
+    // own_hi false: hi_area holds the neighbour sums' high words only
+    uint64_t *Xhi = own_hi ? hi_area : nullptr, *Shi = own_hi && hi_area ? hi_area + XT : hi_area;
     if (DMA)
         for (int hs = 1; hs <= phi; hs++)
             if (A.Slo[hs]) lds_dma_words(A.Slo[hs] + (size_t)v * L.WS[hs], Slo + L.soff[hs], L.WS[hs]);
@@ -1111,17 +1122,25 @@ __device__ inline void combine_vertex_pf(const CombineArgs &A, int64_t v, uint64
         return;
     }
     const bool owide = hi64(U) != 0;
-    bool wide = false;
-    if (owide)
-        wide = __ballot(lane <= phi && ((lane >= 2 && h_wide<SLOTS>(hd)) || (lane >= 1 && hi64(Mq) != 0))) != 0;
+    bool wide = false, xwide = false;
+    if (owide) {
+        xwide = __ballot(lane >= 2 && lane <= phi && h_wide<SLOTS>(hd)) != 0;
+        wide = xwide || __ballot(lane >= 1 && lane <= phi && hi64(Mq) != 0) != 0;
+    }
     if (wide && !hi_area) {
+        // own records with high words: from the back of the list (wide_count[2]);
+        // neighbour sums alone: from the front (wide_count[0])
         if (DMA) wait_vm_all();
-        if (lane == 0) wide_list[atomicAdd(wide_count, 1)] = (int)v;
+        if (lane == 0) {
+            if (xwide) wide_list[A.g.n - 1 - atomicAdd(wide_count + 2, 1)] = (int)v;
+            else wide_list[atomicAdd(wide_count, 1)] = (int)v;
+        }
         return;
     }
+    const bool stage_xhi = wide && Xhi;
     for (int i = lane; i < XT; i += WAVE) {
         Xlo[i] = 0;
-        if (wide) Xhi[i] = 0;
+        if (stage_xhi) Xhi[i] = 0;
     }
     if (!DMA) {
 #pragma unroll
@@ -1152,17 +1171,17 @@ __device__ inline void combine_vertex_pf(const CombineArgs &A, int64_t v, uint64
         } else if ((uint32_t)lane < r.len) {
             Xlo[L.xoff[q] + xidx[ek[q]]] = el[q];
         }
-        if (r.len > WAVE || wide) {
+        if (r.len > WAVE || stage_xhi) {
             for (uint32_t e = lane; e < r.len; e += WAVE) {
                 const int x = L.xoff[q] + xidx[r.key[e]];
                 if (e >= WAVE) Xlo[x] = r.lo[e];
-                if (wide) Xhi[x] = r.hi ? r.hi[e] : 0;
+                if (stage_xhi) Xhi[x] = r.hi ? r.hi[e] : 0;
             }
         }
     }
     if (DMA) wait_vm_all();
     __syncthreads();
-    combine_outputs(A, v, cv, Xlo, Slo, Xhi, Shi, owide, wide);
+    combine_outputs(A, v, cv, Xlo, Slo, stage_xhi ? Xhi : nullptr, Shi, owide, wide);
 }
 
 // one workgroup per vertex, low words in LDS; vertices that need 128 bits are
@@ -1184,15 +1203,20 @@ __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(8, 8)
     combine_vertex_pf<false, PMAX, false>(A, __builtin_amdgcn_readfirstlane(rows[blockIdx.x]), sm, nullptr, wide_list, wide_count);
 }
 
-// the listed vertices, with high words in LDS as well (lds = 2 (xoff_h + soff_h) words)
+// the listed vertices, with high words in LDS as well. OWN: vertices whose own
+// records have high words, listed from the back of wide_list (lds = 2 (xoff_h +
+// soff_h) words); else vertices with high words in neighbour sums only, listed
+// from the front, which stage just those (lds = xoff_h + 2 soff_h words) and so
+// fit more waves per CU
+template <bool OWN>
 __global__ void __launch_bounds__(WAVE) k_combine_wide(CombineArgs A, const int *wide_list, const int *wide_count)
 {
     extern __shared__ uint64_t sm[];
     const int cnt = __builtin_amdgcn_readfirstlane(*wide_count);
     const int lo_words = A.L->xoff[A.h] + A.L->soff[A.h];
     for (int i = blockIdx.x; i < cnt; i += gridDim.x) {
-        const int v = __builtin_amdgcn_readfirstlane(wide_list[i]);
-        combine_vertex_pf<false, SCC_KMAX - 1, false>(A, v, sm, sm + lo_words, nullptr, nullptr);
+        const int v = __builtin_amdgcn_readfirstlane(OWN ? wide_list[A.g.n - 1 - i] : wide_list[i]);
+        combine_vertex_pf<false, SCC_KMAX - 1, false>(A, v, sm, sm + lo_words, nullptr, nullptr, OWN);
         __syncthreads();
     }
 }
@@ -1978,8 +2002,19 @@ static scc_status build_levels(scc_table *T)
             if (phi <= 3) launch_combine<3>(C, n, zl ? zrows : nullptr, nzero, lds, st, wide_list, err + 1);
             else if (phi <= 5) launch_combine<5>(C, n, zl ? zrows : nullptr, nzero, lds, st, wide_list, err + 1);
             else launch_combine<SCC_KMAX - 1>(C, n, zl ? zrows : nullptr, nzero, lds, st, wide_list, err + 1);
-            hipLaunchKernelGGL(k_combine_wide, dim3((unsigned)std::min<int64_t>(n, 1024)), dim3(WAVE), 2 * lds, st, C,
-                               wide_list, err + 1);
+            // the 128-bit vertices (at k = 8 most of level 7, nearly all with high
+            // words in neighbour sums only) stride over as many waves as each
+            // kernel's LDS staging lets the chip hold
+            int dev = 0, ncu = 0, per_s = 0, per_own = 0;
+            const size_t lds_s = (size_t)(HL.xoff[h] + 2 * HL.soff[h]) * 8;
+            HIP_TRY(hipGetDevice(&dev));
+            HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+            HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_s, k_combine_wide<false>, WAVE, lds_s));
+            HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_own, k_combine_wide<true>, WAVE, 2 * lds));
+            const int64_t gs = std::min<int64_t>(n, std::max<int64_t>(1024, (int64_t)ncu * per_s));
+            const int64_t go = std::min<int64_t>(n, std::max<int64_t>(1024, (int64_t)ncu * per_own));
+            hipLaunchKernelGGL(k_combine_wide<false>, dim3((unsigned)gs), dim3(WAVE), lds_s, st, C, wide_list, err + 1);
+            hipLaunchKernelGGL(k_combine_wide<true>, dim3((unsigned)go), dim3(WAVE), 2 * lds, st, C, wide_list, err + 3);
         }
         // record sizes and offsets; the pool size and the error flags in one read
         if (n) hipLaunchKernelGGL(k_words, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, meta, words);
