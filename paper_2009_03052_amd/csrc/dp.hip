@@ -289,7 +289,9 @@ __device__ inline void round_owners(OwnerLds &O, uint32_t q0, uint32_t s, uint32
 // and returns (in every lane) the saturating sum of those neighbours' level
 // sums N. With wideS false only low words are added: exact whenever that
 // returned bound is below 2^64, since every entry and every partial sum is
-// at most the bound.
+// at most the bound. A 64-bit pass stops at the first chunk of neighbours whose
+// headers take the bound to 2^64 (the row is redone in 128 bits) and returns
+// that partial bound, which is enough to say so.
 template <bool SLOTS>
 __device__ inline u128 gather_range(const GatherArgs &A, int64_t a, int64_t b, bool wideS, uint64_t *acc_lo,
                                     uint64_t *acc_hi, const int16_t *ssm, OwnerLds &O)
@@ -301,6 +303,11 @@ __device__ inline u128 gather_range(const GatherArgs &A, int64_t a, int64_t b, b
         const uint64_t hd = e < b ? src_handle<SLOTS>(A.L, A.g.col_idx[e]) : (SLOTS ? ~0ull << 32 : 0ull);
         const uint32_t len = e < b ? h_len<SLOTS>(hd) : 0u;
         if (len) m = sat_add(m, h_N<SLOTS>(A.L, hd));
+        // 64 lane sums below 2^58 each stay below 2^64: the wave sum only when one is not
+        if (!wideS && __ballot(hi64(m) != 0 || (lo64(m) >> 58) != 0)) {
+            const u128 mt = wave_satsum128(m);
+            if (hi64(mt)) return mt;
+        }
         const uint32_t incl = wave_incl_scan32(len);
         const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, WAVE - 1);
         const uint32_t first = incl - len;
