@@ -1740,8 +1740,12 @@ static scc_status build_levels(scc_table *T)
         if (HL.designated[q]) s_need[k - HL.dec_hp[k][q]] = true;
     const int hub_degree = T->hub_degree;
 
-    // [0] flags, [1] wide vertices, [2] wide gather rows; bytes 16..23 receive
-    // a level's pool size, so that one read returns it with the flags
+    // [0] flags, [1] 128-bit vertices with high words in neighbour sums only,
+    // [2] wide gather rows, [3] 128-bit vertices whose own records have high
+    // words; bytes 16..23 receive a level's pool size, so that one read returns
+    // it with the flags. A high-word array released while its copy is still
+    // queued is safe: the allocator hooks free in the table's stream order
+    // (hipFree, without hooks, waits for the device).
     int *err = (int *)T->mem.get(32);
     std::vector<void *> scratch{err};
     struct Guard {
@@ -1891,7 +1895,7 @@ static scc_status build_levels(scc_table *T)
     for (int h = 2; h <= k; h++) {
         const bool last = h == k;
         HIP_TRY(hipEventRecord(ev[h][0], st));
-        HIP_TRY(hipMemsetAsync(err, 0, 16, st));   // [0] flags, [1] wide vertices
+        HIP_TRY(hipMemsetAsync(err, 0, 16, st));   // flags and the level's counts of listed rows
         const int hs = h - 1;   // neighbour sums needed now
         if (hs >= 2 && s_need[hs]) {
             TableSums &Sx = T->S[hs];
