@@ -115,7 +115,7 @@ def round_skipping(scc, dg, dcol, k, ns, sseed, verts, par, zinfo, zbuild_ms):
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
     torch.cuda.synchronize()
     ev[0].record()
-    bt = scc.Table(dg, dcol, k, rooting=scc.ROOT_BALANCED)
+    bt = scc.Table(dg, dcol, k, rooting=scc.ROOT_BALANCED, validate=False)
     ev[1].record()
     bt.sample(ns, seed=sseed, out=(verts, par))
     ev[2].record()
@@ -151,7 +151,7 @@ def biased_colouring(scc, dg, k, lam, cseed, ns, sseed, verts, par, zinfo, zbuil
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
     torch.cuda.synchronize()
     ev[0].record()
-    bt = scc.Table(dg, dcol, k, rooting=scc.ROOT_ZERO)
+    bt = scc.Table(dg, dcol, k, rooting=scc.ROOT_ZERO, validate=False)
     ev[1].record()
     bt.sample(ns, seed=sseed, out=(verts, par))
     ev[2].record()
@@ -172,14 +172,14 @@ def biased_colouring(scc, dg, k, lam, cseed, ns, sseed, verts, par, zinfo, zbuil
 
 
 def variable_length(scc, dg, dcol, k, ns, sseed, verts, par, zinfo):
-    """The same table re-encoded with variable-length counts (Sec. 3.5): build
+    """The same table re-encoded with variable-length counts (Sec. 3.3): build
     (with the sampler's running sums, then the re-encoding), record bytes and
     sampling rate next to the fixed layout."""
     import torch
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
     torch.cuda.synchronize()
     ev[0].record()
-    vt = scc.Table(dg, dcol, k, rooting=scc.ROOT_ZERO, vlc=True)
+    vt = scc.Table(dg, dcol, k, rooting=scc.ROOT_ZERO, vlc=True, validate=False)
     ev[1].record()
     vt.sample(ns, seed=sseed, out=(verts, par))
     ev[2].record()
@@ -254,11 +254,11 @@ def run_batching(a):
 
     def plain():
         for g, c, k in inst:
-            t = scc.Table(g, c, k)
+            t = scc.Table(g, c, k, validate=False)
             del t
 
     def batched():
-        tabs, rep = scc.build_batch(inst, autotune=True)
+        tabs, rep = scc.build_batch(inst, autotune=True, validate=False)
         del tabs
         return rep
 
@@ -387,7 +387,7 @@ def run_serving(a):
         dg = scc.DeviceGraph.from_graph(g)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        tabs.append(scc.Table(dg, torch.as_tensor(c).cuda(), k, rooting=scc.ROOT_ZERO))
+        tabs.append(scc.Table(dg, torch.as_tensor(c).cuda(), k, rooting=scc.ROOT_ZERO, validate=False))
         torch.cuda.synchronize()
         build_s.append(time.perf_counter() - t0)
         print(f"# table built in {build_s[-1]:.3f} s, {tabs[-1].info().bytes / 1e9:.1f} GB", file=sys.stderr, flush=True)
@@ -497,7 +497,7 @@ def main():
     print(f"# graph n={g.n} m={g.m} d_max={int(g.degrees().max())}", file=sys.stderr, flush=True)
 
     def step():
-        tab = scc.Table(dg, dcol, k, rooting=scc.ROOT_ZERO)
+        tab = scc.Table(dg, dcol, k, rooting=scc.ROOT_ZERO, validate=False)
         tab.sample(ns, seed=sseed, out=(verts, par))
         tab.classify(verts, out=(code, cls))
         return tab
@@ -520,7 +520,7 @@ def main():
     # phase split (one extra step, events around each call)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
     ev[0].record()
-    tab = scc.Table(dg, dcol, k, rooting=scc.ROOT_ZERO)
+    tab = scc.Table(dg, dcol, k, rooting=scc.ROOT_ZERO, validate=False)
     ev[1].record()
     tab.sample(ns, seed=sseed, out=(verts, par))
     ev[2].record()

@@ -239,6 +239,24 @@ def lollipop(clique: int, tail: int) -> Graph:
     return csr_from_edges(clique + tail, np.array(e, dtype=np.int64))
 
 
+def two_hubs(d: int = 1 << 15, shared: int = 1 << 13, n_mid: int = 48, mid_deg: int = 150, seed: int = 5) -> Graph:
+    """Two hubs of degree d over a path of 2d - shared leaves (the hubs share
+    `shared` of them), plus n_mid vertices of degree mid_deg, each adjacent to
+    mid_deg - 2 random leaves and to both hubs. The hubs take the two largest
+    ids, so they come last in every row that holds them."""
+    rng = np.random.default_rng(seed)
+    L = 2 * d - shared
+    A, B = L + n_mid, L + n_mid + 1
+    e = [np.stack([np.arange(L - 1), np.arange(1, L)], 1),
+         np.stack([np.full(d, A), np.arange(d)], 1),
+         np.stack([np.full(d, B), np.arange(L - d, L)], 1)]
+    for m in range(L, L + n_mid):
+        nb = rng.choice(L, mid_deg - 2, replace=False)
+        e.append(np.stack([np.full(nb.size, m), nb], 1))
+        e.append(np.array([[m, A], [m, B]]))
+    return csr_from_edges(L + n_mid + 2, np.concatenate(e).astype(np.int64))
+
+
 def from_networkx(g) -> Graph:
     nodes = sorted(g.nodes())
     idx = {v: i for i, v in enumerate(nodes)}

@@ -70,16 +70,21 @@ typedef struct {
 
 typedef struct {
     int64_t n;                 /* number of vertices, < 2^31 */
-    int64_t nnz;               /* 2m, length of col_idx */
-    const int64_t *row_ptr;    /* device pointer, n + 1 entries */
-    const int32_t *col_idx;    /* device pointer, nnz entries */
+    int64_t nnz;               /* 2m, length of col_idx, < 2^40 */
+    const int64_t *row_ptr;    /* n + 1 entries (never NULL, also for n = 0) */
+    const int32_t *col_idx;    /* nnz entries */
+    int on_device;             /* 1: row_ptr, col_idx and the call's colours are device
+                                  pointers, borrowed for the table's lifetime (the caller
+                                  keeps them alive and unchanged); 0: host pointers, copied
+                                  by the build into device memory the table owns (the
+                                  caller may free them when the call returns) */
 } scc_csr;
 
 typedef struct {
     int rooting;               /* SCC_ROOT_ZERO (default): level k kept at colour-0
                                   vertices only (zero-rooting, Sec. 3.4);
                                   SCC_ROOT_ALL: at every vertex (Eq. (1) as is);
-                                  SCC_ROOT_BALANCED: round skipping (Sec. 3.5, the
+                                  SCC_ROOT_BALANCED: round skipping (Sec. 3.3, the
                                   balanced decomposition), k >= 4: level k-1 is not
                                   built and level k holds, at every vertex, only the
                                   designated rooting of each non-star unrooted shape
@@ -92,14 +97,18 @@ typedef struct {
     const scc_allocator *alloc;/* NULL: hipMalloc / hipFree */
     int hub_degree;            /* gather rows of at least this degree are split over
                                   many workgroups; 0 = library default */
-    int validate;              /* nonzero: check the CSR and colours on the device first */
+    int no_validate;           /* 0 (default): check the CSR and colours on the device
+                                  before anything reads them, SCC_EINVAL on a violation;
+                                  nonzero: skip the check (the caller vouches for the
+                                  input; a malformed CSR then makes the kernels read
+                                  out of bounds) */
     int gather_mode;           /* neighbour-sum gather of the rows below the hub threshold:
                                   SCC_GATHER_AUTO (0) chooses per level from the level's
                                   record sizes; SCC_GATHER_GROUPED: rows of at most 64
                                   neighbours several to a wave; SCC_GATHER_ROW: one
                                   row per wave. Results are identical in every mode. */
     int vlc;                   /* nonzero: after the build, re-encode every stored level
-                                  with variable-length counts (Sec. 3.5): per entry a
+                                  with variable-length counts (Sec. 3.3): per entry a
                                   u16 of key (11 bits) and byte length l (5 bits), the
                                   count in l bytes, a byte-offset checkpoint every 32
                                   entries. The sampler's running sums are built first.
@@ -126,13 +135,15 @@ enum { SCC_GATHER_AUTO = 0, SCC_GATHER_GROUPED = 1, SCC_GATHER_ROW = 2 };
  * the non-star t_j; the number of uncoloured k-stars is in scc_table_info.stars
  * (SCC_EOVERFLOW if it needs more than 128 bits).
  *
- * g, colors: device pointers, borrowed for the lifetime of the table (the
- * sampler and classifier read them); the caller keeps them alive and unchanged.
- * colors: uint8[n]. k in [2, 8]. opt may be NULL (defaults).
- * *out receives a library-owned, immutable table; free it with
- * scc_table_destroy. Errors: SCC_EINVAL (k, colours or CSR; the CSR is checked
- * only when opt->validate is set), SCC_EOVERFLOW (a count needs more than
- * max_bits bits; detected from a per-vertex bound before anything wraps),
+ * g, colors: device pointers borrowed for the lifetime of the table (the
+ * sampler and classifier read them) when g->on_device is set, else host
+ * pointers that the build copies. colors: uint8[n]. k in [2, 8]. opt may be
+ * NULL (defaults). *out receives a library-owned, immutable table; free it
+ * with scc_table_destroy. Errors: SCC_EINVAL (k, sizes, colours or CSR: unless
+ * opt->no_validate is set, the CSR is checked to be simple, symmetric and
+ * sorted with row_ptr[0] = 0 and row_ptr[n] = nnz, and every colour to be below
+ * k, before any other kernel reads them), SCC_EOVERFLOW (a count needs more
+ * than max_bits bits; detected from a per-vertex bound before anything wraps),
  * SCC_ENOMEM, SCC_EDEVICE. On error *out is NULL.
  */
 scc_status scc_build_table(const scc_csr *g, const uint8_t *colors, int k,
@@ -183,11 +194,17 @@ scc_status scc_gather_bytes(const scc_table *t, double out[9]);
 scc_status scc_occ(const scc_table *t, int64_t v, int32_t key, uint64_t out[2]);
 
 /*
- * scc_export_level -- the stored level-h records in vertex order.
+ * scc_export_level -- the stored level-h records in vertex order: the
+ * non-zero counts c(T_C, v) of the coloured rooted treelets on h nodes at each
+ * vertex, sorted by key, as the count tables of Sec. 3.2 keep them (pairs of
+ * treelet and count, zeros dropped). Level 1 is one count of 1 per vertex, at
+ * the key of ({root}, {c_v}).
  * With off == NULL only *nnz_out is set (the number of stored counts).
  * Otherwise off: device int64[n+1] (record of v is [off[v], off[v+1])),
  * key: device uint16[nnz] (ascending within a record), lo/hi: device
  * uint64[nnz] (the count's low and high 64 bits). All caller-owned.
+ * Errors: SCC_EINVAL (h outside [1, k]), SCC_ENOMEM (n * 8 bytes of scratch),
+ * SCC_EDEVICE. Synchronises `stream`.
  */
 scc_status scc_export_level(const scc_table *t, int h, int64_t *nnz_out,
                             int64_t *off, uint16_t *key, uint64_t *lo, uint64_t *hi, void *stream);
@@ -209,7 +226,7 @@ scc_status scc_export_level(const scc_table *t, int h, int64_t *nnz_out,
  * and rejected when >= N; draw 0 is the root, draws 1 + 2i and 2 + 2i belong
  * to the i-th decomposition. Sample s uses index first_index + s.
  *
- * Tables built with SCC_ROOT_BALANCED (round skipping, Sec. 3.5): level k
+ * Tables built with SCC_ROOT_BALANCED (round skipping, Sec. 3.3): level k
  * holds only designated rootings, so shape = -1 draws the shape first: draw 0
  * picks the non-star shape j with probability t_j / t (first j, ascending,
  * whose running sum of t_j exceeds a uniform integer below t), then shape j is
@@ -261,12 +278,15 @@ scc_status scc_catalog(int k, int64_t *num_classes, uint32_t *codes, int64_t *si
  * Round r draws `round_size` samples of one unrooted shape j with sample
  * indices [drawn, drawn + round_size) of (seed, stream_id), classifies them and
  * adds the hits to c_i and round_size to n_j. Start: the shape with the largest
- * t_j (ties: smaller j). After a round in which some class first reaches
- * c_i >= cbar it becomes covered, and the next shape is
+ * t_j (ties: smaller j). After a round, every class the round hit whose count
+ * has reached c_i >= cbar is covered (from then on), and if there is any such
+ * class the next shape is chosen again:
  *   j* = argmin_{j: t_j > 0} (1/t_j) sum_{i covered} sigma_ij c_i / w_i,
- *   w_i = sum_j n_j sigma_ij / t_j  (double precision, j and i ascending; ties
- * to the smaller j). Stops when every class is covered or the next round would
- * exceed `budget` samples. round_size = 1 is the algorithm as printed.
+ *   w_i = sum_j n_j sigma_ij / t_j  (double precision, j and i ascending; a
+ * score within a relative 2^-40 of the best so far is a tie, and ties go to
+ * the smaller j). Stops when every class is covered or the next round would
+ * exceed `budget` samples. round_size = 1 is the algorithm as printed: its
+ * switch test runs after every sample whose class has reached cbar.
  * Outputs (host): hits int64[N_k]; w double[N_k] (0 for classes never hit;
  * c_i / w_i estimates the colourful count of class i, divide by p_k =
  * scc_colour_set_probability(k, lambda, k, 1) of the colouring's law (k!/k^k
@@ -283,7 +303,7 @@ scc_status scc_ags(const scc_table *t, int64_t cbar, int64_t round_size, int64_t
    DFS bitstring among their rootings. */
 int scc_num_unrooted(int k);
 
-/* Round skipping (Sec. 3.5): the designated rooting of unrooted k-shape j, the
+/* Round skipping (Sec. 3.3): the designated rooting of unrooted k-shape j, the
    smallest rooted rank (ascending DFS bitstring among the rooted k-shapes)
    whose canonical decomposition splits the tree into two trees of 2..k-2
    nodes. Returns -1 for the k-star, which has no such rooting, for k < 4 and

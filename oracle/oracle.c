@@ -20,7 +20,7 @@
  *   - induced-graphlet classification by a minimum-over-permutations
  *     adjacency code, spanning-tree numbers (Sec. 4.4 "Graphlet manipulations")
  *   - AGS, adaptive graphlet sampling (Sec. 4.1, Algorithm AGS)
- *   - round skipping: balanced rootings, direct star sampling (Sec. 3.5)
+ *   - round skipping: balanced rootings, direct star sampling (Sec. 3.3)
  *   - biased colourings and the probability of a colour set (Sec. 3.5)
  *
  * Parity status: every function here is pinned by a CPU test (brute force on
@@ -209,7 +209,7 @@ static void build_shapes(void)
 }
 
 /* ------------------------------------------------------------------------- */
-/* Round skipping (Sec. 3.5, balanced treelet decomposition). A rooted shape  */
+/* Round skipping (Sec. 3.3, balanced treelet decomposition). A rooted shape  */
 /* is balanced when its canonical decomposition splits it into two trees of   */
 /* at least 2 and at most h-2 nodes. Every unrooted h-shape except the star   */
 /* has a balanced rooting (root at an end of an edge whose removal leaves two */
@@ -861,7 +861,7 @@ static int sample_one(const orc_table *T, int shape, const u128 *pre, uint64_t s
     return ORC_OK;
 }
 
-/* Uncoloured k-stars (round skipping, Sec. 3.5): the centre v with probability
+/* Uncoloured k-stars (round skipping, Sec. 3.3): the centre v with probability
    proportional to binom(d_v, k-1) (draw 0), then k-1 distinct neighbours, the
    i-th uniform among those not taken yet (draw 1 + i): position r of the
    remaining d_v - i neighbours, where a taken position is refilled by the last
@@ -1200,12 +1200,19 @@ int orc_spanning_trees_by_shape(uint32_t code, int k, int64_t *out /* unr_n[k] *
 /* ------------------------------------------------------------------------- */
 /* AGS (Sec. 4.1): rounds of `round_size` samples of one treelet shape.       */
 /* Start with the most frequent shape (largest t_j, ties to the smaller id).   */
-/* After each round: n_j += round size, c_i += hits; classes with            */
-/* c_i >= cbar become covered; on any new cover, switch to                    */
+/* After each round: n_j += round size, c_i += hits. The algorithm's switch   */
+/* test looks at the class just sampled: if its count has reached cbar, the   */
+/* class joins the covered set (if it was not there) and the next shape is    */
+/* chosen again, whether or not the cover is new. With rounds, that test is   */
+/* made for every class the round hit; if any of them has c_i >= cbar, switch */
+/* to                                                                          */
 /*   j* = argmin_{j : t_j > 0} (1/t_j) sum_{i covered} sigma_ij c_i / w_i,     */
-/* with w_i = sum_j n_j sigma_ij / t_j (ties to the smaller j). Stop when all  */
-/* classes are covered or `budget` samples were drawn. Round r draws sample   */
-/* indices [drawn, drawn + round_size) of (seed, stream).                     */
+/* with w_i = sum_j n_j sigma_ij / t_j. Scores within a relative 2^-40 of the  */
+/* best so far count as ties, and ties go to the smaller j (exactly equal     */
+/* rationals must not be split by FP64 rounding). Stop when all classes are   */
+/* covered or `budget` samples were drawn. Round r draws sample indices       */
+/* [drawn, drawn + round_size) of (seed, stream); round_size = 1 is the       */
+/* algorithm sample by sample.                                                 */
 /* Outputs per class: hits c_i and w_i; the estimate of the colourful count   */
 /* is c_i / w_i.                                                              */
 /* ------------------------------------------------------------------------- */
@@ -1227,6 +1234,7 @@ int orc_ags(const orc_table *T, int64_t cbar, int64_t round_size, int64_t budget
     double *w = calloc(s, sizeof(double));
     int64_t *nj = calloc(ns, sizeof(int64_t));
     char *cov = calloc(s, 1);
+    char *hit = calloc(s, 1);
     int32_t *verts = malloc(round_size * k * sizeof(int32_t));
     int8_t *par = malloc(round_size * k);
     int32_t *cls = malloc(round_size * sizeof(int32_t));
@@ -1250,12 +1258,18 @@ int orc_ags(const orc_table *T, int64_t cbar, int64_t round_size, int64_t budget
             int i = cls[q];
             if (i < 0) { st = ORC_EINVAL; set_err("internal: unclassified sample"); goto done; }
             c[i]++;
+            hit[i] = 1;
             if (!sig_ok[i]) { orc_spanning_trees_by_shape(cat_codes[k][i], k, sig + (size_t)i * ns); sig_ok[i] = 1; }
         }
-        int newcov = 0;
-        for (int i = 0; i < s; i++)
-            if (!cov[i] && c[i] >= cbar) { cov[i] = 1; ncov++; newcov = 1; }
-        if (newcov && ncov < s) {
+        int reselect = 0;
+        for (int i = 0; i < s; i++) {
+            if (hit[i] && c[i] >= cbar) {
+                reselect = 1;
+                if (!cov[i]) { cov[i] = 1; ncov++; }
+            }
+            hit[i] = 0;
+        }
+        if (reselect && ncov < s) {
             for (int i = 0; i < s; i++) {
                 if (!cov[i]) continue;
                 double acc = 0.0;
@@ -1271,7 +1285,7 @@ int orc_ags(const orc_table *T, int64_t cbar, int64_t round_size, int64_t budget
                 for (int i = 0; i < s; i++)
                     if (cov[i]) acc += (double)sig[(size_t)i * ns + q] * (double)c[i] / w[i];
                 acc /= tjd[q];
-                if (best < 0 || acc < bv) { best = q; bv = acc; }
+                if (best < 0 || acc < bv * (1.0 - 0x1p-40)) { best = q; bv = acc; }
             }
             j = best;
         }
@@ -1288,6 +1302,6 @@ int orc_ags(const orc_table *T, int64_t cbar, int64_t round_size, int64_t budget
     *out_nrounds = nr;
     st = ORC_OK;
 done:
-    free(sig); free(sig_ok); free(c); free(w); free(nj); free(cov); free(verts); free(par); free(cls);
+    free(sig); free(sig_ok); free(c); free(w); free(nj); free(cov); free(hit); free(verts); free(par); free(cls);
     return st;
 }

@@ -41,12 +41,13 @@ class _Allocator(C.Structure):
 
 
 class _Csr(C.Structure):
-    _fields_ = [("n", C.c_int64), ("nnz", C.c_int64), ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p)]
+    _fields_ = [("n", C.c_int64), ("nnz", C.c_int64), ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p),
+                ("on_device", C.c_int)]
 
 
 class _BuildOpts(C.Structure):
     _fields_ = [("rooting", C.c_int), ("max_bits", C.c_int), ("stream", C.c_void_p),
-                ("alloc", C.POINTER(_Allocator)), ("hub_degree", C.c_int), ("validate", C.c_int),
+                ("alloc", C.POINTER(_Allocator)), ("hub_degree", C.c_int), ("no_validate", C.c_int),
                 ("gather_mode", C.c_int), ("vlc", C.c_int)]
 
 
@@ -214,27 +215,45 @@ class DeviceGraph:
 
 
 class Table:
-    """The count table of one graph and colouring (``scc_build_table``)."""
+    """The count table of one graph and colouring (``scc_build_table``).
 
-    def __init__(self, graph: DeviceGraph, colors, k: int, rooting: int = ROOT_ZERO, max_bits: int = 128,
-                 validate: bool = False, stream=None, use_torch_allocator: bool = True, hub_degree: int = 0,
+    ``graph`` is a :class:`DeviceGraph` (borrowed device arrays, ``on_device = 1``)
+    or any object with ``n``, ``row_ptr`` and ``col_idx`` numpy arrays (a host
+    graph: the library copies it and the colours, ``on_device = 0``). The input
+    is checked on the device unless ``validate=False``.
+    """
+
+    def __init__(self, graph, colors, k: int, rooting: int = ROOT_ZERO, max_bits: int = 128,
+                 validate: bool = True, stream=None, use_torch_allocator: bool = True, hub_degree: int = 0,
                  gather_mode: int = 0, vlc: bool = False):
         self.graph = graph
-        self.colors = torch.as_tensor(np.asarray(colors) if not torch.is_tensor(colors) else colors,
-                                      dtype=torch.uint8).to(graph.row_ptr.device).contiguous()
         self.k = k
         self._stream = stream
-        csr = _Csr(graph.n, graph.nnz, graph.row_ptr.data_ptr(), graph.col_idx.data_ptr())
+        if isinstance(graph, DeviceGraph):
+            self.device = graph.row_ptr.device
+            self.colors = torch.as_tensor(np.asarray(colors) if not torch.is_tensor(colors) else colors,
+                                          dtype=torch.uint8).to(self.device).contiguous()
+            csr = _Csr(graph.n, graph.nnz, graph.row_ptr.data_ptr(), graph.col_idx.data_ptr(), 1)
+            cptr = _ptr(self.colors)
+        else:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+            rp = np.ascontiguousarray(graph.row_ptr, dtype=np.int64)
+            ci = np.ascontiguousarray(graph.col_idx, dtype=np.int32)
+            self.colors = np.ascontiguousarray(colors.cpu().numpy() if torch.is_tensor(colors) else colors,
+                                               dtype=np.uint8)
+            csr = _Csr(int(rp.size - 1), int(ci.size), rp.ctypes.data, ci.ctypes.data, 0)
+            cptr = C.c_void_p(self.colors.ctypes.data)
         opts = _BuildOpts(rooting, max_bits, _stream_ptr(stream),
                           C.pointer(TORCH_ALLOCATOR) if use_torch_allocator else None, hub_degree,
-                          1 if validate else 0, gather_mode, 1 if vlc else 0)
+                          0 if validate else 1, gather_mode, 1 if vlc else 0)
         self._h = _P()
-        _check(_lib.scc_build_table(C.byref(csr), _ptr(self.colors), k, C.byref(opts), C.byref(self._h)))
+        _check(_lib.scc_build_table(C.byref(csr), cptr, k, C.byref(opts), C.byref(self._h)))
 
     @classmethod
     def _wrap(cls, handle, graph, colors, k):
         t = cls.__new__(cls)
         t.graph, t.colors, t.k, t._stream, t._h = graph, colors, k, None, _P(handle)
+        t.device = graph.row_ptr.device
         return t
 
     def close(self):
@@ -277,8 +296,8 @@ class Table:
         """(off int64[n+1], key uint16 as int32[nnz], lo uint64[nnz], hi uint64[nnz]) as numpy arrays."""
         nnz = _i64()
         _check(_lib.scc_export_level(self._h, h, C.byref(nnz), None, None, None, None, None))
-        dev = self.graph.row_ptr.device
-        off = torch.empty(self.graph.n + 1, dtype=torch.int64, device=dev)
+        dev = self.device
+        off = torch.empty(self.info().n + 1, dtype=torch.int64, device=dev)
         key = torch.empty(max(nnz.value, 1), dtype=torch.int16, device=dev)
         lo = torch.empty(max(nnz.value, 1), dtype=torch.int64, device=dev)
         hi = torch.empty(max(nnz.value, 1), dtype=torch.int64, device=dev)
@@ -291,7 +310,7 @@ class Table:
     def sample(self, n: int, seed: int, stream_id: int = 0, shape: int = -1, first_index: int = 0, stream=None,
                out=None):
         """(verts int32[n, k], parent int8[n, k]) device tensors."""
-        dev = self.graph.row_ptr.device
+        dev = self.device
         if out is None:
             verts = torch.empty((max(n, 1), self.k), dtype=torch.int32, device=dev)
             par = torch.empty((max(n, 1), self.k), dtype=torch.int8, device=dev)
@@ -329,7 +348,8 @@ class Table:
 
 
 def build_batch(instances, rooting: int = ROOT_ZERO, max_bits: int = 128, tile: int = 0, hub_degree: int = 0,
-                autotune: bool = False, stream=None, use_torch_allocator: bool = True, waves: int = 0):
+                autotune: bool = False, stream=None, use_torch_allocator: bool = True, waves: int = 0,
+                validate: bool = True):
     """``scc_build_batch``: instances is a list of (DeviceGraph, colours, k).
     Returns ([Table], report dict)."""
     n = len(instances)
@@ -339,9 +359,9 @@ def build_batch(instances, rooting: int = ROOT_ZERO, max_bits: int = 128, tile: 
         col = torch.as_tensor(np.asarray(colors) if not torch.is_tensor(colors) else colors,
                               dtype=torch.uint8).to(g.row_ptr.device).contiguous()
         keep.append(col)
-        arr[i] = _Instance(_Csr(g.n, g.nnz, g.row_ptr.data_ptr(), g.col_idx.data_ptr()), col.data_ptr(), k)
+        arr[i] = _Instance(_Csr(g.n, g.nnz, g.row_ptr.data_ptr(), g.col_idx.data_ptr(), 1), col.data_ptr(), k)
     opts = _BuildOpts(rooting, max_bits, _stream_ptr(stream),
-                      C.pointer(TORCH_ALLOCATOR) if use_torch_allocator else None, 0, 0)
+                      C.pointer(TORCH_ALLOCATOR) if use_torch_allocator else None, 0, 0 if validate else 1)
     bo = _BatchOpts(tile, hub_degree, 1 if autotune else 0, waves)
     outs = (_P * n)()
     rep = BatchReport()

@@ -529,12 +529,20 @@ void AgsState::add_round(int64_t n, const unsigned long long *hh)
         class_sigma_rows(k, fresh, rows);
         for (size_t q = 0; q < fresh.size(); q++) sig[fresh[q]] = rows[q];
     }
-    bool newcov = false;
-    for (int i = 0; i < S; i++)
-        if (!cov[i] && c[i] >= cbar) { cov[i] = 1; ncov++; newcov = true; }
-    if (!newcov || ncov >= S) return;
+    // Algorithm AGS tests the class each sample falls in: once its count has
+    // reached cbar it is (or stays) covered and the shape is chosen again. A
+    // round makes that test for every class it hit.
+    bool reselect = false;
+    for (int i = 0; i < S; i++) {
+        if (!hh[i] || c[i] < cbar) continue;
+        reselect = true;
+        if (!cov[i]) { cov[i] = 1; ncov++; }
+    }
+    if (!reselect || ncov >= S) return;
     // w_i = sum_j n_j sigma_ij / t_j over covered classes, then the shape that
-    // minimises (1/t_j) sum_{i covered} sigma_ij c_i / w_i (ties: smaller j)
+    // minimises (1/t_j) sum_{i covered} sigma_ij c_i / w_i; a score within a
+    // relative 2^-40 of the best so far is a tie, and ties go to the smaller j
+    // (exactly equal rationals are not split by rounding)
     for (int i = 0; i < S; i++) {
         if (!cov[i]) continue;
         double acc = 0.0;
@@ -550,7 +558,7 @@ void AgsState::add_round(int64_t n, const unsigned long long *hh)
         for (int i = 0; i < S; i++)
             if (cov[i]) acc += (double)sig[i][q] * (double)c[i] / w[i];
         acc /= tjd[q];
-        if (best < 0 || acc < bv) { best = q; bv = acc; }
+        if (best < 0 || acc < bv * (1.0 - 0x1p-40)) { best = q; bv = acc; }
     }
     j = best;
 }

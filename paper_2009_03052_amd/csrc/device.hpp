@@ -37,7 +37,7 @@ __host__ __device__ inline uint64_t make_loc(uint64_t off, uint32_t len, uint32_
     return len ? (off | ((uint64_t)len << 40) | ((uint64_t)wide << 52)) : 0ull;
 }
 
-// Variable-length records (Sec. 3.5, "Variable-length counts"): after the
+// Variable-length records (Sec. 3.3, "Variable-length counts"): after the
 // level sum N, one u16 per entry holding the key (11 bits) and the count's
 // length in bytes (5 bits), ceil(len/4) words; then the byte offset of every
 // 32nd entry's count (u16 each, ceil(ceil(len/32)/4) words); then the counts,

@@ -28,27 +28,52 @@ namespace {
 // ---------------------------------------------------------------------------
 // CSR and colour validation (Sec. 1.3: simple undirected graph)
 // ---------------------------------------------------------------------------
-__global__ void k_validate(GraphView g, int k, int *err)
+// Pass 1 reads row_ptr only: 0 = row_ptr[0] <= row_ptr[1] <= ... <= row_ptr[n]
+// = nnz. Pass 2 runs only when pass 1 found nothing, so its col_idx reads stay
+// inside [0, nnz) and its row_ptr reads inside [0, n].
+__global__ void k_validate_rows(const int64_t *row_ptr, int64_t n, int64_t nnz, int *err)
 {
-    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= g.n) return;
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v > n) return;
+    const int64_t a = row_ptr[v];
     int bad = 0;
-    if (g.colors[v] >= k) bad |= 1;
-    int64_t a = g.row_ptr[v], b = g.row_ptr[v + 1];
-    if (b < a) bad |= 2;
-    for (int64_t e = a; e < b && !(bad & 2); e++) {
-        int32_t u = g.col_idx[e];
-        if (u < 0 || u >= g.n || u == v) { bad |= 4; break; }
-        if (e > a && g.col_idx[e - 1] >= u) { bad |= 8; break; }
-        int64_t lo = g.row_ptr[u], hi = g.row_ptr[u + 1];
-        int found = 0;
+    if (a < 0 || a > nnz) bad |= 2;
+    if (v == 0 && a != 0) bad |= 2;
+    if (v == n && a != nnz) bad |= 32;
+    if (v < n && row_ptr[v + 1] < a) bad |= 2;
+    if (bad) atomicOr(err, bad);
+}
+
+// Pass 2, one thread per vertex (its colour) and per CSR entry e: the row v
+// holding e, then u = col_idx[e] in range and not v, the row strictly
+// increasing at e, and v present in the row of u (symmetry).
+__global__ void k_validate_edges(GraphView g, int64_t nnz, int k, int *err)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int bad = 0;
+    if (i < g.n && g.colors[i] >= k) bad |= 1;
+    if (i < nnz) {
+        int64_t lo = 0, hi = g.n - 1;        // the last v with row_ptr[v] <= i
         while (lo < hi) {
-            int64_t mid = (lo + hi) >> 1;
-            int32_t w = g.col_idx[mid];
-            if (w == v) { found = 1; break; }
-            if (w < v) lo = mid + 1; else hi = mid;
+            const int64_t mid = (lo + hi + 1) >> 1;
+            if (g.row_ptr[mid] <= i) lo = mid; else hi = mid - 1;
         }
-        if (!found) { bad |= 16; break; }
+        const int64_t v = lo;
+        const int32_t u = g.col_idx[i];
+        if (u < 0 || u >= g.n || u == v) {
+            bad |= 4;
+        } else {
+            if (i > g.row_ptr[v] && g.col_idx[i - 1] >= u) bad |= 8;
+            int64_t a = g.row_ptr[u], b = g.row_ptr[u + 1];
+            bool found = false;
+            while (a < b) {
+                const int64_t mid = (a + b) >> 1;
+                const int32_t w = g.col_idx[mid];
+                if (w == v) { found = true; break; }
+                if (w < v) a = mid + 1; else b = mid;
+            }
+            if (!found) bad |= 16;
+        }
     }
     if (bad) atomicOr(err, bad);
 }
@@ -1381,7 +1406,7 @@ __global__ void __launch_bounds__(256) k_reduce_parts(const u128 *part, int nb, 
 }
 
 // ---------------------------------------------------------------------------
-// Variable-length counts (Sec. 3.5): re-encoding of a finished level. Pass 1
+// Variable-length counts (Sec. 3.3): re-encoding of a finished level. Pass 1
 // sizes every record in the new layout, a scan places them, pass 2 writes
 // them: per chunk of 64 entries a wave scan of the byte lengths gives each
 // count's offset.
@@ -1437,7 +1462,7 @@ __global__ void __launch_bounds__(WAVE) k_vlc_write(int64_t n, LevelView L, cons
     }
 }
 
-// Round skipping (Sec. 3.5): the uncoloured k-stars centred at v, binom(d_v, k-1),
+// Round skipping (Sec. 3.3): the uncoloured k-stars centred at v, binom(d_v, k-1),
 // by the exact recurrence c_i = c_{i-1} (d - r + i) / i; flags a product that
 // does not fit 128 bits
 __global__ void k_star_weight(GraphView g, int r, u128 *w, unsigned long long *flag)
@@ -1731,7 +1756,7 @@ static scc_status build_levels(scc_table *T)
     hipStream_t st = T->stream;
     GraphView g{n, T->row_ptr, T->col_idx, T->colors};
     const bool zero = T->rooting == SCC_ROOT_ZERO;
-    // round skipping (Sec. 3.5): level k-1 is not built, and of the neighbour sums
+    // round skipping (Sec. 3.3): level k-1 is not built, and of the neighbour sums
     // above level k-3 only those the designated decompositions use (|T''| = hs)
     const bool bal = T->rooting == SCC_ROOT_BALANCED;
     bool s_need[SCC_KMAX + 1];
@@ -2195,7 +2220,7 @@ static scc_status build_totals(scc_table *T)
     return s ? s : totals_finish(T);
 }
 
-// Re-encodes every stored level with variable-length counts (Sec. 3.5). The
+// Re-encodes every stored level with variable-length counts (Sec. 3.3). The
 // sampler's running sums are prepared first, from the fixed layout; every
 // reader after this point goes through the layout-aware record view.
 static scc_status compact_levels(scc_table *T)
@@ -2269,16 +2294,71 @@ static scc_status make_key_maps(scc_table *T)
     return SCC_OK;
 }
 
+static scc_table *new_table(const scc_csr *g, const uint8_t *colors, int k, const scc_build_opts &o);
+
+// The table's graph on the device: a host graph (on_device = 0) and its
+// colours are copied into memory the table owns; device pointers are borrowed.
+static scc_status attach_graph(scc_table *T, const scc_csr *g, const uint8_t *colors)
+{
+    if (g->on_device) return SCC_OK;
+    const int64_t n = g->n, nnz = g->nnz;
+    int64_t *rp = (int64_t *)T->alloc((size_t)(n + 1) * 8);
+    int32_t *ci = (int32_t *)T->alloc((size_t)std::max<int64_t>(nnz, 1) * 4);
+    uint8_t *cl = (uint8_t *)T->alloc((size_t)std::max<int64_t>(n, 1));
+    if (!rp || !ci || !cl) return set_error(SCC_ENOMEM, "graph copy");
+    HIP_TRY(hipMemcpyAsync(rp, g->row_ptr, (size_t)(n + 1) * 8, hipMemcpyHostToDevice, T->stream));
+    if (nnz > 0) HIP_TRY(hipMemcpyAsync(ci, g->col_idx, (size_t)nnz * 4, hipMemcpyHostToDevice, T->stream));
+    if (n > 0) HIP_TRY(hipMemcpyAsync(cl, colors, (size_t)n, hipMemcpyHostToDevice, T->stream));
+    // the caller may free or change its host arrays once the call returns
+    HIP_TRY(hipStreamSynchronize(T->stream));
+    T->row_ptr = rp; T->col_idx = ci; T->colors = cl;
+    return SCC_OK;
+}
+
+// Checks the table's CSR and colours on the device (Sec. 1.3: a simple
+// undirected graph; Sec. 2: colours in [0, k)): EINVAL on any violation.
+static scc_status validate_graph(scc_table *T)
+{
+    const int64_t n = T->n, nnz = T->nnz_g;
+    if (n == 0) return nnz == 0 ? SCC_OK : set_error(SCC_EINVAL, "invalid input (an empty graph with nnz = %lld)", (long long)nnz);
+    int *err = (int *)T->mem.get(16);
+    if (!err) return set_error(SCC_ENOMEM, "validate");
+    int herr = 0;
+    hipError_t e = hipMemsetAsync(err, 0, 4, T->stream);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_validate_rows, dim3((unsigned)((n + 1 + 255) / 256)), dim3(256), 0, T->stream, T->row_ptr, n,
+                           nnz, err);
+        e = hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, T->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(T->stream);
+    }
+    if (e == hipSuccess && herr == 0) {
+        GraphView gv{n, T->row_ptr, T->col_idx, T->colors};
+        const int64_t m = std::max(n, nnz);
+        hipLaunchKernelGGL(k_validate_edges, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, T->stream, gv, nnz, T->k, err);
+        e = hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, T->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(T->stream);
+    }
+    T->mem.put(err);
+    if (e != hipSuccess) return set_error(SCC_EDEVICE, "validate: %s", hipGetErrorString(e));
+    if (herr)
+        return set_error(SCC_EINVAL, "invalid input (%s%s%s%s%s%s)", herr & 1 ? "colour >= k " : "",
+                         herr & 2 ? "row_ptr not increasing from 0 within [0, nnz] " : "",
+                         herr & 4 ? "neighbour out of range or self-loop " : "",
+                         herr & 8 ? "row not strictly increasing " : "", herr & 16 ? "asymmetric edge " : "",
+                         herr & 32 ? "row_ptr[n] != nnz" : "");
+    return SCC_OK;
+}
+
 extern "C" scc_status scc_build_table(const scc_csr *g, const uint8_t *colors, int k,
                                       const scc_build_opts *opt, scc_table **out)
 {
     if (!out) return set_error(SCC_EINVAL, "out is NULL");
     *out = nullptr;
-    if (!g || !colors) return set_error(SCC_EINVAL, "graph or colours NULL");
+    if (!g || (g->n > 0 && !colors)) return set_error(SCC_EINVAL, "graph or colours NULL");
     if (k < 2 || k > SCC_KMAX) return set_error(SCC_EINVAL, "k = %d not in [2, 8]", k);
     if (g->n < 0 || g->n >= ((int64_t)1 << 31)) return set_error(SCC_EINVAL, "n out of range");
-    if (g->nnz < 0 || (g->n > 0 && (!g->row_ptr || (g->nnz > 0 && !g->col_idx))))
-        return set_error(SCC_EINVAL, "bad CSR pointers");
+    if (g->nnz < 0 || g->nnz >= ((int64_t)1 << 40) || !g->row_ptr || (g->nnz > 0 && !g->col_idx))
+        return set_error(SCC_EINVAL, "bad CSR pointers or size");
     scc_build_opts o{};
     if (opt) o = *opt;
     if (o.rooting != SCC_ROOT_ZERO && o.rooting != SCC_ROOT_ALL && o.rooting != SCC_ROOT_BALANCED)
@@ -2286,47 +2366,13 @@ extern "C" scc_status scc_build_table(const scc_csr *g, const uint8_t *colors, i
     if (o.rooting == SCC_ROOT_BALANCED && k < 4) return set_error(SCC_EINVAL, "round skipping needs k >= 4 (k = %d)", k);
     if (o.max_bits == 0) o.max_bits = 128;
     if (o.max_bits != 64 && o.max_bits != 128) return set_error(SCC_EINVAL, "max_bits must be 64 or 128");
-
-    scc_table *T = new scc_table();
-    T->k = k; T->rooting = o.rooting; T->max_bits = o.max_bits;
-    T->n = g->n; T->nnz_g = g->nnz;
-    T->row_ptr = g->row_ptr; T->col_idx = g->col_idx; T->colors = colors;
-    T->stream = (hipStream_t)o.stream;
-    T->mem.alloc = o.alloc; T->mem.stream = T->stream;
-    T->hub_degree = o.hub_degree > 0 ? o.hub_degree : 1024;
-    T->hub_chunk = 256;
-    if (o.gather_mode < SCC_GATHER_AUTO || o.gather_mode > SCC_GATHER_ROW) {
-        delete T;
+    if (o.gather_mode < SCC_GATHER_AUTO || o.gather_mode > SCC_GATHER_ROW)
         return set_error(SCC_EINVAL, "bad gather_mode %d", o.gather_mode);
-    }
-    T->gather_mode = o.gather_mode;
-    build_lut(k, &T->hlut);
 
-    scc_status s = SCC_OK;
-    if (o.validate && g->n > 0) {
-        int *err = (int *)T->mem.get(16);
-        if (!err) { delete T; return set_error(SCC_ENOMEM, "validate"); }
-        GraphView gv{g->n, g->row_ptr, g->col_idx, colors};
-        int herr = 0;
-        hipError_t e = hipMemsetAsync(err, 0, 4, T->stream);
-        if (e == hipSuccess) {
-            int64_t rp_last = 0;
-            e = hipMemcpyAsync(&rp_last, g->row_ptr + g->n, 8, hipMemcpyDeviceToHost, T->stream);
-            hipLaunchKernelGGL(k_validate, dim3((unsigned)((g->n + 255) / 256)), dim3(256), 0, T->stream, gv, k, err);
-            if (e == hipSuccess) e = hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, T->stream);
-            if (e == hipSuccess) e = hipStreamSynchronize(T->stream);
-            if (e == hipSuccess && rp_last != g->nnz) herr |= 32;
-        }
-        T->mem.put(err);
-        if (e != hipSuccess) { delete T; return set_error(SCC_EDEVICE, "validate: %s", hipGetErrorString(e)); }
-        if (herr) {
-            delete T;
-            return set_error(SCC_EINVAL, "invalid input (%s%s%s%s%s%s)", herr & 1 ? "colour >= k " : "",
-                             herr & 2 ? "row_ptr decreasing " : "", herr & 4 ? "neighbour out of range or self-loop " : "",
-                             herr & 8 ? "row not strictly increasing " : "", herr & 16 ? "asymmetric edge " : "",
-                             herr & 32 ? "row_ptr[n] != nnz" : "");
-        }
-    }
+    scc_table *T = new_table(g, colors, k, o);
+    T->gather_mode = o.gather_mode;
+    scc_status s = attach_graph(T, g, colors);
+    if (!s && !o.no_validate) s = validate_graph(T);
     if (!s) s = make_key_maps(T);
     if (!s) s = build_levels(T);
     if (!s) s = build_totals(T);
@@ -2871,11 +2917,16 @@ extern "C" scc_status scc_build_batch(const scc_instance *inst, int n_inst, cons
     for (int i = 0; i < n_inst; i++) {
         const scc_instance &I = inst[i];
         if (I.k < 2 || I.k > SCC_KMAX) return fail(set_error(SCC_EINVAL, "instance %d: k = %d not in [2, 8]", i, I.k));
-        if (I.g.n < 0 || I.g.n >= ((int64_t)1 << 31) || (I.g.n > 0 && !I.g.row_ptr) || !I.colors)
+        if (I.g.n < 0 || I.g.n >= ((int64_t)1 << 31) || !I.g.row_ptr || (I.g.n > 0 && !I.colors))
+            return fail(set_error(SCC_EINVAL, "instance %d: bad graph", i));
+        if (I.g.nnz < 0 || I.g.nnz >= ((int64_t)1 << 40) || (I.g.nnz > 0 && !I.g.col_idx))
             return fail(set_error(SCC_EINVAL, "instance %d: bad graph", i));
         scc_table *T = new_table(&I.g, I.colors, I.k, o);
         H[i].T = T;
-        scc_status s = make_key_maps(T);
+        scc_status s = attach_graph(T, &I.g, I.colors);
+        if (!s && !o.no_validate) s = validate_graph(T);
+        if (s) return fail(s);
+        s = make_key_maps(T);
         if (s) return fail(s);
         const DevLut &HL = T->hlut;
         const int64_t n = T->n;

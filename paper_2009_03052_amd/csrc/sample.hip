@@ -123,7 +123,7 @@ struct SampleLds {
     u128 st_cnt[2 * SCC_KMAX];
 };
 
-// An uncoloured k-star (round skipping, Sec. 3.5): the centre v by its running
+// An uncoloured k-star (round skipping, Sec. 3.3): the centre v by its running
 // sum of binom(d_v, k-1) (draw 0), then the i-th leaf at position r uniform
 // below d_v - i (draw 1 + i) among the neighbours not taken yet, where a taken
 // position is refilled by the last remaining one. Every lane makes the same

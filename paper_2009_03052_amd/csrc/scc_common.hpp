@@ -38,7 +38,7 @@ struct DevLut {
     uint8_t dec_b[SCC_KMAX + 1][SCC_MAXSH];    // rank of T''
     uint8_t dec_beta[SCC_KMAX + 1][SCC_MAXSH]; // beta_T
     uint8_t unr_of[SCC_MAXSH];                 // unrooted id of each rooted k-shape
-    // Round skipping (Sec. 3.5): the designated rooting of each unrooted k-shape
+    // Round skipping (Sec. 3.3): the designated rooting of each unrooted k-shape
     // is its smallest rooted rank whose canonical decomposition splits it into
     // two trees of 2..k-2 nodes (-1: the star, which has none; every shape for
     // k < 4); its orbit is the number of nodes of a copy that give that rooting.

@@ -142,7 +142,7 @@ struct scc_server {
     std::unordered_map<int64_t, Request> reqs;
     std::vector<int64_t> active;
     size_t rr = 0;
-    std::vector<Session> sessions;
+    std::deque<Session> sessions;     // a deque: opening a session moves no other
     int64_t next_id = 1;
     bool stop = false;
     int fatal = SCC_OK;
@@ -294,34 +294,48 @@ scc_status scc_server::launch_step(int b)
 }
 
 // rows of step b are done: finish requests whose rows are all done; an AGS
-// round reads its class histogram and advances its session
+// round reads its class histogram and advances its session first, and only
+// then is marked finished (a finished request may be released by a caller)
 void scc_server::complete_step_locked(int b, std::unique_lock<std::mutex> &lk)
 {
     StepBuf &B = sb[b];
     const double t = now_s(t0);
     const int err = *B.herr;
+    auto finish = [&](Request &r) {
+        r.finished = true;
+        r.t_done = t;
+        n_completed++;
+        samples_done += r.q.n;
+        last_done = t;
+        lat.push_back(r.t_done - r.t_submit);
+    };
+    std::vector<int64_t> rounds;
     for (int c = 0; c < B.nch; c++) {
         Request &r = reqs[B.req[c]];
         r.done += B.hch[c].count;
         if (err) r.status = SCC_EDEVICE;
         if (r.done < r.q.n) continue;
-        r.finished = true;
-        r.t_done = t;
         active.erase(std::find(active.begin(), active.end(), r.id));
-        if (r.q.kind == SCC_REQ_AGS_ROUND) {
-            Session &s = sessions[r.q.session];
-            lk.unlock();
-            hipError_t e = hipMemcpyAsync(s.hh.data(), s.dhist, (size_t)s.st.S * 8, hipMemcpyDeviceToHost, side);
-            if (e == hipSuccess) e = hipStreamSynchronize(side);
-            lk.lock();
-            if (e != hipSuccess) r.status = SCC_EDEVICE;
-            else s.st.add_round(r.q.n, s.hh.data());
-            s.busy = false;
-        }
-        n_completed++;
-        samples_done += r.q.n;
-        last_done = t;
-        lat.push_back(r.t_done - r.t_submit);
+        if (r.q.kind == SCC_REQ_AGS_ROUND) rounds.push_back(r.id);
+        else finish(r);
+    }
+    for (int64_t id : rounds) {
+        // the histogram copy runs without the lock: the request is not finished
+        // yet, so no caller can release it, and sessions live in a deque, whose
+        // elements keep their addresses when sessions are opened meanwhile
+        Session &s = sessions[reqs.at(id).q.session];
+        unsigned long long *dst = s.hh.data();
+        const unsigned long long *src = s.dhist;
+        const size_t bytes = (size_t)s.st.S * 8;
+        lk.unlock();
+        hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, side);
+        if (e == hipSuccess) e = hipStreamSynchronize(side);
+        lk.lock();
+        Request &r = reqs.at(id);
+        if (e != hipSuccess) r.status = SCC_EDEVICE;
+        else if (r.status == SCC_OK) s.st.add_round(r.q.n, s.hh.data());
+        s.busy = false;
+        finish(r);
     }
     steps++;
     cv_done.notify_all();

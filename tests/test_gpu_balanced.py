@@ -1,4 +1,4 @@
-"""Round skipping (Sec. 3.5, balanced decomposition) on the GPU vs the oracle, bit for bit.
+"""Round skipping (Sec. 3.3, balanced decomposition) on the GPU vs the oracle, bit for bit.
 
 * Tables built with the balanced rooting: every level (level k-1 empty, level
   k holding only the designated rootings, at every vertex), t, the

@@ -10,6 +10,7 @@ paths, and the full mid-size workload (Chung-Lu n=1e6, m=1e7, k=6).
 from __future__ import annotations
 
 import numpy as np
+import torch
 import pytest
 
 import graphgen as gg
@@ -164,6 +165,63 @@ def test_invalid_inputs():
     assert e.value.status == S.EINVAL
 
 
+def test_invalid_inputs_rejected_by_default():
+    # validation is the default (no flag): malformed CSRs and colours give EINVAL
+    # before any kernel reads col_idx through them; rows whose bounds leave
+    # [0, nnz] are caught by the first pass, which reads row_ptr only
+    S = scc()
+    g = gg.erdos_renyi(30, 60, seed=3)
+    colors = gg.colors(30, 5, seed=4)
+    cases = {}
+    c = colors.copy(); c[7] = 5
+    cases["colour >= k"] = (g.row_ptr, g.col_idx, c)
+    rp = g.row_ptr.copy(); rp[10] = rp[-1] + 1000          # row bounds past nnz
+    cases["row_ptr past nnz"] = (rp, g.col_idx, colors)
+    rp = g.row_ptr.copy(); rp[5] = -3
+    cases["negative row_ptr"] = (rp, g.col_idx, colors)
+    rp = g.row_ptr.copy(); rp[0] = 1
+    cases["row_ptr[0] != 0"] = (rp, g.col_idx, colors)
+    rp = g.row_ptr.copy(); rp[-1] -= 1
+    cases["row_ptr[n] != nnz"] = (rp, g.col_idx, colors)
+    ci = g.col_idx.copy(); ci[3] = 30
+    cases["neighbour out of range"] = (g.row_ptr, ci, colors)
+    ci = g.col_idx.copy(); v = 2; ci[g.row_ptr[v]] = v
+    cases["self-loop"] = (g.row_ptr, ci, colors)
+    v = int(np.argmax(np.diff(g.row_ptr) >= 2))
+    ci = g.col_idx.copy(); a = g.row_ptr[v]; ci[a], ci[a + 1] = ci[a + 1], ci[a]
+    cases["unsorted row"] = (g.row_ptr, ci, colors)
+    for name, (rp, ci, col) in cases.items():
+        print("invalid case:", name, flush=True)
+        with pytest.raises(S.SccError) as e:
+            S.Table(S.DeviceGraph(rp, ci), col, 5)
+        assert e.value.status == S.EINVAL, name
+        # the host-graph form is checked the same way
+        host = type("HostGraph", (), {"row_ptr": rp, "col_idx": ci})()
+        with pytest.raises(S.SccError) as e:
+            S.Table(host, col, 5)
+        assert e.value.status == S.EINVAL, name
+    # an empty graph is valid
+    empty = S.Table(S.DeviceGraph(np.zeros(1, np.int64), np.zeros(0, np.int32)), np.zeros(0, np.uint8), 4)
+    assert empty.totals()[0] == 0
+
+
+def test_host_graph_equals_device_graph():
+    # on_device = 0: the library copies the host CSR and colours; the table is
+    # the device-graph table and the oracle's, bit for bit, and sampling and
+    # classification read the table's own copies
+    S = scc()
+    g = gg.chung_lu(3000, 12000, 2.2, 150, seed=41)
+    k = 6
+    colors = gg.colors(g.n, k, seed=42)
+    host = S.Table(g, colors.copy(), k)
+    dev, ot = build_pair(g, colors, k)
+    assert_tables_equal(host, ot, k, "host graph")
+    hv, hp = host.sample(500, seed=5)
+    dv, dp = dev.sample(500, seed=5)
+    assert torch.equal(hv, dv) and torch.equal(hp, dp)
+    assert torch.equal(host.classify(hv)[1], dev.classify(dv)[1])
+
+
 def test_occ_queries_match():
     g = gg.chung_lu(2000, 8000, 2.2, 200, seed=21)
     k = 6
@@ -189,3 +247,33 @@ def test_mid_workload_full_table():
     assert_tables_equal(gt, ot, 6, "mid")
     from gpu_util import assert_samples_equal
     assert_samples_equal(gt, ot, 300, seed=22, label="mid samples")
+
+
+@pytest.mark.timeout(900)
+def test_k8_counts_beyond_64_bits():
+    # k = 8 with 128-bit counts, entry by entry: two hubs of 2^15 leaves (shared
+    # in part, the leaves linked into a path) carry counts above 2^64 from level
+    # 7 on and 128-bit bounds from level 6; 48 rows of 150 neighbours hold both
+    # hubs last, so their neighbour-sum bounds reach 2^64 only in their third
+    # 64-neighbour chunk (the 64-bit gather pass stops there and the row is
+    # redone in 128 bits). Every level, t, t_j and 2000 samples, with grouped
+    # rows and with one row per wave.
+    S = scc()
+    g = gg.two_hubs()
+    k = 8
+    colors = gg.colors(g.n, k, seed=77)
+    ot = O.Table(g, colors, k)
+    print("two hubs: oracle table built", flush=True)
+    ov, op = ot.sample(2000, seed=3)
+    print("two hubs: oracle samples drawn", flush=True)
+    dg = S.DeviceGraph.from_graph(g)
+    for mode in (S.GATHER_GROUPED, S.GATHER_ROW):
+        gt = S.Table(dg, colors, k, gather_mode=mode)
+        info = gt.info()
+        for h in (6, 7, 8):
+            assert info.wide_vertices[h] > 0, (mode, h, list(info.wide_vertices))
+        assert gt.totals()[0] >= 1 << 64
+        assert_tables_equal(gt, ot, k, f"two hubs mode {mode}")
+        gv, gp = gt.sample(2000, seed=3)
+        assert np.array_equal(gv.cpu().numpy(), ov) and np.array_equal(gp.cpu().numpy(), op), mode
+        print(f"two hubs: mode {mode} equal", flush=True)

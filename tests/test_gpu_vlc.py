@@ -1,4 +1,4 @@
-"""Variable-length counts (Sec. 3.5) on the GPU: a table re-encoded after the
+"""Variable-length counts (Sec. 3.3) on the GPU: a table re-encoded after the
 build answers every query exactly as the fixed-layout table and the oracle.
 
 * Every level (offsets, keys, both count words), t and t_j equal the oracle's

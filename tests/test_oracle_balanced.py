@@ -1,5 +1,5 @@
 """Pins of the oracle's round-skipping mode (balanced treelet decomposition and
-direct star sampling, Sec. 3.5) against what the paper and mathematics fix.
+direct star sampling, Sec. 3.3) against what the paper and mathematics fix.
 
 * The lemma of the section: every unrooted k-treelet except the star has a
   rooting whose canonical decomposition is balanced (both parts of at least 2
