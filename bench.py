@@ -1,14 +1,19 @@
-"""Benchmark: the whole hot path on the mid workload, on one MI355X.
+"""Benchmark: the whole hot path on one MI355X.
 
-One step = table build (Eq. (1) DP, all levels, totals) + 10^6 uniform
-colourful 6-treelet samples + their classification, on a Chung-Lu graph with
-n = 10^6, m = 10^7, exponent 2.1, maximum expected degree 5e4 (seeded), k = 6,
-zero-rooting. The graph and colours are resident in HBM before timing starts.
+Default workload (large): one step = table build (Eq. (1) DP, all levels,
+totals) + 10^7 uniform colourful 8-treelet samples + their classification, on a
+Chung-Lu graph with n = 4*10^6, m = 6*10^7, exponent 2.3, maximum expected
+degree 2*10^5 (seeded), k = 8, zero-rooting, counts 64- or 128-bit by the
+per-vertex bound. The graph and colours are resident in HBM before timing
+starts. `--workload mid` runs the same step at k = 6 on the mid graph;
+`batching` and `serving` run the project's batched build and request server.
 
 Prints one JSON line. `value` is classified samples per second of whole steps
-(build included). The dominant kernel is the neighbour-record gather of the DP
-(HBM-bound); its roofline entry divides the algorithmic bytes of the gather
-launches by their duration measured with HIP events on the build's stream.
+(build included). The roofline entry is the DP join (neighbour-sum gather,
+combine with compaction and packing, level-k totals): the algorithmic bytes of
+its launches divided by their duration, measured with HIP events on the
+build's stream; `roofline_parts` splits it into the gather and the combine and
+adds the sampler.
 """
 from __future__ import annotations
 
@@ -35,8 +40,8 @@ def parse():
                    help="leave out the extra round-skipping, biased-colouring and variable-length builds "
                         "(counter runs: only the plain step's kernels)")
     p.add_argument("--small", action="store_true", help="small graph (for quick checks)")
-    p.add_argument("--workload", default="mid", choices=["mid", "large", "batching", "serving"],
-                   help="mid (default) / large: the plain method on the mid / large graph; batching: 48 "
+    p.add_argument("--workload", default="large", choices=["mid", "large", "batching", "serving"],
+                   help="large (default) / mid: the plain method on the large / mid graph; batching: 48 "
                         "instances, plain vs one "
                         "batched launch; serving: three resident k=7 tables under a Poisson request mix, continuous "
                         "batching vs first-in first-out")
@@ -52,58 +57,132 @@ def parse():
 
 PLAIN = {
     "mid": dict(n=1_000_000, m=10_000_000, gamma=2.1, wmax=5e4, gseed=2, k=6, cseed=12, samples=1_000_000,
-                sseed=22, oracle_scale=8, traffic="gather_mid_k6_hbm_traffic.txt", biased_lambda=0.02,
+                sseed=22, oracle_full=True, traffic="dp_mid_k6_hbm_traffic.txt", biased_lambda=0.02,
                 label="mid: Chung-Lu n=1e6 m=1e7 exponent 2.1 w_max=5e4, k=6, zero-rooting"),
     "large": dict(n=4_000_000, m=60_000_000, gamma=2.3, wmax=2e5, gseed=3, k=8, cseed=13, samples=10_000_000,
-                  sseed=23, oracle_scale=64, traffic="gather_large_k8_hbm_traffic.txt", biased_lambda=0.01,
+                  sseed=23, oracle_scales=(256, 128), traffic="dp_large_k8_hbm_traffic.txt", biased_lambda=0.01,
                   label="large: Chung-Lu n=4e6 m=6e7 exponent 2.3 w_max=2e5, k=8, zero-rooting",
                   ags=dict(cbar=1000, round_size=100_000, budget=20_000_000, seed=33)),
 }
 
+ORACLE_SAMPLES = 200       # samples drawn (and classified) per timed oracle run
+ORACLE_WORKERS_MAX = 16    # forked sampling workers of the all-core figure
+
+
+def _oracle_rates(tab, g, k, sseed, workers):
+    """Seconds per sample (draw + classification) of the oracle on one core, and
+    with `workers` forked processes drawing disjoint index ranges of the same
+    stream from the (inherited) table."""
+    import multiprocessing as mp
+
+    import oracle as O
+    O.classify(g, k, tab.sample(1, seed=sseed)[0])          # per-k catalog, outside the timing
+    t0 = time.perf_counter()
+    v, _ = tab.sample(ORACLE_SAMPLES, seed=sseed)
+    O.classify(g, k, v)
+    one = (time.perf_counter() - t0) / ORACLE_SAMPLES
+
+    def work(i, q):
+        v, _ = tab.sample(ORACLE_SAMPLES, seed=sseed, first_index=i * ORACLE_SAMPLES)
+        O.classify(g, k, v)
+        q.put(i)
+
+    ctx = mp.get_context("fork")
+    q = ctx.Queue()
+    t0 = time.perf_counter()
+    ps = [ctx.Process(target=work, args=(i, q)) for i in range(workers)]
+    for p in ps:
+        p.start()
+    for _ in ps:
+        q.get()
+    for p in ps:
+        p.join()
+    many = (time.perf_counter() - t0) / (workers * ORACLE_SAMPLES)
+    return one, many
+
 
 def cpu_baseline(cfg, full_m, samples):
-    """The oracle, as is, on a bounded sample of the workload (single thread)."""
+    """The oracle, as is: its build (single-threaded: its DP has no parallel
+    form) and its sampler + classification on one core and on all host cores
+    (forked workers over disjoint sample indices). Runs before the GPU is
+    touched. mid: on the bench's own input. large: the full build does not
+    finish in the bench's time, so it is timed on two scaled graphs of the same
+    family and extrapolated (labelled as such)."""
     import graphgen as gg
     import oracle as O
-    scale = cfg["oracle_scale"]
-    n, m, k = cfg["n"] // scale, cfg["m"] // scale, cfg["k"]
-    g = gg.chung_lu(n, m, cfg["gamma"], cfg["wmax"] / scale, seed=cfg["gseed"])
-    colors = gg.colors(g.n, k, seed=cfg["cseed"])
-    t0 = time.perf_counter()
-    tab = O.Table(g, colors, k, O.ROOT_ZERO)
-    t_build = time.perf_counter() - t0
-    ns = 300
-    t0 = time.perf_counter()
-    v, _ = tab.sample(ns, seed=cfg["sseed"])
-    O.classify(g, k, v)
-    t_samp = (time.perf_counter() - t0) / ns
-    est_step = t_build * (full_m / g.m) + samples * t_samp
+    k = cfg["k"]
+    workers = max(1, min(os.cpu_count() or 1, ORACLE_WORKERS_MAX))
+    if cfg.get("oracle_full"):
+        g = gg.chung_lu(cfg["n"], cfg["m"], cfg["gamma"], cfg["wmax"], seed=cfg["gseed"])
+        colors = gg.colors(g.n, k, seed=cfg["cseed"])
+        t0 = time.perf_counter()
+        tab = O.Table(g, colors, k, O.ROOT_ZERO)
+        t_build = time.perf_counter() - t0
+        one, many = _oracle_rates(tab, g, k, cfg["sseed"], workers)
+        how = (f"measured on the bench's own input (Chung-Lu n={g.n}, m={g.m}, k={k}): build {t_build:.1f} s on one "
+               f"core; {ORACLE_SAMPLES} samples + classification at {one * 1e3:.2f} ms/sample on one core, "
+               f"{many * 1e3:.3f} ms/sample with {workers} forked workers (first {ORACLE_SAMPLES} indices of each "
+               f"worker's range of the bench's stream)")
+        extrapolated = False
+    else:
+        pts = []
+        for scale in cfg["oracle_scales"]:
+            n, m = cfg["n"] // scale, cfg["m"] // scale
+            g = gg.chung_lu(n, m, cfg["gamma"], cfg["wmax"] / scale, seed=cfg["gseed"])
+            colors = gg.colors(g.n, k, seed=cfg["cseed"])
+            t0 = time.perf_counter()
+            tab = O.Table(g, colors, k, O.ROOT_ZERO)
+            tb = time.perf_counter() - t0
+            one, many = _oracle_rates(tab, g, k, cfg["sseed"], workers)
+            pts.append((scale, g.m, tb, one, many))
+            del tab
+        import math
+        (s0, m0, b0, o0, y0), (s1, m1, b1, o1, y1) = pts
+        # power laws in the edge count through the two measured scales
+        eb = math.log(b1 / b0) / math.log(m1 / m0)
+        eo = math.log(o1 / o0) / math.log(m1 / m0)
+        ey = math.log(y1 / y0) / math.log(m1 / m0)
+        f = full_m / m1
+        t_build, one, many = b1 * f ** eb, o1 * f ** eo, y1 * f ** ey
+        how = (f"EXTRAPOLATED: the oracle timed on Chung-Lu graphs of the same family at 1/{s0} and 1/{s1} scale "
+               f"(m = {m0} and {m1}, w_max scaled alike, k={k}): build {b0:.2f} s and {b1:.2f} s on one core, "
+               f"{ORACLE_SAMPLES} samples + classification at {o0 * 1e3:.2f} and {o1 * 1e3:.2f} ms/sample on one "
+               f"core ({y0 * 1e3:.3f} and {y1 * 1e3:.3f} ms/sample with {workers} forked workers); each figure "
+               f"extended to m = {full_m} by the power law through its two points (exponents build {eb:.2f}, "
+               f"sample {eo:.2f}, all-core sample {ey:.2f}): build {t_build:.0f} s, {one * 1e3:.2f} ms/sample")
+        extrapolated = True
+    step1 = t_build + samples * one
+    stepn = t_build + samples * many
     return {
-        "value": samples / est_step, "unit": "samples/s", "cores": 1, "kind": "oracle",
-        "sample": (f"oracle build on a 1/{scale}-scale graph of the same family (Chung-Lu n={n}, m={g.m}, "
-                   f"exponent {cfg['gamma']}, w_max={cfg['wmax'] / scale:.0f}, k={k}) took {t_build:.2f} s, scaled "
-                   f"by edges to m={full_m}; sampling+classification {t_samp * 1e3:.2f} ms/sample measured on {ns} "
-                   f"samples of that table; value = {samples} / (scaled build + {samples} samples)"),
+        "value": samples / step1, "unit": "classified samples/s (table build + sampling + classification per step)",
+        "cores": 1, "kind": "oracle", "extrapolated": extrapolated,
+        "sample": how + f"; value = {samples} / (build + {samples} samples)",
+        "build_s": t_build, "s_per_sample": one,
+        "all_cores": {"value": samples / stepn, "cores": workers, "host_cpus": os.cpu_count(),
+                      "s_per_sample": many,
+                      "note": "build on one core (the oracle's DP is sequential), samples by forked workers"},
     }
 
 
-def measured_traffic(name):
-    """HBM bytes per step of the gather kernels from the committed counter summary,
-    or None when the gather source changed since the counters were taken."""
+def profile_fields(name):
+    """Fields of a committed counter summary (profiles/<name>) when it was taken
+    for the current DP and sampler sources, else None."""
     import hashlib
     path = os.path.join(ROOT, "profiles", name)
-    src = os.path.join(ROOT, "paper_2009_03052_amd", "csrc", "dp.hip")
+    csrc = os.path.join(ROOT, "paper_2009_03052_amd", "csrc")
     try:
         fields = {}
         for line in open(path):
             parts = line.split()
             if len(parts) >= 2:
                 fields[parts[0]] = parts[1]
-        cur = hashlib.sha256(open(src, "rb").read()).hexdigest()
-        if fields.get("source_sha256") != cur:
+        h = hashlib.sha256()
+        for f in ("dp.hip", "sample.hip", "device.hpp"):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+        if fields.get("source_sha256") != h.hexdigest():
             return None
-        return float(fields["traffic_bytes_per_step"])
-    except (OSError, KeyError, ValueError):
+        return fields
+    except OSError:
         return None
 
 
@@ -455,6 +534,55 @@ def run_serving(a):
     print(json.dumps(out), flush=True)
 
 
+def _u(x):
+    return int(x[0]) | (int(x[1]) << 64)
+
+
+def rooflines(tab, infos, k, samp_ms, ns, prof):
+    """Roofline entries of the step: the DP join (gather of levels 1..k-1,
+    combine of levels 2..k, level-k totals), its gather and combine parts, and
+    the sampler. Bytes are algorithmic (from the stored record lengths), times
+    the HIP-event durations of the timed builds (mean over steps)."""
+    gb = tab.gather_bytes()
+    cb, tb = tab.combine_bytes()
+    mean = lambda f: sum(f(x) for x in infos) / len(infos)
+    g_ms = mean(lambda x: sum(x.gather_ms[h] for h in range(2, k)))
+    c_ms = mean(lambda x: sum(x.combine_ms[h] for h in range(2, k + 1)))
+    j_ms = mean(lambda x: sum(x.level_ms[h] for h in range(1, k + 1)) + x.totals_ms)
+    g_bytes = sum(gb[h] for h in range(2, k))
+    c_bytes = sum(cb[h] for h in range(2, k + 1))
+    j_bytes = sum(gb[h] for h in range(1, k)) + c_bytes + tb
+
+    def entry(bytes_, ms, kernel, traffic_key=None):
+        ach = bytes_ / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+        tr = float(prof[traffic_key]) if (prof and traffic_key and traffic_key in prof) else None
+        return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                "traffic": tr, "kernel": kernel, "bytes_per_build": bytes_, "ms_per_build": ms}
+
+    join = entry(j_bytes, j_ms, "DP join: k_gather1, k_gather*, k_hub_prepare, k_combine*, k_words, scans, k_pack, "
+                 "k_totals and scans (every level of the build plus the level-k totals)", "traffic_bytes_per_build")
+    join["traffic_unit"] = "HBM bytes per build from TCC_EA0 read requests by size (32/64/128 B) and write requests"
+    parts = {
+        "gather": entry(g_bytes, g_ms, "neighbour-sum gather of levels 2..k-1 (k_gather_group, k_gather_list, "
+                        "k_gather, k_gather_wide, k_gather_hub, k_hub_prepare)", "gather_traffic_bytes_per_build"),
+        "combine": entry(c_bytes, c_ms, "combine of levels 2..k with compaction and packing (k_combine*, "
+                         "k_combine_list, k_combine_wide, k_words, scans, k_pack)", "combine_traffic_bytes_per_build"),
+    }
+    sp = {"bound": "hbm random access", "samples_per_s": ns / (samp_ms / 1e3) if samp_ms > 0 else 0.0,
+          "ms_per_launch": samp_ms, "kernel": "k_sample"}
+    if prof and "sampler_read_bytes_per_sample" in prof:
+        bps = float(prof["sampler_read_bytes_per_sample"])
+        sp.update({"hbm_read_bytes_per_sample": bps, "achieved": bps * ns / (samp_ms * 1e-3) / 1e9,
+                   "peak": HBM_PEAK_GBS, "unit": "GB/s"})
+        sp["frac"] = sp["achieved"] / HBM_PEAK_GBS
+        if "sampler_l2_request_bytes_per_sample" in prof:
+            sp["l2_request_bytes_per_sample"] = float(prof["sampler_l2_request_bytes_per_sample"])
+    else:
+        sp.update({"hbm_read_bytes_per_sample": None, "achieved": None, "frac": None})
+    parts["sampler"] = sp
+    return join, parts
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -464,6 +592,13 @@ def main():
         return run_batching(a)
     if a.workload == "serving":
         return run_serving(a)
+    cfg = PLAIN[a.workload]
+    base = None
+    if not a.no_cpu_baseline and not a.small:
+        # first, while no GPU context exists (its sampling workers are forked)
+        print("# cpu baseline (the oracle) ...", file=sys.stderr, flush=True)
+        base = cpu_baseline(cfg, cfg["m"], a.samples if a.samples is not None else cfg["samples"])
+        print(f"# cpu baseline: {base['value']:.1f} samples/s on 1 core", file=sys.stderr, flush=True)
     import torch
 
     import graphgen as gg
@@ -472,14 +607,13 @@ def main():
     torch.cuda.set_device(0)
     if a.calibrate_copy:
         # a plain copy of known size: reads and writes 2^30 bytes each; the ratio of
-        # these to what FETCH_SIZE / WRITE_SIZE report for it scales the counters
+        # these to what the read / write request counters report scales them
         src = torch.ones(1 << 30, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
         print("# calibration copy of 1073741824 bytes done", file=sys.stderr, flush=True)
-    cfg = PLAIN[a.workload]
     if a.small:
         g = gg.chung_lu(cfg["n"] // 10, cfg["m"] // 10, cfg["gamma"], cfg["wmax"] / 10, seed=cfg["gseed"])
     else:
@@ -529,17 +663,13 @@ def main():
     torch.cuda.synchronize()
     build_ms, samp_ms, cls_ms = ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2]), ev[2].elapsed_time(ev[3])
     info = tab.info()
-
-    # gather launches of the timed builds: HIP-event durations recorded on the
-    # build's stream; algorithmic bytes are the same for every build of the input
-    gms = [sum(x.gather_ms[h] for h in range(2, k)) for x in infos]
-    g_ms = sum(gms) / len(gms)
-    gb = tab.gather_bytes()
-    g_bytes = sum(gb[h] for h in range(2, k))
-    achieved = g_bytes / (g_ms * 1e-3) / 1e9 if g_ms > 0 else 0.0
-    traffic = measured_traffic(cfg["traffic"])
+    prof = profile_fields(cfg["traffic"])
+    join, parts = rooflines(tab, infos, k, samp_ms, ns, prof)
+    print(f"# DP join {join['achieved']:.0f} GB/s ({join['frac']:.3f} of peak); gather "
+          f"{parts['gather']['achieved']:.0f} GB/s, combine {parts['combine']['achieved']:.0f} GB/s",
+          file=sys.stderr, flush=True)
     ags = None
-    if "ags" in cfg:
+    if "ags" in cfg and not a.no_round_skipping:
         A = cfg["ags"]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -557,9 +687,10 @@ def main():
     bc = None if a.no_round_skipping else biased_colouring(scc, dg, k, cfg["biased_lambda"], cfg["cseed"], ns, sseed,
                                                            verts, par, info, build_ms)
     vl = None if a.no_round_skipping else variable_length(scc, dg, dcol, k, ns, sseed, verts, par, info)
-    rr = random_read_ceiling(scc, torch)
-    print(f"# random reads: {rr['GBs_64B']:.0f} GB/s (64 B), {rr['GBs_128B']:.0f} GB/s (128 B)", file=sys.stderr,
-          flush=True)
+    rr = None if a.no_round_skipping else random_read_ceiling(scc, torch)
+    if rr:
+        print(f"# random reads: {rr['GBs_64B']:.0f} GB/s (64 B), {rr['GBs_128B']:.0f} GB/s (128 B)", file=sys.stderr,
+              flush=True)
     out = {
         "metric": "DP table build s & colorful-treelet samples/sec, batched/served vs plain",
         "value": ns / dt,
@@ -571,14 +702,16 @@ def main():
                    "n": g.n, "m": g.m, "d_max": int(g.degrees().max()), "k": k, "samples": ns},
         "build_s": build_ms / 1e3, "sample_per_s": ns / (samp_ms / 1e3), "classify_per_s": ns / (cls_ms / 1e3),
         "level_ms": [round(info.level_ms[h], 3) for h in range(1, k + 1)],
-        "table_bytes": int(info.bytes), "t": str(int(info.t[0]) | (int(info.t[1]) << 64)),
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "traffic_unit": f"bytes per step ({k - 2} gather launches), FETCH_SIZE x2.0 + WRITE_SIZE x1.0",
-                     "kernel": "k_gather_group + k_gather_list + k_gather_hub + k_hub_prepare (neighbour-record gather of the DP, levels 2..k-1)",
-                     "bytes_per_step": g_bytes, "ms_per_step": g_ms},
+        "gather_ms": [round(info.gather_ms[h], 3) for h in range(1, k)],
+        "combine_ms": [round(info.combine_ms[h], 3) for h in range(2, k + 1)],
+        "totals_ms": round(info.totals_ms, 3),
+        "wide_vertices": [int(info.wide_vertices[h]) for h in range(1, k + 1)],
+        "table_bytes": int(info.bytes), "t": str(_u(info.t)),
+        "roofline": join,
+        "roofline_parts": parts,
     }
-    out["random_read_ceiling"] = rr
+    if rr is not None:
+        out["random_read_ceiling"] = rr
     if ags is not None:
         out["ags"] = ags
     if rs is not None:
@@ -587,8 +720,8 @@ def main():
         out["biased_colouring"] = bc
     if vl is not None:
         out["variable_length_counts"] = vl
-    if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg, g.m, ns)
+    if base is not None:
+        out["cpu_baseline"] = base
     print(json.dumps(out), flush=True)
 
 

@@ -169,6 +169,9 @@ typedef struct {
                                   sum_v binom(d_v, k-1) (lo, hi); 0 otherwise */
     int64_t record_bytes;      /* bytes of the stored records of levels 2..k */
     int vlc;                   /* records in the variable-length layout */
+    double combine_ms[9];      /* device time of the combine of level h (Eq. (1) products,
+                                  compaction, packing; scc_build_table only) */
+    double totals_ms;          /* device time of the level-k totals and running sums */
 } scc_table_info;
 
 /* Table summary (host struct; no device work). */
@@ -183,6 +186,20 @@ scc_status scc_table_info_get(const scc_table *t, scc_table_info *out);
  * counting kernel on the table's stream and synchronises it.
  */
 scc_status scc_gather_bytes(const scc_table *t, double out[9]);
+
+/*
+ * scc_combine_bytes -- algorithmic bytes of each level's combine (Eq. (1) at
+ * every vertex that has level h; under zero-rooting level k at colour-0
+ * vertices only): the vertex's own records of levels 2..h-1 (10 B per entry,
+ * 18 B for a 128-bit vertex; level 1 is implicit), its dense neighbour sums of
+ * levels 1..h-1 that were built (8 B per entry, 16 B for rows with high words)
+ * and its level-h record written. out: host double[9], out[h] for h = 2..k.
+ * *totals: bytes of the level-k totals (the level-k records read; eta_v and
+ * its running sum written, 32 B per vertex). Tables in the fixed layout only
+ * (SCC_EUNSUPPORTED after a variable-length re-encoding). Runs a counting
+ * kernel on the table's stream and synchronises it.
+ */
+scc_status scc_combine_bytes(const scc_table *t, double out[9], double *totals);
 
 /*
  * scc_occ -- database queries of Sec. 3: occ(T_C, v) (key >= 0: the count of
@@ -297,6 +314,24 @@ scc_status scc_catalog(int k, int64_t *num_classes, uint32_t *codes, int64_t *si
 scc_status scc_ags(const scc_table *t, int64_t cbar, int64_t round_size, int64_t budget,
                    uint64_t seed, uint64_t stream_id, int64_t *hits, double *w, int64_t *n_j,
                    int32_t *round_shapes, int64_t *n_rounds, void *stream);
+
+/*
+ * scc_estimate -- graphlet count estimates (Sec. 2.2). A uniform colourful
+ * k-treelet copy spans a copy of graphlet class i with probability
+ * c_i sigma_i / t (c_i: colourful copies of class i, sigma_i: its spanning
+ * trees, t: the table's total), so from uniform samples (w == NULL) of which
+ * hits[i] fell in class i out of n_samples,
+ *     c_i = t (hits_i / n_samples) / sigma_i;
+ * from an AGS run (w = scc_ags's weights), c_i = hits_i / w_i (0 where w_i = 0).
+ * The copies in G are g_i = c_i / p_k, p_k the probability that k given
+ * vertices are colourful: scc_colour_set_probability(k, lambda, k, 1) for a
+ * biased colouring; p_k <= 0 means uniform colours (k!/k^k).
+ * hits: host int64[N_k]; w: host double[N_k] or NULL; out_colourful and
+ * out_count: host double[N_k], either may be NULL. FP64, classes ascending.
+ * Errors: SCC_EINVAL (NULL table or hits, n_samples <= 0 without w).
+ */
+scc_status scc_estimate(const scc_table *t, const int64_t *hits, const double *w, int64_t n_samples,
+                        double p_k, double *out_colourful, double *out_count);
 
 /* Number of unrooted k-treelet shapes (free trees on k nodes), -1 if k is
    outside [1, 8]. Shape ids j in [0, this) order the shapes by the smallest

@@ -85,6 +85,7 @@ def lib():
             "orc_spanning_trees": (i64, [u32, C.c_int]),
             "orc_spanning_trees_by_shape": (C.c_int, [u32, C.c_int, P]),
             "orc_ags": (C.c_int, [P, i64, i64, i64, u64, u64, P, P, P, P, P]),
+            "orc_estimate": (C.c_int, [P, P, P, i64, C.c_double, P, P]),
             "orc_balanced_rank": (C.c_int, [C.c_int, C.c_int]),
             "orc_balanced_orbit": (C.c_int, [C.c_int, C.c_int]),
             "orc_star_class": (C.c_int, [C.c_int]),
@@ -251,6 +252,18 @@ class Table:
         _check(lib().orc_ags(self._h, cbar, round_size, budget, seed, stream,
                              _p(hits), _p(w), _p(nj), _p(shapes), C.byref(nr)))
         return {"hits": hits, "w": w, "n_j": nj, "round_shapes": shapes[:nr.value]}
+
+
+def estimate(tab: "Table", hits, n: int = 0, w=None, pk: float = 0.0):
+    """(colourful-copy estimates c_i, graph-copy estimates g_i = c_i / p_k) per class (Sec. 2.2);
+    uniform hits of n samples, or AGS hits with their weights w."""
+    s = num_classes(tab.k)
+    hits = np.ascontiguousarray(hits, dtype=np.int64)
+    wv = None if w is None else np.ascontiguousarray(w, dtype=np.float64)
+    c = np.zeros(s, np.float64)
+    g = np.zeros(s, np.float64)
+    _check(lib().orc_estimate(tab._h, _p(hits), _p(wv) if wv is not None else None, n, pk, _p(c), _p(g)))
+    return c, g
 
 
 def check_csr(g) -> int:

@@ -20,6 +20,7 @@
  *   - induced-graphlet classification by a minimum-over-permutations
  *     adjacency code, spanning-tree numbers (Sec. 4.4 "Graphlet manipulations")
  *   - AGS, adaptive graphlet sampling (Sec. 4.1, Algorithm AGS)
+ *   - the estimators of colourful and of all graphlet copies (Sec. 2.2)
  *   - round skipping: balanced rootings, direct star sampling (Sec. 3.3)
  *   - biased colourings and the probability of a colour set (Sec. 3.5)
  *
@@ -27,7 +28,8 @@
  * tiny graphs, closed forms, printed constants, library cross-checks), except
  * the accuracy of AGS estimates on the paper's real graphs, which is
  * "parity unpinned" (the datasets are not available); AGS itself is pinned by
- * its behaviour on the lollipop graph and by replay.
+ * its behaviour on the lollipop graph, by replay and by a sample-by-sample
+ * transcription of the printed algorithm.
  */
 #include <stdint.h>
 #include <stdio.h>
@@ -1304,4 +1306,35 @@ int orc_ags(const orc_table *T, int64_t cbar, int64_t round_size, int64_t budget
 done:
     free(sig); free(sig_ok); free(c); free(w); free(nj); free(cov); free(hit); free(verts); free(par); free(cls);
     return st;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Estimators (Sec. 2.2). A uniform colourful k-treelet copy spans graphlet  */
+/* H_i with probability c_i sigma_i / t, where c_i counts the colourful       */
+/* copies of H_i and sigma_i its spanning trees; so with hits_i of n samples */
+/* in class i,  c_i ~= t (hits_i / n) / sigma_i.  AGS (Sec. 4.1) gives        */
+/* c_i ~= hits_i / w_i instead (w given; 0 where w_i = 0). A colourful        */
+/* k-subset has probability p_k, so the copies in G are g_i ~= c_i / p_k     */
+/* (p_k <= 0 here: the uniform colouring's k!/k^k).                          */
+/* ------------------------------------------------------------------------- */
+int orc_estimate(const orc_table *T, const int64_t *hits, const double *w, int64_t n, double pk,
+                 double *out_c, double *out_g)
+{
+    const int k = T->k;
+    int st = build_catalog(k);
+    if (st) return st;
+    if (!hits || (!w && n <= 0)) { set_err("bad estimator input"); return ORC_EINVAL; }
+    if (pk <= 0) {
+        pk = 1.0;
+        for (int i = 1; i <= k; i++) pk *= (double)i / (double)k;
+    }
+    const double t = (double)T->t;
+    for (int i = 0; i < cat_n[k]; i++) {
+        double c;
+        if (w) c = w[i] > 0 ? (double)hits[i] / w[i] : 0.0;
+        else c = t * ((double)hits[i] / (double)n) / (double)orc_spanning_trees(cat_codes[k][i], k);
+        if (out_c) out_c[i] = c;
+        if (out_g) out_g[i] = c / pk;
+    }
+    return ORC_OK;
 }

@@ -79,7 +79,8 @@ class TableInfo(C.Structure):
                 ("nnz", C.c_int64 * 9), ("wide_vertices", C.c_int64 * 9), ("bytes", C.c_int64),
                 ("t", C.c_uint64 * 2), ("tj", (C.c_uint64 * 2) * 32), ("level_ms", C.c_double * 9),
                 ("gather_ms", C.c_double * 9), ("num_hubs", C.c_int), ("stars", C.c_uint64 * 2),
-                ("record_bytes", C.c_int64), ("vlc", C.c_int)]
+                ("record_bytes", C.c_int64), ("vlc", C.c_int), ("combine_ms", C.c_double * 9),
+                ("totals_ms", C.c_double)]
 
 
 class _ServerOpts(C.Structure):
@@ -118,6 +119,7 @@ _SIGS = {
     "scc_table_destroy": (None, [_P]),
     "scc_table_info_get": (C.c_int, [_P, C.POINTER(TableInfo)]),
     "scc_gather_bytes": (C.c_int, [_P, _P]),
+    "scc_combine_bytes": (C.c_int, [_P, _P, C.POINTER(C.c_double)]),
     "scc_probe_random_reads": (C.c_int, [_P, _u64, C.c_int, _i64, _u64, _P, _P, C.POINTER(C.c_float)]),
     "scc_occ": (C.c_int, [_P, _i64, _i32, _P]),
     "scc_export_level": (C.c_int, [_P, C.c_int, C.POINTER(_i64), _P, _P, _P, _P, _P]),
@@ -125,6 +127,7 @@ _SIGS = {
     "scc_classify": (C.c_int, [_P, _P, _i64, _P, _P, _P]),
     "scc_catalog": (C.c_int, [C.c_int, C.POINTER(_i64), _P, _P, _P, _P]),
     "scc_ags": (C.c_int, [_P, _i64, _i64, _i64, _u64, _u64, _P, _P, _P, _P, C.POINTER(_i64), _P]),
+    "scc_estimate": (C.c_int, [_P, _P, _P, _i64, C.c_double, _P, _P]),
     "scc_build_batch": (C.c_int, [C.POINTER(_Instance), C.c_int, C.POINTER(_BuildOpts), C.POINTER(_BatchOpts),
                                   C.POINTER(_P), C.POINTER(BatchReport)]),
     "scc_server_create": (C.c_int, [C.POINTER(_ServerOpts), C.POINTER(_P)]),
@@ -277,6 +280,13 @@ class Table:
         _check(_lib.scc_gather_bytes(self._h, out))
         return list(out)
 
+    def combine_bytes(self):
+        """(per-level combine bytes [9], level-k totals bytes) (``scc_combine_bytes``)."""
+        out = (C.c_double * 9)()
+        tot = C.c_double(0)
+        _check(_lib.scc_combine_bytes(self._h, out, C.byref(tot)))
+        return list(out), tot.value
+
     def totals(self):
         """(t, [t_j]) as Python ints."""
         i = self.info()
@@ -332,6 +342,17 @@ class Table:
             code, cls = out
         _check(_lib.scc_classify(self._h, _ptr(verts), n, _ptr(code), _ptr(cls), _stream_ptr(stream)))
         return (code[:n] if code is not None else None), cls[:n]
+
+    def estimate(self, hits, n: int = 0, w=None, p_k: float = 0.0):
+        """``scc_estimate``: (colourful-copy estimates, graph-copy estimates) per class."""
+        s = num_classes(self.k)
+        hits = np.ascontiguousarray(hits, dtype=np.int64)
+        wv = None if w is None else np.ascontiguousarray(w, dtype=np.float64)
+        c = np.zeros(s, np.float64)
+        g = np.zeros(s, np.float64)
+        _check(_lib.scc_estimate(self._h, hits.ctypes.data_as(_P), wv.ctypes.data_as(_P) if wv is not None else None,
+                                 n, p_k, c.ctypes.data_as(_P), g.ctypes.data_as(_P)))
+        return c, g
 
     def ags(self, cbar: int, round_size: int, budget: int, seed: int, stream_id: int = 0, stream=None):
         s = num_classes(self.k)

@@ -436,6 +436,33 @@ extern "C" scc_status scc_catalog(int k, int64_t *num_classes, uint32_t *codes, 
     return SCC_OK;
 }
 
+// Sec. 2.2: a uniform colourful k-treelet copy spans graphlet H_i with
+// probability c_i sigma_i / t, so c_i ~= t (hits_i / n) / sigma_i; AGS gives
+// c_i ~= hits_i / w_i; the copies in G are c_i / p_k.
+extern "C" scc_status scc_estimate(const scc_table *T, const int64_t *hits, const double *w, int64_t n_samples,
+                                   double p_k, double *out_colourful, double *out_count)
+{
+    if (!T || !hits) return set_error(SCC_EINVAL, "NULL argument");
+    if (!w && n_samples <= 0) return set_error(SCC_EINVAL, "uniform estimates need n_samples > 0");
+    const int k = T->k;
+    ClassData *cd;
+    scc_status s = ensure_classes(k, T->stream, &cd);
+    if (s) return s;
+    if (p_k <= 0) {
+        p_k = 1.0;
+        for (int i = 1; i <= k; i++) p_k *= (double)i / (double)k;
+    }
+    const double t = (double)T->t;
+    for (size_t i = 0; i < cd->codes.size(); i++) {
+        double c;
+        if (w) c = w[i] > 0 ? (double)hits[i] / w[i] : 0.0;
+        else c = t * ((double)hits[i] / (double)n_samples) / (double)spanning_trees_host(cd->codes[i], k);
+        if (out_colourful) out_colourful[i] = c;
+        if (out_count) out_count[i] = c / p_k;
+    }
+    return SCC_OK;
+}
+
 extern "C" void scc_release_caches(void)
 {
     std::lock_guard<std::mutex> lk(g_cls_mu);

@@ -798,6 +798,49 @@ __global__ void __launch_bounds__(256) k_gather_bytes(GraphView g, LevelView L, 
     if (lane_id() == 0 && bytes) atomicAdd(out, (unsigned long long)bytes);
 }
 
+// Algorithmic bytes of the combine of every level h >= 2 at each vertex that
+// has level h (under zero-rooting level k only at colour-0 vertices): Eq. (1)
+// reads the vertex's own records of levels 2..h-1 (10 B per entry, 18 B for a
+// 128-bit vertex; level 1 is implicit) and its dense neighbour sums of levels
+// 1..h-1 that exist (8 B per entry, 16 B for rows with high words), and writes
+// its level-h record. out[h] accumulates level h; out[0] the level-k totals
+// (the level-k records read, eta and its running sum written: 32 B a vertex).
+struct CombineBytesArgs {
+    GraphView g;
+    int k, zero;
+    LevelView lev[SCC_KMAX + 1];
+    const int32_t *hrow[SCC_KMAX + 1];
+    int WS[SCC_KMAX + 1];
+    int s_built[SCC_KMAX + 1];
+};
+
+__global__ void __launch_bounds__(256) k_combine_bytes(CombineBytesArgs A, unsigned long long *out)
+{
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint64_t own[SCC_KMAX + 1] = {0}, sums[SCC_KMAX + 1] = {0};
+    uint64_t by[SCC_KMAX + 1] = {0};
+    if (v < A.g.n) {
+        for (int h = 2; h <= A.k; h++) {
+            const uint64_t l = A.lev[h].loc[v];
+            own[h] = (uint64_t)LOC_LEN(l) * (LOC_WIDE(l) ? 18u : 10u);
+        }
+        for (int h = 1; h < A.k; h++)
+            if (A.s_built[h]) sums[h] = (uint64_t)A.WS[h] * ((h >= 2 && A.hrow[h] && A.hrow[h][v] >= 0) ? 16u : 8u);
+        uint64_t below = sums[1];
+        for (int h = 2; h <= A.k; h++) {
+            const bool here = !(A.zero && h == A.k && A.g.colors[v] != 0);
+            if (here) by[h] = below + own[h];
+            below += own[h] + sums[h];
+        }
+        by[0] = own[A.k] + 32u;
+    }
+    for (int h = 0; h <= A.k; h++) {
+        if (h == 1) continue;
+        const uint64_t b = wave_sum64(by[h]);
+        if (lane_id() == 0 && b) atomicAdd(out + h, (unsigned long long)b);
+    }
+}
+
 __global__ void k_hub_rows(GraphView g, const int32_t *hubs, int nhub, int64_t *rows)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1783,22 +1826,27 @@ static scc_status build_levels(scc_table *T)
     if (!gwide) return set_error(SCC_ENOMEM, "wide rows");
 
     // per-level start/end events (whole level, and its gather), read once at the end
-    hipEvent_t ev[SCC_KMAX + 1][2] = {}, gev[SCC_KMAX + 1][2] = {};
+    // and the start of its combine (which ends with the level)
+    hipEvent_t ev[SCC_KMAX + 1][2] = {}, gev[SCC_KMAX + 1][2] = {}, cev[SCC_KMAX + 1] = {};
     struct EvGuard {
-        hipEvent_t (*a)[2], (*b)[2];
+        hipEvent_t (*a)[2], (*b)[2], *c;
         ~EvGuard() {
-            for (int h = 0; h <= SCC_KMAX; h++)
+            for (int h = 0; h <= SCC_KMAX; h++) {
                 for (int j = 0; j < 2; j++) {
                     if (a[h][j]) (void)hipEventDestroy(a[h][j]);
                     if (b[h][j]) (void)hipEventDestroy(b[h][j]);
                 }
+                if (c[h]) (void)hipEventDestroy(c[h]);
+            }
         }
-    } evg{ev, gev};
-    for (int h = 1; h <= k; h++)
+    } evg{ev, gev, cev};
+    for (int h = 1; h <= k; h++) {
         for (int j = 0; j < 2; j++) {
             HIP_TRY(hipEventCreate(&ev[h][j]));
             HIP_TRY(hipEventCreate(&gev[h][j]));
         }
+        HIP_TRY(hipEventCreate(&cev[h]));
+    }
 
     // hub rows and their neighbour chunks, and the rows between the grouped
     // low-degree ones and the hubs (the same for every level)
@@ -2016,6 +2064,7 @@ static scc_status build_levels(scc_table *T)
             HIP_TRY(hipEventRecord(ev[h][1], st));
             continue;
         }
+        HIP_TRY(hipEventRecord(cev[h], st));
         CombineArgs C{};
         C.g = g; C.L = T->dlut; C.h = h; C.zero_only = zero && last; C.max_bits = T->max_bits;
         C.bal = bal && last;
@@ -2089,6 +2138,10 @@ static scc_status build_levels(scc_table *T)
         HIP_TRY(hipEventElapsedTime(&ms, ev[h][0], ev[h][1]));
         T->level_ms[h] = ms;
         if (h == 1) T->gather_ms[1] = ms;
+        if (h >= 2 && !(bal && h == k - 1)) {
+            HIP_TRY(hipEventElapsedTime(&ms, cev[h], ev[h][1]));
+            T->combine_ms[h] = ms;
+        }
         if (h >= 2 && h < k && s_need[h]) {
             HIP_TRY(hipEventElapsedTime(&ms, gev[h][0], gev[h][1]));
             T->gather_ms[h] = ms;
@@ -2117,6 +2170,22 @@ static scc_status gather_stats(scc_table *T)
         HIP_TRY(hipStreamSynchronize(st));
         T->gather_bytes[hs] = (double)b;
     }
+    // the combine of every level and the level-k totals, in one counting pass
+    HIP_TRY(hipMemsetAsync(acc, 0, 64, st));
+    CombineBytesArgs A{};
+    A.g = g; A.k = T->k; A.zero = T->rooting == SCC_ROOT_ZERO;
+    for (int h = 2; h <= T->k; h++) A.lev[h] = view(T->lev[h]);
+    for (int h = 1; h < T->k; h++) {
+        A.WS[h] = h == 1 ? T->k - 1 : T->hlut.WS[h];
+        A.s_built[h] = T->S[h].lo != nullptr;
+        A.hrow[h] = T->S[h].hrow;
+    }
+    if (n) hipLaunchKernelGGL(k_combine_bytes, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, A, acc);
+    unsigned long long cb[SCC_KMAX + 1] = {0};
+    HIP_TRY(hipMemcpyAsync(cb, acc, sizeof cb, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int h = 2; h <= T->k; h++) T->combine_bytes[h] = (double)cb[h];
+    T->totals_bytes = (double)cb[0];
     T->mem.put(acc);
     T->stats_done = true;
     return SCC_OK;
@@ -2216,8 +2285,21 @@ static scc_status totals_finish(scc_table *T)
 
 static scc_status build_totals(scc_table *T)
 {
+    hipEvent_t e[2] = {};
+    struct G { hipEvent_t *e; ~G() { for (int i = 0; i < 2; i++) if (e[i]) (void)hipEventDestroy(e[i]); } } gd{e};
+    HIP_TRY(hipEventCreate(&e[0]));
+    HIP_TRY(hipEventCreate(&e[1]));
+    HIP_TRY(hipEventRecord(e[0], T->stream));
     scc_status s = totals_launch(T);
-    return s ? s : totals_finish(T);
+    if (s) return s;
+    HIP_TRY(hipEventRecord(e[1], T->stream));
+    s = totals_finish(T);
+    if (s) return s;
+    float ms = 0;
+    HIP_TRY(hipEventSynchronize(e[1]));
+    HIP_TRY(hipEventElapsedTime(&ms, e[0], e[1]));
+    T->totals_ms = ms;
+    return SCC_OK;
 }
 
 // Re-encodes every stored level with variable-length counts (Sec. 3.3). The
@@ -2399,6 +2481,17 @@ extern "C" scc_status scc_gather_bytes(const scc_table *t, double out[9])
     return SCC_OK;
 }
 
+extern "C" scc_status scc_combine_bytes(const scc_table *t, double out[9], double *totals)
+{
+    if (!t || !out || !totals) return set_error(SCC_EINVAL, "NULL argument");
+    if (t->vlc) return set_error(SCC_EUNSUPPORTED, "byte counts of tables in the variable-length layout");
+    scc_status s = gather_stats(const_cast<scc_table *>(t));
+    if (s) return s;
+    for (int h = 0; h < 9; h++) out[h] = h <= t->k ? t->combine_bytes[h] : 0.0;
+    *totals = t->totals_bytes;
+    return SCC_OK;
+}
+
 extern "C" scc_status scc_table_info_get(const scc_table *t, scc_table_info *out)
 {
     if (!t || !out) return set_error(SCC_EINVAL, "NULL argument");
@@ -2409,6 +2502,7 @@ extern "C" scc_status scc_table_info_get(const scc_table *t, scc_table_info *out
         out->wide_vertices[h] = t->lev[h].wide;
         out->level_ms[h] = t->level_ms[h];
         out->gather_ms[h] = t->gather_ms[h];
+        out->combine_ms[h] = t->combine_ms[h];
     }
     out->num_hubs = t->nhub;
     out->bytes = t->bytes;
@@ -2417,6 +2511,7 @@ extern "C" scc_status scc_table_info_get(const scc_table *t, scc_table_info *out
     out->stars[0] = lo64(t->stars); out->stars[1] = hi64(t->stars);
     for (int h = 2; h <= t->k; h++) out->record_bytes += (int64_t)t->lev[h].pool_words * 8;
     out->vlc = t->vlc ? 1 : 0;
+    out->totals_ms = t->totals_ms;
     return SCC_OK;
 }
 

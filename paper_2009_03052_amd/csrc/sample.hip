@@ -800,13 +800,14 @@ static scc_status ensure_shape_first(scc_table *T)
     return SCC_OK;
 }
 
-scc_status prepare_sampling(scc_table *T, int shape, SampleArgs *out)
+// The sampling arguments from structures that already exist: EINVAL (with the
+// reason) when a running sum the draw needs has not been built yet.
+static scc_status sampling_args(scc_table *T, int shape, SampleArgs *out)
 {
     const bool bal = T->rooting == SCC_ROOT_BALANCED;
     const u128 *pre = nullptr;
     u128 total = 0;
     int mode = 0;
-    scc_status s = SCC_OK;
     if (bal && shape == T->hlut.star_unr) {
         mode = 2;
         pre = T->star_pre;
@@ -816,14 +817,24 @@ scc_status prepare_sampling(scc_table *T, int shape, SampleArgs *out)
         mode = 1;
         total = T->t;
         if (total == 0) return set_error(SCC_EEMPTY, "no colourful %d-treelet to sample", T->k);
-        s = ensure_shape_first(T);
+        std::lock_guard<std::mutex> g(T->mu);
+        if (!T->bal_spre) return set_error(SCC_EINVAL, "the shape-first running sums are not built");
+    } else if (shape < 0) {
+        pre = T->pre;
+        total = T->root_total;
+        if (total == 0) return set_error(SCC_EEMPTY, "no colourful %d-treelet to sample", T->k);
     } else {
-        s = table_prefix(T, shape, &pre, &total);
-        if (!s && total == 0) return set_error(SCC_EEMPTY, "no colourful %d-treelet to sample", T->k);
+        std::lock_guard<std::mutex> g(T->mu);
+        auto it = T->pre_shape.find(shape);
+        if (it == T->pre_shape.end()) return set_error(SCC_EINVAL, "the running sums of shape %d are not built", shape);
+        pre = it->second;
+        total = T->tot_shape[shape];
+        if (total == 0) return set_error(SCC_EEMPTY, "no colourful %d-treelet to sample", T->k);
     }
-    if (s) return s;
-    s = ensure_hub_prefix(T);
-    if (s) return s;
+    {
+        std::lock_guard<std::mutex> g(T->hub_mu);
+        if (!T->hubpre_ready && !T->hub_host.empty()) return set_error(SCC_EINVAL, "the hub running sums are not built");
+    }
     SampleArgs A{};
     A.mode = mode;
     A.spre = T->bal_spre;
@@ -839,6 +850,27 @@ scc_status prepare_sampling(scc_table *T, int shape, SampleArgs *out)
     A.pre = pre; A.total = total;
     *out = A;
     return SCC_OK;
+}
+
+scc_status prepare_sampling(scc_table *T, int shape, SampleArgs *out)
+{
+    const bool bal = T->rooting == SCC_ROOT_BALANCED;
+    scc_status s = SCC_OK;
+    if (bal && shape == T->hlut.star_unr) {
+        if (T->stars == 0) return set_error(SCC_EEMPTY, "no %d-star to sample", T->k);
+    } else if (bal && shape < 0) {
+        if (T->t == 0) return set_error(SCC_EEMPTY, "no colourful %d-treelet to sample", T->k);
+        s = ensure_shape_first(T);
+    } else {
+        const u128 *pre = nullptr;
+        u128 total = 0;
+        s = table_prefix(T, shape, &pre, &total);
+        if (!s && total == 0) return set_error(SCC_EEMPTY, "no colourful %d-treelet to sample", T->k);
+    }
+    if (s) return s;
+    s = ensure_hub_prefix(T);
+    if (s) return s;
+    return sampling_args(T, shape, out);
 }
 
 scc_status prepare_all_sampling(scc_table *T)

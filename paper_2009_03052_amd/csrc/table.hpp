@@ -64,6 +64,9 @@ struct scc_table {
     double level_ms[SCC_KMAX + 1] = {0};
     double gather_ms[SCC_KMAX + 1] = {0};
     double gather_bytes[SCC_KMAX + 1] = {0};
+    double combine_ms[SCC_KMAX + 1] = {0};     // combine, compaction and packing of level h
+    double combine_bytes[SCC_KMAX + 1] = {0};
+    double totals_ms = 0, totals_bytes = 0;
     int64_t bytes = 0;
     int hub_degree = 1024;           // rows above this degree are gathered in chunks
     int hub_chunk = 256;             // neighbours per chunk
