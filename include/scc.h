@@ -265,6 +265,26 @@ scc_status scc_sample(const scc_table *t, int32_t shape, int64_t n, uint64_t see
                       int32_t *out_verts, int8_t *out_parent, void *stream);
 
 /*
+ * scc_sample_noalloc -- scc_sample for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation). Same arguments, samples and errors as scc_sample, bit
+ * for bit; it calls no hipMalloc, hipFree or allocating routine. Its only
+ * scratch, the call's error flags, lives in a static device array of 256
+ * bytes (the maximum; it does not grow with n) that each GPU keeps until the
+ * process ends; the flags are cleared by a kernel at the start of every call.
+ * Every call on one GPU shares that GPU's array, so calls that overlap on one
+ * GPU race (serialise them, for example on one stream). It draws only from
+ * running sums that already exist: SCC_EINVAL when the draw would need one
+ * that is not built yet (per-shape root sums, hub sums built lazily, or the
+ * shape-first sums of round skipping) -- one scc_sample call with the same
+ * shape, or creating a server on the table, builds them. Synchronises
+ * `stream` to read the flags.
+ */
+scc_status scc_sample_noalloc(const scc_table *t, int32_t shape, int64_t n, uint64_t seed,
+                              uint64_t stream_id, uint64_t first_index,
+                              int32_t *out_verts, int8_t *out_parent, void *stream);
+
+/*
  * scc_classify -- graphlet classification of samples (Sec. 4.4).
  * For each sample (k vertices of the table's graph), the induced adjacency
  * code  sum_{i<j} [v_i ~ v_j] 2^{idx(i,j)}  (pairs numbered row by row) and the

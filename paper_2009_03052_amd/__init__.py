@@ -124,6 +124,7 @@ _SIGS = {
     "scc_occ": (C.c_int, [_P, _i64, _i32, _P]),
     "scc_export_level": (C.c_int, [_P, C.c_int, C.POINTER(_i64), _P, _P, _P, _P, _P]),
     "scc_sample": (C.c_int, [_P, _i32, _i64, _u64, _u64, _u64, _P, _P, _P]),
+    "scc_sample_noalloc": (C.c_int, [_P, _i32, _i64, _u64, _u64, _u64, _P, _P, _P]),
     "scc_classify": (C.c_int, [_P, _P, _i64, _P, _P, _P]),
     "scc_catalog": (C.c_int, [C.c_int, C.POINTER(_i64), _P, _P, _P, _P]),
     "scc_ags": (C.c_int, [_P, _i64, _i64, _i64, _u64, _u64, _P, _P, _P, _P, C.POINTER(_i64), _P]),
@@ -329,6 +330,13 @@ class Table:
         _check(_lib.scc_sample(self._h, shape, n, seed, stream_id, first_index, _ptr(verts), _ptr(par),
                                _stream_ptr(stream)))
         return verts[:n], par[:n]
+
+    def sample_noalloc(self, verts: torch.Tensor, par: torch.Tensor, seed: int, stream_id: int = 0, shape: int = -1,
+                       first_index: int = 0, stream=None):
+        """``scc_sample_noalloc`` into caller-owned device tensors verts int32[n, k], par int8[n, k]."""
+        n = int(verts.shape[0])
+        _check(_lib.scc_sample_noalloc(self._h, shape, n, seed, stream_id, first_index, _ptr(verts), _ptr(par),
+                                       _stream_ptr(stream)))
 
     def classify(self, verts: torch.Tensor, stream=None, want_code: bool = True, out=None):
         """(code uint32 as int32[n] or None, class uint32 as int32[n]) device tensors."""

@@ -923,6 +923,74 @@ extern "C" scc_status scc_sample(const scc_table *tc, int32_t shape, int64_t n, 
     return SCC_OK;
 }
 
+// ---------------------------------------------------------------------------
+// The allocation-free sampling entry point. Its only device scratch, the error
+// flags of one call, is this file-scope array: each GPU holds one copy for the
+// life of the process. Host code never uses the array's name as an address:
+// the device address of each GPU's copy comes from hipGetSymbolAddress, taken
+// once per device (with that device current) on the first call there.
+// ---------------------------------------------------------------------------
+constexpr int NOALLOC_MAX_DEVICES = 64;
+constexpr size_t NOALLOC_SCRATCH_BYTES = 256;   // the maximum: one call's flags, whatever n
+static __device__ __align__(256) int scratch[NOALLOC_SCRATCH_BYTES / sizeof(int)];
+
+static std::mutex g_scratch_mu;
+static int *g_scratch_ptr[NOALLOC_MAX_DEVICES];   // device address of each GPU's copy, or null
+
+static scc_status scratch_of_current_device(int **out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+        return set_error(SCC_EDEVICE, "no usable current device (%d)", dev);
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return set_error(SCC_EDEVICE, "scratch address on device %d: %s", dev, hipGetErrorString(e));
+        g_scratch_ptr[dev] = (int *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return SCC_OK;
+}
+
+// clears the flags (a kernel, not a memset node, so that capture records it as one)
+__global__ void k_clear_flags(int *flags, int n)
+{
+    if ((int)threadIdx.x < n) flags[threadIdx.x] = 0;
+}
+
+extern "C" scc_status scc_sample_noalloc(const scc_table *tc, int32_t shape, int64_t n, uint64_t seed,
+                                         uint64_t stream_id, uint64_t first_index, int32_t *out_verts,
+                                         int8_t *out_parent, void *stream)
+{
+    scc_table *T = const_cast<scc_table *>(tc);
+    if (!T) return set_error(SCC_EINVAL, "table NULL");
+    if (n < 0) return set_error(SCC_EINVAL, "n < 0");
+    if (shape < -1 || shape >= T->hlut.num_unr) return set_error(SCC_EINVAL, "shape %d out of range", shape);
+    if (n == 0) return SCC_OK;
+    if (!out_verts || !out_parent) return set_error(SCC_EINVAL, "output NULL");
+    SampleArgs A;
+    scc_status s = sampling_args(T, shape, &A);
+    if (s) return s;
+    int *flags = nullptr;
+    s = scratch_of_current_device(&flags);
+    if (s) return s;
+    hipStream_t st = stream ? (hipStream_t)stream : T->stream;
+    A.seed = seed; A.stream = stream_id; A.first = first_index;
+    A.nsamp = n; A.verts = out_verts; A.par = out_parent; A.err = flags;
+    hipLaunchKernelGGL(k_clear_flags, dim3(1), dim3(WAVE), 0, st, flags, 1);
+    const int64_t grid = std::min<int64_t>(n, (int64_t)1 << 20);
+    hipLaunchKernelGGL(k_sample, dim3((unsigned)grid), dim3(WAVE), 0, st, A);
+    int herr = 0;
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(&herr, flags, 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return set_error(SCC_EDEVICE, "sample: %s", hipGetErrorString(e));
+    if (herr) return set_error(SCC_EDEVICE, "internal: a sample draw fell off its list (%d)", herr);
+    return SCC_OK;
+}
+
 extern "C" scc_status scc_occ(const scc_table *T, int64_t v, int32_t key, uint64_t out[2])
 {
     if (!T || !out) return set_error(SCC_EINVAL, "NULL argument");
