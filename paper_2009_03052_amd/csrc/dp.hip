@@ -1066,7 +1066,9 @@ __device__ inline void combine_outputs(const CombineArgs &A, int64_t v, int cv, 
                 }
             }
             const uint32_t beta = (uint32_t)((d >> 56) & 0x7fu);
-            val = beta == 1 ? acc : div_small(acc, beta);
+            // beta divides the sum exactly (Eq. (1) counts each copy beta times)
+            if (beta != 1) val = owide ? div_exact_small(acc, beta) : (u128)div_exact_small64(lo64(acc), beta);
+            else val = acc;
         }
         const bool nz = val != 0;
         const uint64_t bal = __ballot(nz);

@@ -107,6 +107,34 @@ __host__ __device__ inline u128 sat_mul(u128 a, u128 b)
     u128 sh = phi << 64;
     return sat_add(plo, sh);
 }
+// The inverse of an odd d modulo 2^128, by Newton's iteration x <- x (2 - d x)
+// (each step doubles the correct low bits; x = d is right to 3 bits).
+__host__ __device__ constexpr u128 inv_odd128(uint32_t d)
+{
+    u128 x = d;
+    for (int i = 0; i < 7; i++) x *= (u128)2 - (u128)d * x;
+    return x;
+}
+// x / d for a small d (1..8) that divides x exactly (exact division, Granlund
+// and Montgomery, PLDI'94): the factors of two are shifted out, then the odd
+// part is a multiplication by its inverse modulo 2^128 (or 2^64). The result
+// is meaningless when d does not divide x.
+__host__ __device__ inline u128 div_exact_small(u128 x, uint32_t d)
+{
+    const int s = d & 1u ? 0 : (d & 2u ? 1 : (d & 4u ? 2 : 3));
+    const uint32_t o = d >> s;
+    x >>= s;
+    if (o == 1) return x;
+    return x * (o == 3 ? inv_odd128(3) : o == 5 ? inv_odd128(5) : inv_odd128(7));
+}
+__host__ __device__ inline uint64_t div_exact_small64(uint64_t x, uint32_t d)
+{
+    const int s = d & 1u ? 0 : (d & 2u ? 1 : (d & 4u ? 2 : 3));
+    const uint32_t o = d >> s;
+    x >>= s;
+    if (o == 1) return x;
+    return x * (uint64_t)(o == 3 ? inv_odd128(3) : o == 5 ? inv_odd128(5) : inv_odd128(7));
+}
 // floor(x / d) for a small divisor d (1..8), by 32-bit long division.
 __host__ __device__ inline u128 div_small(u128 x, uint32_t d)
 {

@@ -135,3 +135,35 @@ def test_ags_equal_on_chung_lu_k5():
     r_orc = ot.ags(cbar=50, round_size=500, budget=20000, seed=8, stream=1)
     for key in ["hits", "w", "n_j", "round_shapes"]:
         assert np.array_equal(r_gpu[key], r_orc[key]), key
+
+
+def test_ags_printed_rule_at_round_size_one():
+    # rounds of one sample are the printed algorithm: the GPU controller makes
+    # the oracle's choices draw by draw (the oracle is pinned to a transcription)
+    g = gg.chung_lu(120, 300, 2.2, 25, seed=31)
+    k = 5
+    gt, ot = build_pair(g, gg.colors(g.n, k, seed=8), k)
+    r_gpu = gt.ags(cbar=20, round_size=1, budget=2000, seed=8, stream_id=1)
+    r_orc = ot.ags(cbar=20, round_size=1, budget=2000, seed=8, stream=1)
+    assert len(set(r_orc["round_shapes"].tolist())) > 1
+    for key in ["hits", "w", "n_j", "round_shapes"]:
+        assert np.array_equal(r_gpu[key], r_orc[key]), key
+
+
+def test_estimates_equal_oracle():
+    # Sec. 2.2 estimators from the GPU's own samples and classes, and from AGS
+    g = gg.chung_lu(3000, 12000, 2.2, 200, seed=31)
+    k = 5
+    gt, ot = build_pair(g, gg.colors(g.n, k, seed=32), k)
+    v, _ = gt.sample(20000, seed=4)
+    _, cls = gt.classify(v)
+    hits = np.bincount(cls.cpu().numpy(), minlength=O.num_classes(k)).astype(np.int64)
+    for pk in (0.0, 0.01):
+        gc, gg_ = gt.estimate(hits, n=20000, p_k=pk)
+        oc, og = O.estimate(ot, hits, n=20000, pk=pk)
+        assert np.allclose(gc, oc, rtol=1e-14, atol=0) and np.allclose(gg_, og, rtol=1e-14, atol=0)
+    r = gt.ags(cbar=50, round_size=500, budget=20000, seed=8, stream_id=1)
+    gc, gg_ = gt.estimate(r["hits"], w=r["w"])
+    oc, og = O.estimate(ot, r["hits"], w=r["w"])
+    assert np.array_equal(gc, oc) and np.allclose(gg_, og, rtol=1e-14, atol=0)
+    assert (gc > 0).sum() == (r["hits"] > 0).sum()

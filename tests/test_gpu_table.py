@@ -277,3 +277,30 @@ def test_k8_counts_beyond_64_bits():
         gv, gp = gt.sample(2000, seed=3)
         assert np.array_equal(gv.cpu().numpy(), ov) and np.array_equal(gp.cpu().numpy(), op), mode
         print(f"two hubs: mode {mode} equal", flush=True)
+
+
+def test_combine_bytes_match_their_definition():
+    # scc_combine_bytes against its definition from the exported records: at
+    # level h, every vertex that has level h reads its own records of levels
+    # 2..h-1 (10 B an entry), its dense neighbour sums of levels 1..h-1 (8 B an
+    # entry; widths r_h'' binom(k-1, h'')), and writes its level-h record; level
+    # k at colour-0 vertices only; the totals read level k and write 32 B a vertex
+    from math import comb
+    S = scc()
+    g = gg.erdos_renyi(3000, 12000, seed=71)
+    k = 5
+    colors = gg.colors(g.n, k, seed=72)
+    gt = S.Table(S.DeviceGraph.from_graph(g), colors, k)
+    assert all(gt.info().wide_vertices[h] == 0 for h in range(9))
+    lens = {}
+    for h in range(2, k + 1):
+        off = gt.export_level(h)[0]
+        lens[h] = np.diff(off).astype(np.int64)
+    ws = {hs: O.num_shapes(hs) * comb(k - 1, hs) for hs in range(1, k)}
+    zero = colors == 0
+    cb, tb = gt.combine_bytes()
+    for h in range(2, k + 1):
+        per_v = 10 * lens[h] + sum(10 * lens[q] for q in range(2, h)) + sum(8 * ws[q] for q in range(1, h))
+        want = int(per_v[zero].sum()) if h == k else int(per_v.sum())
+        assert cb[h] == want, h
+    assert tb == int(10 * lens[k].sum() + 32 * g.n)
