@@ -317,6 +317,19 @@ def batching_instances():
     return out
 
 
+def tables_equal_on_device(ta, tb, k):
+    """Every stored level (offsets, keys, both count words) and the totals of two
+    tables equal, compared on the device."""
+    import torch
+    if ta.totals() != tb.totals():
+        return False
+    for h in range(1, k + 1):
+        xa, xb = ta.export_level(h, to_host=False), tb.export_level(h, to_host=False)
+        if not all(x.shape == y.shape and torch.equal(x, y) for x, y in zip(xa, xb)):
+            return False
+    return True
+
+
 def run_batching(a):
     import torch
 
@@ -330,31 +343,55 @@ def run_batching(a):
             devg[id(g)] = scc.DeviceGraph.from_graph(g)
         inst.append((devg[id(g)], torch.as_tensor(c).cuda(), k))
     print(f"# batching: {len(inst)} instances, {sum(g.n for _, g, _, _ in raw)} vertices", file=sys.stderr, flush=True)
+    groups = {"colourings": inst[:16], "uneven_graphs": inst[16:], "all": inst}
 
-    def plain():
-        for g, c, k in inst:
+    def plain(xs):
+        for g, c, k in xs:
             t = scc.Table(g, c, k, validate=False)
             del t
 
-    def batched():
-        tabs, rep = scc.build_batch(inst, autotune=True, validate=False)
+    def batched(xs):
+        tabs, rep = scc.build_batch(xs, autotune=True, validate=False)
         del tabs
         return rep
 
-    plain()
-    rep0 = batched()      # tunes once (probes), later calls reuse the choice
-    print(f"# tuned: tile={rep0['tile']} hub={rep0['hub_degree']} waves={rep0['waves']} probes={rep0['probes']}",
-          file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    tp = []
-    tb = []
+    def timed(f, *args):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = f(*args)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, r
+
+    tuned = {}
+    for name, xs in groups.items():
+        plain(xs)
+        tuned[name] = batched(xs)      # tunes once per batch shape (probes); later calls reuse the choice
+        r = tuned[name]
+        print(f"# {name}: tuned tile={r['tile']} hub={r['hub_degree']} waves={r['waves']}", file=sys.stderr, flush=True)
+    per = {}
     reps = []
-    for i in range(a.steps):
-        torch.cuda.synchronize(); t0 = time.perf_counter(); plain(); torch.cuda.synchronize()
-        tp.append(time.perf_counter() - t0)
-        t0 = time.perf_counter(); reps.append(batched()); torch.cuda.synchronize()
-        tb.append(time.perf_counter() - t0)
-    p_s, b_s = sum(tp) / len(tp), sum(tb) / len(tb)
+    for name, xs in groups.items():
+        tp, tb = [], []
+        for i in range(a.steps):
+            tp.append(timed(plain, xs)[0])
+            dt, rep = timed(batched, xs)
+            tb.append(dt)
+            if name == "all":
+                reps.append(rep)
+        per[name] = {"plain_s": sum(tp) / len(tp), "batched_s": sum(tb) / len(tb)}
+        per[name]["speedup_vs_plain"] = per[name]["plain_s"] / per[name]["batched_s"]
+        print(f"# {name}: plain {per[name]['plain_s'] * 1e3:.1f} ms, batched {per[name]['batched_s'] * 1e3:.1f} ms",
+              file=sys.stderr, flush=True)
+    # full-size check: every batched table equals the plain build of its instance
+    tabs, _ = scc.build_batch(inst, autotune=True, validate=False)
+    equal = True
+    for (g, c, k), bt in zip(inst, tabs):
+        pt = scc.Table(g, c, k, validate=False)
+        equal = equal and tables_equal_on_device(pt, bt, k)
+        del pt
+    del tabs
+    print(f"# every batched table equals its plain build: {equal}", file=sys.stderr, flush=True)
+    p_s, b_s = per["all"]["plain_s"], per["all"]["batched_s"]
     out = {
         "metric": "DP table build s & colorful-treelet samples/sec, batched/served vs plain",
         "value": len(inst) / b_s, "unit": "tables built per second (one batched launch for all 48 instances)",
@@ -364,8 +401,10 @@ def run_batching(a):
                                "n in [1e3, 1e5], k = 5..7, zero-rooting",
                    "instances": len(inst)},
         "plain_s": p_s, "batched_s": b_s, "speedup_vs_plain": p_s / b_s,
+        "groups": per,
+        "batched_tables_equal_plain": equal,
         "batch_report": {k: v for k, v in reps[-1].items() if k != "probes"},
-        "tuning_probes": rep0["probes"],
+        "tuning_probes": tuned["all"]["probes"],
     }
     print(json.dumps(out), flush=True)
 
@@ -395,9 +434,10 @@ def serving_trace(count, seed=31):
             for i in range(count)]
 
 
-def drive(srv, trace, rate, sessions, window):
+def drive(srv, trace, rate, sessions, window, keep_every=0):
     """Submits `trace` at Poisson arrival times (rate per second; rate = inf: all at once) from one
-    thread, waits for and releases the results in order from another; returns the server's stats."""
+    thread, waits for and releases the results in order from another; returns the server's stats.
+    keep_every > 0: the rows of every keep_every-th uniform request are copied out (st["kept"])."""
     import queue
     import threading
     q = queue.Queue()
@@ -419,19 +459,25 @@ def drive(srv, trace, rate, sessions, window):
                 rid = srv.submit(r["graph"], r["n"], session=sessions[r["graph"]])
             else:
                 rid = srv.submit(r["graph"], r["n"], seed=r["seed"], stream_id=i, classify=True)
-            q.put((rid, "ags" if r["ags"] else "uniform"))
+            q.put((rid, "ags" if r["ags"] else "uniform", i))
         q.put(None)
 
     lat = {"uniform": [], "ags": []}
+    kept = []
 
     def waiter():
         done = 0
+        nu = 0
         while True:
             item = q.get()
             if item is None:
                 break
-            rid, kind = item
-            r = srv.wait(rid, timeout=900.0, copy=False)
+            rid, kind, i = item
+            keep = kind == "uniform" and keep_every > 0 and nu % keep_every == 0
+            nu += kind == "uniform"
+            r = srv.wait(rid, timeout=900.0, copy=keep)
+            if keep:
+                kept.append((i, r["verts"], r["parent"], r["cls"]))
             lat[kind].append(r["t_done"] - r["t_submit"])
             srv.release(rid)
             done += 1
@@ -445,6 +491,7 @@ def drive(srv, trace, rate, sessions, window):
         t.join()
     st = srv.stats()
     st["wall_s"] = time.perf_counter() - t0
+    st["kept"] = kept
     for kind, xs in lat.items():
         xs = sorted(xs)
         if xs:
@@ -499,7 +546,7 @@ def run_serving(a):
                                 ("continuous_ags16", False, 16.0, 0.0), ("continuous_age2ms", False, 1.0, 0.002),
                                 ("fifo", True, 1.0, 0.0)):
         srv, sess = server(fifo, aw, tau)
-        res[name] = drive(srv, trace, rate, sess, a.window)
+        res[name] = drive(srv, trace, rate, sess, a.window, keep_every=40 if name == "continuous" else 0)
         srv.close()
         r = res[name]
         print(f"# {name}: {r['completed']} requests, {r['samples_per_s'] / 1e6:.1f} M samples/s, "
@@ -507,6 +554,16 @@ def run_serving(a):
               f"{r.get('uniform_p50_ms', 0):.1f}/{r.get('uniform_p99_ms', 0):.1f} ms, AGS rounds p50/p99 "
               f"{r.get('ags_p50_ms', 0):.1f}/{r.get('ags_p99_ms', 0):.1f} ms", file=sys.stderr, flush=True)
     c, f = res["continuous"], res["fifo"]
+    # served rows equal scc_sample / scc_classify alone with the same arguments
+    alone_equal = True
+    for i, v, p, cl in c["kept"]:
+        r = trace[i]
+        t = tabs[r["graph"]]
+        av, ap = t.sample(r["n"], seed=r["seed"], stream_id=i)
+        _, acl = t.classify(av)
+        alone_equal = alone_equal and torch.equal(av, v) and torch.equal(ap, p) and torch.equal(acl.view(torch.int32),
+                                                                                              cl.view(torch.int32))
+    print(f"# {len(c['kept'])} served requests equal scc_sample alone: {alone_equal}", file=sys.stderr, flush=True)
     keep = ("completed", "samples", "steps", "span_s", "samples_per_s", "p50_ms", "p99_ms", "mean_ms", "max_ms",
             "arena_peak", "uniform_p50_ms", "uniform_p99_ms", "ags_p50_ms", "ags_p99_ms")
     out = {
@@ -527,6 +584,7 @@ def run_serving(a):
         "continuous_equal_shares": {k: res["continuous_equal"][k] for k in keep},
         "continuous_equal_ags_weight_16": {k: res["continuous_ags16"][k] for k in keep},
         "continuous_age_tau_2ms": {k: res["continuous_age2ms"][k] for k in keep},
+        "served_equal_alone": alone_equal, "served_checked": len(c["kept"]),
         "p99_speedup_vs_fifo": f["p99_ms"] / c["p99_ms"] if c["p99_ms"] > 0 else None,
         "p50_speedup_vs_fifo": f["p50_ms"] / c["p50_ms"] if c["p50_ms"] > 0 else None,
         "throughput_vs_fifo": c["samples_per_s"] / f["samples_per_s"] if f["samples_per_s"] > 0 else None,

@@ -303,8 +303,9 @@ class Table:
         _check(_lib.scc_occ(self._h, v, key, out))
         return _u128(out[0], out[1])
 
-    def export_level(self, h: int, stream=None):
-        """(off int64[n+1], key uint16 as int32[nnz], lo uint64[nnz], hi uint64[nnz]) as numpy arrays."""
+    def export_level(self, h: int, stream=None, to_host: bool = True):
+        """(off int64[n+1], key uint16[nnz], lo uint64[nnz], hi uint64[nnz]) as numpy arrays, or
+        (to_host=False) as device tensors of the same bits (int64, int16, int64, int64)."""
         nnz = _i64()
         _check(_lib.scc_export_level(self._h, h, C.byref(nnz), None, None, None, None, None))
         dev = self.device
@@ -315,6 +316,8 @@ class Table:
         _check(_lib.scc_export_level(self._h, h, C.byref(nnz), _ptr(off), _ptr(key), _ptr(lo), _ptr(hi),
                                      _stream_ptr(stream)))
         n = nnz.value
+        if not to_host:
+            return off, key[:n], lo[:n], hi[:n]
         return (off.cpu().numpy(), key[:n].cpu().numpy().view(np.uint16), lo[:n].cpu().numpy().view(np.uint64),
                 hi[:n].cpu().numpy().view(np.uint64))
 

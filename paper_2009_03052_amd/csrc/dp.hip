@@ -1038,28 +1038,68 @@ __device__ inline void combine_outputs(const CombineArgs &A, int64_t v, int cv, 
             const int xb = (int)(d & 0xffffu), sb = (int)((d >> 16) & 0xffffu), tb = (int)((d >> 32) & 0xffffu);
             const int nsplit = (int)((d >> 48) & 0xffu);
             u128 acc = 0;
+            // terms four at a time: the four descriptors, then all their LDS
+            // operands, are requested before any product, so that the loads of
+            // a group overlap instead of one latency per term
+            const uint16_t *txs = L.term_xs + tb;
+            const int n4 = nsplit & ~3;
             if (!owide) {
                 uint64_t a64 = 0;
-                for (int i = 0; i < nsplit; i++) {
-                    const uint32_t xs = L.term_xs[tb + i];
+                for (int i = 0; i < n4; i += 4) {
+                    uint32_t xs[4];
+                    uint64_t xv[4], sv[4];
+#pragma unroll
+                    for (int j = 0; j < 4; j++) xs[j] = txs[i + j];
+#pragma unroll
+                    for (int j = 0; j < 4; j++) { xv[j] = Xlo[xb + (xs[j] & 0xffu)]; sv[j] = Slo[sb + (xs[j] >> 8)]; }
+#pragma unroll
+                    for (int j = 0; j < 4; j++) a64 += xv[j] * sv[j];
+                }
+                for (int i = n4; i < nsplit; i++) {
+                    const uint32_t xs = txs[i];
                     a64 += Xlo[xb + (xs & 0xffu)] * Slo[sb + (xs >> 8)];
                 }
                 acc = a64;
             } else if (!wide) {
-                for (int i = 0; i < nsplit; i++) {
-                    const uint32_t xs = L.term_xs[tb + i];
+                for (int i = 0; i < n4; i += 4) {
+                    uint32_t xs[4];
+                    uint64_t xv[4], sv[4];
+#pragma unroll
+                    for (int j = 0; j < 4; j++) xs[j] = txs[i + j];
+#pragma unroll
+                    for (int j = 0; j < 4; j++) { xv[j] = Xlo[xb + (xs[j] & 0xffu)]; sv[j] = Slo[sb + (xs[j] >> 8)]; }
+#pragma unroll
+                    for (int j = 0; j < 4; j++) acc += (u128)xv[j] * sv[j];
+                }
+                for (int i = n4; i < nsplit; i++) {
+                    const uint32_t xs = txs[i];
                     acc += (u128)Xlo[xb + (xs & 0xffu)] * Slo[sb + (xs >> 8)];
                 }
             } else if (!Xhi) {
                 // own counts in 64 bits, neighbour sums in 128
-                for (int i = 0; i < nsplit; i++) {
-                    const uint32_t xs = L.term_xs[tb + i];
+                for (int i = 0; i < n4; i += 4) {
+                    uint32_t xs[4];
+                    uint64_t xv[4], sl[4], sh2[4];
+#pragma unroll
+                    for (int j = 0; j < 4; j++) xs[j] = txs[i + j];
+#pragma unroll
+                    for (int j = 0; j < 4; j++) {
+                        const int si = sb + (int)(xs[j] >> 8);
+                        xv[j] = Xlo[xb + (xs[j] & 0xffu)];
+                        sl[j] = Slo[si];
+                        sh2[j] = Shi[si];
+                    }
+#pragma unroll
+                    for (int j = 0; j < 4; j++) acc += mul_64x128(xv[j], mk128(sl[j], sh2[j]));
+                }
+                for (int i = n4; i < nsplit; i++) {
+                    const uint32_t xs = txs[i];
                     const int xi = xb + (int)(xs & 0xffu), si = sb + (int)(xs >> 8);
                     acc += mul_64x128(Xlo[xi], mk128(Slo[si], Shi[si]));
                 }
             } else {
                 for (int i = 0; i < nsplit; i++) {
-                    const uint32_t xs = L.term_xs[tb + i];
+                    const uint32_t xs = txs[i];
                     const int xi = xb + (int)(xs & 0xffu), si = sb + (int)(xs >> 8);
                     u128 x = mk128(Xlo[xi], Xhi[xi]), s = mk128(Slo[si], Shi[si]);
                     acc += x * s;
@@ -2159,7 +2199,9 @@ static scc_status gather_stats(scc_table *T)
     const int64_t n = T->n;
     hipStream_t st = T->stream;
     GraphView g{n, T->row_ptr, T->col_idx, T->colors};
-    unsigned long long *acc = (unsigned long long *)T->mem.get(64);
+    // one counter per level 0..k (the combine pass fills all of them)
+    constexpr size_t ACC_BYTES = (SCC_KMAX + 1) * sizeof(unsigned long long);
+    unsigned long long *acc = (unsigned long long *)T->mem.get(ACC_BYTES);
     if (!acc) return set_error(SCC_ENOMEM, "stats");
     for (int hs = 2; hs < T->k; hs++) {
         if (!T->S[hs].M) { T->gather_bytes[hs] = 0; continue; }   // not built (round skipping)
@@ -2173,7 +2215,7 @@ static scc_status gather_stats(scc_table *T)
         T->gather_bytes[hs] = (double)b;
     }
     // the combine of every level and the level-k totals, in one counting pass
-    HIP_TRY(hipMemsetAsync(acc, 0, 64, st));
+    HIP_TRY(hipMemsetAsync(acc, 0, ACC_BYTES, st));
     CombineBytesArgs A{};
     A.g = g; A.k = T->k; A.zero = T->rooting == SCC_ROOT_ZERO;
     for (int h = 2; h <= T->k; h++) A.lev[h] = view(T->lev[h]);
@@ -2184,7 +2226,8 @@ static scc_status gather_stats(scc_table *T)
     }
     if (n) hipLaunchKernelGGL(k_combine_bytes, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, A, acc);
     unsigned long long cb[SCC_KMAX + 1] = {0};
-    HIP_TRY(hipMemcpyAsync(cb, acc, sizeof cb, hipMemcpyDeviceToHost, st));
+    static_assert(sizeof cb == ACC_BYTES, "one counter per level");
+    HIP_TRY(hipMemcpyAsync(cb, acc, ACC_BYTES, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     for (int h = 2; h <= T->k; h++) T->combine_bytes[h] = (double)cb[h];
     T->totals_bytes = (double)cb[0];

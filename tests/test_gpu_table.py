@@ -279,7 +279,8 @@ def test_k8_counts_beyond_64_bits():
         print(f"two hubs: mode {mode} equal", flush=True)
 
 
-def test_combine_bytes_match_their_definition():
+@pytest.mark.parametrize("k,n,m", [(5, 3000, 12000), (8, 600, 1500)])
+def test_combine_bytes_match_their_definition(k, n, m):
     # scc_combine_bytes against its definition from the exported records: at
     # level h, every vertex that has level h reads its own records of levels
     # 2..h-1 (10 B an entry), its dense neighbour sums of levels 1..h-1 (8 B an
@@ -287,8 +288,7 @@ def test_combine_bytes_match_their_definition():
     # k at colour-0 vertices only; the totals read level k and write 32 B a vertex
     from math import comb
     S = scc()
-    g = gg.erdos_renyi(3000, 12000, seed=71)
-    k = 5
+    g = gg.erdos_renyi(n, m, seed=71)
     colors = gg.colors(g.n, k, seed=72)
     gt = S.Table(S.DeviceGraph.from_graph(g), colors, k)
     assert all(gt.info().wide_vertices[h] == 0 for h in range(9))
