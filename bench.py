@@ -409,6 +409,10 @@ def run_batching(a):
     print(json.dumps(out), flush=True)
 
 
+SMALL_REQUEST = 1 << 14   # serving: requests of at most this many samples go first, whole
+SMALL_STEP = 1 << 16      # serving: step size while a small request runs
+
+
 def serving_tables():
     """Three Chung-Lu graphs, n = 2e6, m = 3e7, exponents 2.1 / 2.4 / 2.8, w_max = 1e5, k = 7."""
     import graphgen as gg
@@ -463,6 +467,7 @@ def drive(srv, trace, rate, sessions, window, keep_every=0):
         q.put(None)
 
     lat = {"uniform": [], "ags": []}
+    by_size = {}
     kept = []
 
     def waiter():
@@ -479,6 +484,7 @@ def drive(srv, trace, rate, sessions, window, keep_every=0):
             if keep:
                 kept.append((i, r["verts"], r["parent"], r["cls"]))
             lat[kind].append(r["t_done"] - r["t_submit"])
+            by_size.setdefault(size_bucket(trace[i]["n"]), []).append(r["t_done"] - r["t_submit"])
             srv.release(rid)
             done += 1
             if done % 250 == 0:
@@ -498,7 +504,17 @@ def drive(srv, trace, rate, sessions, window, keep_every=0):
             st[f"{kind}_p50_ms"] = 1e3 * xs[max(0, int(0.5 * len(xs) + 0.5) - 1)]
             st[f"{kind}_p99_ms"] = 1e3 * xs[max(0, min(len(xs), int(0.99 * len(xs) + 0.5)) - 1)]
     st["samples_per_s"] = st["samples"] / st["span_s"] if st["span_s"] > 0 else 0.0
+    st["by_size"] = {}
+    for b, xs in sorted(by_size.items()):
+        xs = sorted(xs)
+        st["by_size"][b] = {"requests": len(xs), "p50_ms": 1e3 * xs[max(0, int(0.5 * len(xs) + 0.5) - 1)],
+                            "p99_ms": 1e3 * xs[max(0, min(len(xs), int(0.99 * len(xs) + 0.5)) - 1)]}
     return st
+
+
+def size_bucket(n):
+    """Request-size bucket for latency reports: 1e3-1e4, 1e4-1e5, 1e5-1e6 samples."""
+    return "1e3-1e4" if n < 10_000 else ("1e4-1e5" if n < 100_000 else "1e5-1e6")
 
 
 def run_serving(a):
@@ -521,15 +537,16 @@ def run_serving(a):
     opts = dict(hbm_budget=24 << 30, step_samples=a.serve_step, chunk=4096, max_active=512)
     cbar = 1000
 
-    def server(fifo, ags_weight=1.0, age_tau=0.0):
-        srv = scc.Server(tabs, fifo=fifo, ags_weight=ags_weight, age_tau=age_tau, **opts)
+    def server(fifo, ags_weight=1.0, age_tau=0.0, small=False):
+        extra = dict(small_request=SMALL_REQUEST, small_step=SMALL_STEP) if small else {}
+        srv = scc.Server(tabs, fifo=fifo, ags_weight=ags_weight, age_tau=age_tau, **opts, **extra)
         sessions = [srv.ags_open(t, cbar=cbar, seed=900 + t, stream_id=t) for t in range(len(tabs))]
         return srv, sessions
 
     # saturated rates: a burst of the first requests, all submitted at once, in each mode
     sat = {}
     for name, fifo in (("continuous", False), ("fifo", True)):
-        srv, sess = server(fifo, 1.0, 0.0 if fifo else 0.01)
+        srv, sess = server(fifo, 1.0, 0.0, small=not fifo)
         sat[name] = drive(srv, trace[:min(300, len(trace))], float("inf"), sess, 1e9)["samples_per_s"]
         srv.close()
         print(f"# saturated {name}: {sat[name] / 1e6:.1f} M samples/s", file=sys.stderr, flush=True)
@@ -542,10 +559,9 @@ def run_serving(a):
     res = {}
     # continuous: shares weighted by age (tau 10 ms), which bounds the tail of large
     # requests; the plain equal shares and heavier AGS rounds are reported beside it
-    for name, fifo, aw, tau in (("continuous", False, 1.0, 0.01), ("continuous_equal", False, 1.0, 0.0),
-                                ("continuous_ags16", False, 16.0, 0.0), ("continuous_age2ms", False, 1.0, 0.002),
-                                ("fifo", True, 1.0, 0.0)):
-        srv, sess = server(fifo, aw, tau)
+    for name, fifo, aw, tau, small in (("continuous", False, 1.0, 0.0, True), ("continuous_age10ms", False, 1.0, 0.01, False),
+                                       ("continuous_equal", False, 1.0, 0.0, False), ("fifo", True, 1.0, 0.0, False)):
+        srv, sess = server(fifo, aw, tau, small)
         res[name] = drive(srv, trace, rate, sess, a.window, keep_every=40 if name == "continuous" else 0)
         srv.close()
         r = res[name]
@@ -565,10 +581,10 @@ def run_serving(a):
                                                                                               cl.view(torch.int32))
     print(f"# {len(c['kept'])} served requests equal scc_sample alone: {alone_equal}", file=sys.stderr, flush=True)
     keep = ("completed", "samples", "steps", "span_s", "samples_per_s", "p50_ms", "p99_ms", "mean_ms", "max_ms",
-            "arena_peak", "uniform_p50_ms", "uniform_p99_ms", "ags_p50_ms", "ags_p99_ms")
+            "arena_peak", "uniform_p50_ms", "uniform_p99_ms", "ags_p50_ms", "ags_p99_ms", "by_size")
     out = {
         "metric": "DP table build s & colorful-treelet samples/sec, batched/served vs plain",
-        "value": c["samples_per_s"], "unit": "samples/s served (continuous batching with age-weighted shares, "
+        "value": c["samples_per_s"], "unit": "samples/s served (continuous batching, small requests first, "
                                              "Poisson arrivals at 0.7x saturation, submission to completion)",
         "n_gpus": 1, "steps": c["completed"], "warmup": 0, "ms_per_step": c["mean_ms"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u64/u128", "data": "synthetic",
@@ -580,10 +596,10 @@ def run_serving(a):
         "saturated_samples_per_s": sat["continuous"], "saturated_samples_per_s_fifo": sat["fifo"],
         "saturated_throughput_vs_fifo": sat["continuous"] / sat["fifo"] if sat["fifo"] > 0 else None,
         "continuous": {k: c[k] for k in keep}, "fifo": {k: f[k] for k in keep},
-        "age_tau_s": 0.01,
+        "policy": f"small requests (<= {SMALL_REQUEST} samples) first and whole, then submission order; steps "
+                  f"of {a.serve_step} samples, cut to {SMALL_STEP} while a small request runs",
+        "continuous_age_weighted_shares_10ms": {k: res["continuous_age10ms"][k] for k in keep},
         "continuous_equal_shares": {k: res["continuous_equal"][k] for k in keep},
-        "continuous_equal_ags_weight_16": {k: res["continuous_ags16"][k] for k in keep},
-        "continuous_age_tau_2ms": {k: res["continuous_age2ms"][k] for k in keep},
         "served_equal_alone": alone_equal, "served_checked": len(c["kept"]),
         "p99_speedup_vs_fifo": f["p99_ms"] / c["p99_ms"] if c["p99_ms"] > 0 else None,
         "p50_speedup_vs_fifo": f["p50_ms"] / c["p50_ms"] if c["p50_ms"] > 0 else None,

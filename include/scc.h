@@ -496,6 +496,12 @@ typedef struct {
     double age_tau;          /* > 0: a request's share also grows with its age, by the
                                 factor 1 + (seconds since submission) / age_tau, so that
                                 long-waiting requests finish first (tail latency); 0: off */
+    int64_t small_request;   /* > 0: requests of at most this many samples are small: each
+                                step takes the small requests first, whole, then the others in
+                                submission order (no shares); 0: shares as above */
+    int64_t small_step;      /* with small_request: a step that holds a small request is cut
+                                to this many samples (0: step_samples), so that small requests
+                                wait for short steps only */
 } scc_server_opts;
 
 enum { SCC_REQ_SAMPLE = 0, SCC_REQ_AGS_ROUND = 1 };

@@ -87,7 +87,8 @@ class _ServerOpts(C.Structure):
     _fields_ = [("tables", C.POINTER(C.c_void_p)), ("n_tables", C.c_int), ("hbm_budget", C.c_int64),
                 ("max_pending", C.c_int), ("max_active", C.c_int), ("step_samples", C.c_int64), ("chunk", C.c_int64),
                 ("grid", C.c_int), ("fifo", C.c_int), ("ags_weight", C.c_double), ("stream", C.c_void_p),
-                ("alloc", C.POINTER(_Allocator)), ("age_tau", C.c_double)]
+                ("alloc", C.POINTER(_Allocator)), ("age_tau", C.c_double), ("small_request", C.c_int64),
+                ("small_step", C.c_int64)]
 
 
 class _Request(C.Structure):
@@ -425,14 +426,16 @@ class Server:
 
     def __init__(self, tables, hbm_budget: int = 1 << 30, max_pending: int = 0, max_active: int = 0,
                  step_samples: int = 0, chunk: int = 0, grid: int = 0, fifo: bool = False, stream=None,
-                 use_torch_allocator: bool = True, ags_weight: float = 0.0, age_tau: float = 0.0):
+                 use_torch_allocator: bool = True, ags_weight: float = 0.0, age_tau: float = 0.0,
+                 small_request: int = 0, small_step: int = 0):
         self.tables = list(tables)
         arr = (C.c_void_p * len(self.tables))(*[t._h.value for t in self.tables])
         self._arr = arr
         opts = _ServerOpts(C.cast(arr, C.POINTER(C.c_void_p)), len(self.tables), int(hbm_budget), max_pending,
                            max_active, step_samples, chunk, grid, 1 if fifo else 0, float(ags_weight),
                            C.c_void_p(stream.cuda_stream) if stream is not None else None,
-                           C.pointer(TORCH_ALLOCATOR) if use_torch_allocator else None, float(age_tau))
+                           C.pointer(TORCH_ALLOCATOR) if use_torch_allocator else None, float(age_tau),
+                           int(small_request), int(small_step))
         h = _P()
         _check(_lib.scc_server_create(C.byref(opts), C.byref(h)))
         self._h = h

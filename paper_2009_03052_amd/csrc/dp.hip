@@ -920,6 +920,7 @@ struct CombineArgs {
     const u128 *M[SCC_KMAX + 1];
     const int16_t *key_xidx;              // [k * nkeys]
     int W;                                // slot capacity = W_h
+    int late_dma;                         // listing passes stage the sums after the width test
     uint16_t *slot_key;
     uint64_t *slot_lo, *slot_hi;          // slot_hi may be null (no wide vertex)
     uint32_t *meta;
@@ -1173,9 +1174,16 @@ __device__ inline void combine_vertex_pf(const CombineArgs &A, int64_t v, uint64
     uint64_t *Xlo = lo_area, *Slo = lo_area + XT;
     // own_hi false: hi_area holds the neighbour sums' high words only
     uint64_t *Xhi = own_hi ? hi_area : nullptr, *Shi = own_hi && hi_area ? hi_area + XT : hi_area;
-    if (DMA)
+    // the neighbour sums go to LDS at once, unless this is a listing pass (no
+    // hi_area) at a level where many vertices will be listed for 128 bits
+    // (late_dma): there the vertex first learns whether it stays (below), so
+    // that a listed vertex loads nothing it will load again
+    auto dma_sums = [&]() {
         for (int hs = 1; hs <= phi; hs++)
             if (A.Slo[hs]) lds_dma_words(A.Slo[hs] + (size_t)v * L.WS[hs], Slo + L.soff[hs], L.WS[hs]);
+    };
+    const bool late = DMA && !hi_area && A.late_dma;
+    if (DMA && !late) dma_sums();
     if (!A.zero_only) cv = A.g.colors[v];
     // lane q: handle of v's level-q record (q >= 2) and M_q(v) (0: sums not built)
     // packed levels of one bitmap word also give each lane q that word: bit l marks
@@ -1254,6 +1262,7 @@ __device__ inline void combine_vertex_pf(const CombineArgs &A, int64_t v, uint64
         }
         return;
     }
+    if (late) dma_sums();
     const bool stage_xhi = wide && Xhi;
     for (int i = lane; i < XT; i += WAVE) {
         Xlo[i] = 0;
@@ -1273,7 +1282,10 @@ __device__ inline void combine_vertex_pf(const CombineArgs &A, int64_t v, uint64
         if (wide) {
             const bool sw128 = hi64(A.M[hs][v]) != 0;
             const uint64_t *gh = sw128 ? A.Shi[hs] + hi_row(A.Shrow[hs], v) * ws : nullptr;
-            for (int i = lane; i < ws; i += WAVE) Shi[L.soff[hs] + i] = sw128 ? gh[i] : 0;
+            uint64_t *dst = Shi + L.soff[hs];
+            if (DMA && sw128) lds_dma_words(gh, dst, ws);
+            else
+                for (int i = lane; i < ws; i += WAVE) dst[i] = sw128 ? gh[i] : 0;
         }
     }
     __syncthreads();
@@ -1309,7 +1321,7 @@ template <int PMAX>
 __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(8, 8))) k_combine(CombineArgs A, int *wide_list, int *wide_count)
 {
     extern __shared__ uint64_t sm[];
-    if ((int64_t)blockIdx.x < A.g.n) combine_vertex_pf<false, PMAX, false>(A, blockIdx.x, sm, nullptr, wide_list, wide_count);
+    if ((int64_t)blockIdx.x < A.g.n) combine_vertex_pf<false, PMAX, true>(A, blockIdx.x, sm, nullptr, wide_list, wide_count);
 }
 
 // the listed vertices only (level k under zero-rooting: the colour-0 vertices)
@@ -1317,7 +1329,7 @@ template <int PMAX>
 __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(8, 8))) k_combine_list(CombineArgs A, const int32_t *rows, int *wide_list, int *wide_count)
 {
     extern __shared__ uint64_t sm[];
-    combine_vertex_pf<false, PMAX, false>(A, __builtin_amdgcn_readfirstlane(rows[blockIdx.x]), sm, nullptr, wide_list, wide_count);
+    combine_vertex_pf<false, PMAX, true>(A, __builtin_amdgcn_readfirstlane(rows[blockIdx.x]), sm, nullptr, wide_list, wide_count);
 }
 
 // the listed vertices, with high words in LDS as well. OWN: vertices whose own
@@ -1333,7 +1345,7 @@ __global__ void __launch_bounds__(WAVE) k_combine_wide(CombineArgs A, const int 
     const int lo_words = A.L->xoff[A.h] + A.L->soff[A.h];
     for (int i = blockIdx.x; i < cnt; i += gridDim.x) {
         const int v = __builtin_amdgcn_readfirstlane(OWN ? wide_list[A.g.n - 1 - i] : wide_list[i]);
-        combine_vertex_pf<false, SCC_KMAX - 1, false>(A, v, sm, sm + lo_words, nullptr, nullptr, OWN);
+        combine_vertex_pf<false, SCC_KMAX - 1, true>(A, v, sm, sm + lo_words, nullptr, nullptr, OWN);
         __syncthreads();
     }
 }
@@ -2009,6 +2021,7 @@ static scc_status build_levels(scc_table *T)
 
     for (int h = 2; h <= k; h++) {
         const bool last = h == k;
+        int64_t top_wide_rows = 0;   // rows of the sums gathered now whose high words exist
         HIP_TRY(hipEventRecord(ev[h][0], st));
         HIP_TRY(hipMemsetAsync(err, 0, 16, st));   // flags and the level's counts of listed rows
         const int hs = h - 1;   // neighbour sums needed now
@@ -2066,6 +2079,7 @@ static scc_status build_levels(scc_table *T)
             int nw = 0;
             HIP_TRY(hipMemcpyAsync(&nw, err + 2, 4, hipMemcpyDeviceToHost, st));
             HIP_TRY(hipStreamSynchronize(st));
+            top_wide_rows = (int64_t)nw + nhub;
             if (nw) {
                 uint64_t *hi = (uint64_t *)T->alloc((size_t)(nhub + nw) * row_bytes + 8);
                 if (!hi) return set_error(SCC_ENOMEM, "neighbour sums level %d, high words", hs);
@@ -2115,6 +2129,9 @@ static scc_status build_levels(scc_table *T)
             C.Slo[q] = T->S[q].lo; C.Shi[q] = T->S[q].hi; C.Shrow[q] = T->S[q].hrow; C.M[q] = T->S[q].M;
         }
         C.key_xidx = T->key_xidx; C.W = HL.W[h];
+        // many rows of the top sum level with high words: most vertices will be
+        // listed for the 128-bit combine, so the listing pass stages late
+        C.late_dma = 8 * top_wide_rows > n;
         C.slot_key = slot_key; C.slot_lo = slot_lo; C.slot_hi = slot_hi;
         C.meta = meta; C.Nout = Nsc; C.err = err;
         const size_t lds = (size_t)(HL.xoff[h] + HL.soff[h]) * 8;
@@ -2944,6 +2961,7 @@ static scc_status batch_launch(std::vector<BatchInstHost> &H, int tile, int hub_
             for (int q = 2; q < h; q++) C.lev[q] = slot_src(q);
             for (int q = 1; q < h; q++) { C.Slo[q] = T->S[q].lo; C.Shi[q] = T->S[q].hi; C.M[q] = T->S[q].M; }
             C.key_xidx = T->key_xidx; C.W = HL.W[h];
+            C.late_dma = 0;   // the batched worker stages high words itself: nothing is listed
             C.slot_key = H[i].skey[h]; C.slot_lo = H[i].slo[h]; C.slot_hi = H[i].shi[h];
             C.meta = H[i].meta[h]; C.Nout = H[i].N[h];
         }

@@ -108,6 +108,7 @@ struct scc_server {
     void admit_locked();
     void activate_rounds_locked();
     bool build_step_locked(int b);
+    void add_chunk_locked(StepBuf &B, int64_t id, int64_t c);
     scc_status launch_step(int b);
     void complete_step_locked(int b, std::unique_lock<std::mutex> &lk);
     void run();
@@ -181,6 +182,25 @@ bool scc_server::build_step_locked(int b)
         const int64_t id = *std::min_element(cand.begin(), cand.end());
         cand.assign(1, id);
     }
+    if (o.small_request > 0 && !o.fifo) {
+        // small requests first (whole), then the others in arrival order (ids
+        // increase with submission), each taking what the step still holds; a
+        // step holding a small request is cut to small_step samples, so that a
+        // small request waits for short steps only
+        std::vector<int64_t> small, large;
+        for (int64_t id : cand) (reqs[id].q.n <= o.small_request ? small : large).push_back(id);
+        std::sort(small.begin(), small.end());
+        std::sort(large.begin(), large.end());
+        const int64_t cap = !small.empty() && o.small_step > 0 ? std::min(o.small_step, o.step_samples) : o.step_samples;
+        small.insert(small.end(), large.begin(), large.end());
+        for (int64_t id : small) {
+            if (B.total >= cap) break;
+            Request &r = reqs[id];
+            const int64_t c = std::min(cap - B.total, r.q.n - r.assigned);
+            add_chunk_locked(B, id, c);
+        }
+        return true;
+    }
     // weighted shares of the step: an AGS round (which holds up its session's later
     // rounds) weighs ags_weight, a sample request 1, times 1 + age / age_tau when
     // age weighting is on; every share is at least `chunk`
@@ -199,32 +219,39 @@ bool scc_server::build_step_locked(int b)
         const int64_t quota = o.fifo ? INT64_MAX
                                      : std::max<int64_t>(o.chunk, (int64_t)((double)o.step_samples * w / wsum));
         const int64_t c = std::min(quota, r.q.n - r.assigned);
-        if (r.assigned == 0) r.t_start = now_s(t0);
-        const int a = B.nch;
-        SampleArgs A = base[r.q.table][r.shape + 1];
-        A.seed = r.seed; A.stream = r.stream; A.first = r.first; A.nsamp = r.q.n;
-        A.verts = r.verts; A.par = r.par; A.err = B.derr;
-        B.hargs[a] = A;
-        ServeClassArgs C{};
-        const scc_table *T = tables[r.q.table];
-        C.g = GraphView{T->n, T->row_ptr, T->col_idx, T->colors};
-        C.k = T->k;
-        C.nclass = (uint32_t)nclass[r.q.table];
-        C.lut = lut[r.q.table];
-        C.verts = r.verts;
-        C.cls = r.cls;
-        C.hist = r.q.kind == SCC_REQ_AGS_ROUND ? sessions[r.q.session].dhist : nullptr;
-        B.hcls[a] = C;
-        B.hch[a] = ServeChunk{a, 0, r.assigned, c};
-        B.total += c;
-        B.hend[a] = B.total;
-        B.req.push_back(id);
-        B.nch++;
-        r.assigned += c;
+        add_chunk_locked(B, id, c);
         if (B.total >= o.step_samples && !o.fifo) break;
     }
     rr = (rr + 1) % std::max<size_t>(1, nc);
     return true;
+}
+
+// the next c rows of request id as one chunk of step buffer B
+void scc_server::add_chunk_locked(StepBuf &B, int64_t id, int64_t c)
+{
+    Request &r = reqs[id];
+    if (r.assigned == 0) r.t_start = now_s(t0);
+    const int a = B.nch;
+    SampleArgs A = base[r.q.table][r.shape + 1];
+    A.seed = r.seed; A.stream = r.stream; A.first = r.first; A.nsamp = r.q.n;
+    A.verts = r.verts; A.par = r.par; A.err = B.derr;
+    B.hargs[a] = A;
+    ServeClassArgs C{};
+    const scc_table *T = tables[r.q.table];
+    C.g = GraphView{T->n, T->row_ptr, T->col_idx, T->colors};
+    C.k = T->k;
+    C.nclass = (uint32_t)nclass[r.q.table];
+    C.lut = lut[r.q.table];
+    C.verts = r.verts;
+    C.cls = r.cls;
+    C.hist = r.q.kind == SCC_REQ_AGS_ROUND ? sessions[r.q.session].dhist : nullptr;
+    B.hcls[a] = C;
+    B.hch[a] = ServeChunk{a, 0, r.assigned, c};
+    B.total += c;
+    B.hend[a] = B.total;
+    B.req.push_back(id);
+    B.nch++;
+    r.assigned += c;
 }
 
 scc_status scc_server::launch_step(int b)

@@ -6,7 +6,7 @@ per table. Each sample request must equal scc_sample / scc_classify called on
 its own with the same (table, shape, seed, stream, first index), and one is
 also checked against the oracle; each AGS session must pick the shapes and
 reach the counts of scc_ags with the same round size (and of the oracle's AGS).
-The first-in first-out mode and age-weighted shares must give the same rows. Admission: a request that
+The first-in first-out mode, age-weighted shares and small-first steps must give the same rows. Admission: a request that
 does not fit the budget waits until earlier outputs are released; a request
 larger than the budget is refused with ENOMEM, and a full queue with EBUSY.
 """
@@ -140,17 +140,44 @@ def test_fifo_mode_gives_the_same_rows():
     mix = S.Server([t[3] for t in tabs], hbm_budget=32 << 20, step_samples=2048, chunk=128)
     fifo = S.Server([t[3] for t in tabs], hbm_budget=32 << 20, fifo=True)
     aged = S.Server([t[3] for t in tabs], hbm_budget=32 << 20, step_samples=2048, chunk=128, age_tau=0.002)
+    small = S.Server([t[3] for t in tabs], hbm_budget=32 << 20, step_samples=2048, small_request=600,
+                     small_step=512)
     a = _run(mix, reqs, [], 0, 1)
     b = _run(fifo, reqs, [], 0, 1)
     c = _run(aged, reqs, [], 0, 1)
-    for ra, rb, rc in zip(a, b, c):
+    d = _run(small, reqs, [], 0, 1)
+    for ra, rb, rc, rd in zip(a, b, c, d):
         assert np.array_equal(ra["verts"].cpu().numpy(), rb["verts"].cpu().numpy())
         assert np.array_equal(ra["parent"].cpu().numpy(), rb["parent"].cpu().numpy())
         assert np.array_equal(ra["verts"].cpu().numpy(), rc["verts"].cpu().numpy())
+        assert np.array_equal(ra["verts"].cpu().numpy(), rd["verts"].cpu().numpy())
+        assert np.array_equal(ra["parent"].cpu().numpy(), rd["parent"].cpu().numpy())
     assert fifo.stats()["steps"] >= len(reqs)
-    mix.close()
-    fifo.close()
-    aged.close()
+    for srv in (mix, fifo, aged, small):
+        srv.close()
+
+
+def test_small_first_mode_with_ags_rounds():
+    # small requests first, then submission order, steps cut while a small one
+    # runs: rows and AGS sessions as with shares
+    S = scc()
+    tabs = _tables()
+    reqs = _requests(tabs, 30, seed=13)
+    srv = S.Server([t[3] for t in tabs], hbm_budget=48 << 20, step_samples=4096, small_request=1000, small_step=1024)
+    sessions = [srv.ags_open(t, cbar=15, seed=300 + t, stream_id=t) for t in range(len(tabs))]
+    rounds, rsize = 3, 700
+    res = _run(srv, reqs, sessions, rounds, rsize)
+    for q, r in zip(reqs, res):
+        v, p, cls = _alone(tabs[q["table"]][3], q)
+        assert np.array_equal(r["verts"].cpu().numpy(), v) and np.array_equal(r["parent"].cpu().numpy(), p), q
+        if q["classify"]:
+            assert np.array_equal(r["cls"].cpu().numpy(), cls), q
+    for t, sid in enumerate(sessions):
+        got = srv.ags_result(sid, t)
+        ref = tabs[t][3].ags(cbar=15, round_size=rsize, budget=rounds * rsize, seed=300 + t, stream_id=t)
+        for key in ("hits", "w", "n_j", "round_shapes"):
+            assert np.array_equal(got[key], ref[key]), (t, key)
+    srv.close()
 
 
 def test_admission_by_budget():
