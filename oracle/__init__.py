@@ -21,6 +21,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
+_SRC16 = os.path.join(_HERE, "oracle16.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 ROOT_ZERO = 0
@@ -40,7 +41,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle with gcc (plain -O2, no fast-math, no contraction)."""
     if force or not os.path.exists(_LIB):
         subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-shared", "-fPIC",
-                               "-ffp-contract=off", _SRC, "-o", _LIB + ".tmp"])
+                               "-ffp-contract=off", _SRC, _SRC16, "-o", _LIB + ".tmp"])
         os.replace(_LIB + ".tmp", _LIB)
     return _LIB
 
@@ -51,7 +52,7 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(os.path.getmtime(_SRC), os.path.getmtime(_SRC16)):
             build()
         L = C.CDLL(_LIB)
         P = C.c_void_p
@@ -86,6 +87,12 @@ def lib():
             "orc_spanning_trees_by_shape": (C.c_int, [u32, C.c_int, P]),
             "orc_ags": (C.c_int, [P, i64, i64, i64, u64, u64, P, P, P, P, P]),
             "orc_estimate": (C.c_int, [P, P, P, i64, C.c_double, P, P]),
+            "orc16_last_error": (C.c_char_p, []),
+            "orc16_build": (C.c_int, [i64, P, P, P, C.c_int, C.c_int, C.POINTER(P)]),
+            "orc16_table_free": (None, [P]),
+            "orc16_level_nnz": (i64, [P, C.c_int]),
+            "orc16_export_level": (C.c_int, [P, C.c_int, P, P, P, P]),
+            "orc16_total": (None, [P, P]),
             "orc_balanced_rank": (C.c_int, [C.c_int, C.c_int]),
             "orc_balanced_orbit": (C.c_int, [C.c_int, C.c_int]),
             "orc_star_class": (C.c_int, [C.c_int]),
@@ -252,6 +259,53 @@ class Table:
         _check(lib().orc_ags(self._h, cbar, round_size, budget, seed, stream,
                              _p(hits), _p(w), _p(nj), _p(shapes), C.byref(nr)))
         return {"hits": hits, "w": w, "n_j": nj, "round_shapes": shapes[:nr.value]}
+
+
+class Table16:
+    """The oracle's sparse table for k <= 16 (oracle16.c): keys s_T << 16 | C."""
+
+    def __init__(self, g, colors: np.ndarray, k: int, rooting: int = ROOT_ZERO):
+        self.g, self.k, self.rooting = g, k, rooting
+        self.colors = np.ascontiguousarray(colors, dtype=np.uint8)
+        self._h = C.c_void_p()
+        st = lib().orc16_build(g.n, _p(g.row_ptr), _p(g.col_idx), _p(self.colors), k, rooting, C.byref(self._h))
+        if st != OK:
+            raise OracleError(st, lib().orc16_last_error().decode())
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().orc16_table_free(h)
+            self._h = None
+
+    def level_nnz(self, h: int) -> int:
+        return int(lib().orc16_level_nnz(self._h, h))
+
+    def export_level(self, h: int):
+        """(off int64[n+1], key uint64[nnz], lo uint64[nnz], hi uint64[nnz])."""
+        nnz = self.level_nnz(h)
+        off = np.zeros(self.g.n + 1, np.int64)
+        key = np.zeros(max(nnz, 1), np.uint64)
+        lo = np.zeros(max(nnz, 1), np.uint64)
+        hi = np.zeros(max(nnz, 1), np.uint64)
+        st = lib().orc16_export_level(self._h, h, _p(off), _p(key), _p(lo), _p(hi))
+        if st != OK:
+            raise OracleError(st, lib().orc16_last_error().decode())
+        return off, key[:nnz], lo[:nnz], hi[:nnz]
+
+    def level_dict(self, h: int) -> dict:
+        """{(v, key): count} of level h."""
+        off, key, lo, hi = self.export_level(h)
+        return {(v, int(key[q])): _u128(lo[q], hi[q]) for v in range(self.g.n) for q in range(off[v], off[v + 1])}
+
+    def total(self) -> int:
+        t = np.zeros(2, np.uint64)
+        lib().orc16_total(self._h, _p(t))
+        return _u128(t[0], t[1])
+
+
+def key16(shape_bits: int, mask: int) -> int:
+    return (shape_bits << 16) | mask
 
 
 def estimate(tab: "Table", hits, n: int = 0, w=None, pk: float = 0.0):

@@ -2,7 +2,8 @@
  * Driver for an AddressSanitizer / UndefinedBehaviorSanitizer build of the
  * oracle (oracle.c, test infrastructure): every entry point on small seeded
  * graphs, k = 2..8, all three rootings (classification, AGS and estimates up
- * to k = 7: the k = 8 class catalog alone takes minutes under the sanitizers).
+ * to k = 7: the k = 8 class catalog alone takes minutes under the sanitizers),
+ * and the sparse k <= 16 oracle (oracle16.c) for k = 2..12 and both rootings.
  * Exits 0 when every call succeeds and the sanitizers report nothing (they
  * abort on the first finding).
  */
@@ -34,6 +35,13 @@ int orc_estimate(const orc_table *T, const int64_t *hits, const double *w, int64
                  double *g);
 int orc_color_biased(int64_t n, int k, uint32_t L, uint64_t seed, uint64_t stream, uint8_t *out);
 int orc_check_csr(int64_t n, const int64_t *row_ptr, const int32_t *col_idx);
+typedef struct orc16_table orc16_table;
+int orc16_build(int64_t n, const int64_t *row_ptr, const int32_t *col_idx, const uint8_t *colors, int k, int rooting,
+                orc16_table **out);
+void orc16_table_free(orc16_table *T);
+int64_t orc16_level_nnz(const orc16_table *T, int h);
+int orc16_export_level(const orc16_table *T, int h, int64_t *off, uint64_t *key, uint64_t *lo, uint64_t *hi);
+void orc16_total(const orc16_table *T, uint64_t t[2]);
 
 static uint64_t rng = 88172645463325252ull;
 static uint64_t next(void) { rng ^= rng << 13; rng ^= rng >> 7; rng ^= rng << 17; return rng; }
@@ -115,6 +123,28 @@ int main(void)
         uint8_t *bc = malloc(n);
         CHECK(orc_color_biased(n, k, 1u << 26, 5, 0, bc));
         free(bc); free(col); free(rp); free(ci);
+    }
+    for (int k = 2; k <= 12; k++) {
+        const int n = 18;
+        int64_t *rp; int32_t *ci;
+        make_graph(n, 2 * n, 5, &rp, &ci);
+        uint8_t *col = malloc(n);
+        for (int v = 0; v < n; v++) col[v] = (uint8_t)(next() % k);
+        for (int rooting = 0; rooting <= 1; rooting++) {
+            orc16_table *T = NULL;
+            CHECK(orc16_build(n, rp, ci, col, k, rooting, &T));
+            for (int h = 1; h <= k; h++) {
+                int64_t nnz = orc16_level_nnz(T, h);
+                int64_t *off = malloc(sizeof(int64_t) * (n + 1));
+                uint64_t *key = malloc(8 * (nnz + 1)), *lo = malloc(8 * (nnz + 1)), *hi = malloc(8 * (nnz + 1));
+                CHECK(orc16_export_level(T, h, off, key, lo, hi));
+                free(off); free(key); free(lo); free(hi);
+            }
+            uint64_t t[2];
+            orc16_total(T, t);
+            orc16_table_free(T);
+        }
+        free(col); free(rp); free(ci);
     }
     printf("oracle checks done\n");
     return 0;

@@ -1,8 +1,8 @@
 """AddressSanitizer and UndefinedBehaviorSanitizer builds of host code, run on the CPU.
 
 * the oracle (oracle/oracle.c) under a driver that calls every entry point on
-  small seeded graphs for k = 2..8 and all three rootings
-  (tests/sanitize/oracle_checks.c);
+  small seeded graphs for k = 2..8 and all three rootings, and the sparse
+  k <= 16 oracle (oracle/oracle16.c) for k = 2..12 (tests/sanitize/oracle_checks.c);
 * the library's host runtime: the treelet algebra and per-k lookup tables of
   treelets.cpp with every index the kernels take from them checked against
   the staging layout, the serving arena's first-fit allocator under random
@@ -38,7 +38,7 @@ def _run(cmd, exe):
 def test_oracle_under_sanitizers(tmp_path):
     exe = str(tmp_path / "oracle_checks")
     out = _run(["gcc", "-std=gnu11", *SAN, os.path.join(ROOT, "tests", "sanitize", "oracle_checks.c"),
-                os.path.join(ROOT, "oracle", "oracle.c"), "-o", exe], exe)
+                os.path.join(ROOT, "oracle", "oracle.c"), os.path.join(ROOT, "oracle", "oracle16.c"), "-o", exe], exe)
     assert "oracle checks done" in out
 
 
