@@ -928,6 +928,7 @@ struct CombineArgs {
     int *err;                             // [0]: overflow
 };
 
+template <int ILP>
 __device__ inline void combine_outputs(const CombineArgs &A, int64_t v, int cv, const uint64_t *Xlo,
                                        const uint64_t *Slo, const uint64_t *Xhi, const uint64_t *Shi, bool owide,
                                        bool wide);
@@ -1005,7 +1006,7 @@ __device__ inline void combine_vertex(const CombineArgs &A, int64_t v, uint64_t 
         }
     }
     __syncthreads();
-    combine_outputs(A, v, cv, Xlo, Slo, Xhi, Shi, owide, wide);
+    combine_outputs<4>(A, v, cv, Xlo, Slo, Xhi, Shi, owide, wide);
 }
 
 // The outputs of vertex v at level h from its staged counts (X) and neighbour
@@ -1015,6 +1016,10 @@ __device__ inline void combine_vertex(const CombineArgs &A, int64_t v, uint64_t 
 // x s modulo 2^128 (the vertex's bound keeps every product below it)
 __device__ inline u128 mul_64x128(uint64_t x, u128 s) { return (u128)x * lo64(s) + ((u128)(x * hi64(s)) << 64); }
 
+// ILP = 4: an output's terms four at a time (the level kernels); ILP = 1: one
+// at a time (the batched worker, whose register budget has no room for the
+// four-wide form)
+template <int ILP>
 __device__ inline void combine_outputs(const CombineArgs &A, int64_t v, int cv, const uint64_t *Xlo,
                                        const uint64_t *Slo, const uint64_t *Xhi, const uint64_t *Shi, bool owide,
                                        bool wide)
@@ -1043,7 +1048,7 @@ __device__ inline void combine_outputs(const CombineArgs &A, int64_t v, int cv, 
             // operands, are requested before any product, so that the loads of
             // a group overlap instead of one latency per term
             const uint16_t *txs = L.term_xs + tb;
-            const int n4 = nsplit & ~3;
+            const int n4 = ILP >= 4 ? (nsplit & ~3) : 0;
             if (!owide) {
                 uint64_t a64 = 0;
                 for (int i = 0; i < n4; i += 4) {
@@ -1107,9 +1112,12 @@ __device__ inline void combine_outputs(const CombineArgs &A, int64_t v, int cv, 
                 }
             }
             const uint32_t beta = (uint32_t)((d >> 56) & 0x7fu);
-            // beta divides the sum exactly (Eq. (1) counts each copy beta times)
-            if (beta != 1) val = owide ? div_exact_small(acc, beta) : (u128)div_exact_small64(lo64(acc), beta);
-            else val = acc;
+            // beta divides the sum exactly (Eq. (1) counts each copy beta times): the
+            // level kernels divide by a modular inverse; the batched worker keeps
+            // the long division, which needs fewer registers there
+            if (beta == 1) val = acc;
+            else if (ILP >= 4) val = owide ? div_exact_small(acc, beta) : (u128)div_exact_small64(lo64(acc), beta);
+            else val = div_small(acc, beta);
         }
         const bool nz = val != 0;
         const uint64_t bal = __ballot(nz);
@@ -1154,7 +1162,10 @@ __device__ inline void wait_vm_all() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 // products instead of one per dependent step. PMAX bounds the levels unrolled
 // (PMAX >= h - 1); longer rows and records are finished by loops, and high
 // words (wide) are staged by loops as well.
-template <bool SLOTS, int PMAX, bool DMA>
+// DMA: the neighbour sums reach lo_area (LDS) by direct-to-LDS loads; HI_LDS:
+// hi_area is LDS too, so their high words may go the same way (the batched
+// worker's hi_area is global scratch: filled by ordinary stores)
+template <bool SLOTS, int PMAX, bool DMA, bool HI_LDS = false>
 __device__ inline void combine_vertex_pf(const CombineArgs &A, int64_t v, uint64_t *lo_area, uint64_t *hi_area,
                                          int *wide_list, int *wide_count, bool own_hi = true)
 {
@@ -1283,7 +1294,7 @@ __device__ inline void combine_vertex_pf(const CombineArgs &A, int64_t v, uint64
             const bool sw128 = hi64(A.M[hs][v]) != 0;
             const uint64_t *gh = sw128 ? A.Shi[hs] + hi_row(A.Shrow[hs], v) * ws : nullptr;
             uint64_t *dst = Shi + L.soff[hs];
-            if (DMA && sw128) lds_dma_words(gh, dst, ws);
+            if (DMA && HI_LDS && sw128) lds_dma_words(gh, dst, ws);
             else
                 for (int i = lane; i < ws; i += WAVE) dst[i] = sw128 ? gh[i] : 0;
         }
@@ -1310,7 +1321,7 @@ __device__ inline void combine_vertex_pf(const CombineArgs &A, int64_t v, uint64
     }
     if (DMA) wait_vm_all();
     __syncthreads();
-    combine_outputs(A, v, cv, Xlo, Slo, stage_xhi ? Xhi : nullptr, Shi, owide, wide);
+    combine_outputs<SLOTS ? 1 : 4>(A, v, cv, Xlo, Slo, stage_xhi ? Xhi : nullptr, Shi, owide, wide);
 }
 
 // one workgroup per vertex, low words in LDS; vertices that need 128 bits are
@@ -1345,7 +1356,7 @@ __global__ void __launch_bounds__(WAVE) k_combine_wide(CombineArgs A, const int 
     const int lo_words = A.L->xoff[A.h] + A.L->soff[A.h];
     for (int i = blockIdx.x; i < cnt; i += gridDim.x) {
         const int v = __builtin_amdgcn_readfirstlane(OWN ? wide_list[A.g.n - 1 - i] : wide_list[i]);
-        combine_vertex_pf<false, SCC_KMAX - 1, true>(A, v, sm, sm + lo_words, nullptr, nullptr, OWN);
+        combine_vertex_pf<false, SCC_KMAX - 1, true, true>(A, v, sm, sm + lo_words, nullptr, nullptr, OWN);
         __syncthreads();
     }
 }
@@ -1832,6 +1843,97 @@ void launch_eta_shape(scc_table *T, int shape, u128 *eta)
 // Host orchestration
 // ---------------------------------------------------------------------------
 // one workgroup per vertex, or per listed vertex (rows non-null)
+// Level 2 of Eq. (1) has one term per output: an edge rooted at v with colour set
+// {c_v, j} has c = S_1(v)[j] copies (beta = 1), below 2^31. One thread per vertex
+// writes the nonzero ones into v's slot in output order (ascending key), as the
+// general combine would.
+__global__ void __launch_bounds__(256) k_combine_level2(CombineArgs A)
+{
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= A.g.n) return;
+    const DevLut &L = *A.L;
+    const int cv = A.g.colors[v];
+    const int W = L.W[2];
+    const uint64_t *s1 = A.Slo[1] + (size_t)v * W;          // S_1 has W_2 = k - 1 entries
+    const uint16_t *okey = L.out_key[cv] + L.out_off[2];
+    uint16_t *sk = A.slot_key + (size_t)v * A.W;
+    uint64_t *sl = A.slot_lo + (size_t)v * A.W;
+    uint32_t cnt = 0;
+    uint64_t sum = 0;
+    for (int o = 0; o < W; o++) {
+        const uint64_t c = s1[o];
+        if (!c) continue;
+        sk[cnt] = okey[o];
+        sl[cnt] = c;
+        cnt++;
+        sum += c;
+    }
+    A.meta[v] = cnt;
+    A.Nout[v] = sum;
+}
+
+// Level 3 of Eq. (1) reads only dense arrays: its own counts are X_1 = 1 and
+// X_2, which equals S_1 entry for entry (an edge rooted at v with colours
+// {c_v, j} has S_1(v)[j] copies), and its neighbour sums are S_1 and S_2. One
+// thread per vertex evaluates the outputs from the same descriptors and terms
+// as the general combine, in output order. The bound N_1 M_2 + N_2 M_1 is at
+// most 2m + d_v^2, so 128 bits always suffice; a vertex whose S_2 needs high
+// words is listed for the 128-bit combine instead.
+__global__ void __launch_bounds__(256) k_combine_level3(CombineArgs A, int *wide_list, int *wide_count)
+{
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= A.g.n) return;
+    const DevLut &L = *A.L;
+    const int cv = A.g.colors[v];
+    const int k1 = L.WS[1];                                  // k - 1
+    if (hi64(A.M[2][v]) != 0) {
+        wide_list[atomicAdd(wide_count, 1)] = (int)v;
+        return;
+    }
+    const uint64_t *s1 = A.Slo[1] + (size_t)v * k1;
+    const uint64_t *s2 = A.Slo[2] + (size_t)v * L.WS[2];
+    uint64_t n2 = 0;
+    for (int j = 0; j < k1; j++) n2 += s1[j];
+    const u128 U = (u128)lo64(A.M[2][v]) + (u128)n2 * lo64(A.M[1][v]);
+    const bool owide = hi64(U) != 0;
+    if (bitlen128(U) > A.max_bits) {
+        atomicOr(A.err, 1);
+        A.meta[v] = 0;
+        A.Nout[v] = 0;
+        return;
+    }
+    const uint32_t ob = L.out_off[3];
+    const uint16_t *okey = L.out_key[cv] + ob;
+    uint16_t *sk = A.slot_key + (size_t)v * A.W;
+    uint64_t *sl = A.slot_lo + (size_t)v * A.W;
+    uint64_t *sh = A.slot_hi + (size_t)v * A.W;
+    uint32_t cnt = 0;
+    u128 nsum = 0;
+    for (int o = 0; o < L.W[3]; o++) {
+        const uint64_t d = L.out[ob + o];
+        const int xb = (int)(d & 0xffffu), sb = (int)((d >> 16) & 0xffffu), tb = (int)((d >> 32) & 0xffffu);
+        const int nsplit = (int)((d >> 48) & 0xffu);
+        const uint32_t beta = (uint32_t)((d >> 56) & 0x7fu);
+        u128 acc = 0;
+        for (int i = 0; i < nsplit; i++) {
+            const uint32_t xs = L.term_xs[tb + i];
+            const int xi = xb + (int)(xs & 0xffu), si = sb + (int)(xs >> 8);
+            const uint64_t x = xi == 0 ? 1ull : s1[xi - 1];      // staging: [X_1 | X_2]
+            const uint64_t sv = si < k1 ? s1[si] : s2[si - k1];  // staging: [S_1 | S_2]
+            acc += (u128)x * sv;
+        }
+        const u128 val = beta == 1 ? acc : div_exact_small(acc, beta);
+        if (val == 0) continue;
+        sk[cnt] = okey[o];
+        sl[cnt] = lo64(val);
+        if (owide) sh[cnt] = hi64(val);
+        cnt++;
+        nsum += val;
+    }
+    A.meta[v] = cnt | (owide ? 0x80000000u : 0u);
+    A.Nout[v] = nsum;
+}
+
 template <int PMAX>
 static void launch_combine(const CombineArgs &C, int64_t n, const int32_t *rows, int64_t nrows, size_t lds,
                            hipStream_t st, int *wide_list, int *wide_count)
@@ -2143,7 +2245,12 @@ static scc_status build_levels(scc_table *T)
                 HIP_TRY(hipMemsetAsync(Nsc, 0, (size_t)n * 16, st));
             }
             const int phi = C.bal ? h - 2 : h - 1;
-            if (phi <= 3) launch_combine<3>(C, n, zl ? zrows : nullptr, nzero, lds, st, wide_list, err + 1);
+            if (h == 2 && !zl && !C.bal)
+                hipLaunchKernelGGL(k_combine_level2, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, C);
+            else if (h == 3 && !zl && !C.bal)
+                hipLaunchKernelGGL(k_combine_level3, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, C, wide_list,
+                                   err + 1);
+            else if (phi <= 3) launch_combine<3>(C, n, zl ? zrows : nullptr, nzero, lds, st, wide_list, err + 1);
             else if (phi <= 5) launch_combine<5>(C, n, zl ? zrows : nullptr, nzero, lds, st, wide_list, err + 1);
             else launch_combine<SCC_KMAX - 1>(C, n, zl ? zrows : nullptr, nzero, lds, st, wide_list, err + 1);
             // the 128-bit vertices (at k = 8 most of level 7, nearly all with high

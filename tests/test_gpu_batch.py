@@ -90,6 +90,23 @@ def test_batch_with_wide_counts():
     assert tabs[0].totals()[0] > 2 ** 64
 
 
+@pytest.mark.parametrize("rooting", [0, 1])
+def test_batch_with_128_bit_neighbour_sums(rooting):
+    # a hub of 2^17 leaves at k = 7: the hub's level-6 counts exceed 2^64, so the
+    # leaves' level-6 neighbour sums have nonzero high words, which the batched
+    # worker stages beside the low words for the level-7 combine
+    S = scc()
+    leaves = 1 << 17
+    edges = [(0, i) for i in range(1, leaves + 1)] + [(i, i + 1) for i in range(1, 200)]
+    g = gg.csr_from_edges(leaves + 1, np.array(edges, np.int64))
+    colors = np.concatenate([[0], (np.arange(leaves) % 6) + 1]).astype(np.uint8)
+    small = gg.erdos_renyi(100, 300, seed=1)
+    dev = [(S.DeviceGraph.from_graph(small), gg.colors(100, 7, seed=2), 7), (S.DeviceGraph.from_graph(g), colors, 7)]
+    tabs, _ = S.build_batch(dev, rooting=rooting, tile=512, hub_degree=1024, waves=8)
+    assert_tables_equal(tabs[1], O.Table(g, colors, 7, rooting), 7, "128-bit sums in a batch")
+    assert tabs[1].occ(0, -1) > 2 ** 64
+
+
 def test_batch_zero_rooting_colour_zero_sparse():
     # zero-rooting: the level-k combine and the level k-1 gather visit only the
     # colour-0 vertices of each tile (none, one, or about a k-th of them)
