@@ -40,11 +40,12 @@ def parse():
                    help="leave out the extra round-skipping, biased-colouring and variable-length builds "
                         "(counter runs: only the plain step's kernels)")
     p.add_argument("--small", action="store_true", help="small graph (for quick checks)")
-    p.add_argument("--workload", default="large", choices=["mid", "large", "batching", "serving"],
+    p.add_argument("--workload", default="large", choices=["mid", "large", "batching", "serving", "k16"],
                    help="large (default) / mid: the plain method on the large / mid graph; batching: 48 "
                         "instances, plain vs one "
                         "batched launch; serving: three resident k=7 tables under a Poisson request mix, continuous "
-                        "batching vs first-in first-out")
+                        "batching vs first-in first-out; k16: the sparse-record build for k up to 16 "
+                        "(k = 10 on a sparse Chung-Lu graph)")
     p.add_argument("--serve-step", type=int, default=1 << 18,
                    help="serving: samples per step of the continuous-batching server (its share granularity; "
                         "2^18 is the library's default)")
@@ -517,6 +518,84 @@ def size_bucket(n):
     return "1e3-1e4" if n < 10_000 else ("1e4-1e5" if n < 100_000 else "1e5-1e6")
 
 
+K16 = dict(n=1 << 16, m=1 << 17, gamma=2.5, wmax=40.0, gseed=7, k=10, cseed=17, oracle_scale=64)
+
+
+def run_k16(a):
+    """The build for k up to 16 (sparse records keyed by DFS bitstring and
+    colour set): whole builds timed, per-level terms and sort time, and the
+    oracle on a graph of the same recipe 1/64 the size (time per vertex)."""
+    cfg = K16
+    import graphgen as gg
+    base = None
+    if not a.no_cpu_baseline:
+        import oracle as O
+        ns = cfg["n"] // cfg["oracle_scale"]
+        gs = gg.chung_lu(ns, cfg["m"] // cfg["oracle_scale"], cfg["gamma"], cfg["wmax"], seed=cfg["gseed"])
+        cs = gg.colors(gs.n, cfg["k"], seed=cfg["cseed"])
+        t0 = time.perf_counter()
+        ot = O.Table16(gs, cs, cfg["k"], O.ROOT_ZERO)
+        o_s = time.perf_counter() - t0
+        base = {"value": gs.n / o_s, "unit": "vertices per second (whole build)", "cores": 1, "kind": "oracle",
+                "sample": f"the oracle's build of a Chung-Lu graph of the same recipe with n = {gs.n}, "
+                          f"m = {gs.m} (1/{cfg['oracle_scale']} of the workload), k = {cfg['k']}: {o_s:.2f} s",
+                "t": str(ot.total())}
+        del ot
+        print(f"# oracle: {o_s:.2f} s for n = {gs.n}", file=sys.stderr, flush=True)
+    import torch
+
+    import paper_2009_03052_amd as scc
+    torch.cuda.set_device(0)
+    n = cfg["n"] // 16 if a.small else cfg["n"]
+    g = gg.chung_lu(n, cfg["m"] * n // cfg["n"], cfg["gamma"], cfg["wmax"], seed=cfg["gseed"])
+    k = cfg["k"]
+    colors = gg.colors(g.n, k, seed=cfg["cseed"])
+    dg = scc.DeviceGraph.from_graph(g)
+    dcol = torch.as_tensor(colors).cuda()
+    print(f"# graph n={g.n} m={g.m} d_max={int(g.degrees().max())}, k={k}", file=sys.stderr, flush=True)
+    for i in range(a.warmup):
+        t = scc.Table16(dg, dcol, k, validate=False)
+        del t
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    for i in range(a.steps):
+        t = scc.Table16(dg, dcol, k, validate=False)
+        infos.append(t.info())
+        total = t.total()
+        del t
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / a.steps
+    inf = infos[-1]
+    sort_ms = sum(inf.sort_ms[h] for h in range(1, k + 1))
+    sort_b = sum(inf.sort_bytes[h] for h in range(1, k + 1))
+    print(f"# timed {a.steps} builds: {dt * 1e3:.1f} ms/build, sorts {sort_ms:.1f} ms", file=sys.stderr, flush=True)
+    out = {
+        "metric": "DP table build s & colorful-treelet samples/sec, batched/served vs plain",
+        "value": g.n / dt, "unit": f"vertices per second (whole k = {k} build, sparse records)",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u128", "data": "synthetic",
+        "config": {"workload": f"k16: Chung-Lu n={g.n} m={g.m} exponent {cfg['gamma']} w_max={cfg['wmax']}, "
+                               f"k={k}, zero-rooting, sparse records keyed by DFS bitstring",
+                   "n": g.n, "m": g.m, "k": k},
+        "build_s": dt, "t": str(total),
+        "level_ms": [round(inf.level_ms[h], 3) for h in range(1, k + 1)],
+        "sort_ms": [round(inf.sort_ms[h], 3) for h in range(1, k + 1)],
+        "nnz": [int(inf.nnz[h]) for h in range(1, k + 1)],
+        "terms": [int(inf.terms[h]) for h in range(1, k + 1)],
+        "nbr_terms": [int(inf.nbr_terms[h]) for h in range(1, k + 1)],
+        "table_bytes": int(inf.bytes), "peak_bytes": int(inf.peak_bytes),
+        "roofline": {"bound": "hbm", "achieved": sort_b / (sort_ms * 1e6) if sort_ms > 0 else None,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": sort_b / (sort_ms * 1e6) / HBM_PEAK_GBS if sort_ms > 0 else None, "traffic": None,
+                     "kernel": "radix sort of the terms (k16_hist, k16_scatter and their scans): 32 B per "
+                               "element and pass", "bytes_per_build": sort_b, "ms_per_build": sort_ms},
+    }
+    if base is not None:
+        out["cpu_baseline"] = base
+    print(json.dumps(out), flush=True)
+
+
 def run_serving(a):
     import torch
 
@@ -666,6 +745,8 @@ def main():
         return run_batching(a)
     if a.workload == "serving":
         return run_serving(a)
+    if a.workload == "k16":
+        return run_k16(a)
     cfg = PLAIN[a.workload]
     base = None
     if not a.no_cpu_baseline and not a.small:
@@ -799,5 +880,137 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+# ---------------------------------------------------------------------------
+# Summaries of rocprofv3 output (what profiles/ holds):
+#   python bench.py summarise trace <run_kernel_trace.csv>
+#   python bench.py summarise counters <label> <samples per k_sample> <dir of the read pass> <dir of the write pass>
+# ---------------------------------------------------------------------------
+def _short_kernel(name):
+    name = name.replace("(anonymous namespace)::", "").replace("void ", "")
+    return name[:name.index("(")].strip() if "(" in name else name.strip()
+
+
+def _first_build(names):
+    """Indices of the first table build: from its first kernel to the last one before the first k_sample."""
+    start = next(i for i, nm in enumerate(names) if nm in ("k_row_lists", "k_validate_rows"))
+    end = next(i for i, nm in enumerate(names) if nm == "k_sample")
+    return start, end
+
+
+def summarise_trace(path):
+    import csv
+    import collections
+    rows = sorted(csv.DictReader(open(path)), key=lambda r: int(r["Start_Timestamp"]))
+    names = [_short_kernel(r["Kernel_Name"]) for r in rows]
+    a, b = _first_build(names)
+    build = rows[a:b]
+    t0 = int(build[0]["Start_Timestamp"])
+    t1 = max(int(r["End_Timestamp"]) for r in build)
+    dur = lambda r: int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+    busy = sum(dur(r) for r in build)
+    agg = collections.defaultdict(lambda: [0, 0])
+    for r, nm in zip(build, names[a:b]):
+        agg[nm][0] += 1
+        agg[nm][1] += dur(r)
+    print(f"one build (the first): {(t1 - t0) / 1e6:.1f} ms from its first kernel to the end of its last, "
+          f"kernels busy {busy / 1e6:.1f} ms\n")
+    print("| kernel (one build) | calls | ms | % of busy |\n|---|---|---|---|")
+    for nm, (c, d) in sorted(agg.items(), key=lambda x: -x[1][1]):
+        if d >= 0.001 * busy:
+            print(f"| {nm} | {c} | {d / 1e6:.2f} | {100 * d / busy:.1f} |")
+    print()
+    for want in ("k_sample", "k_classify"):
+        ds = [dur(r) for r, nm in zip(rows, names) if nm == want]
+        if ds:
+            print(f"{want}: {len(ds)} calls, average {sum(ds) / len(ds) / 1e6:.3f} ms")
+
+
+def _counter_dispatches(d):
+    import csv
+    import collections
+    import glob
+    f = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if not f:
+        raise SystemExit(f"no counter_collection.csv under {d}")
+    disp = collections.OrderedDict()
+    for r in csv.DictReader(open(f[0])):
+        e = disp.setdefault(int(r["Dispatch_Id"]), {"name": _short_kernel(r["Kernel_Name"]), "c": {}})
+        e["c"][r["Counter_Name"]] = e["c"].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    return [disp[i] for i in sorted(disp)]
+
+
+def summarise_counters(label, ns, dir_a, dir_b):
+    """HBM bytes per kernel of one build from the TCC_EA0 request counters: reads
+    32 RDREQ_32B + 64 RDREQ_64B + 128 RDREQ_128B (pass A), writes
+    32 (WRREQ - WRREQ_64B) + 64 WRREQ_64B (pass B), calibrated on the 1 GiB copy."""
+    import collections
+    import hashlib
+    A, B = _counter_dispatches(dir_a), _counter_dispatches(dir_b)
+    rd = lambda c: (32 * c.get("TCC_EA0_RDREQ_32B_sum", 0) + 64 * c.get("TCC_EA0_RDREQ_64B_sum", 0)
+                    + 128 * c.get("TCC_EA0_RDREQ_128B_sum", 0))
+    wr = lambda c: (32 * (c.get("TCC_EA0_WRREQ_sum", 0) - c.get("TCC_EA0_WRREQ_64B_sum", 0))
+                    + 64 * c.get("TCC_EA0_WRREQ_64B_sum", 0))
+
+    def calib(ds, f):   # the copy: the largest pre-build dispatch
+        best = None
+        for d in ds:
+            if d["name"].startswith("k_"):
+                break
+            if best is None or f(d["c"]) > best[1]:
+                best = (d["name"], f(d["c"]))
+        return best
+
+    def cls(nm):
+        if (nm.startswith("k_gather") and nm != "k_gather_bytes") or nm == "k_hub_prepare":
+            return "gather"
+        if nm.startswith("k_combine") or nm in ("k_pack", "k_words"):
+            return "combine"
+        return "other"
+
+    ca, cb = calib(A, rd), calib(B, wr)
+    na, nb = [d["name"] for d in A], [d["name"] for d in B]
+    (a0, a1), (b0, b1) = _first_build(na), _first_build(nb)
+    ba, bb = A[a0:a1], B[b0:b1]
+    if [d["name"] for d in ba] != [d["name"] for d in bb]:
+        raise SystemExit("the two passes dispatched different kernels")
+    tot = collections.defaultdict(lambda: [0.0, 0.0, 0, 0.0])
+    for da, db in zip(ba, bb):
+        t = tot[da["name"]]
+        t[0] += rd(da["c"])
+        t[1] += wr(db["c"])
+        t[2] += 1
+        t[3] += db["c"].get("TCC_EA0_RDREQ_DRAM_sum", 0)
+    g = collections.defaultdict(lambda: [0.0, 0.0])
+    for nm, t in tot.items():
+        g[cls(nm)][0] += t[0]
+        g[cls(nm)][1] += t[1]
+    sa = [d for d in A if d["name"] == "k_sample"]
+    sb = [d for d in B if d["name"] == "k_sample"]
+    h = hashlib.sha256()
+    for f in ("dp.hip", "sample.hip", "device.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_2009_03052_amd", "csrc", f), "rb").read())
+    print(f"workload: {label}")
+    print(f"calibration copy (1073741824 bytes each way): read requests by size give {ca[1]:.0f} bytes ({ca[0]}), "
+          f"write requests {cb[1]:.0f} bytes ({cb[0]})")
+    print("per kernel of one build (HBM-side TCC_EA0 requests; DRAM rdreq = TCC_EA0_RDREQ_DRAM, requests):")
+    print(f"  {'kernel':28s} {'dispatches':>10s} {'read MB':>12s} {'write MB':>12s}  {'DRAM rdreq':>12s}")
+    for nm, t in sorted(tot.items(), key=lambda x: -(x[1][0] + x[1][1])):
+        print(f"  {nm:28s} {t[2]:10d} {t[0] / 1e6:12.1f} {t[1] / 1e6:12.1f}  {t[3]:12.0f}")
+    for key in ("gather", "combine", "other"):
+        print(f"{key}_read_bytes_per_build {g[key][0]:.0f}\n{key}_write_bytes_per_build {g[key][1]:.0f}")
+    print(f"traffic_bytes_per_build {sum(x[0] + x[1] for x in g.values()):.0f}")
+    print(f"gather_traffic_bytes_per_build {g['gather'][0] + g['gather'][1]:.0f}")
+    print(f"combine_traffic_bytes_per_build {g['combine'][0] + g['combine'][1]:.0f}")
+    print(f"sampler_dispatches {len(sa)}")
+    print(f"sampler_read_bytes_per_sample {sum(rd(d['c']) for d in sa) / (ns * max(1, len(sa))):.1f}")
+    print(f"sampler_write_bytes_per_sample {sum(wr(d['c']) for d in sb) / (ns * max(1, len(sb))):.1f}")
+    print(f"source_sha256 {h.hexdigest()}  (dp.hip + sample.hip + device.hpp at the time of the counter runs)")
+
+
 if __name__ == "__main__":
-    main()
+    if len(sys.argv) > 2 and sys.argv[1] == "summarise" and sys.argv[2] == "trace":
+        summarise_trace(sys.argv[3])
+    elif len(sys.argv) > 2 and sys.argv[1] == "summarise" and sys.argv[2] == "counters":
+        summarise_counters(sys.argv[3], int(sys.argv[4]), sys.argv[5], sys.argv[6])
+    else:
+        main()

@@ -563,6 +563,76 @@ scc_status scc_server_get_stats(scc_server *s, scc_server_stats *out);
    steps in flight finish, and every buffer of the server is freed. */
 void scc_server_destroy(scc_server *s);
 
+/* ------------------------------------------------------------------------ */
+/* k up to 16: sparse records keyed by DFS bitstring (Sec. 3.2)             */
+/* ------------------------------------------------------------------------ */
+typedef struct scc16_table scc16_table;
+
+typedef struct {
+    int rooting;               /* SCC_ROOT_ZERO (default): level k at colour-0 vertices
+                                  (Sec. 3.4); SCC_ROOT_ALL: at every vertex */
+    void *stream;              /* hipStream_t for all work of the build */
+    const scc_allocator *alloc;/* NULL: hipMalloc / hipFree */
+    int no_validate;           /* as in scc_build_opts */
+    int64_t chunk_terms;       /* terms (neighbour entries or Eq. (1) products) formed and
+                                  sorted at a time; 0 = 2^26. Results do not depend on it. */
+} scc16_build_opts;
+
+typedef struct {
+    int64_t n;
+    int k;
+    int rooting;
+    int64_t nnz[17];           /* stored counts of level h (nnz[0] unused) */
+    int64_t terms[17];         /* non-zero products of Eq. (1) formed for level h */
+    int64_t nbr_terms[17];     /* neighbour entries gathered into the sums of level h */
+    int64_t sum_nnz[17];       /* distinct neighbour sums kept for level h */
+    int64_t chunks[17];        /* vertex chunks of level h's products */
+    int64_t bytes;             /* device bytes of the stored levels */
+    int64_t peak_bytes;        /* largest device working set of the build */
+    uint64_t t[2];             /* colourful k-treelet copies (lo, hi) */
+    double level_ms[17];       /* device time of level h (products and its sums) */
+    double sort_ms[17];        /* of which radix sorting */
+    double sort_bytes[17];     /* algorithmic bytes of those sorts: 32 per element and pass
+                                  (8 read by the histogram; 12 read and 12 written by the
+                                  scatter) */
+    double build_ms;           /* the whole build after validation */
+} scc16_table_info;
+
+/*
+ * scc16_build_table -- the build-up phase (Sec. 2.1, Eq. (1)) for k in
+ * [2, 16], with the treelet representation of Sec. 3.2: a rooted treelet on h
+ * nodes is its DFS bitstring s_T of 2(h-1) bits ('1' away from the root, '0'
+ * back, the root's child words "1 s 0" in descending lexicographic order,
+ * first edge at the most significant bit), and a coloured treelet (T, C) the
+ * key s_T << 16 | C (C the k-bit colour mask; 46 bits at most). Every vertex
+ * keeps only its non-zero counts, sorted by key (the count tables of Sec. 3.2).
+ * c(T_C, v) is as in scc_build_table, T'' being T's largest root child
+ * subtree. Counts are exact 128-bit integers: a count, product or sum that
+ * needs more bits gives SCC_EOVERFLOW (counts wider than 128 bits are not
+ * supported). The table holds the levels and t; it has no sampler.
+ *
+ * g, colors: as in scc_build_table (device pointers borrowed, or host
+ * pointers copied). opt may be NULL. *out: free with scc16_table_destroy.
+ * Errors: SCC_EINVAL (k, rooting, sizes, colours, CSR), SCC_EOVERFLOW,
+ * SCC_ENOMEM (also when one vertex alone forms 2^31 or more terms),
+ * SCC_EDEVICE. On error *out is NULL.
+ */
+scc_status scc16_build_table(const scc_csr *g, const uint8_t *colors, int k, const scc16_build_opts *opt,
+                             scc16_table **out);
+void scc16_table_destroy(scc16_table *t);
+scc_status scc16_table_info_get(const scc16_table *t, scc16_table_info *out);
+
+/*
+ * scc16_export_level -- level h's records in vertex order (Sec. 3.2, "Count
+ * tables"): off device int64[n+1] (the record of v is [off[v], off[v+1])),
+ * key device uint64[nnz] (s_T << 16 | C, ascending within a record), lo/hi
+ * device uint64[nnz]. With off == NULL only *nnz_out is set. Caller-owned
+ * outputs. Errors: SCC_EINVAL (h outside [1, k]), SCC_EDEVICE. Synchronises
+ * `stream`.
+ */
+scc_status scc16_export_level(const scc16_table *t, int h, int64_t *nnz_out, int64_t *off, uint64_t *key,
+                              uint64_t *lo, uint64_t *hi, void *stream);
+
 /* Frees the per-k class data kept by scc_classify, scc_catalog and AGS (device
    lookup tables, spanning-tree counts). Call only when no classification, AGS
    run or server is in progress. */

@@ -83,6 +83,19 @@ class TableInfo(C.Structure):
                 ("totals_ms", C.c_double)]
 
 
+class _Build16Opts(C.Structure):
+    _fields_ = [("rooting", C.c_int), ("stream", C.c_void_p), ("alloc", C.POINTER(_Allocator)),
+                ("no_validate", C.c_int), ("chunk_terms", C.c_int64)]
+
+
+class Table16Info(C.Structure):
+    _fields_ = [("n", C.c_int64), ("k", C.c_int), ("rooting", C.c_int), ("nnz", C.c_int64 * 17),
+                ("terms", C.c_int64 * 17), ("nbr_terms", C.c_int64 * 17), ("sum_nnz", C.c_int64 * 17),
+                ("chunks", C.c_int64 * 17), ("bytes", C.c_int64), ("peak_bytes", C.c_int64),
+                ("t", C.c_uint64 * 2), ("level_ms", C.c_double * 17), ("sort_ms", C.c_double * 17),
+                ("sort_bytes", C.c_double * 17), ("build_ms", C.c_double)]
+
+
 class _ServerOpts(C.Structure):
     _fields_ = [("tables", C.POINTER(C.c_void_p)), ("n_tables", C.c_int), ("hbm_budget", C.c_int64),
                 ("max_pending", C.c_int), ("max_active", C.c_int), ("step_samples", C.c_int64), ("chunk", C.c_int64),
@@ -140,6 +153,10 @@ _SIGS = {
     "scc_server_release": (C.c_int, [_P, _i64]),
     "scc_server_get_stats": (C.c_int, [_P, C.POINTER(ServerStats)]),
     "scc_server_destroy": (None, [_P]),
+    "scc16_build_table": (C.c_int, [C.POINTER(_Csr), _P, C.c_int, C.POINTER(_Build16Opts), C.POINTER(_P)]),
+    "scc16_table_destroy": (None, [_P]),
+    "scc16_table_info_get": (C.c_int, [_P, C.POINTER(Table16Info)]),
+    "scc16_export_level": (C.c_int, [_P, C.c_int, C.POINTER(_i64), _P, _P, _P, _P, _P]),
     "scc_release_caches": (None, []),
     "scc_num_unrooted": (C.c_int, [C.c_int]),
     "scc_balanced_rooting": (C.c_int, [C.c_int, C.c_int, C.POINTER(C.c_int)]),
@@ -379,6 +396,73 @@ class Table:
                             shapes.ctypes.data_as(_P), C.byref(nr), _stream_ptr(stream)))
         return {"hits": hits, "w": w, "n_j": nj, "round_shapes": shapes[:nr.value]}
 
+
+
+class Table16:
+    """The count table for k up to 16 with sparse records (``scc16_build_table``).
+
+    Keys are ``s_T << 16 | C`` (DFS bitstring and colour mask). ``graph`` is a
+    :class:`DeviceGraph` or a host graph, as for :class:`Table`.
+    """
+
+    def __init__(self, graph, colors, k: int, rooting: int = ROOT_ZERO, validate: bool = True,
+                 chunk_terms: int = 0, stream=None, use_torch_allocator: bool = True):
+        self.graph, self.k, self._stream = graph, k, stream
+        if isinstance(graph, DeviceGraph):
+            self.device = graph.row_ptr.device
+            self.colors = torch.as_tensor(np.asarray(colors) if not torch.is_tensor(colors) else colors,
+                                          dtype=torch.uint8).to(self.device).contiguous()
+            csr = _Csr(graph.n, graph.nnz, graph.row_ptr.data_ptr(), graph.col_idx.data_ptr(), 1)
+            cptr = _ptr(self.colors)
+        else:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+            rp = np.ascontiguousarray(graph.row_ptr, dtype=np.int64)
+            ci = np.ascontiguousarray(graph.col_idx, dtype=np.int32)
+            self.colors = np.ascontiguousarray(colors.cpu().numpy() if torch.is_tensor(colors) else colors,
+                                               dtype=np.uint8)
+            csr = _Csr(int(rp.size - 1), int(ci.size), rp.ctypes.data, ci.ctypes.data, 0)
+            cptr = C.c_void_p(self.colors.ctypes.data)
+        opts = _Build16Opts(rooting, _stream_ptr(stream), C.pointer(TORCH_ALLOCATOR) if use_torch_allocator else None,
+                            0 if validate else 1, chunk_terms)
+        self._h = _P()
+        _check(_lib.scc16_build_table(C.byref(csr), cptr, k, C.byref(opts), C.byref(self._h)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.scc16_table_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> Table16Info:
+        out = Table16Info()
+        _check(_lib.scc16_table_info_get(self._h, C.byref(out)))
+        return out
+
+    def total(self) -> int:
+        i = self.info()
+        return _u128(i.t[0], i.t[1])
+
+    def export_level(self, h: int, stream=None, to_host: bool = True):
+        """(off int64[n+1], key uint64[nnz], lo uint64[nnz], hi uint64[nnz]) as numpy arrays, or
+        (to_host=False) device tensors of the same bits."""
+        nnz = _i64()
+        _check(_lib.scc16_export_level(self._h, h, C.byref(nnz), None, None, None, None, None))
+        dev = self.device
+        m = max(nnz.value, 1)
+        off = torch.empty(self.info().n + 1, dtype=torch.int64, device=dev)
+        key, lo, hi = (torch.empty(m, dtype=torch.int64, device=dev) for _ in range(3))
+        _check(_lib.scc16_export_level(self._h, h, C.byref(nnz), _ptr(off), _ptr(key), _ptr(lo), _ptr(hi),
+                                       _stream_ptr(stream)))
+        n = nnz.value
+        if not to_host:
+            return off, key[:n], lo[:n], hi[:n]
+        return (off.cpu().numpy(), key[:n].cpu().numpy().view(np.uint64), lo[:n].cpu().numpy().view(np.uint64),
+                hi[:n].cpu().numpy().view(np.uint64))
 
 def build_batch(instances, rooting: int = ROOT_ZERO, max_bits: int = 128, tile: int = 0, hub_degree: int = 0,
                 autotune: bool = False, stream=None, use_torch_allocator: bool = True, waves: int = 0,

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libscc.so")
-SOURCES = ["treelets.cpp", "dp.hip", "sample.hip", "classify.hip", "serve.cpp", "colour.hip", "probe.hip"]
+SOURCES = ["treelets.cpp", "dp.hip", "dp16.hip", "sample.hip", "classify.hip", "serve.cpp", "colour.hip", "probe.hip"]
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall", "-Wno-unused-function"]
 

@@ -2566,30 +2566,30 @@ static scc_status attach_graph(scc_table *T, const scc_csr *g, const uint8_t *co
     return SCC_OK;
 }
 
-// Checks the table's CSR and colours on the device (Sec. 1.3: a simple
-// undirected graph; Sec. 2: colours in [0, k)): EINVAL on any violation.
-static scc_status validate_graph(scc_table *T)
+// Checks a CSR and its colours on the device (Sec. 1.3: a simple undirected
+// graph; Sec. 2: colours in [0, k)): EINVAL on any violation.
+scc_status validate_csr(int64_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col_idx,
+                        const uint8_t *colors, int k, hipStream_t stream, DevMem &mem)
 {
-    const int64_t n = T->n, nnz = T->nnz_g;
     if (n == 0) return nnz == 0 ? SCC_OK : set_error(SCC_EINVAL, "invalid input (an empty graph with nnz = %lld)", (long long)nnz);
-    int *err = (int *)T->mem.get(16);
+    int *err = (int *)mem.get(16);
     if (!err) return set_error(SCC_ENOMEM, "validate");
     int herr = 0;
-    hipError_t e = hipMemsetAsync(err, 0, 4, T->stream);
+    hipError_t e = hipMemsetAsync(err, 0, 4, stream);
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_validate_rows, dim3((unsigned)((n + 1 + 255) / 256)), dim3(256), 0, T->stream, T->row_ptr, n,
+        hipLaunchKernelGGL(k_validate_rows, dim3((unsigned)((n + 1 + 255) / 256)), dim3(256), 0, stream, row_ptr, n,
                            nnz, err);
-        e = hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, T->stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(T->stream);
+        e = hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
     }
     if (e == hipSuccess && herr == 0) {
-        GraphView gv{n, T->row_ptr, T->col_idx, T->colors};
+        GraphView gv{n, row_ptr, col_idx, colors};
         const int64_t m = std::max(n, nnz);
-        hipLaunchKernelGGL(k_validate_edges, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, T->stream, gv, nnz, T->k, err);
-        e = hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, T->stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(T->stream);
+        hipLaunchKernelGGL(k_validate_edges, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, stream, gv, nnz, k, err);
+        e = hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
     }
-    T->mem.put(err);
+    mem.put(err);
     if (e != hipSuccess) return set_error(SCC_EDEVICE, "validate: %s", hipGetErrorString(e));
     if (herr)
         return set_error(SCC_EINVAL, "invalid input (%s%s%s%s%s%s)", herr & 1 ? "colour >= k " : "",
@@ -2598,6 +2598,11 @@ static scc_status validate_graph(scc_table *T)
                          herr & 8 ? "row not strictly increasing " : "", herr & 16 ? "asymmetric edge " : "",
                          herr & 32 ? "row_ptr[n] != nnz" : "");
     return SCC_OK;
+}
+
+static scc_status validate_graph(scc_table *T)
+{
+    return validate_csr(T->n, T->nnz_g, T->row_ptr, T->col_idx, T->colors, T->k, T->stream, T->mem);
 }
 
 extern "C" scc_status scc_build_table(const scc_csr *g, const uint8_t *colors, int k,

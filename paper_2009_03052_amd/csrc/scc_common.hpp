@@ -186,6 +186,11 @@ struct DevMem {
     void put(void *p);
 };
 
+// Checks a CSR (sorted, symmetric, simple rows; row_ptr from 0 to nnz) and its
+// colours (below k) on the device; SCC_EINVAL on a violation (dp.hip).
+scc_status validate_csr(int64_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col_idx,
+                        const uint8_t *colors, int k, hipStream_t stream, DevMem &mem);
+
 // Device buffer owned by a table; freed through the same allocator.
 struct Buf {
     void *p = nullptr;
