@@ -39,9 +39,12 @@ namespace {
 constexpr int K16 = 16;
 constexpr int WPB = 4;                      // waves per block
 constexpr int BLOCK = WPB * WAVE;           // 256 threads
+constexpr int SCAN_ITEMS = 8;
+constexpr int SCAN_TILE = BLOCK * SCAN_ITEMS;   // elements per scan block
+constexpr int RADIX_BITS = 8;                   // digit width of the radix sort
+constexpr int RADIX = 1 << RADIX_BITS;
 constexpr int SORT_ITEMS = 8;
-constexpr int SORT_TILE = BLOCK * SORT_ITEMS;   // elements per sort / scan block
-constexpr int RADIX = 256;
+constexpr int SORT_TILE = BLOCK * SORT_ITEMS;   // elements per sort block
 constexpr int64_t DEFAULT_CHUNK_TERMS = (int64_t)1 << 26;
 constexpr int64_t MAX_CHUNK_TERMS = ((int64_t)1 << 31) - 1;   // sort permutations are uint32
 
@@ -258,16 +261,37 @@ struct CombArgs {
 
 // One wave per vertex v, one lane per own entry (T', C') of each level hp < h:
 // the sums (T'', D) of S_{h-hp}(v) with D disjoint from C' whose word may
-// lead T'. The colour sets D are taken either from a walk over all of
-// S_{h-hp}(v) or, when that record is long, by listing the (h-hp)-subsets of
-// the free colours and finding each by binary search.
+// lead T'. Three ways to find them, chosen per (v, hp) for the whole wave:
+//  * a short record is walked entry by entry (every lane reads the same entry);
+//  * otherwise each lane lists the (h-hp)-subsets D of its free colours and
+//    looks each up in a directory of the record in LDS, indexed by the colex
+//    rank of D among the (h-hp)-subsets of the k-1 colours other than c_v (the
+//    record is sorted by D, and colex order of equal-size sets is their
+//    numeric order, so each D's sums are one range);
+//  * when that directory would exceed DIR_MAX entries, by binary search.
+constexpr int DIR_MAX = 512;
+
 template <bool EMIT>
 __global__ __launch_bounds__(BLOCK) void k16_comb(CombArgs A)
 {
     __shared__ uint64_t ctr[WPB];
+    __shared__ uint32_t dir_st[WPB][DIR_MAX];
+    __shared__ uint32_t dir_en[WPB][DIR_MAX];
+    __shared__ uint16_t binom_t[K16][K16 + 1];     // binom(p, q), p < 16, q <= 16
+    for (int q = threadIdx.x; q < K16 * (K16 + 1); q += BLOCK) {
+        const int pp = q / (K16 + 1), qq = q % (K16 + 1);
+        binom_t[pp][qq] = (uint16_t)binom_small(pp, qq);
+    }
+    __syncthreads();
     const int w = threadIdx.x / WAVE, lane = lane_id();
     const int64_t nw = (int64_t)gridDim.x * WPB;
     const uint32_t full = (1u << A.k) - 1u;
+    // colex rank of a set of j colours of the (k-1)-colour universe
+    auto rank_of = [&](uint32_t Dc) {
+        uint32_t r = 0;
+        for (int t = 1; Dc; Dc &= Dc - 1u, t++) r += binom_t[__builtin_ctz(Dc)][t];
+        return r;
+    };
     for (int64_t v = A.v0 + (int64_t)blockIdx.x * WPB + w; v < A.v1; v += nw) {
         if (lane == 0) ctr[w] = 0;
         __builtin_amdgcn_wave_barrier();
@@ -275,18 +299,41 @@ __global__ __launch_bounds__(BLOCK) void k16_comb(CombArgs A)
         bool ovf = false;
         const int64_t base = EMIT ? A.toff[v] - A.toff[A.v0] : 0;
         const uint64_t vl = (uint64_t)(v - A.v0) << A.KB;
-        const bool active = !(A.zero_rooting && A.h == A.k && A.colors[v] != 0);
+        const int cv = A.colors[v];
+        const bool active = !(A.zero_rooting && A.h == A.k && cv != 0);
         for (int hp = 1; active && hp < A.h; hp++) {
             const int j = A.h - hp, lp = 2 * (hp - 1), sb = 2 * (j - 1), lw = 2 * j;
             const Lev16View X = A.X[hp], S = A.S[j];
             const int64_t xa = X.off[v], xb = X.off[v + 1], sa = S.off[v], se = S.off[v + 1];
             if (xa == xb || sa == se) continue;
+            const uint32_t smask = (1u << sb) - 1u;
             const int64_t nb = se - sa;
             const int m = A.k - hp;
+            const int nsub = binom_small(m, j), ndir = binom_small(A.k - 1, j);
             int lg = 1;
             while (((int64_t)1 << lg) < nb) lg++;
-            const bool walk = nb <= (int64_t)binom_small(m, j) * (lg + 1);
-            const uint32_t smask = (1u << sb) - 1u;
+            const int mode = nb <= (int64_t)nsub * 4 ? 0 : (ndir <= DIR_MAX ? 1 : 2);   // walk, directory, search
+            if (mode == 1) {
+                for (int q = lane; q < ndir; q += WAVE) dir_st[w][q] = dir_en[w][q] = 0;
+                __builtin_amdgcn_wave_barrier();
+                uint32_t prevD = 0xffffffffu;
+                for (int64_t e0 = sa; e0 < se; e0 += WAVE) {
+                    const int64_t e = e0 + lane;
+                    const uint32_t D = e < se ? (uint32_t)(S.key[e] >> sb) : 0xffffffffu;
+                    uint32_t before = (uint32_t)shfl64(D, lane == 0 ? 0 : lane - 1);
+                    if (lane == 0) before = prevD;
+                    if (e < se && D != before) {
+                        dir_st[w][rank_of(compress_out(D, cv))] = (uint32_t)(e - sa);
+                        if (before != 0xffffffffu) dir_en[w][rank_of(compress_out(before, cv))] = (uint32_t)(e - sa);
+                    }
+                    prevD = (uint32_t)readlane64(D, WAVE - 1);
+                }
+                if (lane == 0) {
+                    const uint32_t last = (uint32_t)(S.key[se - 1] >> sb);
+                    dir_en[w][rank_of(compress_out(last, cv))] = (uint32_t)nb;
+                }
+                __builtin_amdgcn_wave_barrier();
+            }
             for (int64_t x = xa + lane; x < xb; x += WAVE) {
                 const uint64_t kx = X.key[x];
                 const uint32_t Cp = (uint32_t)kx & 0xffffu, sp = (uint32_t)(kx >> 16);
@@ -303,10 +350,30 @@ __global__ __launch_bounds__(BLOCK) void k16_comb(CombArgs A)
                     A.tkey[q] = vl | (sT << A.k) | (uint64_t)(Cp | D);
                     A.tcnt[q] = mul_checked(cx, S.cnt[e], ovf);
                 };
-                if (walk) {
+                if (mode == 0) {
                     for (int64_t e = sa; e < se; e++) {
                         const uint32_t D = (uint32_t)(S.key[e] >> sb);
                         if (!(D & Cp)) term(e, D);
+                    }
+                } else if (mode == 1) {
+                    // the free colours, in the (k-1)-colour universe, as 4-bit positions
+                    const uint32_t freec = compress_out(full & ~Cp, cv);
+                    uint64_t pos = 0;
+                    {
+                        int t = 0;
+                        for (uint32_t f = freec; f; f &= f - 1u, t++) pos |= (uint64_t)__builtin_ctz(f) << (4 * t);
+                    }
+                    for (uint32_t idx = (1u << j) - 1u; idx < (1u << m); idx = next_comb(idx)) {
+                        uint32_t Dc = 0, r = 0;
+                        int t = 1;
+                        for (uint32_t b = idx; b; b &= b - 1u, t++) {
+                            const int p = (int)((pos >> (4 * __builtin_ctz(b))) & 15u);
+                            Dc |= 1u << p;
+                            r += binom_t[p][t];
+                        }
+                        const int64_t e1 = sa + dir_en[w][r];
+                        const uint32_t D = expand_in(Dc, cv);
+                        for (int64_t e = sa + dir_st[w][r]; e < e1; e++) term(e, D);
                     }
                 } else {
                     const uint32_t freec = full & ~Cp;
@@ -322,6 +389,7 @@ __global__ __launch_bounds__(BLOCK) void k16_comb(CombArgs A)
                     }
                 }
             }
+            __builtin_amdgcn_wave_barrier();
         }
         if (EMIT) {
             if (ovf) atomicOr(A.err, E16_OVERFLOW);
@@ -334,15 +402,15 @@ __global__ __launch_bounds__(BLOCK) void k16_comb(CombArgs A)
 }
 
 // ---------------------------------------------------------------------------
-// Exclusive scan of uint64 arrays (blocks of SORT_TILE, then the block sums)
+// Exclusive scan of uint64 arrays (blocks of SCAN_TILE, then the block sums)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(BLOCK) void k16_scan_tiles(uint64_t *d, int64_t N, uint64_t *tile_sums)
 {
     __shared__ uint64_t wsum[WPB];
-    const int64_t t0 = (int64_t)blockIdx.x * SORT_TILE + (int64_t)threadIdx.x * SORT_ITEMS;
-    uint64_t x[SORT_ITEMS], s = 0;
+    const int64_t t0 = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
+    uint64_t x[SCAN_ITEMS], s = 0;
 #pragma unroll
-    for (int i = 0; i < SORT_ITEMS; i++) {
+    for (int i = 0; i < SCAN_ITEMS; i++) {
         x[i] = t0 + i < N ? d[t0 + i] : 0;
         s += x[i];
     }
@@ -353,7 +421,7 @@ __global__ __launch_bounds__(BLOCK) void k16_scan_tiles(uint64_t *d, int64_t N, 
     uint64_t before = incl - s;
     for (int i = 0; i < w; i++) before += wsum[i];
 #pragma unroll
-    for (int i = 0; i < SORT_ITEMS; i++) {
+    for (int i = 0; i < SCAN_ITEMS; i++) {
         if (t0 + i < N) d[t0 + i] = before;
         before += x[i];
     }
@@ -363,39 +431,46 @@ __global__ __launch_bounds__(BLOCK) void k16_scan_tiles(uint64_t *d, int64_t N, 
 __global__ void k16_scan_add(uint64_t *d, int64_t N, const uint64_t *tile_off)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < N) d[i] += tile_off[i / SORT_TILE];
+    if (i < N) d[i] += tile_off[i / SCAN_TILE];
 }
 
 // ---------------------------------------------------------------------------
-// Radix sort of (64-bit word, uint32 index) pairs, 8 bits per pass
+// Radix sort of (64-bit word, uint32 index) pairs, RADIX_BITS bits per pass
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(BLOCK) void k16_hist(const uint64_t *keys, int64_t N, int shift, uint64_t *hist,
                                                   int64_t nblocks)
 {
     __shared__ uint32_t c[RADIX];
-    c[threadIdx.x] = 0;
+    for (int q = threadIdx.x; q < RADIX; q += BLOCK) c[q] = 0;
     __syncthreads();
     const int64_t t0 = (int64_t)blockIdx.x * SORT_TILE;
-#pragma unroll
+#pragma unroll 4
     for (int it = 0; it < SORT_ITEMS; it++) {
         const int64_t i = t0 + it * BLOCK + threadIdx.x;
         if (i < N) atomicAdd(&c[(keys[i] >> shift) & (RADIX - 1)], 1u);
     }
     __syncthreads();
-    hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = c[threadIdx.x];
+    for (int q = threadIdx.x; q < RADIX; q += BLOCK) hist[(int64_t)q * nblocks + blockIdx.x] = c[q];
 }
 
 // Stable scatter: the tile's elements are ranked in the order (item, wave,
 // lane), which is their index order; off[d * nblocks + b] is where digit d of
-// block b starts.
+// block b starts. Lanes of a wave with equal digits find each other by one
+// ballot per digit bit; the lowest such lane (the leader) publishes their
+// number, and after the item it adds it to the digit's running count and
+// clears its entry again.
 __global__ __launch_bounds__(BLOCK) void k16_scatter(const uint64_t *kin, const uint32_t *pin, uint64_t *kout,
                                                      uint32_t *pout, int64_t N, int shift, const uint64_t *off,
                                                      int64_t nblocks)
 {
     __shared__ uint32_t seen[RADIX];        // elements of each digit ranked so far in this tile
     __shared__ uint32_t wcnt[WPB][RADIX];   // this item's elements of each digit, per wave
-    const int w = threadIdx.x / WAVE, lane = lane_id();
-    seen[threadIdx.x] = 0;
+    const int w = threadIdx.x / WAVE;
+    for (int q = threadIdx.x; q < RADIX; q += BLOCK) {
+        seen[q] = 0;
+        for (int x = 0; x < WPB; x++) wcnt[x][q] = 0;
+    }
+    __syncthreads();
     const int64_t t0 = (int64_t)blockIdx.x * SORT_TILE;
     for (int it = 0; it < SORT_ITEMS; it++) {
         const int64_t i = t0 + it * BLOCK + threadIdx.x;
@@ -403,16 +478,16 @@ __global__ __launch_bounds__(BLOCK) void k16_scatter(const uint64_t *kin, const 
         const uint64_t key = valid ? kin[i] : 0;
         const uint32_t p = valid ? (pin ? pin[i] : (uint32_t)i) : 0;
         const uint32_t d = (uint32_t)(key >> shift) & (RADIX - 1);
-        for (int q = 0; q < RADIX / WAVE; q++) wcnt[w][lane + q * WAVE] = 0;
-        __builtin_amdgcn_wave_barrier();
         uint64_t peers = __ballot(valid);
 #pragma unroll
-        for (int b = 0; b < 8; b++) {
+        for (int b = 0; b < RADIX_BITS; b++) {
             const uint64_t ones = __ballot((d >> b) & 1u);
             peers &= ((d >> b) & 1u) ? ones : ~ones;
         }
         const uint64_t below = peers & lanemask_lt();
-        if (valid && below == 0) wcnt[w][d] = (uint32_t)__popcll(peers);
+        const bool leader = valid && below == 0;
+        const uint32_t cnt = (uint32_t)__popcll(peers);
+        if (leader) wcnt[w][d] = cnt;
         __syncthreads();
         if (valid) {
             uint64_t pos = off[(int64_t)d * nblocks + blockIdx.x] + seen[d] + (uint64_t)__popcll(below);
@@ -421,7 +496,10 @@ __global__ __launch_bounds__(BLOCK) void k16_scatter(const uint64_t *kin, const 
             pout[pos] = p;
         }
         __syncthreads();
-        seen[threadIdx.x] += wcnt[0][threadIdx.x] + wcnt[1][threadIdx.x] + wcnt[2][threadIdx.x] + wcnt[3][threadIdx.x];
+        if (leader) {
+            atomicAdd(&seen[d], cnt);
+            wcnt[w][d] = 0;
+        }
         __syncthreads();
     }
 }
@@ -435,52 +513,93 @@ __global__ void k16_heads(const uint64_t *keys, int64_t N, uint64_t *flag)
     if (i < N) flag[i] = (i == 0 || keys[i] != keys[i - 1]) ? 1u : 0u;
 }
 
-struct RedArgs {
+// x += v at p (two 64-bit atomics, the low word's carry passed on); true when
+// the 128-bit sum wraps
+__device__ inline bool atomic_add128(u128 *p, u128 v)
+{
+    unsigned long long *w = (unsigned long long *)p;
+    const unsigned long long lo = lo64(v), hi = hi64(v);
+    const unsigned long long old = atomicAdd(&w[0], lo);
+    const unsigned long long add_hi = hi + (old + lo < old ? 1ull : 0ull);
+    bool wrap = add_hi < hi;
+    if (add_hi) {
+        const unsigned long long oh = atomicAdd(&w[1], add_hi);
+        if (oh + add_hi < oh) wrap = true;
+    }
+    return wrap;
+}
+
+struct RunArgs {
     const uint64_t *keys;       // sorted words
     const uint32_t *perm;       // term index of each sorted word
     const u128 *tcnt;
-    const uint64_t *hpos;       // output index of each run head
+    const uint64_t *hpos;       // exclusive scan of the run heads: output index of each run
     int64_t N;
-    int KB, k, hlen;            // hlen = 2(h-1)
-    int x_level;                // 1: X_h (divide by beta_T, export key); 0: S_h (key kept)
+    int KB;
     int64_t v0;
-    uint64_t *okey;
-    u128 *ocnt;
+    u128 *ocnt;                 // [U] sums, zero on entry
+    uint64_t *oword;            // [U] the run's word
     int64_t *vcount;            // [n] entries per vertex
     int *err;
 };
 
-__global__ void k16_reduce(RedArgs A)
+// Sums of the runs of equal words: each term's count is fetched once, the
+// runs are summed within the wave by a segmented scan, and the last lane of
+// each run piece adds its partial sum to the run's output.
+__global__ __launch_bounds__(BLOCK) void k16_runsum(RunArgs A)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= A.N) return;
-    const uint64_t word = A.keys[i];
-    if (i > 0 && A.keys[i - 1] == word) return;
-    u128 sum = A.tcnt[A.perm[i]];
-    int bad = 0;
-    for (int64_t q = i + 1; q < A.N && A.keys[q] == word; q++) {
-        const u128 s = sum + A.tcnt[A.perm[q]];
-        if (s < sum) bad |= E16_OVERFLOW;
-        sum = s;
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    const int lane = lane_id();
+    const bool valid = i < A.N;
+    uint64_t word = 0, o = 0;
+    bool head = true;
+    u128 val = 0;
+    if (valid) {
+        word = A.keys[i];
+        head = i == 0 || A.keys[i - 1] != word;
+        val = A.tcnt[A.perm[i]];
+        o = A.hpos[i] - (head ? 0u : 1u);
     }
-    const uint64_t sk = word & ((1ull << A.KB) - 1ull);
-    const int64_t v = A.v0 + (int64_t)(word >> A.KB);
-    uint64_t key = sk;
-    if (A.x_level) {
-        const uint32_t s = (uint32_t)(sk >> A.k), C = (uint32_t)sk & ((1u << A.k) - 1u);
-        const uint32_t b = beta_of(s, A.hlen);
-        if (b > 1) {
-            const u128 qt = div_small(sum, b);
-            if (qt * b != sum) bad |= E16_BETA;
-            sum = qt;
+    bool wrap = false, f = head;
+    for (int d = 1; d < WAVE; d <<= 1) {
+        const u128 pv = mk128(__shfl_up((unsigned long long)lo64(val), d), __shfl_up((unsigned long long)hi64(val), d));
+        const bool pf = __shfl_up((int)f, d) != 0;
+        if (lane >= d) {
+            if (!f) {
+                const u128 t = val + pv;
+                if (t < val) wrap = true;
+                val = t;
+            }
+            f = f || pf;
         }
-        key = ((uint64_t)s << 16) | C;
     }
-    const uint64_t o = A.hpos[i];
-    A.okey[o] = key;
-    A.ocnt[o] = sum;
-    atomicAdd((unsigned long long *)&A.vcount[v], 1ull);
-    if (bad) atomicOr(A.err, bad);
+    const bool next_starts = __shfl_down((int)(head || !valid), 1) != 0;
+    if (valid && (lane == WAVE - 1 || next_starts)) wrap |= atomic_add128(&A.ocnt[o], val);
+    if (valid && head) {
+        A.oword[o] = word;
+        atomicAdd((unsigned long long *)&A.vcount[A.v0 + (int64_t)(word >> A.KB)], 1ull);
+    }
+    if (wrap) atomicOr(A.err, E16_OVERFLOW);
+}
+
+// The run words become keys; for X_h each sum is divided by beta_T.
+__global__ void k16_finish(uint64_t *okey, u128 *ocnt, int64_t U, int KB, int k, int hlen, int x_level, int *err)
+{
+    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= U) return;
+    const uint64_t sk = okey[o] & ((1ull << KB) - 1ull);
+    if (!x_level) {
+        okey[o] = sk;
+        return;
+    }
+    const uint32_t s = (uint32_t)(sk >> k), C = (uint32_t)sk & ((1u << k) - 1u);
+    const uint32_t b = beta_of(s, hlen);
+    if (b > 1) {
+        const u128 sum = ocnt[o], q = div_small(sum, b);
+        if (q * b != sum) atomicOr(err, E16_BETA);
+        ocnt[o] = q;
+    }
+    okey[o] = ((uint64_t)s << 16) | C;
 }
 
 // ---------------------------------------------------------------------------
@@ -626,7 +745,7 @@ scc_status scan_u64(scc16_table *T, uint64_t *d, int64_t N, uint64_t *total)
         HIP_TRY(hipMemsetAsync(total, 0, 8, T->stream));
         return SCC_OK;
     }
-    const int64_t nb = (N + SORT_TILE - 1) / SORT_TILE;
+    const int64_t nb = (N + SCAN_TILE - 1) / SCAN_TILE;
     if (nb == 1) {
         hipLaunchKernelGGL(k16_scan_tiles, dim3(1), dim3(BLOCK), 0, T->stream, d, N, total);
         return SCC_OK;
@@ -651,7 +770,7 @@ scc_status radix_sort(scc16_table *T, uint64_t **keys, uint64_t *keys_alt, uint3
     const int64_t nb = (N + SORT_TILE - 1) / SORT_TILE;
     uint64_t *kin = *keys, *kout = keys_alt;
     uint32_t *pin = nullptr, *pout = *perm, *pspare = perm_alt;
-    for (int shift = 0; shift < bits; shift += 8) {
+    for (int shift = 0; shift < bits; shift += RADIX_BITS) {
         hipLaunchKernelGGL(k16_hist, dim3((unsigned)nb), dim3(BLOCK), 0, T->stream, kin, N, shift, hist, nb);
         scc_status s = scan_u64(T, hist, nb * RADIX, total);
         if (s) return s;
@@ -802,8 +921,11 @@ scc_status build_pass(scc16_table *T, int x_level, int h, const Lev16 *S, Lev16 
             uint64_t *ok = (uint64_t *)parts_mem.get((size_t)U * 8);
             u128 *oc = (u128 *)parts_mem.get((size_t)U * 16);
             if (!ok || !oc) return set_error(SCC_ENOMEM, "level %d records", h);
-            RedArgs R{keys, perm, tc, flag, N, KB, k, 2 * (h - 1), x_level, v0, ok, oc, out.off, err};
-            hipLaunchKernelGGL(k16_reduce, dim3(blocks_for(N, 256)), dim3(256), 0, T->stream, R);
+            HIP_TRY(hipMemsetAsync(oc, 0, (size_t)U * 16, T->stream));
+            RunArgs R{keys, perm, tc, flag, N, KB, v0, oc, ok, out.off, err};
+            hipLaunchKernelGGL(k16_runsum, dim3(blocks_for(N, BLOCK)), dim3(BLOCK), 0, T->stream, R);
+            hipLaunchKernelGGL(k16_finish, dim3(blocks_for((int64_t)U, 256)), dim3(256), 0, T->stream, ok, oc, (int64_t)U,
+                               KB, k, 2 * (h - 1), x_level, err);
             HIP_TRY(hipGetLastError());
             parts.push_back({ok, oc});
             part_n.push_back((int64_t)U);
