@@ -351,8 +351,8 @@ def run_batching(a):
             t = scc.Table(g, c, k, validate=False)
             del t
 
-    def batched(xs):
-        tabs, rep = scc.build_batch(xs, autotune=True, validate=False)
+    def batched(xs, plain_nnz=0):
+        tabs, rep = scc.build_batch(xs, autotune=True, validate=False, plain_nnz=plain_nnz)
         del tabs
         return rep
 
@@ -367,22 +367,26 @@ def run_batching(a):
     for name, xs in groups.items():
         plain(xs)
         tuned[name] = batched(xs)      # tunes once per batch shape (probes); later calls reuse the choice
+        batched(xs, -1)
         r = tuned[name]
         print(f"# {name}: tuned tile={r['tile']} hub={r['hub_degree']} waves={r['waves']}", file=sys.stderr, flush=True)
     per = {}
     reps = []
     for name, xs in groups.items():
-        tp, tb = [], []
+        tp, tb, tq = [], [], []
         for i in range(a.steps):
             tp.append(timed(plain, xs)[0])
             dt, rep = timed(batched, xs)
             tb.append(dt)
+            tq.append(timed(batched, xs, -1)[0])
             if name == "all":
                 reps.append(rep)
-        per[name] = {"plain_s": sum(tp) / len(tp), "batched_s": sum(tb) / len(tb)}
+        per[name] = {"plain_s": sum(tp) / len(tp), "batched_s": sum(tb) / len(tb),
+                     "persistent_only_s": sum(tq) / len(tq), "plain_instances": rep["plain_instances"]}
         per[name]["speedup_vs_plain"] = per[name]["plain_s"] / per[name]["batched_s"]
-        print(f"# {name}: plain {per[name]['plain_s'] * 1e3:.1f} ms, batched {per[name]['batched_s'] * 1e3:.1f} ms",
-              file=sys.stderr, flush=True)
+        print(f"# {name}: plain {per[name]['plain_s'] * 1e3:.1f} ms, batched {per[name]['batched_s'] * 1e3:.1f} ms "
+              f"({rep['plain_instances']} instances on the level kernels), every instance in the persistent "
+              f"launch {per[name]['persistent_only_s'] * 1e3:.1f} ms", file=sys.stderr, flush=True)
     # full-size check: every batched table equals the plain build of its instance
     tabs, _ = scc.build_batch(inst, autotune=True, validate=False)
     equal = True
@@ -395,7 +399,9 @@ def run_batching(a):
     p_s, b_s = per["all"]["plain_s"], per["all"]["batched_s"]
     out = {
         "metric": "DP table build s & colorful-treelet samples/sec, batched/served vs plain",
-        "value": len(inst) / b_s, "unit": "tables built per second (one batched launch for all 48 instances)",
+        "value": len(inst) / b_s,
+        "unit": "tables built per second (the batch scheduler: instances of at least 2^21 CSR entries on the "
+                "level kernels, the rest in one persistent launch)",
         "n_gpus": 1, "steps": a.steps, "warmup": 1, "ms_per_step": b_s * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u64/u128", "data": "synthetic",
         "config": {"workload": "batching: 16 colourings of Chung-Lu n=5e5 m=5e6 exponent 2.2 + 32 ER/BA graphs "
@@ -567,6 +573,7 @@ def run_k16(a):
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / a.steps
     inf = infos[-1]
+    prof = profile_fields16("k16_k10_hbm_traffic.txt")
     sort_ms = sum(inf.sort_ms[h] for h in range(1, k + 1))
     sort_b = sum(inf.sort_bytes[h] for h in range(1, k + 1))
     print(f"# timed {a.steps} builds: {dt * 1e3:.1f} ms/build, sorts {sort_ms:.1f} ms", file=sys.stderr, flush=True)
@@ -587,7 +594,9 @@ def run_k16(a):
         "table_bytes": int(inf.bytes), "peak_bytes": int(inf.peak_bytes),
         "roofline": {"bound": "hbm", "achieved": sort_b / (sort_ms * 1e6) if sort_ms > 0 else None,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": sort_b / (sort_ms * 1e6) / HBM_PEAK_GBS if sort_ms > 0 else None, "traffic": None,
+                     "frac": sort_b / (sort_ms * 1e6) / HBM_PEAK_GBS if sort_ms > 0 else None,
+                     "traffic": float(prof["sort_traffic_bytes_per_build"]) if prof else None,
+                     "traffic_unit": "HBM bytes per build of k16_hist + k16_scatter from TCC_EA0 requests",
                      "kernel": "radix sort of the terms (k16_hist, k16_scatter and their scans): 32 B per "
                                "element and pass", "bytes_per_build": sort_b, "ms_per_build": sort_ms},
     }
@@ -1007,8 +1016,57 @@ def summarise_counters(label, ns, dir_a, dir_b):
     print(f"source_sha256 {h.hexdigest()}  (dp.hip + sample.hip + device.hpp at the time of the counter runs)")
 
 
+def summarise_counters16(label, dir_a, dir_b):
+    """HBM bytes per kernel of one k <= 16 build (every k16_* dispatch of the run),
+    from the same request counters as summarise_counters."""
+    import collections
+    import hashlib
+    A, B = _counter_dispatches(dir_a), _counter_dispatches(dir_b)
+    rd = lambda c: (32 * c.get("TCC_EA0_RDREQ_32B_sum", 0) + 64 * c.get("TCC_EA0_RDREQ_64B_sum", 0)
+                    + 128 * c.get("TCC_EA0_RDREQ_128B_sum", 0))
+    wr = lambda c: (32 * (c.get("TCC_EA0_WRREQ_sum", 0) - c.get("TCC_EA0_WRREQ_64B_sum", 0))
+                    + 64 * c.get("TCC_EA0_WRREQ_64B_sum", 0))
+    ba = [d for d in A if d["name"].startswith("k16_")]
+    bb = [d for d in B if d["name"].startswith("k16_")]
+    if [d["name"] for d in ba] != [d["name"] for d in bb]:
+        raise SystemExit("the two passes dispatched different kernels")
+    tot = collections.defaultdict(lambda: [0.0, 0.0, 0])
+    for da, db in zip(ba, bb):
+        t = tot[da["name"]]
+        t[0] += rd(da["c"])
+        t[1] += wr(db["c"])
+        t[2] += 1
+    h = hashlib.sha256(open(os.path.join(ROOT, "paper_2009_03052_amd", "csrc", "dp16.hip"), "rb").read())
+    print(f"workload: {label}")
+    print("per kernel of one build (HBM-side TCC_EA0 requests):")
+    print(f"  {'kernel':28s} {'dispatches':>10s} {'read MB':>12s} {'write MB':>12s}")
+    for nm, t in sorted(tot.items(), key=lambda x: -(x[1][0] + x[1][1])):
+        print(f"  {nm:28s} {t[2]:10d} {t[0] / 1e6:12.1f} {t[1] / 1e6:12.1f}")
+    sort = sum(t[0] + t[1] for nm, t in tot.items() if nm in ("k16_hist", "k16_scatter"))
+    print(f"traffic_bytes_per_build {sum(t[0] + t[1] for t in tot.values()):.0f}")
+    print(f"sort_traffic_bytes_per_build {sort:.0f}  (k16_hist + k16_scatter)")
+    print(f"source_sha256 {h.hexdigest()}  (dp16.hip at the time of the counter runs)")
+
+
+def profile_fields16(name):
+    """Fields of profiles/<name> when taken for the current dp16.hip, else None."""
+    import hashlib
+    try:
+        fields = {}
+        for line in open(os.path.join(ROOT, "profiles", name)):
+            parts = line.split()
+            if len(parts) >= 2:
+                fields[parts[0]] = parts[1]
+        h = hashlib.sha256(open(os.path.join(ROOT, "paper_2009_03052_amd", "csrc", "dp16.hip"), "rb").read())
+        return fields if fields.get("source_sha256") == h.hexdigest() else None
+    except OSError:
+        return None
+
+
 if __name__ == "__main__":
-    if len(sys.argv) > 2 and sys.argv[1] == "summarise" and sys.argv[2] == "trace":
+    if len(sys.argv) > 2 and sys.argv[1] == "summarise" and sys.argv[2] == "counters16":
+        summarise_counters16(sys.argv[3], sys.argv[4], sys.argv[5])
+    elif len(sys.argv) > 2 and sys.argv[1] == "summarise" and sys.argv[2] == "trace":
         summarise_trace(sys.argv[3])
     elif len(sys.argv) > 2 and sys.argv[1] == "summarise" and sys.argv[2] == "counters":
         summarise_counters(sys.argv[3], int(sys.argv[4]), sys.argv[5], sys.argv[6])

@@ -431,6 +431,9 @@ typedef struct {
                           batch and keep the fastest for later batches of the same shape */
     int waves;         /* worker register budget: 8 = eight waves per SIMD (a few spills),
                           0 = tuned or the compiler's own (about five waves per SIMD) */
+    int64_t plain_nnz; /* instances with at least this many CSR entries are built by the
+                          level kernels, one after another, before the persistent launch
+                          (which holds the others); 0 = 2^21, negative = none */
 } scc_batch_opts;
 
 typedef struct {
@@ -445,6 +448,8 @@ typedef struct {
     int nprobe;
     int probe_tile[16], probe_hub[16], probe_waves[16];
     double probe_ms[16];
+    int plain_instances;       /* instances built by the level kernels (plain_nnz) */
+    double plain_ms;           /* host-observed time of those builds */
 } scc_batch_report;
 
 /*
@@ -452,7 +457,9 @@ typedef struct {
  * (graphs x colourings x k) in one persistent launch. The multi-threaded
  * build of Sec. 3.4 assigns vertices to a thread pool; here vertex tiles of
  * every instance and level are work items of one resident grid, ordered so
- * that an item only waits for earlier ones. Each out[i] receives a table equal
+ * that an item only waits for earlier ones. Instances with at least
+ * bopt->plain_nnz CSR entries (large enough to fill the GPU alone) are built by
+ * the level kernels of scc_build_table instead, before that launch. Each out[i] receives a table equal
  * to what scc_build_table would build for instance i with the same options
  * (bit for bit). opt applies to every instance (rooting, max_bits, stream,
  * allocator; hub_degree and validate are ignored: the schedule decides the

@@ -56,7 +56,8 @@ class _Instance(C.Structure):
 
 
 class _BatchOpts(C.Structure):
-    _fields_ = [("tile", C.c_int), ("hub_degree", C.c_int), ("autotune", C.c_int), ("waves", C.c_int)]
+    _fields_ = [("tile", C.c_int), ("hub_degree", C.c_int), ("autotune", C.c_int), ("waves", C.c_int),
+                ("plain_nnz", C.c_int64)]
 
 
 class BatchReport(C.Structure):
@@ -64,12 +65,13 @@ class BatchReport(C.Structure):
                 ("grid", C.c_int), ("items", C.c_int64), ("launch_ms", C.c_double), ("pack_ms", C.c_double),
                 ("total_ms", C.c_double), ("setup_ms", C.c_double), ("nprobe", C.c_int),
                 ("probe_tile", C.c_int * 16), ("probe_hub", C.c_int * 16), ("probe_waves", C.c_int * 16),
-                ("probe_ms", C.c_double * 16)]
+                ("probe_ms", C.c_double * 16), ("plain_instances", C.c_int), ("plain_ms", C.c_double)]
 
     def as_dict(self):
         return {"tile": self.tile, "hub_degree": self.hub_degree, "waves": self.waves, "tuned": bool(self.tuned),
                 "grid": self.grid, "items": self.items, "launch_ms": self.launch_ms, "pack_ms": self.pack_ms,
-                "total_ms": self.total_ms, "setup_ms": self.setup_ms,
+                "total_ms": self.total_ms, "setup_ms": self.setup_ms, "plain_instances": self.plain_instances,
+                "plain_ms": self.plain_ms,
                 "probes": [(self.probe_tile[i], self.probe_hub[i], self.probe_waves[i], self.probe_ms[i])
                            for i in range(self.nprobe)]}
 
@@ -466,9 +468,10 @@ class Table16:
 
 def build_batch(instances, rooting: int = ROOT_ZERO, max_bits: int = 128, tile: int = 0, hub_degree: int = 0,
                 autotune: bool = False, stream=None, use_torch_allocator: bool = True, waves: int = 0,
-                validate: bool = True):
+                validate: bool = True, plain_nnz: int = 0):
     """``scc_build_batch``: instances is a list of (DeviceGraph, colours, k).
-    Returns ([Table], report dict)."""
+    Instances with at least ``plain_nnz`` CSR entries (0: 2^21; -1: none) are built by
+    the level kernels, the others in one persistent launch. Returns ([Table], report dict)."""
     n = len(instances)
     arr = (_Instance * n)()
     keep = []
@@ -479,7 +482,7 @@ def build_batch(instances, rooting: int = ROOT_ZERO, max_bits: int = 128, tile: 
         arr[i] = _Instance(_Csr(g.n, g.nnz, g.row_ptr.data_ptr(), g.col_idx.data_ptr(), 1), col.data_ptr(), k)
     opts = _BuildOpts(rooting, max_bits, _stream_ptr(stream),
                       C.pointer(TORCH_ALLOCATOR) if use_torch_allocator else None, 0, 0 if validate else 1)
-    bo = _BatchOpts(tile, hub_degree, 1 if autotune else 0, waves)
+    bo = _BatchOpts(tile, hub_degree, 1 if autotune else 0, waves, plain_nnz)
     outs = (_P * n)()
     rep = BatchReport()
     _check(_lib.scc_build_batch(arr, n, C.byref(opts), C.byref(bo), outs, C.byref(rep)))

@@ -3159,11 +3159,63 @@ static scc_status batch_launch(std::vector<BatchInstHost> &H, int tile, int hub_
     return SCC_OK;
 }
 
+static scc_status batch_persistent(const scc_instance *inst, int n_inst, const scc_build_opts *opt,
+                                   const scc_batch_opts *bopt, scc_table **out, scc_batch_report *rep);
+
+// The batch scheduler: instances with at least plain_nnz CSR entries are built
+// one after another by the level kernels (exactly as scc_build_table builds
+// them), the others together in one persistent launch.
 extern "C" scc_status scc_build_batch(const scc_instance *inst, int n_inst, const scc_build_opts *opt,
                                       const scc_batch_opts *bopt, scc_table **out, scc_batch_report *rep)
 {
     if (!inst || !out || n_inst < 1) return set_error(SCC_EINVAL, "bad batch arguments");
     for (int i = 0; i < n_inst; i++) out[i] = nullptr;
+    scc_batch_opts bo{};
+    if (bopt) bo = *bopt;
+    const int64_t plain_nnz = bo.plain_nnz > 0 ? bo.plain_nnz : (bo.plain_nnz < 0 ? INT64_MAX : ((int64_t)1 << 21));
+    std::vector<int> plain, pers;
+    for (int i = 0; i < n_inst; i++) (inst[i].g.nnz >= plain_nnz ? plain : pers).push_back(i);
+    scc_batch_report R{};
+    auto free_out = [&]() {
+        for (int i = 0; i < n_inst; i++) {
+            scc_table_destroy(out[i]);
+            out[i] = nullptr;
+        }
+    };
+    auto t0 = std::chrono::steady_clock::now();
+    for (int i : plain) {
+        scc_build_opts po{};
+        if (opt) po = *opt;
+        po.hub_degree = 0;
+        if (po.rooting == SCC_ROOT_BALANCED) return set_error(SCC_EINVAL, "round skipping is not supported by the batched build");
+        po.vlc = 0;
+        scc_status s = scc_build_table(&inst[i].g, inst[i].colors, inst[i].k, &po, &out[i]);
+        if (s) {
+            free_out();
+            return s;
+        }
+    }
+    const double plain_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (!pers.empty()) {
+        std::vector<scc_instance> sub;
+        for (int i : pers) sub.push_back(inst[i]);
+        std::vector<scc_table *> sout(pers.size(), nullptr);
+        scc_status s = batch_persistent(sub.data(), (int)sub.size(), opt, &bo, sout.data(), &R);
+        if (s) {
+            free_out();
+            return s;
+        }
+        for (size_t q = 0; q < pers.size(); q++) out[pers[q]] = sout[q];
+    }
+    R.plain_instances = (int)plain.size();
+    R.plain_ms = plain_ms;
+    if (rep) *rep = R;
+    return SCC_OK;
+}
+
+static scc_status batch_persistent(const scc_instance *inst, int n_inst, const scc_build_opts *opt,
+                                   const scc_batch_opts *bopt, scc_table **out, scc_batch_report *rep)
+{
     scc_build_opts o{};
     if (opt) o = *opt;
     if (o.max_bits == 0) o.max_bits = 128;

@@ -2,8 +2,8 @@
 
 Every instance of a batch must give the same table as scc_build_table on its
 own: every level, totals, and the sample stream. Batches mix graph families,
-sizes and k, force the chunked hub path and ragged vertex tiles, and run the
-autotuner.
+sizes and k, force the chunked hub path and ragged vertex tiles, run the
+autotuner, and route instances above a size to the level kernels.
 """
 from __future__ import annotations
 
@@ -124,3 +124,25 @@ def test_batch_zero_rooting_colour_zero_sparse():
     tabs, _ = S.build_batch(dev, tile=100, hub_degree=64, waves=8)
     for (g, c, k), bt in zip(inst, tabs):
         assert_tables_equal(bt, O.Table(g, c, k, O.ROOT_ZERO), k, f"batch colour-0 n={g.n} k={k}")
+
+
+@pytest.mark.parametrize("plain_nnz", [5000, 1, -1])
+def test_batch_scheduler_routes_large_instances_to_the_level_kernels(plain_nnz):
+    # instances with at least plain_nnz CSR entries are built by the level
+    # kernels before the persistent launch; every table is the same either way
+    S = scc()
+    inst = instances(seed0=200)
+    dev = [(S.DeviceGraph.from_graph(g), c, k) for g, c, k in inst]
+    tabs, rep = S.build_batch(dev, plain_nnz=plain_nnz, tile=64, hub_degree=1024)
+    want = sum(1 for g, _, _ in inst if plain_nnz > 0 and g.nnz >= plain_nnz)
+    assert rep["plain_instances"] == want
+    if want < len(inst):
+        assert rep["items"] > 0
+    for (g, c, k), bt in zip(inst, tabs):
+        pt = plain(S, g, c, k, 0)
+        for h in range(1, k + 1):
+            for x, y in zip(bt.export_level(h), pt.export_level(h)):
+                assert np.array_equal(x, y), (g.n, k, h)
+        assert bt.totals() == pt.totals()
+    for (g, c, k), bt in list(zip(inst, tabs))[:4]:
+        assert_tables_equal(bt, O.Table(g, c, k, O.ROOT_ZERO), k, f"scheduled batch n={g.n} k={k}")
