@@ -596,6 +596,8 @@ def run_k16(a):
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": sort_b / (sort_ms * 1e6) / HBM_PEAK_GBS if sort_ms > 0 else None,
                      "traffic": float(prof["sort_traffic_bytes_per_build"]) if prof else None,
+                     "traffic_gbs": (float(prof["sort_traffic_bytes_per_build"]) / (sort_ms * 1e6)
+                                     if prof and sort_ms > 0 else None),
                      "traffic_unit": "HBM bytes per build of k16_hist + k16_scatter from TCC_EA0 requests",
                      "kernel": "radix sort of the terms (k16_hist, k16_scatter and their scans): 32 B per "
                                "element and pass", "bytes_per_build": sort_b, "ms_per_build": sort_ms},
@@ -718,8 +720,13 @@ def rooflines(tab, infos, k, samp_ms, ns, prof):
     def entry(bytes_, ms, kernel, traffic_key=None):
         ach = bytes_ / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
         tr = float(prof[traffic_key]) if (prof and traffic_key and traffic_key in prof) else None
-        return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-                "traffic": tr, "kernel": kernel, "bytes_per_build": bytes_, "ms_per_build": ms}
+        out = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+               "traffic": tr, "kernel": kernel, "bytes_per_build": bytes_, "ms_per_build": ms}
+        if tr is not None and ms > 0:
+            # what the memory system moved: the counters' bytes over the same duration
+            out["traffic_gbs"] = tr / (ms * 1e-3) / 1e9
+            out["traffic_frac"] = out["traffic_gbs"] / HBM_PEAK_GBS
+        return out
 
     join = entry(j_bytes, j_ms, "DP join: k_gather1, k_gather*, k_hub_prepare, k_combine*, k_words, scans, k_pack, "
                  "k_totals and scans (every level of the build plus the level-k totals)", "traffic_bytes_per_build")
