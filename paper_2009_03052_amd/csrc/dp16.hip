@@ -43,7 +43,7 @@ constexpr int SCAN_ITEMS = 8;
 constexpr int SCAN_TILE = BLOCK * SCAN_ITEMS;   // elements per scan block
 constexpr int RADIX_BITS = 8;                   // digit width of the radix sort
 constexpr int RADIX = 1 << RADIX_BITS;
-constexpr int SORT_ITEMS = 8;
+constexpr int SORT_ITEMS = 16;
 constexpr int SORT_TILE = BLOCK * SORT_ITEMS;   // elements per sort block
 constexpr int64_t DEFAULT_CHUNK_TERMS = (int64_t)1 << 26;
 constexpr int64_t MAX_CHUNK_TERMS = ((int64_t)1 << 31) - 1;   // sort permutations are uint32
@@ -545,7 +545,8 @@ struct RunArgs {
 
 // Sums of the runs of equal words: each term's count is fetched once, the
 // runs are summed within the wave by a segmented scan, and the last lane of
-// each run piece adds its partial sum to the run's output.
+// each run piece writes it: a run that lies wholly in the wave is stored, a
+// piece of a longer run is added to the run's output atomically.
 __global__ __launch_bounds__(BLOCK) void k16_runsum(RunArgs A)
 {
     const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
@@ -574,7 +575,12 @@ __global__ __launch_bounds__(BLOCK) void k16_runsum(RunArgs A)
         }
     }
     const bool next_starts = __shfl_down((int)(head || !valid), 1) != 0;
-    if (valid && (lane == WAVE - 1 || next_starts)) wrap |= atomic_add128(&A.ocnt[o], val);
+    if (valid && (lane == WAVE - 1 || next_starts)) {
+        // f: the run's head lies in this wave at or before this lane
+        const bool ends = lane < WAVE - 1 || i + 1 >= A.N || A.keys[i + 1] != word;
+        if (f && ends) A.ocnt[o] = val;
+        else wrap |= atomic_add128(&A.ocnt[o], val);
+    }
     if (valid && head) {
         A.oword[o] = word;
         atomicAdd((unsigned long long *)&A.vcount[A.v0 + (int64_t)(word >> A.KB)], 1ull);
