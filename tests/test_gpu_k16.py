@@ -190,3 +190,58 @@ def test_star_closed_form_beyond_64_bits():
         assert C & 1 and C >> cl & 1
         others = [c for c in range(1, k) if C >> c & 1 and c != cl]
         assert int(lo[q]) | (int(hi[q]) << 64) == prod(int(sizes[c]) for c in others)
+
+
+def _ball(g, v, r):
+    """Vertices within distance r of v (v first)."""
+    seen = {v: 0}
+    order = [v]
+    frontier = [v]
+    for d in range(r):
+        nxt = []
+        for x in frontier:
+            for u in g.col_idx[g.row_ptr[x]:g.row_ptr[x + 1]]:
+                u = int(u)
+                if u not in seen:
+                    seen[u] = d + 1
+                    order.append(u)
+                    nxt.append(u)
+        frontier = nxt
+    return order
+
+
+def test_bench_workload_properties():
+    # the k16 bench workload (Chung-Lu n = 65536, m = 131072, k = 10) at full size:
+    # (1) zero-rooting and all rootings build identical levels 1..k-1 and the same t
+    #     (each colourful copy has one colour-0 vertex, and k roots);
+    # (2) a vertex's level-h record depends only on its ball of radius h-1, so for
+    #     sampled vertices levels 2..4 equal the oracle's on that induced ball
+    import torch
+    g = gg.chung_lu(1 << 16, 1 << 17, 2.5, 40.0, seed=7)
+    k = 10
+    colors = gg.colors(g.n, k, seed=17)
+    dg = scc.DeviceGraph.from_graph(g)
+    tz = scc.Table16(dg, colors, k, rooting=scc.ROOT_ZERO)
+    ta = scc.Table16(dg, colors, k, rooting=scc.ROOT_ALL)
+    assert tz.total() == ta.total() > 0
+    for h in range(1, k):
+        a, b = tz.export_level(h, to_host=False), ta.export_level(h, to_host=False)
+        assert all(torch.equal(x, y) for x, y in zip(a, b)), h
+        del a, b
+    levels = {h: tz.export_level(h) for h in (2, 3, 4)}
+    rng = np.random.default_rng(3)
+    deg = np.diff(g.row_ptr)
+    picks = [int(np.argmax(deg))] + [int(x) for x in rng.choice(g.n, 12, replace=False)]
+    for v in picks:
+        ball = _ball(g, v, 3)
+        pos = {u: i for i, u in enumerate(ball)}
+        edges = [(pos[x], pos[int(u)]) for x in ball for u in g.col_idx[g.row_ptr[x]:g.row_ptr[x + 1]]
+                 if int(u) in pos and pos[x] < pos[int(u)]]
+        sub = gg.csr_from_edges(len(ball), np.array(edges, np.int64).reshape(-1, 2))
+        ot = O.Table16(sub, colors[ball], k, O.ROOT_ALL)
+        for h in (2, 3, 4):
+            off, key, lo, hi = levels[h]
+            oo, ok, ol, oh = ot.export_level(h)
+            a, b = off[v], off[v + 1]
+            assert np.array_equal(key[a:b], ok[oo[0]:oo[1]]), (v, h)
+            assert np.array_equal(lo[a:b], ol[oo[0]:oo[1]]) and np.array_equal(hi[a:b], oh[oo[0]:oo[1]]), (v, h)
