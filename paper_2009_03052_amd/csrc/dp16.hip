@@ -543,48 +543,102 @@ struct RunArgs {
     int *err;
 };
 
-// Sums of the runs of equal words: each term's count is fetched once, the
-// runs are summed within the wave by a segmented scan, and the last lane of
-// each run piece writes it: a run that lies wholly in the wave is stored, a
-// piece of a longer run is added to the run's output atomically.
+// Sums of the runs of equal words. Each thread takes RUN_ITEMS consecutive
+// sorted terms and fetches their counts (independent loads); it sums the
+// elements after its last run head, the wave passes those partial sums on by a
+// segmented scan over lanes, and the last element of each run piece writes the
+// piece's sum: a run that lies wholly in the wave's range is stored, a piece of
+// a longer run is added to the run's output atomically.
+constexpr int RUN_ITEMS = 4;
+
 __global__ __launch_bounds__(BLOCK) void k16_runsum(RunArgs A)
 {
-    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     const int lane = lane_id();
-    const bool valid = i < A.N;
-    uint64_t word = 0, o = 0;
-    bool head = true;
-    u128 val = 0;
-    if (valid) {
-        word = A.keys[i];
-        head = i == 0 || A.keys[i - 1] != word;
-        val = A.tcnt[A.perm[i]];
-        o = A.hpos[i] - (head ? 0u : 1u);
+    const int64_t i0 = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) * RUN_ITEMS;
+    uint64_t word[RUN_ITEMS], o[RUN_ITEMS];
+    u128 val[RUN_ITEMS];
+    bool head[RUN_ITEMS], valid[RUN_ITEMS];
+    uint64_t prev = i0 > 0 && i0 < A.N ? A.keys[i0 - 1] : 0;
+#pragma unroll
+    for (int j = 0; j < RUN_ITEMS; j++) {
+        const int64_t i = i0 + j;
+        valid[j] = i < A.N;
+        word[j] = valid[j] ? A.keys[i] : 0;
+        head[j] = valid[j] && (i == 0 || (j == 0 ? prev : word[j - 1]) != word[j]);
     }
-    bool wrap = false, f = head;
+#pragma unroll
+    for (int j = 0; j < RUN_ITEMS; j++) {
+        const int64_t i = i0 + j;
+        val[j] = valid[j] ? A.tcnt[A.perm[i]] : (u128)0;
+        o[j] = valid[j] ? A.hpos[i] - (head[j] ? 0u : 1u) : 0u;
+    }
+    bool wrap = false, any = false;
+    u128 tail = 0;   // this thread's elements after its last head (all of them without one)
+#pragma unroll
+    for (int j = 0; j < RUN_ITEMS; j++) {
+        if (head[j]) {
+            tail = val[j];
+            any = true;
+        } else {
+            const u128 t = tail + val[j];
+            wrap |= t < tail;
+            tail = t;
+        }
+    }
+    // inclusive segmented scan of (tail, any) over the lanes
+    u128 c = tail;
+    bool f = any;
     for (int d = 1; d < WAVE; d <<= 1) {
-        const u128 pv = mk128(__shfl_up((unsigned long long)lo64(val), d), __shfl_up((unsigned long long)hi64(val), d));
+        const u128 pv = mk128(__shfl_up((unsigned long long)lo64(c), d), __shfl_up((unsigned long long)hi64(c), d));
         const bool pf = __shfl_up((int)f, d) != 0;
         if (lane >= d) {
             if (!f) {
-                const u128 t = val + pv;
-                if (t < val) wrap = true;
-                val = t;
+                const u128 t = c + pv;
+                wrap |= t < c;
+                c = t;
             }
             f = f || pf;
         }
     }
-    const bool next_starts = __shfl_down((int)(head || !valid), 1) != 0;
-    if (valid && (lane == WAVE - 1 || next_starts)) {
-        // f: the run's head lies in this wave at or before this lane
-        const bool ends = lane < WAVE - 1 || i + 1 >= A.N || A.keys[i + 1] != word;
-        if (f && ends) A.ocnt[o] = val;
-        else wrap |= atomic_add128(&A.ocnt[o], val);
+    // what the lanes before this one carry into its first run, and whether that
+    // run's head lies in the wave's range
+    u128 run = mk128(__shfl_up((unsigned long long)lo64(c), 1), __shfl_up((unsigned long long)hi64(c), 1));
+    bool seen = __shfl_up((int)f, 1) != 0;
+    if (lane == 0) {
+        run = 0;
+        seen = false;
     }
-    if (valid && head) {
-        A.oword[o] = word;
-        atomicAdd((unsigned long long *)&A.vcount[A.v0 + (int64_t)(word >> A.KB)], 1ull);
+    const bool next_lane_starts = __shfl_down((int)(head[0] || !valid[0]), 1) != 0;
+#pragma unroll
+    for (int j = 0; j < RUN_ITEMS; j++) {
+        if (!valid[j]) break;
+        if (head[j]) {
+            run = val[j];
+            seen = true;
+        } else {
+            const u128 t = run + val[j];
+            wrap |= t < run;
+            run = t;
+        }
+        bool ends, piece_end;
+        if (j < RUN_ITEMS - 1) {
+            ends = piece_end = !valid[j + 1] || head[j + 1];
+        } else if (lane < WAVE - 1) {
+            ends = piece_end = next_lane_starts;
+        } else {
+            piece_end = true;
+            ends = i0 + j + 1 >= A.N || A.keys[i0 + j + 1] != word[j];
+        }
+        if (!piece_end) continue;
+        if (seen && ends) A.ocnt[o[j]] = run;
+        else wrap |= atomic_add128(&A.ocnt[o[j]], run);
     }
+#pragma unroll
+    for (int j = 0; j < RUN_ITEMS; j++)
+        if (head[j]) {
+            A.oword[o[j]] = word[j];
+            atomicAdd((unsigned long long *)&A.vcount[A.v0 + (int64_t)(word[j] >> A.KB)], 1ull);
+        }
     if (wrap) atomicOr(A.err, E16_OVERFLOW);
 }
 
@@ -929,7 +983,7 @@ scc_status build_pass(scc16_table *T, int x_level, int h, const Lev16 *S, Lev16 
             if (!ok || !oc) return set_error(SCC_ENOMEM, "level %d records", h);
             HIP_TRY(hipMemsetAsync(oc, 0, (size_t)U * 16, T->stream));
             RunArgs R{keys, perm, tc, flag, N, KB, v0, oc, ok, out.off, err};
-            hipLaunchKernelGGL(k16_runsum, dim3(blocks_for(N, BLOCK)), dim3(BLOCK), 0, T->stream, R);
+            hipLaunchKernelGGL(k16_runsum, dim3(blocks_for(N, BLOCK * RUN_ITEMS)), dim3(BLOCK), 0, T->stream, R);
             hipLaunchKernelGGL(k16_finish, dim3(blocks_for((int64_t)U, 256)), dim3(256), 0, T->stream, ok, oc, (int64_t)U,
                                KB, k, 2 * (h - 1), x_level, err);
             HIP_TRY(hipGetLastError());
