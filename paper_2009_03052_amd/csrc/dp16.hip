@@ -278,6 +278,10 @@ __global__ __launch_bounds__(BLOCK) void k16_comb(CombArgs A)
     __shared__ uint32_t dir_st[WPB][DIR_MAX];
     __shared__ uint32_t dir_en[WPB][DIR_MAX];
     __shared__ uint16_t binom_t[K16][K16 + 1];     // binom(p, q), p < 16, q <= 16
+    // the lanes' own entries and ranges for the directory path (one set per wave)
+    __shared__ uint32_t own_sp[WPB][WAVE], own_c1[WPB][WAVE], own_lc[WPB][WAVE], own_cd[WPB][WAVE];
+    __shared__ uint32_t own_st[WPB][WAVE], own_ex[WPB][WAVE];
+    __shared__ uint64_t own_cxl[WPB][WAVE], own_cxh[WPB][WAVE];
     for (int q = threadIdx.x; q < K16 * (K16 + 1); q += BLOCK) {
         const int pp = q / (K16 + 1), qq = q % (K16 + 1);
         binom_t[pp][qq] = (uint16_t)binom_small(pp, qq);
@@ -334,6 +338,98 @@ __global__ __launch_bounds__(BLOCK) void k16_comb(CombArgs A)
                 }
                 __builtin_amdgcn_wave_barrier();
             }
+            if (mode == 1) {
+                // directory path, one colour subset per lane at a time: the lanes'
+                // ranges of sums are laid end to end and the wave takes 64 sums per
+                // round, so the lanes stay together and slots come from one ballot
+                for (int64_t x0 = xa; x0 < xb; x0 += WAVE) {
+                    const int64_t x = x0 + lane;
+                    const bool xv = x < xb;
+                    uint32_t Cp = 0, sp = 0, c1 = 0, freec = 0;
+                    int lc = 0;
+                    u128 cx = 0;
+                    uint64_t pos = 0;
+                    if (xv) {
+                        const uint64_t kx = X.key[x];
+                        Cp = (uint32_t)kx & 0xffffu;
+                        sp = (uint32_t)(kx >> 16);
+                        lc = first_word_len(sp, lp);
+                        c1 = lc ? sp >> (lp - lc) : 0u;
+                        cx = X.cnt[x];
+                        freec = compress_out(full & ~Cp, cv);
+                        int t = 0;
+                        for (uint32_t f = freec; f; f &= f - 1u, t++) pos |= (uint64_t)__builtin_ctz(f) << (4 * t);
+                    }
+                    own_sp[w][lane] = sp;
+                    own_c1[w][lane] = c1;
+                    own_lc[w][lane] = (uint32_t)lc;
+                    own_cxl[w][lane] = lo64(cx);
+                    own_cxh[w][lane] = hi64(cx);
+                    for (uint32_t idx = (1u << j) - 1u; idx < (1u << m); idx = next_comb(idx)) {
+                        uint32_t st = 0, cntd = 0, D = 0;
+                        if (xv) {
+                            uint32_t Dc = 0, r = 0;
+                            int t = 1;
+                            for (uint32_t b = idx; b; b &= b - 1u, t++) {
+                                const int p = (int)((pos >> (4 * __builtin_ctz(b))) & 15u);
+                                Dc |= 1u << p;
+                                r += binom_t[p][t];
+                            }
+                            st = dir_st[w][r];
+                            cntd = dir_en[w][r] - st;
+                            D = expand_in(Dc, cv);
+                        }
+                        const uint32_t incl = wave_incl_scan32(cntd);
+                        const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, WAVE - 1);
+                        if (total == 0) continue;
+                        own_st[w][lane] = st;
+                        own_ex[w][lane] = incl - cntd;
+                        own_cd[w][lane] = Cp | D;
+                        __builtin_amdgcn_wave_barrier();
+                        for (uint32_t f0 = 0; f0 < total; f0 += WAVE) {
+                            const uint32_t f = f0 + lane;
+                            bool keep = false;
+                            uint64_t okey = 0;
+                            u128 prod = 0;
+                            if (f < total) {
+                                int lo = 0, hi = WAVE - 1;   // the last lane whose range starts at or before f
+                                while (lo < hi) {
+                                    const int mid = (lo + hi + 1) >> 1;
+                                    if (own_ex[w][mid] <= f) lo = mid; else hi = mid - 1;
+                                }
+                                const int64_t e = sa + own_st[w][lo] + (f - own_ex[w][lo]);
+                                const uint64_t ks = S.key[e];
+                                const uint32_t wd = (1u << (lw - 1)) | (((uint32_t)ks & smask) << 1);
+                                if (word_not_smaller(wd, lw, own_c1[w][lo], (int)own_lc[w][lo])) {
+                                    keep = true;
+                                    if (EMIT) {
+                                        const uint64_t sT = ((uint64_t)wd << lp) | own_sp[w][lo];
+                                        okey = vl | (sT << A.k) | (uint64_t)own_cd[w][lo];
+                                        prod = mul_checked(mk128(own_cxl[w][lo], own_cxh[w][lo]), S.cnt[e], ovf);
+                                    }
+                                }
+                            }
+                            if (EMIT) {
+                                const uint64_t mk = __ballot(keep);
+                                const uint64_t b0 = ctr[w];
+                                if (keep) {
+                                    const uint64_t q = (uint64_t)base + b0 + (uint64_t)__popcll(mk & lanemask_lt());
+                                    A.tkey[q] = okey;
+                                    A.tcnt[q] = prod;
+                                }
+                                __builtin_amdgcn_wave_barrier();
+                                if (lane == 0) ctr[w] = b0 + (uint64_t)__popcll(mk);
+                                __builtin_amdgcn_wave_barrier();
+                            } else {
+                                nterms += keep ? 1u : 0u;
+                            }
+                        }
+                        __builtin_amdgcn_wave_barrier();
+                    }
+                }
+                __builtin_amdgcn_wave_barrier();
+                continue;
+            }
             for (int64_t x = xa + lane; x < xb; x += WAVE) {
                 const uint64_t kx = X.key[x];
                 const uint32_t Cp = (uint32_t)kx & 0xffffu, sp = (uint32_t)(kx >> 16);
@@ -354,26 +450,6 @@ __global__ __launch_bounds__(BLOCK) void k16_comb(CombArgs A)
                     for (int64_t e = sa; e < se; e++) {
                         const uint32_t D = (uint32_t)(S.key[e] >> sb);
                         if (!(D & Cp)) term(e, D);
-                    }
-                } else if (mode == 1) {
-                    // the free colours, in the (k-1)-colour universe, as 4-bit positions
-                    const uint32_t freec = compress_out(full & ~Cp, cv);
-                    uint64_t pos = 0;
-                    {
-                        int t = 0;
-                        for (uint32_t f = freec; f; f &= f - 1u, t++) pos |= (uint64_t)__builtin_ctz(f) << (4 * t);
-                    }
-                    for (uint32_t idx = (1u << j) - 1u; idx < (1u << m); idx = next_comb(idx)) {
-                        uint32_t Dc = 0, r = 0;
-                        int t = 1;
-                        for (uint32_t b = idx; b; b &= b - 1u, t++) {
-                            const int p = (int)((pos >> (4 * __builtin_ctz(b))) & 15u);
-                            Dc |= 1u << p;
-                            r += binom_t[p][t];
-                        }
-                        const int64_t e1 = sa + dir_en[w][r];
-                        const uint32_t D = expand_in(Dc, cv);
-                        for (int64_t e = sa + dir_st[w][r]; e < e1; e++) term(e, D);
                     }
                 } else {
                     const uint32_t freec = full & ~Cp;
