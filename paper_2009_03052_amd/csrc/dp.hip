@@ -21,6 +21,9 @@
 #include "table.hpp"
 
 #include <map>
+#include <mutex>
+#include <string>
+#include <thread>
 
 namespace {
 
@@ -3162,9 +3165,27 @@ static scc_status batch_launch(std::vector<BatchInstHost> &H, int tile, int hub_
 static scc_status batch_persistent(const scc_instance *inst, int n_inst, const scc_build_opts *opt,
                                    const scc_batch_opts *bopt, scc_table **out, scc_batch_report *rep);
 
+// A second stream per device for the batch scheduler (created once, default
+// priority, not synchronised with the legacy default stream).
+static hipStream_t aux_stream(int dev)
+{
+    static std::mutex mu;
+    static std::map<int, hipStream_t> streams;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = streams.find(dev);
+    if (it != streams.end()) return it->second;
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return nullptr;
+    streams[dev] = s;
+    return s;
+}
+
 // The batch scheduler: instances with at least plain_nnz CSR entries are built
 // one after another by the level kernels (exactly as scc_build_table builds
-// them), the others together in one persistent launch.
+// them), the others together in one persistent launch. When there are both,
+// the persistent launch runs from a second host thread on a second stream
+// while the level kernels run, and its tables are handed back on the caller's
+// stream.
 extern "C" scc_status scc_build_batch(const scc_instance *inst, int n_inst, const scc_build_opts *opt,
                                       const scc_batch_opts *bopt, scc_table **out, scc_batch_report *rep)
 {
@@ -3182,31 +3203,68 @@ extern "C" scc_status scc_build_batch(const scc_instance *inst, int n_inst, cons
             out[i] = nullptr;
         }
     };
+    if (opt && opt->rooting == SCC_ROOT_BALANCED)
+        return set_error(SCC_EINVAL, "round skipping is not supported by the batched build");
+    std::vector<scc_instance> sub;
+    for (int i : pers) sub.push_back(inst[i]);
+    std::vector<scc_table *> sout(pers.size(), nullptr);
+    scc_build_opts popt{};
+    if (opt) popt = *opt;
+    const hipStream_t caller = (hipStream_t)popt.stream;
+    scc_status sp = SCC_OK;
+    std::string perr;
+    std::thread worker;
+    if (!plain.empty() && !pers.empty()) {
+        int dev = 0;
+        HIP_TRY(hipGetDevice(&dev));
+        const hipStream_t aux = aux_stream(dev);
+        if (!aux) return set_error(SCC_EDEVICE, "could not create the batch scheduler's stream");
+        popt.stream = (void *)aux;
+        worker = std::thread([&, dev] {
+            if (hipSetDevice(dev) != hipSuccess) {
+                sp = SCC_EDEVICE;
+                perr = "hipSetDevice failed in the batch scheduler's thread";
+                return;
+            }
+            sp = batch_persistent(sub.data(), (int)sub.size(), &popt, &bo, sout.data(), &R);
+            if (sp) perr = scc_last_error();
+        });
+    }
+    auto free_sub = [&]() {
+        for (auto &t : sout) {
+            scc_table_destroy(t);
+            t = nullptr;
+        }
+    };
     auto t0 = std::chrono::steady_clock::now();
+    scc_status s = SCC_OK;
     for (int i : plain) {
         scc_build_opts po{};
         if (opt) po = *opt;
         po.hub_degree = 0;
-        if (po.rooting == SCC_ROOT_BALANCED) return set_error(SCC_EINVAL, "round skipping is not supported by the batched build");
         po.vlc = 0;
-        scc_status s = scc_build_table(&inst[i].g, inst[i].colors, inst[i].k, &po, &out[i]);
-        if (s) {
-            free_out();
-            return s;
-        }
+        s = scc_build_table(&inst[i].g, inst[i].colors, inst[i].k, &po, &out[i]);
+        if (s) break;
     }
     const double plain_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    if (!pers.empty()) {
-        std::vector<scc_instance> sub;
-        for (int i : pers) sub.push_back(inst[i]);
-        std::vector<scc_table *> sout(pers.size(), nullptr);
-        scc_status s = batch_persistent(sub.data(), (int)sub.size(), opt, &bo, sout.data(), &R);
-        if (s) {
-            free_out();
-            return s;
-        }
-        for (size_t q = 0; q < pers.size(); q++) out[pers[q]] = sout[q];
+    if (worker.joinable()) {
+        worker.join();
+        for (scc_table *t : sout)
+            if (t) {   // finished and synchronised on the second stream: hand over to the caller's
+                t->stream = caller;
+                t->mem.stream = caller;
+            }
+    } else if (!s && !pers.empty()) {
+        sp = batch_persistent(sub.data(), (int)sub.size(), opt, &bo, sout.data(), &R);
+        if (sp) perr = scc_last_error();
     }
+    if (s || sp) {
+        const std::string msg = s ? std::string(scc_last_error()) : perr;
+        free_out();
+        free_sub();
+        return set_error(s ? s : sp, "%s", msg.c_str());
+    }
+    for (size_t q = 0; q < pers.size(); q++) out[pers[q]] = sout[q];
     R.plain_instances = (int)plain.size();
     R.plain_ms = plain_ms;
     if (rep) *rep = R;
