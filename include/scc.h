@@ -57,8 +57,9 @@ enum { SCC_ROOT_ZERO = 0, SCC_ROOT_ALL = 1, SCC_ROOT_BALANCED = 2 };
 typedef struct scc_table scc_table;
 
 /* Device allocator hooks. alloc returns device memory of at least `bytes`
-   bytes (or NULL); free releases it. Both are called on the caller's thread
-   with the build's stream in `stream`. free may be called while work that
+   bytes (or NULL); free releases it. Both are called with the build's stream in
+   `stream`, on the caller's thread (scc_build_batch may also call them from its
+   second thread, with its second stream, while the call runs). free may be called while work that
    uses the block is still queued on that stream: the allocator must hand the
    block out again only in that stream's order (as a stream-ordered caching
    allocator does), or wait for the stream first. */
@@ -459,7 +460,10 @@ typedef struct {
  * every instance and level are work items of one resident grid, ordered so
  * that an item only waits for earlier ones. Instances with at least
  * bopt->plain_nnz CSR entries (large enough to fill the GPU alone) are built by
- * the level kernels of scc_build_table instead, before that launch. Each out[i] receives a table equal
+ * the level kernels of scc_build_table instead, on the caller's stream; when
+ * there are both kinds the persistent launch runs meanwhile from a second host
+ * thread on a library-owned second stream, and its tables are synchronised
+ * before the call returns. Each out[i] receives a table equal
  * to what scc_build_table would build for instance i with the same options
  * (bit for bit). opt applies to every instance (rooting, max_bits, stream,
  * allocator; hub_degree and validate are ignored: the schedule decides the
