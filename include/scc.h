@@ -587,6 +587,8 @@ typedef struct {
     int no_validate;           /* as in scc_build_opts */
     int64_t chunk_terms;       /* terms (neighbour entries or Eq. (1) products) formed and
                                   sorted at a time; 0 = 2^26. Results do not depend on it. */
+    int max_bits;              /* count width: 128 or 256; 0 (default) = 128, and the
+                                  whole build again at 256 when a count needs more bits */
 } scc16_build_opts;
 
 typedef struct {
@@ -600,7 +602,8 @@ typedef struct {
     int64_t chunks[17];        /* vertex chunks of level h's products */
     int64_t bytes;             /* device bytes of the stored levels */
     int64_t peak_bytes;        /* largest device working set of the build */
-    uint64_t t[2];             /* colourful k-treelet copies (lo, hi) */
+    uint64_t t[4];             /* colourful k-treelet copies, four words, least significant first */
+    int count_bits;            /* width of the stored counts: 128 or 256 */
     double level_ms[17];       /* device time of level h (products and its sums) */
     double sort_ms[17];        /* of which radix sorting */
     double sort_bytes[17];     /* algorithmic bytes of those sorts: 32 per element and pass
@@ -618,9 +621,10 @@ typedef struct {
  * key s_T << 16 | C (C the k-bit colour mask; 46 bits at most). Every vertex
  * keeps only its non-zero counts, sorted by key (the count tables of Sec. 3.2).
  * c(T_C, v) is as in scc_build_table, T'' being T's largest root child
- * subtree. Counts are exact 128-bit integers: a count, product or sum that
- * needs more bits gives SCC_EOVERFLOW (counts wider than 128 bits are not
- * supported). The table holds the levels and t; it has no sampler.
+ * subtree. Counts are exact unsigned integers of 128 bits, or of 256 bits when
+ * opt->max_bits asks for them or (max_bits = 0) a count needs more than 128
+ * bits; a count, product or sum beyond 256 bits gives SCC_EOVERFLOW. The table
+ * holds the levels and t; it has no sampler.
  *
  * g, colors: as in scc_build_table (device pointers borrowed, or host
  * pointers copied). opt may be NULL. *out: free with scc16_table_destroy.
@@ -636,13 +640,14 @@ scc_status scc16_table_info_get(const scc16_table *t, scc16_table_info *out);
 /*
  * scc16_export_level -- level h's records in vertex order (Sec. 3.2, "Count
  * tables"): off device int64[n+1] (the record of v is [off[v], off[v+1])),
- * key device uint64[nnz] (s_T << 16 | C, ascending within a record), lo/hi
- * device uint64[nnz]. With off == NULL only *nnz_out is set. Caller-owned
- * outputs. Errors: SCC_EINVAL (h outside [1, k]), SCC_EDEVICE. Synchronises
- * `stream`.
+ * key device uint64[nnz] (s_T << 16 | C, ascending within a record), words
+ * device uint64[nnz * nwords]: each count as nwords (2 or 4) 64-bit words, least
+ * significant first. With off == NULL only *nnz_out is set. Caller-owned
+ * outputs. Errors: SCC_EINVAL (h outside [1, k]; nwords not 2 or 4, or 2 for a
+ * table of 256-bit counts), SCC_EDEVICE. Synchronises `stream`.
  */
 scc_status scc16_export_level(const scc16_table *t, int h, int64_t *nnz_out, int64_t *off, uint64_t *key,
-                              uint64_t *lo, uint64_t *hi, void *stream);
+                              uint64_t *words, int nwords, void *stream);
 
 /* Frees the per-k class data kept by scc_classify, scc_catalog and AGS (device
    lookup tables, spanning-tree counts). Call only when no classification, AGS

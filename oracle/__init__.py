@@ -91,8 +91,9 @@ def lib():
             "orc16_build": (C.c_int, [i64, P, P, P, C.c_int, C.c_int, C.POINTER(P)]),
             "orc16_table_free": (None, [P]),
             "orc16_level_nnz": (i64, [P, C.c_int]),
-            "orc16_export_level": (C.c_int, [P, C.c_int, P, P, P, P]),
+            "orc16_export_level": (C.c_int, [P, C.c_int, P, P, P]),
             "orc16_total": (None, [P, P]),
+            "orc16_u256_ops": (None, [P, P, C.c_uint64, P, P, P, P, P]),
             "orc_balanced_rank": (C.c_int, [C.c_int, C.c_int]),
             "orc_balanced_orbit": (C.c_int, [C.c_int, C.c_int]),
             "orc_star_class": (C.c_int, [C.c_int]),
@@ -281,27 +282,49 @@ class Table16:
     def level_nnz(self, h: int) -> int:
         return int(lib().orc16_level_nnz(self._h, h))
 
-    def export_level(self, h: int):
-        """(off int64[n+1], key uint64[nnz], lo uint64[nnz], hi uint64[nnz])."""
+    def export_words(self, h: int):
+        """(off int64[n+1], key uint64[nnz], words uint64[nnz, 4]): counts as four
+        64-bit words, least significant first."""
         nnz = self.level_nnz(h)
         off = np.zeros(self.g.n + 1, np.int64)
         key = np.zeros(max(nnz, 1), np.uint64)
-        lo = np.zeros(max(nnz, 1), np.uint64)
-        hi = np.zeros(max(nnz, 1), np.uint64)
-        st = lib().orc16_export_level(self._h, h, _p(off), _p(key), _p(lo), _p(hi))
+        words = np.zeros((max(nnz, 1), 4), np.uint64)
+        st = lib().orc16_export_level(self._h, h, _p(off), _p(key), _p(words))
         if st != OK:
             raise OracleError(st, lib().orc16_last_error().decode())
-        return off, key[:nnz], lo[:nnz], hi[:nnz]
+        return off, key[:nnz], words[:nnz]
+
+    def export_level(self, h: int):
+        """(off, key, lo, hi): the low two words of each count (all of it below 2^128)."""
+        off, key, words = self.export_words(h)
+        return off, key, words[:, 0].copy(), words[:, 1].copy()
 
     def level_dict(self, h: int) -> dict:
         """{(v, key): count} of level h."""
-        off, key, lo, hi = self.export_level(h)
-        return {(v, int(key[q])): _u128(lo[q], hi[q]) for v in range(self.g.n) for q in range(off[v], off[v + 1])}
+        off, key, words = self.export_words(h)
+        return {(v, int(key[q])): words_int(words[q]) for v in range(self.g.n) for q in range(off[v], off[v + 1])}
 
     def total(self) -> int:
-        t = np.zeros(2, np.uint64)
+        t = np.zeros(4, np.uint64)
         lib().orc16_total(self._h, _p(t))
-        return _u128(t[0], t[1])
+        return words_int(t)
+
+
+def words_int(w) -> int:
+    """An unsigned integer from 64-bit words, least significant first."""
+    return sum(int(x) << (64 * i) for i, x in enumerate(w))
+
+
+def u256_ops(a: int, b: int, d: int):
+    """The oracle's 256-bit arithmetic on (a, b, d): (a + b, a * b, a // d, a % d,
+    sum overflowed, product overflowed), results mod 2^256."""
+    wa = np.array([(a >> (64 * i)) & (2 ** 64 - 1) for i in range(4)], np.uint64)
+    wb = np.array([(b >> (64 * i)) & (2 ** 64 - 1) for i in range(4)], np.uint64)
+    s, p, q = (np.zeros(4, np.uint64) for _ in range(3))
+    rem = C.c_uint64(0)
+    flags = C.c_int(0)
+    lib().orc16_u256_ops(_p(wa), _p(wb), d, _p(s), _p(p), _p(q), C.byref(rem), C.byref(flags))
+    return words_int(s), words_int(p), words_int(q), rem.value, bool(flags.value & 1), bool(flags.value & 2)
 
 
 def key16(shape_bits: int, mask: int) -> int:

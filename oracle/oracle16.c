@@ -9,7 +9,8 @@
  * with the first edge at bit 2(h-1)-1. A coloured treelet (T, C) is the 46-bit
  * key s_T << 16 | C, C the colour set as a k-bit mask (h = |C|). A vertex's
  * level-h record is the list of its non-zero counts sorted by key (Sec. 3.2,
- * "Count tables"); counts are unsigned 128-bit, every add and multiply checked.
+ * "Count tables"); counts are unsigned 256-bit integers (four 64-bit words),
+ * every add and multiply checked.
  *
  * Level h at v (Eq. (1)): for every pair of a record entry (T', C') of v of
  * some size h' and an entry (T'', C'') of v's neighbour sum S_{h-h'}(v) =
@@ -34,6 +35,75 @@
 
 typedef unsigned __int128 u128;
 
+/* Unsigned 256-bit counts: four 64-bit words, least significant first. */
+typedef struct { uint64_t w[4]; } u256;
+
+static u256 u256_of(uint64_t x)
+{
+    u256 r = {{x, 0, 0, 0}};
+    return r;
+}
+static int u256_is_zero(u256 a) { return !(a.w[0] | a.w[1] | a.w[2] | a.w[3]); }
+
+/* *r = a + b; nonzero when the sum needs more than 256 bits */
+static int u256_add(u256 *r, u256 a, u256 b)
+{
+    u128 c = 0;
+    for (int i = 0; i < 4; i++) {
+        c += (u128)a.w[i] + b.w[i];
+        r->w[i] = (uint64_t)c;
+        c >>= 64;
+    }
+    return c != 0;
+}
+
+/* *r = a * b, schoolbook on 64-bit words; nonzero when the product needs more
+ * than 256 bits */
+static int u256_mul(u256 *r, u256 a, u256 b)
+{
+    uint64_t p[8] = {0};
+    for (int i = 0; i < 4; i++) {
+        u128 c = 0;
+        for (int j = 0; j < 4; j++) {
+            c += (u128)a.w[i] * b.w[j] + p[i + j];
+            p[i + j] = (uint64_t)c;
+            c >>= 64;
+        }
+        p[i + 4] = (uint64_t)c;
+    }
+    for (int i = 0; i < 4; i++) r->w[i] = p[i];
+    return (p[4] | p[5] | p[6] | p[7]) != 0;
+}
+
+/* *q = a / d (d > 0); returns the remainder */
+static uint64_t u256_divmod(u256 *q, u256 a, uint64_t d)
+{
+    u128 r = 0;
+    for (int i = 3; i >= 0; i--) {
+        r = (r << 64) | a.w[i];
+        q->w[i] = (uint64_t)(r / d);
+        r %= d;
+    }
+    return (uint64_t)r;
+}
+
+/* The arithmetic above on caller-given words (a test hook for the pins):
+ * sum = a + b, prod = a * b, quot = a / d, *rem = a mod d; flags bit 0: the sum
+ * overflowed, bit 1: the product overflowed. */
+void orc16_u256_ops(const uint64_t a[4], const uint64_t b[4], uint64_t d, uint64_t sum[4], uint64_t prod[4],
+                    uint64_t quot[4], uint64_t *rem, int *flags)
+{
+    u256 x, y, r;
+    for (int i = 0; i < 4; i++) { x.w[i] = a[i]; y.w[i] = b[i]; }
+    *flags = 0;
+    if (u256_add(&r, x, y)) *flags |= 1;
+    for (int i = 0; i < 4; i++) sum[i] = r.w[i];
+    if (u256_mul(&r, x, y)) *flags |= 2;
+    for (int i = 0; i < 4; i++) prod[i] = r.w[i];
+    *rem = u256_divmod(&r, x, d);
+    for (int i = 0; i < 4; i++) quot[i] = r.w[i];
+}
+
 #define K16 16
 #define O16_OK 0
 #define O16_EINVAL -1
@@ -43,10 +113,10 @@ typedef unsigned __int128 u128;
 static char o16_err[256];
 const char *orc16_last_error(void) { return o16_err; }
 
-typedef struct { uint64_t key; u128 cnt; } ent;
+typedef struct { uint64_t key; u256 cnt; } ent;
 typedef struct { ent *e; int64_t len, cap; } rec;
 
-static int rec_push(rec *r, uint64_t key, u128 cnt)
+static int rec_push(rec *r, uint64_t key, u256 cnt)
 {
     if (r->len == r->cap) {
         int64_t nc = r->cap ? 2 * r->cap : 8;
@@ -75,14 +145,14 @@ static int rec_normalise(rec *r)
     int64_t w = 0;
     for (int64_t i = 0; i < r->len; i++) {
         if (w > 0 && r->e[w - 1].key == r->e[i].key) {
-            if (__builtin_add_overflow(r->e[w - 1].cnt, r->e[i].cnt, &r->e[w - 1].cnt)) return O16_EOVERFLOW;
+            if (u256_add(&r->e[w - 1].cnt, r->e[w - 1].cnt, r->e[i].cnt)) return O16_EOVERFLOW;
         } else {
             r->e[w++] = r->e[i];
         }
     }
     int64_t z = 0;
     for (int64_t i = 0; i < w; i++)
-        if (r->e[i].cnt) r->e[z++] = r->e[i];
+        if (!u256_is_zero(r->e[i].cnt)) r->e[z++] = r->e[i];
     r->len = z;
     return O16_OK;
 }
@@ -150,7 +220,7 @@ typedef struct orc16_table {
     int k, rooting;
     int64_t n;
     rec *X[K16 + 1];   /* [n] per level */
-    u128 t;
+    u256 t;
 } orc16_table;
 
 void orc16_table_free(orc16_table *T)
@@ -184,7 +254,7 @@ int orc16_build(int64_t n, const int64_t *row_ptr, const int32_t *col_idx, const
         if (!T->X[h]) { st = O16_ENOMEM; break; }
     }
     /* level 1: the single node coloured c_v, once */
-    for (int64_t v = 0; v < n && !st; v++) st = rec_push(&T->X[1][v], make_key(0, 1u << colors[v]), 1);
+    for (int64_t v = 0; v < n && !st; v++) st = rec_push(&T->X[1][v], make_key(0, 1u << colors[v]), u256_of(1));
     for (int h = 2; h <= k && !st; h++) {
         /* neighbour sums of level h-1 */
         const int hs = h - 1;
@@ -213,10 +283,10 @@ int orc16_build(int64_t n, const int64_t *row_ptr, const int32_t *col_idx, const
                         const int b = merge_shapes(key_shape(x->e[i].key), 2 * (hp - 1), key_shape(s->e[j].key),
                                                    2 * (h - hp - 1), &sT);
                         if (!b) continue;
-                        u128 p;
-                        if (__builtin_mul_overflow(x->e[i].cnt, s->e[j].cnt, &p)) st = O16_EOVERFLOW;
+                        u256 p;
+                        if (u256_mul(&p, x->e[i].cnt, s->e[j].cnt)) st = O16_EOVERFLOW;
                         else st = rec_push(&acc, make_key(sT, Cp | Cpp), p);
-                        if (!st) st = rec_push(&beta, make_key(sT, Cp | Cpp), (u128)b);
+                        if (!st) st = rec_push(&beta, make_key(sT, Cp | Cpp), u256_of((uint64_t)b));
                     }
             }
             if (!st) st = rec_normalise(&acc);
@@ -226,16 +296,18 @@ int orc16_build(int64_t n, const int64_t *row_ptr, const int32_t *col_idx, const
                 int64_t q = 0;
                 for (int64_t i = 0; i < acc.len && !st; i++) {
                     while (beta.e[q].key != acc.e[i].key) q++;
-                    const u128 b = beta.e[q].cnt;
-                    if (acc.e[i].cnt % b) { snprintf(o16_err, sizeof o16_err, "beta does not divide a sum"); st = O16_EINVAL; }
-                    acc.e[i].cnt /= b;
+                    const uint64_t b = beta.e[q].cnt.w[0];
+                    if (u256_divmod(&acc.e[i].cnt, acc.e[i].cnt, b)) {
+                        snprintf(o16_err, sizeof o16_err, "beta does not divide a sum");
+                        st = O16_EINVAL;
+                    }
                 }
             }
             free(beta.e);
             if (st) { free(acc.e); break; }
             T->X[h][v] = acc;
         }
-        if (st == O16_EOVERFLOW) snprintf(o16_err, sizeof o16_err, "a count needs more than 128 bits");
+        if (st == O16_EOVERFLOW) snprintf(o16_err, sizeof o16_err, "a count needs more than 256 bits");
     }
     for (int h = 1; h <= K16; h++) {
         if (!S[h]) continue;
@@ -243,13 +315,13 @@ int orc16_build(int64_t n, const int64_t *row_ptr, const int32_t *col_idx, const
         free(S[h]);
     }
     if (!st) {
-        u128 t = 0;
+        u256 t = u256_of(0);
         for (int64_t v = 0; v < n && !st; v++)
             for (int64_t i = 0; i < T->X[k][v].len && !st; i++)
-                if (__builtin_add_overflow(t, T->X[k][v].e[i].cnt, &t)) st = O16_EOVERFLOW;
-        if (!st && rooting == 1) {
-            if (t % (u128)k) { snprintf(o16_err, sizeof o16_err, "k does not divide the level-k total"); st = O16_EINVAL; }
-            t /= (u128)k;
+                if (u256_add(&t, t, T->X[k][v].e[i].cnt)) st = O16_EOVERFLOW;
+        if (!st && rooting == 1 && u256_divmod(&t, t, (uint64_t)k)) {
+            snprintf(o16_err, sizeof o16_err, "k does not divide the level-k total");
+            st = O16_EINVAL;
         }
         T->t = t;
     }
@@ -266,8 +338,9 @@ int64_t orc16_level_nnz(const orc16_table *T, int h)
     return s;
 }
 
-/* level h in vertex order: off[n+1], key[nnz] (s_T << 16 | C), counts (lo, hi) */
-int orc16_export_level(const orc16_table *T, int h, int64_t *off, uint64_t *key, uint64_t *lo, uint64_t *hi)
+/* level h in vertex order: off[n+1], key[nnz] (s_T << 16 | C), counts as four
+ * words each, least significant first (words[4 * i .. 4 * i + 3]) */
+int orc16_export_level(const orc16_table *T, int h, int64_t *off, uint64_t *key, uint64_t *words)
 {
     if (h < 1 || h > T->k) return O16_EINVAL;
     int64_t at = 0;
@@ -276,16 +349,15 @@ int orc16_export_level(const orc16_table *T, int h, int64_t *off, uint64_t *key,
         const rec *r = &T->X[h][v];
         for (int64_t i = 0; i < r->len; i++, at++) {
             key[at] = r->e[i].key;
-            lo[at] = (uint64_t)r->e[i].cnt;
-            hi[at] = (uint64_t)(r->e[i].cnt >> 64);
+            for (int q = 0; q < 4; q++) words[4 * at + q] = r->e[i].cnt.w[q];
         }
     }
     off[T->n] = at;
     return O16_OK;
 }
 
-void orc16_total(const orc16_table *T, uint64_t t[2])
+/* t as four words, least significant first */
+void orc16_total(const orc16_table *T, uint64_t t[4])
 {
-    t[0] = (uint64_t)T->t;
-    t[1] = (uint64_t)(T->t >> 64);
+    for (int q = 0; q < 4; q++) t[q] = T->t.w[q];
 }

@@ -87,14 +87,15 @@ class TableInfo(C.Structure):
 
 class _Build16Opts(C.Structure):
     _fields_ = [("rooting", C.c_int), ("stream", C.c_void_p), ("alloc", C.POINTER(_Allocator)),
-                ("no_validate", C.c_int), ("chunk_terms", C.c_int64)]
+                ("no_validate", C.c_int), ("chunk_terms", C.c_int64), ("max_bits", C.c_int)]
 
 
 class Table16Info(C.Structure):
     _fields_ = [("n", C.c_int64), ("k", C.c_int), ("rooting", C.c_int), ("nnz", C.c_int64 * 17),
                 ("terms", C.c_int64 * 17), ("nbr_terms", C.c_int64 * 17), ("sum_nnz", C.c_int64 * 17),
                 ("chunks", C.c_int64 * 17), ("bytes", C.c_int64), ("peak_bytes", C.c_int64),
-                ("t", C.c_uint64 * 2), ("level_ms", C.c_double * 17), ("sort_ms", C.c_double * 17),
+                ("t", C.c_uint64 * 4), ("count_bits", C.c_int), ("level_ms", C.c_double * 17),
+                ("sort_ms", C.c_double * 17),
                 ("sort_bytes", C.c_double * 17), ("build_ms", C.c_double)]
 
 
@@ -158,7 +159,7 @@ _SIGS = {
     "scc16_build_table": (C.c_int, [C.POINTER(_Csr), _P, C.c_int, C.POINTER(_Build16Opts), C.POINTER(_P)]),
     "scc16_table_destroy": (None, [_P]),
     "scc16_table_info_get": (C.c_int, [_P, C.POINTER(Table16Info)]),
-    "scc16_export_level": (C.c_int, [_P, C.c_int, C.POINTER(_i64), _P, _P, _P, _P, _P]),
+    "scc16_export_level": (C.c_int, [_P, C.c_int, C.POINTER(_i64), _P, _P, _P, C.c_int, _P]),
     "scc_release_caches": (None, []),
     "scc_num_unrooted": (C.c_int, [C.c_int]),
     "scc_balanced_rooting": (C.c_int, [C.c_int, C.c_int, C.POINTER(C.c_int)]),
@@ -408,7 +409,7 @@ class Table16:
     """
 
     def __init__(self, graph, colors, k: int, rooting: int = ROOT_ZERO, validate: bool = True,
-                 chunk_terms: int = 0, stream=None, use_torch_allocator: bool = True):
+                 chunk_terms: int = 0, stream=None, use_torch_allocator: bool = True, max_bits: int = 0):
         self.graph, self.k, self._stream = graph, k, stream
         if isinstance(graph, DeviceGraph):
             self.device = graph.row_ptr.device
@@ -425,7 +426,7 @@ class Table16:
             csr = _Csr(int(rp.size - 1), int(ci.size), rp.ctypes.data, ci.ctypes.data, 0)
             cptr = C.c_void_p(self.colors.ctypes.data)
         opts = _Build16Opts(rooting, _stream_ptr(stream), C.pointer(TORCH_ALLOCATOR) if use_torch_allocator else None,
-                            0 if validate else 1, chunk_terms)
+                            0 if validate else 1, chunk_terms, max_bits)
         self._h = _P()
         _check(_lib.scc16_build_table(C.byref(csr), cptr, k, C.byref(opts), C.byref(self._h)))
 
@@ -447,24 +448,34 @@ class Table16:
 
     def total(self) -> int:
         i = self.info()
-        return _u128(i.t[0], i.t[1])
+        return sum(int(i.t[q]) << (64 * q) for q in range(4))
 
-    def export_level(self, h: int, stream=None, to_host: bool = True):
-        """(off int64[n+1], key uint64[nnz], lo uint64[nnz], hi uint64[nnz]) as numpy arrays, or
-        (to_host=False) device tensors of the same bits."""
+    def count_bits(self) -> int:
+        return self.info().count_bits
+
+    def export_words(self, h: int, nwords: int = 4, stream=None, to_host: bool = True):
+        """(off int64[n+1], key uint64[nnz], words uint64[nnz, nwords]): counts as 64-bit
+        words, least significant first (numpy arrays, or device tensors of the same bits)."""
         nnz = _i64()
-        _check(_lib.scc16_export_level(self._h, h, C.byref(nnz), None, None, None, None, None))
+        _check(_lib.scc16_export_level(self._h, h, C.byref(nnz), None, None, None, nwords, None))
         dev = self.device
         m = max(nnz.value, 1)
         off = torch.empty(self.info().n + 1, dtype=torch.int64, device=dev)
-        key, lo, hi = (torch.empty(m, dtype=torch.int64, device=dev) for _ in range(3))
-        _check(_lib.scc16_export_level(self._h, h, C.byref(nnz), _ptr(off), _ptr(key), _ptr(lo), _ptr(hi),
+        key = torch.empty(m, dtype=torch.int64, device=dev)
+        words = torch.empty((m, nwords), dtype=torch.int64, device=dev)
+        _check(_lib.scc16_export_level(self._h, h, C.byref(nnz), _ptr(off), _ptr(key), _ptr(words), nwords,
                                        _stream_ptr(stream)))
         n = nnz.value
         if not to_host:
-            return off, key[:n], lo[:n], hi[:n]
-        return (off.cpu().numpy(), key[:n].cpu().numpy().view(np.uint64), lo[:n].cpu().numpy().view(np.uint64),
-                hi[:n].cpu().numpy().view(np.uint64))
+            return off, key[:n], words[:n]
+        return off.cpu().numpy(), key[:n].cpu().numpy().view(np.uint64), words[:n].cpu().numpy().view(np.uint64)
+
+    def export_level(self, h: int, stream=None, to_host: bool = True):
+        """(off, key, lo, hi) of a table of 128-bit counts (see export_words)."""
+        off, key, words = self.export_words(h, 2, stream, to_host)
+        if not to_host:
+            return off, key, words[:, 0], words[:, 1]
+        return off, key, words[:, 0].copy(), words[:, 1].copy()
 
 def build_batch(instances, rooting: int = ROOT_ZERO, max_bits: int = 128, tile: int = 0, hub_degree: int = 0,
                 autotune: bool = False, stream=None, use_torch_allocator: bool = True, waves: int = 0,

@@ -27,8 +27,9 @@
 // chunk above the sort key) with its count, sorts the words (least
 // significant digit radix sort, 8-bit digits, stable), adds the counts of
 // equal words and, for X_h, divides each sum by beta_T. Counts are exact
-// unsigned 128-bit integers; a product or sum that needs more bits ends the
-// build with SCC_EOVERFLOW.
+// unsigned integers of 128 bits, or of 256 bits when a build needs them (every
+// kernel that carries counts is instantiated for both widths); a product or sum
+// that needs more bits than the build's width ends it with SCC_EOVERFLOW.
 #include <algorithm>
 #include <vector>
 
@@ -50,10 +51,11 @@ constexpr int64_t MAX_CHUNK_TERMS = ((int64_t)1 << 31) - 1;   // sort permutatio
 
 enum { E16_OVERFLOW = 1, E16_BETA = 2, E16_ROOTS = 4 };
 
+template <typename CT>
 struct Lev16View {
     const int64_t *off;
     const uint64_t *key;
-    const u128 *cnt;
+    const CT *cnt;
 };
 
 // ---------------------------------------------------------------------------
@@ -113,6 +115,110 @@ __device__ inline u128 mul_checked(u128 a, u128 b, bool &ovf)
     return r;
 }
 
+// Unsigned 256-bit counts: four 64-bit words, least significant first.
+struct U256 {
+    uint64_t w[4];
+};
+
+// The arithmetic the kernels need, for either count type.
+template <typename CT> struct Cnt;
+
+template <> struct Cnt<u128> {
+    static constexpr int words = 2;
+    __device__ static u128 of(uint64_t x) { return x; }
+    __device__ static bool zero(u128 a) { return a == 0; }
+    __device__ static u128 add(u128 a, u128 b, bool &ovf)
+    {
+        const u128 t = a + b;
+        if (t < a) ovf = true;
+        return t;
+    }
+    __device__ static u128 mul(u128 a, u128 b, bool &ovf) { return mul_checked(a, b, ovf); }
+    // a / d for 1 <= d < 2^32; inexact is set when d does not divide a
+    __device__ static u128 div(u128 a, uint32_t d, bool &inexact)
+    {
+        const u128 q = div_small(a, d);
+        if (q * d != a) inexact = true;
+        return q;
+    }
+    __device__ static u128 shfl_up(u128 x, int d)
+    {
+        return mk128(__shfl_up((unsigned long long)lo64(x), d), __shfl_up((unsigned long long)hi64(x), d));
+    }
+    __device__ static uint64_t word(u128 x, int i) { return i == 0 ? lo64(x) : (i == 1 ? hi64(x) : 0); }
+};
+
+template <> struct Cnt<U256> {
+    static constexpr int words = 4;
+    __device__ static U256 of(uint64_t x)
+    {
+        U256 r = {{x, 0, 0, 0}};
+        return r;
+    }
+    __device__ static bool zero(const U256 &a) { return !(a.w[0] | a.w[1] | a.w[2] | a.w[3]); }
+    __device__ static U256 add(const U256 &a, const U256 &b, bool &ovf)
+    {
+        U256 r;
+        uint64_t c = 0;
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            const uint64_t t = a.w[i] + b.w[i], u = t + c;
+            c = (t < a.w[i] ? 1u : 0u) + (u < t ? 1u : 0u);
+            r.w[i] = u;
+        }
+        if (c) ovf = true;
+        return r;
+    }
+    // schoolbook on 64-bit words; any partial product above word 3 overflows
+    __device__ static U256 mul(const U256 &a, const U256 &b, bool &ovf)
+    {
+        U256 r = {{0, 0, 0, 0}};
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            if (!a.w[i]) continue;
+            uint64_t carry = 0;
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                if (i + j >= 4) {
+                    if (b.w[j]) ovf = true;
+                    continue;
+                }
+                const u128 t = (u128)a.w[i] * b.w[j] + r.w[i + j] + carry;
+                r.w[i + j] = lo64(t);
+                carry = hi64(t);
+            }
+            if (carry) ovf = true;
+        }
+        return r;
+    }
+    // long division by 32-bit halves of the words, most significant first
+    __device__ static U256 div(const U256 &a, uint32_t d, bool &inexact)
+    {
+        U256 q;
+        uint64_t r = 0;
+#pragma unroll
+        for (int i = 3; i >= 0; i--) {
+            uint64_t t = (r << 32) | (a.w[i] >> 32);
+            const uint64_t qh = t / d;
+            r = t % d;
+            t = (r << 32) | (a.w[i] & 0xffffffffu);
+            const uint64_t ql = t / d;
+            r = t % d;
+            q.w[i] = (qh << 32) | ql;
+        }
+        if (r) inexact = true;
+        return q;
+    }
+    __device__ static U256 shfl_up(const U256 &x, int d)
+    {
+        U256 r;
+#pragma unroll
+        for (int i = 0; i < 4; i++) r.w[i] = __shfl_up((unsigned long long)x.w[i], d);
+        return r;
+    }
+    __device__ static uint64_t word(const U256 &x, int i) { return x.w[i]; }
+};
+
 __device__ inline int binom_small(int n, int r)
 {
     if (r < 0 || r > n) return 0;
@@ -151,35 +257,37 @@ __device__ inline uint64_t wave_reserve(uint64_t *ctr)
 // ---------------------------------------------------------------------------
 // Level 1 and the neighbour sums
 // ---------------------------------------------------------------------------
-__global__ void k16_level1(const uint8_t *colors, int64_t n, int64_t *off, uint64_t *key, u128 *cnt)
+template <typename CT>
+__global__ void k16_level1(const uint8_t *colors, int64_t n, int64_t *off, uint64_t *key, CT *cnt)
 {
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v <= n) off[v] = v;
     if (v < n) {
         key[v] = 1ull << colors[v];
-        cnt[v] = 1;
+        cnt[v] = Cnt<CT>::of(1);
     }
 }
 
+template <typename CT>
 struct NbrArgs {
     const int64_t *row_ptr;
     const int32_t *col_idx;
     const uint8_t *colors;
     int64_t v0, v1;             // vertices [v0, v1)
-    Lev16View X;                // level j
+    Lev16View<CT> X;            // level j
     int j, KB;                  // S_j sort key: C << 2(j-1) | s, KB bits
     int64_t *tnum;              // count: terms of v (written at tnum[v])
     const int64_t *toff;        // emit: exclusive term offsets over all vertices
     uint64_t *tkey;             // emit: (v - v0) << KB | sort key, at toff[v] - toff[v0] + i
-    u128 *tcnt;
+    CT *tcnt;
 };
 
 // S_j(v): the entries of the neighbours' level-j records whose colour set
 // avoids c_v. One wave per vertex; the neighbours are taken 64 at a time and
 // their records walked as one flat range (entry f lies in the last record
 // starting at or before f).
-template <bool EMIT>
-__global__ __launch_bounds__(BLOCK) void k16_nbr(NbrArgs A)
+template <bool EMIT, typename CT>
+__global__ __launch_bounds__(BLOCK) void k16_nbr(NbrArgs<CT> A)
 {
     __shared__ int64_t seg_a[WPB][WAVE];
     __shared__ int64_t seg_p[WPB][WAVE];
@@ -245,17 +353,18 @@ __global__ __launch_bounds__(BLOCK) void k16_nbr(NbrArgs A)
 // ---------------------------------------------------------------------------
 // Eq. (1): the products of a level
 // ---------------------------------------------------------------------------
+template <typename CT>
 struct CombArgs {
     const uint8_t *colors;
     int64_t v0, v1;
     int h, k, KB;               // X_h sort key: s_T << k | C, KB bits
     int zero_rooting;           // level k only at colour-0 vertices
-    Lev16View X[K16];           // X[hp], hp = 1..h-1
-    Lev16View S[K16];           // S[j], j = 1..h-1
+    Lev16View<CT> X[K16];       // X[hp], hp = 1..h-1
+    Lev16View<CT> S[K16];       // S[j], j = 1..h-1
     int64_t *tnum;
     const int64_t *toff;
     uint64_t *tkey;
-    u128 *tcnt;
+    CT *tcnt;
     int *err;
 };
 
@@ -271,8 +380,8 @@ struct CombArgs {
 //  * when that directory would exceed DIR_MAX entries, by binary search.
 constexpr int DIR_MAX = 512;
 
-template <bool EMIT>
-__global__ __launch_bounds__(BLOCK) void k16_comb(CombArgs A)
+template <bool EMIT, typename CT>
+__global__ __launch_bounds__(BLOCK) void k16_comb(CombArgs<CT> A)
 {
     __shared__ uint64_t ctr[WPB];
     __shared__ uint32_t dir_st[WPB][DIR_MAX];
@@ -281,7 +390,7 @@ __global__ __launch_bounds__(BLOCK) void k16_comb(CombArgs A)
     // the lanes' own entries and ranges for the directory path (one set per wave)
     __shared__ uint32_t own_sp[WPB][WAVE], own_c1[WPB][WAVE], own_lc[WPB][WAVE], own_cd[WPB][WAVE];
     __shared__ uint32_t own_st[WPB][WAVE], own_ex[WPB][WAVE];
-    __shared__ uint64_t own_cxl[WPB][WAVE], own_cxh[WPB][WAVE];
+    __shared__ CT own_cx[WPB][WAVE];
     for (int q = threadIdx.x; q < K16 * (K16 + 1); q += BLOCK) {
         const int pp = q / (K16 + 1), qq = q % (K16 + 1);
         binom_t[pp][qq] = (uint16_t)binom_small(pp, qq);
@@ -307,7 +416,7 @@ __global__ __launch_bounds__(BLOCK) void k16_comb(CombArgs A)
         const bool active = !(A.zero_rooting && A.h == A.k && cv != 0);
         for (int hp = 1; active && hp < A.h; hp++) {
             const int j = A.h - hp, lp = 2 * (hp - 1), sb = 2 * (j - 1), lw = 2 * j;
-            const Lev16View X = A.X[hp], S = A.S[j];
+            const Lev16View<CT> X = A.X[hp], S = A.S[j];
             const int64_t xa = X.off[v], xb = X.off[v + 1], sa = S.off[v], se = S.off[v + 1];
             if (xa == xb || sa == se) continue;
             const uint32_t smask = (1u << sb) - 1u;
@@ -347,7 +456,7 @@ __global__ __launch_bounds__(BLOCK) void k16_comb(CombArgs A)
                     const bool xv = x < xb;
                     uint32_t Cp = 0, sp = 0, c1 = 0, freec = 0;
                     int lc = 0;
-                    u128 cx = 0;
+                    CT cx = Cnt<CT>::of(0);
                     uint64_t pos = 0;
                     if (xv) {
                         const uint64_t kx = X.key[x];
@@ -363,8 +472,7 @@ __global__ __launch_bounds__(BLOCK) void k16_comb(CombArgs A)
                     own_sp[w][lane] = sp;
                     own_c1[w][lane] = c1;
                     own_lc[w][lane] = (uint32_t)lc;
-                    own_cxl[w][lane] = lo64(cx);
-                    own_cxh[w][lane] = hi64(cx);
+                    own_cx[w][lane] = cx;
                     for (uint32_t idx = (1u << j) - 1u; idx < (1u << m); idx = next_comb(idx)) {
                         uint32_t st = 0, cntd = 0, D = 0;
                         if (xv) {
@@ -390,7 +498,7 @@ __global__ __launch_bounds__(BLOCK) void k16_comb(CombArgs A)
                             const uint32_t f = f0 + lane;
                             bool keep = false;
                             uint64_t okey = 0;
-                            u128 prod = 0;
+                            CT prod = Cnt<CT>::of(0);
                             if (f < total) {
                                 int lo = 0, hi = WAVE - 1;   // the last lane whose range starts at or before f
                                 while (lo < hi) {
@@ -405,7 +513,7 @@ __global__ __launch_bounds__(BLOCK) void k16_comb(CombArgs A)
                                     if (EMIT) {
                                         const uint64_t sT = ((uint64_t)wd << lp) | own_sp[w][lo];
                                         okey = vl | (sT << A.k) | (uint64_t)own_cd[w][lo];
-                                        prod = mul_checked(mk128(own_cxl[w][lo], own_cxh[w][lo]), S.cnt[e], ovf);
+                                        prod = Cnt<CT>::mul(own_cx[w][lo], S.cnt[e], ovf);
                                     }
                                 }
                             }
@@ -435,7 +543,7 @@ __global__ __launch_bounds__(BLOCK) void k16_comb(CombArgs A)
                 const uint32_t Cp = (uint32_t)kx & 0xffffu, sp = (uint32_t)(kx >> 16);
                 const int lc = first_word_len(sp, lp);
                 const uint32_t c1 = lc ? sp >> (lp - lc) : 0u;
-                const u128 cx = X.cnt[x];
+                const CT cx = X.cnt[x];
                 auto term = [&](int64_t e, uint32_t D) {
                     const uint64_t ks = S.key[e];
                     const uint32_t wd = (1u << (lw - 1)) | (((uint32_t)ks & smask) << 1);
@@ -444,7 +552,7 @@ __global__ __launch_bounds__(BLOCK) void k16_comb(CombArgs A)
                     const uint64_t q = (uint64_t)base + wave_reserve(&ctr[w]);
                     const uint64_t sT = ((uint64_t)wd << lp) | sp;
                     A.tkey[q] = vl | (sT << A.k) | (uint64_t)(Cp | D);
-                    A.tcnt[q] = mul_checked(cx, S.cnt[e], ovf);
+                    A.tcnt[q] = Cnt<CT>::mul(cx, S.cnt[e], ovf);
                 };
                 if (mode == 0) {
                     for (int64_t e = sa; e < se; e++) {
@@ -605,15 +713,35 @@ __device__ inline bool atomic_add128(u128 *p, u128 v)
     return wrap;
 }
 
+// the same for four words: each word's carry (out of the add, or out of the
+// atomic) goes into the next one
+__device__ inline bool atomic_add256(U256 *p, const U256 &v)
+{
+    unsigned long long *w = (unsigned long long *)p;
+    unsigned long long carry = 0;
+    for (int i = 0; i < 4; i++) {
+        const unsigned long long add = v.w[i] + carry;
+        carry = add < v.w[i] ? 1ull : 0ull;
+        if (add) {
+            const unsigned long long old = atomicAdd(&w[i], add);
+            if (old + add < old) carry++;
+        }
+    }
+    return carry != 0;
+}
+__device__ inline bool atomic_addc(u128 *p, u128 v) { return atomic_add128(p, v); }
+__device__ inline bool atomic_addc(U256 *p, const U256 &v) { return atomic_add256(p, v); }
+
+template <typename CT>
 struct RunArgs {
     const uint64_t *keys;       // sorted words
     const uint32_t *perm;       // term index of each sorted word
-    const u128 *tcnt;
+    const CT *tcnt;
     const uint64_t *hpos;       // exclusive scan of the run heads: output index of each run
     int64_t N;
     int KB;
     int64_t v0;
-    u128 *ocnt;                 // [U] sums, zero on entry
+    CT *ocnt;                   // [U] sums, zero on entry
     uint64_t *oword;            // [U] the run's word
     int64_t *vcount;            // [n] entries per vertex
     int *err;
@@ -627,12 +755,13 @@ struct RunArgs {
 // a longer run is added to the run's output atomically.
 constexpr int RUN_ITEMS = 4;
 
-__global__ __launch_bounds__(BLOCK) void k16_runsum(RunArgs A)
+template <typename CT>
+__global__ __launch_bounds__(BLOCK) void k16_runsum(RunArgs<CT> A)
 {
     const int lane = lane_id();
     const int64_t i0 = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) * RUN_ITEMS;
     uint64_t word[RUN_ITEMS], o[RUN_ITEMS];
-    u128 val[RUN_ITEMS];
+    CT val[RUN_ITEMS];
     bool head[RUN_ITEMS], valid[RUN_ITEMS];
     uint64_t prev = i0 > 0 && i0 < A.N ? A.keys[i0 - 1] : 0;
 #pragma unroll
@@ -645,43 +774,37 @@ __global__ __launch_bounds__(BLOCK) void k16_runsum(RunArgs A)
 #pragma unroll
     for (int j = 0; j < RUN_ITEMS; j++) {
         const int64_t i = i0 + j;
-        val[j] = valid[j] ? A.tcnt[A.perm[i]] : (u128)0;
+        val[j] = valid[j] ? A.tcnt[A.perm[i]] : Cnt<CT>::of(0);
         o[j] = valid[j] ? A.hpos[i] - (head[j] ? 0u : 1u) : 0u;
     }
     bool wrap = false, any = false;
-    u128 tail = 0;   // this thread's elements after its last head (all of them without one)
+    CT tail = Cnt<CT>::of(0);   // this thread's elements after its last head (all of them without one)
 #pragma unroll
     for (int j = 0; j < RUN_ITEMS; j++) {
         if (head[j]) {
             tail = val[j];
             any = true;
         } else {
-            const u128 t = tail + val[j];
-            wrap |= t < tail;
-            tail = t;
+            tail = Cnt<CT>::add(tail, val[j], wrap);
         }
     }
     // inclusive segmented scan of (tail, any) over the lanes
-    u128 c = tail;
+    CT c = tail;
     bool f = any;
     for (int d = 1; d < WAVE; d <<= 1) {
-        const u128 pv = mk128(__shfl_up((unsigned long long)lo64(c), d), __shfl_up((unsigned long long)hi64(c), d));
+        const CT pv = Cnt<CT>::shfl_up(c, d);
         const bool pf = __shfl_up((int)f, d) != 0;
         if (lane >= d) {
-            if (!f) {
-                const u128 t = c + pv;
-                wrap |= t < c;
-                c = t;
-            }
+            if (!f) c = Cnt<CT>::add(c, pv, wrap);
             f = f || pf;
         }
     }
     // what the lanes before this one carry into its first run, and whether that
     // run's head lies in the wave's range
-    u128 run = mk128(__shfl_up((unsigned long long)lo64(c), 1), __shfl_up((unsigned long long)hi64(c), 1));
+    CT run = Cnt<CT>::shfl_up(c, 1);
     bool seen = __shfl_up((int)f, 1) != 0;
     if (lane == 0) {
-        run = 0;
+        run = Cnt<CT>::of(0);
         seen = false;
     }
     const bool next_lane_starts = __shfl_down((int)(head[0] || !valid[0]), 1) != 0;
@@ -692,9 +815,7 @@ __global__ __launch_bounds__(BLOCK) void k16_runsum(RunArgs A)
             run = val[j];
             seen = true;
         } else {
-            const u128 t = run + val[j];
-            wrap |= t < run;
-            run = t;
+            run = Cnt<CT>::add(run, val[j], wrap);
         }
         bool ends, piece_end;
         if (j < RUN_ITEMS - 1) {
@@ -707,7 +828,7 @@ __global__ __launch_bounds__(BLOCK) void k16_runsum(RunArgs A)
         }
         if (!piece_end) continue;
         if (seen && ends) A.ocnt[o[j]] = run;
-        else wrap |= atomic_add128(&A.ocnt[o[j]], run);
+        else wrap |= atomic_addc(&A.ocnt[o[j]], run);
     }
 #pragma unroll
     for (int j = 0; j < RUN_ITEMS; j++)
@@ -719,7 +840,8 @@ __global__ __launch_bounds__(BLOCK) void k16_runsum(RunArgs A)
 }
 
 // The run words become keys; for X_h each sum is divided by beta_T.
-__global__ void k16_finish(uint64_t *okey, u128 *ocnt, int64_t U, int KB, int k, int hlen, int x_level, int *err)
+template <typename CT>
+__global__ void k16_finish(uint64_t *okey, CT *ocnt, int64_t U, int KB, int k, int hlen, int x_level, int *err)
 {
     const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (o >= U) return;
@@ -731,9 +853,9 @@ __global__ void k16_finish(uint64_t *okey, u128 *ocnt, int64_t U, int KB, int k,
     const uint32_t s = (uint32_t)(sk >> k), C = (uint32_t)sk & ((1u << k) - 1u);
     const uint32_t b = beta_of(s, hlen);
     if (b > 1) {
-        const u128 sum = ocnt[o], q = div_small(sum, b);
-        if (q * b != sum) atomicOr(err, E16_BETA);
-        ocnt[o] = q;
+        bool inexact = false;
+        ocnt[o] = Cnt<CT>::div(ocnt[o], b, inexact);
+        if (inexact) atomicOr(err, E16_BETA);
     }
     okey[o] = ((uint64_t)s << 16) | C;
 }
@@ -742,56 +864,47 @@ __global__ void k16_finish(uint64_t *okey, u128 *ocnt, int64_t U, int KB, int k,
 // Totals and export
 // ---------------------------------------------------------------------------
 // per-block checked sums of cnt[0, N) into part[block]
-__global__ __launch_bounds__(BLOCK) void k16_sum(const u128 *cnt, int64_t N, u128 *part, int *err)
+template <typename CT>
+__global__ __launch_bounds__(BLOCK) void k16_sum(const CT *cnt, int64_t N, CT *part, int *err)
 {
-    __shared__ u128 ws[BLOCK];
-    u128 s = 0;
-    int bad = 0;
-    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < N; i += (int64_t)gridDim.x * BLOCK) {
-        const u128 t = s + cnt[i];
-        if (t < s) bad = 1;
-        s = t;
-    }
+    __shared__ CT ws[BLOCK];
+    CT s = Cnt<CT>::of(0);
+    bool bad = false;
+    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < N; i += (int64_t)gridDim.x * BLOCK)
+        s = Cnt<CT>::add(s, cnt[i], bad);
     ws[threadIdx.x] = s;
     __syncthreads();
     for (int st = BLOCK / 2; st > 0; st >>= 1) {
-        if ((int)threadIdx.x < st) {
-            const u128 a = ws[threadIdx.x], t = a + ws[threadIdx.x + st];
-            if (t < a) bad = 1;
-            ws[threadIdx.x] = t;
-        }
+        if ((int)threadIdx.x < st) ws[threadIdx.x] = Cnt<CT>::add(ws[threadIdx.x], ws[threadIdx.x + st], bad);
         __syncthreads();
     }
     if (threadIdx.x == 0) part[blockIdx.x] = ws[0];
     if (bad) atomicOr(err, E16_OVERFLOW);
 }
 
-// t = the sum of the level-k counts (divided by k when every vertex is a root)
-__global__ void k16_total(const u128 *part, int nparts, int divide_by, uint64_t *out, int *err)
+// t = the sum of the level-k counts (divided by k when every vertex is a root),
+// as four words
+template <typename CT>
+__global__ void k16_total(const CT *part, int nparts, int divide_by, uint64_t *out, int *err)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    u128 s = 0;
-    for (int i = 0; i < nparts; i++) {
-        const u128 t = s + part[i];
-        if (t < s) atomicOr(err, E16_OVERFLOW);
-        s = t;
-    }
-    if (divide_by > 1) {
-        const u128 q = div_small(s, (uint32_t)divide_by);
-        if (q * (uint32_t)divide_by != s) atomicOr(err, E16_ROOTS);
-        s = q;
-    }
-    out[0] = lo64(s);
-    out[1] = hi64(s);
+    CT s = Cnt<CT>::of(0);
+    bool ovf = false, inexact = false;
+    for (int i = 0; i < nparts; i++) s = Cnt<CT>::add(s, part[i], ovf);
+    if (divide_by > 1) s = Cnt<CT>::div(s, (uint32_t)divide_by, inexact);
+    if (ovf) atomicOr(err, E16_OVERFLOW);
+    if (inexact) atomicOr(err, E16_ROOTS);
+    for (int i = 0; i < 4; i++) out[i] = Cnt<CT>::word(s, i);
 }
 
-__global__ void k16_split(const u128 *cnt, int64_t N, uint64_t *lo, uint64_t *hi)
+// counts as nwords words each (the count's own words, then zeros)
+template <typename CT>
+__global__ void k16_words(const CT *cnt, int64_t N, uint64_t *out, int nwords)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < N) {
-        const u128 c = cnt[i];
-        lo[i] = lo64(c);
-        hi[i] = hi64(c);
+        const CT c = cnt[i];
+        for (int q = 0; q < nwords; q++) out[i * nwords + q] = Cnt<CT>::word(c, q);
     }
 }
 
@@ -806,9 +919,9 @@ inline unsigned wave_grid(int64_t nv) { return (unsigned)std::min<int64_t>(std::
 struct Lev16 {
     int64_t *off = nullptr;
     uint64_t *key = nullptr;
-    u128 *cnt = nullptr;
+    void *cnt = nullptr;        // u128[nnz] or U256[nnz], by the table's width
     int64_t nnz = 0;
-    Lev16View view() const { return {off, key, cnt}; }
+    template <typename CT> Lev16View<CT> view() const { return {off, key, (const CT *)cnt}; }
 };
 
 struct scc16_table {
@@ -821,7 +934,8 @@ struct scc16_table {
     DevMem mem;
     std::vector<void *> owned;      // device blocks held by the table
     Lev16 X[K16 + 1];
-    uint64_t t[2] = {0, 0};
+    int count_bits = 128;           // width of every stored count: 128 or 256
+    uint64_t t[4] = {0, 0, 0, 0};
     scc16_table_info info{};
     int64_t live = 0;               // device bytes of the build at this moment (for peak_bytes)
 
@@ -940,9 +1054,11 @@ struct Timer {
 // One level: x_level = 1 builds X_h from X_1..X_{h-1} and S_1..S_{h-1}
 // (Eq. (1)); x_level = 0 builds S_h from X_h. `own` receives the result; its
 // arrays are held by the table (X) or by `hold` (S, freed after the build).
+template <typename CT>
 scc_status build_pass(scc16_table *T, int x_level, int h, const Lev16 *S, Lev16 &out, std::vector<void *> &hold,
                       int64_t &terms_out, int64_t &chunks_out, double &sort_ms, double &sort_bytes)
 {
+    constexpr size_t CB = sizeof(CT);
     const int64_t n = T->n;
     const int k = T->k, KB = 2 * (h - 1) + k;
     Scratch sc(T);
@@ -959,8 +1075,8 @@ scc_status build_pass(scc16_table *T, int x_level, int h, const Lev16 *S, Lev16 
     HIP_TRY(hipMemsetAsync(toff, 0, (size_t)(n + 1) * 8, T->stream));
     HIP_TRY(hipMemsetAsync(err, 0, 4, T->stream));
 
-    NbrArgs NA{};
-    CombArgs CA{};
+    NbrArgs<CT> NA{};
+    CombArgs<CT> CA{};
     if (x_level) {
         CA.colors = T->colors;
         CA.h = h;
@@ -968,25 +1084,25 @@ scc_status build_pass(scc16_table *T, int x_level, int h, const Lev16 *S, Lev16 
         CA.KB = KB;
         CA.zero_rooting = T->rooting == SCC_ROOT_ZERO;
         for (int q = 1; q < h; q++) {
-            CA.X[q] = T->X[q].view();
-            CA.S[q] = S[q].view();
+            CA.X[q] = T->X[q].view<CT>();
+            CA.S[q] = S[q].view<CT>();
         }
         CA.err = err;
         CA.tnum = (int64_t *)toff;
         CA.v0 = 0;
         CA.v1 = n;
-        hipLaunchKernelGGL(k16_comb<false>, dim3(wave_grid(n)), dim3(BLOCK), 0, T->stream, CA);
+        hipLaunchKernelGGL((k16_comb<false, CT>), dim3(wave_grid(n)), dim3(BLOCK), 0, T->stream, CA);
     } else {
         NA.row_ptr = T->row_ptr;
         NA.col_idx = T->col_idx;
         NA.colors = T->colors;
-        NA.X = T->X[h].view();
+        NA.X = T->X[h].view<CT>();
         NA.j = h;
         NA.KB = KB;
         NA.tnum = (int64_t *)toff;
         NA.v0 = 0;
         NA.v1 = n;
-        hipLaunchKernelGGL(k16_nbr<false>, dim3(wave_grid(n)), dim3(BLOCK), 0, T->stream, NA);
+        hipLaunchKernelGGL((k16_nbr<false, CT>), dim3(wave_grid(n)), dim3(BLOCK), 0, T->stream, NA);
     }
     HIP_TRY(hipGetLastError());
     scc_status s = scan_u64(T, toff, n + 1, word);
@@ -1018,14 +1134,14 @@ scc_status build_pass(scc16_table *T, int x_level, int h, const Lev16 *S, Lev16 
     out.off = (int64_t *)keep((size_t)(n + 1) * 8);
     if (!out.off) return set_error(SCC_ENOMEM, "level %d offsets", h);
     HIP_TRY(hipMemsetAsync(out.off, 0, (size_t)(n + 1) * 8, T->stream));
-    std::vector<std::pair<uint64_t *, u128 *>> parts;
+    std::vector<std::pair<uint64_t *, CT *>> parts;
     std::vector<int64_t> part_n;
     Scratch parts_mem(T);
     if (nmax > 0) {
         const int64_t nbs = (nmax + SORT_TILE - 1) / SORT_TILE;
         uint64_t *ka = (uint64_t *)sc.get((size_t)nmax * 8), *kb = (uint64_t *)sc.get((size_t)nmax * 8);
         uint32_t *pa = (uint32_t *)sc.get((size_t)nmax * 4), *pb = (uint32_t *)sc.get((size_t)nmax * 4);
-        u128 *tc = (u128 *)sc.get((size_t)nmax * 16);
+        CT *tc = (CT *)sc.get((size_t)nmax * CB);
         uint64_t *flag = (uint64_t *)sc.get((size_t)nmax * 8);
         uint64_t *hist = (uint64_t *)sc.get((size_t)nbs * RADIX * 8);
         if (!ka || !kb || !pa || !pb || !tc || !flag || !hist) return set_error(SCC_ENOMEM, "level %d sort", h);
@@ -1034,10 +1150,10 @@ scc_status build_pass(scc16_table *T, int x_level, int h, const Lev16 *S, Lev16 
             const int64_t v0 = c.first, v1 = c.second, N = ht[(size_t)v1] - ht[(size_t)v0];
             if (x_level) {
                 CA.v0 = v0; CA.v1 = v1; CA.toff = (const int64_t *)toff; CA.tkey = ka; CA.tcnt = tc;
-                hipLaunchKernelGGL(k16_comb<true>, dim3(wave_grid(v1 - v0)), dim3(BLOCK), 0, T->stream, CA);
+                hipLaunchKernelGGL((k16_comb<true, CT>), dim3(wave_grid(v1 - v0)), dim3(BLOCK), 0, T->stream, CA);
             } else {
                 NA.v0 = v0; NA.v1 = v1; NA.toff = (const int64_t *)toff; NA.tkey = ka; NA.tcnt = tc;
-                hipLaunchKernelGGL(k16_nbr<true>, dim3(wave_grid(v1 - v0)), dim3(BLOCK), 0, T->stream, NA);
+                hipLaunchKernelGGL((k16_nbr<true, CT>), dim3(wave_grid(v1 - v0)), dim3(BLOCK), 0, T->stream, NA);
             }
             HIP_TRY(hipGetLastError());
             int vb = 0;
@@ -1055,13 +1171,13 @@ scc_status build_pass(scc16_table *T, int x_level, int h, const Lev16 *S, Lev16 
             HIP_TRY(hipMemcpyAsync(&U, word, 8, hipMemcpyDeviceToHost, T->stream));
             HIP_TRY(hipStreamSynchronize(T->stream));
             uint64_t *ok = (uint64_t *)parts_mem.get((size_t)U * 8);
-            u128 *oc = (u128 *)parts_mem.get((size_t)U * 16);
+            CT *oc = (CT *)parts_mem.get((size_t)U * CB);
             if (!ok || !oc) return set_error(SCC_ENOMEM, "level %d records", h);
-            HIP_TRY(hipMemsetAsync(oc, 0, (size_t)U * 16, T->stream));
-            RunArgs R{keys, perm, tc, flag, N, KB, v0, oc, ok, out.off, err};
-            hipLaunchKernelGGL(k16_runsum, dim3(blocks_for(N, BLOCK * RUN_ITEMS)), dim3(BLOCK), 0, T->stream, R);
-            hipLaunchKernelGGL(k16_finish, dim3(blocks_for((int64_t)U, 256)), dim3(256), 0, T->stream, ok, oc, (int64_t)U,
-                               KB, k, 2 * (h - 1), x_level, err);
+            HIP_TRY(hipMemsetAsync(oc, 0, (size_t)U * CB, T->stream));
+            RunArgs<CT> R{keys, perm, tc, flag, N, KB, v0, oc, ok, out.off, err};
+            hipLaunchKernelGGL((k16_runsum<CT>), dim3(blocks_for(N, BLOCK * RUN_ITEMS)), dim3(BLOCK), 0, T->stream, R);
+            hipLaunchKernelGGL((k16_finish<CT>), dim3(blocks_for((int64_t)U, 256)), dim3(256), 0, T->stream, ok, oc,
+                               (int64_t)U, KB, k, 2 * (h - 1), x_level, err);
             HIP_TRY(hipGetLastError());
             parts.push_back({ok, oc});
             part_n.push_back((int64_t)U);
@@ -1071,13 +1187,13 @@ scc_status build_pass(scc16_table *T, int x_level, int h, const Lev16 *S, Lev16 
     for (int64_t u : part_n) nnz += u;
     out.nnz = nnz;
     out.key = (uint64_t *)keep((size_t)nnz * 8);
-    out.cnt = (u128 *)keep((size_t)nnz * 16);
+    out.cnt = keep((size_t)nnz * CB);
     if (!out.key || !out.cnt) return set_error(SCC_ENOMEM, "level %d records", h);
     int64_t at = 0;
     for (size_t i = 0; i < parts.size(); i++) {
         if (part_n[i] == 0) continue;
         HIP_TRY(hipMemcpyAsync(out.key + at, parts[i].first, (size_t)part_n[i] * 8, hipMemcpyDeviceToDevice, T->stream));
-        HIP_TRY(hipMemcpyAsync(out.cnt + at, parts[i].second, (size_t)part_n[i] * 16, hipMemcpyDeviceToDevice,
+        HIP_TRY(hipMemcpyAsync((CT *)out.cnt + at, parts[i].second, (size_t)part_n[i] * CB, hipMemcpyDeviceToDevice,
                                T->stream));
         at += part_n[i];
     }
@@ -1086,13 +1202,16 @@ scc_status build_pass(scc16_table *T, int x_level, int h, const Lev16 *S, Lev16 
     int herr = 0;
     HIP_TRY(hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, T->stream));
     HIP_TRY(hipStreamSynchronize(T->stream));
-    if (herr & E16_OVERFLOW) return set_error(SCC_EOVERFLOW, "level %d: a count needs more than 128 bits", h);
+    if (herr & E16_OVERFLOW)
+        return set_error(SCC_EOVERFLOW, "level %d: a count needs more than %d bits", h, (int)(8 * CB));
     if (herr) return set_error(SCC_EDEVICE, "level %d: internal check failed (%d)", h, herr);
     return SCC_OK;
 }
 
+template <typename CT>
 scc_status build_all(scc16_table *T)
 {
+    constexpr size_t CB = sizeof(CT);
     const int64_t n = T->n;
     const int k = T->k;
     Lev16 S[K16 + 1];
@@ -1109,11 +1228,11 @@ scc_status build_all(scc16_table *T)
         Lev16 &L = T->X[1];
         L.off = (int64_t *)T->hold((size_t)(n + 1) * 8);
         L.key = (uint64_t *)T->hold((size_t)std::max<int64_t>(n, 1) * 8);
-        L.cnt = (u128 *)T->hold((size_t)std::max<int64_t>(n, 1) * 16);
+        L.cnt = T->hold((size_t)std::max<int64_t>(n, 1) * CB);
         if (!L.off || !L.key || !L.cnt) return set_error(SCC_ENOMEM, "level 1");
-        T->live += (n + 1) * 8 + n * 24;
-        hipLaunchKernelGGL(k16_level1, dim3(blocks_for(n + 1, 256)), dim3(256), 0, T->stream, T->colors, n, L.off, L.key,
-                           L.cnt);
+        T->live += (n + 1) * 8 + n * (int64_t)(8 + CB);
+        hipLaunchKernelGGL((k16_level1<CT>), dim3(blocks_for(n + 1, 256)), dim3(256), 0, T->stream, T->colors, n, L.off,
+                           L.key, (CT *)L.cnt);
         HIP_TRY(hipGetLastError());
         L.nnz = n;
     }
@@ -1123,14 +1242,14 @@ scc_status build_all(scc16_table *T)
         double sms = 0, sbytes = 0;
         if (h >= 2) {
             int64_t terms = 0, chunks = 0;
-            scc_status s = build_pass(T, 1, h, S, T->X[h], hold, terms, chunks, sms, sbytes);
+            scc_status s = build_pass<CT>(T, 1, h, S, T->X[h], hold, terms, chunks, sms, sbytes);
             if (s) return s;
             T->info.terms[h] = terms;
             T->info.chunks[h] = chunks;
         }
         if (h < k) {
             int64_t terms = 0, chunks = 0;
-            scc_status s = build_pass(T, 0, h, S, S[h], hold, terms, chunks, sms, sbytes);
+            scc_status s = build_pass<CT>(T, 0, h, S, S[h], hold, terms, chunks, sms, sbytes);
             if (s) return s;
             T->info.nbr_terms[h] = terms;
             T->info.sum_nnz[h] = S[h].nnz;
@@ -1144,21 +1263,21 @@ scc_status build_all(scc16_table *T)
     {
         Scratch sc(T);
         const int parts = 256;
-        u128 *part = (u128 *)sc.get(parts * 16);
+        CT *part = (CT *)sc.get(parts * CB);
         uint64_t *tout = (uint64_t *)sc.get(64);
         int *err = (int *)sc.get(64);
         if (!part || !tout || !err) return set_error(SCC_ENOMEM, "totals");
         HIP_TRY(hipMemsetAsync(err, 0, 4, T->stream));
-        hipLaunchKernelGGL(k16_sum, dim3(parts), dim3(BLOCK), 0, T->stream, (const u128 *)T->X[k].cnt, T->X[k].nnz, part,
-                           err);
-        hipLaunchKernelGGL(k16_total, dim3(1), dim3(64), 0, T->stream, (const u128 *)part, parts,
+        hipLaunchKernelGGL((k16_sum<CT>), dim3(parts), dim3(BLOCK), 0, T->stream, (const CT *)T->X[k].cnt, T->X[k].nnz,
+                           part, err);
+        hipLaunchKernelGGL((k16_total<CT>), dim3(1), dim3(64), 0, T->stream, (const CT *)part, parts,
                            T->rooting == SCC_ROOT_ALL ? k : 1, tout, err);
         HIP_TRY(hipGetLastError());
         int herr = 0;
-        HIP_TRY(hipMemcpyAsync(T->t, tout, 16, hipMemcpyDeviceToHost, T->stream));
+        HIP_TRY(hipMemcpyAsync(T->t, tout, 32, hipMemcpyDeviceToHost, T->stream));
         HIP_TRY(hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, T->stream));
         HIP_TRY(hipStreamSynchronize(T->stream));
-        if (herr & E16_OVERFLOW) return set_error(SCC_EOVERFLOW, "t needs more than 128 bits");
+        if (herr & E16_OVERFLOW) return set_error(SCC_EOVERFLOW, "t needs more than %d bits", (int)(8 * CB));
         if (herr) return set_error(SCC_EDEVICE, "the level-k sum is not a multiple of k");
     }
     T->info.build_ms = all.stop(T->stream);
@@ -1167,22 +1286,10 @@ scc_status build_all(scc16_table *T)
 
 } // namespace
 
-extern "C" scc_status scc16_build_table(const scc_csr *g, const uint8_t *colors, int k, const scc16_build_opts *opt,
-                                        scc16_table **out)
+// One build attempt at the given count width; *out on success.
+static scc_status build16(const scc_csr *g, const uint8_t *colors, int k, const scc16_build_opts &o, int bits,
+                          bool validate, scc16_table **out)
 {
-    if (!out) return set_error(SCC_EINVAL, "out is NULL");
-    *out = nullptr;
-    if (!g || (g->n > 0 && !colors)) return set_error(SCC_EINVAL, "graph or colours NULL");
-    if (k < 2 || k > K16) return set_error(SCC_EINVAL, "k = %d not in [2, 16]", k);
-    if (g->n < 0 || g->n >= ((int64_t)1 << 31)) return set_error(SCC_EINVAL, "n out of range");
-    if (g->nnz < 0 || g->nnz >= ((int64_t)1 << 40) || !g->row_ptr || (g->nnz > 0 && !g->col_idx))
-        return set_error(SCC_EINVAL, "bad CSR pointers or size");
-    scc16_build_opts o{};
-    if (opt) o = *opt;
-    if (o.rooting != SCC_ROOT_ZERO && o.rooting != SCC_ROOT_ALL)
-        return set_error(SCC_EINVAL, "rooting must be SCC_ROOT_ZERO or SCC_ROOT_ALL");
-    if (o.chunk_terms < 0) return set_error(SCC_EINVAL, "chunk_terms < 0");
-
     scc16_table *T = new scc16_table;
     T->k = k;
     T->rooting = o.rooting;
@@ -1192,9 +1299,11 @@ extern "C" scc_status scc16_build_table(const scc_csr *g, const uint8_t *colors,
     T->stream = (hipStream_t)o.stream;
     T->mem.alloc = o.alloc;
     T->mem.stream = T->stream;
+    T->count_bits = bits;
     T->info.n = g->n;
     T->info.k = k;
     T->info.rooting = o.rooting;
+    T->info.count_bits = bits;
     scc_status s = SCC_OK;
     if (g->on_device) {
         T->row_ptr = g->row_ptr;
@@ -1217,19 +1326,42 @@ extern "C" scc_status scc16_build_table(const scc_csr *g, const uint8_t *colors,
         T->col_idx = ci;
         T->colors = cl;
     }
-    if (!s && !o.no_validate) s = validate_csr(T->n, T->nnz_g, T->row_ptr, T->col_idx, T->colors, k, T->stream, T->mem);
-    if (!s) s = build_all(T);
+    if (!s && validate) s = validate_csr(T->n, T->nnz_g, T->row_ptr, T->col_idx, T->colors, k, T->stream, T->mem);
+    if (!s) s = bits == 256 ? build_all<U256>(T) : build_all<u128>(T);
     if (s) {
         delete T;
         return s;
     }
     int64_t bytes = 0;
-    for (int h = 1; h <= k; h++) bytes += (T->n + 1) * 8 + T->X[h].nnz * 24;
+    for (int h = 1; h <= k; h++) bytes += (T->n + 1) * 8 + T->X[h].nnz * (8 + bits / 8);
     T->info.bytes = bytes;
-    T->info.t[0] = T->t[0];
-    T->info.t[1] = T->t[1];
+    for (int i = 0; i < 4; i++) T->info.t[i] = T->t[i];
     *out = T;
     return SCC_OK;
+}
+
+extern "C" scc_status scc16_build_table(const scc_csr *g, const uint8_t *colors, int k, const scc16_build_opts *opt,
+                                        scc16_table **out)
+{
+    if (!out) return set_error(SCC_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!g || (g->n > 0 && !colors)) return set_error(SCC_EINVAL, "graph or colours NULL");
+    if (k < 2 || k > K16) return set_error(SCC_EINVAL, "k = %d not in [2, 16]", k);
+    if (g->n < 0 || g->n >= ((int64_t)1 << 31)) return set_error(SCC_EINVAL, "n out of range");
+    if (g->nnz < 0 || g->nnz >= ((int64_t)1 << 40) || !g->row_ptr || (g->nnz > 0 && !g->col_idx))
+        return set_error(SCC_EINVAL, "bad CSR pointers or size");
+    scc16_build_opts o{};
+    if (opt) o = *opt;
+    if (o.rooting != SCC_ROOT_ZERO && o.rooting != SCC_ROOT_ALL)
+        return set_error(SCC_EINVAL, "rooting must be SCC_ROOT_ZERO or SCC_ROOT_ALL");
+    if (o.chunk_terms < 0) return set_error(SCC_EINVAL, "chunk_terms < 0");
+    if (o.max_bits != 0 && o.max_bits != 128 && o.max_bits != 256)
+        return set_error(SCC_EINVAL, "max_bits must be 0, 128 or 256");
+    // 0: 128-bit counts, and the whole build again with 256-bit counts if a count
+    // needs more than 128 bits
+    scc_status s = build16(g, colors, k, o, o.max_bits == 256 ? 256 : 128, !o.no_validate, out);
+    if (s == SCC_EOVERFLOW && o.max_bits == 0) s = build16(g, colors, k, o, 256, false, out);
+    return s;
 }
 
 extern "C" void scc16_table_destroy(scc16_table *t) { delete t; }
@@ -1242,19 +1374,27 @@ extern "C" scc_status scc16_table_info_get(const scc16_table *t, scc16_table_inf
 }
 
 extern "C" scc_status scc16_export_level(const scc16_table *t, int h, int64_t *nnz_out, int64_t *off, uint64_t *key,
-                                         uint64_t *lo, uint64_t *hi, void *stream)
+                                         uint64_t *words, int nwords, void *stream)
 {
     if (!t || !nnz_out) return set_error(SCC_EINVAL, "NULL argument");
     if (h < 1 || h > t->k) return set_error(SCC_EINVAL, "h = %d not in [1, %d]", h, t->k);
     const Lev16 &L = t->X[h];
     *nnz_out = L.nnz;
     if (!off) return SCC_OK;
-    if (L.nnz > 0 && (!key || !lo || !hi)) return set_error(SCC_EINVAL, "NULL output array");
+    if (nwords != 2 && nwords != 4) return set_error(SCC_EINVAL, "nwords must be 2 or 4");
+    if (nwords * 64 < t->count_bits)
+        return set_error(SCC_EINVAL, "the table's counts are %d-bit: ask for 4 words", t->count_bits);
+    if (L.nnz > 0 && (!key || !words)) return set_error(SCC_EINVAL, "NULL output array");
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(hipMemcpyAsync(off, L.off, (size_t)(t->n + 1) * 8, hipMemcpyDeviceToDevice, s));
     if (L.nnz > 0) {
         HIP_TRY(hipMemcpyAsync(key, L.key, (size_t)L.nnz * 8, hipMemcpyDeviceToDevice, s));
-        hipLaunchKernelGGL(k16_split, dim3(blocks_for(L.nnz, 256)), dim3(256), 0, s, (const u128 *)L.cnt, L.nnz, lo, hi);
+        if (t->count_bits == 256)
+            hipLaunchKernelGGL((k16_words<U256>), dim3(blocks_for(L.nnz, 256)), dim3(256), 0, s, (const U256 *)L.cnt,
+                               L.nnz, words, nwords);
+        else
+            hipLaunchKernelGGL((k16_words<u128>), dim3(blocks_for(L.nnz, 256)), dim3(256), 0, s, (const u128 *)L.cnt,
+                               L.nnz, words, nwords);
         HIP_TRY(hipGetLastError());
     }
     HIP_TRY(hipStreamSynchronize(s));

@@ -40,8 +40,8 @@ int orc16_build(int64_t n, const int64_t *row_ptr, const int32_t *col_idx, const
                 orc16_table **out);
 void orc16_table_free(orc16_table *T);
 int64_t orc16_level_nnz(const orc16_table *T, int h);
-int orc16_export_level(const orc16_table *T, int h, int64_t *off, uint64_t *key, uint64_t *lo, uint64_t *hi);
-void orc16_total(const orc16_table *T, uint64_t t[2]);
+int orc16_export_level(const orc16_table *T, int h, int64_t *off, uint64_t *key, uint64_t *words);
+void orc16_total(const orc16_table *T, uint64_t t[4]);
 
 static uint64_t rng = 88172645463325252ull;
 static uint64_t next(void) { rng ^= rng << 13; rng ^= rng >> 7; rng ^= rng << 17; return rng; }
@@ -136,11 +136,11 @@ int main(void)
             for (int h = 1; h <= k; h++) {
                 int64_t nnz = orc16_level_nnz(T, h);
                 int64_t *off = malloc(sizeof(int64_t) * (n + 1));
-                uint64_t *key = malloc(8 * (nnz + 1)), *lo = malloc(8 * (nnz + 1)), *hi = malloc(8 * (nnz + 1));
-                CHECK(orc16_export_level(T, h, off, key, lo, hi));
-                free(off); free(key); free(lo); free(hi);
+                uint64_t *key = malloc(8 * (nnz + 1)), *words = malloc(32 * (nnz + 1));
+                CHECK(orc16_export_level(T, h, off, key, words));
+                free(off); free(key); free(words);
             }
-            uint64_t t[2];
+            uint64_t t[4];
             orc16_total(T, t);
             orc16_table_free(T);
         }

@@ -152,15 +152,57 @@ def test_invalid_inputs():
         assert e.value.status == scc.EINVAL
 
 
-def test_128_bit_limit_star():
-    # centre colour 0, leaf i colour 1 + i % 15: class sizes 546 and 547; the
-    # centre's level-16 star counts are products of 15 class sizes (about 2^136)
+def test_star_beyond_128_bits():
+    # centre colour 0, leaf i colour 1 + i % 15: class sizes 546 and 547. The only
+    # colourful 16-treelets are the stars around the centre, one for each choice
+    # of a leaf of every colour: the centre's level-16 count and t are the product
+    # of the 15 class sizes (about 2^136). A 128-bit build stops with
+    # SCC_EOVERFLOW; the default builds again with 256-bit counts.
     d = 8192
     g = gg.star(d)
     colors = np.concatenate([[0], 1 + np.arange(d) % 15]).astype(np.uint8)
+    sizes = np.bincount(colors[1:], minlength=16)
+    want = prod(int(sizes[c]) for c in range(1, 16))
+    assert want > 1 << 128
+    dg = scc.DeviceGraph.from_graph(g)
     with pytest.raises(scc.SccError) as e:
-        scc.Table16(scc.DeviceGraph.from_graph(g), colors, 16)
+        scc.Table16(dg, colors, 16, max_bits=128)
     assert e.value.status == scc.EOVERFLOW
+    t = scc.Table16(dg, colors, 16)
+    assert t.count_bits() == 256
+    assert t.total() == want
+    off, key, words = t.export_words(16)
+    star = int("10" * 15, 2)
+    got = {int(key[q]): O.words_int(words[q]) for q in range(off[0], off[1])}
+    assert got == {(star << 16) | 0xffff: want}
+    assert off[-1] == off[1]                      # zero-rooting: level 16 at the centre only
+    # level 15 at a leaf: the leaf, then the centre with 13 more leaves
+    off, key, words = t.export_words(15)
+    leaf = 1
+    cl = int(colors[leaf])
+    for q in range(off[leaf], off[leaf + 1]):
+        C = int(key[q]) & 0xffff
+        others = [c for c in range(1, 16) if C >> c & 1 and c != cl]
+        assert O.words_int(words[q]) == prod(int(sizes[c]) for c in others)
+
+
+@pytest.mark.parametrize("k,rooting", [(5, O.ROOT_ALL), (9, O.ROOT_ZERO), (11, O.ROOT_ALL)])
+def test_256_bit_build_equals_oracle(k, rooting):
+    # the 256-bit kernels on graphs whose counts are small: every level equals the
+    # oracle's (itself computed in 256 bits), word for word
+    g = _sparse_graph(44, 12, 30 + k) if k > 8 else gg.erdos_renyi(80, 240, seed=k)
+    colors = gg.colors(g.n, k, seed=k + 3)
+    gt = scc.Table16(scc.DeviceGraph.from_graph(g), colors, k, rooting=rooting, max_bits=256, chunk_terms=500)
+    ot = O.Table16(g, colors, k, rooting)
+    assert gt.count_bits() == 256
+    for h in range(1, k + 1):
+        go, gk, gw = gt.export_words(h)
+        oo, ok, ow = ot.export_words(h)
+        assert np.array_equal(go, oo) and np.array_equal(gk, ok) and np.array_equal(gw, ow), h
+    assert gt.total() == ot.total()
+    with pytest.raises(scc.SccError) as e:
+        gt.export_level(k)                        # two words cannot hold a 256-bit table's counts
+    assert e.value.status == scc.EINVAL
 
 
 def test_star_closed_form_beyond_64_bits():

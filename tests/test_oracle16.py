@@ -110,3 +110,21 @@ def test_path_levels_at_k16():
     for h in range(1, 17):
         assert tab.level_dict(h) == want[h], h
     assert tab.total() == sum(1 for i in range(20 - 15) if len(set(colors[i:i + 16])) == 16)
+
+
+def test_u256_arithmetic():
+    # the oracle's 256-bit add, multiply and small division against Python's integers
+    M = 1 << 256
+    rng = np.random.default_rng(9)
+    cases = [(0, 0, 1), (M - 1, 1, 7), (M - 1, M - 1, 3), (1 << 128, 1 << 127, 5), (1 << 192, 1 << 64, 15),
+             ((1 << 255) + 12345, 2, 16), (2 ** 64 - 1, 2 ** 64 - 1, 2 ** 64 - 1)]
+    for _ in range(300):
+        bits = rng.integers(1, 257, 2)
+        a = int(rng.integers(0, 2 ** 62)) << int(max(0, bits[0] - 62)) | int(rng.integers(0, 2 ** 62))
+        b = int(rng.integers(0, 2 ** 62)) << int(max(0, bits[1] - 62)) | int(rng.integers(0, 2 ** 62))
+        cases.append((a % M, b % M, int(rng.integers(1, 2 ** 63))))
+    for a, b, d in cases:
+        s, p, q, r, so, po = O.u256_ops(a, b, d)
+        assert s == (a + b) % M and so == (a + b >= M)
+        assert p == (a * b) % M and po == (a * b >= M)
+        assert q == a // d and r == a % d
