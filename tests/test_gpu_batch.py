@@ -146,3 +146,25 @@ def test_batch_scheduler_routes_large_instances_to_the_level_kernels(plain_nnz):
         assert bt.totals() == pt.totals()
     for (g, c, k), bt in list(zip(inst, tabs))[:4]:
         assert_tables_equal(bt, O.Table(g, c, k, O.ROOT_ZERO), k, f"scheduled batch n={g.n} k={k}")
+
+
+@pytest.mark.parametrize("bad", ["plain", "persistent"])
+def test_batch_scheduler_error_in_either_half(bad):
+    # one invalid instance (a colour >= k) on either side of the scheduler: the call
+    # fails with EINVAL after the other side has finished, and returns no table
+    S = scc()
+    inst = instances(seed0=300)
+    dev = [(S.DeviceGraph.from_graph(g), c.copy(), k) for g, c, k in inst]
+    big = [i for i, (g, _, _) in enumerate(inst) if g.nnz >= 5000]
+    small = [i for i, (g, _, _) in enumerate(inst) if 0 < g.nnz < 5000]
+    assert big and small
+    i = big[0] if bad == "plain" else small[0]
+    g, c, k = dev[i]
+    c[0] = k
+    dev[i] = (g, c, k)
+    with pytest.raises(S.SccError) as e:
+        S.build_batch(dev, plain_nnz=5000)
+    assert e.value.status == S.EINVAL
+    # the library is still usable afterwards
+    tabs, rep = S.build_batch([x for j, x in enumerate(dev) if j != i], plain_nnz=5000)
+    assert rep["plain_instances"] == len(big) - (1 if bad == "plain" else 0)
