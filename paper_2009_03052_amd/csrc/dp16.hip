@@ -691,10 +691,29 @@ __global__ __launch_bounds__(BLOCK) void k16_scatter(const uint64_t *kin, const 
 // ---------------------------------------------------------------------------
 // Aggregation of sorted terms
 // ---------------------------------------------------------------------------
-__global__ void k16_heads(const uint64_t *keys, int64_t N, uint64_t *flag)
+constexpr int RUN_ITEMS = 4;                       // sorted terms per thread of the run sums
+constexpr int RUN_TILE = BLOCK * RUN_ITEMS;         // sorted terms per block
+
+// Run heads (first terms of runs of equal words) per block of RUN_TILE sorted terms.
+__global__ __launch_bounds__(BLOCK) void k16_heads(const uint64_t *keys, int64_t N, uint64_t *bcount)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < N) flag[i] = (i == 0 || keys[i] != keys[i - 1]) ? 1u : 0u;
+    __shared__ uint32_t wsum[WPB];
+    const int64_t i0 = (int64_t)blockIdx.x * RUN_TILE + (int64_t)threadIdx.x * RUN_ITEMS;
+    uint32_t c = 0;
+    uint64_t prev = i0 > 0 && i0 < N ? keys[i0 - 1] : 0;
+#pragma unroll
+    for (int j = 0; j < RUN_ITEMS; j++) {
+        const int64_t i = i0 + j;
+        if (i < N) {
+            const uint64_t kw = keys[i];
+            if (i == 0 || kw != prev) c++;
+            prev = kw;
+        }
+    }
+    const uint32_t t = (uint32_t)wave_sum64(c);
+    if (lane_id() == 0) wsum[threadIdx.x / WAVE] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) bcount[blockIdx.x] = (uint64_t)wsum[0] + wsum[1] + wsum[2] + wsum[3];
 }
 
 // x += v at p (two 64-bit atomics, the low word's carry passed on); true when
@@ -737,7 +756,7 @@ struct RunArgs {
     const uint64_t *keys;       // sorted words
     const uint32_t *perm;       // term index of each sorted word
     const CT *tcnt;
-    const uint64_t *hpos;       // exclusive scan of the run heads: output index of each run
+    const uint64_t *bhead;      // exclusive scan of the blocks' run heads
     int64_t N;
     int KB;
     int64_t v0;
@@ -753,12 +772,11 @@ struct RunArgs {
 // segmented scan over lanes, and the last element of each run piece writes the
 // piece's sum: a run that lies wholly in the wave's range is stored, a piece of
 // a longer run is added to the run's output atomically.
-constexpr int RUN_ITEMS = 4;
-
 template <typename CT>
 __global__ __launch_bounds__(BLOCK) void k16_runsum(RunArgs<CT> A)
 {
-    const int lane = lane_id();
+    __shared__ uint32_t wheads[WPB];
+    const int lane = lane_id(), wv = threadIdx.x / WAVE;
     const int64_t i0 = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) * RUN_ITEMS;
     uint64_t word[RUN_ITEMS], o[RUN_ITEMS];
     CT val[RUN_ITEMS];
@@ -775,7 +793,22 @@ __global__ __launch_bounds__(BLOCK) void k16_runsum(RunArgs<CT> A)
     for (int j = 0; j < RUN_ITEMS; j++) {
         const int64_t i = i0 + j;
         val[j] = valid[j] ? A.tcnt[A.perm[i]] : Cnt<CT>::of(0);
-        o[j] = valid[j] ? A.hpos[i] - (head[j] ? 0u : 1u) : 0u;
+    }
+    // output index of each term's run: the heads before it, minus one when it is
+    // not a head itself (heads of earlier blocks, earlier waves, earlier lanes,
+    // then this thread's own)
+    uint32_t nh = 0;
+#pragma unroll
+    for (int j = 0; j < RUN_ITEMS; j++) nh += head[j] ? 1u : 0u;
+    const uint32_t hincl = wave_incl_scan32(nh);
+    if (lane == WAVE - 1) wheads[wv] = hincl;
+    __syncthreads();
+    uint64_t before = A.bhead[blockIdx.x] + (hincl - nh);
+    for (int q = 0; q < wv; q++) before += wheads[q];
+#pragma unroll
+    for (int j = 0; j < RUN_ITEMS; j++) {
+        before += head[j] ? 1u : 0u;
+        o[j] = valid[j] ? before - 1u : 0u;
     }
     bool wrap = false, any = false;
     CT tail = Cnt<CT>::of(0);   // this thread's elements after its last head (all of them without one)
@@ -1142,7 +1175,7 @@ scc_status build_pass(scc16_table *T, int x_level, int h, const Lev16 *S, Lev16 
         uint64_t *ka = (uint64_t *)sc.get((size_t)nmax * 8), *kb = (uint64_t *)sc.get((size_t)nmax * 8);
         uint32_t *pa = (uint32_t *)sc.get((size_t)nmax * 4), *pb = (uint32_t *)sc.get((size_t)nmax * 4);
         CT *tc = (CT *)sc.get((size_t)nmax * CB);
-        uint64_t *flag = (uint64_t *)sc.get((size_t)nmax * 8);
+        uint64_t *flag = (uint64_t *)sc.get((size_t)((nmax + RUN_TILE - 1) / RUN_TILE + 1) * 8);
         uint64_t *hist = (uint64_t *)sc.get((size_t)nbs * RADIX * 8);
         if (!ka || !kb || !pa || !pb || !tc || !flag || !hist) return set_error(SCC_ENOMEM, "level %d sort", h);
         Timer tm;
@@ -1164,8 +1197,9 @@ scc_status build_pass(scc16_table *T, int x_level, int h, const Lev16 *S, Lev16 
             s = radix_sort(T, &keys, kb, &perm, pb, N, KB + vb, hist, word, sort_bytes);
             if (s) return s;
             sort_ms += tm.stop(T->stream);
-            hipLaunchKernelGGL(k16_heads, dim3(blocks_for(N, 256)), dim3(256), 0, T->stream, keys, N, flag);
-            s = scan_u64(T, flag, N, word);
+            const int64_t nrb = (N + RUN_TILE - 1) / RUN_TILE;
+            hipLaunchKernelGGL(k16_heads, dim3((unsigned)nrb), dim3(BLOCK), 0, T->stream, keys, N, flag);
+            s = scan_u64(T, flag, nrb, word);
             if (s) return s;
             uint64_t U = 0;
             HIP_TRY(hipMemcpyAsync(&U, word, 8, hipMemcpyDeviceToHost, T->stream));
@@ -1175,7 +1209,7 @@ scc_status build_pass(scc16_table *T, int x_level, int h, const Lev16 *S, Lev16 
             if (!ok || !oc) return set_error(SCC_ENOMEM, "level %d records", h);
             HIP_TRY(hipMemsetAsync(oc, 0, (size_t)U * CB, T->stream));
             RunArgs<CT> R{keys, perm, tc, flag, N, KB, v0, oc, ok, out.off, err};
-            hipLaunchKernelGGL((k16_runsum<CT>), dim3(blocks_for(N, BLOCK * RUN_ITEMS)), dim3(BLOCK), 0, T->stream, R);
+            hipLaunchKernelGGL((k16_runsum<CT>), dim3((unsigned)nrb), dim3(BLOCK), 0, T->stream, R);
             hipLaunchKernelGGL((k16_finish<CT>), dim3(blocks_for((int64_t)U, 256)), dim3(256), 0, T->stream, ok, oc,
                                (int64_t)U, KB, k, 2 * (h - 1), x_level, err);
             HIP_TRY(hipGetLastError());
