@@ -265,9 +265,15 @@ def variable_length(scc, dg, dcol, k, ns, sseed, verts, par, zinfo):
     ev[2].record()
     torch.cuda.synchronize()
     vi = vt.info()
+    # the fixed layout here is already narrow (a u16 key and a 64-bit count for
+    # most vertices); a layout of 16-bit keys and 128-bit counts throughout is
+    # 18 bytes per stored count
+    entries = sum(int(zinfo.nnz[h]) for h in range(2, k + 1))
     out = {"build_s": ev[0].elapsed_time(ev[1]) / 1e3, "record_bytes": int(vi.record_bytes),
            "fixed_record_bytes": int(zinfo.record_bytes),
            "record_saving": 1 - vi.record_bytes / zinfo.record_bytes if zinfo.record_bytes else None,
+           "entries": entries,
+           "saving_vs_128_bit_counts": 1 - vi.record_bytes / (18 * entries) if entries else None,
            "table_bytes": int(vi.bytes), "fixed_table_bytes": int(zinfo.bytes),
            "sample_per_s": ns / (ev[1].elapsed_time(ev[2]) / 1e3)}
     del vt
