@@ -13,7 +13,10 @@ Prints one JSON line. `value` is classified samples per second of whole steps
 combine with compaction and packing, level-k totals): the algorithmic bytes of
 its launches divided by their duration, measured with HIP events on the
 build's stream; `roofline_parts` splits it into the gather and the combine and
-adds the sampler.
+adds the sampler. The large line also carries `batched_vs_plain` and
+`served_vs_fifo`: the batching workload with three timed steps per group, and
+the serving workload's trace through continuous batching and first-in first-out
+only (`--no-companions` leaves them out).
 """
 from __future__ import annotations
 
@@ -51,6 +54,8 @@ def parse():
                         "2^18 is the library's default)")
     p.add_argument("--requests", type=int, default=2000, help="serving: requests per run")
     p.add_argument("--window", type=float, default=40.0, help="serving: longest arrival window per run (s)")
+    p.add_argument("--no-companions", action="store_true",
+                   help="large: leave out the shortened batching and serving comparisons added to the line")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="also run a plain 1 GiB device copy (reference for HBM traffic counters)")
     return p.parse_args()
@@ -337,7 +342,7 @@ def tables_equal_on_device(ta, tb, k):
     return True
 
 
-def run_batching(a):
+def run_batching(a, emit=True):
     import torch
 
     import paper_2009_03052_amd as scc
@@ -419,7 +424,9 @@ def run_batching(a):
         "batch_report": {k: v for k, v in reps[-1].items() if k != "probes"},
         "tuning_probes": tuned["all"]["probes"],
     }
-    print(json.dumps(out), flush=True)
+    if emit:
+        print(json.dumps(out), flush=True)
+    return out
 
 
 SMALL_REQUEST = 1 << 14   # serving: requests of at most this many samples go first, whole
@@ -613,7 +620,7 @@ def run_k16(a):
     print(json.dumps(out), flush=True)
 
 
-def run_serving(a):
+def run_serving(a, emit=True, modes=("continuous", "continuous_age10ms", "continuous_equal", "fifo")):
     import torch
 
     import paper_2009_03052_amd as scc
@@ -657,6 +664,8 @@ def run_serving(a):
     # requests; the plain equal shares and heavier AGS rounds are reported beside it
     for name, fifo, aw, tau, small in (("continuous", False, 1.0, 0.0, True), ("continuous_age10ms", False, 1.0, 0.01, False),
                                        ("continuous_equal", False, 1.0, 0.0, False), ("fifo", True, 1.0, 0.0, False)):
+        if name not in modes:
+            continue
         srv, sess = server(fifo, aw, tau, small)
         res[name] = drive(srv, trace, rate, sess, a.window, keep_every=40 if name == "continuous" else 0)
         srv.close()
@@ -694,14 +703,19 @@ def run_serving(a):
         "continuous": {k: c[k] for k in keep}, "fifo": {k: f[k] for k in keep},
         "policy": f"small requests (<= {SMALL_REQUEST} samples) first and whole, then submission order; steps "
                   f"of {a.serve_step} samples, cut to {SMALL_STEP} while a small request runs",
-        "continuous_age_weighted_shares_10ms": {k: res["continuous_age10ms"][k] for k in keep},
-        "continuous_equal_shares": {k: res["continuous_equal"][k] for k in keep},
         "served_equal_alone": alone_equal, "served_checked": len(c["kept"]),
         "p99_speedup_vs_fifo": f["p99_ms"] / c["p99_ms"] if c["p99_ms"] > 0 else None,
         "p50_speedup_vs_fifo": f["p50_ms"] / c["p50_ms"] if c["p50_ms"] > 0 else None,
         "throughput_vs_fifo": c["samples_per_s"] / f["samples_per_s"] if f["samples_per_s"] > 0 else None,
     }
-    print(json.dumps(out), flush=True)
+    if "continuous_age10ms" in res:
+        out["continuous_age_weighted_shares_10ms"] = {k: res["continuous_age10ms"][k] for k in keep}
+    if "continuous_equal" in res:
+        out["continuous_equal_shares"] = {k: res["continuous_equal"][k] for k in keep}
+    del tabs
+    if emit:
+        print(json.dumps(out), flush=True)
+    return out
 
 
 def _u(x):
@@ -899,7 +913,42 @@ def main():
         out["variable_length_counts"] = vl
     if base is not None:
         out["cpu_baseline"] = base
+    if a.workload == "large" and not a.no_round_skipping and not a.no_companions and not a.small:
+        # the batched and served forms beside the plain one, shortened (the full runs are
+        # --workload batching and --workload serving)
+        del tab, dg, dcol, verts, par, code, cls
+        torch.cuda.empty_cache()
+        out["batched_vs_plain"] = companion_batching(a)
+        torch.cuda.empty_cache()
+        out["served_vs_fifo"] = companion_serving(a)
     print(json.dumps(out), flush=True)
+
+
+def companion_batching(a):
+    """The batching workload, three timed steps per group."""
+    b = run_batching(argparse.Namespace(**{**vars(a), "steps": 3}), emit=False)
+    g = b["groups"]
+    return {"plain_s": b["plain_s"], "batched_s": b["batched_s"], "speedup_vs_plain": b["speedup_vs_plain"],
+            "colourings_speedup_vs_plain": g["colourings"]["speedup_vs_plain"],
+            "uneven_graphs_speedup_vs_plain": g["uneven_graphs"]["speedup_vs_plain"],
+            "batched_tables_equal_plain": b["batched_tables_equal_plain"], "steps": 3,
+            "workload": b["config"]["workload"]}
+
+
+def companion_serving(a):
+    """The serving workload's trace, continuous batching (small requests first) against
+    first-in first-out only."""
+    r = run_serving(argparse.Namespace(**{**vars(a), "requests": 2000, "window": 40.0}), emit=False,
+                    modes=("continuous", "fifo"))
+    c, f = r["continuous"], r["fifo"]
+    return {"continuous_p50_ms": c["p50_ms"], "continuous_p99_ms": c["p99_ms"],
+            "fifo_p50_ms": f["p50_ms"], "fifo_p99_ms": f["p99_ms"],
+            "p50_speedup_vs_fifo": r["p50_speedup_vs_fifo"], "p99_speedup_vs_fifo": r["p99_speedup_vs_fifo"],
+            "saturated_samples_per_s": r["saturated_samples_per_s"],
+            "saturated_throughput_vs_fifo": r["saturated_throughput_vs_fifo"],
+            "served_equal_alone": r["served_equal_alone"], "served_checked": r["served_checked"],
+            "requests_submitted": r["config"]["requests"], "completed": c["completed"],
+            "window_s": r["config"]["window_s"], "workload": r["config"]["workload"]}
 
 
 # ---------------------------------------------------------------------------
