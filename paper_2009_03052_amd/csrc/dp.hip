@@ -1346,6 +1346,78 @@ __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(8, 8)
     combine_vertex_pf<false, PMAX, true>(A, __builtin_amdgcn_readfirstlane(rows[blockIdx.x]), sm, nullptr, wide_list, wide_count);
 }
 
+// The combine's width test alone, one vertex per lane (rows: a row list, else
+// vertices 0..nrows-1). At levels where most vertices need 128-bit inputs, a
+// wave per vertex that only learns this would hold a combine's LDS while it
+// waits on the same few loads. Same bound U and tests as combine_vertex_pf: an
+// overflowing vertex is flagged, one with U = 0 has no nonzero output and is
+// finished here, and the rest are listed: 64-bit inputs in narrow
+// (count[5]), high words in neighbour sums only at the front of wide_list
+// (count[0]), own records with high words at its back (count[2]).
+__global__ void __launch_bounds__(256) k_combine_classify(CombineArgs A, const int32_t *rows, int64_t nrows,
+                                                          int32_t *narrow, int *wide_list, int *count)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool in = i < nrows;
+    const int64_t v = in ? (rows ? (int64_t)rows[i] : i) : 0;
+    const int h = A.h;
+    const int plo = A.bal ? 2 : 1, phi = A.bal ? h - 2 : h - 1;
+    int cls = -1;   // 0 narrow, 1 front of wide_list, 2 back
+    if (in) {
+        u128 N[SCC_KMAX], M[SCC_KMAX];
+        bool xwide = false, mwide = false;
+#pragma unroll
+        for (int q = 1; q < SCC_KMAX; q++) {
+            N[q] = 1;
+            M[q] = 0;
+            if (q > phi) continue;
+            if (q >= 2) {
+                const uint64_t hd = A.lev[q].P.loc[v];
+                xwide |= h_wide<false>(hd);
+                N[q] = h_N<false>(A.lev[q], hd);
+            }
+            if (A.M[q]) M[q] = A.M[q][v];
+            mwide |= hi64(M[q]) != 0;
+        }
+        u128 U = 0;
+#pragma unroll
+        for (int hp = 1; hp < SCC_KMAX; hp++) {
+            if (hp < plo || hp > phi) continue;
+            u128 Mp = 0;   // M[h - hp], picked without a dynamic register index
+#pragma unroll
+            for (int q = 1; q < SCC_KMAX; q++)
+                if (q + hp == h) Mp = M[q];
+            U = sat_add(U, sat_mul(N[hp], Mp));
+        }
+        if (U == ~(u128)0 || bitlen128(U) > A.max_bits) {
+            atomicOr(A.err, 1);
+            A.meta[v] = 0;
+            A.Nout[v] = 0;
+        } else if (U == 0) {
+            A.meta[v] = 0;
+            A.Nout[v] = 0;
+        } else {
+            const bool wide = hi64(U) != 0 && (xwide || mwide);
+            cls = !wide ? 0 : (xwide ? 2 : 1);
+        }
+    }
+    // one atomic per wave and list
+    const uint64_t b0 = __ballot(cls == 0), b1 = __ballot(cls == 1), b2 = __ballot(cls == 2);
+    int base0 = 0, base1 = 0, base2 = 0;
+    if (lane_id() == 0) {
+        if (b0) base0 = atomicAdd(count + 5, __popcll(b0));
+        if (b1) base1 = atomicAdd(count, __popcll(b1));
+        if (b2) base2 = atomicAdd(count + 2, __popcll(b2));
+    }
+    base0 = __shfl(base0, 0);
+    base1 = __shfl(base1, 0);
+    base2 = __shfl(base2, 0);
+    const uint64_t below = lanemask_lt();
+    if (cls == 0) narrow[base0 + __popcll(b0 & below)] = (int32_t)v;
+    else if (cls == 1) wide_list[base1 + __popcll(b1 & below)] = (int)v;
+    else if (cls == 2) wide_list[A.g.n - 1 - (base2 + __popcll(b2 & below))] = (int)v;
+}
+
 // the listed vertices, with high words in LDS as well. OWN: vertices whose own
 // records have high words, listed from the back of wide_list (lds = 2 (xoff_h +
 // soff_h) words); else vertices with high words in neighbour sums only, listed
@@ -2121,14 +2193,15 @@ static scc_status build_levels(scc_table *T)
     uint32_t *meta = (uint32_t *)get((size_t)n * 4 + 256);
     u128 *Nsc = (u128 *)get((size_t)n * 16 + 256);
     int *wide_list = (int *)get((size_t)n * 4 + 256);
-    if (!slot_key || !slot_lo || !slot_hi || !words || !meta || !Nsc || !wide_list)
+    int32_t *narrow = (int32_t *)get((size_t)n * 4 + 256);   // the classified levels' 64-bit vertices
+    if (!slot_key || !slot_lo || !slot_hi || !words || !meta || !Nsc || !wide_list || !narrow)
         return set_error(SCC_ENOMEM, "combine scratch (%lld bytes)", (long long)n * maxW * 18);
 
     for (int h = 2; h <= k; h++) {
         const bool last = h == k;
         int64_t top_wide_rows = 0;   // rows of the sums gathered now whose high words exist
         HIP_TRY(hipEventRecord(ev[h][0], st));
-        HIP_TRY(hipMemsetAsync(err, 0, 16, st));   // flags and the level's counts of listed rows
+        HIP_TRY(hipMemsetAsync(err, 0, 32, st));   // flags and the level's counts of listed rows
         const int hs = h - 1;   // neighbour sums needed now
         if (hs >= 2 && s_need[hs]) {
             TableSums &Sx = T->S[hs];
@@ -2235,7 +2308,8 @@ static scc_status build_levels(scc_table *T)
         }
         C.key_xidx = T->key_xidx; C.W = HL.W[h];
         // many rows of the top sum level with high words: most vertices will be
-        // listed for the 128-bit combine, so the listing pass stages late
+        // listed for the 128-bit combine, so they are classified one per lane
+        // first (a listing pass at levels 2 and 3 stages late instead)
         C.late_dma = 8 * top_wide_rows > n;
         C.slot_key = slot_key; C.slot_lo = slot_lo; C.slot_hi = slot_hi;
         C.meta = meta; C.Nout = Nsc; C.err = err;
@@ -2248,7 +2322,22 @@ static scc_status build_levels(scc_table *T)
                 HIP_TRY(hipMemsetAsync(Nsc, 0, (size_t)n * 16, st));
             }
             const int phi = C.bal ? h - 2 : h - 1;
-            if (h == 2 && !zl && !C.bal)
+            if (C.late_dma && h >= 4) {
+                // most vertices will need 128-bit inputs: the width test one vertex
+                // per lane first, then the 64-bit combine of the narrow ones alone
+                const int64_t nr = zl ? nzero : n;
+                if (nr)
+                    hipLaunchKernelGGL(k_combine_classify, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, st, C,
+                                       zl ? zrows : nullptr, nr, narrow, wide_list, err + 1);
+                int nn = 0;
+                HIP_TRY(hipMemcpyAsync(&nn, err + 6, 4, hipMemcpyDeviceToHost, st));
+                HIP_TRY(hipStreamSynchronize(st));
+                CombineArgs Cn = C;
+                Cn.late_dma = 0;
+                if (phi <= 3) launch_combine<3>(Cn, n, narrow, nn, lds, st, wide_list, err + 1);
+                else if (phi <= 5) launch_combine<5>(Cn, n, narrow, nn, lds, st, wide_list, err + 1);
+                else launch_combine<SCC_KMAX - 1>(Cn, n, narrow, nn, lds, st, wide_list, err + 1);
+            } else if (h == 2 && !zl && !C.bal)
                 hipLaunchKernelGGL(k_combine_level2, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, C);
             else if (h == 3 && !zl && !C.bal)
                 hipLaunchKernelGGL(k_combine_level3, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, C, wide_list,
