@@ -897,6 +897,8 @@ def main():
         "combine_ms": [round(info.combine_ms[h], 3) for h in range(2, k + 1)],
         "totals_ms": round(info.totals_ms, 3),
         "wide_vertices": [int(info.wide_vertices[h]) for h in range(1, k + 1)],
+        "wide_input_rows": [[int(x) for x in info.wide_input_rows[h]] for h in range(1, k + 1)],
+        "lane_width_test_levels": [h for h in range(1, k + 1) if info.lane_width_test >> h & 1],
         "table_bytes": int(info.bytes), "t": str(_u(info.t)),
         "roofline": join,
         "roofline_parts": parts,

@@ -114,9 +114,17 @@ typedef struct {
                                   count in l bytes, a byte-offset checkpoint every 32
                                   entries. The sampler's running sums are built first.
                                   Every query and sample is unchanged, bit for bit. */
+    int width_test;            /* how the combine learns which vertices need 128-bit inputs
+                                  (levels 4..k): SCC_WIDTH_AUTO (0): one vertex per lane
+                                  first at levels where most rows of the top-level neighbour
+                                  sums have high words, else inside the per-vertex combine;
+                                  SCC_WIDTH_PER_LANE: one vertex per lane at every such
+                                  level; SCC_WIDTH_PER_WAVE: always inside the combine.
+                                  Results are identical in every mode. */
 } scc_build_opts;
 
 enum { SCC_GATHER_AUTO = 0, SCC_GATHER_GROUPED = 1, SCC_GATHER_ROW = 2 };
+enum { SCC_WIDTH_AUTO = 0, SCC_WIDTH_PER_LANE = 1, SCC_WIDTH_PER_WAVE = 2 };
 
 /*
  * scc_build_table -- the build-up phase (Sec. 2.1, Eq. (1)).
@@ -173,6 +181,15 @@ typedef struct {
     double combine_ms[9];      /* device time of the combine of level h (Eq. (1) products,
                                   compaction, packing; scc_build_table only) */
     double totals_ms;          /* device time of the level-k totals and running sums */
+    int64_t wide_input_rows[9][3]; /* vertices of level h combined from 128-bit inputs, by
+                                  route (scc_build_table only): [0] high words in neighbour
+                                  sums of more than the top level h-1 (none in own records),
+                                  [1] in the top-level sums only (a launch of its own, with LDS
+                                  for that level's high words; levels in lane_width_test only),
+                                  [2] in own records */
+    int lane_width_test;       /* bit h: level h's width test (64- or 128-bit inputs) ran one
+                                  vertex per lane before the combine, as at levels where most
+                                  vertices have high words in their top-level neighbour sums */
 } scc_table_info;
 
 /* Table summary (host struct; no device work). */

@@ -25,6 +25,7 @@ LIB_PATH = os.path.join(_HERE, "libscc.so")
 OK, EINVAL, ENOMEM, EOVERFLOW, EDEVICE, EEMPTY, EBUSY, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
 ROOT_ZERO, ROOT_ALL, ROOT_BALANCED = 0, 1, 2
 GATHER_AUTO, GATHER_GROUPED, GATHER_ROW = 0, 1, 2
+WIDTH_AUTO, WIDTH_PER_LANE, WIDTH_PER_WAVE = 0, 1, 2
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with paper_2009_03052_amd/build.py "
@@ -48,7 +49,7 @@ class _Csr(C.Structure):
 class _BuildOpts(C.Structure):
     _fields_ = [("rooting", C.c_int), ("max_bits", C.c_int), ("stream", C.c_void_p),
                 ("alloc", C.POINTER(_Allocator)), ("hub_degree", C.c_int), ("no_validate", C.c_int),
-                ("gather_mode", C.c_int), ("vlc", C.c_int)]
+                ("gather_mode", C.c_int), ("vlc", C.c_int), ("width_test", C.c_int)]
 
 
 class _Instance(C.Structure):
@@ -82,7 +83,7 @@ class TableInfo(C.Structure):
                 ("t", C.c_uint64 * 2), ("tj", (C.c_uint64 * 2) * 32), ("level_ms", C.c_double * 9),
                 ("gather_ms", C.c_double * 9), ("num_hubs", C.c_int), ("stars", C.c_uint64 * 2),
                 ("record_bytes", C.c_int64), ("vlc", C.c_int), ("combine_ms", C.c_double * 9),
-                ("totals_ms", C.c_double)]
+                ("totals_ms", C.c_double), ("wide_input_rows", (C.c_int64 * 3) * 9), ("lane_width_test", C.c_int)]
 
 
 class _Build16Opts(C.Structure):
@@ -250,7 +251,7 @@ class Table:
 
     def __init__(self, graph, colors, k: int, rooting: int = ROOT_ZERO, max_bits: int = 128,
                  validate: bool = True, stream=None, use_torch_allocator: bool = True, hub_degree: int = 0,
-                 gather_mode: int = 0, vlc: bool = False):
+                 gather_mode: int = 0, vlc: bool = False, width_test: int = WIDTH_AUTO):
         self.graph = graph
         self.k = k
         self._stream = stream
@@ -270,7 +271,7 @@ class Table:
             cptr = C.c_void_p(self.colors.ctypes.data)
         opts = _BuildOpts(rooting, max_bits, _stream_ptr(stream),
                           C.pointer(TORCH_ALLOCATOR) if use_torch_allocator else None, hub_degree,
-                          0 if validate else 1, gather_mode, 1 if vlc else 0)
+                          0 if validate else 1, gather_mode, 1 if vlc else 0, width_test)
         self._h = _P()
         _check(_lib.scc_build_table(C.byref(csr), cptr, k, C.byref(opts), C.byref(self._h)))
 

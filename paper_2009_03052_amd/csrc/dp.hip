@@ -924,6 +924,7 @@ struct CombineArgs {
     const int16_t *key_xidx;              // [k * nkeys]
     int W;                                // slot capacity = W_h
     int late_dma;                         // listing passes stage the sums after the width test
+    int hi_cap;                           // > 0: words of LDS for staged sum high words (checked)
     uint16_t *slot_key;
     uint64_t *slot_lo, *slot_hi;          // slot_hi may be null (no wide vertex)
     uint32_t *meta;
@@ -934,7 +935,7 @@ struct CombineArgs {
 template <int ILP>
 __device__ inline void combine_outputs(const CombineArgs &A, int64_t v, int cv, const uint64_t *Xlo,
                                        const uint64_t *Slo, const uint64_t *Xhi, const uint64_t *Shi, bool owide,
-                                       bool wide);
+                                       bool wide, int s_hi0 = 0, const uint16_t *tx_lds = nullptr);
 
 // Counts of vertex v at level h. The low words of v's own counts X and of its
 // neighbour sums S are staged in lo_area (LDS); high words are needed only when
@@ -1022,10 +1023,14 @@ __device__ inline u128 mul_64x128(uint64_t x, u128 s) { return (u128)x * lo64(s)
 // ILP = 4: an output's terms four at a time (the level kernels); ILP = 1: one
 // at a time (the batched worker, whose register budget has no room for the
 // four-wide form)
+// s_hi0: Shi holds the high words of the neighbour sums from staging index
+// s_hi0 on (the sums below have none); with own counts in 64 bits, an output
+// whose T'' block lies below s_hi0 takes 64 x 64-bit products. tx_lds: the
+// level's term descriptors copied to LDS (level_terms), else read from L.
 template <int ILP>
 __device__ inline void combine_outputs(const CombineArgs &A, int64_t v, int cv, const uint64_t *Xlo,
                                        const uint64_t *Slo, const uint64_t *Xhi, const uint64_t *Shi, bool owide,
-                                       bool wide)
+                                       bool wide, int s_hi0, const uint16_t *tx_lds)
 {
     const DevLut &L = *A.L;
     const int lane = threadIdx.x;
@@ -1050,7 +1055,7 @@ __device__ inline void combine_outputs(const CombineArgs &A, int64_t v, int cv, 
             // terms four at a time: the four descriptors, then all their LDS
             // operands, are requested before any product, so that the loads of
             // a group overlap instead of one latency per term
-            const uint16_t *txs = L.term_xs + tb;
+            const uint16_t *txs = tx_lds ? tx_lds + (tb - L.term_base[h][1]) : L.term_xs + tb;
             const int n4 = ILP >= 4 ? (nsplit & ~3) : 0;
             if (!owide) {
                 uint64_t a64 = 0;
@@ -1069,7 +1074,7 @@ __device__ inline void combine_outputs(const CombineArgs &A, int64_t v, int cv, 
                     a64 += Xlo[xb + (xs & 0xffu)] * Slo[sb + (xs >> 8)];
                 }
                 acc = a64;
-            } else if (!wide) {
+            } else if (!wide || (!Xhi && sb < s_hi0)) {
                 for (int i = 0; i < n4; i += 4) {
                     uint32_t xs[4];
                     uint64_t xv[4], sv[4];
@@ -1096,7 +1101,7 @@ __device__ inline void combine_outputs(const CombineArgs &A, int64_t v, int cv, 
                         const int si = sb + (int)(xs[j] >> 8);
                         xv[j] = Xlo[xb + (xs[j] & 0xffu)];
                         sl[j] = Slo[si];
-                        sh2[j] = Shi[si];
+                        sh2[j] = Shi[si - s_hi0];
                     }
 #pragma unroll
                     for (int j = 0; j < 4; j++) acc += mul_64x128(xv[j], mk128(sl[j], sh2[j]));
@@ -1104,7 +1109,7 @@ __device__ inline void combine_outputs(const CombineArgs &A, int64_t v, int cv, 
                 for (int i = n4; i < nsplit; i++) {
                     const uint32_t xs = txs[i];
                     const int xi = xb + (int)(xs & 0xffu), si = sb + (int)(xs >> 8);
-                    acc += mul_64x128(Xlo[xi], mk128(Slo[si], Shi[si]));
+                    acc += mul_64x128(Xlo[xi], mk128(Slo[si], Shi[si - s_hi0]));
                 }
             } else {
                 for (int i = 0; i < nsplit; i++) {
@@ -1170,7 +1175,8 @@ __device__ inline void wait_vm_all() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 // worker's hi_area is global scratch: filled by ordinary stores)
 template <bool SLOTS, int PMAX, bool DMA, bool HI_LDS = false>
 __device__ inline void combine_vertex_pf(const CombineArgs &A, int64_t v, uint64_t *lo_area, uint64_t *hi_area,
-                                         int *wide_list, int *wide_count, bool own_hi = true)
+                                         int *wide_list, int *wide_count, bool own_hi = true,
+                                         const uint16_t *tx_lds = nullptr)
 {
     const DevLut &L = *A.L;
     const int lane = threadIdx.x;
@@ -1262,9 +1268,11 @@ __device__ inline void combine_vertex_pf(const CombineArgs &A, int64_t v, uint64
     }
     const bool owide = hi64(U) != 0;
     bool wide = false, xwide = false;
+    uint64_t smask = 0;   // bit q: the level-q neighbour sums have high words
     if (owide) {
         xwide = __ballot(lane >= 2 && lane <= phi && h_wide<SLOTS>(hd)) != 0;
-        wide = xwide || __ballot(lane >= 1 && lane <= phi && hi64(Mq) != 0) != 0;
+        smask = __ballot(lane >= 1 && lane <= phi && hi64(Mq) != 0);
+        wide = xwide || smask != 0;
     }
     if (wide && !hi_area) {
         // own records with high words: from the back of the list (wide_count[2]);
@@ -1274,6 +1282,17 @@ __device__ inline void combine_vertex_pf(const CombineArgs &A, int64_t v, uint64
             if (xwide) wide_list[A.g.n - 1 - atomicAdd(wide_count + 2, 1)] = (int)v;
             else wide_list[atomicAdd(wide_count, 1)] = (int)v;
         }
+        return;
+    }
+    // own counts in 64 bits: high words are staged from the lowest sum level that
+    // has them (hs_hi), at the start of hi_area
+    const int hs_hi = Xhi || !smask ? 1 : __builtin_ctzll(smask);
+    const int s_hi0 = L.soff[hs_hi];
+    if (wide && A.hi_cap > 0 && L.soff[phi + 1] - s_hi0 > A.hi_cap) {
+        // a launch sized for fewer high words than this vertex has (not expected:
+        // the listing applies the same test)
+        if (DMA) wait_vm_all();
+        if (lane == 0) { atomicOr(A.err, 4); A.meta[v] = 0; A.Nout[v] = 0; }
         return;
     }
     if (late) dma_sums();
@@ -1293,10 +1312,10 @@ __device__ inline void combine_vertex_pf(const CombineArgs &A, int64_t v, uint64
         const uint64_t *gl = A.Slo[hs] + (size_t)v * ws;
         if (!DMA)
             for (int i = WAVE + lane; i < ws; i += WAVE) Slo[L.soff[hs] + i] = gl[i];
-        if (wide) {
+        if (wide && hs >= hs_hi) {
             const bool sw128 = hi64(A.M[hs][v]) != 0;
             const uint64_t *gh = sw128 ? A.Shi[hs] + hi_row(A.Shrow[hs], v) * ws : nullptr;
-            uint64_t *dst = Shi + L.soff[hs];
+            uint64_t *dst = Shi + (L.soff[hs] - s_hi0);
             if (DMA && HI_LDS && sw128) lds_dma_words(gh, dst, ws);
             else
                 for (int i = lane; i < ws; i += WAVE) dst[i] = sw128 ? gh[i] : 0;
@@ -1324,7 +1343,7 @@ __device__ inline void combine_vertex_pf(const CombineArgs &A, int64_t v, uint64
     }
     if (DMA) wait_vm_all();
     __syncthreads();
-    combine_outputs<SLOTS ? 1 : 4>(A, v, cv, Xlo, Slo, stage_xhi ? Xhi : nullptr, Shi, owide, wide);
+    combine_outputs<SLOTS ? 1 : 4>(A, v, cv, Xlo, Slo, stage_xhi ? Xhi : nullptr, Shi, owide, wide, s_hi0, tx_lds);
 }
 
 // one workgroup per vertex, low words in LDS; vertices that need 128 bits are
@@ -1351,9 +1370,10 @@ __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(8, 8)
 // wave per vertex that only learns this would hold a combine's LDS while it
 // waits on the same few loads. Same bound U and tests as combine_vertex_pf: an
 // overflowing vertex is flagged, one with U = 0 has no nonzero output and is
-// finished here, and the rest are listed: 64-bit inputs in narrow
-// (count[5]), high words in neighbour sums only at the front of wide_list
-// (count[0]), own records with high words at its back (count[2]).
+// finished here, and the rest are listed: 64-bit inputs at the front of
+// narrow (count[5]); high words in the top-level neighbour sums only at its
+// back (count[6]); in lower-level sums too at the front of wide_list
+// (count[0]); own records with high words at its back (count[2]).
 __global__ void __launch_bounds__(256) k_combine_classify(CombineArgs A, const int32_t *rows, int64_t nrows,
                                                           int32_t *narrow, int *wide_list, int *count)
 {
@@ -1362,10 +1382,10 @@ __global__ void __launch_bounds__(256) k_combine_classify(CombineArgs A, const i
     const int64_t v = in ? (rows ? (int64_t)rows[i] : i) : 0;
     const int h = A.h;
     const int plo = A.bal ? 2 : 1, phi = A.bal ? h - 2 : h - 1;
-    int cls = -1;   // 0 narrow, 1 front of wide_list, 2 back
+    int cls = -1;   // 0 narrow, 1 front of wide_list, 2 its back, 3 back of narrow
     if (in) {
         u128 N[SCC_KMAX], M[SCC_KMAX];
-        bool xwide = false, mwide = false;
+        bool xwide = false, mwide = false, lower = false;
 #pragma unroll
         for (int q = 1; q < SCC_KMAX; q++) {
             N[q] = 1;
@@ -1378,6 +1398,7 @@ __global__ void __launch_bounds__(256) k_combine_classify(CombineArgs A, const i
             }
             if (A.M[q]) M[q] = A.M[q][v];
             mwide |= hi64(M[q]) != 0;
+            lower |= q < phi && hi64(M[q]) != 0;
         }
         u128 U = 0;
 #pragma unroll
@@ -1398,40 +1419,65 @@ __global__ void __launch_bounds__(256) k_combine_classify(CombineArgs A, const i
             A.Nout[v] = 0;
         } else {
             const bool wide = hi64(U) != 0 && (xwide || mwide);
-            cls = !wide ? 0 : (xwide ? 2 : 1);
+            cls = !wide ? 0 : (xwide ? 2 : (lower ? 1 : 3));
         }
     }
     // one atomic per wave and list
-    const uint64_t b0 = __ballot(cls == 0), b1 = __ballot(cls == 1), b2 = __ballot(cls == 2);
-    int base0 = 0, base1 = 0, base2 = 0;
+    const uint64_t b0 = __ballot(cls == 0), b1 = __ballot(cls == 1), b2 = __ballot(cls == 2), b3 = __ballot(cls == 3);
+    int base0 = 0, base1 = 0, base2 = 0, base3 = 0;
     if (lane_id() == 0) {
         if (b0) base0 = atomicAdd(count + 5, __popcll(b0));
         if (b1) base1 = atomicAdd(count, __popcll(b1));
         if (b2) base2 = atomicAdd(count + 2, __popcll(b2));
+        if (b3) base3 = atomicAdd(count + 6, __popcll(b3));
     }
     base0 = __shfl(base0, 0);
     base1 = __shfl(base1, 0);
     base2 = __shfl(base2, 0);
+    base3 = __shfl(base3, 0);
     const uint64_t below = lanemask_lt();
     if (cls == 0) narrow[base0 + __popcll(b0 & below)] = (int32_t)v;
     else if (cls == 1) wide_list[base1 + __popcll(b1 & below)] = (int)v;
     else if (cls == 2) wide_list[A.g.n - 1 - (base2 + __popcll(b2 & below))] = (int)v;
+    else if (cls == 3) narrow[A.g.n - 1 - (base3 + __popcll(b3 & below))] = (int32_t)v;
 }
 
 // the listed vertices, with high words in LDS as well. OWN: vertices whose own
 // records have high words, listed from the back of wide_list (lds = 2 (xoff_h +
 // soff_h) words); else vertices with high words in neighbour sums only, listed
 // from the front, which stage just those (lds = xoff_h + 2 soff_h words) and so
-// fit more waves per CU
-template <bool OWN>
+// fit more waves per CU; BACK: such vertices listed from the back of the list
+// (those with high words in the top-level sums only: lds = xoff_h + soff_h +
+// WS_{h-1} words, A.hi_cap = WS_{h-1})
+// The level's term descriptors of Eq. (1) (term_xs from term_base[h][1] on:
+// binom(k-1, h-1) (2^(h-1) - 1) of them) as 64-bit words of LDS, rounded up to 8
+__host__ __device__ inline int level_term_words(int k, int h)
+{
+    int b = 1;   // binom(k-1, h-1)
+    for (int i = 0; i < h - 1; i++) b = b * (k - 1 - i) / (i + 1);
+    const int n = b * ((1 << (h - 1)) - 1);
+    return (n * 2 + 63) / 64 * 8;
+}
+
+// persistent over the listed vertices: the LDS holds the level's term
+// descriptors (copied once), then each vertex's staging areas
+template <bool OWN, bool BACK = OWN>
 __global__ void __launch_bounds__(WAVE) k_combine_wide(CombineArgs A, const int *wide_list, const int *wide_count)
 {
     extern __shared__ uint64_t sm[];
     const int cnt = __builtin_amdgcn_readfirstlane(*wide_count);
-    const int lo_words = A.L->xoff[A.h] + A.L->soff[A.h];
+    if ((int)blockIdx.x >= cnt) return;
+    const DevLut &L = *A.L;
+    const int tw = level_term_words(L.k, A.h);
+    uint16_t *tx = (uint16_t *)sm;
+    const uint16_t *src = L.term_xs + L.term_base[A.h][1];
+    for (int i = threadIdx.x; i < tw * 4; i += WAVE) tx[i] = src[i];
+    uint64_t *lo = sm + tw;
+    const int lo_words = L.xoff[A.h] + L.soff[A.h];
+    __syncthreads();
     for (int i = blockIdx.x; i < cnt; i += gridDim.x) {
-        const int v = __builtin_amdgcn_readfirstlane(OWN ? wide_list[A.g.n - 1 - i] : wide_list[i]);
-        combine_vertex_pf<false, SCC_KMAX - 1, true, true>(A, v, sm, sm + lo_words, nullptr, nullptr, OWN);
+        const int v = __builtin_amdgcn_readfirstlane(BACK ? wide_list[A.g.n - 1 - i] : wide_list[i]);
+        combine_vertex_pf<false, SCC_KMAX - 1, true, true>(A, v, lo, lo + lo_words, nullptr, nullptr, OWN, tx);
         __syncthreads();
     }
 }
@@ -2322,7 +2368,10 @@ static scc_status build_levels(scc_table *T)
                 HIP_TRY(hipMemsetAsync(Nsc, 0, (size_t)n * 16, st));
             }
             const int phi = C.bal ? h - 2 : h - 1;
-            if (C.late_dma && h >= 4) {
+            const bool classified = h >= 4 && (T->width_test == SCC_WIDTH_PER_LANE ||
+                                               (T->width_test == SCC_WIDTH_AUTO && C.late_dma));
+            if (classified) {
+                T->lane_width_test |= 1 << h;
                 // most vertices will need 128-bit inputs: the width test one vertex
                 // per lane first, then the 64-bit combine of the narrow ones alone
                 const int64_t nr = zl ? nzero : n;
@@ -2349,21 +2398,34 @@ static scc_status build_levels(scc_table *T)
             // words in neighbour sums only) stride over as many waves as each
             // kernel's LDS staging lets the chip hold
             int dev = 0, ncu = 0, per_s = 0, per_own = 0;
-            const size_t lds_s = (size_t)(HL.xoff[h] + 2 * HL.soff[h]) * 8;
+            const size_t ltw = (size_t)level_term_words(k, h) * 8;   // the level's term descriptors
+            const size_t lds_s = (size_t)(HL.xoff[h] + 2 * HL.soff[h]) * 8 + ltw, lds_o = 2 * lds + ltw;
             HIP_TRY(hipGetDevice(&dev));
             HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
             HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_s, k_combine_wide<false>, WAVE, lds_s));
-            HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_own, k_combine_wide<true>, WAVE, 2 * lds));
+            HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_own, k_combine_wide<true>, WAVE, lds_o));
             const int64_t gs = std::min<int64_t>(n, std::max<int64_t>(1024, (int64_t)ncu * per_s));
             const int64_t go = std::min<int64_t>(n, std::max<int64_t>(1024, (int64_t)ncu * per_own));
             hipLaunchKernelGGL(k_combine_wide<false>, dim3((unsigned)gs), dim3(WAVE), lds_s, st, C, wide_list, err + 1);
-            hipLaunchKernelGGL(k_combine_wide<true>, dim3((unsigned)go), dim3(WAVE), 2 * lds, st, C, wide_list, err + 3);
+            hipLaunchKernelGGL(k_combine_wide<true>, dim3((unsigned)go), dim3(WAVE), lds_o, st, C, wide_list, err + 3);
+            if (classified) {
+                // high words in the top-level sums only (listed at the back of narrow):
+                // the high-word area holds that level alone, so more waves fit per CU
+                CombineArgs Ct = C;
+                Ct.hi_cap = HL.WS[phi];
+                const size_t lds_t = (size_t)(HL.xoff[h] + HL.soff[h] + HL.WS[phi]) * 8 + ltw;
+                int per_t = 0;
+                HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_t, (k_combine_wide<false, true>), WAVE, lds_t));
+                const int64_t gt = std::min<int64_t>(n, std::max<int64_t>(1024, (int64_t)ncu * per_t));
+                hipLaunchKernelGGL((k_combine_wide<false, true>), dim3((unsigned)gt), dim3(WAVE), lds_t, st, Ct,
+                                   (const int *)narrow, err + 7);
+            }
         }
         // record sizes and offsets; the pool size and the error flags in one read
         if (n) hipLaunchKernelGGL(k_words, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, meta, words);
         scc_status sst = scan_incl<uint64_t>(T, words, words, n);
         if (sst) return sst;
-        struct { int f[4]; uint64_t total; } hr{};
+        struct { int f[4]; uint64_t total; int g[2]; } hr{};   // the layout of err
         if (n) HIP_TRY(hipMemcpyAsync(err + 4, words + (n - 1), 8, hipMemcpyDeviceToDevice, st));
         HIP_TRY(hipMemcpyAsync(&hr, err, sizeof hr, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
@@ -2371,6 +2433,11 @@ static scc_status build_levels(scc_table *T)
         const uint64_t total = n ? hr.total : 0;
         if (herr[0] & 1) return set_error(SCC_EOVERFLOW, "a level-%d count needs more than %d bits", h, T->max_bits);
         if (herr[0] & 2) return set_error(SCC_EOVERFLOW, "a level-%d neighbour sum may exceed 128 bits", h);
+        if (herr[0] & 4)
+            return set_error(SCC_EDEVICE, "level %d: a vertex listed for the top-level 128-bit combine has more high words", h);
+        T->wide_input_rows[h][0] = herr[1];
+        T->wide_input_rows[h][1] = hr.g[1];
+        T->wide_input_rows[h][2] = herr[3];
         Lv.pool_words = total;
         Lv.pool = (uint64_t *)T->alloc((size_t)total * 8 + 64);
         if (!Lv.pool) return set_error(SCC_ENOMEM, "level %d pool (%llu words)", h, (unsigned long long)total);
@@ -2716,9 +2783,12 @@ extern "C" scc_status scc_build_table(const scc_csr *g, const uint8_t *colors, i
     if (o.max_bits != 64 && o.max_bits != 128) return set_error(SCC_EINVAL, "max_bits must be 64 or 128");
     if (o.gather_mode < SCC_GATHER_AUTO || o.gather_mode > SCC_GATHER_ROW)
         return set_error(SCC_EINVAL, "bad gather_mode %d", o.gather_mode);
+    if (o.width_test < SCC_WIDTH_AUTO || o.width_test > SCC_WIDTH_PER_WAVE)
+        return set_error(SCC_EINVAL, "bad width_test %d", o.width_test);
 
     scc_table *T = new_table(g, colors, k, o);
     T->gather_mode = o.gather_mode;
+    T->width_test = o.width_test;
     scc_status s = attach_graph(T, g, colors);
     if (!s && !o.no_validate) s = validate_graph(T);
     if (!s) s = make_key_maps(T);
@@ -2769,7 +2839,9 @@ extern "C" scc_status scc_table_info_get(const scc_table *t, scc_table_info *out
         out->level_ms[h] = t->level_ms[h];
         out->gather_ms[h] = t->gather_ms[h];
         out->combine_ms[h] = t->combine_ms[h];
+        for (int r = 0; r < 3; r++) out->wide_input_rows[h][r] = t->wide_input_rows[h][r];
     }
+    out->lane_width_test = t->lane_width_test;
     out->num_hubs = t->nhub;
     out->bytes = t->bytes;
     out->t[0] = lo64(t->t); out->t[1] = hi64(t->t);

@@ -66,11 +66,14 @@ struct scc_table {
     double gather_bytes[SCC_KMAX + 1] = {0};
     double combine_ms[SCC_KMAX + 1] = {0};     // combine, compaction and packing of level h
     double combine_bytes[SCC_KMAX + 1] = {0};
+    int64_t wide_input_rows[SCC_KMAX + 1][3] = {};   // 128-bit-input combines of level h, by route
+    int lane_width_test = 0;                   // bit h: level h's width test ran one vertex per lane
     double totals_ms = 0, totals_bytes = 0;
     int64_t bytes = 0;
     int hub_degree = 1024;           // rows above this degree are gathered in chunks
     int hub_chunk = 256;             // neighbours per chunk
     int gather_mode = SCC_GATHER_AUTO;
+    int width_test = SCC_WIDTH_AUTO;
     bool vlc = false;                // levels re-encoded with variable-length counts after the build
     int nhub = 0;
     bool stats_done = false;

@@ -12,10 +12,11 @@ def scc():
     return S
 
 
-def build_pair(g, colors, k, rooting=0, validate=True, hub_degree=0, gather_mode=0):
+def build_pair(g, colors, k, rooting=0, validate=True, hub_degree=0, gather_mode=0, width_test=0):
     S = scc()
     dg = S.DeviceGraph.from_graph(g)
-    gt = S.Table(dg, colors, k, rooting=rooting, validate=validate, hub_degree=hub_degree, gather_mode=gather_mode)
+    gt = S.Table(dg, colors, k, rooting=rooting, validate=validate, hub_degree=hub_degree, gather_mode=gather_mode,
+                 width_test=width_test)
     ot = O.Table(g, colors, k, rooting)
     return gt, ot
 

@@ -58,23 +58,28 @@ def test_chung_lu_k6_multi_tile(hub_degree, gather_mode):
     assert_tables_equal(gt, ot, 6, "cl20k")
 
 
-@pytest.mark.parametrize("gather_mode", [1, 2])
-def test_chung_lu_k8(gather_mode):
+# (gather mode, width test): both gathers with the automatic width test, and
+# each width test forced (one vertex per lane before the combine; inside it)
+GATHER_WIDTH = [(1, 0), (2, 0), (0, 1), (0, 2)]
+
+
+@pytest.mark.parametrize("gather_mode,width_test", GATHER_WIDTH)
+def test_chung_lu_k8(gather_mode, width_test):
     g = gg.chung_lu(3000, 12000, 2.3, 300, seed=13)
     colors = gg.colors(g.n, 8, seed=14)
-    gt, ot = build_pair(g, colors, 8, gather_mode=gather_mode)
+    gt, ot = build_pair(g, colors, 8, gather_mode=gather_mode, width_test=width_test)
     assert_tables_equal(gt, ot, 8, "cl3k-k8")
 
 
-@pytest.mark.parametrize("gather_mode", [1, 2])
-def test_counts_beyond_64_bits(gather_mode):
+@pytest.mark.parametrize("gather_mode,width_test", GATHER_WIDTH)
+def test_counts_beyond_64_bits(gather_mode, width_test):
     # a 6-star at a hub of degree 2^16 has about 1e22 copies (Sec. 3.2 footnote);
     # the leaves' neighbour sums need 128 bits (grouped rows redo them alone)
     leaves = 1 << 16
     edges = [(0, i) for i in range(1, leaves + 1)] + [(i, i + 1) for i in range(1, 200)]
     g = gg.csr_from_edges(leaves + 1, np.array(edges, np.int64))
     colors = np.concatenate([[0], (np.arange(leaves) % 5) + 1]).astype(np.uint8)
-    gt, ot = build_pair(g, colors, 6, gather_mode=gather_mode)
+    gt, ot = build_pair(g, colors, 6, gather_mode=gather_mode, width_test=width_test)
     assert_tables_equal(gt, ot, 6, "wide star")
     t, _ = gt.totals()
     assert t > 2 ** 64
@@ -86,8 +91,8 @@ def test_counts_beyond_64_bits(gather_mode):
     assert e.value.status == S.EOVERFLOW
 
 
-@pytest.mark.parametrize("gather_mode", [1, 2])
-def test_low_degree_rows_with_128_bit_sums(gather_mode):
+@pytest.mark.parametrize("gather_mode,width_test", GATHER_WIDTH)
+def test_low_degree_rows_with_128_bit_sums(gather_mode, width_test):
     # a hub of 2^17 leaves at k = 7, all rootings: the hub's level-6 sum exceeds
     # 2^64, so the leaves (rows of one or two neighbours, grouped in mode 1) need
     # 128-bit neighbour sums at level 6 and are redone alone
@@ -95,8 +100,15 @@ def test_low_degree_rows_with_128_bit_sums(gather_mode):
     edges = [(0, i) for i in range(1, leaves + 1)] + [(i, i + 1) for i in range(1, 200)]
     g = gg.csr_from_edges(leaves + 1, np.array(edges, np.int64))
     colors = np.concatenate([[0], (np.arange(leaves) % 6) + 1]).astype(np.uint8)
-    gt, ot = build_pair(g, colors, 7, rooting=O.ROOT_ALL, gather_mode=gather_mode)
+    gt, ot = build_pair(g, colors, 7, rooting=O.ROOT_ALL, gather_mode=gather_mode, width_test=width_test)
     assert_tables_equal(gt, ot, 7, "hub k7")
+    info = gt.info()
+    if width_test == 1:
+        assert info.lane_width_test == sum(1 << h for h in range(4, 8))
+    if width_test == 2:
+        assert info.lane_width_test == 0
+    # the leaves' level-6 sums are 128-bit, their own records are not
+    assert sum(info.wide_input_rows[7][r] for r in (0, 1)) > 0
     assert gt.occ(0, -1) > 2 ** 64
 
 
@@ -148,6 +160,10 @@ def test_invalid_inputs():
     with pytest.raises(S.SccError) as e:
         S.Table(dg, gg.colors(20, 4, seed=2), 4, gather_mode=3)
     assert e.value.status == S.EINVAL
+    for w in (-1, 3):
+        with pytest.raises(S.SccError) as e:
+            S.Table(dg, gg.colors(20, 4, seed=2), 4, width_test=w)
+        assert e.value.status == S.EINVAL
     bad_colors = gg.colors(20, 4, seed=2)
     bad_colors[3] = 4
     with pytest.raises(S.SccError) as e:
@@ -257,7 +273,10 @@ def test_k8_counts_beyond_64_bits():
     # hubs last, so their neighbour-sum bounds reach 2^64 only in their third
     # 64-neighbour chunk (the 64-bit gather pass stops there and the row is
     # redone in 128 bits). Every level, t, t_j and 2000 samples, with grouped
-    # rows and with one row per wave.
+    # rows and with one row per wave; with the width test before the combine
+    # (automatic: level 7, where the leaves' level-6 sums are 128-bit; forced at
+    # every level) and inside it, which covers both 128-bit-input routes of
+    # vertices with high words in their top-level sums only.
     S = scc()
     g = gg.two_hubs()
     k = 8
@@ -267,16 +286,23 @@ def test_k8_counts_beyond_64_bits():
     ov, op = ot.sample(2000, seed=3)
     print("two hubs: oracle samples drawn", flush=True)
     dg = S.DeviceGraph.from_graph(g)
-    for mode in (S.GATHER_GROUPED, S.GATHER_ROW):
-        gt = S.Table(dg, colors, k, gather_mode=mode)
+    for mode, width in GATHER_WIDTH:
+        gt = S.Table(dg, colors, k, gather_mode=mode, width_test=width)
         info = gt.info()
+        print(f"two hubs: modes {mode}, {width} 128-bit-input routes per level "
+              f"{[list(info.wide_input_rows[h]) for h in range(k + 1)]}, per-lane width test "
+              f"{info.lane_width_test:#x}", flush=True)
+        if width == 2:
+            assert info.lane_width_test == 0 and info.wide_input_rows[7][0] > 0, mode
+        else:
+            assert info.lane_width_test >> 7 & 1 and info.wide_input_rows[7][1] > 0, (mode, width)
         for h in (6, 7, 8):
             assert info.wide_vertices[h] > 0, (mode, h, list(info.wide_vertices))
         assert gt.totals()[0] >= 1 << 64
-        assert_tables_equal(gt, ot, k, f"two hubs mode {mode}")
+        assert_tables_equal(gt, ot, k, f"two hubs modes {mode}, {width}")
         gv, gp = gt.sample(2000, seed=3)
-        assert np.array_equal(gv.cpu().numpy(), ov) and np.array_equal(gp.cpu().numpy(), op), mode
-        print(f"two hubs: mode {mode} equal", flush=True)
+        assert np.array_equal(gv.cpu().numpy(), ov) and np.array_equal(gp.cpu().numpy(), op), (mode, width)
+        print(f"two hubs: modes {mode}, {width} equal", flush=True)
 
 
 @pytest.mark.parametrize("k,n,m", [(5, 3000, 12000), (8, 600, 1500)])
