@@ -1588,32 +1588,42 @@ __global__ void __launch_bounds__(WAVE) k_pack(PackView P)
 // ---------------------------------------------------------------------------
 // Level-k totals: eta_v (all shapes) and per-block partial sums per unrooted shape
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_totals(GraphView g, const DevLut *Lp, LevelView Lk, int zero_only, u128 *eta, u128 *part)
+constexpr int TOT_WAVES = 4;   // waves per block of k_totals
+// one wave per vertex, strided over the grid: the lanes take the record's
+// entries (one pass), eta_v is their wave sum, and each entry's count goes to
+// its unrooted shape's 128-bit sum in the wave's LDS (64-bit atomics, the
+// carry into the high word)
+__global__ void __launch_bounds__(TOT_WAVES * WAVE) k_totals(GraphView g, const DevLut *Lp, LevelView Lk, int zero_only,
+                                                             u128 *eta, u128 *part)
 {
-    __shared__ u128 wpart[256 / WAVE][32];
+    __shared__ unsigned long long acc[TOT_WAVES][32][2];
     const DevLut &L = *Lp;
-    const int tid = threadIdx.x;
+    const int w = threadIdx.x / WAVE, lane = lane_id();
     const int nu = L.num_unr;
-    const int64_t v = (int64_t)blockIdx.x * blockDim.x + tid;
-    Rec r{nullptr, 0, 0, false};
-    if (v < g.n && (!zero_only || g.colors[v] == 0)) r = rec_of(Lk, v);
-    u128 e = 0;
-    for (int j = 0; j < nu; j++) {
-        u128 sj = 0;
-        for (uint32_t q = 0; q < r.len; q++) {
-            const int t = (int)(r.key(q) - L.off[L.k]) / L.bk[L.k];
-            if (L.unr_of[t] == j) sj += r.cnt(q);
-        }
-        e += sj;
-        sj = wave_sum128(sj);
-        if (lane_id() == 0) wpart[tid / WAVE][j] = sj;
-    }
-    if (v < g.n) eta[v] = e;
+    if (lane < 32) acc[w][lane][0] = acc[w][lane][1] = 0;
     __syncthreads();
-    if (tid < nu) {
+    const int64_t stride = (int64_t)gridDim.x * TOT_WAVES;
+    for (int64_t v = (int64_t)blockIdx.x * TOT_WAVES + w; v < g.n; v += stride) {
+        Rec r{nullptr, 0, 0, false, false};
+        if (!zero_only || g.colors[v] == 0) r = rec_of(Lk, v);
+        u128 e = 0;
+        for (uint32_t q = lane; q < r.len; q += WAVE) {
+            const int t = (int)(r.key(q) - L.off[L.k]) / L.bk[L.k];
+            const int j = L.unr_of[t];
+            const u128 c = r.cnt(q);
+            e += c;
+            const unsigned long long lo = lo64(c), old = atomicAdd(&acc[w][j][0], lo);
+            const unsigned long long hi = hi64(c) + (old + lo < old ? 1ull : 0ull);
+            if (hi) atomicAdd(&acc[w][j][1], hi);
+        }
+        e = wave_sum128(e);
+        if (lane == 0) eta[v] = e;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < nu) {
         u128 s = 0;
-        for (int w = 0; w < (int)(blockDim.x / WAVE); w++) s += wpart[w][tid];
-        part[(size_t)blockIdx.x * 32 + tid] = s;
+        for (int q = 0; q < TOT_WAVES; q++) s += mk128(acc[q][threadIdx.x][0], acc[q][threadIdx.x][1]);
+        part[(size_t)blockIdx.x * 32 + threadIdx.x] = s;
     }
 }
 
@@ -2536,11 +2546,13 @@ static scc_status totals_launch(scc_table *T)
     const bool zero = T->rooting == SCC_ROOT_ZERO;
     T->eta = (u128 *)T->alloc((size_t)n * 16 + 16);
     T->pre = (u128 *)T->alloc((size_t)n * 16 + 16);
-    const int64_t nb = std::max<int64_t>(1, (n + 255) / 256);
+    const int64_t nb = std::max<int64_t>(1, std::min<int64_t>((n + TOT_WAVES - 1) / TOT_WAVES, 8192));
     u128 *part = (u128 *)T->mem.get((size_t)nb * 32 * 16);
     if (!T->eta || !T->pre || !part) { T->mem.put(part); return set_error(SCC_ENOMEM, "totals"); }
     u128 *tjd = (u128 *)(T->dsum + DSUM_TJ);
-    if (n) hipLaunchKernelGGL(k_totals, dim3((unsigned)nb), dim3(256), 0, st, g, T->dlut, view(T->lev[k]), zero ? 1 : 0, T->eta, part);
+    if (n)
+        hipLaunchKernelGGL(k_totals, dim3((unsigned)nb), dim3(TOT_WAVES * WAVE), 0, st, g, T->dlut, view(T->lev[k]),
+                           zero ? 1 : 0, T->eta, part);
     hipLaunchKernelGGL(k_reduce_parts, dim3((unsigned)T->hlut.num_unr), dim3(256), 0, st, part, (int)(n ? nb : 0),
                        T->hlut.num_unr, tjd);
     T->mem.put(part);   // stream-ordered
