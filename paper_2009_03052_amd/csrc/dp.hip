@@ -930,6 +930,8 @@ struct CombineArgs {
     uint32_t *meta;
     u128 *Nout;
     int *err;                             // [0]: overflow
+    uint64_t *bm;                         // the level's presence bitmaps (BW words a vertex), or null
+    int BW;
 };
 
 template <int ILP>
@@ -1129,6 +1131,9 @@ __device__ inline void combine_outputs(const CombineArgs &A, int64_t v, int cv, 
         }
         const bool nz = val != 0;
         const uint64_t bal = __ballot(nz);
+        // output o is dense position o of the vertex's colour, so this round's
+        // ballot is word o0 / 64 of its presence bitmap
+        if (A.bm && lane == 0) A.bm[(size_t)v * A.BW + (o0 >> 6)] = bal;
         if (nz) {
             const uint32_t pos = cnt + (uint32_t)__popcll(bal & lanemask_lt());
             sk[pos] = okey[o];
@@ -1514,9 +1519,9 @@ __global__ void k_words(int64_t n, const uint32_t *meta, uint64_t *words)
 }
 
 // Packing: each vertex's slot is copied into the pool at its offset, in one
-// pass that also sets the presence bitmap (bit = position in the dense level-h
-// layout). Records are short, so 16 lanes take one vertex and a wave packs four
-// at a time. Returns the vertex's (stored entries, 128-bit flag) in lane 0 of its
+// pass that can also set the presence bitmap (bit = position in the dense level-h
+// layout) from the keys. Records are short, so 16 lanes take one vertex and a
+// wave packs four at a time. Returns the vertex's (stored entries, 128-bit flag) in lane 0 of its
 // group.
 struct PackView {
     int64_t n;
@@ -1537,6 +1542,9 @@ __device__ inline uint64_t rec_words(uint32_t m)
     return len ? (uint64_t)REC_HDR + key_words(len) + (uint64_t)len * (META_WIDE(m) ? 2u : 1u) : 0;
 }
 
+// BITS: also the presence bitmaps, from the keys (the level kernels' combine
+// writes them itself)
+template <bool BITS>
 __device__ inline void pack_four(const PackView &P, int64_t v0, unsigned long long (*bits)[8], uint64_t &nlen,
                                  uint64_t &nwide)
 {
@@ -1545,8 +1553,10 @@ __device__ inline void pack_four(const PackView &P, int64_t v0, unsigned long lo
     const bool act = v < P.n;
     const uint32_t m = act ? P.meta[v] : 0u, len = META_LEN(m);
     if (act && l == 0) { nlen += len; nwide += META_WIDE(m); }
-    if (l < P.BW) bits[g][l] = 0;
-    __syncthreads();
+    if (BITS) {
+        if (l < P.BW) bits[g][l] = 0;
+        __syncthreads();
+    }
     if (act) {
         const uint32_t kw = key_words(len);
         const uint64_t start = P.off_incl[v] - rec_words(m);
@@ -1562,8 +1572,10 @@ __device__ inline void pack_four(const PackView &P, int64_t v0, unsigned long lo
                 uint16_t key = 0;
                 if (e < len) {
                     key = P.skey[base + e];
-                    const int li = xi[key];
-                    if (li >= 0) atomicOr(&bits[g][li >> 6], 1ull << (li & 63));
+                    if (BITS) {
+                        const int li = xi[key];
+                        if (li >= 0) atomicOr(&bits[g][li >> 6], 1ull << (li & 63));
+                    }
                 }
                 keys[e] = key;
             }
@@ -1572,17 +1584,22 @@ __device__ inline void pack_four(const PackView &P, int64_t v0, unsigned long lo
                 for (uint32_t e = l; e < len; e += 16) rec[kw + len + e] = P.shi[base + e];
         }
     }
-    __syncthreads();
-    if (act && l < P.BW) P.bm[(size_t)v * P.BW + l] = bits[g][l];
-    __syncthreads();
+    if (BITS) {
+        __syncthreads();
+        if (act && l < P.BW) P.bm[(size_t)v * P.BW + l] = bits[g][l];
+        __syncthreads();
+    }
 }
 
+// BITS: the level's combine did not set the bitmaps (the dedicated level-2 and
+// level-3 kernels)
+template <bool BITS>
 __global__ void __launch_bounds__(WAVE) k_pack(PackView P)
 {
     __shared__ unsigned long long bits[4][8];   // BW <= ceil(420 / 64)
     uint64_t nlen = 0, nwide = 0;
     for (int64_t v0 = (int64_t)blockIdx.x * 4; v0 < P.n; v0 += (int64_t)gridDim.x * 4)
-        pack_four(P, v0, bits, nlen, nwide);
+        pack_four<BITS>(P, v0, bits, nlen, nwide);
 }
 
 // ---------------------------------------------------------------------------
@@ -1914,7 +1931,7 @@ __global__ void __launch_bounds__(WAVE) k_mpack(const PackJobDev *Js)
                J.key_xidx, J.colors};
     uint64_t nlen = 0, nwide = 0;
     for (int64_t v0 = (int64_t)blockIdx.x * 4; v0 < J.n; v0 += (int64_t)gridDim.x * 4)
-        pack_four(P, v0, bits, nlen, nwide);
+        pack_four<true>(P, v0, bits, nlen, nwide);
     nlen = wave_sum64(nlen);
     nwide = wave_sum64(nwide);
     if (threadIdx.x == 0 && nlen) atomicAdd(&J.stats[0], (unsigned long long)nlen);
@@ -2342,6 +2359,8 @@ static scc_status build_levels(scc_table *T)
             Lv.BW = (HL.W[h] + 63) / 64;
             Lv.bm = (uint64_t *)T->alloc((size_t)n * Lv.BW * 8 + 8);
             if (!Lv.bm) return set_error(SCC_ENOMEM, "level %d bitmaps", h);
+            // the combine writes the words of the vertices it evaluates; the rest stay 0
+            HIP_TRY(hipMemsetAsync(Lv.bm, 0, (size_t)n * Lv.BW * 8, st));
         }
         if (skipped) {
             // skipped level: every record empty (its entry count stays 0 in the summary)
@@ -2369,6 +2388,7 @@ static scc_status build_levels(scc_table *T)
         C.late_dma = 8 * top_wide_rows > n;
         C.slot_key = slot_key; C.slot_lo = slot_lo; C.slot_hi = slot_hi;
         C.meta = meta; C.Nout = Nsc; C.err = err;
+        C.bm = Lv.bm; C.BW = Lv.BW;
         const size_t lds = (size_t)(HL.xoff[h] + HL.soff[h]) * 8;
         if (n) {
             // level k under zero-rooting: only the colour-0 vertices have records
@@ -2454,8 +2474,12 @@ static scc_status build_levels(scc_table *T)
         if (n) {
             PackView P{n, HL.W[h], Lv.BW, HL.nkeys, meta, words, slot_key, slot_lo, slot_hi, Nsc, Lv.pool, Lv.loc,
                        Lv.bm, T->key_xidx, T->colors};
-            // one group of four vertices per wave: the waves' dependent loads overlap
-            hipLaunchKernelGGL(k_pack, dim3((unsigned)((n + 3) / 4)), dim3(WAVE), 0, st, P);
+            // one group of four vertices per wave: the waves' dependent loads overlap.
+            // The bitmaps come from the combine, except after the dedicated level-2
+            // and level-3 kernels, which do not write them
+            const bool bits = (h == 2 || h == 3) && !C.zero_only && !C.bal;
+            if (bits) hipLaunchKernelGGL(k_pack<true>, dim3((unsigned)((n + 3) / 4)), dim3(WAVE), 0, st, P);
+            else hipLaunchKernelGGL(k_pack<false>, dim3((unsigned)((n + 3) / 4)), dim3(WAVE), 0, st, P);
         }
         HIP_TRY(hipEventRecord(ev[h][1], st));
         if (n) hipLaunchKernelGGL(k_meta_sum, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 1024)), dim3(256), 0, st,
@@ -3252,6 +3276,8 @@ static scc_status batch_launch(std::vector<BatchInstHost> &H, int tile, int hub_
             C.late_dma = 0;   // the batched worker stages high words itself: nothing is listed
             C.slot_key = H[i].skey[h]; C.slot_lo = H[i].slo[h]; C.slot_hi = H[i].shi[h];
             C.meta = H[i].meta[h]; C.Nout = H[i].N[h];
+            C.bm = nullptr;   // k_mpack sets the bitmaps from the keys
+            C.BW = 0;
         }
     }
     const size_t ncount = (size_t)ni * 2 * (SCC_KMAX + 1);
