@@ -1036,7 +1036,7 @@ def summarise_counters(label, ns, dir_a, dir_b):
     def cls(nm):
         if (nm.startswith("k_gather") and nm != "k_gather_bytes") or nm == "k_hub_prepare":
             return "gather"
-        if nm.startswith("k_combine") or nm in ("k_pack", "k_words"):
+        if nm.startswith("k_combine") or nm.startswith("k_pack") or nm == "k_words":
             return "combine"
         return "other"
 
