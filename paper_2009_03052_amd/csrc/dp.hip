@@ -1370,6 +1370,126 @@ __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(8, 8)
     combine_vertex_pf<false, PMAX, true>(A, __builtin_amdgcn_readfirstlane(rows[blockIdx.x]), sm, nullptr, wide_list, wide_count);
 }
 
+// The combine of a level with at most 64 outputs per vertex, four vertices per
+// wave (16 lanes each): such a vertex has few terms (k = 6: 40 and 45 outputs
+// of 2 and 3 terms on average at levels 4 and 5), so one vertex per wave spends
+// its time waiting on the loads that stage it; four groups overlap them. The
+// rows (a list, else 0..nrows-1) whose bound U reaches 2^64 are listed in
+// fallback (count[5]) for k_combine_list; the others end here as in
+// combine_vertex_pf: slot, meta, N and the level's single bitmap word.
+constexpr int CGL = 16;   // lanes per vertex of the grouped combine
+__device__ inline uint64_t grp_shfl64(uint64_t x, int src) { return shfl64(x, (lane_id() & ~(CGL - 1)) + src); }
+template <int PMAX>
+__global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(8, 8))) k_combine_group(CombineArgs A, const int32_t *rows, int64_t nrows, int32_t *fallback, int *count)
+{
+    extern __shared__ uint64_t sm[];
+    const DevLut &L = *A.L;
+    const int lane = threadIdx.x, g = lane / CGL, s = lane % CGL;
+    const int h = A.h;
+    const int plo = A.bal ? 2 : 1, phi = A.bal ? h - 2 : h - 1;
+    const int XT = L.xoff[h], ST = L.soff[h], Wh = L.W[h];
+    uint64_t *Xlo = sm + (size_t)g * (XT + ST), *Slo = Xlo + XT;
+    const int64_t i = (int64_t)blockIdx.x * (WAVE / CGL) + g;
+    const bool in = i < nrows;
+    const int64_t v = in ? (rows ? (int64_t)rows[i] : i) : 0;
+    const int cv = in ? (int)A.g.colors[v] : 0;
+    const bool act = in && !(A.zero_only && cv != 0);
+    if (in && !act && s == 0) { A.meta[v] = 0; A.Nout[v] = 0; }
+    // sub-lane q: the handle of v's level-q record (q >= 2) and M_q(v)
+    const u128 *mp = nullptr;
+    const uint64_t *locp = nullptr, *poolp = nullptr;
+#pragma unroll
+    for (int q = 1; q <= PMAX; q++)
+        if (s == q && q <= phi) {
+            mp = A.M[q];
+            if (q >= 2) { locp = A.lev[q].P.loc; poolp = A.lev[q].P.pool; }
+        }
+    const uint64_t hd = act && locp ? locp[v] : 0ull;
+    const u128 Mq = act && mp ? mp[v] : (u128)0;
+    u128 Nq = 0;
+    if (LOC_LEN(hd)) { const uint64_t *rp = poolp + LOC_OFF(hd); Nq = mk128(rp[0], rp[1]); }
+    // bound: sub-lane hp contributes N_hp(v) M_{h-hp}(v) (level 1: N = 1), summed
+    // (saturating) over the group
+    const int pr = (h - s) & (CGL - 1);
+    const u128 Mpair = mk128(grp_shfl64(lo64(Mq), pr), grp_shfl64(hi64(Mq), pr));
+    u128 U = act && s >= plo && s <= phi ? sat_mul(s == 1 ? (u128)1 : Nq, Mpair) : (u128)0;
+#pragma unroll
+    for (int off = CGL / 2; off >= 1; off >>= 1)
+        U = sat_add(U, mk128(shfl64(lo64(U), lane ^ off), shfl64(hi64(U), lane ^ off)));
+    const bool ovf = U == ~(u128)0 || bitlen128(U) > A.max_bits;
+    if (act && ovf && s == 0) { atomicOr(A.err, 1); A.meta[v] = 0; A.Nout[v] = 0; }
+    const bool owide = hi64(U) != 0;
+    const bool run = act && !ovf && !owide;
+    const bool isfb = act && !ovf && owide && s == 0;
+    const uint64_t fb = __ballot(isfb);
+    int fbase = 0;
+    if (lane == 0 && fb) fbase = atomicAdd(count + 5, __popcll(fb));
+    fbase = __shfl(fbase, 0);
+    if (isfb) fallback[fbase + __popcll(fb & lanemask_lt())] = (int32_t)v;
+    // staging: own counts X (zeroed, then the records) and neighbour sums S
+    if (run) {
+        for (int j = s; j < XT; j += CGL) Xlo[j] = 0;
+        for (int hs = 1; hs <= phi; hs++) {
+            if (!A.Slo[hs]) continue;
+            const int ws = L.WS[hs];
+            const uint64_t *gl = A.Slo[hs] + (size_t)v * ws;
+            for (int j = s; j < ws; j += CGL) Slo[L.soff[hs] + j] = gl[j];
+        }
+    }
+    __syncthreads();
+    const int16_t *xidx = A.key_xidx + (size_t)cv * L.nkeys;
+    if (run && s == 0) Xlo[L.xoff[1]] = 1;
+#pragma unroll
+    for (int q = 2; q <= PMAX; q++) {
+        const uint64_t hq = grp_shfl64(hd, q);
+        if (!run || q > phi) continue;
+        const RecView<false> r = h_rec<false>(A.lev[q], hq);
+        for (uint32_t e = s; e < r.len; e += CGL) Xlo[L.xoff[q] + xidx[r.key[e]]] = r.lo[e];
+    }
+    __syncthreads();
+    // outputs o = s, s + 16, ... of the group's vertex, compacted in order
+    const uint32_t ob = L.out_off[h];
+    const uint16_t *okey = L.out_key[cv] + ob;
+    uint16_t *sk = A.slot_key + (size_t)v * A.W;
+    uint64_t *sl = A.slot_lo + (size_t)v * A.W;
+    uint32_t cnt = 0;
+    uint64_t nsum = 0, bmw = 0;
+    for (int o0 = 0; o0 < Wh; o0 += CGL) {
+        const int o = o0 + s;
+        uint64_t val = 0;
+        const uint64_t d = run && o < Wh ? L.out[ob + o] : 0ull;
+        if (run && o < Wh && !(A.bal && !(d >> 63))) {
+            const int xb = (int)(d & 0xffffu), sb = (int)((d >> 16) & 0xffffu), tb = (int)((d >> 32) & 0xffffu);
+            const int nsplit = (int)((d >> 48) & 0xffu);
+            const uint16_t *txs = L.term_xs + tb;
+            uint64_t a64 = 0;
+            for (int t = 0; t < nsplit; t++) {
+                const uint32_t xs = txs[t];
+                a64 += Xlo[xb + (xs & 0xffu)] * Slo[sb + (xs >> 8)];
+            }
+            const uint32_t beta = (uint32_t)((d >> 56) & 0x7fu);
+            val = beta == 1 ? a64 : div_exact_small64(a64, beta);
+        }
+        const bool nz = val != 0;
+        const uint32_t gm = (uint32_t)(__ballot(nz) >> (g * CGL)) & 0xffffu;
+        if (nz) {
+            const uint32_t pos = cnt + (uint32_t)__popc(gm & ((1u << s) - 1u));
+            sk[pos] = okey[o];
+            sl[pos] = val;
+            nsum += val;
+        }
+        bmw |= (uint64_t)gm << o0;
+        cnt += (uint32_t)__popc(gm);
+    }
+#pragma unroll
+    for (int off = CGL / 2; off >= 1; off >>= 1) nsum += shfl64(nsum, lane ^ off);
+    if (run && s == 0) {
+        A.meta[v] = cnt;
+        A.Nout[v] = nsum;
+        if (A.bm) A.bm[(size_t)v * A.BW] = bmw;
+    }
+}
+
 // The combine's width test alone, one vertex per lane (rows: a row list, else
 // vertices 0..nrows-1). At levels where most vertices need 128-bit inputs, a
 // wave per vertex that only learns this would hold a combine's LDS while it
@@ -2400,6 +2520,8 @@ static scc_status build_levels(scc_table *T)
             const int phi = C.bal ? h - 2 : h - 1;
             const bool classified = h >= 4 && (T->width_test == SCC_WIDTH_PER_LANE ||
                                                (T->width_test == SCC_WIDTH_AUTO && C.late_dma));
+            // at most 64 outputs per vertex: four vertices per wave
+            const bool grouped = !classified && h >= 4 && HL.W[h] <= 64 && phi <= 5;
             if (classified) {
                 T->lane_width_test |= 1 << h;
                 // most vertices will need 128-bit inputs: the width test one vertex
@@ -2416,6 +2538,24 @@ static scc_status build_levels(scc_table *T)
                 if (phi <= 3) launch_combine<3>(Cn, n, narrow, nn, lds, st, wide_list, err + 1);
                 else if (phi <= 5) launch_combine<5>(Cn, n, narrow, nn, lds, st, wide_list, err + 1);
                 else launch_combine<SCC_KMAX - 1>(Cn, n, narrow, nn, lds, st, wide_list, err + 1);
+            } else if (grouped) {
+                const int64_t nr = zl ? nzero : n;
+                const size_t lds_g = (size_t)(WAVE / CGL) * (HL.xoff[h] + HL.soff[h]) * 8;
+                if (nr) {
+                    const dim3 grid((unsigned)((nr + WAVE / CGL - 1) / (WAVE / CGL)));
+                    if (phi <= 3)
+                        hipLaunchKernelGGL(k_combine_group<3>, grid, dim3(WAVE), lds_g, st, C, zl ? zrows : nullptr, nr,
+                                           narrow, err + 1);
+                    else
+                        hipLaunchKernelGGL(k_combine_group<5>, grid, dim3(WAVE), lds_g, st, C, zl ? zrows : nullptr, nr,
+                                           narrow, err + 1);
+                }
+                // the vertices whose bound reaches 2^64, one per wave
+                int nf = 0;
+                HIP_TRY(hipMemcpyAsync(&nf, err + 6, 4, hipMemcpyDeviceToHost, st));
+                HIP_TRY(hipStreamSynchronize(st));
+                if (phi <= 3) launch_combine<3>(C, n, narrow, nf, lds, st, wide_list, err + 1);
+                else launch_combine<5>(C, n, narrow, nf, lds, st, wide_list, err + 1);
             } else if (h == 2 && !zl && !C.bal)
                 hipLaunchKernelGGL(k_combine_level2, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, C);
             else if (h == 3 && !zl && !C.bal)
