@@ -470,6 +470,55 @@ __global__ void __launch_bounds__(WAVE) k_gather_wide(GatherArgs A)
     gather_vertex<false>(A, __builtin_amdgcn_readfirstlane(A.wide_rows[blockIdx.x]), sm, GS_WIDE);
 }
 
+// Which rows of a level's gather need 128-bit sums, four rows per wave (16
+// lanes each, over the row's neighbours): the bound M_hs(v), the saturating sum
+// of the neighbours' level sums N as the 64-bit pass forms it. Rows whose bound
+// reaches 2^64 go to wide_rows, as that pass would list them; the others to
+// narrow (*ncount) for it; hub rows are left to their kernels. Used where many
+// rows are wide: the 64-bit pass would start each of them only to stop.
+constexpr int GCL = 16;   // lanes per row of k_gather_classify
+__global__ void __launch_bounds__(WAVE) k_gather_classify(GatherArgs A, int32_t *narrow, int *ncount)
+{
+    const int lane = threadIdx.x, g = lane / GCL, s = lane % GCL;
+    const int64_t v = (int64_t)blockIdx.x * (WAVE / GCL) + g;
+    const bool in = v < A.g.n;
+    const int64_t a = in ? A.g.row_ptr[v] : 0, b = in ? A.g.row_ptr[v + 1] : 0;
+    const bool act = in && b - a <= A.hub_degree;
+    u128 m = 0;
+    if (act)
+        for (int64_t e = a + s; e < b; e += GCL) {
+            const uint64_t hd = src_handle<false>(A.L, A.g.col_idx[e]);
+            if (h_len<false>(hd)) m = sat_add(m, h_N<false>(A.L, hd));
+        }
+#pragma unroll
+    for (int off = GCL / 2; off >= 1; off >>= 1)
+        m = sat_add(m, mk128(shfl64(lo64(m), lane ^ off), shfl64(hi64(m), lane ^ off)));
+    const bool wide = act && hi64(m) != 0, nar = act && !wide;
+    const uint64_t bw = __ballot(wide && s == 0), bn = __ballot(nar && s == 0);
+    int bw0 = 0, bn0 = 0;
+    if (lane == 0) {
+        if (bw) bw0 = atomicAdd(A.wide_count, __popcll(bw));
+        if (bn) bn0 = atomicAdd(ncount, __popcll(bn));
+    }
+    bw0 = __shfl(bw0, 0);
+    bn0 = __shfl(bn0, 0);
+    const uint64_t below = lanemask_lt();
+    if (wide && s == 0) A.wide_rows[bw0 + __popcll(bw & below)] = (int32_t)v;
+    if (nar && s == 0) narrow[bn0 + __popcll(bn & below)] = (int32_t)v;
+}
+
+// the degrees of the vertices whose level sum N has a high word, summed: the
+// rows of the next level's gather that will need 128-bit sums are at least
+// their neighbours
+__global__ void __launch_bounds__(256) k_heavy_degree(GraphView g, const u128 *N, unsigned long long *out)
+{
+    unsigned long long d = 0;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < g.n; v += (int64_t)gridDim.x * blockDim.x)
+        if (hi64(N[v])) d += (unsigned long long)(g.row_ptr[v + 1] - g.row_ptr[v]);
+    d = wave_sum64(d);
+    if (lane_id() == 0 && d) atomicAdd(out, d);
+}
+
 // hrow[rows[i]] = base + i
 __global__ void k_set_rows(int32_t *hrow, const int32_t *rows, const int *count, int64_t fixed, int32_t base)
 {
@@ -2238,7 +2287,9 @@ static scc_status build_levels(scc_table *T)
     // it with the flags. A high-word array released while its copy is still
     // queued is safe: the allocator hooks free in the table's stream order
     // (hipFree, without hooks, waits for the device).
-    int *err = (int *)T->mem.get(32);
+    // [0] flags; [1], [3] combine lists; [2] gather's wide rows; [4..5] pool size;
+    // [6], [7] combine lists; [8..9] heavy degree (u64); [10] gather's narrow rows
+    int *err = (int *)T->mem.get(64);
     std::vector<void *> scratch{err};
     struct Guard {
         scc_table *T; std::vector<void *> *s;
@@ -2390,11 +2441,12 @@ static scc_status build_levels(scc_table *T)
     if (!slot_key || !slot_lo || !slot_hi || !words || !meta || !Nsc || !wide_list || !narrow)
         return set_error(SCC_ENOMEM, "combine scratch (%lld bytes)", (long long)n * maxW * 18);
 
+    int64_t heavy_prev = 0;   // sum of degrees of the vertices whose previous-level N has a high word
     for (int h = 2; h <= k; h++) {
         const bool last = h == k;
         int64_t top_wide_rows = 0;   // rows of the sums gathered now whose high words exist
         HIP_TRY(hipEventRecord(ev[h][0], st));
-        HIP_TRY(hipMemsetAsync(err, 0, 32, st));   // flags and the level's counts of listed rows
+        HIP_TRY(hipMemsetAsync(err, 0, 64, st));   // flags and the level's counts of listed rows
         const int hs = h - 1;   // neighbour sums needed now
         if (hs >= 2 && s_need[hs]) {
             TableSums &Sx = T->S[hs];
@@ -2429,6 +2481,15 @@ static scc_status build_levels(scc_table *T)
                                        group_lds(HL.WS[hs], gs), st, G, gs);
             } else if (G.rows_zero) {
                 if (nzero) hipLaunchKernelGGL(k_gather_list, dim3((unsigned)nzero), dim3(WAVE), lds, st, G, zrows);
+            } else if (n && heavy_prev * 8 > n) {
+                // many rows border a vertex whose level sum needs 128 bits: sort the
+                // rows out first, then the 64-bit pass takes the others only
+                hipLaunchKernelGGL(k_gather_classify, dim3((unsigned)((n + WAVE / GCL - 1) / (WAVE / GCL))), dim3(WAVE),
+                                   0, st, G, narrow, err + 10);
+                int nn = 0;
+                HIP_TRY(hipMemcpyAsync(&nn, err + 10, 4, hipMemcpyDeviceToHost, st));
+                HIP_TRY(hipStreamSynchronize(st));
+                if (nn) hipLaunchKernelGGL(k_gather_list, dim3((unsigned)nn), dim3(WAVE), lds, st, G, narrow);
             } else if (n) {
                 hipLaunchKernelGGL(k_gather, dim3((unsigned)n), dim3(WAVE), lds, st, G);
             }
@@ -2591,11 +2652,14 @@ static scc_status build_levels(scc_table *T)
                                    (const int *)narrow, err + 7);
             }
         }
+        if (n && !last)
+            hipLaunchKernelGGL(k_heavy_degree, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 2048)), dim3(256), 0,
+                               st, g, Nsc, (unsigned long long *)(err + 8));
         // record sizes and offsets; the pool size and the error flags in one read
         if (n) hipLaunchKernelGGL(k_words, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, meta, words);
         scc_status sst = scan_incl<uint64_t>(T, words, words, n);
         if (sst) return sst;
-        struct { int f[4]; uint64_t total; int g[2]; } hr{};   // the layout of err
+        struct { int f[4]; uint64_t total; int g[2]; uint64_t heavy; } hr{};   // the layout of err
         if (n) HIP_TRY(hipMemcpyAsync(err + 4, words + (n - 1), 8, hipMemcpyDeviceToDevice, st));
         HIP_TRY(hipMemcpyAsync(&hr, err, sizeof hr, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
@@ -2605,6 +2669,7 @@ static scc_status build_levels(scc_table *T)
         if (herr[0] & 2) return set_error(SCC_EOVERFLOW, "a level-%d neighbour sum may exceed 128 bits", h);
         if (herr[0] & 4)
             return set_error(SCC_EDEVICE, "level %d: a vertex listed for the top-level 128-bit combine has more high words", h);
+        heavy_prev = (int64_t)hr.heavy;
         T->wide_input_rows[h][0] = herr[1];
         T->wide_input_rows[h][1] = hr.g[1];
         T->wide_input_rows[h][2] = herr[3];
