@@ -470,41 +470,36 @@ __global__ void __launch_bounds__(WAVE) k_gather_wide(GatherArgs A)
     gather_vertex<false>(A, __builtin_amdgcn_readfirstlane(A.wide_rows[blockIdx.x]), sm, GS_WIDE);
 }
 
-// Which rows of a level's gather need 128-bit sums, four rows per wave (16
-// lanes each, over the row's neighbours): the bound M_hs(v), the saturating sum
-// of the neighbours' level sums N as the 64-bit pass forms it. Rows whose bound
-// reaches 2^64 go to wide_rows, as that pass would list them; the others to
-// narrow (*ncount) for it; hub rows are left to their kernels. Used where many
-// rows are wide: the 64-bit pass would start each of them only to stop.
-constexpr int GCL = 16;   // lanes per row of k_gather_classify
-__global__ void __launch_bounds__(WAVE) k_gather_classify(GatherArgs A, int32_t *narrow, int *ncount)
+// Which rows of a level's gather need 128-bit sums, one row per lane: the
+// bound M_hs(v), the saturating sum of the neighbours' level sums N (read from
+// the combine's per-vertex array N, equal to the records' headers) as the
+// 64-bit pass forms it. Rows whose bound reaches 2^64 go to wide_rows, as that
+// pass would list them; the others to narrow (*ncount) for it; hub rows are
+// left to their kernels. Used where many rows are wide: the 64-bit pass would
+// start each of them only to stop. (A lane per row measured faster than 2, 4,
+// 8, 16 or 64 lanes per row: 101, 102, 105, 110, 117 and 145 ms for the large
+// workload's level-6 sums.)
+__global__ void __launch_bounds__(256) k_gather_classify(GatherArgs A, const u128 *N, int32_t *narrow, int *ncount)
 {
-    const int lane = threadIdx.x, g = lane / GCL, s = lane % GCL;
-    const int64_t v = (int64_t)blockIdx.x * (WAVE / GCL) + g;
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool in = v < A.g.n;
     const int64_t a = in ? A.g.row_ptr[v] : 0, b = in ? A.g.row_ptr[v + 1] : 0;
     const bool act = in && b - a <= A.hub_degree;
     u128 m = 0;
     if (act)
-        for (int64_t e = a + s; e < b; e += GCL) {
-            const uint64_t hd = src_handle<false>(A.L, A.g.col_idx[e]);
-            if (h_len<false>(hd)) m = sat_add(m, h_N<false>(A.L, hd));
-        }
-#pragma unroll
-    for (int off = GCL / 2; off >= 1; off >>= 1)
-        m = sat_add(m, mk128(shfl64(lo64(m), lane ^ off), shfl64(hi64(m), lane ^ off)));
+        for (int64_t e = a; e < b; e++) m = sat_add(m, N[A.g.col_idx[e]]);
     const bool wide = act && hi64(m) != 0, nar = act && !wide;
-    const uint64_t bw = __ballot(wide && s == 0), bn = __ballot(nar && s == 0);
+    const uint64_t bw = __ballot(wide), bn = __ballot(nar);
     int bw0 = 0, bn0 = 0;
-    if (lane == 0) {
+    if (lane_id() == 0) {
         if (bw) bw0 = atomicAdd(A.wide_count, __popcll(bw));
         if (bn) bn0 = atomicAdd(ncount, __popcll(bn));
     }
     bw0 = __shfl(bw0, 0);
     bn0 = __shfl(bn0, 0);
     const uint64_t below = lanemask_lt();
-    if (wide && s == 0) A.wide_rows[bw0 + __popcll(bw & below)] = (int32_t)v;
-    if (nar && s == 0) narrow[bn0 + __popcll(bn & below)] = (int32_t)v;
+    if (wide) A.wide_rows[bw0 + __popcll(bw & below)] = (int32_t)v;
+    if (nar) narrow[bn0 + __popcll(bn & below)] = (int32_t)v;
 }
 
 // the degrees of the vertices whose level sum N has a high word, summed: the
@@ -2483,9 +2478,9 @@ static scc_status build_levels(scc_table *T)
                 if (nzero) hipLaunchKernelGGL(k_gather_list, dim3((unsigned)nzero), dim3(WAVE), lds, st, G, zrows);
             } else if (n && heavy_prev * 8 > n) {
                 // many rows border a vertex whose level sum needs 128 bits: sort the
-                // rows out first, then the 64-bit pass takes the others only
-                hipLaunchKernelGGL(k_gather_classify, dim3((unsigned)((n + WAVE / GCL - 1) / (WAVE / GCL))), dim3(WAVE),
-                                   0, st, G, narrow, err + 10);
+                // rows out first (one per lane), then the 64-bit pass takes the others only
+                hipLaunchKernelGGL(k_gather_classify, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, G, Nsc,
+                                   narrow, err + 10);
                 int nn = 0;
                 HIP_TRY(hipMemcpyAsync(&nn, err + 10, 4, hipMemcpyDeviceToHost, st));
                 HIP_TRY(hipStreamSynchronize(st));
