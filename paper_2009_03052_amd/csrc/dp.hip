@@ -1732,16 +1732,28 @@ __device__ inline void pack_four(const PackView &P, int64_t v0, unsigned long lo
             uint16_t *keys = (uint16_t *)rec;
             const int16_t *xi = P.key_xidx + (size_t)P.colors[v] * P.nkeys;
             const size_t base = (size_t)v * P.W;
-            for (uint32_t e = l; e < kw * 4; e += 16) {
-                uint16_t key = 0;
-                if (e < len) {
-                    key = P.skey[base + e];
-                    if (BITS) {
-                        const int li = xi[key];
-                        if (li >= 0) atomicOr(&bits[g][li >> 6], 1ull << (li & 63));
-                    }
+            if (!BITS && (base & 3) == 0) {
+                // four keys a word; past the record's end the word keeps zeros (the
+                // slot words read there lie inside the slot array and its margin)
+                const uint64_t *src = (const uint64_t *)(P.skey + base);
+                for (uint32_t q = l; q < kw; q += 16) {
+                    uint64_t x = src[q];
+                    const uint32_t rem = len - 4 * q;   // >= 1
+                    if (rem < 4) x &= (1ull << (16 * rem)) - 1ull;
+                    rec[q] = x;
                 }
-                keys[e] = key;
+            } else {
+                for (uint32_t e = l; e < kw * 4; e += 16) {
+                    uint16_t key = 0;
+                    if (e < len) {
+                        key = P.skey[base + e];
+                        if (BITS) {
+                            const int li = xi[key];
+                            if (li >= 0) atomicOr(&bits[g][li >> 6], 1ull << (li & 63));
+                        }
+                    }
+                    keys[e] = key;
+                }
             }
             for (uint32_t e = l; e < len; e += 16) rec[kw + e] = P.slo[base + e];
             if (META_WIDE(m))
