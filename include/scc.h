@@ -190,6 +190,11 @@ typedef struct {
     int lane_width_test;       /* bit h: level h's width test (64- or 128-bit inputs) ran one
                                   vertex per lane before the combine, as at levels where most
                                   vertices have high words in their top-level neighbour sums */
+    int sorted_sum_rows;       /* bit h: the rows of the level-h neighbour sums were sorted into
+                                  64- and 128-bit ones (one per lane) before the gather, as where
+                                  many rows border a vertex whose level-h sum needs 128 bits */
+    int grouped_combine;       /* bit h: level h was combined four vertices per wave (at most
+                                  64 outputs per vertex) */
 } scc_table_info;
 
 /* Table summary (host struct; no device work). */

@@ -83,7 +83,8 @@ class TableInfo(C.Structure):
                 ("t", C.c_uint64 * 2), ("tj", (C.c_uint64 * 2) * 32), ("level_ms", C.c_double * 9),
                 ("gather_ms", C.c_double * 9), ("num_hubs", C.c_int), ("stars", C.c_uint64 * 2),
                 ("record_bytes", C.c_int64), ("vlc", C.c_int), ("combine_ms", C.c_double * 9),
-                ("totals_ms", C.c_double), ("wide_input_rows", (C.c_int64 * 3) * 9), ("lane_width_test", C.c_int)]
+                ("totals_ms", C.c_double), ("wide_input_rows", (C.c_int64 * 3) * 9), ("lane_width_test", C.c_int),
+                ("sorted_sum_rows", C.c_int), ("grouped_combine", C.c_int)]
 
 
 class _Build16Opts(C.Structure):

@@ -2491,6 +2491,7 @@ static scc_status build_levels(scc_table *T)
             } else if (n && heavy_prev * 8 > n) {
                 // many rows border a vertex whose level sum needs 128 bits: sort the
                 // rows out first (one per lane), then the 64-bit pass takes the others only
+                T->sorted_sum_rows |= 1 << hs;
                 hipLaunchKernelGGL(k_gather_classify, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, G, Nsc,
                                    narrow, err + 10);
                 int nn = 0;
@@ -2607,6 +2608,7 @@ static scc_status build_levels(scc_table *T)
                 else if (phi <= 5) launch_combine<5>(Cn, n, narrow, nn, lds, st, wide_list, err + 1);
                 else launch_combine<SCC_KMAX - 1>(Cn, n, narrow, nn, lds, st, wide_list, err + 1);
             } else if (grouped) {
+                T->grouped_combine |= 1 << h;
                 const int64_t nr = zl ? nzero : n;
                 const size_t lds_g = (size_t)(WAVE / CGL) * (HL.xoff[h] + HL.soff[h]) * 8;
                 if (nr) {
@@ -3090,6 +3092,8 @@ extern "C" scc_status scc_table_info_get(const scc_table *t, scc_table_info *out
         for (int r = 0; r < 3; r++) out->wide_input_rows[h][r] = t->wide_input_rows[h][r];
     }
     out->lane_width_test = t->lane_width_test;
+    out->sorted_sum_rows = t->sorted_sum_rows;
+    out->grouped_combine = t->grouped_combine;
     out->num_hubs = t->nhub;
     out->bytes = t->bytes;
     out->t[0] = lo64(t->t); out->t[1] = hi64(t->t);

@@ -68,6 +68,8 @@ struct scc_table {
     double combine_bytes[SCC_KMAX + 1] = {0};
     int64_t wide_input_rows[SCC_KMAX + 1][3] = {};   // 128-bit-input combines of level h, by route
     int lane_width_test = 0;                   // bit h: level h's width test ran one vertex per lane
+    int sorted_sum_rows = 0;                   // bit h: the level-h sums' rows were sorted before the gather
+    int grouped_combine = 0;                   // bit h: level h combined four vertices per wave
     double totals_ms = 0, totals_bytes = 0;
     int64_t bytes = 0;
     int hub_degree = 1024;           // rows above this degree are gathered in chunks

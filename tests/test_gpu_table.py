@@ -83,7 +83,15 @@ def test_counts_beyond_64_bits(gather_mode, width_test):
     assert_tables_equal(gt, ot, 6, "wide star")
     t, _ = gt.totals()
     assert t > 2 ** 64
-    assert gt.info().wide_vertices[6] >= 1
+    info = gt.info()
+    assert info.wide_vertices[6] >= 1
+    # levels 4-6 have at most 64 outputs per vertex: four vertices per wave, the
+    # hub (128-bit level-6 counts) passed on to the per-vertex combine (level 6
+    # takes the width test per lane instead unless the test is forced per wave)
+    if width_test != 1:
+        assert info.grouped_combine >> 4 & 1 and info.grouped_combine >> 5 & 1, info.grouped_combine
+    if width_test == 2:
+        assert info.grouped_combine >> 6 & 1, info.grouped_combine
     # with 64-bit counts only, the build refuses instead of wrapping
     S = scc()
     with pytest.raises(S.SccError) as e:
@@ -103,6 +111,9 @@ def test_low_degree_rows_with_128_bit_sums(gather_mode, width_test):
     gt, ot = build_pair(g, colors, 7, rooting=O.ROOT_ALL, gather_mode=gather_mode, width_test=width_test)
     assert_tables_equal(gt, ot, 7, "hub k7")
     info = gt.info()
+    if gather_mode == 2:
+        # the hub's level-6 sum needs 128 bits: the rows are sorted before the gather
+        assert info.sorted_sum_rows >> 6 & 1, info.sorted_sum_rows
     if width_test == 1:
         assert info.lane_width_test == sum(1 << h for h in range(4, 8))
     if width_test == 2:
@@ -260,6 +271,7 @@ def test_mid_workload_full_table():
     print("mid: graph ready", flush=True)
     gt, ot = build_pair(g, colors, 6, validate=False)
     print("mid: both tables built", flush=True)
+    assert all(gt.info().grouped_combine >> h & 1 for h in (4, 5, 6))
     assert_tables_equal(gt, ot, 6, "mid")
     from gpu_util import assert_samples_equal
     assert_samples_equal(gt, ot, 300, seed=22, label="mid samples")
@@ -291,7 +303,9 @@ def test_k8_counts_beyond_64_bits():
         info = gt.info()
         print(f"two hubs: modes {mode}, {width} 128-bit-input routes per level "
               f"{[list(info.wide_input_rows[h]) for h in range(k + 1)]}, per-lane width test "
-              f"{info.lane_width_test:#x}", flush=True)
+              f"{info.lane_width_test:#x}, sorted sum rows {info.sorted_sum_rows:#x}", flush=True)
+        if mode == S.GATHER_ROW:
+            assert info.sorted_sum_rows >> 6 & 1, info.sorted_sum_rows
         if width == 2:
             assert info.lane_width_test == 0 and info.wide_input_rows[7][0] > 0, mode
         else:
