@@ -637,31 +637,34 @@ __global__ __launch_bounds__(BLOCK) void k16_hist(const uint64_t *keys, int64_t 
     for (int q = threadIdx.x; q < RADIX; q += BLOCK) hist[(int64_t)q * nblocks + blockIdx.x] = c[q];
 }
 
-// Stable scatter: the tile's elements are ranked in the order (item, wave,
-// lane), which is their index order; off[d * nblocks + b] is where digit d of
-// block b starts. Lanes of a wave with equal digits find each other by one
-// ballot per digit bit; the lowest such lane (the leader) publishes their
-// number, and after the item it adds it to the digit's running count and
-// clears its entry again.
+// Stable scatter. Each wave owns a contiguous quarter of the tile (its items
+// in index order), so an element's rank among the tile's elements of its digit
+// is: the elements of that digit in earlier waves' quarters, plus those in the
+// wave's earlier items (a per-wave count in LDS, kept by the wave alone), plus
+// the earlier lanes of its item with that digit (one ballot per digit bit).
+// off[d * nblocks + b] is where digit d of block b starts. Two block barriers
+// per tile: after the counts, and after their running sum over the waves.
 __global__ __launch_bounds__(BLOCK) void k16_scatter(const uint64_t *kin, const uint32_t *pin, uint64_t *kout,
                                                      uint32_t *pout, int64_t N, int shift, const uint64_t *off,
                                                      int64_t nblocks)
 {
-    __shared__ uint32_t seen[RADIX];        // elements of each digit ranked so far in this tile
-    __shared__ uint32_t wcnt[WPB][RADIX];   // this item's elements of each digit, per wave
-    const int w = threadIdx.x / WAVE;
-    for (int q = threadIdx.x; q < RADIX; q += BLOCK) {
-        seen[q] = 0;
-        for (int x = 0; x < WPB; x++) wcnt[x][q] = 0;
-    }
+    __shared__ uint32_t wc[WPB][RADIX];   // per wave: elements of each digit so far, then the waves before
+    const int w = threadIdx.x / WAVE, lane = lane_id();
+    for (int q = threadIdx.x; q < WPB * RADIX; q += BLOCK) wc[q / RADIX][q % RADIX] = 0;
     __syncthreads();
-    const int64_t t0 = (int64_t)blockIdx.x * SORT_TILE;
+    const int64_t base = (int64_t)blockIdx.x * SORT_TILE + (int64_t)w * (SORT_ITEMS * WAVE);
+    uint64_t key[SORT_ITEMS];
+    uint32_t p[SORT_ITEMS], rank[SORT_ITEMS];
+#pragma unroll
     for (int it = 0; it < SORT_ITEMS; it++) {
-        const int64_t i = t0 + it * BLOCK + threadIdx.x;
-        const bool valid = i < N;
-        const uint64_t key = valid ? kin[i] : 0;
-        const uint32_t p = valid ? (pin ? pin[i] : (uint32_t)i) : 0;
-        const uint32_t d = (uint32_t)(key >> shift) & (RADIX - 1);
+        const int64_t i = base + it * WAVE + lane;
+        key[it] = i < N ? kin[i] : 0;
+        p[it] = i < N ? (pin ? pin[i] : (uint32_t)i) : 0;
+    }
+#pragma unroll
+    for (int it = 0; it < SORT_ITEMS; it++) {
+        const bool valid = base + it * WAVE + lane < N;
+        const uint32_t d = (uint32_t)(key[it] >> shift) & (RADIX - 1);
         uint64_t peers = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < RADIX_BITS; b++) {
@@ -669,22 +672,27 @@ __global__ __launch_bounds__(BLOCK) void k16_scatter(const uint64_t *kin, const 
             peers &= ((d >> b) & 1u) ? ones : ~ones;
         }
         const uint64_t below = peers & lanemask_lt();
-        const bool leader = valid && below == 0;
-        const uint32_t cnt = (uint32_t)__popcll(peers);
-        if (leader) wcnt[w][d] = cnt;
-        __syncthreads();
-        if (valid) {
-            uint64_t pos = off[(int64_t)d * nblocks + blockIdx.x] + seen[d] + (uint64_t)__popcll(below);
-            for (int q = 0; q < w; q++) pos += wcnt[q][d];
-            kout[pos] = key;
-            pout[pos] = p;
+        const uint32_t cur = valid ? wc[w][d] : 0u;
+        rank[it] = cur + (uint32_t)__popcll(below);
+        if (valid && below == 0) wc[w][d] = cur + (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < RADIX; q += BLOCK) {
+        uint32_t run = 0;
+        for (int x = 0; x < WPB; x++) {
+            const uint32_t c = wc[x][q];
+            wc[x][q] = run;
+            run += c;
         }
-        __syncthreads();
-        if (leader) {
-            atomicAdd(&seen[d], cnt);
-            wcnt[w][d] = 0;
-        }
-        __syncthreads();
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < SORT_ITEMS; it++) {
+        if (base + it * WAVE + lane >= N) continue;
+        const uint32_t d = (uint32_t)(key[it] >> shift) & (RADIX - 1);
+        const uint64_t pos = off[(int64_t)d * nblocks + blockIdx.x] + wc[w][d] + rank[it];
+        kout[pos] = key[it];
+        pout[pos] = p[it];
     }
 }
 
