@@ -1072,7 +1072,7 @@ __device__ inline u128 mul_64x128(uint64_t x, u128 s) { return (u128)x * lo64(s)
 // s_hi0: Shi holds the high words of the neighbour sums from staging index
 // s_hi0 on (the sums below have none); with own counts in 64 bits, an output
 // whose T'' block lies below s_hi0 takes 64 x 64-bit products. tx_lds: the
-// level's term descriptors copied to LDS (level_terms), else read from L.
+// level's term descriptors copied to LDS (level_term_words), else read from L.
 template <int ILP>
 __device__ inline void combine_outputs(const CombineArgs &A, int64_t v, int cv, const uint64_t *Xlo,
                                        const uint64_t *Slo, const uint64_t *Xhi, const uint64_t *Shi, bool owide,
@@ -2444,7 +2444,10 @@ static scc_status build_levels(scc_table *T)
     uint32_t *meta = (uint32_t *)get((size_t)n * 4 + 256);
     u128 *Nsc = (u128 *)get((size_t)n * 16 + 256);
     int *wide_list = (int *)get((size_t)n * 4 + 256);
-    int32_t *narrow = (int32_t *)get((size_t)n * 4 + 256);   // the classified levels' 64-bit vertices
+    // row lists of one level: the gather's 64-bit rows where its rows are sorted,
+    // then the combine's 64-bit vertices (width test per lane) or the grouped
+    // combine's vertices whose bound reaches 2^64
+    int32_t *narrow = (int32_t *)get((size_t)n * 4 + 256);
     if (!slot_key || !slot_lo || !slot_hi || !words || !meta || !Nsc || !wide_list || !narrow)
         return set_error(SCC_ENOMEM, "combine scratch (%lld bytes)", (long long)n * maxW * 18);
 
