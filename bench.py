@@ -957,6 +957,7 @@ def companion_serving(a):
 # Summaries of rocprofv3 output (what profiles/ holds):
 #   python bench.py summarise trace <run_kernel_trace.csv>
 #   python bench.py summarise counters <label> <samples per k_sample> <dir of the read pass> <dir of the write pass>
+#   python bench.py summarise sq <dir of SQ pass 1> <dir of SQ pass 2>
 # ---------------------------------------------------------------------------
 def _short_kernel(name):
     name = name.replace("(anonymous namespace)::", "").replace("void ", "")
@@ -1112,6 +1113,32 @@ def summarise_counters16(label, dir_a, dir_b):
     print(f"source_sha256 {h.hexdigest()}  (dp16.hip at the time of the counter runs)")
 
 
+def summarise_sq(dir_1, dir_2):
+    """Per kernel of the first build and its first sampler launch: the shader
+    sequencer's wave counters summed over dispatches, per wave. SQ_WAVE_CYCLES and
+    SQ_WAIT_ANY count in the counters' own cycle unit; their ratio is the share of a
+    wave's lifetime spent waiting (on memory, LDS or a barrier)."""
+    import collections
+    agg = collections.defaultdict(collections.Counter)
+    for d in (dir_1, dir_2):
+        ds = _counter_dispatches(d)
+        names = [e["name"] for e in ds]
+        a, b = _first_build(names)
+        for e in ds[a:b + 1]:
+            agg[e["name"]].update(e["c"])
+    print("| kernel | waves | cycles / wave | waiting | VALU instr / wave | SALU | LDS instr | VMEM reads | "
+          "LDS bank-conflict cycles / wave |")
+    print("|---|---|---|---|---|---|---|---|---|")
+    for nm, c in sorted(agg.items(), key=lambda x: -x[1]["SQ_WAVE_CYCLES"]):
+        w = c["SQ_WAVES"] or 1.0
+        if c["SQ_WAVE_CYCLES"] < 1e9:
+            continue
+        wait = c["SQ_WAIT_ANY"] / c["SQ_WAVE_CYCLES"] if c["SQ_WAVE_CYCLES"] else 0.0
+        print(f"| {nm} | {c['SQ_WAVES']:.3g} | {c['SQ_WAVE_CYCLES'] / w:.0f} | {100 * wait:.0f} % | "
+              f"{c['SQ_INSTS_VALU'] / w:.0f} | {c['SQ_INSTS_SALU'] / w:.0f} | {c['SQ_INSTS_LDS'] / w:.0f} | "
+              f"{c['SQ_INSTS_VMEM_RD'] / w:.0f} | {c['SQ_LDS_BANK_CONFLICT'] / w:.0f} |")
+
+
 def profile_fields16(name):
     """Fields of profiles/<name> when taken for the current dp16.hip, else None."""
     import hashlib
@@ -1134,5 +1161,7 @@ if __name__ == "__main__":
         summarise_trace(sys.argv[3])
     elif len(sys.argv) > 2 and sys.argv[1] == "summarise" and sys.argv[2] == "counters":
         summarise_counters(sys.argv[3], int(sys.argv[4]), sys.argv[5], sys.argv[6])
+    elif len(sys.argv) > 2 and sys.argv[1] == "summarise" and sys.argv[2] == "sq":
+        summarise_sq(sys.argv[3], sys.argv[4])
     else:
         main()
