@@ -1706,6 +1706,7 @@ __device__ inline uint64_t rec_words(uint32_t m)
     return len ? (uint64_t)REC_HDR + key_words(len) + (uint64_t)len * (META_WIDE(m) ? 2u : 1u) : 0;
 }
 
+constexpr int PACK_ILP = 4;   // copies in flight per lane in pack_four
 // BITS: also the presence bitmaps, from the keys (the level kernels' combine
 // writes them itself)
 template <bool BITS>
@@ -1736,11 +1737,20 @@ __device__ inline void pack_four(const PackView &P, int64_t v0, unsigned long lo
                 // four keys a word; past the record's end the word keeps zeros (the
                 // slot words read there lie inside the slot array and its margin)
                 const uint64_t *src = (const uint64_t *)(P.skey + base);
-                for (uint32_t q = l; q < kw; q += 16) {
-                    uint64_t x = src[q];
-                    const uint32_t rem = len - 4 * q;   // >= 1
-                    if (rem < 4) x &= (1ull << (16 * rem)) - 1ull;
-                    rec[q] = x;
+                for (uint32_t q0 = l; q0 < kw; q0 += 16 * PACK_ILP) {
+                    uint64_t x[PACK_ILP];
+#pragma unroll
+                    for (int j = 0; j < PACK_ILP; j++) {
+                        const uint32_t q = q0 + 16 * j;
+                        x[j] = q < kw ? src[q] : 0ull;
+                    }
+#pragma unroll
+                    for (int j = 0; j < PACK_ILP; j++) {
+                        const uint32_t q = q0 + 16 * j;
+                        if (q >= kw) continue;
+                        const uint32_t rem = len - 4 * q;   // >= 1
+                        rec[q] = rem < 4 ? x[j] & ((1ull << (16 * rem)) - 1ull) : x[j];
+                    }
                 }
             } else {
                 for (uint32_t e = l; e < kw * 4; e += 16) {
@@ -1755,9 +1765,25 @@ __device__ inline void pack_four(const PackView &P, int64_t v0, unsigned long lo
                     keys[e] = key;
                 }
             }
-            for (uint32_t e = l; e < len; e += 16) rec[kw + e] = P.slo[base + e];
-            if (META_WIDE(m))
-                for (uint32_t e = l; e < len; e += 16) rec[kw + len + e] = P.shi[base + e];
+            // PACK_ILP loads of a lane in flight before its stores (the compiler
+            // cannot move a load above a store to the pool by itself)
+            for (int part = 0; part < (META_WIDE(m) ? 2 : 1); part++) {
+                const uint64_t *src = (part ? P.shi : P.slo) + base;
+                uint64_t *dst = rec + kw + (part ? len : 0u);
+                for (uint32_t e0 = l; e0 < len; e0 += 16 * PACK_ILP) {
+                    uint64_t x[PACK_ILP];
+#pragma unroll
+                    for (int j = 0; j < PACK_ILP; j++) {
+                        const uint32_t e = e0 + 16 * j;
+                        x[j] = e < len ? src[e] : 0ull;
+                    }
+#pragma unroll
+                    for (int j = 0; j < PACK_ILP; j++) {
+                        const uint32_t e = e0 + 16 * j;
+                        if (e < len) dst[e] = x[j];
+                    }
+                }
+            }
         }
     }
     if (BITS) {
