@@ -1382,11 +1382,30 @@ __device__ inline void combine_vertex_pf(const CombineArgs &A, int64_t v, uint64
         } else if ((uint32_t)lane < r.len) {
             Xlo[L.xoff[q] + xidx[ek[q]]] = el[q];
         }
-        if (r.len > WAVE || stage_xhi) {
+        if (stage_xhi) {
             for (uint32_t e = lane; e < r.len; e += WAVE) {
                 const int x = L.xoff[q] + xidx[r.key[e]];
                 if (e >= WAVE) Xlo[x] = r.lo[e];
-                if (stage_xhi) Xhi[x] = r.hi ? r.hi[e] : 0;
+                Xhi[x] = r.hi ? r.hi[e] : 0;
+            }
+        } else if (r.len > WAVE) {
+            // the entries past the first 64, four per lane with their loads issued
+            // before any store
+            for (uint32_t e0 = WAVE + lane; e0 < r.len; e0 += 4 * WAVE) {
+                uint32_t kx[4];
+                uint64_t lx[4];
+                int xi[4];
+#pragma unroll
+                for (int j = 0; j < 4; j++) {
+                    const uint32_t e = e0 + j * WAVE;
+                    kx[j] = e < r.len ? r.key[e] : 0u;
+                    lx[j] = e < r.len ? r.lo[e] : 0ull;
+                }
+#pragma unroll
+                for (int j = 0; j < 4; j++) xi[j] = e0 + j * WAVE < r.len ? xidx[kx[j]] : 0;
+#pragma unroll
+                for (int j = 0; j < 4; j++)
+                    if (e0 + j * WAVE < r.len) Xlo[L.xoff[q] + xi[j]] = lx[j];
             }
         }
     }
@@ -1488,7 +1507,23 @@ __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(8, 8)
         const uint64_t hq = grp_shfl64(hd, q);
         if (!run || q > phi) continue;
         const RecView<false> r = h_rec<false>(A.lev[q], hq);
-        for (uint32_t e = s; e < r.len; e += CGL) Xlo[L.xoff[q] + xidx[r.key[e]]] = r.lo[e];
+        // four entries per lane with their loads issued before any store
+        for (uint32_t e0 = s; e0 < r.len; e0 += 4 * CGL) {
+            uint32_t kx[4];
+            uint64_t lx[4];
+            int xi[4];
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const uint32_t e = e0 + j * CGL;
+                kx[j] = e < r.len ? r.key[e] : 0u;
+                lx[j] = e < r.len ? r.lo[e] : 0ull;
+            }
+#pragma unroll
+            for (int j = 0; j < 4; j++) xi[j] = e0 + j * CGL < r.len ? xidx[kx[j]] : 0;
+#pragma unroll
+            for (int j = 0; j < 4; j++)
+                if (e0 + j * CGL < r.len) Xlo[L.xoff[q] + xi[j]] = lx[j];
+        }
     }
     __syncthreads();
     // outputs o = s, s + 16, ... of the group's vertex, compacted in order
