@@ -486,8 +486,17 @@ __global__ void __launch_bounds__(256) k_gather_classify(GatherArgs A, const u12
     const int64_t a = in ? A.g.row_ptr[v] : 0, b = in ? A.g.row_ptr[v + 1] : 0;
     const bool act = in && b - a <= A.hub_degree;
     u128 m = 0;
-    if (act)
-        for (int64_t e = a; e < b; e++) m = sat_add(m, N[A.g.col_idx[e]]);
+    // four neighbours at a time, their loads issued before any is summed
+    for (int64_t e0 = a; act && e0 < b; e0 += 4) {
+        int32_t u[4];
+        u128 x[4];
+#pragma unroll
+        for (int j = 0; j < 4; j++) u[j] = e0 + j < b ? A.g.col_idx[e0 + j] : -1;
+#pragma unroll
+        for (int j = 0; j < 4; j++) x[j] = u[j] >= 0 ? N[u[j]] : (u128)0;
+#pragma unroll
+        for (int j = 0; j < 4; j++) m = sat_add(m, x[j]);
+    }
     const bool wide = act && hi64(m) != 0, nar = act && !wide;
     const uint64_t bw = __ballot(wide), bn = __ballot(nar);
     int bw0 = 0, bn0 = 0;
