@@ -281,7 +281,10 @@ scc_status scc_export_level(const scc_table *t, int h, int64_t *nnz_out,
  *
  * out_verts: device int32[n * k], vertex ids in discovery order, root first.
  * out_parent: device int8[n * k], position of each vertex's parent (-1 for the
- * root). Errors: SCC_EINVAL (shape id), SCC_EEMPTY (total 0).
+ * root). The first call on a table also stores, with the table, the colour of
+ * every edge's head in CSR order (one byte per CSR entry), read by the
+ * neighbour draw; it changes no sample. Errors: SCC_EINVAL (shape id),
+ * SCC_EEMPTY (total 0), SCC_ENOMEM.
  */
 scc_status scc_sample(const scc_table *t, int32_t shape, int64_t n, uint64_t seed,
                       uint64_t stream_id, uint64_t first_index,
@@ -300,8 +303,9 @@ scc_status scc_sample(const scc_table *t, int32_t shape, int64_t n, uint64_t see
  * running sums that already exist: SCC_EINVAL when the draw would need one
  * that is not built yet (per-shape root sums, hub sums built lazily, or the
  * shape-first sums of round skipping) -- one scc_sample call with the same
- * shape, or creating a server on the table, builds them. Synchronises
- * `stream` to read the flags.
+ * shape, or creating a server on the table, builds them. Before such a call it
+ * reads neighbour colours from the colour array instead of the per-edge copy;
+ * the samples are the same. Synchronises `stream` to read the flags.
  */
 scc_status scc_sample_noalloc(const scc_table *t, int32_t shape, int64_t n, uint64_t seed,
                               uint64_t stream_id, uint64_t first_index,

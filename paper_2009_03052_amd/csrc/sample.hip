@@ -103,14 +103,45 @@ __device__ inline u128 draw_cached(const DrawCache &D, u128 N, uint64_t seed, ui
     return N - 1;
 }
 
-// count of (T, C) with the given key at x (level h >= 1)
-__device__ inline u128 own_count(const SampleArgs &A, int h, int64_t x, uint32_t key)
+// count of (T, C) with the given key at x (level h >= 1), x of colour cx
+__device__ inline u128 own_count_c(const SampleArgs &A, int h, int64_t x, int cx, uint32_t key)
 {
-    const int cx = A.g.colors[x];
     if (h == 1) return (key == (uint32_t)cx) ? 1 : 0;   // key of ({.}, {c}) is c
     const int li = A.key_xidx[(size_t)cx * A.nkeys + key];
     if (li < 0) return 0;
-    return record_at(A.lev[h], x, li);
+    // dense position li: its bitmap word, then the popcount of the words before
+    // it gives the entry; the locator goes out with the word
+    const LevelView &L = A.lev[h];
+    const uint64_t *bw = L.bm + (size_t)x * L.BW;
+    const int w = li >> 6;
+    const uint64_t l = L.loc[x];
+    const uint64_t word = bw[w];
+    // an empty record has no bit set: testing its locator as well keeps the
+    // locator's load beside the word's instead of after the test
+    if (!((word >> (li & 63)) & 1ull) || !l) return 0;
+    uint32_t pos = (uint32_t)__popcll(word & ((1ull << (li & 63)) - 1ull));
+    int q = 0;
+    for (; q + 1 < w; q += 2) {   // two words per load
+        const uint64_t a = bw[q], b = bw[q + 1];
+        pos += (uint32_t)(__popcll(a) + __popcll(b));
+    }
+    if (q < w) pos += (uint32_t)__popcll(bw[q]);
+    Rec r;
+    r.len = LOC_LEN(l);
+    r.wide = LOC_WIDE(l) != 0;
+    r.vlc = L.vlc != 0;
+    r.kw = key_words(r.len);
+    r.p = L.pool + LOC_OFF(l);
+    return r.cnt(pos);
+}
+__device__ inline u128 own_count(const SampleArgs &A, int h, int64_t x, uint32_t key)
+{
+    return own_count_c(A, h, x, A.g.colors[x], key);
+}
+// colour of the head of edge e (u = col_idx[e])
+__device__ inline int edge_colour(const SampleArgs &A, int64_t e, int32_t u)
+{
+    return A.ecol ? A.ecol[e] : A.g.colors[u];
 }
 
 // LDS of one wave's sample: the vertices found so far with their parents, and
@@ -309,7 +340,7 @@ __device__ inline int sample_one(const SampleArgs &A, int64_t r, SampleLds &W)
                 int32_t uu = -1;
                 if (e < rb) {
                     uu = A.g.col_idx[e];
-                    c = own_count(A, hpp, uu, kpp);
+                    c = own_count_c(A, hpp, uu, edge_colour(A, e, uu), kpp);
                 }
                 const u128 incl = (b > 0 ? P(b - 1) : (u128)0) + wave_incl_scan128(c);
                 const int w2 = first_exceeding(incl, Z);
@@ -320,19 +351,24 @@ __device__ inline int sample_one(const SampleArgs &A, int64_t r, SampleLds &W)
             }
         } else {
             // CSR order, 2 x 64 neighbours per round: every lane issues the loads of
-            // its 2 neighbours before using any, then the 2 groups are scanned in order
+            // its 2 neighbours (and their colours, stored per edge) before using any,
+            // then the 2 groups are scanned in order
             u128 run2 = 0;
             bool found = false;
             for (int64_t base = ra; base < rb && !found; base += 2 * WAVE) {
                 int32_t uu[2];
+                int cu[2];
                 u128 c[2];
 #pragma unroll
                 for (int g4 = 0; g4 < 2; g4++) {
                     const int64_t e = base + g4 * WAVE + lane;
                     uu[g4] = e < rb ? A.g.col_idx[e] : -1;
+                    cu[g4] = e < rb && A.ecol ? A.ecol[e] : 0;
                 }
 #pragma unroll
-                for (int g4 = 0; g4 < 2; g4++) c[g4] = uu[g4] >= 0 ? own_count(A, hpp, uu[g4], kpp) : (u128)0;
+                for (int g4 = 0; g4 < 2; g4++)
+                    c[g4] = uu[g4] >= 0 ? own_count_c(A, hpp, uu[g4], A.ecol ? cu[g4] : A.g.colors[uu[g4]], kpp)
+                                        : (u128)0;
 #pragma unroll
                 for (int g4 = 0; g4 < 2; g4++) {
                     if (found) break;
@@ -638,6 +674,31 @@ __global__ void k_hub_info(const int32_t *hubs, int nhub, int k, const uint8_t *
     for (int h = 1; h < k; h++) out[(size_t)i * (SCC_KMAX + 2) + h] = A.M[h] && hi64(A.M[h][x]) ? 1 : 0;
 }
 
+// colour of every edge's head, in CSR order
+__global__ void k_edge_colours(const int32_t *col_idx, const uint8_t *colors, int64_t nnz, uint8_t *ecol)
+{
+    const int64_t e0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+#pragma unroll
+    for (int j = 0; j < 4; j++)
+        if (e0 + j < nnz) ecol[e0 + j] = colors[col_idx[e0 + j]];
+}
+
+// The per-edge colours of the neighbour draw (nnz bytes, built once per table).
+static scc_status ensure_edge_colours(scc_table *T)
+{
+    std::lock_guard<std::mutex> g(T->hub_mu);
+    if (T->ecol || T->nnz_g == 0) return SCC_OK;
+    uint8_t *ec = (uint8_t *)T->alloc((size_t)T->nnz_g + 8);
+    if (!ec) return set_error(SCC_ENOMEM, "edge colours (%lld bytes)", (long long)T->nnz_g);
+    const int64_t nt = (T->nnz_g + 3) / 4;
+    hipLaunchKernelGGL(k_edge_colours, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, T->stream, T->col_idx,
+                       T->colors, T->nnz_g, ec);
+    HIP_TRY(hipStreamSynchronize(T->stream));
+    HIP_TRY(hipGetLastError());
+    T->ecol = ec;
+    return SCC_OK;
+}
+
 // Builds the per-hub running sums used by the sampler's neighbour draw. Hubs
 // are taken by decreasing degree while the tables fit in `budget` bytes.
 static scc_status ensure_hub_prefix(scc_table *T)
@@ -808,6 +869,7 @@ static scc_status sampling_args(scc_table *T, int shape, SampleArgs *out)
     const u128 *pre = nullptr;
     u128 total = 0;
     int mode = 0;
+    const uint8_t *A_ecol = nullptr;
     if (bal && shape == T->hlut.star_unr) {
         mode = 2;
         pre = T->star_pre;
@@ -834,8 +896,10 @@ static scc_status sampling_args(scc_table *T, int shape, SampleArgs *out)
     {
         std::lock_guard<std::mutex> g(T->hub_mu);
         if (!T->hubpre_ready && !T->hub_host.empty()) return set_error(SCC_EINVAL, "the hub running sums are not built");
+        A_ecol = T->ecol;
     }
     SampleArgs A{};
+    A.ecol = A_ecol;
     A.mode = mode;
     A.spre = T->bal_spre;
     A.stj = T->bal_stj;
@@ -869,6 +933,7 @@ scc_status prepare_sampling(scc_table *T, int shape, SampleArgs *out)
     }
     if (s) return s;
     s = ensure_hub_prefix(T);
+    if (!s) s = ensure_edge_colours(T);
     if (s) return s;
     return sampling_args(T, shape, out);
 }

@@ -18,6 +18,7 @@ struct SampleArgs {
     const int32_t *hub_index;             // [n] hub number or -1
     const int64_t *hub_poff;              // [nhub * (k+1)]
     const uint64_t *hub_pre;
+    const uint8_t *ecol;                  // [nnz] colour of each edge's head, or null (read colors[])
     const u128 *pre;                      // running sums of admissible level-k totals
     u128 total;
     // 0: the draw above; 1: shape first (round skipping, shape -1): total = t,

@@ -91,6 +91,10 @@ struct scc_table {
     int32_t *hub_index = nullptr;    // [n] hub number or -1
     int64_t *hub_poff = nullptr;     // [nhub * (k+1)] word offset of each (hub, level) block
     uint64_t *hub_pre = nullptr;     // the running sums (low words, then high words if wide)
+    // colour of each edge's head in CSR order (colors[col_idx[e]]), built with the
+    // hub running sums: the neighbour draw reads it with the edge instead of
+    // looking the neighbour's colour up at random
+    uint8_t *ecol = nullptr;
     // root draw: every ROOT_STRIDE-th running sum, for a two-level search
     u128 *pre_coarse = nullptr;
 

@@ -68,3 +68,20 @@ def test_noalloc_arguments():
         tab.sample_noalloc(v, p, seed=1, shape=99)
     assert e.value.status == S.EINVAL
     tab.sample_noalloc(v[:0], p[:0], seed=1)       # n = 0: nothing to do
+
+
+def test_noalloc_before_any_sample():
+    """Before the first scc_sample the table has no per-edge colour copy, and the
+    neighbour draw reads the colour array instead: the samples are the same."""
+    S, tab = _table()
+    n = 3000
+    v = torch.full((n, tab.k), -7, dtype=torch.int32, device="cuda")
+    p = torch.full((n, tab.k), 9, dtype=torch.int8, device="cuda")
+    print("noalloc before any sample", n, flush=True)
+    tab.sample_noalloc(v, p, seed=9, first_index=11)
+    torch.cuda.synchronize()
+    rv, rp = tab.sample(n, seed=9, first_index=11)
+    assert torch.equal(rv, v) and torch.equal(rp, p)
+    print("noalloc after the first sample", n, flush=True)
+    rv2, rp2, v2, p2 = _pair(tab, n, seed=9, first=11)
+    assert torch.equal(rv2, v) and torch.equal(v2, v) and torch.equal(p2, p)
