@@ -965,9 +965,12 @@ def _short_kernel(name):
 
 
 def _first_build(names):
-    """Indices of the first table build: from its first kernel to the last one before the first k_sample."""
+    """Indices of the first table build: from its first kernel to the last one before
+    the first sampling call's preparation (per-edge colours, hub running sums built
+    apart from the build) or, without one, before the first k_sample."""
     start = next(i for i, nm in enumerate(names) if nm in ("k_row_lists", "k_validate_rows"))
-    end = next(i for i, nm in enumerate(names) if nm == "k_sample")
+    prep = ("k_sample", "k_edge_colours", "k_hub_info", "k_hub_index", "k_hubpre_chunk")
+    end = next(i for i, nm in enumerate(names) if i > start and nm in prep)
     return start, end
 
 
