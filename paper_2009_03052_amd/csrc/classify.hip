@@ -145,41 +145,63 @@ __global__ void k_class_lut(uint64_t ncodes, const uint32_t *canon, const uint32
     if (m == (uint32_t)c) cat[rank_incl[c] - 1u] = (uint32_t)c;
 }
 
-__device__ inline bool has_edge(const GraphView &g, int32_t a, int32_t b)
+// target in the sorted list col[lo, hi): halve the range down to CLS_WIN
+// entries, then compare those entries, their loads issued together (one memory
+// latency for the last four halvings of a binary search)
+constexpr int CLS_WIN = 16;
+__device__ inline bool in_sorted(const int32_t *col, int64_t lo, int64_t hi, int32_t target)
 {
-    int64_t lo = g.row_ptr[a], hi = g.row_ptr[a + 1];
-    const int64_t lo2 = g.row_ptr[b], hi2 = g.row_ptr[b + 1];
-    int32_t target = b;
-    if (hi2 - lo2 < hi - lo) { lo = lo2; hi = hi2; target = a; }
-    while (lo < hi) {
+    while (hi - lo > CLS_WIN) {
         const int64_t mid = (lo + hi) >> 1;
-        const int32_t w = g.col_idx[mid];
+        const int32_t w = col[mid];
         if (w == target) return true;
         if (w < target) lo = mid + 1; else hi = mid;
     }
-    return false;
+    int32_t x[CLS_WIN];
+#pragma unroll
+    for (int q = 0; q < CLS_WIN; q++) x[q] = lo + q < hi ? col[lo + q] : -1;
+    bool f = false;
+#pragma unroll
+    for (int q = 0; q < CLS_WIN; q++) f |= x[q] == target;
+    return f;
 }
 
 // induced adjacency code of one sample (bit q for the q-th pair i < j) and its
-// class through the lookup table; 0xffffffff for both when a vertex id is invalid
+// class through the lookup table; 0xffffffff for both when a vertex id is invalid.
+// Every vertex's row bounds are read once; a pair searches the shorter row.
 __device__ inline uint32_t classify_row(const GraphView &g, int k, const int32_t *row, const uint16_t *lut,
                                         uint32_t *code_out)
 {
     int32_t vs[SCC_KMAX];
     bool ok = true;
-    for (int i = 0; i < k; i++) {
-        vs[i] = row[i];
-        ok = ok && vs[i] >= 0 && vs[i] < g.n;
+#pragma unroll
+    for (int i = 0; i < SCC_KMAX; i++) {
+        vs[i] = i < k ? row[i] : 0;
+        ok = ok && (i >= k || (vs[i] >= 0 && vs[i] < g.n));
     }
     if (!ok) {
         *code_out = 0xffffffffu;
         return 0xffffffffu;
     }
+    int64_t rb[SCC_KMAX], re[SCC_KMAX];
+#pragma unroll
+    for (int i = 0; i < SCC_KMAX; i++) {
+        rb[i] = i < k ? g.row_ptr[vs[i]] : 0;
+        re[i] = i < k ? g.row_ptr[vs[i] + 1] : 0;
+    }
+    // the pairs unrolled over SCC_KMAX vertices, so that the arrays stay in registers
     uint32_t code = 0;
     int q = 0;
-    for (int i = 0; i < k; i++)
-        for (int j = i + 1; j < k; j++, q++)
-            if (has_edge(g, vs[i], vs[j])) code |= 1u << q;
+#pragma unroll
+    for (int i = 0; i < SCC_KMAX; i++)
+#pragma unroll
+        for (int j = i + 1; j < SCC_KMAX; j++) {
+            if (j >= k) continue;
+            const bool in_j = re[j] - rb[j] < re[i] - rb[i];
+            if (in_j ? in_sorted(g.col_idx, rb[j], re[j], vs[i]) : in_sorted(g.col_idx, rb[i], re[i], vs[j]))
+                code |= 1u << q;
+            q++;
+        }
     *code_out = code;
     const uint16_t c = lut[code];
     return c == 0xffff ? 0xffffffffu : (uint32_t)c;
