@@ -23,6 +23,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <atomic>
 #include <thread>
 
 namespace {
@@ -3653,27 +3654,31 @@ static scc_status batch_launch(std::vector<BatchInstHost> &H, int tile, int hub_
 static scc_status batch_persistent(const scc_instance *inst, int n_inst, const scc_build_opts *opt,
                                    const scc_batch_opts *bopt, scc_table **out, scc_batch_report *rep);
 
-// A second stream per device for the batch scheduler (created once, default
-// priority, not synchronised with the legacy default stream).
-static hipStream_t aux_stream(int dev)
+// Extra streams per device for the batch scheduler (slot 0: the persistent
+// launch, slot 1: a second level-kernel build; created once, default priority,
+// not synchronised with the legacy default stream).
+static hipStream_t aux_stream(int dev, int slot)
 {
     static std::mutex mu;
-    static std::map<int, hipStream_t> streams;
+    static std::map<std::pair<int, int>, hipStream_t> streams;
     std::lock_guard<std::mutex> lk(mu);
-    auto it = streams.find(dev);
+    auto it = streams.find({dev, slot});
     if (it != streams.end()) return it->second;
     hipStream_t s = nullptr;
     if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return nullptr;
-    streams[dev] = s;
+    streams[{dev, slot}] = s;
     return s;
 }
 
 // The batch scheduler: instances with at least plain_nnz CSR entries are built
-// one after another by the level kernels (exactly as scc_build_table builds
-// them), the others together in one persistent launch. When there are both,
-// the persistent launch runs from a second host thread on a second stream
-// while the level kernels run, and its tables are handed back on the caller's
-// stream.
+// by the level kernels (exactly as scc_build_table builds them), the others
+// together in one persistent launch. When there are both, the persistent launch
+// runs from a second host thread on a second stream while the level kernels
+// run. The level-kernel instances are taken from a shared queue by two host
+// threads on two streams when the two largest of them would fit in free device
+// memory together at 1 KiB per CSR entry (one build's kernels then cover the
+// other's host waits), else by one. Tables built on a scheduler stream are
+// handed back on the caller's stream.
 extern "C" scc_status scc_build_batch(const scc_instance *inst, int n_inst, const scc_build_opts *opt,
                                       const scc_batch_opts *bopt, scc_table **out, scc_batch_report *rep)
 {
@@ -3705,7 +3710,7 @@ extern "C" scc_status scc_build_batch(const scc_instance *inst, int n_inst, cons
     if (!plain.empty() && !pers.empty()) {
         int dev = 0;
         HIP_TRY(hipGetDevice(&dev));
-        const hipStream_t aux = aux_stream(dev);
+        const hipStream_t aux = aux_stream(dev, 0);
         if (!aux) return set_error(SCC_EDEVICE, "could not create the batch scheduler's stream");
         popt.stream = (void *)aux;
         worker = std::thread([&, dev] {
@@ -3725,14 +3730,69 @@ extern "C" scc_status scc_build_batch(const scc_instance *inst, int n_inst, cons
         }
     };
     auto t0 = std::chrono::steady_clock::now();
-    scc_status s = SCC_OK;
-    for (int i : plain) {
-        scc_build_opts po{};
-        if (opt) po = *opt;
-        po.hub_degree = 0;
-        po.vlc = 0;
-        s = scc_build_table(&inst[i].g, inst[i].colors, inst[i].k, &po, &out[i]);
-        if (s) break;
+    scc_status s = SCC_OK, s2 = SCC_OK;
+    std::string err2;
+    std::atomic<size_t> next{0};
+    // builds queued level-kernel instances until the queue is empty or one fails
+    auto build_plain = [&](hipStream_t st, bool second, scc_status &res, std::string *err) {
+        for (size_t q; (q = next.fetch_add(1)) < plain.size();) {
+            const int i = plain[q];
+            scc_build_opts po{};
+            if (opt) po = *opt;
+            po.hub_degree = 0;
+            po.vlc = 0;
+            if (second) po.stream = (void *)st;
+            res = scc_build_table(&inst[i].g, inst[i].colors, inst[i].k, &po, &out[i]);
+            if (res) {
+                if (err) *err = scc_last_error();
+                next = plain.size();
+                return;
+            }
+        }
+    };
+    hipStream_t st2 = nullptr;
+    if (plain.size() >= 2) {
+        int64_t a = 0, b = 0;   // the two largest level-kernel instances
+        for (int i : plain) {
+            const int64_t z = inst[i].g.nnz;
+            if (z > a) { b = a; a = z; } else if (z > b) b = z;
+        }
+        size_t fr = 0, tot = 0;
+        int dev = 0;
+        if (hipGetDevice(&dev) == hipSuccess && hipMemGetInfo(&fr, &tot) == hipSuccess &&
+            (double)fr > 1024.0 * (double)(a + b))
+            st2 = aux_stream(dev, 1);
+    }
+    std::thread plain2;
+    if (st2) {
+        int dev = 0;
+        HIP_TRY(hipGetDevice(&dev));
+        plain2 = std::thread([&, dev] {
+            if (hipSetDevice(dev) != hipSuccess) {
+                s2 = SCC_EDEVICE;
+                err2 = "hipSetDevice failed in the batch scheduler's thread";
+                next = plain.size();
+                return;
+            }
+            build_plain(st2, true, s2, &err2);
+        });
+    }
+    build_plain(nullptr, false, s, nullptr);
+    if (plain2.joinable()) {
+        plain2.join();
+        if (!s2 && hipStreamSynchronize(st2) != hipSuccess) {
+            s2 = SCC_EDEVICE;
+            err2 = "synchronising the batch scheduler's second stream";
+        }
+        for (int i : plain)   // finished on the second stream: hand over to the caller's
+            if (out[i] && out[i]->stream == st2) {
+                out[i]->stream = caller;
+                out[i]->mem.stream = caller;
+            }
+        if (!s && s2) {
+            s = s2;
+            set_error(s2, "%s", err2.c_str());
+        }
     }
     const double plain_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     if (worker.joinable()) {
